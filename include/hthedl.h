@@ -1,0 +1,191 @@
+/*
+ * hthedl.h -- C ABI of libhthedl.so: exact evaluation of ALCQI(D) concept
+ * hypotheses over a knowledge base resident in the memory of one MI355X GPU.
+ *
+ * The problem statement follows HT-HEDL (Algahtani, "HT-HEDL: High-Throughput
+ * Hypothesis Evaluation in Description Logic"):
+ *   - the knowledge base lives entirely in device memory (Section 3.1): concept
+ *     memberships as rows over individuals (the transposed concepts matrix),
+ *     role assertions grouped per role, numeric concrete-role values, and the
+ *     learning-examples matrix;
+ *   - a hypothesis is an array of DL operations in consecutive memory
+ *     (Section 4), here in postfix order;
+ *   - its result is the instance set and the (covered positives, covered
+ *     negatives) pair of the coverage matrix (Section 4, Algorithm 15).
+ *
+ * Conventions for every call:
+ *   - Every call returns hth_status; nothing throws or longjmps across the ABI.
+ *   - Validation happens before anything is launched.  On error no output is
+ *     written and hth_last_error() returns a message for the calling thread.
+ *   - "device" pointers are HIP device memory owned by the caller.  The library
+ *     never allocates or frees device memory; the knowledge base, the derived
+ *     buffer, the workspace and every output belong to the caller and must
+ *     outlive the calls (and the kb handle) that use them.
+ *   - "host" pointers are read during the call only.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Calls are
+ *     asynchronous on it unless stated otherwise.  One kb may be used from
+ *     several streams at once only with a distinct workspace per stream.
+ *   - Bit rows: individual i is bit (i & 63) of uint64 word (i >> 6), least
+ *     significant bit first.  Bits at positions >= N must be zero on input and
+ *     are zero on output.
+ */
+#ifndef HTHEDL_H
+#define HTHEDL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hth_status;
+enum {
+  HTH_OK = 0,
+  HTH_E_INVALID = -1,     /* malformed argument or knowledge base */
+  HTH_E_RANGE = -2,       /* id, index or size out of range */
+  HTH_E_NOMEM = -3,       /* caller-provided buffer too small */
+  HTH_E_DEVICE = -4,      /* a HIP call failed (text in hth_last_error) */
+  HTH_E_PLAN = -5,        /* hypothesis not in postfix form */
+  HTH_E_STATE = -6,       /* handle used in the wrong state */
+  HTH_E_UNSUPPORTED = -7  /* valid request outside this build's limits */
+};
+
+/* DL constructs (Section 3.2).  The paper's string restrictions (EQUAL,
+ * CONTAIN) and multi-valued numeric roles are not part of this library. */
+enum {
+  HTH_TOP = 0,      /* every individual */
+  HTH_BOT = 1,      /* no individual */
+  HTH_ATOM = 2,     /* arg = concept id: one row of the concepts matrix */
+  HTH_NOT = 3,      /* complement in the domain (closed world, Section 3.1) */
+  HTH_AND = 4,      /* n-ary conjunction (Algorithms 1/2); arity 0 = TOP */
+  HTH_OR = 5,       /* n-ary disjunction; arity 0 = BOT */
+  HTH_EXISTS = 6,   /* {x : some successor in C} (Algorithms 3/4) */
+  HTH_FORALL = 7,   /* {x : every successor in C}, incl. x without successors (Algorithms 5/6) */
+  HTH_ATLEAST = 8,  /* {x : cnt(x) >= n}, cnt = successors in C (Algorithms 7/8) */
+  HTH_ATMOST = 9,   /* {x : cnt(x) <= n}; textbook reading: includes cnt = 0 */
+  HTH_EXACTLY = 10, /* {x : cnt(x) == n} */
+  HTH_DATA_GE = 11, /* {x : value of property arg defined and >= t} (Algorithms 9/10) */
+  HTH_DATA_LE = 12, /* {x : value of property arg defined and <= t} */
+  HTH_NUM_OPS = 13
+};
+
+/* One node of a hypothesis, 16 bytes.  Nodes are in postfix order: every child
+ * index is smaller than its parent's index; the root is the last node of the
+ * hypothesis.  Nodes may be shared (a DAG). */
+typedef struct {
+  uint8_t op;       /* HTH_* construct */
+  uint8_t inv;      /* role constructs: 1 = inverse role r^- (subject and object swapped) */
+  uint16_t arity;   /* AND/OR: number of children; 0 otherwise */
+  uint32_t arg;     /* ATOM: concept id; role constructs: role id; DATA_*: property id */
+  uint32_t child;   /* NOT and role constructs: child node index (local to the
+                       hypothesis); AND/OR: first entry in the children array */
+  union {
+    uint32_t n;     /* ATLEAST/ATMOST/EXACTLY: n (<= 2^31 - 1) */
+    float t;        /* DATA_GE/DATA_LE: threshold (not NaN; +-inf allowed) */
+  } q;
+} hth_node;
+
+typedef struct hth_kb_s* hth_kb;   /* opaque host handle */
+
+/* The knowledge base (Section 3.1).  Every pointer is device memory. */
+typedef struct {
+  uint32_t n_individuals;        /* N, 1 <= N < 2^31 */
+  uint32_t stride_words;         /* words per bit row: >= ceil(N/64), a multiple of 8 */
+  uint32_t n_concepts;
+  const uint64_t* concept_bits;  /* [n_concepts][stride_words] membership rows */
+  uint32_t n_roles;
+  uint64_t n_edges;              /* E: total role assertions over all roles */
+  const int64_t* role_offsets;   /* [n_roles][N+1]: assertions of role r with subject x are
+                                    role_targets[role_offsets[r][x] .. role_offsets[r][x+1]);
+                                    role_offsets[0][0] = 0, role_offsets[r][0] =
+                                    role_offsets[r-1][N], role_offsets[n_roles-1][N] = E */
+  const int32_t* role_targets;   /* [E] objects; strictly increasing inside each row (a role is
+                                    a set of assertions); each < N.  E_r < 2^32 per role. */
+  uint32_t n_data;
+  const float* data;             /* [n_data][N] one value per individual and property; NaN = none */
+  const uint64_t* pos_bits;      /* [stride_words] positive examples */
+  const uint64_t* neg_bits;      /* [stride_words] negative examples (may overlap pos) */
+} hth_kb_desc;
+
+/* Size of the derived buffer that hth_kb_create fills: per-role 32-bit row
+ * offsets for both directions and the inverse-role CSR (transpose). */
+hth_status hth_kb_derived_bytes(const hth_kb_desc* desc, size_t* bytes);
+
+/* Validate the knowledge base on the device and build the derived layouts into
+ * `derived` (device memory of at least hth_kb_derived_bytes).  Synchronous:
+ * returns after validation and the build have finished on `stream`.  Errors:
+ * HTH_E_INVALID (non-monotone offsets, target out of range, duplicate or
+ * unsorted targets, set padding bits), HTH_E_NOMEM (derived too small),
+ * HTH_E_RANGE (sizes beyond the limits above). */
+hth_status hth_kb_create(const hth_kb_desc* desc, void* derived, size_t derived_bytes,
+                         void* stream, hth_kb* out);
+
+/* Replace the example rows (device [stride_words] each, zero padding). */
+hth_status hth_kb_set_examples(hth_kb kb, const uint64_t* pos_bits, const uint64_t* neg_bits);
+
+/* Largest out-degree of role r in direction inv (0 = forward, 1 = inverse). */
+hth_status hth_kb_max_degree(hth_kb kb, uint32_t role, uint32_t inv, uint32_t* out);
+
+/* Free the host handle.  Device memory is the caller's. */
+hth_status hth_kb_destroy(hth_kb kb);
+
+/* Workspace needed to evaluate up to max_hyps hypotheses with at most
+ * max_nodes nodes in total per call (device memory, caller-owned, no
+ * initialisation required). */
+hth_status hth_workspace_bytes(hth_kb kb, uint32_t max_nodes, uint32_t max_hyps, size_t* bytes);
+
+/* Evaluate one hypothesis (Section 4): plan on the host, then a short kernel
+ * sequence on `stream`.  nodes/children are host arrays.  d_counts: device
+ * uint32[2] <- (covered positives, covered negatives) (Algorithm 15).
+ * d_instances: NULL or device uint64[stride_words] <- the instance set. */
+hth_status hth_eval_one(hth_kb kb, const hth_node* nodes, uint32_t n_nodes,
+                        const uint32_t* children, uint32_t n_children,
+                        void* ws, size_t ws_bytes, uint64_t* d_instances, uint32_t* d_counts,
+                        void* stream);
+
+/* Evaluate a batch.  Hypothesis h is nodes[hyp_node_offsets[h] .. hyp_node_offsets[h+1]),
+ * its child indices local to that range; children[] entries are local too.
+ * The batch is compiled once (shared subexpressions across hypotheses are
+ * evaluated once), then run level by level.  d_counts: device uint32[n_hyps][2]. */
+hth_status hth_eval_batch(hth_kb kb, const hth_node* nodes, const uint32_t* hyp_node_offsets,
+                          uint32_t n_hyps, const uint32_t* children, uint32_t n_children,
+                          void* ws, size_t ws_bytes, uint32_t* d_counts, void* stream);
+
+/* Measurement.  Between hth_profile_begin and hth_profile_end every kernel the
+ * library launches for this kb is bracketed by two HIP events recorded on the
+ * launch stream, and the host adds up the algorithmic HBM bytes of the launch
+ * (each input array the kernel must read once, each output it writes once).
+ * hth_profile_end waits for the recorded events and returns, per kernel kind,
+ * the number of launches, their summed event-timed duration (ms) and bytes.
+ * Profiling adds two event records per launch; results are unchanged. */
+enum {
+  HTH_K_THRESHOLD = 0,  /* numeric restriction rows */
+  HTH_K_REGION = 1,     /* boolean regions, with or without coverage */
+  HTH_K_ROLE = 2,       /* one role restriction per task */
+  HTH_K_TBUILD = 3,     /* transposed child rows for shared role passes */
+  HTH_K_GROUP = 4,      /* shared role passes (up to 64 role nodes per CSR scan) */
+  HTH_K_NUM = 8
+};
+typedef struct {
+  uint64_t launches;
+  double ms;
+  double bytes;
+} hth_prof_entry;
+hth_status hth_profile_begin(hth_kb kb);
+hth_status hth_profile_end(hth_kb kb, hth_prof_entry* out /* [HTH_K_NUM] */);
+
+/* Wait for `stream`; turn an asynchronous device error into HTH_E_DEVICE. */
+hth_status hth_sync(void* stream);
+
+/* Name of a status code (static string). */
+const char* hth_status_str(hth_status s);
+
+/* Copy the calling thread's last error message into buf (NUL-terminated,
+ * truncated to n bytes); returns the full message length. */
+size_t hth_last_error(char* buf, size_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HTHEDL_H */

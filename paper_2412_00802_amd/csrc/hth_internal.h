@@ -1,0 +1,158 @@
+// Internal declarations shared by the host code and the kernels of libhthedl.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "hthedl.h"
+
+namespace hth {
+
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr int kStackDepth = 16;       // region-program value stack (per lane, in LDS)
+constexpr int kRegionThreads = 256;   // lanes = words
+constexpr int kMaxK = 64;             // role nodes sharing one CSR pass (bits of a T row)
+
+// ---------------------------------------------------------------------------
+// region programs: postfix bytecode over bit rows, one lane per 64-bit word
+//   bits 0-3 opcode, bit 4 negate (LEAF only), bits 5-31 argument
+// ---------------------------------------------------------------------------
+enum : uint32_t {
+  RP_LEAF = 0,   // push row `arg` (concept id, or n_concepts + slot)
+  RP_TOP = 1,
+  RP_BOT = 2,
+  RP_NOT = 3,    // complement the top of the stack
+  RP_AND = 4,    // pop b, top &= b
+  RP_OR = 5,     // pop b, top |= b
+};
+__host__ __device__ inline uint32_t rp_ins(uint32_t op, uint32_t neg, uint32_t arg) {
+  return op | (neg << 4) | (arg << 5);
+}
+
+// One boolean region evaluated over all words.
+struct RegionTask {
+  uint32_t code_off;   // into the code table
+  uint32_t code_len;
+  uint32_t out_row;    // row id to write (n_concepts + slot), kNone = none, kInstances
+  uint32_t cover;      // hypothesis index for coverage, kNone = none
+};
+constexpr uint32_t kInstances = 0xFFFFFFFEu;   // out_row: the caller's instance buffer
+
+// One numeric threshold row: bit x = value_p(x) >= t (or <= t), NaN -> 0.
+struct ThrTask {
+  uint32_t prop;
+  uint32_t le;
+  float t;
+  uint32_t out_row;
+};
+
+// One role restriction over one CSR direction, evaluated alone (k = 1).
+//   cnt(x) = #{y in succ(x) : bit(child, y) ^ neg};  result = lo <= cnt <= hi
+//   counting may stop at `sat` (every predicate is decided once cnt >= sat).
+struct RoleTask {
+  uint32_t role;
+  uint32_t inv;
+  uint32_t child_row;  // concept id or n_concepts + slot
+  uint32_t neg;        // 0/1: complement the child before counting
+  uint32_t lo, hi, sat;
+  uint32_t out_row;    // n_concepts + slot
+};
+
+// A CSR pass shared by up to 64 role nodes of one (role, direction, level):
+// the children are first transposed into T[y] (bit j = child j contains y,
+// after its negation flag), then one pass over the CSR counts all of them.
+struct GroupTask {
+  uint32_t role;
+  uint32_t inv;
+  uint32_t k;          // nodes in the group, 1..64
+  uint32_t first;      // index of the group's first member in the member table
+  uint64_t t_off;      // word offset of this group's T buffer in the T area
+};
+struct GroupMember {
+  uint32_t child_row;
+  uint32_t neg;
+  uint32_t lo, hi, sat;
+  uint32_t out_row;
+  uint32_t pad0, pad1;
+};
+
+// Device view of the knowledge base and of one call's buffers (by value).
+struct DevKB {
+  const uint64_t* concepts;   // [C][S]
+  uint64_t* slots;            // [n_slots][S] (workspace)
+  const float* data;          // [D][N]
+  const uint32_t* fwd_off;    // [R][N+1], relative to the role's first assertion
+  const uint32_t* inv_off;    // [R][N+1]
+  const int32_t* fwd_tg;      // [E]
+  const int32_t* inv_tg;      // [E]
+  const uint64_t* role_base;  // [R] first assertion of each role (both directions)
+  const uint64_t* pos;        // [S]
+  const uint64_t* neg;        // [S]
+  uint32_t* counts;           // [n_hyps][2]
+  uint64_t* instances;        // [S] or null
+  uint32_t n_concepts;
+  uint32_t N, W, S;
+  uint64_t tail;              // valid-bit mask of word W-1
+};
+
+__device__ __forceinline__ const uint64_t* row_ptr(const DevKB& kb, uint32_t id) {
+  return id < kb.n_concepts ? kb.concepts + (size_t)id * kb.S
+                            : kb.slots + (size_t)(id - kb.n_concepts) * kb.S;
+}
+__device__ __forceinline__ uint64_t* out_ptr(const DevKB& kb, uint32_t id) {
+  if (id == kInstances) return kb.instances;
+  return kb.slots + (size_t)(id - kb.n_concepts) * kb.S;
+}
+
+}  // namespace hth
+
+// ---------------------------------------------------------------------------
+// the knowledge-base handle
+// ---------------------------------------------------------------------------
+struct hth_kb_s {
+  hth_kb_desc d;
+  uint32_t N = 0, W = 0, S = 0;
+  uint64_t tail = 0;
+  uint32_t* fwd_off = nullptr;
+  uint32_t* inv_off = nullptr;
+  int32_t* inv_tg = nullptr;
+  uint64_t* role_base_dev = nullptr;
+  std::vector<uint64_t> role_base;     // [R+1]
+  std::vector<uint32_t> max_deg[2];    // [R] forward, inverse
+  const uint64_t* pos = nullptr;
+  const uint64_t* neg = nullptr;
+  int device = 0;
+  int n_cu = 256;
+  size_t lds_per_block = 65536;
+  std::mutex mu;
+  // measurement (hth_profile_begin/end)
+  struct ProfRec {
+    int kind;
+    double bytes;
+    hipEvent_t a, b;
+  };
+  bool prof = false;
+  std::vector<ProfRec> prof_recs;
+  std::vector<hipEvent_t> event_pool;
+};
+
+namespace hth {
+
+// error reporting (thread-local message)
+void set_error(const std::string& msg);
+hth_status fail(hth_status code, const std::string& msg);
+hth_status hip_fail(hipError_t e, const char* what);
+
+#define HTH_HIP(call)                                   \
+  do {                                                  \
+    hipError_t _e = (call);                             \
+    if (_e != hipSuccess) return ::hth::hip_fail(_e, #call); \
+  } while (0)
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace hth

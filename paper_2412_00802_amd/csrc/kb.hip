@@ -1,0 +1,464 @@
+// Knowledge-base loading: validation on the device and the derived layouts
+// (32-bit per-role row offsets in both directions and the inverse-role CSR).
+//
+// The paper keeps role assertions as (subject, object) rows grouped per role
+// with an offset table (Section 3.1) and obtains inverse restrictions by
+// swapping subjects and objects (end of Section 3.2.2).  Here the forward
+// assertions arrive as a CSR per role and the inverse is its exact transpose,
+// built once at load time so that both directions are scanned row-parallel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "hth_internal.h"
+
+namespace hth {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+hth_status fail(hth_status code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+hth_status hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return HTH_E_DEVICE;
+}
+
+enum : uint32_t {
+  F_NONMONO = 1,   // offsets decrease or leave the role's range
+  F_TARGET = 2,    // target outside [0, N)
+  F_ORDER = 4,     // targets not strictly increasing inside a row
+  F_PAD = 8,       // a padding bit is set
+};
+
+constexpr int kScanThreads = 1024;
+constexpr int kScanItems = 4;
+constexpr uint32_t kScanBlock = kScanThreads * kScanItems;
+
+__global__ void k_gather_bases(const int64_t* __restrict__ off, uint32_t R, uint32_t N,
+                               uint64_t* __restrict__ base) {
+  uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < R) base[r] = (uint64_t)off[(size_t)r * (N + 1)];
+  if (r == R - 1) base[R] = (uint64_t)off[(size_t)r * (N + 1) + N];
+}
+
+// One thread per (role, subject): check the row, write its relative offset,
+// count its assertions per object into inv_off[r][y + 1].
+__global__ void k_validate_rows(const int64_t* __restrict__ off, const int32_t* __restrict__ tg,
+                                const uint64_t* __restrict__ base, uint32_t N,
+                                uint32_t* __restrict__ fwd_off, uint32_t* __restrict__ inv_cnt,
+                                uint32_t* __restrict__ maxdeg, uint32_t* __restrict__ flags) {
+  uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t r = blockIdx.y;
+  if (x >= N) return;
+  const int64_t* o = off + (size_t)r * (N + 1);
+  int64_t o0 = o[x], o1 = o[x + 1];
+  int64_t b0 = (int64_t)base[r], b1 = (int64_t)base[r + 1];
+  uint32_t* fo = fwd_off + (size_t)r * (N + 1);
+  if (o0 < b0 || o1 < o0 || o1 > b1) {
+    atomicOr(flags, F_NONMONO);
+    return;
+  }
+  fo[x] = (uint32_t)(o0 - b0);
+  if (x == N - 1) fo[N] = (uint32_t)(o1 - b0);
+  atomicMax(maxdeg + r, (uint32_t)(o1 - o0));
+  uint32_t* cnt = inv_cnt + (size_t)r * (N + 1);
+  int32_t prev = -1;
+  uint32_t bad = 0;
+  for (int64_t e = o0; e < o1; ++e) {
+    int32_t t = tg[e];
+    if (t < 0 || (uint32_t)t >= N) {
+      bad |= F_TARGET;
+      continue;
+    }
+    if (t <= prev) bad |= F_ORDER;
+    prev = t;
+    atomicAdd(cnt + t + 1, 1u);
+  }
+  if (bad) atomicOr(flags, bad);
+}
+
+// Bits past N in word W-1 and words W..S-1 of every bit row must be zero.
+__global__ void k_check_padding(const uint64_t* __restrict__ rows, uint32_t n_rows, uint32_t W,
+                                uint32_t S, uint64_t tail, uint32_t* __restrict__ flags) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_rows) return;
+  const uint64_t* p = rows + (size_t)i * S;
+  uint64_t bad = p[W - 1] & ~tail;
+  for (uint32_t w = W; w < S; ++w) bad |= p[w];
+  if (bad) atomicOr(flags, F_PAD);
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, size_t n, uint32_t v) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t step = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += step) p[i] = v;
+}
+
+__global__ void k_copy_u32(const uint32_t* __restrict__ s, uint32_t* __restrict__ d, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t step = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += step) d[i] = s[i];
+}
+
+// Inclusive wave scan of one value per lane.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t u = __shfl_up(v, d, 64);
+    if (lane >= d) v += u;
+  }
+  return v;
+}
+
+// Block-wide exclusive scan of one value per thread (blockDim = 1024); returns
+// the exclusive prefix and writes the block total to *total.
+__device__ uint32_t block_excl_scan(uint32_t v, uint32_t* total) {
+  __shared__ uint32_t wsum[kScanThreads / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t inc = wave_incl_scan(v);
+  if (lane == 63) wsum[wid] = inc;
+  __syncthreads();
+  if (wid == 0) {
+    uint32_t s = lane < kScanThreads / 64 ? wsum[lane] : 0;
+    uint32_t si = wave_incl_scan(s);
+    if (lane < kScanThreads / 64) wsum[lane] = si - s;
+    if (lane == kScanThreads / 64 - 1) *total = si;
+  }
+  __syncthreads();
+  uint32_t r = inc - v + wsum[wid];
+  __syncthreads();
+  return r;
+}
+
+// Phase 1: per-block sums (and maxima) of a[r][1 .. N] (the per-object counts).
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_sums(const uint32_t* __restrict__ a, uint32_t N, uint32_t nb, uint32_t* __restrict__ bsum,
+            uint32_t* __restrict__ maxdeg) {
+  uint32_t r = blockIdx.y;
+  const uint32_t* p = a + (size_t)r * (N + 1) + 1;
+  uint32_t start = blockIdx.x * kScanBlock;
+  uint32_t s = 0, m = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    uint32_t i = start + k * kScanThreads + threadIdx.x;
+    if (i < N) {
+      uint32_t v = p[i];
+      s += v;
+      m = max(m, v);
+    }
+  }
+  __shared__ uint32_t ss[kScanThreads / 64], mm[kScanThreads / 64];
+  for (int d = 32; d >= 1; d >>= 1) {
+    s += __shfl_xor(s, d, 64);
+    m = max(m, __shfl_xor(m, d, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    ss[threadIdx.x >> 6] = s;
+    mm[threadIdx.x >> 6] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t ts = 0, tm = 0;
+    for (int i = 0; i < kScanThreads / 64; ++i) {
+      ts += ss[i];
+      tm = max(tm, mm[i]);
+    }
+    bsum[(size_t)r * nb + blockIdx.x] = ts;
+    atomicMax(maxdeg + r, tm);
+  }
+}
+
+// Phase 2: exclusive scan of the block sums of each role (one block per role).
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_block_sums(uint32_t* __restrict__ bsum, uint32_t nb) {
+  uint32_t* p = bsum + (size_t)blockIdx.x * nb;
+  __shared__ uint32_t carry_s;
+  __shared__ uint32_t tot;
+  if (threadIdx.x == 0) carry_s = 0;
+  __syncthreads();
+  for (uint32_t c = 0; c < nb; c += kScanThreads) {
+    uint32_t i = c + threadIdx.x;
+    uint32_t v = i < nb ? p[i] : 0;
+    uint32_t ex = block_excl_scan(v, &tot);
+    uint32_t carry = carry_s;
+    if (i < nb) p[i] = ex + carry;
+    __syncthreads();
+    if (threadIdx.x == 0) carry_s = carry + tot;
+    __syncthreads();
+  }
+}
+
+// Phase 3: inclusive scan inside each block plus its block offset.
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_apply(uint32_t* __restrict__ a, uint32_t N, uint32_t nb, const uint32_t* __restrict__ bsum) {
+  uint32_t r = blockIdx.y;
+  uint32_t* p = a + (size_t)r * (N + 1) + 1;
+  uint32_t start = blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    uint32_t i = start + k;
+    v[k] = i < N ? p[i] : 0;
+    s += v[k];
+  }
+  __shared__ uint32_t tot;
+  uint32_t ex = block_excl_scan(s, &tot) + bsum[(size_t)r * nb + blockIdx.x];
+  for (int k = 0; k < kScanItems; ++k) {
+    uint32_t i = start + k;
+    ex += v[k];
+    if (i < N) p[i] = ex;
+  }
+}
+
+// Scatter: assertion (x, y) of role r becomes (y, x) of r^-.  Row order inside
+// an inverse row follows the atomics and is not fixed; evaluation results do
+// not depend on it.
+__global__ void k_scatter_inverse(const uint32_t* __restrict__ fwd_off, const int32_t* __restrict__ tg,
+                                  const uint64_t* __restrict__ base, uint32_t N,
+                                  uint32_t* __restrict__ cursor, int32_t* __restrict__ inv_tg) {
+  uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t r = blockIdx.y;
+  if (x >= N) return;
+  const uint32_t* fo = fwd_off + (size_t)r * (N + 1);
+  const int32_t* t = tg + base[r];
+  int32_t* it = inv_tg + base[r];
+  uint32_t* cur = cursor + (size_t)r * (N + 1);
+  for (uint32_t e = fo[x]; e < fo[x + 1]; ++e) {
+    uint32_t y = (uint32_t)t[e];
+    uint32_t pos = atomicAdd(cur + y, 1u);
+    it[pos] = (int32_t)x;
+  }
+}
+
+struct DerivedLayout {
+  size_t fwd_off, inv_off, inv_tg, cursor, bsum, base, meta, total;
+  uint32_t nb;
+};
+
+static DerivedLayout layout_for(const hth_kb_desc& d) {
+  DerivedLayout L{};
+  size_t R = d.n_roles, N = d.n_individuals;
+  size_t offs = align_up(R * (N + 1) * 4, 256);
+  L.nb = (uint32_t)((N + kScanBlock - 1) / kScanBlock);
+  size_t at = 0;
+  L.fwd_off = at; at += offs;
+  L.inv_off = at; at += offs;
+  L.inv_tg = at; at += align_up((size_t)d.n_edges * 4, 256);
+  L.cursor = at; at += offs;
+  L.bsum = at; at += align_up(R * L.nb * 4 + 4, 256);
+  L.base = at; at += align_up((R + 1) * 8, 256);
+  L.meta = at; at += align_up((4 + 2 * R) * 4, 256);
+  L.total = at;
+  return L;
+}
+
+static hth_status check_desc(const hth_kb_desc* d) {
+  if (!d) return fail(HTH_E_INVALID, "desc is NULL");
+  if (d->n_individuals == 0 || d->n_individuals >= (1u << 31))
+    return fail(HTH_E_RANGE, "n_individuals must be in [1, 2^31)");
+  uint32_t W = (d->n_individuals + 63) / 64;
+  if (d->stride_words < W || d->stride_words % 8)
+    return fail(HTH_E_INVALID, "stride_words must be >= ceil(N/64) and a multiple of 8");
+  if (d->n_concepts && !d->concept_bits) return fail(HTH_E_INVALID, "concept_bits is NULL");
+  if (d->n_roles && (!d->role_offsets || (d->n_edges && !d->role_targets)))
+    return fail(HTH_E_INVALID, "role arrays are NULL");
+  if (d->n_roles > 65535) return fail(HTH_E_RANGE, "at most 65535 roles");
+  if (d->n_edges >= (1ull << 40)) return fail(HTH_E_RANGE, "too many assertions");
+  if (d->n_data && !d->data) return fail(HTH_E_INVALID, "data is NULL");
+  if (!d->pos_bits || !d->neg_bits) return fail(HTH_E_INVALID, "example rows are NULL");
+  if (d->n_concepts >= (1u << 26)) return fail(HTH_E_RANGE, "too many concepts");
+  return HTH_OK;
+}
+
+}  // namespace hth
+
+using namespace hth;
+
+extern "C" hth_status hth_kb_derived_bytes(const hth_kb_desc* desc, size_t* bytes) {
+  hth_status s = check_desc(desc);
+  if (s) return s;
+  if (!bytes) return fail(HTH_E_INVALID, "bytes is NULL");
+  *bytes = layout_for(*desc).total;
+  return HTH_OK;
+}
+
+static hth_status kb_build(hth_kb_s* kb, char* derived, hipStream_t st) {
+  const hth_kb_desc& d = kb->d;
+  const uint32_t R = d.n_roles, N = kb->N;
+  DerivedLayout L = layout_for(d);
+  kb->fwd_off = reinterpret_cast<uint32_t*>(derived + L.fwd_off);
+  kb->inv_off = reinterpret_cast<uint32_t*>(derived + L.inv_off);
+  kb->inv_tg = reinterpret_cast<int32_t*>(derived + L.inv_tg);
+  uint32_t* cursor = reinterpret_cast<uint32_t*>(derived + L.cursor);
+  uint32_t* bsum = reinterpret_cast<uint32_t*>(derived + L.bsum);
+  uint64_t* base = reinterpret_cast<uint64_t*>(derived + L.base);
+  uint32_t* meta = reinterpret_cast<uint32_t*>(derived + L.meta);
+  uint32_t* flags = meta;
+  uint32_t* maxdeg = meta + 4;   // [2][R]
+  kb->role_base_dev = base;
+
+  const size_t offs = (size_t)R * (N + 1);
+  auto fill = [&](uint32_t* p, size_t n, uint32_t v) {
+    if (!n) return;
+    unsigned g = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_fill_u32, dim3(g), dim3(256), 0, st, p, n, v);
+  };
+  fill(meta, 4 + 2 * R, 0);
+  const uint32_t tb = 256;
+  // padding of concept rows and example rows
+  if (d.n_concepts)
+    hipLaunchKernelGGL(k_check_padding, dim3((d.n_concepts + tb - 1) / tb), dim3(tb), 0, st,
+                       d.concept_bits, d.n_concepts, kb->W, kb->S, kb->tail, flags);
+  hipLaunchKernelGGL(k_check_padding, dim3(1), dim3(1), 0, st, d.pos_bits, 1u, kb->W, kb->S,
+                     kb->tail, flags);
+  hipLaunchKernelGGL(k_check_padding, dim3(1), dim3(1), 0, st, d.neg_bits, 1u, kb->W, kb->S,
+                     kb->tail, flags);
+  kb->role_base.assign(R + 1, 0);
+  kb->max_deg[0].assign(R, 0);
+  kb->max_deg[1].assign(R, 0);
+  if (R) {
+    hipLaunchKernelGGL(k_gather_bases, dim3((R + 255) / 256), dim3(256), 0, st, d.role_offsets,
+                       R, N, base);
+    HTH_HIP(hipGetLastError());
+    HTH_HIP(hipMemcpyAsync(kb->role_base.data(), base, (R + 1) * 8, hipMemcpyDeviceToHost, st));
+    HTH_HIP(hipStreamSynchronize(st));
+    if (kb->role_base[0] != 0) return fail(HTH_E_INVALID, "role_offsets[0][0] must be 0");
+    if (kb->role_base[R] != d.n_edges)
+      return fail(HTH_E_INVALID, "role_offsets[R-1][N] must equal n_edges");
+    for (uint32_t r = 0; r < R; ++r) {
+      if (kb->role_base[r + 1] < kb->role_base[r])
+        return fail(HTH_E_INVALID, "role offsets decrease between roles");
+      if (kb->role_base[r + 1] - kb->role_base[r] >= (1ull << 32))
+        return fail(HTH_E_RANGE, "a role has 2^32 or more assertions");
+    }
+    fill(kb->inv_off, offs, 0);
+    dim3 g((N + tb - 1) / tb, R);
+    hipLaunchKernelGGL(k_validate_rows, g, dim3(tb), 0, st, d.role_offsets, d.role_targets, base,
+                       N, kb->fwd_off, kb->inv_off, maxdeg, flags);
+    HTH_HIP(hipGetLastError());
+    uint32_t hflags = 0;
+    HTH_HIP(hipMemcpyAsync(&hflags, flags, 4, hipMemcpyDeviceToHost, st));
+    HTH_HIP(hipStreamSynchronize(st));
+    if (hflags) {
+      std::string m = "invalid knowledge base:";
+      if (hflags & F_NONMONO) m += " role offsets not monotone;";
+      if (hflags & F_TARGET) m += " role target outside [0, N);";
+      if (hflags & F_ORDER) m += " role targets not strictly increasing in a row;";
+      if (hflags & F_PAD) m += " padding bits set in a bit row;";
+      return fail(HTH_E_INVALID, m);
+    }
+    dim3 gs(L.nb, R);
+    hipLaunchKernelGGL(k_scan_sums, gs, dim3(kScanThreads), 0, st, kb->inv_off, N, L.nb, bsum,
+                       maxdeg + R);
+    hipLaunchKernelGGL(k_scan_block_sums, dim3(R), dim3(kScanThreads), 0, st, bsum, L.nb);
+    hipLaunchKernelGGL(k_scan_apply, gs, dim3(kScanThreads), 0, st, kb->inv_off, N, L.nb, bsum);
+    {
+      unsigned gg = (unsigned)std::min<size_t>((offs + 255) / 256, 65536);
+      hipLaunchKernelGGL(k_copy_u32, dim3(gg), dim3(256), 0, st, kb->inv_off, cursor, offs);
+    }
+    hipLaunchKernelGGL(k_scatter_inverse, g, dim3(tb), 0, st, kb->fwd_off, d.role_targets, base,
+                       N, cursor, kb->inv_tg);
+    HTH_HIP(hipGetLastError());
+    HTH_HIP(hipMemcpyAsync(kb->max_deg[0].data(), maxdeg, R * 4, hipMemcpyDeviceToHost, st));
+    HTH_HIP(hipMemcpyAsync(kb->max_deg[1].data(), maxdeg + R, R * 4, hipMemcpyDeviceToHost, st));
+  }
+  uint32_t hflags = 0;
+  HTH_HIP(hipMemcpyAsync(&hflags, flags, 4, hipMemcpyDeviceToHost, st));
+  HTH_HIP(hipStreamSynchronize(st));
+  if (hflags & F_PAD) return fail(HTH_E_INVALID, "invalid knowledge base: padding bits set in a bit row");
+  return HTH_OK;
+}
+
+extern "C" hth_status hth_kb_create(const hth_kb_desc* desc, void* derived, size_t derived_bytes,
+                                    void* stream, hth_kb* out) {
+  hth_status s = check_desc(desc);
+  if (s) return s;
+  if (!out) return fail(HTH_E_INVALID, "out is NULL");
+  DerivedLayout L = layout_for(*desc);
+  if (!derived || derived_bytes < L.total)
+    return fail(HTH_E_NOMEM, "derived buffer smaller than hth_kb_derived_bytes");
+  if (reinterpret_cast<uintptr_t>(derived) % 256)
+    return fail(HTH_E_INVALID, "derived buffer must be 256-byte aligned");
+  hth_kb_s* kb = new (std::nothrow) hth_kb_s();
+  if (!kb) return fail(HTH_E_NOMEM, "host allocation failed");
+  kb->d = *desc;
+  kb->N = desc->n_individuals;
+  kb->W = (kb->N + 63) / 64;
+  kb->S = desc->stride_words;
+  kb->tail = (kb->N & 63) ? ((1ull << (kb->N & 63)) - 1) : ~0ull;
+  kb->pos = desc->pos_bits;
+  kb->neg = desc->neg_bits;
+  hipError_t e = hipGetDevice(&kb->device);
+  hipDeviceProp_t prop;
+  if (e == hipSuccess) e = hipGetDeviceProperties(&prop, kb->device);
+  if (e != hipSuccess) {
+    delete kb;
+    return hip_fail(e, "hipGetDeviceProperties");
+  }
+  kb->n_cu = prop.multiProcessorCount;
+  kb->lds_per_block = prop.sharedMemPerBlock;
+  s = kb_build(kb, static_cast<char*>(derived), static_cast<hipStream_t>(stream));
+  if (s) {
+    delete kb;
+    return s;
+  }
+  *out = kb;
+  return HTH_OK;
+}
+
+extern "C" hth_status hth_kb_set_examples(hth_kb kb, const uint64_t* pos, const uint64_t* neg) {
+  if (!kb) return fail(HTH_E_INVALID, "kb is NULL");
+  if (!pos || !neg) return fail(HTH_E_INVALID, "example rows are NULL");
+  std::lock_guard<std::mutex> g(kb->mu);
+  kb->pos = pos;
+  kb->neg = neg;
+  return HTH_OK;
+}
+
+extern "C" hth_status hth_kb_max_degree(hth_kb kb, uint32_t role, uint32_t inv, uint32_t* out) {
+  if (!kb || !out) return fail(HTH_E_INVALID, "NULL argument");
+  if (role >= kb->d.n_roles || inv > 1) return fail(HTH_E_RANGE, "role or direction out of range");
+  *out = kb->max_deg[inv][role];
+  return HTH_OK;
+}
+
+extern "C" hth_status hth_kb_destroy(hth_kb kb) {
+  delete kb;
+  return HTH_OK;
+}
+
+extern "C" hth_status hth_sync(void* stream) {
+  HTH_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+  HTH_HIP(hipGetLastError());
+  return HTH_OK;
+}
+
+extern "C" const char* hth_status_str(hth_status s) {
+  switch (s) {
+    case HTH_OK: return "HTH_OK";
+    case HTH_E_INVALID: return "HTH_E_INVALID";
+    case HTH_E_RANGE: return "HTH_E_RANGE";
+    case HTH_E_NOMEM: return "HTH_E_NOMEM";
+    case HTH_E_DEVICE: return "HTH_E_DEVICE";
+    case HTH_E_PLAN: return "HTH_E_PLAN";
+    case HTH_E_STATE: return "HTH_E_STATE";
+    case HTH_E_UNSUPPORTED: return "HTH_E_UNSUPPORTED";
+    default: return "HTH_E_UNKNOWN";
+  }
+}
+
+extern "C" size_t hth_last_error(char* buf, size_t n) {
+  const std::string& m = g_err;
+  if (buf && n) {
+    size_t k = std::min(n - 1, m.size());
+    std::memcpy(buf, m.data(), k);
+    buf[k] = 0;
+  }
+  return m.size();
+}

@@ -1,0 +1,472 @@
+// Plan compiler: validation, canonicalisation, hash-consing across the batch,
+// role-nesting levels, row assignment and region bytecode.
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+namespace hth {
+namespace {
+
+constexpr uint32_t kInf = 0xFFFFFFFFu;
+
+struct CNode {
+  uint8_t op = 0, inv = 0;
+  uint32_t arg = 0, q = 0;
+  uint32_t a = kNone;            // NOT / role child
+  uint32_t kid_off = 0, kid_n = 0;  // AND / OR children (canonical ids, sorted)
+};
+
+inline uint64_t mix(uint64_t h, uint64_t v) {
+  h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+  return h * 0xFF51AFD7ED558CCDull;
+}
+
+class Dag {
+ public:
+  std::vector<CNode> nodes;
+  std::vector<uint32_t> kids;
+
+  Dag() { table_.assign(1 << 12, kNone); }
+
+  uint32_t top() { return leaf(HTH_TOP, 0, 0, 0); }
+  uint32_t bot() { return leaf(HTH_BOT, 0, 0, 0); }
+  uint32_t leaf(uint8_t op, uint8_t inv, uint32_t arg, uint32_t q) {
+    CNode n;
+    n.op = op;
+    n.inv = inv;
+    n.arg = arg;
+    n.q = q;
+    return intern(n, nullptr, 0);
+  }
+  uint32_t mk_not(uint32_t c) {
+    const CNode& x = nodes[c];
+    if (x.op == HTH_NOT) return x.a;
+    if (x.op == HTH_TOP) return bot();
+    if (x.op == HTH_BOT) return top();
+    CNode n;
+    n.op = HTH_NOT;
+    n.a = c;
+    return intern(n, nullptr, 0);
+  }
+  uint32_t mk_role(uint8_t op, uint8_t inv, uint32_t r, uint32_t q, uint32_t c) {
+    if (op == HTH_ATLEAST && q == 0) return top();
+    CNode n;
+    n.op = op;
+    n.inv = inv;
+    n.arg = r;
+    n.q = (op == HTH_EXISTS || op == HTH_FORALL) ? 0 : q;
+    n.a = c;
+    return intern(n, nullptr, 0);
+  }
+  uint32_t mk_nary(uint8_t op, std::vector<uint32_t>& in) {
+    const uint8_t ident = op == HTH_AND ? HTH_TOP : HTH_BOT;
+    const uint8_t absorb = op == HTH_AND ? HTH_BOT : HTH_TOP;
+    tmp_.clear();
+    for (uint32_t c : in) {
+      const CNode& x = nodes[c];
+      if (x.op == op) {
+        for (uint32_t j = 0; j < x.kid_n; ++j) tmp_.push_back(kids[x.kid_off + j]);
+      } else {
+        tmp_.push_back(c);
+      }
+    }
+    std::vector<uint32_t> v;
+    v.reserve(tmp_.size());
+    for (uint32_t c : tmp_) {
+      uint8_t o = nodes[c].op;
+      if (o == absorb) return c;
+      if (o == ident) continue;
+      v.push_back(c);
+    }
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    if (v.empty()) return op == HTH_AND ? top() : bot();
+    if (v.size() == 1) return v[0];
+    CNode n;
+    n.op = op;
+    return intern(n, v.data(), (uint32_t)v.size());
+  }
+
+ private:
+  std::vector<uint32_t> table_;
+  std::vector<uint32_t> tmp_;
+
+  static uint64_t hash_of(const CNode& n, const uint32_t* k, uint32_t kn) {
+    uint64_t h = mix(0x1234567ull, n.op | (uint64_t)n.inv << 8);
+    h = mix(h, n.arg);
+    h = mix(h, n.q);
+    h = mix(h, n.a);
+    for (uint32_t i = 0; i < kn; ++i) h = mix(h, k[i]);
+    return h;
+  }
+  bool same(const CNode& x, const CNode& n, const uint32_t* k, uint32_t kn) const {
+    if (x.op != n.op || x.inv != n.inv || x.arg != n.arg || x.q != n.q || x.a != n.a ||
+        x.kid_n != kn)
+      return false;
+    return kn == 0 || std::memcmp(&kids[x.kid_off], k, kn * 4) == 0;
+  }
+  uint32_t intern(CNode n, const uint32_t* k, uint32_t kn) {
+    if (nodes.size() * 2 >= table_.size()) rehash();
+    uint64_t h = hash_of(n, k, kn);
+    size_t mask = table_.size() - 1;
+    size_t i = h & mask;
+    while (table_[i] != kNone) {
+      if (same(nodes[table_[i]], n, k, kn)) return table_[i];
+      i = (i + 1) & mask;
+    }
+    n.kid_off = (uint32_t)kids.size();
+    n.kid_n = kn;
+    kids.insert(kids.end(), k, k + kn);
+    uint32_t id = (uint32_t)nodes.size();
+    nodes.push_back(n);
+    table_[i] = id;
+    return id;
+  }
+  void rehash() {
+    std::vector<uint32_t> t(table_.size() * 2, kNone);
+    size_t mask = t.size() - 1;
+    for (uint32_t id = 0; id < nodes.size(); ++id) {
+      const CNode& n = nodes[id];
+      size_t i = hash_of(n, kids.data() + n.kid_off, n.kid_n) & mask;
+      while (t[i] != kNone) i = (i + 1) & mask;
+      t[i] = id;
+    }
+    table_.swap(t);
+  }
+};
+
+inline bool is_role(uint8_t op) { return op >= HTH_EXISTS && op <= HTH_EXACTLY; }
+inline bool is_data(uint8_t op) { return op == HTH_DATA_GE || op == HTH_DATA_LE; }
+inline bool is_leaflike(uint8_t op) { return op == HTH_ATOM || is_data(op) || is_role(op); }
+
+struct Compiler {
+  const hth_kb_s& kb;
+  Dag dag;
+  std::vector<uint32_t> roots;
+  // per canonical node
+  std::vector<int32_t> height;   // role nesting below (and including) the node, -1 = none
+  std::vector<uint8_t> live;
+  std::vector<uint32_t> row;     // bit row of data / role / materialised nodes
+  std::vector<int32_t> depth;    // stack depth of the node's region program
+  uint32_t n_slots = 0;
+  uint32_t zero_row = kNone;
+
+  explicit Compiler(const hth_kb_s& k) : kb(k) {}
+
+  hth_status add_hypothesis(const hth_node* nd, uint32_t nn, const uint32_t* children,
+                            uint32_t n_children, uint32_t h) {
+    if (nn == 0) return fail(HTH_E_PLAN, "hypothesis " + std::to_string(h) + " has no nodes");
+    std::vector<uint32_t> map(nn);
+    std::vector<uint32_t> ks;
+    const hth_kb_desc& d = kb.d;
+    for (uint32_t i = 0; i < nn; ++i) {
+      const hth_node& x = nd[i];
+      auto bad = [&](hth_status c, const char* why) {
+        return fail(c, "hypothesis " + std::to_string(h) + " node " + std::to_string(i) + ": " + why);
+      };
+      switch (x.op) {
+        case HTH_TOP: map[i] = dag.top(); break;
+        case HTH_BOT: map[i] = dag.bot(); break;
+        case HTH_ATOM:
+          if (x.arg >= d.n_concepts) return bad(HTH_E_RANGE, "concept id out of range");
+          map[i] = dag.leaf(HTH_ATOM, 0, x.arg, 0);
+          break;
+        case HTH_NOT:
+          if (x.child >= i) return bad(HTH_E_PLAN, "child index not before its parent");
+          map[i] = dag.mk_not(map[x.child]);
+          break;
+        case HTH_AND:
+        case HTH_OR: {
+          if ((uint64_t)x.child + x.arity > n_children)
+            return bad(HTH_E_RANGE, "children range outside the children array");
+          ks.clear();
+          for (uint32_t j = 0; j < x.arity; ++j) {
+            uint32_t c = children[x.child + j];
+            if (c >= i) return bad(HTH_E_PLAN, "child index not before its parent");
+            ks.push_back(map[c]);
+          }
+          map[i] = dag.mk_nary(x.op, ks);
+          break;
+        }
+        case HTH_EXISTS:
+        case HTH_FORALL:
+        case HTH_ATLEAST:
+        case HTH_ATMOST:
+        case HTH_EXACTLY:
+          if (x.arg >= d.n_roles) return bad(HTH_E_RANGE, "role id out of range");
+          if (x.inv > 1) return bad(HTH_E_INVALID, "inv must be 0 or 1");
+          if (x.child >= i) return bad(HTH_E_PLAN, "child index not before its parent");
+          if (x.op >= HTH_ATLEAST && x.q.n > 0x7FFFFFFFu) return bad(HTH_E_RANGE, "n > 2^31-1");
+          map[i] = dag.mk_role(x.op, x.inv, x.arg, x.q.n, map[x.child]);
+          break;
+        case HTH_DATA_GE:
+        case HTH_DATA_LE: {
+          if (x.arg >= d.n_data) return bad(HTH_E_RANGE, "property id out of range");
+          if (std::isnan(x.q.t)) return bad(HTH_E_INVALID, "threshold is NaN");
+          uint32_t bits;
+          std::memcpy(&bits, &x.q.t, 4);
+          map[i] = dag.leaf(x.op, 0, x.arg, bits);
+          break;
+        }
+        default:
+          return bad(HTH_E_INVALID, "unknown op");
+      }
+    }
+    roots.push_back(map[nn - 1]);
+    return HTH_OK;
+  }
+
+  uint32_t new_row() { return kb.d.n_concepts + n_slots++; }
+
+  int32_t region_depth(uint32_t v) {
+    if (depth[v] >= 0) return depth[v];
+    const CNode& n = dag.nodes[v];
+    int32_t r = 1;
+    if (n.op == HTH_NOT) {
+      r = is_leaflike(dag.nodes[n.a].op) ? 1 : region_depth(n.a);
+    } else if (n.op == HTH_AND || n.op == HTH_OR) {
+      std::vector<int32_t> ds;
+      for (uint32_t j = 0; j < n.kid_n; ++j) ds.push_back(region_depth(dag.kids[n.kid_off + j]));
+      std::sort(ds.rbegin(), ds.rend());
+      r = 0;
+      for (size_t j = 0; j < ds.size(); ++j) r = std::max<int32_t>(r, ds[j] + (j ? 1 : 0));
+    }
+    depth[v] = r;
+    return r;
+  }
+
+  uint32_t leaf_row(uint32_t v) const {
+    const CNode& n = dag.nodes[v];
+    return n.op == HTH_ATOM ? n.arg : row[v];
+  }
+
+  void emit(uint32_t v, std::vector<uint32_t>& code) {
+    const CNode& n = dag.nodes[v];
+    switch (n.op) {
+      case HTH_TOP: code.push_back(rp_ins(RP_TOP, 0, 0)); return;
+      case HTH_BOT: code.push_back(rp_ins(RP_BOT, 0, 0)); return;
+      case HTH_NOT:
+        if (is_leaflike(dag.nodes[n.a].op)) {
+          code.push_back(rp_ins(RP_LEAF, 1, leaf_row(n.a)));
+        } else {
+          emit(n.a, code);
+          code.push_back(rp_ins(RP_NOT, 0, 0));
+        }
+        return;
+      case HTH_AND:
+      case HTH_OR: {
+        std::vector<uint32_t> ks(dag.kids.begin() + n.kid_off, dag.kids.begin() + n.kid_off + n.kid_n);
+        std::stable_sort(ks.begin(), ks.end(),
+                         [&](uint32_t a, uint32_t b) { return region_depth(a) > region_depth(b); });
+        emit(ks[0], code);
+        for (size_t j = 1; j < ks.size(); ++j) {
+          emit(ks[j], code);
+          code.push_back(rp_ins(n.op == HTH_AND ? RP_AND : RP_OR, 0, 0));
+        }
+        return;
+      }
+      default:
+        code.push_back(rp_ins(RP_LEAF, 0, leaf_row(v)));
+        return;
+    }
+  }
+
+  hth_status program(uint32_t v, std::vector<uint32_t>& code, uint32_t& off, uint32_t& len) {
+    if (region_depth(v) > kStackDepth)
+      return fail(HTH_E_UNSUPPORTED, "boolean region nested deeper than 16 operand levels");
+    off = (uint32_t)code.size();
+    emit(v, code);
+    len = (uint32_t)code.size() - off;
+    return HTH_OK;
+  }
+
+  hth_status build(const PlanOptions& opt, Plan& P) {
+    const size_t nv = dag.nodes.size();
+    height.assign(nv, -1);
+    live.assign(nv, 0);
+    row.assign(nv, kNone);
+    depth.assign(nv, -1);
+    for (uint32_t v = 0; v < nv; ++v) {
+      const CNode& n = dag.nodes[v];
+      if (n.op == HTH_NOT) height[v] = height[n.a];
+      else if (n.op == HTH_AND || n.op == HTH_OR) {
+        int32_t h = -1;
+        for (uint32_t j = 0; j < n.kid_n; ++j) h = std::max(h, height[dag.kids[n.kid_off + j]]);
+        height[v] = h;
+      } else if (is_role(n.op)) {
+        height[v] = height[n.a] + 1;
+      }
+    }
+    for (uint32_t r : roots) live[r] = 1;
+    for (size_t i = nv; i-- > 0;) {
+      if (!live[i]) continue;
+      const CNode& n = dag.nodes[i];
+      if (n.a != kNone) live[n.a] = 1;
+      for (uint32_t j = 0; j < n.kid_n; ++j) live[dag.kids[n.kid_off + j]] = 1;
+    }
+    int32_t max_level = -1;
+    for (uint32_t v = 0; v < nv; ++v) {
+      if (!live[v]) continue;
+      const CNode& n = dag.nodes[v];
+      if (is_data(n.op)) {
+        row[v] = new_row();
+        ThrTask t;
+        t.prop = n.arg;
+        t.le = n.op == HTH_DATA_LE;
+        std::memcpy(&t.t, &n.q, 4);
+        t.out_row = row[v];
+        P.thr.push_back(t);
+      } else if (is_role(n.op)) {
+        row[v] = new_row();
+        max_level = std::max(max_level, height[v]);
+        P.n_role_nodes++;
+      }
+    }
+    P.levels.assign(max_level + 1, PlanLevel());
+    // role children: resolve to (row, negation), materialising compound children
+    std::vector<uint32_t> matrow(nv, kNone);
+    struct Pending { uint32_t v, child_row, neg; };
+    std::vector<std::vector<Pending>> per_level(max_level + 1);
+    for (uint32_t v = 0; v < nv; ++v) {
+      if (!live[v] || !is_role(dag.nodes[v].op)) continue;
+      const CNode& n = dag.nodes[v];
+      const uint32_t c = n.a;
+      const CNode& cn = dag.nodes[c];
+      uint32_t crow, neg = 0;
+      if (cn.op == HTH_TOP || cn.op == HTH_BOT) {
+        if (zero_row == kNone) {
+          zero_row = new_row();
+          RegionTask z;
+          z.code_off = (uint32_t)P.code.size();
+          P.code.push_back(rp_ins(RP_BOT, 0, 0));
+          z.code_len = 1;
+          z.out_row = zero_row;
+          z.cover = kNone;
+          P.levels[0].mat.push_back(z);
+        }
+        crow = zero_row;
+        neg = cn.op == HTH_TOP;
+      } else if (is_leaflike(cn.op)) {
+        crow = leaf_row(c);
+      } else if (cn.op == HTH_NOT && is_leaflike(dag.nodes[cn.a].op)) {
+        crow = leaf_row(cn.a);
+        neg = 1;
+      } else {
+        if (matrow[c] == kNone) {
+          matrow[c] = new_row();
+          RegionTask m;
+          hth_status s = program(c, P.code, m.code_off, m.code_len);
+          if (s) return s;
+          m.out_row = matrow[c];
+          m.cover = kNone;
+          P.levels[height[v]].mat.push_back(m);
+        }
+        crow = matrow[c];
+      }
+      per_level[height[v]].push_back({v, crow, neg});
+    }
+    // role tasks, grouped per (role, direction) when the bucket is large
+    const uint64_t t_stride = align_up(kb.N, 64);
+    for (int32_t L = 0; L <= max_level; ++L) {
+      PlanLevel& PL = P.levels[L];
+      auto& items = per_level[L];
+      std::stable_sort(items.begin(), items.end(), [&](const Pending& a, const Pending& b) {
+        const CNode& x = dag.nodes[a.v];
+        const CNode& y = dag.nodes[b.v];
+        return x.arg != y.arg ? x.arg < y.arg : x.inv < y.inv;
+      });
+      size_t i = 0;
+      while (i < items.size()) {
+        size_t j = i;
+        const CNode& first = dag.nodes[items[i].v];
+        while (j < items.size() && dag.nodes[items[j].v].arg == first.arg &&
+               dag.nodes[items[j].v].inv == first.inv)
+          ++j;
+        const bool group = (j - i) >= opt.group_min;
+        for (size_t g0 = i; g0 < j; g0 += group ? kMaxK : 1) {
+          size_t g1 = group ? std::min(j, g0 + kMaxK) : g0 + 1;
+          if (group) {
+            GroupTask gt;
+            gt.role = first.arg;
+            gt.inv = first.inv;
+            gt.k = (uint32_t)(g1 - g0);
+            gt.first = (uint32_t)PL.members.size();
+            gt.t_off = PL.t_words;
+            PL.t_words += t_stride;
+            PL.groups.push_back(gt);
+          }
+          for (size_t q = g0; q < g1; ++q) {
+            const Pending& it = items[q];
+            const CNode& n = dag.nodes[it.v];
+            uint32_t lo, hi, neg = it.neg;
+            switch (n.op) {
+              case HTH_EXISTS: lo = 1; hi = kInf; break;
+              case HTH_FORALL: lo = 0; hi = 0; neg ^= 1; break;
+              case HTH_ATLEAST: lo = n.q; hi = kInf; break;
+              case HTH_ATMOST: lo = 0; hi = n.q; break;
+              default: lo = n.q; hi = n.q; break;
+            }
+            uint32_t sat = hi == kInf ? lo : hi + 1;
+            if (group) {
+              GroupMember m{};
+              m.child_row = it.child_row;
+              m.neg = neg;
+              m.lo = lo;
+              m.hi = hi;
+              m.sat = sat;
+              m.out_row = row[it.v];
+              PL.members.push_back(m);
+            } else {
+              RoleTask t;
+              t.role = n.arg;
+              t.inv = n.inv;
+              t.child_row = it.child_row;
+              t.neg = neg;
+              t.lo = lo;
+              t.hi = hi;
+              t.sat = sat;
+              t.out_row = row[it.v];
+              PL.roles.push_back(t);
+            }
+          }
+        }
+        i = j;
+      }
+      P.t_words = std::max(P.t_words, PL.t_words);
+    }
+    // roots with coverage
+    for (uint32_t h = 0; h < roots.size(); ++h) {
+      RegionTask t;
+      hth_status s = program(roots[h], P.code, t.code_off, t.code_len);
+      if (s) return s;
+      t.out_row = opt.instances ? kInstances : kNone;
+      t.cover = h;
+      P.roots.push_back(t);
+    }
+    P.n_slots = n_slots;
+    P.n_canonical = (uint32_t)nv;
+    return HTH_OK;
+  }
+};
+
+}  // namespace
+
+hth_status compile_plan(const hth_kb_s& kb, const hth_node* nodes, const uint32_t* hyp_off,
+                        uint32_t n_hyps, const uint32_t* children, uint32_t n_children,
+                        const PlanOptions& opt, Plan& out) {
+  out = Plan();
+  Compiler c(kb);
+  for (uint32_t h = 0; h < n_hyps; ++h) {
+    uint32_t b = hyp_off[h], e = hyp_off[h + 1];
+    if (e < b) return fail(HTH_E_INVALID, "hyp_node_offsets decrease");
+    hth_status s = c.add_hypothesis(nodes + b, e - b, children, n_children, h);
+    if (s) return s;
+    out.n_input_nodes += e - b;
+  }
+  return c.build(opt, out);
+}
+
+}  // namespace hth

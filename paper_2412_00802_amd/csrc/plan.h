@@ -1,0 +1,45 @@
+// Host-side evaluation plans: a batch of postfix hypotheses becomes one
+// canonical DAG (shared subexpressions evaluated once) scheduled by role
+// nesting level.  The paper generates an evaluation plan per hypothesis on the
+// CPU before running its DL operations (Section 4, "evaluation plan").
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hth_internal.h"
+
+namespace hth {
+
+struct PlanOptions {
+  bool instances = false;        // write the (single) root's instance set
+  uint32_t group_min = 0xFFFFFFFFu;  // (role, dir, level) buckets with at least this many
+                                     // role nodes use a shared CSR pass; others run alone
+};
+
+struct PlanLevel {
+  std::vector<RegionTask> mat;      // children materialised before this level's role passes
+  std::vector<RoleTask> roles;      // single role nodes (k = 1)
+  std::vector<GroupTask> groups;    // shared passes (k <= 64)
+  std::vector<GroupMember> members;
+  uint64_t t_words = 0;             // T area used by this level's groups (words)
+};
+
+struct Plan {
+  std::vector<ThrTask> thr;
+  std::vector<uint32_t> code;
+  std::vector<PlanLevel> levels;
+  std::vector<RegionTask> roots;
+  uint32_t n_slots = 0;
+  uint64_t t_words = 0;             // max over levels
+  // statistics
+  uint32_t n_input_nodes = 0, n_canonical = 0, n_role_nodes = 0;
+};
+
+// Compile hypotheses nodes[hyp_off[h] .. hyp_off[h+1]) (local child indices).
+hth_status compile_plan(const hth_kb_s& kb, const hth_node* nodes, const uint32_t* hyp_off,
+                        uint32_t n_hyps, const uint32_t* children, uint32_t n_children,
+                        const PlanOptions& opt, Plan& out);
+
+}  // namespace hth

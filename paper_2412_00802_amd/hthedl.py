@@ -1,0 +1,381 @@
+"""Thin ctypes binding of libhthedl.so.
+
+The functions named ``hth_*`` mirror the C entry points of ``include/hthedl.h``
+one to one and only marshal arguments: every step of an evaluation runs in the
+library's HIP kernels.  PyTorch provides the device memory and the stream.
+If the library is not built, importing works but the first call raises.
+
+``Engine`` bundles the usual sequence (upload a knowledge base, create the
+handle, size a workspace, evaluate).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhthedl.so")
+
+HTH_OK = 0
+STATUS = {0: "HTH_OK", -1: "HTH_E_INVALID", -2: "HTH_E_RANGE", -3: "HTH_E_NOMEM",
+          -4: "HTH_E_DEVICE", -5: "HTH_E_PLAN", -6: "HTH_E_STATE", -7: "HTH_E_UNSUPPORTED"}
+
+OPS = {"top": 0, "bot": 1, "atom": 2, "not": 3, "and": 4, "or": 5, "exists": 6, "forall": 7,
+       "atleast": 8, "atmost": 9, "exactly": 10, "dge": 11, "dle": 12}
+
+NODE_DTYPE = np.dtype([("op", np.uint8), ("inv", np.uint8), ("arity", np.uint16),
+                       ("arg", np.uint32), ("child", np.uint32), ("q", np.uint32)])
+assert NODE_DTYPE.itemsize == 16
+
+EXPORTED = ["hth_kb_derived_bytes", "hth_kb_create", "hth_kb_set_examples", "hth_kb_max_degree",
+            "hth_kb_destroy", "hth_workspace_bytes", "hth_eval_one", "hth_eval_batch",
+            "hth_sync", "hth_status_str", "hth_last_error", "hth_profile_begin",
+            "hth_profile_end"]
+
+
+class HthError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class KBDesc(ctypes.Structure):
+    _fields_ = [("n_individuals", ctypes.c_uint32), ("stride_words", ctypes.c_uint32),
+                ("n_concepts", ctypes.c_uint32), ("concept_bits", ctypes.c_void_p),
+                ("n_roles", ctypes.c_uint32), ("n_edges", ctypes.c_uint64),
+                ("role_offsets", ctypes.c_void_p), ("role_targets", ctypes.c_void_p),
+                ("n_data", ctypes.c_uint32), ("data", ctypes.c_void_p),
+                ("pos_bits", ctypes.c_void_p), ("neg_bits", ctypes.c_void_p)]
+
+
+class ProfEntry(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_uint64), ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+HTH_K_NUM = 8
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Open libhthedl.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2412_00802_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, U32, U64, S = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
+        sig = {
+            "hth_kb_derived_bytes": [ctypes.POINTER(KBDesc), ctypes.POINTER(S)],
+            "hth_kb_create": [ctypes.POINTER(KBDesc), P, S, P, ctypes.POINTER(P)],
+            "hth_kb_set_examples": [P, P, P],
+            "hth_kb_max_degree": [P, U32, U32, ctypes.POINTER(U32)],
+            "hth_kb_destroy": [P],
+            "hth_workspace_bytes": [P, U32, U32, ctypes.POINTER(S)],
+            "hth_eval_one": [P, P, U32, P, U32, P, S, P, P, P],
+            "hth_eval_batch": [P, P, P, U32, P, U32, P, S, P, P],
+            "hth_sync": [P],
+            "hth_profile_begin": [P],
+            "hth_profile_end": [P, ctypes.POINTER(ProfEntry)],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int32
+        L.hth_status_str.argtypes = [ctypes.c_int32]
+        L.hth_status_str.restype = ctypes.c_char_p
+        L.hth_last_error.argtypes = [ctypes.c_char_p, S]
+        L.hth_last_error.restype = S
+        _lib = L
+    return _lib
+
+
+def hth_last_error() -> str:
+    buf = ctypes.create_string_buffer(1024)
+    lib().hth_last_error(buf, 1024)
+    return buf.value.decode(errors="replace")
+
+
+def hth_status_str(status: int) -> str:
+    return lib().hth_status_str(status).decode()
+
+
+def _check(status: int) -> None:
+    if status != HTH_OK:
+        raise HthError(status, hth_last_error())
+
+
+def _ptr(x) -> Optional[int]:
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _np_ptr(a: Optional[np.ndarray]) -> Optional[int]:
+    if a is None or a.size == 0:
+        return None
+    return a.ctypes.data
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return stream if isinstance(stream, int) else stream.cuda_stream
+
+
+# ---------------------------------------------------------------------------
+# entry points (same names as the C ABI)
+# ---------------------------------------------------------------------------
+
+
+def hth_kb_derived_bytes(desc: KBDesc) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().hth_kb_derived_bytes(ctypes.byref(desc), ctypes.byref(out)))
+    return out.value
+
+
+def hth_kb_create(desc: KBDesc, derived, derived_bytes: int, stream=None) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(lib().hth_kb_create(ctypes.byref(desc), _ptr(derived), derived_bytes, _stream(stream),
+                               ctypes.byref(h)))
+    return h
+
+
+def hth_kb_set_examples(kb, pos, neg) -> None:
+    _check(lib().hth_kb_set_examples(kb, _ptr(pos), _ptr(neg)))
+
+
+def hth_kb_max_degree(kb, role: int, inv: int) -> int:
+    out = ctypes.c_uint32()
+    _check(lib().hth_kb_max_degree(kb, role, inv, ctypes.byref(out)))
+    return out.value
+
+
+def hth_kb_destroy(kb) -> None:
+    _check(lib().hth_kb_destroy(kb))
+
+
+def hth_workspace_bytes(kb, max_nodes: int, max_hyps: int) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().hth_workspace_bytes(kb, max_nodes, max_hyps, ctypes.byref(out)))
+    return out.value
+
+
+def hth_eval_one(kb, nodes: np.ndarray, children: np.ndarray, ws, ws_bytes: int,
+                 d_instances, d_counts, stream=None) -> None:
+    nodes = np.ascontiguousarray(nodes, dtype=NODE_DTYPE)
+    children = np.ascontiguousarray(children, dtype=np.uint32)
+    _check(lib().hth_eval_one(kb, _np_ptr(nodes), nodes.shape[0], _np_ptr(children),
+                              children.shape[0], _ptr(ws), ws_bytes, _ptr(d_instances),
+                              _ptr(d_counts), _stream(stream)))
+
+
+def hth_eval_batch(kb, nodes: np.ndarray, offsets: np.ndarray, children: np.ndarray, ws,
+                   ws_bytes: int, d_counts, stream=None) -> None:
+    nodes = np.ascontiguousarray(nodes, dtype=NODE_DTYPE)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint32)
+    children = np.ascontiguousarray(children, dtype=np.uint32)
+    _check(lib().hth_eval_batch(kb, _np_ptr(nodes), _np_ptr(offsets), offsets.shape[0] - 1,
+                                _np_ptr(children), children.shape[0], _ptr(ws), ws_bytes,
+                                _ptr(d_counts), _stream(stream)))
+
+
+def hth_sync(stream=None) -> None:
+    _check(lib().hth_sync(_stream(stream)))
+
+
+def hth_profile_begin(kb) -> None:
+    _check(lib().hth_profile_begin(kb))
+
+
+def hth_profile_end(kb) -> List[dict]:
+    """Per kernel kind: launches, event-timed ms and algorithmic bytes."""
+    arr = (ProfEntry * HTH_K_NUM)()
+    _check(lib().hth_profile_end(kb, arr))
+    return [{"launches": int(e.launches), "ms": float(e.ms), "bytes": float(e.bytes)} for e in arr]
+
+
+profile_end = hth_profile_end
+
+
+# ---------------------------------------------------------------------------
+# hypothesis encoding: nested tuples -> postfix node arrays
+# ---------------------------------------------------------------------------
+
+
+def _f32_bits(t: float) -> int:
+    return int(np.array([t], dtype=np.float32).view(np.uint32)[0])
+
+
+def encode(h, nodes: list, children: list) -> int:
+    """Append hypothesis h in postfix order; return its root's local index."""
+    op = h[0]
+    code = OPS[op]
+    if op in ("top", "bot"):
+        nodes.append((code, 0, 0, 0, 0, 0))
+    elif op == "atom":
+        nodes.append((code, 0, 0, h[1], 0, 0))
+    elif op == "not":
+        c = encode(h[1], nodes, children)
+        nodes.append((code, 0, 0, 0, c, 0))
+    elif op in ("and", "or"):
+        cs = [encode(c, nodes, children) for c in h[1:]]
+        start = len(children)
+        children.extend(cs)
+        nodes.append((code, 0, len(cs), 0, start, 0))
+    elif op in ("exists", "forall"):
+        _, r, inv, c = h
+        ci = encode(c, nodes, children)
+        nodes.append((code, inv, 0, r, ci, 0))
+    elif op in ("atleast", "atmost", "exactly"):
+        _, k, r, inv, c = h
+        ci = encode(c, nodes, children)
+        nodes.append((code, inv, 0, r, ci, k))
+    elif op in ("dge", "dle"):
+        nodes.append((code, 0, 0, h[1], 0, _f32_bits(h[2])))
+    else:
+        raise ValueError(op)
+    return len(nodes) - 1
+
+
+def encode_one(h) -> Tuple[np.ndarray, np.ndarray]:
+    nodes: list = []
+    children: list = []
+    encode(h, nodes, children)
+    return np.array(nodes, dtype=NODE_DTYPE), np.array(children, dtype=np.uint32)
+
+
+def encode_batch(hyps: Sequence) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """-> (nodes, hyp_node_offsets [H+1], children); child indices are local."""
+    allnodes: List[tuple] = []
+    children: List[int] = []
+    offs = [0]
+    for h in hyps:
+        local: list = []
+        encode(h, local, children)
+        allnodes.extend(local)
+        offs.append(len(allnodes))
+    return (np.array(allnodes, dtype=NODE_DTYPE), np.array(offs, dtype=np.uint32),
+            np.array(children, dtype=np.uint32))
+
+
+# ---------------------------------------------------------------------------
+# engine: device-resident knowledge base + workspace
+# ---------------------------------------------------------------------------
+
+
+def stride_for(n: int) -> int:
+    w = (n + 63) // 64
+    return (w + 7) // 8 * 8
+
+
+class Engine:
+    """A knowledge base uploaded to one GPU, its handle and a workspace."""
+
+    def __init__(self, kb, device: str = "cuda:0", max_nodes: int = 1 << 14,
+                 max_hyps: int = 4096):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        lib()
+        n = int(kb.n)
+        self.n = n
+        self.W = (n + 63) // 64
+        self.S = stride_for(n)
+        dev = self.device
+
+        def padded(bits2d):
+            a = np.zeros((bits2d.shape[0], self.S), dtype=np.uint64)
+            a[:, : bits2d.shape[1]] = bits2d
+            return torch.from_numpy(a.view(np.int64)).to(dev)
+
+        cb = np.asarray(kb.concept_bits, dtype=np.uint64).reshape(-1, self.W)
+        self.concepts = padded(cb) if cb.shape[0] else torch.zeros((0, self.S), dtype=torch.int64, device=dev)
+        self.offsets = torch.from_numpy(np.ascontiguousarray(kb.role_offsets, dtype=np.int64)).to(dev)
+        self.targets = torch.from_numpy(np.ascontiguousarray(kb.role_targets, dtype=np.int32)).to(dev)
+        self.data = torch.from_numpy(np.ascontiguousarray(kb.data, dtype=np.float32)).to(dev)
+        self.pos = padded(np.asarray(kb.pos_bits, dtype=np.uint64)[None, :])[0]
+        self.neg = padded(np.asarray(kb.neg_bits, dtype=np.uint64)[None, :])[0]
+        self.n_pos = int(np.unpackbits(np.asarray(kb.pos_bits, dtype=np.uint64).view(np.uint8)).sum())
+        self.n_neg = int(np.unpackbits(np.asarray(kb.neg_bits, dtype=np.uint64).view(np.uint8)).sum())
+        d = KBDesc()
+        d.n_individuals = n
+        d.stride_words = self.S
+        d.n_concepts = int(self.concepts.shape[0])
+        d.concept_bits = _ptr(self.concepts) if d.n_concepts else None
+        d.n_roles = int(self.offsets.shape[0])
+        d.n_edges = int(self.targets.shape[0])
+        d.role_offsets = _ptr(self.offsets) if d.n_roles else None
+        d.role_targets = _ptr(self.targets) if d.n_edges else None
+        d.n_data = int(self.data.shape[0])
+        d.data = _ptr(self.data) if d.n_data else None
+        d.pos_bits = _ptr(self.pos)
+        d.neg_bits = _ptr(self.neg)
+        self.desc = d
+        nbytes = hth_kb_derived_bytes(d)
+        self.derived = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
+        self.handle = hth_kb_create(d, self.derived, nbytes)
+        self.ws = None
+        self.ws_bytes = 0
+        self.reserve(max_nodes, max_hyps)
+
+    def reserve(self, max_nodes: int, max_hyps: int) -> None:
+        need = hth_workspace_bytes(self.handle, max(max_nodes, max_hyps), max_hyps)
+        if need > self.ws_bytes:
+            self.ws = None
+            self.ws = self.torch.empty(need, dtype=self.torch.uint8, device=self.device)
+            self.ws_bytes = need
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None:
+            hth_kb_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- evaluation ---------------------------------------------------------
+
+    def eval_one(self, h, instances: bool = False, counts=None, stream=None):
+        """Coverage (and optionally the instance bits) of one hypothesis.
+        With `counts` given (a device uint32 [2] view) nothing is synchronised."""
+        torch = self.torch
+        nodes, ch = encode_one(h)
+        self.reserve(nodes.shape[0], 1)
+        out = counts if counts is not None else torch.empty(2, dtype=torch.int32, device=self.device)
+        inst = torch.empty(self.S, dtype=torch.int64, device=self.device) if instances else None
+        hth_eval_one(self.handle, nodes, ch, self.ws, self.ws_bytes, inst, out, stream)
+        if counts is not None:
+            return None
+        c = tuple(int(v) for v in out.cpu().numpy().view(np.uint32))
+        if instances:
+            return c, inst.cpu().numpy().view(np.uint64)[: self.W]
+        return c
+
+    def eval_plain(self, hyps: Sequence, stream=None) -> np.ndarray:
+        """One hypothesis at a time (host plan + kernel sequence each); uint32 [H][2]."""
+        torch = self.torch
+        out = torch.empty((len(hyps), 2), dtype=torch.int32, device=self.device)
+        for i, h in enumerate(hyps):
+            self.eval_one(h, counts=out[i], stream=stream)
+        return out.cpu().numpy().view(np.uint32)
+
+    def eval_batch(self, hyps: Sequence, stream=None, counts=None) -> Optional[np.ndarray]:
+        """The whole batch compiled and run together; uint32 [H][2]."""
+        torch = self.torch
+        nodes, offs, ch = encode_batch(hyps)
+        self.reserve(nodes.shape[0], len(hyps))
+        out = counts if counts is not None else torch.empty((len(hyps), 2), dtype=torch.int32,
+                                                             device=self.device)
+        hth_eval_batch(self.handle, nodes, offs, ch, self.ws, self.ws_bytes, out, stream)
+        if counts is not None:
+            return None
+        return out.cpu().numpy().view(np.uint32)
