@@ -22,6 +22,84 @@ sys.path.insert(0, ROOT)
 METRIC = "exact hypotheses/sec + achieved HBM GB/s; screened vs plain exhaustive"
 HBM_PEAK_GBS = 8000.0
 KIND_NAMES = {0: "k_threshold", 1: "k_region", 2: "k_role", 3: "k_tbuild", 4: "k_group"}
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2412_00802_amd", "csrc", "exec.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2.json")
+COPY_BYTES = 256 << 20      # plain copy used to calibrate the byte counters
+
+
+def source_sha() -> str:
+    import hashlib
+    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+
+
+def recorded_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha") != source_sha():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["hbm_bytes_per_launch"]
+
+
+def summarize(kt_dir: str, fetch_dir: str, write_dir: str, command: str, out_md: str) -> None:
+    """Turn rocprofv3 outputs (kernel trace stats, FETCH_SIZE, WRITE_SIZE passes,
+    each run with --calibrate-copy) into the committed summary and traffic file."""
+    import csv
+    import glob
+
+    def counters(d, name):
+        per = {}
+        for f in glob.glob(os.path.join(d, "*counter_collection.csv")):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] != name:
+                    continue
+                k = r["Kernel_Name"].split("(")[0].replace("void ", "")
+                e = per.setdefault(k, {"calls": set(), "kib": 0.0})
+                e["calls"].add(r["Dispatch_Id"])
+                e["kib"] += float(r["Counter_Value"])
+        return {k: (len(v["calls"]), v["kib"] / len(v["calls"])) for k, v in per.items()}
+
+    fetch, write = counters(fetch_dir, "FETCH_SIZE"), counters(write_dir, "WRITE_SIZE")
+    copy = [k for k in fetch if "copy" in k.lower() or "elementwise" in k.lower()]
+    ck = max(copy, key=lambda k: fetch[k][1])
+    # the copy reads and writes COPY_BYTES: bytes per counted KiB
+    f_fac = COPY_BYTES / (fetch[ck][1] * 1024)
+    w_fac = COPY_BYTES / (write[ck][1] * 1024)
+    stats = []
+    for f in glob.glob(os.path.join(kt_dir, "*kernel_stats.csv")):
+        stats += list(csv.DictReader(open(f)))
+    lines = ["# rocprofv3 summary: c2 workload (1M individuals, 4096 hypotheses, batched)", "",
+             "Command (kernel trace):", "", "    " + command.format(opts="--kernel-trace --stats --output-format csv"), "",
+             "Counter passes (one counter per run):", "",
+             "    " + command.format(opts="--pmc FETCH_SIZE --output-format csv"),
+             "    " + command.format(opts="--pmc WRITE_SIZE --output-format csv"), "",
+             f"Kernel source sha256[:16] of csrc/exec.hip: {source_sha()}", "",
+             "## Kernel time (kernel trace)", "",
+             "| kernel | calls | avg us | total % |", "|---|---|---|---|"]
+    for r in sorted(stats, key=lambda r: -float(r["Percentage"]))[:12]:
+        lines.append(f"| {r['Name'].split('(')[0].replace('void ', '')[:60]} | {r['Calls']} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    lines += ["", "## Bytes (FETCH_SIZE / WRITE_SIZE, KiB per dispatch)", "",
+              f"Calibration: `{ck[:50]}` copying {COPY_BYTES >> 20} MiB reads "
+              f"{fetch[ck][1]:.0f} KiB and writes {write[ck][1]:.0f} KiB per dispatch: "
+              f"{f_fac:.3f} fetched bytes and {w_fac:.3f} written bytes per counted KiB-byte.", "",
+              "| kernel | fetch KiB | write KiB | HBM bytes per launch (scaled) |", "|---|---|---|---|"]
+    out = {"source_sha": source_sha(), "fetch_factor": f_fac, "write_factor": w_fac, "kernels": {}}
+    for k in sorted(fetch, key=lambda k: -fetch[k][1]):
+        if k not in write:
+            continue
+        hb = fetch[k][1] * 1024 * f_fac + write[k][1] * 1024 * w_fac
+        lines.append(f"| {k[:60]} | {fetch[k][1]:.0f} | {write[k][1]:.0f} | {hb / 1e6:.1f} MB |")
+        base = k.split("<")[0].split("::")[-1]
+        cur = out["kernels"].get(base)
+        if cur is None or hb > cur["hbm_bytes_per_launch"]:
+            out["kernels"][base] = {"name": k, "hbm_bytes_per_launch": hb}
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    json.dump(out, open(TRAFFIC_FILE, "w"), indent=1)
 
 
 def log(*a):
@@ -61,7 +139,16 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=64)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain device copy of 256 MiB (byte-counter calibration)")
+    ap.add_argument("--summarize", nargs=3, metavar=("KT_DIR", "FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--summary-out", default=os.path.join(ROOT, "profiles", "k_group_c2.md"))
+    ap.add_argument("--summary-command", default="rocprofv3 {opts} -d OUT -o run -- python3 bench.py "
+                    "--steps 2 --warmup 1 --plain 0 --cpu-sample 0 --no-profile --calibrate-copy")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(*args.summarize, args.summary_command, args.summary_out)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is a "
               "design note, not part of this build", file=sys.stderr)
@@ -88,6 +175,12 @@ def main():
     def step():
         hthedl.hth_eval_batch(eng.handle, nodes, offs, ch, eng.ws, eng.ws_bytes, counts, stream)
 
+    if args.calibrate_copy:
+        src = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -120,7 +213,7 @@ def main():
         ach = e["bytes"] / (e["ms"] * 1e-3) / 1e9
         roofline = {"kernel": KIND_NAMES.get(dom), "bound": "hbm", "achieved": round(ach, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                    "traffic": None,
+                    "traffic": recorded_traffic(KIND_NAMES.get(dom)),
                     "algorithmic_bytes_per_launch": e["bytes"] / e["launches"],
                     "avg_launch_ms": e["ms"] / e["launches"]}
         log(f"[bench] kernels: {json.dumps(kernels)}")

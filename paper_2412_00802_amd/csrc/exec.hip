@@ -190,10 +190,13 @@ __device__ __forceinline__ void transpose64(uint64_t (&a)[64]) {
 }
 
 // T_g[y] bit j = bit(child_j, y) ^ neg_j for the groups of one launch; one lane
-// per 64-individual word, transposed in registers.
+// per 64-individual word, transposed in registers.  T rows are TW wide
+// (8 * sizeof(TW) >= every group's k).
+template <typename TW>
 __global__ void __launch_bounds__(256)
 k_tbuild(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __restrict__ members,
-         uint64_t* __restrict__ tarea, uint64_t t_stride, uint32_t tiles) {
+         TW* __restrict__ tarea, uint64_t t_stride, uint32_t tiles) {
+  constexpr int KB = 8 * sizeof(TW);
   const uint32_t g = blockIdx.x / tiles, tile = blockIdx.x % tiles;
   const GroupTask G = groups[g];
   const uint32_t w = tile * 256 + threadIdx.x;
@@ -202,73 +205,237 @@ k_tbuild(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __re
 #pragma unroll
   for (int j = 0; j < 64; ++j) {
     uint64_t v = 0;
-    if ((uint32_t)j < G.k) {
+    if (j < KB && (uint32_t)j < G.k) {
       const GroupMember M = members[G.first + j];
       v = row_ptr(kb, M.child_row)[w] ^ (M.neg ? ~0ull : 0ull);
     }
     a[j] = v;
   }
   transpose64(a);
-  uint64_t* T = tarea + (size_t)g * t_stride + (size_t)w * 64;
+  TW* T = tarea + (size_t)g * t_stride + (size_t)w * 64;
 #pragma unroll
-  for (int b = 0; b < 64; ++b) T[b] = a[b];
+  for (int b = 0; b < 64; ++b) T[b] = (TW)a[b];
 }
 
-// One wave per 64 subjects, all members of the group at once: each assertion's
-// object fetches its T row (one 64-bit load serves every member), each member
-// bit is ballotted and each subject lane adds popcount(ballot & its range).
+// Saturating per-member counters for all members of a group at once, one bit
+// per member in each plane: count = c2 c1 c0 (0..7) unless ov (count >= 8).
+template <typename TW>
+struct Planes {
+  TW c0, c1, c2, ov;
+};
+
+template <typename TW>
+__device__ __forceinline__ void planes_inc(Planes<TW>& p, TW v) {   // +1 where v has a bit
+  const TW k0 = p.c0 & v;
+  p.c0 ^= v;
+  const TW k1 = p.c1 & k0;
+  p.c1 ^= k0;
+  const TW k2 = p.c2 & k1;
+  p.c2 ^= k1;
+  p.ov |= k2;
+}
+
+template <typename TW>
+__device__ __forceinline__ void planes_add(Planes<TW>& a, const Planes<TW>& b) {
+  const TW s0 = a.c0 ^ b.c0, k0 = a.c0 & b.c0;
+  const TW t1 = a.c1 ^ b.c1, s1 = t1 ^ k0, k1 = (a.c1 & b.c1) | (k0 & t1);
+  const TW t2 = a.c2 ^ b.c2, s2 = t2 ^ k1, k2 = (a.c2 & b.c2) | (k1 & t2);
+  a.c0 = s0;
+  a.c1 = s1;
+  a.c2 = s2;
+  a.ov = a.ov | b.ov | k2;
+}
+
+template <typename TW>
+__device__ __forceinline__ TW shfl_up_w(TW v, int d) {
+  if constexpr (sizeof(TW) == 8) return (TW)__shfl_up((unsigned long long)v, d, 64);
+  else return (TW)__shfl_up((unsigned int)v, d, 64);
+}
+
+template <typename TW>
+__device__ __forceinline__ Planes<TW> planes_shfl_up(const Planes<TW>& p, int d) {
+  return Planes<TW>{shfl_up_w(p.c0, d), shfl_up_w(p.c1, d), shfl_up_w(p.c2, d), shfl_up_w(p.ov, d)};
+}
+
+// 64 x 64 bit transpose across the lanes of a wave: on entry lane l holds row
+// l (bit j = M[l][j]); on exit lane l holds column l (bit j = M[j][l]).  Six
+// butterfly stages, each swapping the off-diagonal blocks with the partner lane.
+__device__ __forceinline__ uint64_t wave_transpose64(uint64_t x, int lane) {
+  uint64_t m = 0x00000000FFFFFFFFull;
+#pragma unroll
+  for (int d = 32; d != 0; d >>= 1, m ^= (m << d)) {
+    const uint64_t y = __shfl_xor((unsigned long long)x, d, 64);
+    x = (lane & d) ? (((y >> d) & m) | (x & ~m)) : ((x & m) | ((y << d) & ~m));
+  }
+  return x;
+}
+
+// One wave per 64 subjects (one word of every member's output row), all members
+// of the group at once.  The word's assertions are cut into 64 contiguous
+// slices of ceil(E_w / 64), one per lane (balanced whatever the degrees); a lane
+// walks its slice, fetches each object's T row (one load serves every member)
+// and adds it into bit-sliced counters, closing a row's counters when the row
+// ends.  Rows that straddle slices leave a tail partial in each lane they cross;
+// one segmented scan over the lanes adds them up for the lane holding the row's
+// last assertion.  Finally lane x evaluates every member's predicate for
+// subject x from the acceptance masks and the result is transposed by ballots.
+template <typename TW, int U>   // U: assertions in flight per lane
 __global__ void __launch_bounds__(256)
 k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __restrict__ members,
-        const uint64_t* __restrict__ tarea, uint64_t t_stride, uint32_t bpg) {
-  const uint32_t g = blockIdx.x / bpg, b = blockIdx.x % bpg;
-  const GroupTask G = groups[g];
-  const uint64_t* T = tarea + (size_t)g * t_stride;
-  const size_t ro = (size_t)G.role * (kb.N + 1);
-  const uint32_t* off = (G.inv ? kb.inv_off : kb.fwd_off) + ro;
-  const int32_t* tg = (G.inv ? kb.inv_tg : kb.fwd_tg) + kb.role_base[G.role];
-  const int lane = threadIdx.x & 63;
+        const TW* __restrict__ tarea, uint64_t t_stride, uint32_t bpg, uint32_t n_groups,
+        uint32_t xcd_local) {
+  __shared__ uint32_t s_ro[4][65];
+  __shared__ TW s_fin[4][4][64];
+  uint32_t g, b;
+  if (xcd_local) {
+    // workgroups are dealt to the 8 XCDs round robin: keep every block of a
+    // group on one XCD so that its L2 serves that group's T rows
+    const uint32_t x = blockIdx.x & 7, j = blockIdx.x >> 3;
+    g = x + 8 * (j / bpg);
+    b = j % bpg;
+    if (g >= n_groups) return;
+  } else {
+    g = blockIdx.x / bpg;
+    b = blockIdx.x % bpg;
+  }
+  const GroupTask* G = groups + g;
+  const uint32_t k = G->k;
+  const TW* T = tarea + (size_t)g * t_stride;
+  const size_t roff = (size_t)G->role * (kb.N + 1);
+  const uint32_t* off = (G->inv ? kb.inv_off : kb.fwd_off) + roff;
+  const int32_t* tg = (G->inv ? kb.inv_tg : kb.fwd_tg) + kb.role_base[G->role];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t* ro = s_ro[wv];
+  TW(*fin)[64] = s_fin[wv];
+  TW acc[kGroupMaxCount + 1];
+#pragma unroll
+  for (int v = 0; v <= (int)kGroupMaxCount; ++v) acc[v] = (TW)G->acc[v];
   const uint32_t nw = blockDim.x >> 6;
-  for (uint32_t w = b * nw + (threadIdx.x >> 6); w < kb.W; w += bpg * nw) {
+  const uint32_t wstep = bpg * nw;
+  uint32_t w = b * nw + wv;
+  uint32_t olo_n = 0, ohi_n = 0;     // row offsets of the wave's next word, fetched ahead
+  if (w < kb.W) {
+    const uint32_t xn = w * 64 + lane;
+    olo_n = off[xn < kb.N ? xn : kb.N];
+    ohi_n = xn < kb.N ? off[xn + 1] : olo_n;
+  }
+  for (; w < kb.W; w += wstep) {
     const uint32_t x = w * 64 + lane;
     const bool in = x < kb.N;
-    const uint32_t olo = off[in ? x : kb.N];
-    const uint32_t ohi = in ? off[x + 1] : olo;
-    const uint32_t ee = (uint32_t)__shfl((int)ohi, 63, 64);
-    uint32_t cnt[64];
+    const uint32_t olo = olo_n, ohi = ohi_n;
+    if (w + wstep < kb.W) {
+      const uint32_t xn = (w + wstep) * 64 + lane;
+      olo_n = off[xn < kb.N ? xn : kb.N];
+      ohi_n = xn < kb.N ? off[xn + 1] : olo_n;
+    }
+    ro[lane] = olo;
+    if (lane == 63) ro[64] = ohi;
+    fin[0][lane] = fin[1][lane] = fin[2][lane] = fin[3][lane] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint32_t E0 = (uint32_t)__shfl((int)olo, 0, 64);
+    const uint32_t E1 = (uint32_t)__shfl((int)ohi, 63, 64);
+    const uint32_t S = (E1 - E0 + 63) >> 6;
+    const uint32_t s = E0 + lane * S;
+    const uint32_t se = min(s + S, E1);
+    Planes<TW> cur{0, 0, 0, 0}, hp{0, 0, 0, 0}, tp{0, 0, 0, 0};
+    int hp_row = -1, key = -2 - lane;
+    if (s < se) {
+      int r = 0;
 #pragma unroll
-    for (int j = 0; j < 64; ++j) cnt[j] = 0;
-    for (uint32_t i0 = (uint32_t)__shfl((int)olo, 0, 64); i0 < ee; i0 += 64) {
-      const uint32_t e = i0 + lane;
-      const uint64_t v = e < ee ? T[(uint32_t)tg[e]] : 0ull;
-      const uint32_t a = olo > i0 ? min(olo - i0, 64u) : 0u;
-      const uint32_t bb = ohi > i0 ? min(ohi - i0, 64u) : 0u;
-      uint64_t rm = 0;
-      if (bb > a) rm = (bb - a == 64) ? ~0ull : (((1ull << (bb - a)) - 1ull) << a);
+      for (int step = 32; step; step >>= 1)
+        if (r + step <= 63 && ro[r + step] <= s) r += step;
+      bool head = ro[r] < s;
+      uint32_t rend = ro[r + 1];
+      for (uint32_t e0 = s; e0 < se; e0 += U) {
+        int32_t t[U];
+        TW v[U];
 #pragma unroll
-      for (int j = 0; j < 64; ++j) {
-        if ((uint32_t)j < G.k) {
-          const uint64_t m = __ballot((v >> j) & 1ull);
-          cnt[j] += (uint32_t)__popcll(m & rm);
+        for (int u = 0; u < U; ++u) t[u] = (e0 + u < se) ? tg[e0 + u] : 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = (e0 + u < se) ? T[(uint32_t)t[u]] : (TW)0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint32_t e = e0 + u;
+          if (e < se) {
+            while (e >= rend) {          // row r is complete in this slice
+              if (head) {
+                hp = cur;
+                hp_row = r;
+              } else {
+                fin[0][r] = cur.c0;
+                fin[1][r] = cur.c1;
+                fin[2][r] = cur.c2;
+                fin[3][r] = cur.ov;
+              }
+              cur = Planes<TW>{0, 0, 0, 0};
+              head = false;
+              ++r;
+              rend = ro[r + 1];
+            }
+            planes_inc(cur, v[u]);
+          }
         }
       }
-    }
-    uint64_t mine = 0;
-#pragma unroll
-    for (int j = 0; j < 64; ++j) {
-      if ((uint32_t)j < G.k) {
-        const GroupMember M = members[G.first + j];
-        const uint64_t word = __ballot(in && cnt[j] >= M.lo && cnt[j] <= M.hi);
-        if (lane == j) mine = word;
+      if (rend > se) {                    // the row continues past this slice
+        tp = cur;
+        key = r;
+      } else if (head) {
+        hp = cur;
+        hp_row = r;
+      } else {
+        fin[0][r] = cur.c0;
+        fin[1][r] = cur.c1;
+        fin[2][r] = cur.c2;
+        fin[3][r] = cur.ov;
       }
     }
-    if ((uint32_t)lane < G.k) out_ptr(kb, members[G.first + lane].out_row)[w] = mine;
+    // segmented inclusive scan of the tail partials, keyed by row; stops once no
+    // segment is longer than the distance covered (most rows cross one boundary)
+    for (int d = 1; d < 64; d <<= 1) {
+      const int pk = __shfl_up(key, d, 64);
+      if (!__ballot(lane >= d && pk == key)) break;
+      const Planes<TW> pp = planes_shfl_up(tp, d);
+      if (lane >= d && pk == key) planes_add(tp, pp);
+    }
+    {
+      const int pk = __shfl_up(key, 1, 64);
+      const Planes<TW> pp = planes_shfl_up(tp, 1);
+      if (hp_row >= 0) {
+        if (lane > 0 && pk == hp_row) planes_add(hp, pp);
+        fin[0][hp_row] = hp.c0;
+        fin[1][hp_row] = hp.c1;
+        fin[2][hp_row] = hp.c2;
+        fin[3][hp_row] = hp.ov;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // predicate of every member for subject x
+    const TW c0 = fin[0][lane], c1 = fin[1][lane], c2 = fin[2][lane], ov = fin[3][lane];
+    const TW n0 = ~c0, n1 = ~c1, n2 = ~c2;
+    TW res = (n2 & n1 & n0 & acc[0]) | (n2 & n1 & c0 & acc[1]) | (n2 & c1 & n0 & acc[2]) |
+             (n2 & c1 & c0 & acc[3]) | (c2 & n1 & n0 & acc[4]) | (c2 & n1 & c0 & acc[5]) |
+             (c2 & c1 & n0 & acc[6]) | (c2 & c1 & c0 & acc[7]);
+    res = (res & ~ov) | (ov & acc[8]);
+    if (!in) res = 0;
+    const uint64_t mine = wave_transpose64((uint64_t)res, lane);
+    if ((uint32_t)lane < k) out_ptr(kb, members[G->first + lane].out_row)[w] = mine;
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
 // ---------------------------------------------------------------------------
 // executor
 // ---------------------------------------------------------------------------
-constexpr uint32_t kTGroups = 32;   // groups whose T rows are resident at once
+// The T rows of the groups of one launch stay within kb.tune.t_budget bytes so
+// that the random T fetches of a launch stay in the last-level caches.
+inline uint32_t t_width_bytes(uint32_t k) { return k <= 8 ? 1 : k <= 16 ? 2 : k <= 32 ? 4 : 8; }
+inline size_t t_area_bytes(const hth_kb_s& kb) {
+  return std::max<size_t>(kb.tune.t_budget, align_up(kb.N, 64) * 8);
+}
 
 namespace {
 
@@ -404,32 +571,69 @@ hth_status launch_roles(Launcher& L, const DevKB& d, const RoleTask* tasks,
   });
 }
 
-hth_status launch_groups(Launcher& L, const DevKB& d, const GroupTask* groups,
-                         const GroupMember* members, const std::vector<GroupTask>& host,
-                         uint64_t* tarea) {
+template <typename TW>
+hth_status launch_group_chunk(Launcher& L, const DevKB& d, const GroupTask* groups,
+                              const GroupMember* members, const std::vector<GroupTask>& host,
+                              size_t g0, uint32_t n, void* tarea) {
   const hth_kb_s& kb = L.kb;
   const uint64_t t_stride = align_up(kb.N, 64);
-  for (size_t g0 = 0; g0 < host.size(); g0 += kTGroups) {
-    const uint32_t n = (uint32_t)std::min<size_t>(kTGroups, host.size() - g0);
-    double tb = 0, gb = 0;
-    for (uint32_t i = 0; i < n; ++i) {
-      const GroupTask& G = host[g0 + i];
-      tb += (double)G.k * kb.W * 8 + (double)t_stride * 8;      // child rows in, T out
-      gb += csr_bytes(kb, G.role) + (double)t_stride * 8 + (double)G.k * kb.W * 8;
-    }
-    const uint32_t tiles = (kb.W + 255) / 256;
-    hth_status s = L.run(HTH_K_TBUILD, tb, [&] {
-      hipLaunchKernelGGL(k_tbuild, dim3(tiles * n), dim3(256), 0, L.st, d, groups + g0, members,
-                         tarea, t_stride, tiles);
-    });
-    if (s) return s;
-    uint32_t bpg = std::max<uint32_t>(1, (8 * kb.n_cu + n - 1) / n);
+  double tb = 0, gb = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    const GroupTask& G = host[g0 + i];
+    tb += (double)G.k * kb.W * 8 + (double)t_stride * sizeof(TW);     // child rows in, T out
+    gb += csr_bytes(kb, G.role) + (double)t_stride * sizeof(TW) + (double)G.k * kb.W * 8;
+  }
+  TW* T = static_cast<TW*>(tarea);
+  const uint32_t tiles = (kb.W + 255) / 256;
+  hth_status s = L.run(HTH_K_TBUILD, tb, [&] {
+    hipLaunchKernelGGL(k_tbuild<TW>, dim3(tiles * n), dim3(256), 0, L.st, d, groups + g0, members,
+                       T, t_stride, tiles);
+  });
+  if (s) return s;
+  const uint32_t xcd = kb.tune.xcd_local && n >= 8;
+  uint32_t bpg, nblocks;
+  if (xcd) {
+    bpg = std::min<uint32_t>(std::max<uint32_t>(1, kb.n_cu / 8 * 8), (kb.W + 3) / 4);
+    nblocks = 8 * bpg * ((n + 7) / 8);
+  } else {
+    bpg = std::max<uint32_t>(1, (8 * kb.n_cu + n - 1) / n);
     bpg = std::min<uint32_t>(bpg, (kb.W + 3) / 4);
-    s = L.run(HTH_K_GROUP, gb, [&] {
-      hipLaunchKernelGGL(k_group, dim3(bpg * n), dim3(256), 0, L.st, d, groups + g0, members,
-                         tarea, t_stride, bpg);
-    });
+    nblocks = bpg * n;
+  }
+  return L.run(HTH_K_GROUP, gb, [&] {
+    if (kb.tune.group_unroll >= 16)
+      hipLaunchKernelGGL((k_group<TW, 16>), dim3(nblocks), dim3(256), 0, L.st, d, groups + g0,
+                         members, T, t_stride, bpg, n, xcd);
+    else
+      hipLaunchKernelGGL((k_group<TW, 8>), dim3(nblocks), dim3(256), 0, L.st, d, groups + g0,
+                         members, T, t_stride, bpg, n, xcd);
+  });
+}
+
+hth_status launch_groups(Launcher& L, const DevKB& d, const GroupTask* groups,
+                         const GroupMember* members, const std::vector<GroupTask>& host,
+                         void* tarea) {
+  const size_t t_stride = align_up(L.kb.N, 64);
+  size_t i = 0;
+  while (i < host.size()) {
+    uint32_t wb = 1;
+    size_t j = i;
+    while (j < host.size()) {
+      const uint32_t nwb = std::max(wb, t_width_bytes(host[j].k));
+      if (j > i && (j - i + 1) * t_stride * nwb > L.kb.tune.t_budget) break;
+      wb = nwb;
+      ++j;
+    }
+    const uint32_t n = (uint32_t)(j - i);
+    hth_status s;
+    switch (wb) {
+      case 1: s = launch_group_chunk<uint8_t>(L, d, groups, members, host, i, n, tarea); break;
+      case 2: s = launch_group_chunk<uint16_t>(L, d, groups, members, host, i, n, tarea); break;
+      case 4: s = launch_group_chunk<uint32_t>(L, d, groups, members, host, i, n, tarea); break;
+      default: s = launch_group_chunk<uint64_t>(L, d, groups, members, host, i, n, tarea); break;
+    }
     if (s) return s;
+    i = j;
   }
   return HTH_OK;
 }
@@ -473,8 +677,7 @@ hth_status run_plan(hth_kb_s& kb, const Plan& P, char* ws, size_t ws_bytes, uint
   const size_t slot_bytes = (size_t)kb.S * 8;
   size_t max_groups = 0;
   for (const PlanLevel& PL : P.levels) max_groups = std::max(max_groups, PL.groups.size());
-  const size_t t_stride = align_up(kb.N, 64);
-  const size_t t_bytes = std::min<size_t>(max_groups, kTGroups) * t_stride * 8;
+  const size_t t_bytes = max_groups ? t_area_bytes(kb) : 0;
   const size_t need = tables + (size_t)P.n_slots * slot_bytes + t_bytes;
   if (need > ws_bytes)
     return fail(HTH_E_NOMEM, "workspace too small: need " + std::to_string(need) + " bytes, have " +
@@ -485,7 +688,7 @@ hth_status run_plan(hth_kb_s& kb, const Plan& P, char* ws, size_t ws_bytes, uint
   d.slots = reinterpret_cast<uint64_t*>(ws + tables);
   d.counts = counts;
   d.instances = instances;
-  uint64_t* tarea = reinterpret_cast<uint64_t*>(ws + tables + (size_t)P.n_slots * slot_bytes);
+  void* tarea = ws + tables + (size_t)P.n_slots * slot_bytes;
   HTH_HIP(hipMemcpyAsync(ws, blob.bytes.data(), blob.bytes.size(), hipMemcpyHostToDevice, st));
   HTH_HIP(hipMemsetAsync(counts, 0, (size_t)n_hyps * 8, st));
   const ThrTask* thr = reinterpret_cast<const ThrTask*>(ws + o_thr);
@@ -526,9 +729,8 @@ extern "C" hth_status hth_workspace_bytes(hth_kb kb, uint32_t max_nodes, uint32_
                                           size_t* bytes) {
   if (!kb || !bytes) return fail(HTH_E_INVALID, "NULL argument");
   if (max_hyps == 0 || max_nodes < max_hyps) return fail(HTH_E_RANGE, "need max_nodes >= max_hyps >= 1");
-  const size_t t_groups = std::min<size_t>(kTGroups, max_nodes);
   *bytes = align_up(table_bound(max_nodes, max_hyps), 256) + (size_t)(max_nodes + 2) * kb->S * 8 +
-           t_groups * align_up(kb->N, 64) * 8;
+           t_area_bytes(*kb);
   return HTH_OK;
 }
 
@@ -549,11 +751,6 @@ extern "C" hth_status hth_eval_one(hth_kb kb, const hth_node* nodes, uint32_t n_
                   static_cast<hipStream_t>(stream));
 }
 
-static uint32_t g_group_min = [] {
-  const char* e = std::getenv("HTHEDL_GROUP_MIN");
-  return e ? (uint32_t)std::strtoul(e, nullptr, 10) : 4u;
-}();
-
 extern "C" hth_status hth_eval_batch(hth_kb kb, const hth_node* nodes, const uint32_t* hyp_node_offsets,
                                      uint32_t n_hyps, const uint32_t* children, uint32_t n_children,
                                      void* ws, size_t ws_bytes, uint32_t* d_counts, void* stream) {
@@ -563,7 +760,8 @@ extern "C" hth_status hth_eval_batch(hth_kb kb, const hth_node* nodes, const uin
   if (n_hyps == 0) return HTH_OK;
   if (hyp_node_offsets[0] != 0) return fail(HTH_E_INVALID, "hyp_node_offsets[0] must be 0");
   PlanOptions opt;
-  opt.group_min = g_group_min ? g_group_min : 0xFFFFFFFFu;
+  opt.group_min = kb->tune.group_min ? kb->tune.group_min : 0xFFFFFFFFu;
+  opt.group_k = kb->tune.group_k;
   Plan P;
   hth_status s = compile_plan(*kb, nodes, hyp_node_offsets, n_hyps, children, n_children, opt, P);
   if (s) return s;

@@ -65,13 +65,17 @@ struct RoleTask {
 // A CSR pass shared by up to 64 role nodes of one (role, direction, level):
 // the children are first transposed into T[y] (bit j = child j contains y,
 // after its negation flag), then one pass over the CSR counts all of them.
+// Members count with saturating 3-bit counters (0..7, and >= 8), so a group
+// only holds nodes whose predicate is decided there: lo <= 8 and hi <= 7 or
+// unbounded.  acc[v] bit j = member j accepts count v (acc[8]: count >= 8).
 struct GroupTask {
   uint32_t role;
   uint32_t inv;
   uint32_t k;          // nodes in the group, 1..64
   uint32_t first;      // index of the group's first member in the member table
-  uint64_t t_off;      // word offset of this group's T buffer in the T area
+  uint64_t acc[9];
 };
+constexpr uint32_t kGroupMaxCount = 8;
 struct GroupMember {
   uint32_t child_row;
   uint32_t neg;
@@ -138,6 +142,15 @@ struct hth_kb_s {
   bool prof = false;
   std::vector<ProfRec> prof_recs;
   std::vector<hipEvent_t> event_pool;
+  // schedule choices of the batched executor (defaults, environment overrides
+  // HTHEDL_GROUP_MIN / _GROUP_K / _XCD / _TBUDGET_MB)
+  struct Tuning {
+    uint32_t group_min = 4;      // smallest (role, dir, level) bucket run as shared passes
+    uint32_t group_k = 64;       // most role nodes per shared pass (T row width)
+    uint32_t xcd_local = 1;      // 1: all blocks of a shared pass on one XCD
+    size_t t_budget = 64ull << 20;  // bytes of T rows resident per launch
+    uint32_t group_unroll = 8;   // assertions in flight per lane in a shared pass
+  } tune;
 };
 
 namespace hth {

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -402,6 +403,15 @@ extern "C" hth_status hth_kb_create(const hth_kb_desc* desc, void* derived, size
     return hip_fail(e, "hipGetDeviceProperties");
   }
   kb->n_cu = prop.multiProcessorCount;
+  auto env_u = [](const char* n, uint64_t dflt) {
+    const char* e = std::getenv(n);
+    return e ? (uint64_t)std::strtoull(e, nullptr, 10) : dflt;
+  };
+  kb->tune.group_min = (uint32_t)env_u("HTHEDL_GROUP_MIN", kb->tune.group_min);
+  kb->tune.group_k = (uint32_t)std::min<uint64_t>(64, std::max<uint64_t>(1, env_u("HTHEDL_GROUP_K", kb->tune.group_k)));
+  kb->tune.xcd_local = (uint32_t)env_u("HTHEDL_XCD", kb->tune.xcd_local);
+  kb->tune.t_budget = env_u("HTHEDL_TBUDGET_MB", kb->tune.t_budget >> 20) << 20;
+  kb->tune.group_unroll = (uint32_t)env_u("HTHEDL_GROUP_UNROLL", kb->tune.group_unroll);
   kb->lds_per_block = prop.sharedMemPerBlock;
   s = kb_build(kb, static_cast<char*>(derived), static_cast<hipStream_t>(stream));
   if (s) {

@@ -369,7 +369,6 @@ struct Compiler {
       per_level[height[v]].push_back({v, crow, neg});
     }
     // role tasks, grouped per (role, direction) when the bucket is large
-    const uint64_t t_stride = align_up(kb.N, 64);
     for (int32_t L = 0; L <= max_level; ++L) {
       PlanLevel& PL = P.levels[L];
       auto& items = per_level[L];
@@ -385,57 +384,67 @@ struct Compiler {
         while (j < items.size() && dag.nodes[items[j].v].arg == first.arg &&
                dag.nodes[items[j].v].inv == first.inv)
           ++j;
-        const bool group = (j - i) >= opt.group_min;
-        for (size_t g0 = i; g0 < j; g0 += group ? kMaxK : 1) {
-          size_t g1 = group ? std::min(j, g0 + kMaxK) : g0 + 1;
-          if (group) {
-            GroupTask gt;
-            gt.role = first.arg;
-            gt.inv = first.inv;
-            gt.k = (uint32_t)(g1 - g0);
-            gt.first = (uint32_t)PL.members.size();
-            gt.t_off = PL.t_words;
-            PL.t_words += t_stride;
-            PL.groups.push_back(gt);
+        // nodes a shared pass can decide (see GroupTask) form groups when the
+        // bucket is large enough; the rest run alone
+        std::vector<Pending> solo, grp;
+        for (size_t q = i; q < j; ++q) {
+          const CNode& n = dag.nodes[items[q].v];
+          const bool groupable = n.op == HTH_EXISTS || n.op == HTH_FORALL ||
+                                 (n.op == HTH_ATLEAST ? n.q <= kGroupMaxCount : n.q < kGroupMaxCount);
+          (groupable ? grp : solo).push_back(items[q]);
+        }
+        if (grp.size() < opt.group_min) {
+          solo.insert(solo.end(), grp.begin(), grp.end());
+          grp.clear();
+        }
+        auto predicate = [&](const Pending& it, uint32_t& lo, uint32_t& hi, uint32_t& neg) {
+          const CNode& n = dag.nodes[it.v];
+          neg = it.neg;
+          switch (n.op) {
+            case HTH_EXISTS: lo = 1; hi = kInf; break;
+            case HTH_FORALL: lo = 0; hi = 0; neg ^= 1; break;
+            case HTH_ATLEAST: lo = n.q; hi = kInf; break;
+            case HTH_ATMOST: lo = 0; hi = n.q; break;
+            default: lo = n.q; hi = n.q; break;
           }
+        };
+        for (const Pending& it : solo) {
+          const CNode& n = dag.nodes[it.v];
+          RoleTask t;
+          t.role = n.arg;
+          t.inv = n.inv;
+          t.child_row = it.child_row;
+          predicate(it, t.lo, t.hi, t.neg);
+          t.sat = t.hi == kInf ? t.lo : t.hi + 1;
+          t.out_row = row[it.v];
+          PL.roles.push_back(t);
+        }
+        const size_t gk = std::max<uint32_t>(1, std::min<uint32_t>(opt.group_k, kMaxK));
+        for (size_t g0 = 0; g0 < grp.size(); g0 += gk) {
+          const size_t g1 = std::min(grp.size(), g0 + gk);
+          GroupTask gt{};
+          gt.role = first.arg;
+          gt.inv = first.inv;
+          gt.k = (uint32_t)(g1 - g0);
+          gt.first = (uint32_t)PL.members.size();
           for (size_t q = g0; q < g1; ++q) {
-            const Pending& it = items[q];
-            const CNode& n = dag.nodes[it.v];
-            uint32_t lo, hi, neg = it.neg;
-            switch (n.op) {
-              case HTH_EXISTS: lo = 1; hi = kInf; break;
-              case HTH_FORALL: lo = 0; hi = 0; neg ^= 1; break;
-              case HTH_ATLEAST: lo = n.q; hi = kInf; break;
-              case HTH_ATMOST: lo = 0; hi = n.q; break;
-              default: lo = n.q; hi = n.q; break;
+            GroupMember m{};
+            predicate(grp[q], m.lo, m.hi, m.neg);
+            m.sat = m.hi == kInf ? m.lo : m.hi + 1;
+            m.child_row = grp[q].child_row;
+            m.out_row = row[grp[q].v];
+            const uint32_t jbit = (uint32_t)(q - g0);
+            for (uint32_t v = 0; v <= kGroupMaxCount; ++v) {
+              const bool ok = v < kGroupMaxCount ? (m.lo <= v && v <= m.hi)
+                                                 : (m.hi == kInf && m.lo <= kGroupMaxCount);
+              if (ok) gt.acc[v] |= 1ull << jbit;
             }
-            uint32_t sat = hi == kInf ? lo : hi + 1;
-            if (group) {
-              GroupMember m{};
-              m.child_row = it.child_row;
-              m.neg = neg;
-              m.lo = lo;
-              m.hi = hi;
-              m.sat = sat;
-              m.out_row = row[it.v];
-              PL.members.push_back(m);
-            } else {
-              RoleTask t;
-              t.role = n.arg;
-              t.inv = n.inv;
-              t.child_row = it.child_row;
-              t.neg = neg;
-              t.lo = lo;
-              t.hi = hi;
-              t.sat = sat;
-              t.out_row = row[it.v];
-              PL.roles.push_back(t);
-            }
+            PL.members.push_back(m);
           }
+          PL.groups.push_back(gt);
         }
         i = j;
       }
-      P.t_words = std::max(P.t_words, PL.t_words);
     }
     // roots with coverage
     for (uint32_t h = 0; h < roots.size(); ++h) {

@@ -16,6 +16,7 @@ struct PlanOptions {
   bool instances = false;        // write the (single) root's instance set
   uint32_t group_min = 0xFFFFFFFFu;  // (role, dir, level) buckets with at least this many
                                      // role nodes use a shared CSR pass; others run alone
+  uint32_t group_k = 64;             // most role nodes per shared pass
 };
 
 struct PlanLevel {
@@ -23,7 +24,6 @@ struct PlanLevel {
   std::vector<RoleTask> roles;      // single role nodes (k = 1)
   std::vector<GroupTask> groups;    // shared passes (k <= 64)
   std::vector<GroupMember> members;
-  uint64_t t_words = 0;             // T area used by this level's groups (words)
 };
 
 struct Plan {
@@ -32,7 +32,6 @@ struct Plan {
   std::vector<PlanLevel> levels;
   std::vector<RegionTask> roots;
   uint32_t n_slots = 0;
-  uint64_t t_words = 0;             // max over levels
   // statistics
   uint32_t n_input_nodes = 0, n_canonical = 0, n_role_nodes = 0;
 };

@@ -205,3 +205,30 @@ def test_max_degrees_and_inverse(gpu):
         tg = kb.role_targets[off[0]:off[-1]]
         assert hthedl.hth_kb_max_degree(eng.handle, r, 0) == int(np.diff(off).max())
         assert hthedl.hth_kb_max_degree(eng.handle, r, 1) == int(np.bincount(tg, minlength=kb.n).max())
+
+
+def _distinct_role_nodes(m, n_concepts, role, inv, seed):
+    rnd = np.random.default_rng(seed)
+    hs, seen = [], set()
+    ops = ["exists", "forall", "atleast", "atmost", "exactly"]
+    while len(hs) < m:
+        op = ops[int(rnd.integers(0, 5))]
+        a, b = int(rnd.integers(0, n_concepts)), int(rnd.integers(0, n_concepts))
+        c = ("atom", a) if rnd.random() < 0.5 else ("or", ("atom", a), ("not", ("atom", b)))
+        h = (op, role, inv, c) if op in ("exists", "forall") else (op, int(rnd.integers(0, 4)), role, inv, c)
+        if h not in seen:
+            seen.add(h)
+            hs.append(h)
+    return hs
+
+
+@pytest.mark.parametrize("m", [4, 8, 9, 16, 17, 32, 33, 64, 65, 130])
+def test_group_widths(m):
+    """A (role, direction, level) bucket of m role nodes: shared passes of every
+    T width and split groups, next to the single-node path."""
+    cfg = synth.small_config(n=9000, n_concepts=40, n_roles=2, s=1.3, cap=400, n_pos=900,
+                             n_neg=800, seed_index=950)
+    kb = synth.make_kb(cfg)
+    hs = _distinct_role_nodes(m, 40, 1, m % 2, seed=m)
+    hs += [("and", h, ("atom", i % 40)) for i, h in enumerate(hs[: m // 2])]
+    check(kb, hs, label=f"group m={m}")
