@@ -175,6 +175,72 @@ typedef struct {
 hth_status hth_profile_begin(hth_kb kb);
 hth_status hth_profile_end(hth_kb kb, hth_prof_entry* out /* [HTH_K_NUM] */);
 
+/* ---------------------------------------------------------------------------
+ * Learned screener (a project extension, not in the paper): it ranks refinement
+ * candidates so that only the best fraction is evaluated exactly.  All buffers
+ * are device memory owned by the caller; bf16 values travel as uint16_t bit
+ * patterns; every matrix is row-major with the given leading dimension.
+ * ------------------------------------------------------------------------- */
+
+/* Hashed subtree features.  For each hypothesis (postfix nodes, local child
+ * indices, as in hth_eval_batch but in device memory) every node's subtree gets
+ * a 64-bit hash: FNV-1a over 12 header bytes (op, inv, arity as 2 LE bytes, arg
+ * and q as 4 LE bytes each; fields a construct does not use are zero), followed
+ * for NOT and role constructs by the child's hash (8 LE bytes) and for AND/OR
+ * by the wrapping sum of splitmix64(child hash) over the children (8 LE bytes,
+ * order independent).  d_feat[i] = hash[i] mod 4096.  d_hash: scratch uint64
+ * [n_nodes].  A malformed child index sets *d_bad to 1 and hashes the node as
+ * 0; nothing traps. */
+hth_status hth_features(const hth_node* d_nodes, const uint32_t* d_hyp_node_offsets, uint32_t n_hyps,
+                        const uint32_t* d_children, uint32_t n_children, uint64_t* d_hash,
+                        uint16_t* d_feat, uint32_t* d_bad, void* stream);
+
+/* Dense bf16 feature rows: d_x[r][f] = number of subtrees of hypothesis row0 + r
+ * with feature index f, for r < n_rows (d_x is [n_rows][4096]). */
+hth_status hth_densify(const uint16_t* d_feat, const uint32_t* d_hyp_node_offsets, uint32_t row0,
+                       uint32_t n_rows, uint16_t* d_x, void* stream);
+
+/* C[M][N] = op(A) op(B) on the MFMA units (bf16 operands, fp32 accumulation).
+ * trans_a = 0: A is [M][lda]; 1: A is given transposed as [K][lda].
+ * trans_b = 0: B is [K][ldb]; 1: B is given as [N][ldb].  (Both transposed is
+ * HTH_E_UNSUPPORTED.)  Epilogue, in this order: + bias[n] (if bias), max(.,0)
+ * (if relu), zero where mask[m][n] <= 0 (if mask, bf16 [M][ldm]); then stored
+ * to c32 (fp32 [M][ldc]) and/or cbf (bf16 [M][ldcb]).  The contiguous
+ * dimension of each operand and its leading dimension must be multiples of 8
+ * and A, B 16-byte aligned. */
+hth_status hth_gemm_bf16(int trans_a, int trans_b, int M, int N, int K, const uint16_t* A, int lda,
+                         const uint16_t* B, int ldb, const float* bias, int relu, const uint16_t* mask,
+                         int ldm, float* c32, int ldc, uint16_t* cbf, int ldcb, void* stream);
+
+/* Output layer of width 2: z[b] = h[b] . w[:, o] + bias[o] (h bf16 [Bn][Kd],
+ * w fp32 [Kd][2]).  With targets y (fp32 [Bn][2], the covered fractions
+ * pos/|P| and neg/|Ng|): adds the summed BCE-with-logits loss into *loss and
+ * writes dz = (sigmoid(z) - y) * scale. */
+hth_status hth_head_forward(const uint16_t* h, int Bn, int Kd, const float* w, const float* bias,
+                            float* z, const float* y, float* dz, float scale, float* loss, void* stream);
+
+/* Backward of the output layer: dw[k][o] = sum_b h[b][k] dz[b][o];
+ * dh[b][k] = (dz[b] . w[k]) where h[b][k] > 0, else 0 (ReLU of the layer below). */
+hth_status hth_head_backward(const uint16_t* h, int Bn, int Kd, const float* w, const float* dz,
+                             float* dw, uint16_t* dh, void* stream);
+
+/* out[n] = sum over m of d[m][n] (d bf16 if is_bf16, else fp32; [M][N]). */
+hth_status hth_colsum(const void* d, int is_bf16, int M, int N, float* out, void* stream);
+
+/* AdamW (decoupled weight decay) on fp32 parameters p with gradient g and
+ * moments m, v; step counts from 1; pbf (optional) receives a bf16 copy. */
+hth_status hth_adamw(float* p, const float* g, float* m, float* v, uint16_t* pbf, size_t n, float lr,
+                     float beta1, float beta2, float eps, float wd, int step, void* stream);
+
+/* d[i] = bf16(s[i]) (round to nearest even). */
+hth_status hth_to_bf16(const float* s, uint16_t* d, size_t n, void* stream);
+
+/* Indices of the k largest scores (d_idx [k], in no particular order; among
+ * equal scores at the threshold, which ones are taken is unspecified; NaN
+ * ranks last).  d_work: uint32 [65538].  Synchronous on `stream`. */
+hth_status hth_topk(const float* d_scores, uint32_t n, uint32_t k, uint32_t* d_idx, uint32_t* d_work,
+                    void* stream);
+
 /* Wait for `stream`; turn an asynchronous device error into HTH_E_DEVICE. */
 hth_status hth_sync(void* stream);
 

@@ -1,0 +1,156 @@
+"""CPU references for the learned screener -- test infrastructure only.
+
+The screener is this project's extension (the paper has no learner): a bf16
+MLP over hashed subtree features that ranks refinement candidates.  These
+references define what its kernels compute:
+
+* ``subtree_features``: the hashed subtree features of a hypothesis given as a
+  nested tuple, node by node in postfix order;
+* ``bf16``: float32 -> bfloat16 round-to-nearest-even, returned as float64;
+* ``forward`` / ``backward``: the MLP 4096 -> 1024 -> 256 -> 2 with ReLU and
+  BCE-with-logits on the two covered fractions, in float64, either exact
+  (``rounding=False``, pinned by finite differences in the tests) or with the
+  bf16 roundings the kernels apply to their stored operands and activations;
+* ``adamw``: one AdamW step with decoupled weight decay.
+
+Parity status: the MLP gradients are pinned by central finite differences;
+the feature hash and the optimiser step follow their written definitions.
+"""
+from __future__ import annotations
+
+import struct
+from typing import Dict, List, Tuple
+
+import numpy as np
+
+FNV_OFFSET = 0xCBF29CE484222325
+FNV_PRIME = 0x100000001B3
+MASK64 = (1 << 64) - 1
+FEATURE_DIM = 4096
+
+_OPS = {"top": 0, "bot": 1, "atom": 2, "not": 3, "and": 4, "or": 5, "exists": 6, "forall": 7,
+        "atleast": 8, "atmost": 9, "exactly": 10, "dge": 11, "dle": 12}
+
+
+def _fnv(h: int, data: bytes) -> int:
+    for byte in data:
+        h ^= byte
+        h = (h * FNV_PRIME) & MASK64
+    return h
+
+
+def _splitmix(x: int) -> int:
+    z = (x + 0x9E3779B97F4A7C15) & MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    return z ^ (z >> 31)
+
+
+def _header(op: str, inv: int = 0, arity: int = 0, arg: int = 0, q: int = 0) -> bytes:
+    return struct.pack("<BBHII", _OPS[op], inv, arity, arg, q)
+
+
+def _f32_bits(t: float) -> int:
+    return struct.unpack("<I", struct.pack("<f", t))[0]
+
+
+def subtree_features(h) -> List[Tuple[int, int]]:
+    """(hash, feature index) of every node of h in postfix order (children
+    left to right before the node), the order of the library's node arrays."""
+    out: List[Tuple[int, int]] = []
+
+    def visit(t) -> int:
+        op = t[0]
+        if op in ("top", "bot"):
+            v = _fnv(FNV_OFFSET, _header(op))
+        elif op == "atom":
+            v = _fnv(FNV_OFFSET, _header(op, arg=t[1]))
+        elif op in ("dge", "dle"):
+            v = _fnv(FNV_OFFSET, _header(op, arg=t[1], q=_f32_bits(t[2])))
+        elif op == "not":
+            c = visit(t[1])
+            v = _fnv(_fnv(FNV_OFFSET, _header(op)), struct.pack("<Q", c))
+        elif op in ("and", "or"):
+            cs = [visit(c) for c in t[1:]]
+            s = sum(_splitmix(c) for c in cs) & MASK64
+            v = _fnv(_fnv(FNV_OFFSET, _header(op, arity=len(cs))), struct.pack("<Q", s))
+        else:
+            if op in ("exists", "forall"):
+                _, r, inv, c = t
+                q = 0
+            else:
+                _, q, r, inv, c = t
+            ch = visit(c)
+            v = _fnv(_fnv(FNV_OFFSET, _header(op, inv=inv, arg=r, q=q)), struct.pack("<Q", ch))
+        out.append((v, v % FEATURE_DIM))
+        return v
+
+    visit(h)
+    return out
+
+
+def dense_features(hyps) -> np.ndarray:
+    """[H][4096] counts of subtrees per feature index."""
+    x = np.zeros((len(hyps), FEATURE_DIM), dtype=np.float64)
+    for i, h in enumerate(hyps):
+        for _, f in subtree_features(h):
+            x[i, f] += 1
+    return x
+
+
+def bf16(x) -> np.ndarray:
+    """Round float32 values to bfloat16 (nearest, ties to even); float64 result."""
+    a = np.asarray(x, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    r = np.where(np.isnan(a), u, r).astype(np.uint32)
+    return r.view(np.float32).astype(np.float64)
+
+
+def _r(x, rounding: bool):
+    return bf16(x) if rounding else np.asarray(x, dtype=np.float64)
+
+
+def forward(p: Dict[str, np.ndarray], x: np.ndarray, y: np.ndarray = None, rounding: bool = False):
+    """Activations (and the summed BCE-with-logits loss when y is given)."""
+    w1, w2 = _r(p["w1"], rounding), _r(p["w2"], rounding)
+    h1 = _r(np.maximum(x @ w1 + p["b1"], 0.0), rounding)
+    h2 = _r(np.maximum(h1 @ w2 + p["b2"], 0.0), rounding)
+    z = h2 @ p["w3"] + p["b3"]
+    acts = {"x": x, "h1": h1, "h2": h2, "z": z}
+    if y is None:
+        return acts, None
+    loss = float(np.sum(np.maximum(z, 0) - z * y + np.log1p(np.exp(-np.abs(z)))))
+    return acts, loss
+
+
+def backward(p, acts, y, scale: float, rounding: bool = False):
+    """Gradients of scale * loss."""
+    x, h1, h2, z = acts["x"], acts["h1"], acts["h2"], acts["z"]
+    dz = (1.0 / (1.0 + np.exp(-z)) - y) * scale
+    g = {"w3": h2.T @ dz, "b3": dz.sum(0)}
+    dh2 = _r((dz @ p["w3"].T) * (h2 > 0), rounding)
+    g["w2"] = h1.T @ dh2
+    g["b2"] = dh2.sum(0)
+    dh1 = _r((dh2 @ _r(p["w2"], rounding).T) * (h1 > 0), rounding)
+    g["w1"] = x.T @ dh1
+    g["b1"] = dh1.sum(0)
+    return g
+
+
+def adamw(p, g, m, v, lr, b1, b2, eps, wd, step):
+    m = b1 * m + (1 - b1) * g
+    v = b2 * v + (1 - b2) * g * g
+    mh = m / (1 - b1 ** step)
+    vh = v / (1 - b2 ** step)
+    p = p * (1 - lr * wd) - lr * mh / (np.sqrt(vh) + eps)
+    return p, m, v
+
+
+def predicted_f1(z: np.ndarray, n_pos: int, n_neg: int) -> np.ndarray:
+    """F1 of the predicted coverage: p = sigmoid(z0) |P|, q = sigmoid(z1) |Ng|,
+    F1 = 2p / (2p + q + (|P| - p))."""
+    p = n_pos / (1.0 + np.exp(-z[:, 0]))
+    q = n_neg / (1.0 + np.exp(-z[:, 1]))
+    den = p + q + n_pos
+    return np.where(den > 0, 2 * p / np.maximum(den, 1e-30), 0.0)

@@ -279,13 +279,16 @@ __device__ __forceinline__ uint64_t wave_transpose64(uint64_t x, int lane) {
 // one segmented scan over the lanes adds them up for the lane holding the row's
 // last assertion.  Finally lane x evaluates every member's predicate for
 // subject x from the acceptance masks and the result is transposed by ballots.
-template <typename TW, int U>   // U: assertions in flight per lane
+template <typename TW, int U, bool NT>   // U: assertions in flight per lane;
+                                          // NT: stream the CSR past the caches
 __global__ void __launch_bounds__(256)
 k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __restrict__ members,
         const TW* __restrict__ tarea, uint64_t t_stride, uint32_t bpg, uint32_t n_groups,
         uint32_t xcd_local) {
+  constexpr uint32_t kStage = 1024;   // assertions of a word staged in LDS
   __shared__ uint32_t s_ro[4][65];
   __shared__ TW s_fin[4][4][64];
+  __shared__ int32_t s_tg[4][kStage];
   uint32_t g, b;
   if (xcd_local) {
     // workgroups are dealt to the 8 XCDs round robin: keep every block of a
@@ -339,6 +342,17 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
     const uint32_t S = (E1 - E0 + 63) >> 6;
     const uint32_t s = E0 + lane * S;
     const uint32_t se = min(s + S, E1);
+    // the word's targets, loaded coalesced into LDS when they fit; lanes then
+    // read their contiguous slices from there
+    int32_t* stg = s_tg[wv];
+    const bool staged = E1 - E0 <= kStage;
+    if (staged) {
+#pragma unroll 4
+      for (uint32_t i = lane; i < E1 - E0; i += 64) stg[i] = tg[E0 + i];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
     Planes<TW> cur{0, 0, 0, 0}, hp{0, 0, 0, 0}, tp{0, 0, 0, 0};
     int hp_row = -1, key = -2 - lane;
     if (s < se) {
@@ -352,7 +366,11 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
         int32_t t[U];
         TW v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) t[u] = (e0 + u < se) ? tg[e0 + u] : 0;
+        for (int u = 0; u < U; ++u)
+          t[u] = (e0 + u < se)
+                     ? (staged ? stg[e0 + u - E0]
+                               : (NT ? __builtin_nontemporal_load(tg + e0 + u) : tg[e0 + u]))
+                     : 0;
 #pragma unroll
         for (int u = 0; u < U; ++u) v[u] = (e0 + u < se) ? T[(uint32_t)t[u]] : (TW)0;
 #pragma unroll
@@ -601,12 +619,22 @@ hth_status launch_group_chunk(Launcher& L, const DevKB& d, const GroupTask* grou
     nblocks = bpg * n;
   }
   return L.run(HTH_K_GROUP, gb, [&] {
-    if (kb.tune.group_unroll >= 16)
-      hipLaunchKernelGGL((k_group<TW, 16>), dim3(nblocks), dim3(256), 0, L.st, d, groups + g0,
-                         members, T, t_stride, bpg, n, xcd);
-    else
-      hipLaunchKernelGGL((k_group<TW, 8>), dim3(nblocks), dim3(256), 0, L.st, d, groups + g0,
-                         members, T, t_stride, bpg, n, xcd);
+    const dim3 grid(nblocks), block(256);
+    if (kb.tune.group_unroll >= 16) {
+      if (kb.tune.nontemporal)
+        hipLaunchKernelGGL((k_group<TW, 16, true>), grid, block, 0, L.st, d, groups + g0, members, T,
+                           t_stride, bpg, n, xcd);
+      else
+        hipLaunchKernelGGL((k_group<TW, 16, false>), grid, block, 0, L.st, d, groups + g0, members, T,
+                           t_stride, bpg, n, xcd);
+    } else {
+      if (kb.tune.nontemporal)
+        hipLaunchKernelGGL((k_group<TW, 8, true>), grid, block, 0, L.st, d, groups + g0, members, T,
+                           t_stride, bpg, n, xcd);
+      else
+        hipLaunchKernelGGL((k_group<TW, 8, false>), grid, block, 0, L.st, d, groups + g0, members, T,
+                           t_stride, bpg, n, xcd);
+    }
   });
 }
 

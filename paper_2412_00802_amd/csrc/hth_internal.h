@@ -149,7 +149,8 @@ struct hth_kb_s {
     uint32_t group_k = 64;       // most role nodes per shared pass (T row width)
     uint32_t xcd_local = 1;      // 1: all blocks of a shared pass on one XCD
     size_t t_budget = 64ull << 20;  // bytes of T rows resident per launch
-    uint32_t group_unroll = 8;   // assertions in flight per lane in a shared pass
+    uint32_t group_unroll = 16;  // assertions in flight per lane in a shared pass
+    uint32_t nontemporal = 0;    // 1: CSR targets loaded with the streaming hint
   } tune;
 };
 

@@ -412,6 +412,7 @@ extern "C" hth_status hth_kb_create(const hth_kb_desc* desc, void* derived, size
   kb->tune.xcd_local = (uint32_t)env_u("HTHEDL_XCD", kb->tune.xcd_local);
   kb->tune.t_budget = env_u("HTHEDL_TBUDGET_MB", kb->tune.t_budget >> 20) << 20;
   kb->tune.group_unroll = (uint32_t)env_u("HTHEDL_GROUP_UNROLL", kb->tune.group_unroll);
+  kb->tune.nontemporal = (uint32_t)env_u("HTHEDL_NT", kb->tune.nontemporal);
   kb->lds_per_block = prop.sharedMemPerBlock;
   s = kb_build(kb, static_cast<char*>(derived), static_cast<hipStream_t>(stream));
   if (s) {

@@ -32,7 +32,8 @@ assert NODE_DTYPE.itemsize == 16
 EXPORTED = ["hth_kb_derived_bytes", "hth_kb_create", "hth_kb_set_examples", "hth_kb_max_degree",
             "hth_kb_destroy", "hth_workspace_bytes", "hth_eval_one", "hth_eval_batch",
             "hth_sync", "hth_status_str", "hth_last_error", "hth_profile_begin",
-            "hth_profile_end"]
+            "hth_profile_end", "hth_features", "hth_densify", "hth_gemm_bf16", "hth_head_forward",
+            "hth_head_backward", "hth_colsum", "hth_adamw", "hth_to_bf16", "hth_topk"]
 
 
 class HthError(RuntimeError):
@@ -67,6 +68,7 @@ def lib() -> ctypes.CDLL:
             raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2412_00802_amd.build`")
         L = ctypes.CDLL(LIB_PATH)
         P, U32, U64, S = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
+        I, F = ctypes.c_int, ctypes.c_float
         sig = {
             "hth_kb_derived_bytes": [ctypes.POINTER(KBDesc), ctypes.POINTER(S)],
             "hth_kb_create": [ctypes.POINTER(KBDesc), P, S, P, ctypes.POINTER(P)],
@@ -79,6 +81,15 @@ def lib() -> ctypes.CDLL:
             "hth_sync": [P],
             "hth_profile_begin": [P],
             "hth_profile_end": [P, ctypes.POINTER(ProfEntry)],
+            "hth_features": [P, P, U32, P, U32, P, P, P, P],
+            "hth_densify": [P, P, U32, U32, P, P],
+            "hth_gemm_bf16": [I, I, I, I, I, P, I, P, I, P, I, P, I, P, I, P, I, P],
+            "hth_head_forward": [P, I, I, P, P, P, P, P, F, P, P],
+            "hth_head_backward": [P, I, I, P, P, P, P, P],
+            "hth_colsum": [P, I, I, I, P, P],
+            "hth_adamw": [P, P, P, P, P, S, F, F, F, F, F, I, P],
+            "hth_to_bf16": [P, P, S, P],
+            "hth_topk": [P, U32, U32, P, P, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -201,6 +212,55 @@ def hth_profile_end(kb) -> List[dict]:
 
 
 profile_end = hth_profile_end
+
+
+# -- learned screener (device tensors; bf16 tensors are torch.bfloat16) ------
+
+
+def hth_features(d_nodes, d_offsets, n_hyps: int, d_children, n_children: int, d_hash, d_feat, d_bad,
+                 stream=None) -> None:
+    _check(lib().hth_features(_ptr(d_nodes), _ptr(d_offsets), n_hyps, _ptr(d_children), n_children,
+                              _ptr(d_hash), _ptr(d_feat), _ptr(d_bad), _stream(stream)))
+
+
+def hth_densify(d_feat, d_offsets, row0: int, n_rows: int, d_x, stream=None) -> None:
+    _check(lib().hth_densify(_ptr(d_feat), _ptr(d_offsets), row0, n_rows, _ptr(d_x), _stream(stream)))
+
+
+def hth_gemm_bf16(trans_a: int, trans_b: int, M: int, N: int, K: int, A, lda: int, B, ldb: int,
+                  bias=None, relu: int = 0, mask=None, ldm: int = 0, c32=None, ldc: int = 0, cbf=None,
+                  ldcb: int = 0, stream=None) -> None:
+    _check(lib().hth_gemm_bf16(trans_a, trans_b, M, N, K, _ptr(A), lda, _ptr(B), ldb, _ptr(bias), relu,
+                               _ptr(mask), ldm, _ptr(c32), ldc, _ptr(cbf), ldcb, _stream(stream)))
+
+
+def hth_head_forward(h, Bn: int, Kd: int, w, bias, z, y=None, dz=None, scale: float = 1.0, loss=None,
+                     stream=None) -> None:
+    _check(lib().hth_head_forward(_ptr(h), Bn, Kd, _ptr(w), _ptr(bias), _ptr(z), _ptr(y), _ptr(dz),
+                                  scale, _ptr(loss), _stream(stream)))
+
+
+def hth_head_backward(h, Bn: int, Kd: int, w, dz, dw, dh, stream=None) -> None:
+    _check(lib().hth_head_backward(_ptr(h), Bn, Kd, _ptr(w), _ptr(dz), _ptr(dw), _ptr(dh),
+                                   _stream(stream)))
+
+
+def hth_colsum(d, is_bf16: int, M: int, N: int, out, stream=None) -> None:
+    _check(lib().hth_colsum(_ptr(d), is_bf16, M, N, _ptr(out), _stream(stream)))
+
+
+def hth_adamw(p, g, m, v, pbf, n: int, lr: float, beta1: float, beta2: float, eps: float, wd: float,
+              step: int, stream=None) -> None:
+    _check(lib().hth_adamw(_ptr(p), _ptr(g), _ptr(m), _ptr(v), _ptr(pbf), n, lr, beta1, beta2, eps, wd,
+                           step, _stream(stream)))
+
+
+def hth_to_bf16(s, d, n: int, stream=None) -> None:
+    _check(lib().hth_to_bf16(_ptr(s), _ptr(d), n, _stream(stream)))
+
+
+def hth_topk(d_scores, n: int, k: int, d_idx, d_work, stream=None) -> None:
+    _check(lib().hth_topk(_ptr(d_scores), n, k, _ptr(d_idx), _ptr(d_work), _stream(stream)))
 
 
 # ---------------------------------------------------------------------------

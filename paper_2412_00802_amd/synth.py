@@ -419,6 +419,79 @@ def make_hypotheses(cfg: KBConfig, kb: KB, count: Optional[int] = None,
     return [g.tree(depth, root=True) for _ in range(count)]
 
 
+class _SizedGen(_HypGen):
+    """Trees of an exact node count; children are drawn from a pool of earlier
+    subtrees of the same size with probability p_share."""
+
+    def __init__(self, *a, p_share=0.3, pool_size=4096, **kw):
+        super().__init__(*a, **kw)
+        self.p_share = p_share
+        self.pool_size = pool_size
+        self.pool = {}          # size -> list of subtrees (ring buffers)
+        self.pool_n = 0
+
+    def _remember(self, t, k):
+        lst = self.pool.setdefault(k, [])
+        if self.pool_n < self.pool_size:
+            lst.append(t)
+            self.pool_n += 1
+        elif lst:
+            lst[int(self.rng.integers(0, len(lst)))] = t
+
+    def child(self, k):
+        lst = self.pool.get(k)
+        if lst and self.rng.random() < self.p_share:
+            return lst[int(self.rng.integers(0, len(lst)))]
+        return self.sized(k)
+
+    def sized(self, k):
+        if k == 1:
+            t = self.leaf()
+        elif k == 2:
+            t = self._unary(self.child(1))
+        else:
+            op = self.ops[int(self.rng.integers(0, len(self.ops)))]
+            if op in ("and", "or"):
+                a = min(k - 1, 2 + int(self.rng.integers(0, 2)))
+                cuts = np.sort(self.rng.choice(np.arange(1, k - 1), size=a - 1, replace=False))
+                parts = np.diff(np.concatenate(([0], cuts, [k - 1]))).tolist()
+                t = (op,) + tuple(self.child(int(p)) for p in parts)
+            else:
+                t = self._unary(self.child(k - 1), op)
+        self._remember(t, k)
+        return t
+
+    def _unary(self, c, op=None):
+        if op is None or op in ("and", "or"):
+            op = ("not", "exists", "forall", "atleast", "atmost")[int(self.rng.integers(0, 5))]
+        if op == "not":
+            return ("not", c)
+        r = int(self.rng.integers(0, self.nr))
+        inv = int(self.rng.random() < self.p_inv)
+        if op in ("exists", "forall"):
+            return (op, r, inv, c)
+        return (op, 1 + int(self.rng.integers(0, self.max_n)), r, inv, c)
+
+
+def make_sized_hypotheses(cfg: KBConfig, kb: KB, count: Optional[int] = None, p_geo: float = 0.15,
+                          max_nodes: int = 31, p_share: float = 0.3, stream: int = 4) -> List[tuple]:
+    """The uneven-batch workload: node counts geometric(p_geo) truncated to
+    1..max_nodes by rejection, trees grown to exactly that many nodes, each
+    child subtree drawn from a pool of 4,096 earlier subtrees of the same size
+    with probability p_share (shared subexpressions across the batch)."""
+    ss = _streams(cfg)[stream]
+    rng = np.random.default_rng(ss)
+    g = _SizedGen(rng, kb.n_concepts, kb.n_roles, kb.n_data, kb.deciles, p_share=p_share)
+    count = cfg.n_hyps if count is None else count
+    out = []
+    while len(out) < count:
+        k = int(rng.geometric(p_geo))
+        if k > max_nodes:
+            continue
+        out.append(g.sized(k))
+    return out
+
+
 def hyp_depth(h) -> int:
     op = h[0]
     if op in ("top", "bot", "atom", "dge", "dle"):

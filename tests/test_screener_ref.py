@@ -1,0 +1,73 @@
+"""Pins of the screener references (no GPU): finite-difference gradients of
+the MLP, bf16 rounding against exact cases, and properties of the subtree hash."""
+import numpy as np
+import pytest
+
+from oracle import screener as S
+
+
+def small_params(rng, d_in=24, h1=16, h2=8, scale=0.4):
+    return {"w1": rng.standard_normal((d_in, h1)) * scale, "b1": rng.standard_normal(h1) * 0.1,
+            "w2": rng.standard_normal((h1, h2)) * scale, "b2": rng.standard_normal(h2) * 0.1,
+            "w3": rng.standard_normal((h2, 2)) * scale, "b3": rng.standard_normal(2) * 0.1}
+
+
+def test_gradients_match_central_differences():
+    rng = np.random.default_rng(0)
+    p = small_params(rng)
+    x = rng.integers(0, 3, size=(7, 24)).astype(np.float64)
+    y = rng.random((7, 2))
+    scale = 1.0 / 14
+    acts, _ = S.forward(p, x, y)
+    g = S.backward(p, acts, y, scale)
+    eps = 1e-6
+    for name in ("w1", "b1", "w2", "b2", "w3", "b3"):
+        flat = p[name].reshape(-1)
+        idx = rng.choice(flat.size, size=min(12, flat.size), replace=False)
+        for i in idx:
+            old = flat[i]
+            flat[i] = old + eps
+            lp = S.forward(p, x, y)[1] * scale
+            flat[i] = old - eps
+            lm = S.forward(p, x, y)[1] * scale
+            flat[i] = old
+            num = (lp - lm) / (2 * eps)
+            ana = g[name].reshape(-1)[i]
+            assert abs(num - ana) <= 1e-6 + 1e-4 * abs(num), (name, i, num, ana)
+
+
+def test_bf16_rounding_exact_cases():
+    vals = np.array([1.0, 1.00390625, 1.005859375, 1.0078125, -2.5, 3.0e-39, 65504.0], dtype=np.float32)
+    r = S.bf16(vals)
+    # 1 + 2^-8 is a tie between 1 and 1 + 2^-7: rounds to even (1.0)
+    assert r[0] == 1.0 and r[1] == 1.0
+    assert r[2] == 1.0078125            # above the tie: rounds up
+    assert r[3] == 1.0078125 and r[4] == -2.5
+    assert r[6] == 65536.0              # 65504 rounds to 2^16 in bf16
+    assert np.isnan(S.bf16(np.array([np.nan], dtype=np.float32)))[0]
+    # every result has a zero low half
+    u = r.astype(np.float32).view(np.uint32)
+    assert np.all((u & 0xFFFF) == 0)
+
+
+def test_subtree_hash_properties():
+    a, b = ("atom", 3), ("exists", 1, 0, ("atom", 4))
+    f1 = S.subtree_features(("and", a, b))
+    f2 = S.subtree_features(("and", b, a))
+    assert f1[-1] == f2[-1]                                   # and/or: order independent
+    assert S.subtree_features(("exists", 1, 0, a))[-1] != S.subtree_features(("exists", 1, 1, a))[-1]
+    assert S.subtree_features(("atleast", 2, 1, 0, a))[-1] != S.subtree_features(("atleast", 3, 1, 0, a))[-1]
+    assert S.subtree_features(("dge", 0, 0.5))[-1] != S.subtree_features(("dle", 0, 0.5))[-1]
+    assert len(S.subtree_features(("or", a, ("not", b)))) == 5
+    x = S.dense_features([("and", a, b), ("atom", 3)])
+    assert x.sum(axis=1).tolist() == [4.0, 1.0]
+    # the atom's own feature is shared between the two hypotheses
+    fa = S.subtree_features(a)[0][1]
+    assert x[0, fa] >= 1 and x[1, fa] == 1
+
+
+def test_adamw_reference_first_step():
+    p, g = np.array([1.0, -2.0]), np.array([0.5, -0.25])
+    q, m, v = S.adamw(p, g, np.zeros(2), np.zeros(2), lr=0.1, b1=0.9, b2=0.999, eps=0.0, wd=0.0, step=1)
+    # first bias-corrected step moves each weight by lr * sign(g)
+    np.testing.assert_allclose(q, p - 0.1 * np.sign(g))

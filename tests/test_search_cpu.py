@@ -1,0 +1,63 @@
+"""Refinement and search logic on the CPU, with the oracle standing in for the
+exact engine (the search code only sees an `evaluate` callable)."""
+import numpy as np
+
+from oracle import Oracle
+from paper_2412_00802_amd import search, synth
+
+
+def small():
+    cfg = synth.small_config(n=1500, n_concepts=24, depth=3, n_roles=3, cap=20, n_data=2,
+                             n_pos=200, n_neg=200, seed_index=1300)
+    kb = synth.make_kb(cfg)
+    return cfg, kb, Oracle(kb)
+
+
+def test_refinements_are_specialisations():
+    cfg, kb, o = small()
+    rng = np.random.default_rng(0)
+    ref = search.Refiner(kb, rng)
+    parents = synth.make_hypotheses(cfg, kb, count=40, depth=4)
+    parents += [("top",), ("atom", 0), ("not", ("atom", 3)), ("atmost", 2, 0, 0, ("atom", 5)),
+                ("dge", 0, float(kb.deciles[0, 3])), ("not", ("atleast", 2, 1, 1, ("atom", 1)))]
+    checked = 0
+    for p in parents:
+        ep = o.ext(p)
+        kids = ref.refine(p, 12)
+        assert len(kids) == len(set(kids)) and p not in kids
+        for c in kids:
+            ec = o.ext(c)
+            assert not np.any(ec & ~ep), (p, c)
+            checked += 1
+    assert checked > 300
+
+
+def test_f1_ranking_exact_ties():
+    counts = np.array([[10, 5], [20, 10], [20, 10], [0, 0], [30, 40], [10, 5]])
+    order = search.rank(counts, n_pos=40, sizes=[3, 3, 2, 1, 1, 1])
+    # (20,10) and (10,5)?  F1 = 40/70 vs 20/55: (20,10) wins; equal rows break by size, then index
+    assert order[0] == 2 and order[1] == 1
+    assert order[-1] == 3
+    top = search.top_indices(counts, 40, 2)
+    assert sorted(top.tolist()) == [1, 2]
+
+
+def test_refinement_trace_with_oracle_engine():
+    cfg, kb, o = small()
+    n_pos = int(o.pos.sum())
+    rng = np.random.default_rng(1)
+    prev_beam = [("top",)]
+    for r, cands, counts in search.refinement_rounds(kb, o.coverages, n_pos, rounds=3, per_round=120,
+                                                    beam=8, rng=rng):
+        assert len(cands) == 120 == len(set(cands)) and counts.shape == (120, 2)
+        # every candidate specialises one of the previous round's beam
+        exts = [o.ext(p) for p in prev_beam]
+        for c in cands[:40]:
+            ec = o.ext(c)
+            assert any(not np.any(ec & ~ep) for ep in exts), c
+        prev_beam = [cands[i] for i in search.top_indices(counts, n_pos, 8)]
+
+
+def test_recall():
+    assert search.recall_at([1, 2, 3], [3, 4, 5]) == 1 / 3
+    assert search.recall_at(range(100), range(100)) == 1.0
