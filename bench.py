@@ -21,7 +21,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "exact hypotheses/sec + achieved HBM GB/s; screened vs plain exhaustive"
 HBM_PEAK_GBS = 8000.0
-KIND_NAMES = {0: "k_threshold", 1: "k_region", 2: "k_role", 3: "k_tbuild", 4: "k_group"}
+KIND_NAMES = {0: "k_threshold", 1: "k_region", 2: "k_role", 3: "k_tbuild", 4: "k_group", 5: "k_fill_rows"}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2412_00802_amd", "csrc", "exec.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2.json")
 COPY_BYTES = 256 << 20      # elementwise pass used to calibrate the byte counters
@@ -107,11 +107,20 @@ def log(*a):
 
 
 def describe(name, cfg, kb) -> str:
+    hyps = (f"{cfg.n_hyps} hypotheses with node counts geometric on 1..31, 30% of child subtrees "
+            f"drawn from a shared pool" if name == "c3" else
+            f"{cfg.n_hyps} random hypotheses of depth <= {cfg.hyp_depth}")
     return (f"{name}: {cfg.n_individuals:,} individuals, {cfg.n_concepts} concepts (tree depth "
             f"{cfg.tree_depth}), {cfg.n_roles} roles / {kb.n_edges:,} assertions (Zipf s={cfg.zipf_s}, "
             f"cap {cfg.degree_cap}), {cfg.n_data} float32 properties ({int(cfg.missing * 100)}% missing), "
-            f"{cfg.n_pos:,}+{cfg.n_neg:,} examples; {cfg.n_hyps} random hypotheses of depth <= "
-            f"{cfg.hyp_depth}, batched exact evaluation")
+            f"{cfg.n_pos:,}+{cfg.n_neg:,} examples; {hyps}; batched exact evaluation")
+
+
+def make_workload_hypotheses(name, cfg, kb):
+    from paper_2412_00802_amd import synth
+    if name == "c3":
+        return synth.make_sized_hypotheses(cfg, kb)
+    return synth.make_hypotheses(cfg, kb)
 
 
 def cpu_baseline(kb, hyps, sample: int, budget_s: float):
@@ -161,11 +170,12 @@ def main():
     cfg = synth.CONFIGS[args.config]
     t = time.perf_counter()
     kb = synth.make_kb(cfg)
-    hyps = synth.make_hypotheses(cfg, kb)
+    hyps = make_workload_hypotheses(args.config, cfg, kb)
     log(f"[bench] generated {args.config} in {time.perf_counter() - t:.1f}s: {kb.n_edges:,} assertions")
     nodes, offs, ch = hthedl.encode_batch(hyps)
     t = time.perf_counter()
-    eng = hthedl.Engine(kb, max_nodes=int(nodes.shape[0]), max_hyps=len(hyps))
+    eng = hthedl.Engine(kb, max_nodes=64, max_hyps=1)
+    eng.ensure_workspace(hthedl.hth_batch_workspace_bytes(eng.handle, nodes, offs, ch))
     torch.cuda.synchronize()
     log(f"[bench] uploaded + kb_create in {time.perf_counter() - t:.1f}s; workspace {eng.ws_bytes / 2**30:.2f} GiB")
     H = len(hyps)

@@ -127,6 +127,25 @@ hth_status hth_kb_set_examples(hth_kb kb, const uint64_t* pos_bits, const uint64
 /* Largest out-degree of role r in direction inv (0 = forward, 1 = inverse). */
 hth_status hth_kb_max_degree(hth_kb kb, uint32_t role, uint32_t inv, uint32_t* out);
 
+/* Schedule of the batched executor (no effect on results, only on speed).
+ * group_min: smallest (role, direction, level) bucket of role nodes evaluated
+ *   by shared CSR passes (0 = never share);
+ * group_k: most role nodes per shared pass (1..64; sets the transposed child
+ *   row width 8/16/32/64 bits);
+ * xcd_local: 1 = keep each shared pass on one XCD (its L2 holds the pass's
+ *   transposed child rows);
+ * t_budget_mb: transposed child rows resident per launch (MiB);
+ * unroll: assertions in flight per lane (8 or 16). */
+typedef struct {
+  uint32_t group_min;
+  uint32_t group_k;
+  uint32_t xcd_local;
+  uint32_t t_budget_mb;
+  uint32_t unroll;
+} hth_tuning;
+hth_status hth_kb_get_tuning(hth_kb kb, hth_tuning* out);
+hth_status hth_kb_set_tuning(hth_kb kb, const hth_tuning* t);   /* HTH_E_RANGE if out of range */
+
 /* Free the host handle.  Device memory is the caller's. */
 hth_status hth_kb_destroy(hth_kb kb);
 
@@ -143,6 +162,12 @@ hth_status hth_eval_one(hth_kb kb, const hth_node* nodes, uint32_t n_nodes,
                         const uint32_t* children, uint32_t n_children,
                         void* ws, size_t ws_bytes, uint64_t* d_instances, uint32_t* d_counts,
                         void* stream);
+
+/* Exact workspace hth_eval_batch needs for this batch (the batch is compiled on
+ * the host; nothing is launched).  Same arguments as hth_eval_batch. */
+hth_status hth_batch_workspace_bytes(hth_kb kb, const hth_node* nodes, const uint32_t* hyp_node_offsets,
+                                     uint32_t n_hyps, const uint32_t* children, uint32_t n_children,
+                                     size_t* bytes);
 
 /* Evaluate a batch.  Hypothesis h is nodes[hyp_node_offsets[h] .. hyp_node_offsets[h+1]),
  * its child indices local to that range; children[] entries are local too.
@@ -165,6 +190,7 @@ enum {
   HTH_K_ROLE = 2,       /* one role restriction per task */
   HTH_K_TBUILD = 3,     /* transposed child rows for shared role passes */
   HTH_K_GROUP = 4,      /* shared role passes (up to 64 role nodes per CSR scan) */
+  HTH_K_FILL = 5,       /* zero-count results of words without assertions */
   HTH_K_NUM = 8
 };
 typedef struct {
@@ -218,6 +244,10 @@ hth_status hth_gemm_bf16(int trans_a, int trans_b, int M, int N, int K, const ui
  * writes dz = (sigmoid(z) - y) * scale. */
 hth_status hth_head_forward(const uint16_t* h, int Bn, int Kd, const float* w, const float* bias,
                             float* z, const float* y, float* dz, float scale, float* loss, void* stream);
+
+/* Screening score from the logits z (fp32 [Bn][2]): the F1 of the predicted
+ * coverage, p = sigmoid(z0) n_pos, q = sigmoid(z1) n_neg, 2p / (p + q + n_pos). */
+hth_status hth_head_score(const float* z, int Bn, float n_pos, float n_neg, float* score, void* stream);
 
 /* Backward of the output layer: dw[k][o] = sum_b h[b][k] dz[b][o];
  * dh[b][k] = (dz[b] . w[k]) where h[b][k] > 0, else 0 (ReLU of the layer below). */

@@ -164,10 +164,11 @@ k_role(DevKB kb, const RoleTask* __restrict__ tasks, uint32_t bpt) {
   const uint32_t* off = (T.inv ? kb.inv_off : kb.fwd_off) + ro;
   const int32_t* tg = (T.inv ? kb.inv_tg : kb.fwd_tg) + kb.role_base[T.role];
   uint64_t* out = out_ptr(kb, T.out_row);
+  const uint32_t* words = kb.words + (size_t)(2 * T.role + T.inv) * kb.W;
   const uint32_t nw = blockDim.x >> 6;
   const int lane = threadIdx.x & 63;
-  for (uint32_t w = b * nw + (threadIdx.x >> 6); w < kb.W; w += bpt * nw)
-    role_word<STAGE>(kb, off, tg, child, T.neg, T.lo, T.hi, T.sat, out, w, lane);
+  for (uint32_t i = b * nw + (threadIdx.x >> 6); i < T.n_words; i += bpt * nw)
+    role_word<STAGE>(kb, off, tg, child, T.neg, T.lo, T.hi, T.sat, out, words[i], lane);
 }
 
 
@@ -257,6 +258,18 @@ __device__ __forceinline__ Planes<TW> planes_shfl_up(const Planes<TW>& p, int d)
   return Planes<TW>{shfl_up_w(p.c0, d), shfl_up_w(p.c1, d), shfl_up_w(p.c2, d), shfl_up_w(p.ov, d)};
 }
 
+// Zero-count results for the words of a role direction without assertions.
+__global__ void __launch_bounds__(256)
+k_fill_rows(DevKB kb, const FillTask* __restrict__ tasks, uint32_t tiles) {
+  const uint32_t t = blockIdx.x / tiles, tile = blockIdx.x % tiles;
+  const FillTask F = tasks[t];
+  const uint32_t w = tile * 256 + threadIdx.x;
+  if (w >= kb.S) return;
+  uint64_t v = 0;
+  if (F.ones && w < kb.W) v = w == kb.W - 1 ? kb.tail : ~0ull;
+  out_ptr(kb, F.out_row)[w] = v;
+}
+
 // 64 x 64 bit transpose across the lanes of a wave: on entry lane l holds row
 // l (bit j = M[l][j]); on exit lane l holds column l (bit j = M[j][l]).  Six
 // butterfly stages, each swapping the off-diagonal blocks with the partner lane.
@@ -315,19 +328,22 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
   for (int v = 0; v <= (int)kGroupMaxCount; ++v) acc[v] = (TW)G->acc[v];
   const uint32_t nw = blockDim.x >> 6;
   const uint32_t wstep = bpg * nw;
-  uint32_t w = b * nw + wv;
+  const uint32_t* words = kb.words + (size_t)(2 * G->role + G->inv) * kb.W;
+  const uint32_t n_words = G->n_words;
+  uint32_t i = b * nw + wv;
   uint32_t olo_n = 0, ohi_n = 0;     // row offsets of the wave's next word, fetched ahead
-  if (w < kb.W) {
-    const uint32_t xn = w * 64 + lane;
+  if (i < n_words) {
+    const uint32_t xn = words[i] * 64 + lane;
     olo_n = off[xn < kb.N ? xn : kb.N];
     ohi_n = xn < kb.N ? off[xn + 1] : olo_n;
   }
-  for (; w < kb.W; w += wstep) {
+  for (; i < n_words; i += wstep) {
+    const uint32_t w = words[i];
     const uint32_t x = w * 64 + lane;
     const bool in = x < kb.N;
     const uint32_t olo = olo_n, ohi = ohi_n;
-    if (w + wstep < kb.W) {
-      const uint32_t xn = (w + wstep) * 64 + lane;
+    if (i + wstep < n_words) {
+      const uint32_t xn = words[i + wstep] * 64 + lane;
       olo_n = off[xn < kb.N ? xn : kb.N];
       ohi_n = xn < kb.N ? off[xn + 1] : olo_n;
     }
@@ -489,6 +505,7 @@ DevKB dev_view(const hth_kb_s& kb) {
   d.fwd_tg = kb.d.role_targets;
   d.inv_tg = kb.inv_tg;
   d.role_base = kb.role_base_dev;
+  d.words = kb.words;
   d.pos = kb.pos;
   d.neg = kb.neg;
   d.n_concepts = kb.d.n_concepts;
@@ -550,8 +567,10 @@ double region_bytes(const hth_kb_s& kb, const RegionTask& t, const std::vector<u
 }
 
 // a CSR direction scanned once: 32-bit row offsets and the role's targets
-double csr_bytes(const hth_kb_s& kb, uint32_t role) {
-  return 4.0 * ((double)kb.N + 1) + 4.0 * (double)(kb.role_base[role + 1] - kb.role_base[role]);
+double csr_bytes(const hth_kb_s& kb, uint32_t role, uint32_t inv) {
+  const double words = kb.n_words.empty() ? kb.W : kb.n_words[2 * role + inv];
+  return 4.0 * std::min<double>((double)kb.N + 1, 65.0 * words) +
+         4.0 * (double)(kb.role_base[role + 1] - kb.role_base[role]);
 }
 
 hth_status launch_regions(Launcher& L, const DevKB& d, const RegionTask* tasks, const uint32_t* code,
@@ -573,7 +592,7 @@ hth_status launch_roles(Launcher& L, const DevKB& d, const RoleTask* tasks,
   const uint32_t n = (uint32_t)host.size();
   if (!n) return HTH_OK;
   double bytes = 0;
-  for (const RoleTask& t : host) bytes += csr_bytes(kb, t.role) + 2.0 * kb.W * 8;
+  for (const RoleTask& t : host) bytes += csr_bytes(kb, t.role, t.inv) + 2.0 * kb.W * 8;
   const size_t lds = (size_t)kb.W * 8;
   if (lds <= kb.lds_per_block) {
     uint32_t bpt = std::max<uint32_t>(1, (2 * kb.n_cu + n - 1) / n);
@@ -599,7 +618,7 @@ hth_status launch_group_chunk(Launcher& L, const DevKB& d, const GroupTask* grou
   for (uint32_t i = 0; i < n; ++i) {
     const GroupTask& G = host[g0 + i];
     tb += (double)G.k * kb.W * 8 + (double)t_stride * sizeof(TW);     // child rows in, T out
-    gb += csr_bytes(kb, G.role) + (double)t_stride * sizeof(TW) + (double)G.k * kb.W * 8;
+    gb += csr_bytes(kb, G.role, G.inv) + (double)t_stride * sizeof(TW) + (double)G.k * kb.W * 8;
   }
   TW* T = static_cast<TW*>(tarea);
   const uint32_t tiles = (kb.W + 255) / 256;
@@ -666,6 +685,29 @@ hth_status launch_groups(Launcher& L, const DevKB& d, const GroupTask* groups,
   return HTH_OK;
 }
 
+// bytes of the packed tables plus slots plus T area for a plan
+size_t plan_workspace_bytes(const hth_kb_s& kb, const Plan& P) {
+  size_t tables = 0;
+  auto add = [&](size_t n, size_t each) { tables = align_up(tables, 256) + n * each; };
+  size_t n_reg = P.roots.size(), n_role = 0, n_grp = 0, n_mem = 0, n_fill = 0, max_groups = 0;
+  for (const PlanLevel& PL : P.levels) {
+    n_reg += PL.mat.size();
+    n_role += PL.roles.size();
+    n_grp += PL.groups.size();
+    n_mem += PL.members.size();
+    n_fill += PL.roles.size() + PL.members.size();
+    max_groups = std::max(max_groups, PL.groups.size());
+  }
+  add(P.thr.size(), sizeof(ThrTask));
+  add(n_reg, sizeof(RegionTask));
+  add(n_role, sizeof(RoleTask));
+  add(n_grp, sizeof(GroupTask));
+  add(n_mem, sizeof(GroupMember));
+  add(n_fill, sizeof(FillTask));
+  add(P.code.size(), sizeof(uint32_t));
+  return align_up(tables, 256) + (size_t)P.n_slots * kb.S * 8 + (max_groups ? t_area_bytes(kb) : 0);
+}
+
 std::once_flag g_attr_once;
 
 hth_status run_plan(hth_kb_s& kb, const Plan& P, char* ws, size_t ws_bytes, uint32_t* counts,
@@ -678,19 +720,35 @@ hth_status run_plan(hth_kb_s& kb, const Plan& P, char* ws, size_t ws_bytes, uint
   std::vector<RoleTask> roles;
   std::vector<GroupTask> groups;
   std::vector<GroupMember> members;
-  struct LevelAt { size_t mat, role, group; };
+  std::vector<FillTask> fills;
+  struct LevelAt { size_t mat, role, group, fill, nrole, ngroup, nfill; };
   std::vector<LevelAt> at(P.levels.size());
+  std::vector<std::vector<RoleTask>> lv_roles(P.levels.size());
+  std::vector<std::vector<GroupTask>> lv_groups(P.levels.size());
   for (size_t L = 0; L < P.levels.size(); ++L) {
     const PlanLevel& PL = P.levels[L];
-    at[L] = {regions.size(), roles.size(), groups.size()};
+    at[L] = {regions.size(), roles.size(), groups.size(), fills.size(), 0, 0, 0};
     regions.insert(regions.end(), PL.mat.begin(), PL.mat.end());
-    roles.insert(roles.end(), PL.roles.begin(), PL.roles.end());
+    for (RoleTask t : PL.roles) {
+      t.n_words = kb.n_words[2 * t.role + t.inv];
+      if (t.n_words < kb.W) fills.push_back(FillTask{t.out_row, t.lo == 0 ? 1u : 0u});
+      roles.push_back(t);
+      lv_roles[L].push_back(t);
+    }
     const uint32_t mbase = (uint32_t)members.size();
     for (GroupTask g : PL.groups) {
+      g.n_words = kb.n_words[2 * g.role + g.inv];
+      if (g.n_words < kb.W)
+        for (uint32_t j = 0; j < g.k; ++j)
+          fills.push_back(FillTask{PL.members[g.first + j].out_row, (uint32_t)((g.acc[0] >> j) & 1)});
       g.first += mbase;
       groups.push_back(g);
+      lv_groups[L].push_back(g);
     }
     members.insert(members.end(), PL.members.begin(), PL.members.end());
+    at[L].nrole = roles.size() - at[L].role;
+    at[L].ngroup = groups.size() - at[L].group;
+    at[L].nfill = fills.size() - at[L].fill;
   }
   const size_t root_at = regions.size();
   regions.insert(regions.end(), P.roots.begin(), P.roots.end());
@@ -700,6 +758,7 @@ hth_status run_plan(hth_kb_s& kb, const Plan& P, char* ws, size_t ws_bytes, uint
   const size_t o_role = blob.add(roles);
   const size_t o_grp = blob.add(groups);
   const size_t o_mem = blob.add(members);
+  const size_t o_fill = blob.add(fills);
   const size_t o_code = blob.add(P.code);
   const size_t tables = align_up(blob.bytes.size(), 256);
   const size_t slot_bytes = (size_t)kb.S * 8;
@@ -724,6 +783,7 @@ hth_status run_plan(hth_kb_s& kb, const Plan& P, char* ws, size_t ws_bytes, uint
   const RoleTask* rol = reinterpret_cast<const RoleTask*>(ws + o_role);
   const GroupTask* grp = reinterpret_cast<const GroupTask*>(ws + o_grp);
   const GroupMember* mem = reinterpret_cast<const GroupMember*>(ws + o_mem);
+  const FillTask* fil = reinterpret_cast<const FillTask*>(ws + o_fill);
   const uint32_t* code = reinterpret_cast<const uint32_t*>(ws + o_code);
   Launcher Lc{kb, st};
   if (!P.thr.empty()) {
@@ -740,9 +800,16 @@ hth_status run_plan(hth_kb_s& kb, const Plan& P, char* ws, size_t ws_bytes, uint
     const PlanLevel& PL = P.levels[L];
     hth_status s = launch_regions(Lc, d, reg + at[L].mat, code, PL.mat, P.code);
     if (s) return s;
-    s = launch_roles(Lc, d, rol + at[L].role, PL.roles);
+    if (at[L].nfill) {
+      const uint32_t n = (uint32_t)at[L].nfill, tiles = (kb.S + 255) / 256;
+      s = Lc.run(HTH_K_FILL, (double)n * kb.W * 8, [&] {
+        hipLaunchKernelGGL(k_fill_rows, dim3(tiles * n), dim3(256), 0, st, d, fil + at[L].fill, tiles);
+      });
+      if (s) return s;
+    }
+    s = launch_roles(Lc, d, rol + at[L].role, lv_roles[L]);
     if (s) return s;
-    s = launch_groups(Lc, d, grp + at[L].group, mem, PL.groups, tarea);
+    s = launch_groups(Lc, d, grp + at[L].group, mem, lv_groups[L], tarea);
     if (s) return s;
   }
   return launch_regions(Lc, d, reg + root_at, code, P.roots, P.code);
@@ -796,6 +863,26 @@ extern "C" hth_status hth_eval_batch(hth_kb kb, const hth_node* nodes, const uin
   std::lock_guard<std::mutex> g(kb->mu);
   return run_plan(*kb, P, static_cast<char*>(ws), ws_bytes, d_counts, n_hyps, nullptr,
                   static_cast<hipStream_t>(stream));
+}
+
+extern "C" hth_status hth_batch_workspace_bytes(hth_kb kb, const hth_node* nodes,
+                                                 const uint32_t* hyp_node_offsets, uint32_t n_hyps,
+                                                 const uint32_t* children, uint32_t n_children,
+                                                 size_t* bytes) {
+  if (!kb || !nodes || !hyp_node_offsets || !bytes) return fail(HTH_E_INVALID, "NULL argument");
+  if (n_children && !children) return fail(HTH_E_INVALID, "children is NULL");
+  if (n_hyps == 0) {
+    *bytes = 0;
+    return HTH_OK;
+  }
+  PlanOptions opt;
+  opt.group_min = kb->tune.group_min ? kb->tune.group_min : 0xFFFFFFFFu;
+  opt.group_k = kb->tune.group_k;
+  Plan P;
+  hth_status s = compile_plan(*kb, nodes, hyp_node_offsets, n_hyps, children, n_children, opt, P);
+  if (s) return s;
+  *bytes = plan_workspace_bytes(*kb, P) + 4096;
+  return HTH_OK;
 }
 
 extern "C" hth_status hth_profile_begin(hth_kb kb) {

@@ -60,6 +60,15 @@ struct RoleTask {
   uint32_t neg;        // 0/1: complement the child before counting
   uint32_t lo, hi, sat;
   uint32_t out_row;    // n_concepts + slot
+  uint32_t n_words;    // non-empty words of (role, inv), set at launch
+  uint32_t pad;
+};
+
+// Output rows of role nodes whose (role, direction) has words without any
+// assertion: those words hold the zero-count result, all ones or all zeros.
+struct FillTask {
+  uint32_t out_row;
+  uint32_t ones;
 };
 
 // A CSR pass shared by up to 64 role nodes of one (role, direction, level):
@@ -74,6 +83,8 @@ struct GroupTask {
   uint32_t k;          // nodes in the group, 1..64
   uint32_t first;      // index of the group's first member in the member table
   uint64_t acc[9];
+  uint32_t n_words;    // non-empty words of (role, inv), set at launch
+  uint32_t pad;
 };
 constexpr uint32_t kGroupMaxCount = 8;
 struct GroupMember {
@@ -94,6 +105,7 @@ struct DevKB {
   const int32_t* fwd_tg;      // [E]
   const int32_t* inv_tg;      // [E]
   const uint64_t* role_base;  // [R] first assertion of each role (both directions)
+  const uint32_t* words;      // [R][2][W] non-empty words (role r, direction d at row 2r + d)
   const uint64_t* pos;        // [S]
   const uint64_t* neg;        // [S]
   uint32_t* counts;           // [n_hyps][2]
@@ -125,6 +137,8 @@ struct hth_kb_s {
   uint32_t* inv_off = nullptr;
   int32_t* inv_tg = nullptr;
   uint64_t* role_base_dev = nullptr;
+  uint32_t* words = nullptr;           // [R][2][W] non-empty words per role and direction
+  std::vector<uint32_t> n_words;       // [R][2]
   std::vector<uint64_t> role_base;     // [R+1]
   std::vector<uint32_t> max_deg[2];    // [R] forward, inverse
   const uint64_t* pos = nullptr;

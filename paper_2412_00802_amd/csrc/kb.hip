@@ -238,9 +238,39 @@ __global__ void k_scatter_inverse(const uint32_t* __restrict__ fwd_off, const in
 }
 
 struct DerivedLayout {
-  size_t fwd_off, inv_off, inv_tg, cursor, bsum, base, meta, total;
+  size_t fwd_off, inv_off, inv_tg, cursor, bsum, base, meta, words, total;
   uint32_t nb;
 };
+
+// Words (64 consecutive subjects) with at least one assertion, per role and
+// direction: the role passes visit only these.  One block per 256 words; each
+// block appends its non-empty words (in order) at an atomically reserved spot,
+// so the list order across blocks is not fixed (results do not depend on it).
+__global__ void __launch_bounds__(256)
+k_nonempty_words(const uint32_t* __restrict__ off, uint32_t N, uint32_t W, uint32_t* __restrict__ list,
+                 uint32_t* __restrict__ count) {
+  __shared__ uint32_t wsum[4], base;
+  const uint32_t dir_role = blockIdx.y;                 // 2 * role + direction
+  const uint32_t* o = off + (size_t)dir_role * (N + 1);
+  const uint32_t w = blockIdx.x * 256 + threadIdx.x;
+  bool ne = false;
+  if (w < W) {
+    const uint32_t a = w * 64, b = min(a + 64, N);
+    ne = o[b] != o[a];
+  }
+  const uint64_t m = __ballot(ne);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) wsum[wv] = (uint32_t)__popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    base = tot ? atomicAdd(count + dir_role, tot) : 0;
+  }
+  __syncthreads();
+  uint32_t before = base;
+  for (int i = 0; i < wv; ++i) before += wsum[i];
+  if (ne) list[(size_t)dir_role * W + before + (uint32_t)__popcll(m & ((1ull << lane) - 1))] = w;
+}
 
 static DerivedLayout layout_for(const hth_kb_desc& d) {
   DerivedLayout L{};
@@ -254,7 +284,8 @@ static DerivedLayout layout_for(const hth_kb_desc& d) {
   L.cursor = at; at += offs;
   L.bsum = at; at += align_up(R * L.nb * 4 + 4, 256);
   L.base = at; at += align_up((R + 1) * 8, 256);
-  L.meta = at; at += align_up((4 + 2 * R) * 4, 256);
+  L.meta = at; at += align_up((4 + 4 * R) * 4, 256);
+  L.words = at; at += align_up(2 * R * ((N + 63) / 64) * 4, 256);
   L.total = at;
   return L;
 }
@@ -310,7 +341,7 @@ static hth_status kb_build(hth_kb_s* kb, char* derived, hipStream_t st) {
     unsigned g = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
     hipLaunchKernelGGL(k_fill_u32, dim3(g), dim3(256), 0, st, p, n, v);
   };
-  fill(meta, 4 + 2 * R, 0);
+  fill(meta, 4 + 4 * R, 0);
   const uint32_t tb = 256;
   // padding of concept rows and example rows
   if (d.n_concepts)
@@ -368,6 +399,22 @@ static hth_status kb_build(hth_kb_s* kb, char* derived, hipStream_t st) {
     HTH_HIP(hipGetLastError());
     HTH_HIP(hipMemcpyAsync(kb->max_deg[0].data(), maxdeg, R * 4, hipMemcpyDeviceToHost, st));
     HTH_HIP(hipMemcpyAsync(kb->max_deg[1].data(), maxdeg + R, R * 4, hipMemcpyDeviceToHost, st));
+    // non-empty word lists; the two directions' offsets are [R][N+1] each, so
+    // run the kernel once per direction with list rows 2r + dir
+    uint32_t* words = reinterpret_cast<uint32_t*>(derived + L.words);
+    uint32_t* wcount = meta + 4 + 2 * R;                  // [R][2]
+    kb->words = words;
+    for (int dir = 0; dir < 2; ++dir) {
+      const uint32_t* off = dir ? kb->inv_off : kb->fwd_off;
+      for (uint32_t r = 0; r < R; ++r) {
+        hipLaunchKernelGGL(k_nonempty_words, dim3((kb->W + 255) / 256, 1), dim3(256), 0, st,
+                           off + (size_t)r * (N + 1), N, kb->W,
+                           words + (size_t)(2 * r + dir) * kb->W, wcount + 2 * r + dir);
+      }
+    }
+    HTH_HIP(hipGetLastError());
+    kb->n_words.assign(2 * R, 0);
+    HTH_HIP(hipMemcpyAsync(kb->n_words.data(), wcount, 2 * R * 4, hipMemcpyDeviceToHost, st));
   }
   uint32_t hflags = 0;
   HTH_HIP(hipMemcpyAsync(&hflags, flags, 4, hipMemcpyDeviceToHost, st));
@@ -436,6 +483,31 @@ extern "C" hth_status hth_kb_max_degree(hth_kb kb, uint32_t role, uint32_t inv, 
   if (!kb || !out) return fail(HTH_E_INVALID, "NULL argument");
   if (role >= kb->d.n_roles || inv > 1) return fail(HTH_E_RANGE, "role or direction out of range");
   *out = kb->max_deg[inv][role];
+  return HTH_OK;
+}
+
+extern "C" hth_status hth_kb_get_tuning(hth_kb kb, hth_tuning* out) {
+  if (!kb || !out) return fail(HTH_E_INVALID, "NULL argument");
+  std::lock_guard<std::mutex> g(kb->mu);
+  out->group_min = kb->tune.group_min;
+  out->group_k = kb->tune.group_k;
+  out->xcd_local = kb->tune.xcd_local;
+  out->t_budget_mb = (uint32_t)(kb->tune.t_budget >> 20);
+  out->unroll = kb->tune.group_unroll;
+  return HTH_OK;
+}
+
+extern "C" hth_status hth_kb_set_tuning(hth_kb kb, const hth_tuning* t) {
+  if (!kb || !t) return fail(HTH_E_INVALID, "NULL argument");
+  if (t->group_k < 1 || t->group_k > 64 || t->xcd_local > 1 || t->t_budget_mb < 1 ||
+      t->t_budget_mb > (1u << 20) || (t->unroll != 8 && t->unroll != 16))
+    return fail(HTH_E_RANGE, "tuning value out of range");
+  std::lock_guard<std::mutex> g(kb->mu);
+  kb->tune.group_min = t->group_min;
+  kb->tune.group_k = t->group_k;
+  kb->tune.xcd_local = t->xcd_local;
+  kb->tune.t_budget = (size_t)t->t_budget_mb << 20;
+  kb->tune.group_unroll = t->unroll;
   return HTH_OK;
 }
 

@@ -273,6 +273,17 @@ __global__ void k_head_forward(const __bf16* __restrict__ h, int Bn, int Kd, con
   }
 }
 
+// predicted F1 of each candidate from its two logits: p = sigmoid(z0) |P|,
+// q = sigmoid(z1) |Ng|, F1 = 2p / (p + q + |P|)
+__global__ void k_head_score(const float* __restrict__ z, int Bn, float n_pos, float n_neg,
+                             float* __restrict__ score) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= Bn) return;
+  const float p = n_pos / (1.f + expf(-z[2 * b])), q = n_neg / (1.f + expf(-z[2 * b + 1]));
+  const float den = p + q + n_pos;
+  score[b] = den > 0.f ? 2.f * p / den : 0.f;
+}
+
 // dw[k][o] = sum_b h[b][k] dz[b][o] (one block per k); dh[b][k] = (dz[b] . w[k]) * (h[b][k] > 0)
 __global__ void __launch_bounds__(256)
 k_head_backward(const __bf16* __restrict__ h, int Bn, int Kd, const float* __restrict__ w,
@@ -454,6 +465,16 @@ extern "C" hth_status hth_head_forward(const uint16_t* h, int Bn, int Kd, const 
   if (Bn <= 0) return HTH_OK;
   hipLaunchKernelGGL(k_head_forward, dim3((Bn + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream),
                      reinterpret_cast<const __bf16*>(h), Bn, Kd, w, bias, z, y, dz, scale, loss);
+  HTH_HIP(hipGetLastError());
+  return HTH_OK;
+}
+
+extern "C" hth_status hth_head_score(const float* z, int Bn, float n_pos, float n_neg, float* score,
+                                     void* stream) {
+  if (!z || !score) return fail(HTH_E_INVALID, "NULL argument");
+  if (Bn <= 0) return HTH_OK;
+  hipLaunchKernelGGL(k_head_score, dim3((Bn + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream),
+                     z, Bn, n_pos, n_neg, score);
   HTH_HIP(hipGetLastError());
   return HTH_OK;
 }

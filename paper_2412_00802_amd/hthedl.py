@@ -33,7 +33,8 @@ EXPORTED = ["hth_kb_derived_bytes", "hth_kb_create", "hth_kb_set_examples", "hth
             "hth_kb_destroy", "hth_workspace_bytes", "hth_eval_one", "hth_eval_batch",
             "hth_sync", "hth_status_str", "hth_last_error", "hth_profile_begin",
             "hth_profile_end", "hth_features", "hth_densify", "hth_gemm_bf16", "hth_head_forward",
-            "hth_head_backward", "hth_colsum", "hth_adamw", "hth_to_bf16", "hth_topk"]
+            "hth_head_backward", "hth_colsum", "hth_adamw", "hth_to_bf16", "hth_topk",
+            "hth_batch_workspace_bytes", "hth_head_score", "hth_kb_get_tuning", "hth_kb_set_tuning"]
 
 
 class HthError(RuntimeError):
@@ -49,6 +50,15 @@ class KBDesc(ctypes.Structure):
                 ("role_offsets", ctypes.c_void_p), ("role_targets", ctypes.c_void_p),
                 ("n_data", ctypes.c_uint32), ("data", ctypes.c_void_p),
                 ("pos_bits", ctypes.c_void_p), ("neg_bits", ctypes.c_void_p)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("group_min", ctypes.c_uint32), ("group_k", ctypes.c_uint32),
+                ("xcd_local", ctypes.c_uint32), ("t_budget_mb", ctypes.c_uint32),
+                ("unroll", ctypes.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 class ProfEntry(ctypes.Structure):
@@ -75,9 +85,12 @@ def lib() -> ctypes.CDLL:
             "hth_kb_set_examples": [P, P, P],
             "hth_kb_max_degree": [P, U32, U32, ctypes.POINTER(U32)],
             "hth_kb_destroy": [P],
+            "hth_kb_get_tuning": [P, ctypes.POINTER(Tuning)],
+            "hth_kb_set_tuning": [P, ctypes.POINTER(Tuning)],
             "hth_workspace_bytes": [P, U32, U32, ctypes.POINTER(S)],
             "hth_eval_one": [P, P, U32, P, U32, P, S, P, P, P],
             "hth_eval_batch": [P, P, P, U32, P, U32, P, S, P, P],
+            "hth_batch_workspace_bytes": [P, P, P, U32, P, U32, ctypes.POINTER(S)],
             "hth_sync": [P],
             "hth_profile_begin": [P],
             "hth_profile_end": [P, ctypes.POINTER(ProfEntry)],
@@ -86,6 +99,7 @@ def lib() -> ctypes.CDLL:
             "hth_gemm_bf16": [I, I, I, I, I, P, I, P, I, P, I, P, I, P, I, P, I, P],
             "hth_head_forward": [P, I, I, P, P, P, P, P, F, P, P],
             "hth_head_backward": [P, I, I, P, P, P, P, P],
+            "hth_head_score": [P, I, F, F, P, P],
             "hth_colsum": [P, I, I, I, P, P],
             "hth_adamw": [P, P, P, P, P, S, F, F, F, F, F, I, P],
             "hth_to_bf16": [P, P, S, P],
@@ -167,6 +181,17 @@ def hth_kb_max_degree(kb, role: int, inv: int) -> int:
     return out.value
 
 
+def hth_kb_get_tuning(kb) -> dict:
+    t = Tuning()
+    _check(lib().hth_kb_get_tuning(kb, ctypes.byref(t)))
+    return t.as_dict()
+
+
+def hth_kb_set_tuning(kb, **kw) -> None:
+    t = Tuning(**{**hth_kb_get_tuning(kb), **kw})
+    _check(lib().hth_kb_set_tuning(kb, ctypes.byref(t)))
+
+
 def hth_kb_destroy(kb) -> None:
     _check(lib().hth_kb_destroy(kb))
 
@@ -194,6 +219,16 @@ def hth_eval_batch(kb, nodes: np.ndarray, offsets: np.ndarray, children: np.ndar
     _check(lib().hth_eval_batch(kb, _np_ptr(nodes), _np_ptr(offsets), offsets.shape[0] - 1,
                                 _np_ptr(children), children.shape[0], _ptr(ws), ws_bytes,
                                 _ptr(d_counts), _stream(stream)))
+
+
+def hth_batch_workspace_bytes(kb, nodes: np.ndarray, offsets: np.ndarray, children: np.ndarray) -> int:
+    nodes = np.ascontiguousarray(nodes, dtype=NODE_DTYPE)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint32)
+    children = np.ascontiguousarray(children, dtype=np.uint32)
+    out = ctypes.c_size_t()
+    _check(lib().hth_batch_workspace_bytes(kb, _np_ptr(nodes), _np_ptr(offsets), offsets.shape[0] - 1,
+                                           _np_ptr(children), children.shape[0], ctypes.byref(out)))
+    return out.value
 
 
 def hth_sync(stream=None) -> None:
@@ -238,6 +273,10 @@ def hth_head_forward(h, Bn: int, Kd: int, w, bias, z, y=None, dz=None, scale: fl
                      stream=None) -> None:
     _check(lib().hth_head_forward(_ptr(h), Bn, Kd, _ptr(w), _ptr(bias), _ptr(z), _ptr(y), _ptr(dz),
                                   scale, _ptr(loss), _stream(stream)))
+
+
+def hth_head_score(z, Bn: int, n_pos: float, n_neg: float, score, stream=None) -> None:
+    _check(lib().hth_head_score(_ptr(z), Bn, n_pos, n_neg, _ptr(score), _stream(stream)))
 
 
 def hth_head_backward(h, Bn: int, Kd: int, w, dz, dw, dh, stream=None) -> None:
@@ -310,18 +349,60 @@ def encode_one(h) -> Tuple[np.ndarray, np.ndarray]:
     return np.array(nodes, dtype=NODE_DTYPE), np.array(children, dtype=np.uint32)
 
 
-def encode_batch(hyps: Sequence) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
-    """-> (nodes, hyp_node_offsets [H+1], children); child indices are local."""
+def encode_batch(hyps: Sequence, child_offsets: bool = False):
+    """-> (nodes, hyp_node_offsets [H+1], children); child indices are local.
+    With child_offsets, also the [H+1] start of each hypothesis's children."""
     allnodes: List[tuple] = []
     children: List[int] = []
     offs = [0]
+    coffs = [0]
     for h in hyps:
         local: list = []
         encode(h, local, children)
         allnodes.extend(local)
         offs.append(len(allnodes))
-    return (np.array(allnodes, dtype=NODE_DTYPE), np.array(offs, dtype=np.uint32),
-            np.array(children, dtype=np.uint32))
+        coffs.append(len(children))
+    out = (np.array(allnodes, dtype=NODE_DTYPE), np.array(offs, dtype=np.uint32),
+           np.array(children, dtype=np.uint32))
+    return out + (np.array(coffs, dtype=np.int64),) if child_offsets else out
+
+
+def gather_encoded(encoded, idx: np.ndarray):
+    """The hypotheses `idx` of an encode_batch(..., child_offsets=True) result,
+    as a new batch (nodes, offsets, children)."""
+    nodes, offs, ch, coffs = encoded
+    idx = np.asarray(idx, dtype=np.int64)
+    offs = offs.astype(np.int64)
+    nlen = offs[idx + 1] - offs[idx]
+    clen = coffs[idx + 1] - coffs[idx]
+    new_offs = np.zeros(idx.size + 1, dtype=np.int64)
+    np.cumsum(nlen, out=new_offs[1:])
+    new_coffs = np.zeros(idx.size + 1, dtype=np.int64)
+    np.cumsum(clen, out=new_coffs[1:])
+    node_src = np.repeat(offs[idx] - new_offs[:-1], nlen) + np.arange(new_offs[-1])
+    ch_src = np.repeat(coffs[idx] - new_coffs[:-1], clen) + np.arange(new_coffs[-1])
+    sub = nodes[node_src].copy()
+    shift = np.repeat(coffs[idx] - new_coffs[:-1], nlen)
+    ands = (sub["op"] == OPS["and"]) | (sub["op"] == OPS["or"])
+    sub["child"][ands] = (sub["child"][ands].astype(np.int64) - shift[ands]).astype(np.uint32)
+    return sub, new_offs.astype(np.uint32), ch[ch_src].copy()
+
+
+def slice_encoded(encoded, a: int, b: int):
+    """Hypotheses [a, b) of an encode_batch result, re-based.  Their children
+    entries are contiguous because encode_batch appends per hypothesis."""
+    nodes, offs, ch = encoded
+    n0, n1 = int(offs[a]), int(offs[b])
+    sub = nodes[n0:n1].copy()
+    ands = (sub["op"] == OPS["and"]) | (sub["op"] == OPS["or"])
+    if ands.any():
+        lo = int(sub["child"][ands].min())
+        hi = int((sub["child"][ands] + sub["arity"][ands]).max())
+        sub["child"][ands] -= lo
+        sub_ch = ch[lo:hi].copy()
+    else:
+        sub_ch = np.zeros(0, dtype=np.uint32)
+    return sub, (offs[a:b + 1] - offs[a]).astype(np.uint32), sub_ch
 
 
 # ---------------------------------------------------------------------------
@@ -428,14 +509,28 @@ class Engine:
             self.eval_one(h, counts=out[i], stream=stream)
         return out.cpu().numpy().view(np.uint32)
 
-    def eval_batch(self, hyps: Sequence, stream=None, counts=None) -> Optional[np.ndarray]:
-        """The whole batch compiled and run together; uint32 [H][2]."""
+    def ensure_workspace(self, nbytes: int) -> None:
+        if nbytes > self.ws_bytes:
+            self.ws = None
+            self.ws = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
+            self.ws_bytes = nbytes
+
+    def eval_batch(self, hyps: Sequence, stream=None, counts=None, chunk: Optional[int] = None,
+                   encoded=None) -> Optional[np.ndarray]:
+        """Batched evaluation; uint32 [H][2].  Batches larger than `chunk`
+        hypotheses are run as consecutive sub-batches (each compiled alone)."""
         torch = self.torch
-        nodes, offs, ch = encode_batch(hyps)
-        self.reserve(nodes.shape[0], len(hyps))
-        out = counts if counts is not None else torch.empty((len(hyps), 2), dtype=torch.int32,
-                                                             device=self.device)
-        hth_eval_batch(self.handle, nodes, offs, ch, self.ws, self.ws_bytes, out, stream)
+        H = len(hyps) if encoded is None else int(encoded[1].shape[0] - 1)
+        out = counts if counts is not None else torch.empty((H, 2), dtype=torch.int32, device=self.device)
+        chunk = H if not chunk else chunk
+        for a in range(0, H, chunk):
+            b = min(H, a + chunk)
+            if encoded is None:
+                nodes, offs, ch = encode_batch(hyps[a:b])
+            else:
+                nodes, offs, ch = slice_encoded(encoded, a, b)
+            self.ensure_workspace(hth_batch_workspace_bytes(self.handle, nodes, offs, ch))
+            hth_eval_batch(self.handle, nodes, offs, ch, self.ws, self.ws_bytes, out[a:b], stream)
         if counts is not None:
             return None
         return out.cpu().numpy().view(np.uint32)

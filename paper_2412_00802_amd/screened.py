@@ -1,0 +1,199 @@
+"""Screened search (the c5 workload): train the screener on engine-evaluated
+refinements, then rank a large candidate set with it and evaluate exactly only
+the top fraction plus a uniform audit sample.  The exact engine supplies every
+training label and judges the screener: recall of the exhaustive top-k.
+
+    python -m paper_2412_00802_amd.screened [--small]
+
+Prints one JSON line: screened vs exhaustive hypotheses/s, top-100 recall,
+training time and loss, and the same recall for random selection and for the
+parents' F1 at the same exact budget.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+from typing import List
+
+import numpy as np
+
+from . import hthedl, search, synth
+from .screener import D_IN, FeatureBatch, Screener, init_params
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def coverage_targets(counts: np.ndarray, n_pos: int, n_neg: int) -> np.ndarray:
+    c = counts.astype(np.float64)
+    return np.stack([c[:, 0] / max(1, n_pos), c[:, 1] / max(1, n_neg)], 1).astype(np.float32)
+
+
+def gather_training_pairs(eng, kb, n_pairs, per_round, beam, rng, chunk):
+    """Refinement rounds from top; every candidate is evaluated exactly."""
+    hyps: List[tuple] = []
+    counts = []
+    ev = lambda hs: eng.eval_batch(hs, chunk=chunk)  # noqa: E731
+    rounds = (n_pairs + per_round - 1) // per_round
+    last = None
+    for r, cands, cnt in search.refinement_rounds(kb, ev, eng.n_pos, rounds, per_round, beam, rng):
+        hyps.extend(cands)
+        counts.append(cnt)
+        last = (cands, cnt)
+        log(f"[screen] training round {r}: {len(hyps)} pairs, best F1 "
+            f"{search.f1_float(cnt, eng.n_pos).max():.4f}")
+    return hyps[:n_pairs], np.concatenate(counts)[:n_pairs], last
+
+
+def train(scr: Screener, fb: FeatureBatch, y_dev, n: int, epochs: int, batch: int, rng) -> List[float]:
+    torch = scr.t
+    losses = []
+    nb = n // batch
+    for ep in range(epochs):
+        scr.loss.zero_()
+        for bi in rng.permutation(nb):
+            r0 = int(bi) * batch
+            fb.densify(r0, batch, scr.x)
+            scr.train_step(batch, y_dev[r0:r0 + batch])
+        losses.append(scr.loss.item() / (2 * nb * batch))
+        log(f"[screen] epoch {ep}: loss {losses[-1]:.5f}")
+    torch.cuda.synchronize()
+    return losses
+
+
+def score(scr: Screener, fb: FeatureBatch, n: int, n_pos: int, n_neg: int, out) -> None:
+    B = scr.batch
+    for r0 in range(0, n, B):
+        m = min(B, n - r0)
+        fb.densify(r0, m, scr.x)
+        z = scr.logits(m)
+        hthedl.hth_head_score(z, m, float(n_pos), float(n_neg), out[r0:r0 + m])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--small", action="store_true", help="a reduced run of the same pipeline")
+    ap.add_argument("--pairs", type=int, default=200_000)
+    ap.add_argument("--candidates-beam", type=int, default=4096)
+    ap.add_argument("--refinements", type=int, default=256)
+    ap.add_argument("--epochs", type=int, default=10)
+    ap.add_argument("--top", type=float, default=0.02)
+    ap.add_argument("--audit", type=float, default=0.005)
+    ap.add_argument("--k", type=int, default=100)
+    args = ap.parse_args()
+    import torch
+
+    cfg = synth.CONFIGS["c3"]
+    per_round, chunk = 16384, 65536
+    if args.small:
+        cfg = synth.small_config(n=200_000, n_concepts=256, depth=5, n_roles=12, s=1.6, cap=1024,
+                                 n_data=8, missing=0.1, n_pos=10_000, n_neg=10_000, seed_index=3,
+                                 total_edges=2_000_000)
+        cfg = synth.KBConfig(**{**cfg.__dict__, "examples": "planted"})
+        args.pairs, args.candidates_beam, args.refinements = 40_000, 512, 128
+        per_round = 8192
+    t = time.perf_counter()
+    kb = synth.make_kb(cfg)
+    log(f"[screen] KB {cfg.name}: N={kb.n:,}, {kb.n_edges:,} assertions ({time.perf_counter() - t:.1f}s)")
+    eng = hthedl.Engine(kb, max_nodes=64, max_hyps=1)
+    rng = np.random.default_rng(synth.BASE_SEED + 50)
+
+    # 1. training pairs from the engine
+    t = time.perf_counter()
+    hyps, counts, last = gather_training_pairs(eng, kb, args.pairs, per_round, 256, rng, chunk)
+    t_pairs = time.perf_counter() - t
+    order = rng.permutation(len(hyps))
+    hyps = [hyps[i] for i in order]
+    counts = counts[order]
+    n_val = len(hyps) // 10
+    n_tr = len(hyps) - n_val
+    enc = hthedl.encode_batch(hyps)
+    fb = FeatureBatch(*enc)
+    y = torch.from_numpy(coverage_targets(counts, eng.n_pos, eng.n_neg)).cuda()
+
+    # 2. training
+    scr = Screener(init_params(seed=11), batch=8192, lr=1e-3)
+    t = time.perf_counter()
+    losses = train(scr, fb, y, n_tr, args.epochs, 1024, rng)
+    t_train = time.perf_counter() - t
+
+    # 3. candidates: the best `beam` evaluated so far, each refined
+    top = search.top_indices(counts, eng.n_pos, args.candidates_beam)
+    parents = [hyps[i] for i in top]
+    ref = search.Refiner(kb, rng)
+    cands, parent_of = [], []
+    seen = set()
+    for pi, p in enumerate(parents):
+        for c in ref.refine(p, args.refinements):
+            if c not in seen:
+                seen.add(c)
+                cands.append(c)
+                parent_of.append(pi)
+    parent_of = np.asarray(parent_of)
+    n = len(cands)
+    log(f"[screen] {n:,} candidates from {len(parents)} parents")
+    cenc = hthedl.encode_batch(cands, child_offsets=True)
+    cfb = FeatureBatch(*cenc[:3])
+    n_sel = int(round(args.top * n))
+    n_aud = int(round(args.audit * n))
+    audit = rng.choice(n, size=n_aud, replace=False)           # drawn on the host: an input
+    scores = torch.empty(n, dtype=torch.float32, device="cuda")
+    sel = torch.empty(n_sel, dtype=torch.int32, device="cuda")
+    work = torch.empty(65538, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+
+    # 4. screened: features + scores + top-k + exact evaluation of the selection
+    t0 = time.perf_counter()
+    cfb.recompute()
+    score(scr, cfb, n, eng.n_pos, eng.n_neg, scores)
+    hthedl.hth_topk(scores, n, n_sel, sel, work)
+    chosen = np.union1d(sel.cpu().numpy().astype(np.int64), audit)
+    sub = hthedl.gather_encoded(cenc, chosen)
+    sc = torch.empty((chosen.size, 2), dtype=torch.int32, device="cuda")
+    eng.eval_batch(None, counts=sc, chunk=chunk, encoded=sub)
+    sc_np = sc.cpu().numpy().view(np.uint32)
+    screened_top = chosen[search.top_indices(sc_np, eng.n_pos, args.k)]
+    torch.cuda.synchronize()
+    t_screen = time.perf_counter() - t0
+
+    # 5. exhaustive exact evaluation of every candidate
+    t0 = time.perf_counter()
+    allc = torch.empty((n, 2), dtype=torch.int32, device="cuda")
+    eng.eval_batch(None, counts=allc, chunk=chunk, encoded=cenc[:3])
+    all_np = allc.cpu().numpy().view(np.uint32)
+    exact_top = search.top_indices(all_np, eng.n_pos, args.k)
+    torch.cuda.synchronize()
+    t_exh = time.perf_counter() - t0
+
+    # the exact engine judges the screener's selection
+    assert np.array_equal(all_np[chosen], sc_np), "screened and exhaustive exact counts differ"
+    recall = search.recall_at(screened_top, exact_top)
+    budget = chosen.size
+    rand = rng.choice(n, size=budget, replace=False)
+    rand_top = rand[search.top_indices(all_np[rand], eng.n_pos, args.k)]
+    pf1 = search.f1_float(counts[top], eng.n_pos)[parent_of]
+    heur = np.argsort(-pf1, kind="stable")[:budget]
+    heur_top = heur[search.top_indices(all_np[heur], eng.n_pos, args.k)]
+    s_np = scores.cpu().numpy()
+    f_np = search.f1_float(all_np, eng.n_pos)
+    rank_corr = float(np.corrcoef(np.argsort(np.argsort(s_np)), np.argsort(np.argsort(f_np)))[0, 1])
+    out = {
+        "workload": f"screened search on the {cfg.name} KB ({kb.n:,} individuals)",
+        "candidates": n, "exact_budget": int(budget), "top_fraction": args.top, "audit_fraction": args.audit,
+        "screened_hyp_per_s": round(n / t_screen, 1), "exhaustive_hyp_per_s": round(n / t_exh, 1),
+        "speedup": round(t_exh / t_screen, 3),
+        f"recall_at_{args.k}": recall, f"random_recall_at_{args.k}": search.recall_at(rand_top, exact_top),
+        f"parent_f1_recall_at_{args.k}": search.recall_at(heur_top, exact_top),
+        "score_rank_correlation": round(rank_corr, 4),
+        "training_pairs": len(hyps), "pairs_seconds": round(t_pairs, 2), "train_seconds": round(t_train, 2),
+        "train_loss_first_last": [round(losses[0], 5), round(losses[-1], 5)],
+        "screened_seconds": round(t_screen, 4), "exhaustive_seconds": round(t_exh, 4),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -120,7 +120,12 @@ class FeatureBatch:
         self.hash = t.empty(max(1, n_nodes), dtype=t.int64, device=device)
         self.feat = t.empty(max(1, n_nodes), dtype=t.int16, device=device)
         self.bad = t.zeros(1, dtype=t.int32, device=device)
-        hthedl.hth_features(self.nodes, self.offsets, self.n_hyps, self.children, int(children.size),
+        self.n_children = int(children.size)
+        self.recompute()
+
+    def recompute(self) -> None:
+        """Hash the resident node arrays again (the features step of screening)."""
+        hthedl.hth_features(self.nodes, self.offsets, self.n_hyps, self.children, self.n_children,
                             self.hash, self.feat, self.bad)
 
     def densify(self, row0: int, n: int, x) -> None:
