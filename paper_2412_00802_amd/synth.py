@@ -80,6 +80,9 @@ CONFIGS = {
     # uneven batch (sparse roles: ~40M edges over 48 roles)
     "c3": KBConfig("c3", 4_000_000, 1024, 6, 48, 1.6, 8192, 32, 0.10, 200_000, 200_000,
                    65_536, 5, total_edges=40_000_000, seed_index=3, examples="planted"),
+    # refinement trace at large scale (16 rounds x 16,384 candidates)
+    "c4": KBConfig("c4", 32_000_000, 1024, 6, 64, 1.5, 65_536, 128, 0.10, 1_000_000, 1_000_000,
+                   16_384, 2, total_edges=500_000_000, seed_index=4, examples="planted"),
 }
 
 
@@ -179,8 +182,14 @@ def _streams(cfg: KBConfig, k: int = 6) -> List[np.random.SeedSequence]:
 # ---------------------------------------------------------------------------
 
 
-def _gen_concepts(cfg: KBConfig, ss: np.random.SeedSequence):
-    rng = np.random.default_rng(ss)
+def _gen_concepts(cfg: KBConfig, ss: np.random.SeedSequence, workers: int = 1):
+    """Levels of equal size; a root-level concept holds each individual with
+    probability root_density, a deeper concept keeps each member of a uniform
+    parent on the level above with probability 1/2.  The tree comes from one
+    stream, each concept's row from a stream of its own (rows of one level are
+    drawn in parallel)."""
+    tree_ss, row_ss = ss.spawn(2)
+    rng = np.random.default_rng(tree_ss)
     n, c, depth = cfg.n_individuals, cfg.n_concepts, cfg.tree_depth
     w = cfg.words
     sizes = [c // depth] * depth
@@ -190,21 +199,26 @@ def _gen_concepts(cfg: KBConfig, ss: np.random.SeedSequence):
     parent = np.full(c, -1, dtype=np.int32)
     level = np.zeros(c, dtype=np.int32)
     tail = _tail_mask(n)
+    streams = row_ss.spawn(c)
     start = 0
     prev = None
     for lv, sz in enumerate(sizes):
         ids = np.arange(start, start + sz)
         level[ids] = lv
-        for cid in ids:
-            if lv == 0:
-                row = pack_bits(rng.random(n, dtype=np.float32) < cfg.root_density)
+        if lv:
+            parent[ids] = prev[rng.integers(0, len(prev), size=sz)]
+
+        def row(cid):
+            r = np.random.default_rng(streams[cid])
+            if parent[cid] < 0:
+                out = pack_bits(r.random(n, dtype=np.float32) < cfg.root_density)
             else:
-                p = int(prev[rng.integers(0, len(prev))])
-                parent[cid] = p
-                keep = rng.bit_generator.random_raw(w).astype(np.uint64)
-                row = bits[p] & keep
-            row[-1] &= tail
-            bits[cid] = row
+                out = bits[parent[cid]] & r.bit_generator.random_raw(w).astype(np.uint64)
+            out[-1] &= tail
+            bits[cid] = out
+
+        with _cf.ThreadPoolExecutor(max_workers=workers) as ex:
+            list(ex.map(row, ids.tolist()))
         prev = ids
         start += sz
     return bits, parent, level
@@ -292,20 +306,28 @@ def _gen_roles(cfg: KBConfig, ss: np.random.SeedSequence, workers: int):
 # ---------------------------------------------------------------------------
 
 
-def _gen_data(cfg: KBConfig, ss: np.random.SeedSequence):
-    rng = np.random.default_rng(ss)
+def _gen_data(cfg: KBConfig, ss: np.random.SeedSequence, workers: int = 1):
+    """float32 N(0,1) columns, a Bernoulli(missing) share set to NaN, one
+    stream per property (columns drawn in parallel); deciles as the order
+    statistics t_k = v_((k (m-1)) // 10) of the m defined values."""
     n, d = cfg.n_individuals, cfg.n_data
     cols = np.empty((d, n), dtype=np.float32)
     dec = np.zeros((d, 9), dtype=np.float32)
-    for j in range(d):
+    streams = ss.spawn(d)
+
+    def column(j):
+        rng = np.random.default_rng(streams[j])
         col = rng.standard_normal(n, dtype=np.float32)
         col[rng.random(n, dtype=np.float32) < cfg.missing] = np.nan
         cols[j] = col
-        vals = np.sort(col[~np.isnan(col)])
+        vals = col[~np.isnan(col)]
         m = vals.shape[0]
         if m:
-            for k in range(1, 10):
-                dec[j, k - 1] = vals[(k * (m - 1)) // 10]
+            kth = [(k * (m - 1)) // 10 for k in range(1, 10)]
+            dec[j] = np.partition(vals, kth)[kth]
+
+    with _cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(column, range(d)))
     return cols, dec
 
 
@@ -343,9 +365,9 @@ def make_kb(cfg: KBConfig, workers: Optional[int] = None) -> KB:
     if workers is None:
         workers = max(1, min(16, os.cpu_count() or 1))
     s_con, s_role, s_data, s_ex, _s_hyp, _s_trace = _streams(cfg)
-    bits, parent, level = _gen_concepts(cfg, s_con)
+    bits, parent, level = _gen_concepts(cfg, s_con, workers)
     offsets, targets = _gen_roles(cfg, s_role, workers)
-    cols, dec = _gen_data(cfg, s_data)
+    cols, dec = _gen_data(cfg, s_data, workers)
     if cfg.examples == "planted":
         pos, neg = _gen_examples_planted(cfg, s_ex, bits, level)
     else:
@@ -505,7 +527,7 @@ def hyp_depth(h) -> int:
 
 def hyp_size(h) -> int:
     op = h[0]
-    if op in ("top", "bot", "atom", "dge", "dle"):
+    if op in ("top", "bot", "atom", "dge", "dle", "set"):
         return 1
     if op == "not":
         return 1 + hyp_size(h[1])
