@@ -22,14 +22,19 @@ sys.path.insert(0, ROOT)
 METRIC = "exact hypotheses/sec + achieved HBM GB/s; screened vs plain exhaustive"
 HBM_PEAK_GBS = 8000.0
 KIND_NAMES = {0: "k_threshold", 1: "k_region", 2: "k_role", 3: "k_tbuild", 4: "k_group", 5: "k_fill_rows"}
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2412_00802_amd", "csrc", "exec.hip")
+# the dominant kernel's source: its counters are void once these change
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2412_00802_amd", "csrc", f)
+                  for f in ("group_kernels.h", "hth_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2.json")
 COPY_BYTES = 256 << 20      # elementwise pass used to calibrate the byte counters
 
 
 def source_sha() -> str:
     import hashlib
-    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def recorded_traffic(kernel: str):
@@ -45,9 +50,12 @@ def recorded_traffic(kernel: str):
     return None if k is None else k["hbm_bytes_per_launch"]
 
 
-def summarize(kt_dir: str, fetch_dir: str, write_dir: str, command: str, out_md: str) -> None:
+def summarize(kt_dir: str, fetch_dir: str, write_dir: str, command: str, out_md: str,
+              sha: str = None) -> None:
     """Turn rocprofv3 outputs (kernel trace stats, FETCH_SIZE, WRITE_SIZE passes,
-    each run with --calibrate-copy) into the committed summary and traffic file."""
+    each run with --calibrate-copy) into the committed summary and traffic file.
+    sha: the kernel source hash of the profiled build (default: the current one)."""
+    sha = sha or source_sha()
     import csv
     import glob
 
@@ -77,7 +85,7 @@ def summarize(kt_dir: str, fetch_dir: str, write_dir: str, command: str, out_md:
              "Counter passes (one counter per run):", "",
              "    " + command.format(opts="--pmc FETCH_SIZE --output-format csv"),
              "    " + command.format(opts="--pmc WRITE_SIZE --output-format csv"), "",
-             f"Kernel source sha256[:16] of csrc/exec.hip: {source_sha()}", "",
+             f"Kernel source sha256[:16] of csrc/group_kernels.h + csrc/hth_internal.h: {sha}", "",
              "## Kernel time (kernel trace)", "",
              "| kernel | calls | avg us | total % |", "|---|---|---|---|"]
     for r in sorted(stats, key=lambda r: -float(r["Percentage"]))[:12]:
@@ -88,7 +96,7 @@ def summarize(kt_dir: str, fetch_dir: str, write_dir: str, command: str, out_md:
               f"{fetch[ck][1]:.0f} KiB and writes {write[ck][1]:.0f} KiB per dispatch: "
               f"{f_fac:.3f} fetched bytes and {w_fac:.3f} written bytes per counted KiB-byte.", "",
               "| kernel | fetch KiB | write KiB | HBM bytes per launch (scaled) |", "|---|---|---|---|"]
-    out = {"source_sha": source_sha(), "fetch_factor": f_fac, "write_factor": w_fac, "kernels": {}}
+    out = {"source_sha": sha, "fetch_factor": f_fac, "write_factor": w_fac, "kernels": {}}
     for k in sorted(fetch, key=lambda k: -fetch[k][1]):
         if k not in write:
             continue
@@ -145,18 +153,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c2")
     ap.add_argument("--plain", type=int, default=512, help="hypotheses timed one at a time (0 = skip)")
-    ap.add_argument("--cpu-sample", type=int, default=64)
+    ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of 256 MiB (byte-counter calibration)")
     ap.add_argument("--summarize", nargs=3, metavar=("KT_DIR", "FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--summary-out", default=os.path.join(ROOT, "profiles", "k_group_c2.md"))
+    ap.add_argument("--summary-sha", default=None, help="kernel source hash of the profiled build")
     ap.add_argument("--summary-command", default="rocprofv3 {opts} -d OUT -o run -- python3 bench.py "
                     "--steps 2 --warmup 1 --plain 0 --cpu-sample 0 --no-profile --calibrate-copy")
     args = ap.parse_args()
     if args.summarize:
-        summarize(*args.summarize, args.summary_command, args.summary_out)
+        summarize(*args.summarize, args.summary_command, args.summary_out, args.summary_sha)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is a "

@@ -67,7 +67,10 @@ enum {
   HTH_EXACTLY = 10, /* {x : cnt(x) == n} */
   HTH_DATA_GE = 11, /* {x : value of property arg defined and >= t} (Algorithms 9/10) */
   HTH_DATA_LE = 12, /* {x : value of property arg defined and <= t} */
-  HTH_NUM_OPS = 13
+  HTH_SET = 13,     /* arg = row of the set table registered with hth_kb_set_sets: an
+                       instance set the caller computed earlier (for example the
+                       unchanged subtrees of a refined parent), used as a leaf */
+  HTH_NUM_OPS = 14
 };
 
 /* One node of a hypothesis, 16 bytes.  Nodes are in postfix order: every child
@@ -109,7 +112,10 @@ typedef struct {
 } hth_kb_desc;
 
 /* Size of the derived buffer that hth_kb_create fills: per-role 32-bit row
- * offsets for both directions and the inverse-role CSR (transpose). */
+ * offsets for both directions, the inverse-role CSR (transpose), the
+ * non-empty words of each role direction, and each direction's objects (a
+ * bit row, per-word counts, and the object rank of every assertion's target,
+ * filled where the objects are at most half of the individuals). */
 hth_status hth_kb_derived_bytes(const hth_kb_desc* desc, size_t* bytes);
 
 /* Validate the knowledge base on the device and build the derived layouts into
@@ -124,6 +130,14 @@ hth_status hth_kb_create(const hth_kb_desc* desc, void* derived, size_t derived_
 /* Replace the example rows (device [stride_words] each, zero padding). */
 hth_status hth_kb_set_examples(hth_kb kb, const uint64_t* pos_bits, const uint64_t* neg_bits);
 
+/* Register the set table that HTH_SET leaves read: device uint64
+ * [n_rows][stride_words], zero padding bits, owned by the caller and read by
+ * later evaluations in stream order (rows may be rewritten between calls, for
+ * instance by hth_eval_batch_sets).  rows = NULL with n_rows = 0 removes it.
+ * Must not run concurrently with an evaluation on the same kb.  Errors:
+ * HTH_E_INVALID (NULL rows with n_rows > 0), HTH_E_RANGE (n_rows >= 2^24). */
+hth_status hth_kb_set_sets(hth_kb kb, const uint64_t* rows, uint32_t n_rows);
+
 /* Largest out-degree of role r in direction inv (0 = forward, 1 = inverse). */
 hth_status hth_kb_max_degree(hth_kb kb, uint32_t role, uint32_t inv, uint32_t* out);
 
@@ -135,13 +149,20 @@ hth_status hth_kb_max_degree(hth_kb kb, uint32_t role, uint32_t inv, uint32_t* o
  * xcd_local: 1 = keep each shared pass on one XCD (its L2 holds the pass's
  *   transposed child rows);
  * t_budget_mb: transposed child rows resident per launch (MiB);
- * unroll: assertions in flight per lane (8 or 16). */
+ * unroll: assertions in flight per lane (8 or 16);
+ * region_reg: 1 = boolean regions whose value stack fits six entries run with
+ *   the stack in registers and four words per lane (0 = the LDS-stack kernel);
+ * t_compact: 1 = shared passes over a role direction whose objects (targets)
+ *   are at most half of the individuals keep transposed child rows for those
+ *   objects only, indexed by object rank (0 = rows for every individual). */
 typedef struct {
   uint32_t group_min;
   uint32_t group_k;
   uint32_t xcd_local;
   uint32_t t_budget_mb;
   uint32_t unroll;
+  uint32_t region_reg;
+  uint32_t t_compact;
 } hth_tuning;
 hth_status hth_kb_get_tuning(hth_kb kb, hth_tuning* out);
 hth_status hth_kb_set_tuning(hth_kb kb, const hth_tuning* t);   /* HTH_E_RANGE if out of range */
@@ -176,6 +197,16 @@ hth_status hth_batch_workspace_bytes(hth_kb kb, const hth_node* nodes, const uin
 hth_status hth_eval_batch(hth_kb kb, const hth_node* nodes, const uint32_t* hyp_node_offsets,
                           uint32_t n_hyps, const uint32_t* children, uint32_t n_children,
                           void* ws, size_t ws_bytes, uint32_t* d_counts, void* stream);
+
+/* hth_eval_batch that also writes each hypothesis's instance set: d_sets is
+ * device uint64 [n_hyps][stride_words] (padding words and bits written as 0).
+ * Used to fill the set table with the subtrees of the hypotheses kept for the
+ * next refinement round.  d_sets must not overlap the rows this batch reads
+ * through HTH_SET leaves.  Same workspace as hth_eval_batch. */
+hth_status hth_eval_batch_sets(hth_kb kb, const hth_node* nodes, const uint32_t* hyp_node_offsets,
+                               uint32_t n_hyps, const uint32_t* children, uint32_t n_children,
+                               void* ws, size_t ws_bytes, uint64_t* d_sets, uint32_t* d_counts,
+                               void* stream);
 
 /* Measurement.  Between hth_profile_begin and hth_profile_end every kernel the
  * library launches for this kb is bracketed by two HIP events recorded on the

@@ -92,7 +92,11 @@ k_region(DevKB kb, const RegionTask* __restrict__ tasks, const uint32_t* __restr
   }
   if (!live) top = 0;
   else if (w == kb.W - 1) top &= kb.tail;
-  if (T.out_row != kNone && w < kb.S) out_ptr(kb, T.out_row)[w] = top;
+  if (T.out_row != kNone && w < kb.S) {
+    // kInstances: the caller's rows, one per covered hypothesis
+    uint64_t* o = T.out_row == kInstances ? kb.instances + (size_t)T.cover * kb.S : out_ptr(kb, T.out_row);
+    o[w] = top;
+  }
   if (T.cover != kNone) {
     uint32_t p = live ? (uint32_t)__popcll(top & kb.pos[w]) : 0u;
     uint32_t q = live ? (uint32_t)__popcll(top & kb.neg[w]) : 0u;
@@ -101,6 +105,95 @@ k_region(DevKB kb, const RegionTask* __restrict__ tasks, const uint32_t* __restr
     if ((tid & 63) == 0 && (p | q)) {
       if (p) atomicAdd(kb.counts + 2 * T.cover, p);
       if (q) atomicAdd(kb.counts + 2 * T.cover + 1, q);
+    }
+  }
+}
+
+// The same regions with the value stack in registers (a shift register of
+// depth D, enough for most programs) and R words per lane, so that each leaf
+// puts R independent loads in flight per lane and no LDS limits occupancy.
+// Lane t handles words tile*256R + r*256 + t (coalesced per r).  Coverage is
+// reduced over the block and added with one atomic pair per block.
+constexpr int kRegWords = 4;     // R
+constexpr int kRegDepth = 6;     // D: most stack entries a program may need
+template <int D, int R>
+__global__ void __launch_bounds__(256)
+k_region_reg(DevKB kb, const RegionTask* __restrict__ tasks, const uint32_t* __restrict__ code,
+             uint32_t n_tasks) {
+  __shared__ uint32_t s_pq[2][4];
+  const uint32_t tile = blockIdx.x / n_tasks, task = blockIdx.x % n_tasks;
+  const RegionTask T = tasks[task];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t w0 = tile * (256 * R) + tid;
+  uint64_t top[R], st[D > 1 ? D - 1 : 1][R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) top[r] = 0;
+  for (uint32_t pc = 0; pc < T.code_len; ++pc) {
+    const uint32_t ins = code[T.code_off + pc];
+    const uint32_t op = ins & 15u, arg = ins >> 5;
+    if (op <= RP_BOT) {
+      if (pc) {                                   // push: shift the stack down
+#pragma unroll
+        for (int i = D - 2; i > 0; --i)
+#pragma unroll
+          for (int r = 0; r < R; ++r) st[i][r] = st[i - 1][r];
+#pragma unroll
+        for (int r = 0; r < R; ++r) st[0][r] = top[r];
+      }
+      if (op == RP_LEAF) {
+        const uint64_t* row = row_ptr(kb, arg);
+        const uint64_t negm = (ins & 16u) ? ~0ull : 0ull;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const uint32_t w = w0 + r * 256;
+          top[r] = w < kb.W ? (row[w] ^ negm) : 0ull;
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) top[r] = op == RP_TOP ? ~0ull : 0ull;
+      }
+    } else if (op == RP_NOT) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) top[r] = ~top[r];
+    } else {                                      // pop b, top = top op b
+      const bool conj = op == RP_AND;
+#pragma unroll
+      for (int r = 0; r < R; ++r) top[r] = conj ? (top[r] & st[0][r]) : (top[r] | st[0][r]);
+#pragma unroll
+      for (int i = 0; i + 1 < D - 1; ++i)
+#pragma unroll
+        for (int r = 0; r < R; ++r) st[i][r] = st[i + 1][r];
+    }
+  }
+  uint32_t p = 0, q = 0;
+  uint64_t* out = T.out_row == kNone ? nullptr
+                  : T.out_row == kInstances ? kb.instances + (size_t)T.cover * kb.S
+                                            : out_ptr(kb, T.out_row);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t w = w0 + r * 256;
+    uint64_t v = top[r];
+    if (w >= kb.W) v = 0;
+    else if (w == kb.W - 1) v &= kb.tail;
+    if (out && w < kb.S) out[w] = v;
+    if (T.cover != kNone && w < kb.W) {
+      p += (uint32_t)__popcll(v & kb.pos[w]);
+      q += (uint32_t)__popcll(v & kb.neg[w]);
+    }
+  }
+  if (T.cover != kNone) {
+    p = wave_sum(p);
+    q = wave_sum(q);
+    if ((tid & 63) == 0) {
+      s_pq[0][tid >> 6] = p;
+      s_pq[1][tid >> 6] = q;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const uint32_t P = s_pq[0][0] + s_pq[0][1] + s_pq[0][2] + s_pq[0][3];
+      const uint32_t Q = s_pq[1][0] + s_pq[1][1] + s_pq[1][2] + s_pq[1][3];
+      if (P) atomicAdd(kb.counts + 2 * T.cover, P);
+      if (Q) atomicAdd(kb.counts + 2 * T.cover + 1, Q);
     }
   }
 }
@@ -172,92 +265,6 @@ k_role(DevKB kb, const RoleTask* __restrict__ tasks, uint32_t bpt) {
 }
 
 
-// ---------------------------------------------------------------------------
-// shared role passes: up to 64 role nodes of one (role, direction, level)
-// ---------------------------------------------------------------------------
-// 64 x 64 bit-matrix transpose in registers: on entry a[j] bit b = M[j][b], on
-// exit a[b] bit j = M[j][b].  Recursive exchange of off-diagonal blocks.
-__device__ __forceinline__ void transpose64(uint64_t (&a)[64]) {
-  uint64_t m = 0x00000000FFFFFFFFull;
-#pragma unroll
-  for (int j = 32; j != 0; j >>= 1, m ^= (m << j)) {
-#pragma unroll
-    for (int k = 0; k < 64; k = ((k | j) + 1) & ~j) {
-      const uint64_t t = ((a[k] >> j) ^ a[k | j]) & m;
-      a[k | j] ^= t;
-      a[k] ^= t << j;
-    }
-  }
-}
-
-// T_g[y] bit j = bit(child_j, y) ^ neg_j for the groups of one launch; one lane
-// per 64-individual word, transposed in registers.  T rows are TW wide
-// (8 * sizeof(TW) >= every group's k).
-template <typename TW>
-__global__ void __launch_bounds__(256)
-k_tbuild(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __restrict__ members,
-         TW* __restrict__ tarea, uint64_t t_stride, uint32_t tiles) {
-  constexpr int KB = 8 * sizeof(TW);
-  const uint32_t g = blockIdx.x / tiles, tile = blockIdx.x % tiles;
-  const GroupTask G = groups[g];
-  const uint32_t w = tile * 256 + threadIdx.x;
-  if (w >= kb.W) return;
-  uint64_t a[64];
-#pragma unroll
-  for (int j = 0; j < 64; ++j) {
-    uint64_t v = 0;
-    if (j < KB && (uint32_t)j < G.k) {
-      const GroupMember M = members[G.first + j];
-      v = row_ptr(kb, M.child_row)[w] ^ (M.neg ? ~0ull : 0ull);
-    }
-    a[j] = v;
-  }
-  transpose64(a);
-  TW* T = tarea + (size_t)g * t_stride + (size_t)w * 64;
-#pragma unroll
-  for (int b = 0; b < 64; ++b) T[b] = (TW)a[b];
-}
-
-// Saturating per-member counters for all members of a group at once, one bit
-// per member in each plane: count = c2 c1 c0 (0..7) unless ov (count >= 8).
-template <typename TW>
-struct Planes {
-  TW c0, c1, c2, ov;
-};
-
-template <typename TW>
-__device__ __forceinline__ void planes_inc(Planes<TW>& p, TW v) {   // +1 where v has a bit
-  const TW k0 = p.c0 & v;
-  p.c0 ^= v;
-  const TW k1 = p.c1 & k0;
-  p.c1 ^= k0;
-  const TW k2 = p.c2 & k1;
-  p.c2 ^= k1;
-  p.ov |= k2;
-}
-
-template <typename TW>
-__device__ __forceinline__ void planes_add(Planes<TW>& a, const Planes<TW>& b) {
-  const TW s0 = a.c0 ^ b.c0, k0 = a.c0 & b.c0;
-  const TW t1 = a.c1 ^ b.c1, s1 = t1 ^ k0, k1 = (a.c1 & b.c1) | (k0 & t1);
-  const TW t2 = a.c2 ^ b.c2, s2 = t2 ^ k1, k2 = (a.c2 & b.c2) | (k1 & t2);
-  a.c0 = s0;
-  a.c1 = s1;
-  a.c2 = s2;
-  a.ov = a.ov | b.ov | k2;
-}
-
-template <typename TW>
-__device__ __forceinline__ TW shfl_up_w(TW v, int d) {
-  if constexpr (sizeof(TW) == 8) return (TW)__shfl_up((unsigned long long)v, d, 64);
-  else return (TW)__shfl_up((unsigned int)v, d, 64);
-}
-
-template <typename TW>
-__device__ __forceinline__ Planes<TW> planes_shfl_up(const Planes<TW>& p, int d) {
-  return Planes<TW>{shfl_up_w(p.c0, d), shfl_up_w(p.c1, d), shfl_up_w(p.c2, d), shfl_up_w(p.ov, d)};
-}
-
 // Zero-count results for the words of a role direction without assertions.
 __global__ void __launch_bounds__(256)
 k_fill_rows(DevKB kb, const FillTask* __restrict__ tasks, uint32_t tiles) {
@@ -270,196 +277,11 @@ k_fill_rows(DevKB kb, const FillTask* __restrict__ tasks, uint32_t tiles) {
   out_ptr(kb, F.out_row)[w] = v;
 }
 
-// 64 x 64 bit transpose across the lanes of a wave: on entry lane l holds row
-// l (bit j = M[l][j]); on exit lane l holds column l (bit j = M[j][l]).  Six
-// butterfly stages, each swapping the off-diagonal blocks with the partner lane.
-__device__ __forceinline__ uint64_t wave_transpose64(uint64_t x, int lane) {
-  uint64_t m = 0x00000000FFFFFFFFull;
-#pragma unroll
-  for (int d = 32; d != 0; d >>= 1, m ^= (m << d)) {
-    const uint64_t y = __shfl_xor((unsigned long long)x, d, 64);
-    x = (lane & d) ? (((y >> d) & m) | (x & ~m)) : ((x & m) | ((y << d) & ~m));
-  }
-  return x;
-}
+}  // namespace hth
 
-// One wave per 64 subjects (one word of every member's output row), all members
-// of the group at once.  The word's assertions are cut into 64 contiguous
-// slices of ceil(E_w / 64), one per lane (balanced whatever the degrees); a lane
-// walks its slice, fetches each object's T row (one load serves every member)
-// and adds it into bit-sliced counters, closing a row's counters when the row
-// ends.  Rows that straddle slices leave a tail partial in each lane they cross;
-// one segmented scan over the lanes adds them up for the lane holding the row's
-// last assertion.  Finally lane x evaluates every member's predicate for
-// subject x from the acceptance masks and the result is transposed by ballots.
-template <typename TW, int U, bool NT>   // U: assertions in flight per lane;
-                                          // NT: stream the CSR past the caches
-__global__ void __launch_bounds__(256)
-k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __restrict__ members,
-        const TW* __restrict__ tarea, uint64_t t_stride, uint32_t bpg, uint32_t n_groups,
-        uint32_t xcd_local) {
-  constexpr uint32_t kStage = 1024;   // assertions of a word staged in LDS
-  __shared__ uint32_t s_ro[4][65];
-  __shared__ TW s_fin[4][4][64];
-  __shared__ int32_t s_tg[4][kStage];
-  uint32_t g, b;
-  if (xcd_local) {
-    // workgroups are dealt to the 8 XCDs round robin: keep every block of a
-    // group on one XCD so that its L2 serves that group's T rows
-    const uint32_t x = blockIdx.x & 7, j = blockIdx.x >> 3;
-    g = x + 8 * (j / bpg);
-    b = j % bpg;
-    if (g >= n_groups) return;
-  } else {
-    g = blockIdx.x / bpg;
-    b = blockIdx.x % bpg;
-  }
-  const GroupTask* G = groups + g;
-  const uint32_t k = G->k;
-  const TW* T = tarea + (size_t)g * t_stride;
-  const size_t roff = (size_t)G->role * (kb.N + 1);
-  const uint32_t* off = (G->inv ? kb.inv_off : kb.fwd_off) + roff;
-  const int32_t* tg = (G->inv ? kb.inv_tg : kb.fwd_tg) + kb.role_base[G->role];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  uint32_t* ro = s_ro[wv];
-  TW(*fin)[64] = s_fin[wv];
-  TW acc[kGroupMaxCount + 1];
-#pragma unroll
-  for (int v = 0; v <= (int)kGroupMaxCount; ++v) acc[v] = (TW)G->acc[v];
-  const uint32_t nw = blockDim.x >> 6;
-  const uint32_t wstep = bpg * nw;
-  const uint32_t* words = kb.words + (size_t)(2 * G->role + G->inv) * kb.W;
-  const uint32_t n_words = G->n_words;
-  uint32_t i = b * nw + wv;
-  uint32_t olo_n = 0, ohi_n = 0;     // row offsets of the wave's next word, fetched ahead
-  if (i < n_words) {
-    const uint32_t xn = words[i] * 64 + lane;
-    olo_n = off[xn < kb.N ? xn : kb.N];
-    ohi_n = xn < kb.N ? off[xn + 1] : olo_n;
-  }
-  for (; i < n_words; i += wstep) {
-    const uint32_t w = words[i];
-    const uint32_t x = w * 64 + lane;
-    const bool in = x < kb.N;
-    const uint32_t olo = olo_n, ohi = ohi_n;
-    if (i + wstep < n_words) {
-      const uint32_t xn = words[i + wstep] * 64 + lane;
-      olo_n = off[xn < kb.N ? xn : kb.N];
-      ohi_n = xn < kb.N ? off[xn + 1] : olo_n;
-    }
-    ro[lane] = olo;
-    if (lane == 63) ro[64] = ohi;
-    fin[0][lane] = fin[1][lane] = fin[2][lane] = fin[3][lane] = 0;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const uint32_t E0 = (uint32_t)__shfl((int)olo, 0, 64);
-    const uint32_t E1 = (uint32_t)__shfl((int)ohi, 63, 64);
-    const uint32_t S = (E1 - E0 + 63) >> 6;
-    const uint32_t s = E0 + lane * S;
-    const uint32_t se = min(s + S, E1);
-    // the word's targets, loaded coalesced into LDS when they fit; lanes then
-    // read their contiguous slices from there
-    int32_t* stg = s_tg[wv];
-    const bool staged = E1 - E0 <= kStage;
-    if (staged) {
-#pragma unroll 4
-      for (uint32_t i = lane; i < E1 - E0; i += 64) stg[i] = tg[E0 + i];
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-    Planes<TW> cur{0, 0, 0, 0}, hp{0, 0, 0, 0}, tp{0, 0, 0, 0};
-    int hp_row = -1, key = -2 - lane;
-    if (s < se) {
-      int r = 0;
-#pragma unroll
-      for (int step = 32; step; step >>= 1)
-        if (r + step <= 63 && ro[r + step] <= s) r += step;
-      bool head = ro[r] < s;
-      uint32_t rend = ro[r + 1];
-      for (uint32_t e0 = s; e0 < se; e0 += U) {
-        int32_t t[U];
-        TW v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-          t[u] = (e0 + u < se)
-                     ? (staged ? stg[e0 + u - E0]
-                               : (NT ? __builtin_nontemporal_load(tg + e0 + u) : tg[e0 + u]))
-                     : 0;
-#pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = (e0 + u < se) ? T[(uint32_t)t[u]] : (TW)0;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const uint32_t e = e0 + u;
-          if (e < se) {
-            while (e >= rend) {          // row r is complete in this slice
-              if (head) {
-                hp = cur;
-                hp_row = r;
-              } else {
-                fin[0][r] = cur.c0;
-                fin[1][r] = cur.c1;
-                fin[2][r] = cur.c2;
-                fin[3][r] = cur.ov;
-              }
-              cur = Planes<TW>{0, 0, 0, 0};
-              head = false;
-              ++r;
-              rend = ro[r + 1];
-            }
-            planes_inc(cur, v[u]);
-          }
-        }
-      }
-      if (rend > se) {                    // the row continues past this slice
-        tp = cur;
-        key = r;
-      } else if (head) {
-        hp = cur;
-        hp_row = r;
-      } else {
-        fin[0][r] = cur.c0;
-        fin[1][r] = cur.c1;
-        fin[2][r] = cur.c2;
-        fin[3][r] = cur.ov;
-      }
-    }
-    // segmented inclusive scan of the tail partials, keyed by row; stops once no
-    // segment is longer than the distance covered (most rows cross one boundary)
-    for (int d = 1; d < 64; d <<= 1) {
-      const int pk = __shfl_up(key, d, 64);
-      if (!__ballot(lane >= d && pk == key)) break;
-      const Planes<TW> pp = planes_shfl_up(tp, d);
-      if (lane >= d && pk == key) planes_add(tp, pp);
-    }
-    {
-      const int pk = __shfl_up(key, 1, 64);
-      const Planes<TW> pp = planes_shfl_up(tp, 1);
-      if (hp_row >= 0) {
-        if (lane > 0 && pk == hp_row) planes_add(hp, pp);
-        fin[0][hp_row] = hp.c0;
-        fin[1][hp_row] = hp.c1;
-        fin[2][hp_row] = hp.c2;
-        fin[3][hp_row] = hp.ov;
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // predicate of every member for subject x
-    const TW c0 = fin[0][lane], c1 = fin[1][lane], c2 = fin[2][lane], ov = fin[3][lane];
-    const TW n0 = ~c0, n1 = ~c1, n2 = ~c2;
-    TW res = (n2 & n1 & n0 & acc[0]) | (n2 & n1 & c0 & acc[1]) | (n2 & c1 & n0 & acc[2]) |
-             (n2 & c1 & c0 & acc[3]) | (c2 & n1 & n0 & acc[4]) | (c2 & n1 & c0 & acc[5]) |
-             (c2 & c1 & n0 & acc[6]) | (c2 & c1 & c0 & acc[7]);
-    res = (res & ~ov) | (ov & acc[8]);
-    if (!in) res = 0;
-    const uint64_t mine = wave_transpose64((uint64_t)res, lane);
-    if ((uint32_t)lane < k) out_ptr(kb, members[G->first + lane].out_row)[w] = mine;
-    __builtin_amdgcn_wave_barrier();
-  }
-}
+#include "group_kernels.h"
+
+namespace hth {
 
 // ---------------------------------------------------------------------------
 // executor
@@ -469,6 +291,41 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
 inline uint32_t t_width_bytes(uint32_t k) { return k <= 8 ? 1 : k <= 16 ? 2 : k <= 32 ? 4 : 8; }
 inline size_t t_area_bytes(const hth_kb_s& kb) {
   return std::max<size_t>(kb.tune.t_budget, align_up(kb.N, 64) * 8);
+}
+// T rows of a group: the objects of its direction (compact) or all individuals
+inline uint64_t t_rows(const hth_kb_s& kb, const GroupTask& g) {
+  return align_up(g.compact ? kb.n_obj[2 * g.role + g.inv] : kb.N, 64);
+}
+
+// Consecutive groups of a level share a launch while their T rows, at the
+// widest T width among them, fit the budget; sets each group's T offset.
+struct GroupChunk {
+  size_t first;
+  uint32_t n, wb;
+};
+std::vector<GroupChunk> chunk_groups(const hth_kb_s& kb, std::vector<GroupTask>& gs) {
+  std::vector<GroupChunk> out;
+  size_t i = 0;
+  while (i < gs.size()) {
+    uint32_t wb = t_width_bytes(gs[i].k);
+    uint64_t rows = t_rows(kb, gs[i]);
+    size_t j = i + 1;
+    while (j < gs.size()) {
+      const uint32_t nwb = std::max(wb, t_width_bytes(gs[j].k));
+      if ((rows + t_rows(kb, gs[j])) * nwb > kb.tune.t_budget) break;
+      rows += t_rows(kb, gs[j]);
+      wb = nwb;
+      ++j;
+    }
+    uint64_t off = 0;
+    for (size_t q = i; q < j; ++q) {
+      gs[q].t_off = off;
+      off += t_rows(kb, gs[q]);
+    }
+    out.push_back({i, (uint32_t)(j - i), wb});
+    i = j;
+  }
+  return out;
 }
 
 namespace {
@@ -506,9 +363,14 @@ DevKB dev_view(const hth_kb_s& kb) {
   d.inv_tg = kb.inv_tg;
   d.role_base = kb.role_base_dev;
   d.words = kb.words;
+  d.objmask = kb.objmask;
+  d.objbase = kb.objbase;
+  d.ctg_fwd = kb.ctg_fwd;
+  d.ctg_inv = kb.ctg_inv;
   d.pos = kb.pos;
   d.neg = kb.neg;
   d.n_concepts = kb.d.n_concepts;
+  d.n_fixed = kb.d.n_concepts;
   d.N = kb.N;
   d.W = kb.W;
   d.S = kb.S;
@@ -580,6 +442,24 @@ hth_status launch_regions(Launcher& L, const DevKB& d, const RegionTask* tasks, 
   double bytes = 0;
   if (L.kb.prof)
     for (const RegionTask& t : host) bytes += region_bytes(L.kb, t, hcode);
+  // the register kernel when every program's stack fits its shift register
+  int depth = 0;
+  for (const RegionTask& t : host) {
+    int sp = 0;
+    for (uint32_t i = 0; i < t.code_len; ++i) {
+      const uint32_t op = hcode[t.code_off + i] & 15u;
+      if (op <= RP_BOT) sp += i ? 1 : 0;
+      else if (op != RP_NOT) --sp;
+      depth = std::max(depth, sp + 1);
+    }
+  }
+  if (depth <= kRegDepth && L.kb.tune.region_reg) {
+    const uint32_t tiles = (d.S + 256 * kRegWords - 1) / (256 * kRegWords);
+    return L.run(HTH_K_REGION, bytes, [&] {
+      hipLaunchKernelGGL((k_region_reg<kRegDepth, kRegWords>), dim3(tiles * n), dim3(256), 0, L.st, d,
+                         tasks, code, n);
+    });
+  }
   const uint32_t tiles = (d.S + kRegionThreads - 1) / kRegionThreads;
   return L.run(HTH_K_REGION, bytes, [&] {
     hipLaunchKernelGGL(k_region, dim3(tiles * n), dim3(kRegionThreads), 0, L.st, d, tasks, code, n);
@@ -613,18 +493,18 @@ hth_status launch_group_chunk(Launcher& L, const DevKB& d, const GroupTask* grou
                               const GroupMember* members, const std::vector<GroupTask>& host,
                               size_t g0, uint32_t n, void* tarea) {
   const hth_kb_s& kb = L.kb;
-  const uint64_t t_stride = align_up(kb.N, 64);
   double tb = 0, gb = 0;
   for (uint32_t i = 0; i < n; ++i) {
     const GroupTask& G = host[g0 + i];
-    tb += (double)G.k * kb.W * 8 + (double)t_stride * sizeof(TW);     // child rows in, T out
-    gb += csr_bytes(kb, G.role, G.inv) + (double)t_stride * sizeof(TW) + (double)G.k * kb.W * 8;
+    const double tbytes = (double)t_rows(kb, G) * sizeof(TW);
+    tb += (double)G.k * kb.W * 8 + tbytes;     // child rows in, T out
+    gb += csr_bytes(kb, G.role, G.inv) + tbytes + (double)G.k * kb.W * 8;
   }
   TW* T = static_cast<TW*>(tarea);
   const uint32_t tiles = (kb.W + 255) / 256;
   hth_status s = L.run(HTH_K_TBUILD, tb, [&] {
     hipLaunchKernelGGL(k_tbuild<TW>, dim3(tiles * n), dim3(256), 0, L.st, d, groups + g0, members,
-                       T, t_stride, tiles);
+                       T, tiles);
   });
   if (s) return s;
   const uint32_t xcd = kb.tune.xcd_local && n >= 8;
@@ -642,45 +522,33 @@ hth_status launch_group_chunk(Launcher& L, const DevKB& d, const GroupTask* grou
     if (kb.tune.group_unroll >= 16) {
       if (kb.tune.nontemporal)
         hipLaunchKernelGGL((k_group<TW, 16, true>), grid, block, 0, L.st, d, groups + g0, members, T,
-                           t_stride, bpg, n, xcd);
+                           bpg, n, xcd);
       else
         hipLaunchKernelGGL((k_group<TW, 16, false>), grid, block, 0, L.st, d, groups + g0, members, T,
-                           t_stride, bpg, n, xcd);
+                           bpg, n, xcd);
     } else {
       if (kb.tune.nontemporal)
         hipLaunchKernelGGL((k_group<TW, 8, true>), grid, block, 0, L.st, d, groups + g0, members, T,
-                           t_stride, bpg, n, xcd);
+                           bpg, n, xcd);
       else
         hipLaunchKernelGGL((k_group<TW, 8, false>), grid, block, 0, L.st, d, groups + g0, members, T,
-                           t_stride, bpg, n, xcd);
+                           bpg, n, xcd);
     }
   });
 }
 
 hth_status launch_groups(Launcher& L, const DevKB& d, const GroupTask* groups,
                          const GroupMember* members, const std::vector<GroupTask>& host,
-                         void* tarea) {
-  const size_t t_stride = align_up(L.kb.N, 64);
-  size_t i = 0;
-  while (i < host.size()) {
-    uint32_t wb = 1;
-    size_t j = i;
-    while (j < host.size()) {
-      const uint32_t nwb = std::max(wb, t_width_bytes(host[j].k));
-      if (j > i && (j - i + 1) * t_stride * nwb > L.kb.tune.t_budget) break;
-      wb = nwb;
-      ++j;
-    }
-    const uint32_t n = (uint32_t)(j - i);
+                         const std::vector<GroupChunk>& chunks, void* tarea) {
+  for (const GroupChunk& c : chunks) {
     hth_status s;
-    switch (wb) {
-      case 1: s = launch_group_chunk<uint8_t>(L, d, groups, members, host, i, n, tarea); break;
-      case 2: s = launch_group_chunk<uint16_t>(L, d, groups, members, host, i, n, tarea); break;
-      case 4: s = launch_group_chunk<uint32_t>(L, d, groups, members, host, i, n, tarea); break;
-      default: s = launch_group_chunk<uint64_t>(L, d, groups, members, host, i, n, tarea); break;
+    switch (c.wb) {
+      case 1: s = launch_group_chunk<uint8_t>(L, d, groups, members, host, c.first, c.n, tarea); break;
+      case 2: s = launch_group_chunk<uint16_t>(L, d, groups, members, host, c.first, c.n, tarea); break;
+      case 4: s = launch_group_chunk<uint32_t>(L, d, groups, members, host, c.first, c.n, tarea); break;
+      default: s = launch_group_chunk<uint64_t>(L, d, groups, members, host, c.first, c.n, tarea); break;
     }
     if (s) return s;
-    i = j;
   }
   return HTH_OK;
 }
@@ -725,6 +593,7 @@ hth_status run_plan(hth_kb_s& kb, const Plan& P, char* ws, size_t ws_bytes, uint
   std::vector<LevelAt> at(P.levels.size());
   std::vector<std::vector<RoleTask>> lv_roles(P.levels.size());
   std::vector<std::vector<GroupTask>> lv_groups(P.levels.size());
+  std::vector<std::vector<GroupChunk>> lv_chunks(P.levels.size());
   for (size_t L = 0; L < P.levels.size(); ++L) {
     const PlanLevel& PL = P.levels[L];
     at[L] = {regions.size(), roles.size(), groups.size(), fills.size(), 0, 0, 0};
@@ -742,9 +611,11 @@ hth_status run_plan(hth_kb_s& kb, const Plan& P, char* ws, size_t ws_bytes, uint
         for (uint32_t j = 0; j < g.k; ++j)
           fills.push_back(FillTask{PL.members[g.first + j].out_row, (uint32_t)((g.acc[0] >> j) & 1)});
       g.first += mbase;
-      groups.push_back(g);
+      g.compact = kb.tune.t_compact && 2ull * kb.n_obj[2 * g.role + g.inv] <= kb.N;
       lv_groups[L].push_back(g);
     }
+    lv_chunks[L] = chunk_groups(kb, lv_groups[L]);
+    groups.insert(groups.end(), lv_groups[L].begin(), lv_groups[L].end());
     members.insert(members.end(), PL.members.begin(), PL.members.end());
     at[L].nrole = roles.size() - at[L].role;
     at[L].ngroup = groups.size() - at[L].group;
@@ -772,11 +643,32 @@ hth_status run_plan(hth_kb_s& kb, const Plan& P, char* ws, size_t ws_bytes, uint
   if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(HTH_E_INVALID, "workspace must be 256-byte aligned");
 
   DevKB d = dev_view(kb);
+  d.sets = P.sets;
+  d.n_fixed = kb.d.n_concepts + P.n_sets;
   d.slots = reinterpret_cast<uint64_t*>(ws + tables);
   d.counts = counts;
   d.instances = instances;
   void* tarea = ws + tables + (size_t)P.n_slots * slot_bytes;
-  HTH_HIP(hipMemcpyAsync(ws, blob.bytes.data(), blob.bytes.size(), hipMemcpyHostToDevice, st));
+  {
+    hth_kb_s::Staging& sg = kb.stage[kb.stage_next++ % 4];
+    if (sg.pending) HTH_HIP(hipEventSynchronize(sg.done));
+    sg.pending = false;
+    const size_t nb = blob.bytes.size();
+    if (sg.cap < nb) {
+      if (sg.host) HTH_HIP(hipHostFree(sg.host));
+      sg.host = nullptr;
+      sg.cap = 0;
+      size_t cap = 64 << 10;
+      while (cap < nb) cap <<= 1;
+      HTH_HIP(hipHostMalloc(&sg.host, cap, hipHostMallocDefault));
+      sg.cap = cap;
+    }
+    if (!sg.done) HTH_HIP(hipEventCreateWithFlags(&sg.done, hipEventDisableTiming));
+    std::memcpy(sg.host, blob.bytes.data(), nb);
+    HTH_HIP(hipMemcpyAsync(ws, sg.host, nb, hipMemcpyHostToDevice, st));
+    HTH_HIP(hipEventRecord(sg.done, st));
+    sg.pending = true;
+  }
   HTH_HIP(hipMemsetAsync(counts, 0, (size_t)n_hyps * 8, st));
   const ThrTask* thr = reinterpret_cast<const ThrTask*>(ws + o_thr);
   const RegionTask* reg = reinterpret_cast<const RegionTask*>(ws + o_reg);
@@ -809,7 +701,7 @@ hth_status run_plan(hth_kb_s& kb, const Plan& P, char* ws, size_t ws_bytes, uint
     }
     s = launch_roles(Lc, d, rol + at[L].role, lv_roles[L]);
     if (s) return s;
-    s = launch_groups(Lc, d, grp + at[L].group, mem, lv_groups[L], tarea);
+    s = launch_groups(Lc, d, grp + at[L].group, mem, lv_groups[L], lv_chunks[L], tarea);
     if (s) return s;
   }
   return launch_regions(Lc, d, reg + root_at, code, P.roots, P.code);
@@ -846,9 +738,10 @@ extern "C" hth_status hth_eval_one(hth_kb kb, const hth_node* nodes, uint32_t n_
                   static_cast<hipStream_t>(stream));
 }
 
-extern "C" hth_status hth_eval_batch(hth_kb kb, const hth_node* nodes, const uint32_t* hyp_node_offsets,
-                                     uint32_t n_hyps, const uint32_t* children, uint32_t n_children,
-                                     void* ws, size_t ws_bytes, uint32_t* d_counts, void* stream) {
+namespace {
+hth_status eval_batch_impl(hth_kb kb, const hth_node* nodes, const uint32_t* hyp_node_offsets,
+                           uint32_t n_hyps, const uint32_t* children, uint32_t n_children, void* ws,
+                           size_t ws_bytes, uint64_t* d_sets, uint32_t* d_counts, void* stream) {
   if (!kb || !nodes || !hyp_node_offsets || !ws || !d_counts)
     return fail(HTH_E_INVALID, "NULL argument");
   if (n_children && !children) return fail(HTH_E_INVALID, "children is NULL");
@@ -857,12 +750,31 @@ extern "C" hth_status hth_eval_batch(hth_kb kb, const hth_node* nodes, const uin
   PlanOptions opt;
   opt.group_min = kb->tune.group_min ? kb->tune.group_min : 0xFFFFFFFFu;
   opt.group_k = kb->tune.group_k;
+  opt.instances = d_sets != nullptr;
   Plan P;
   hth_status s = compile_plan(*kb, nodes, hyp_node_offsets, n_hyps, children, n_children, opt, P);
   if (s) return s;
   std::lock_guard<std::mutex> g(kb->mu);
-  return run_plan(*kb, P, static_cast<char*>(ws), ws_bytes, d_counts, n_hyps, nullptr,
+  return run_plan(*kb, P, static_cast<char*>(ws), ws_bytes, d_counts, n_hyps, d_sets,
                   static_cast<hipStream_t>(stream));
+}
+}  // namespace
+
+extern "C" hth_status hth_eval_batch(hth_kb kb, const hth_node* nodes, const uint32_t* hyp_node_offsets,
+                                     uint32_t n_hyps, const uint32_t* children, uint32_t n_children,
+                                     void* ws, size_t ws_bytes, uint32_t* d_counts, void* stream) {
+  return eval_batch_impl(kb, nodes, hyp_node_offsets, n_hyps, children, n_children, ws, ws_bytes,
+                         nullptr, d_counts, stream);
+}
+
+extern "C" hth_status hth_eval_batch_sets(hth_kb kb, const hth_node* nodes,
+                                          const uint32_t* hyp_node_offsets, uint32_t n_hyps,
+                                          const uint32_t* children, uint32_t n_children, void* ws,
+                                          size_t ws_bytes, uint64_t* d_sets, uint32_t* d_counts,
+                                          void* stream) {
+  if (!d_sets) return fail(HTH_E_INVALID, "d_sets is NULL");
+  return eval_batch_impl(kb, nodes, hyp_node_offsets, n_hyps, children, n_children, ws, ws_bytes,
+                         d_sets, d_counts, stream);
 }
 
 extern "C" hth_status hth_batch_workspace_bytes(hth_kb kb, const hth_node* nodes,

@@ -22,7 +22,7 @@ constexpr int kMaxK = 64;             // role nodes sharing one CSR pass (bits o
 //   bits 0-3 opcode, bit 4 negate (LEAF only), bits 5-31 argument
 // ---------------------------------------------------------------------------
 enum : uint32_t {
-  RP_LEAF = 0,   // push row `arg` (concept id, or n_concepts + slot)
+  RP_LEAF = 0,   // push row `arg` (see row_ptr)
   RP_TOP = 1,
   RP_BOT = 2,
   RP_NOT = 3,    // complement the top of the stack
@@ -84,7 +84,8 @@ struct GroupTask {
   uint32_t first;      // index of the group's first member in the member table
   uint64_t acc[9];
   uint32_t n_words;    // non-empty words of (role, inv), set at launch
-  uint32_t pad;
+  uint32_t compact;    // 1: T holds the direction's objects only, indexed by object rank
+  uint64_t t_off;      // first T row of the group in the T area (in T rows)
 };
 constexpr uint32_t kGroupMaxCount = 8;
 struct GroupMember {
@@ -98,6 +99,7 @@ struct GroupMember {
 // Device view of the knowledge base and of one call's buffers (by value).
 struct DevKB {
   const uint64_t* concepts;   // [C][S]
+  const uint64_t* sets;       // [n_sets][S] caller's set table (HTH_SET leaves)
   uint64_t* slots;            // [n_slots][S] (workspace)
   const float* data;          // [D][N]
   const uint32_t* fwd_off;    // [R][N+1], relative to the role's first assertion
@@ -106,22 +108,29 @@ struct DevKB {
   const int32_t* inv_tg;      // [E]
   const uint64_t* role_base;  // [R] first assertion of each role (both directions)
   const uint32_t* words;      // [R][2][W] non-empty words (role r, direction d at row 2r + d)
+  const uint64_t* objmask;    // [R][2][W] objects of each role direction
+  const uint32_t* objbase;    // [R][2][W+1] objects before each word
+  const int32_t* ctg_fwd;     // [E] object ranks of the forward targets
+  const int32_t* ctg_inv;     // [E] object ranks of the inverse targets
   const uint64_t* pos;        // [S]
   const uint64_t* neg;        // [S]
   uint32_t* counts;           // [n_hyps][2]
   uint64_t* instances;        // [S] or null
   uint32_t n_concepts;
+  uint32_t n_fixed;           // n_concepts + n_sets: first workspace slot row
   uint32_t N, W, S;
   uint64_t tail;              // valid-bit mask of word W-1
 };
 
+// Row ids: [0, C) concepts, [C, C + n_sets) the set table, then workspace slots.
 __device__ __forceinline__ const uint64_t* row_ptr(const DevKB& kb, uint32_t id) {
-  return id < kb.n_concepts ? kb.concepts + (size_t)id * kb.S
-                            : kb.slots + (size_t)(id - kb.n_concepts) * kb.S;
+  if (id < kb.n_concepts) return kb.concepts + (size_t)id * kb.S;
+  if (id < kb.n_fixed) return kb.sets + (size_t)(id - kb.n_concepts) * kb.S;
+  return kb.slots + (size_t)(id - kb.n_fixed) * kb.S;
 }
 __device__ __forceinline__ uint64_t* out_ptr(const DevKB& kb, uint32_t id) {
   if (id == kInstances) return kb.instances;
-  return kb.slots + (size_t)(id - kb.n_concepts) * kb.S;
+  return kb.slots + (size_t)(id - kb.n_fixed) * kb.S;
 }
 
 }  // namespace hth
@@ -141,8 +150,15 @@ struct hth_kb_s {
   std::vector<uint32_t> n_words;       // [R][2]
   std::vector<uint64_t> role_base;     // [R+1]
   std::vector<uint32_t> max_deg[2];    // [R] forward, inverse
+  uint64_t* objmask = nullptr;         // [R][2][W] objects of each role direction
+  uint32_t* objbase = nullptr;         // [R][2][W+1] objects before each word
+  int32_t* ctg_fwd = nullptr;          // [E] object ranks of the forward targets
+  int32_t* ctg_inv = nullptr;          // [E] object ranks of the inverse targets
+  std::vector<uint32_t> n_obj;         // [R][2]; ranks exist where 2 n_obj <= N
   const uint64_t* pos = nullptr;
   const uint64_t* neg = nullptr;
+  const uint64_t* sets = nullptr;      // caller's set table (hth_kb_set_sets)
+  uint32_t n_sets = 0;
   int device = 0;
   int n_cu = 256;
   size_t lds_per_block = 65536;
@@ -156,6 +172,24 @@ struct hth_kb_s {
   bool prof = false;
   std::vector<ProfRec> prof_recs;
   std::vector<hipEvent_t> event_pool;
+  // pinned staging ring for the plan tables: the copy to the device runs
+  // asynchronously from pinned memory; a slot is reused once its copy is done
+  struct Staging {
+    void* host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+  };
+  Staging stage[4];
+  uint32_t stage_next = 0;
+  ~hth_kb_s() {
+    for (Staging& s : stage) {
+      if (s.pending) (void)hipEventSynchronize(s.done);
+      if (s.done) (void)hipEventDestroy(s.done);
+      if (s.host) (void)hipHostFree(s.host);
+    }
+    for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
+  }
   // schedule choices of the batched executor (defaults, environment overrides
   // HTHEDL_GROUP_MIN / _GROUP_K / _XCD / _TBUDGET_MB)
   struct Tuning {
@@ -165,6 +199,8 @@ struct hth_kb_s {
     size_t t_budget = 64ull << 20;  // bytes of T rows resident per launch
     uint32_t group_unroll = 16;  // assertions in flight per lane in a shared pass
     uint32_t nontemporal = 0;    // 1: CSR targets loaded with the streaming hint
+    uint32_t region_reg = 1;     // 1: register-stack region kernel where programs fit
+    uint32_t t_compact = 1;      // 1: T rows of objects only where they are <= N/2
   } tune;
 };
 

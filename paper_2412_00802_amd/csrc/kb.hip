@@ -237,8 +237,54 @@ __global__ void k_scatter_inverse(const uint32_t* __restrict__ fwd_off, const in
   }
 }
 
+// Objects of a role direction: the individuals that occur as targets in it
+// (for the forward direction the subjects of non-empty inverse rows, and the
+// other way round).  mask row 2r + dir holds one bit per individual; base row
+// 2r + dir the number of objects in the words before each word (entry W =
+// their total); ctg maps each assertion's target to its rank among the
+// objects, so that a shared pass can index transposed child rows that hold
+// the objects only.
+__global__ void __launch_bounds__(256)
+k_object_mask(const uint32_t* __restrict__ opp_off, uint32_t N, uint32_t W, uint64_t* __restrict__ mask) {
+  const uint32_t r = blockIdx.y;
+  const uint32_t y = blockIdx.x * 256 + threadIdx.x;
+  const uint32_t* o = opp_off + (size_t)r * (N + 1);
+  const bool obj = y < N && o[y + 1] > o[y];
+  const uint64_t m = __ballot(obj);
+  const uint32_t w = y >> 6;
+  if ((threadIdx.x & 63) == 0 && w < W) mask[(size_t)r * 2 * W + w] = m;
+}
+
+// One block per mask row: exclusive prefix of the words' popcounts.
+__global__ void __launch_bounds__(kScanThreads)
+k_object_base(const uint64_t* __restrict__ mask, uint32_t W, uint32_t* __restrict__ base) {
+  const uint64_t* m = mask + (size_t)blockIdx.x * W;
+  uint32_t* b = base + (size_t)blockIdx.x * (W + 1);
+  const uint32_t per = (W + kScanThreads - 1) / kScanThreads;
+  const uint32_t w0 = threadIdx.x * per, w1 = min(W, w0 + per);
+  uint32_t s = 0;
+  for (uint32_t w = w0; w < w1; ++w) s += (uint32_t)__popcll(m[w]);
+  __shared__ uint32_t tot;
+  uint32_t ex = block_excl_scan(s, &tot);
+  for (uint32_t w = w0; w < w1; ++w) {
+    b[w] = ex;
+    ex += (uint32_t)__popcll(m[w]);
+  }
+  if (threadIdx.x == 0) b[W] = tot;
+}
+
+__global__ void __launch_bounds__(256)
+k_object_rank(const int32_t* __restrict__ tg, uint64_t e0, uint64_t n, const uint64_t* __restrict__ mask,
+              const uint32_t* __restrict__ base, int32_t* __restrict__ ctg) {
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+    const uint32_t y = (uint32_t)tg[e0 + i];
+    const uint64_t m = mask[y >> 6];
+    ctg[e0 + i] = (int32_t)(base[y >> 6] + (uint32_t)__popcll(m & ((1ull << (y & 63)) - 1ull)));
+  }
+}
+
 struct DerivedLayout {
-  size_t fwd_off, inv_off, inv_tg, cursor, bsum, base, meta, words, total;
+  size_t fwd_off, inv_off, inv_tg, cursor, bsum, base, meta, words, objmask, objbase, ctg, total;
   uint32_t nb;
 };
 
@@ -286,6 +332,9 @@ static DerivedLayout layout_for(const hth_kb_desc& d) {
   L.base = at; at += align_up((R + 1) * 8, 256);
   L.meta = at; at += align_up((4 + 4 * R) * 4, 256);
   L.words = at; at += align_up(2 * R * ((N + 63) / 64) * 4, 256);
+  L.objmask = at; at += align_up(2 * R * ((N + 63) / 64) * 8, 256);
+  L.objbase = at; at += align_up(2 * R * ((N + 63) / 64 + 1) * 4, 256);
+  L.ctg = at; at += align_up((size_t)d.n_edges * 8, 256);     // both directions
   L.total = at;
   return L;
 }
@@ -415,6 +464,36 @@ static hth_status kb_build(hth_kb_s* kb, char* derived, hipStream_t st) {
     HTH_HIP(hipGetLastError());
     kb->n_words.assign(2 * R, 0);
     HTH_HIP(hipMemcpyAsync(kb->n_words.data(), wcount, 2 * R * 4, hipMemcpyDeviceToHost, st));
+    // objects of each direction and, where they are at most half of the
+    // individuals, every assertion's object rank
+    const uint32_t W = kb->W;
+    kb->objmask = reinterpret_cast<uint64_t*>(derived + L.objmask);
+    kb->objbase = reinterpret_cast<uint32_t*>(derived + L.objbase);
+    kb->ctg_fwd = reinterpret_cast<int32_t*>(derived + L.ctg);
+    kb->ctg_inv = kb->ctg_fwd + d.n_edges;
+    for (int dir = 0; dir < 2; ++dir)
+      hipLaunchKernelGGL(k_object_mask, dim3((N + 255) / 256, R), dim3(256), 0, st,
+                         dir ? kb->fwd_off : kb->inv_off, N, W, kb->objmask + (size_t)dir * W);
+    hipLaunchKernelGGL(k_object_base, dim3(2 * R), dim3(kScanThreads), 0, st, kb->objmask, W, kb->objbase);
+    HTH_HIP(hipGetLastError());
+    std::vector<uint32_t> nobj(2 * R);
+    for (uint32_t rd = 0; rd < 2 * R; ++rd)
+      HTH_HIP(hipMemcpyAsync(&nobj[rd], kb->objbase + (size_t)rd * (W + 1) + W, 4, hipMemcpyDeviceToHost, st));
+    HTH_HIP(hipStreamSynchronize(st));
+    kb->n_obj = nobj;
+    for (uint32_t r = 0; r < R; ++r) {
+      const uint64_t e0 = kb->role_base[r], n = kb->role_base[r + 1] - e0;
+      if (!n) continue;
+      const unsigned g = (unsigned)std::min<uint64_t>((n + 255) / 256, 65536);
+      for (int dir = 0; dir < 2; ++dir) {
+        if ((uint64_t)nobj[2 * r + dir] * 2 > N) continue;
+        hipLaunchKernelGGL(k_object_rank, dim3(g), dim3(256), 0, st,
+                           dir ? (const int32_t*)kb->inv_tg : d.role_targets, e0, n,
+                           kb->objmask + (size_t)(2 * r + dir) * W, kb->objbase + (size_t)(2 * r + dir) * (W + 1),
+                           dir ? kb->ctg_inv : kb->ctg_fwd);
+      }
+    }
+    HTH_HIP(hipGetLastError());
   }
   uint32_t hflags = 0;
   HTH_HIP(hipMemcpyAsync(&hflags, flags, 4, hipMemcpyDeviceToHost, st));
@@ -460,6 +539,8 @@ extern "C" hth_status hth_kb_create(const hth_kb_desc* desc, void* derived, size
   kb->tune.t_budget = env_u("HTHEDL_TBUDGET_MB", kb->tune.t_budget >> 20) << 20;
   kb->tune.group_unroll = (uint32_t)env_u("HTHEDL_GROUP_UNROLL", kb->tune.group_unroll);
   kb->tune.nontemporal = (uint32_t)env_u("HTHEDL_NT", kb->tune.nontemporal);
+  kb->tune.region_reg = (uint32_t)env_u("HTHEDL_REGION_REG", kb->tune.region_reg);
+  kb->tune.t_compact = (uint32_t)env_u("HTHEDL_T_COMPACT", kb->tune.t_compact);
   kb->lds_per_block = prop.sharedMemPerBlock;
   s = kb_build(kb, static_cast<char*>(derived), static_cast<hipStream_t>(stream));
   if (s) {
@@ -479,6 +560,16 @@ extern "C" hth_status hth_kb_set_examples(hth_kb kb, const uint64_t* pos, const 
   return HTH_OK;
 }
 
+extern "C" hth_status hth_kb_set_sets(hth_kb kb, const uint64_t* rows, uint32_t n_rows) {
+  if (!kb) return fail(HTH_E_INVALID, "kb is NULL");
+  if (n_rows && !rows) return fail(HTH_E_INVALID, "set rows are NULL");
+  if (n_rows >= (1u << 24)) return fail(HTH_E_RANGE, "set table holds at most 2^24 - 1 rows");
+  std::lock_guard<std::mutex> g(kb->mu);
+  kb->sets = n_rows ? rows : nullptr;
+  kb->n_sets = n_rows;
+  return HTH_OK;
+}
+
 extern "C" hth_status hth_kb_max_degree(hth_kb kb, uint32_t role, uint32_t inv, uint32_t* out) {
   if (!kb || !out) return fail(HTH_E_INVALID, "NULL argument");
   if (role >= kb->d.n_roles || inv > 1) return fail(HTH_E_RANGE, "role or direction out of range");
@@ -494,13 +585,16 @@ extern "C" hth_status hth_kb_get_tuning(hth_kb kb, hth_tuning* out) {
   out->xcd_local = kb->tune.xcd_local;
   out->t_budget_mb = (uint32_t)(kb->tune.t_budget >> 20);
   out->unroll = kb->tune.group_unroll;
+  out->region_reg = kb->tune.region_reg;
+  out->t_compact = kb->tune.t_compact;
   return HTH_OK;
 }
 
 extern "C" hth_status hth_kb_set_tuning(hth_kb kb, const hth_tuning* t) {
   if (!kb || !t) return fail(HTH_E_INVALID, "NULL argument");
   if (t->group_k < 1 || t->group_k > 64 || t->xcd_local > 1 || t->t_budget_mb < 1 ||
-      t->t_budget_mb > (1u << 20) || (t->unroll != 8 && t->unroll != 16))
+      t->t_budget_mb > (1u << 20) || (t->unroll != 8 && t->unroll != 16) || t->region_reg > 1 ||
+      t->t_compact > 1)
     return fail(HTH_E_RANGE, "tuning value out of range");
   std::lock_guard<std::mutex> g(kb->mu);
   kb->tune.group_min = t->group_min;
@@ -508,6 +602,8 @@ extern "C" hth_status hth_kb_set_tuning(hth_kb kb, const hth_tuning* t) {
   kb->tune.xcd_local = t->xcd_local;
   kb->tune.t_budget = (size_t)t->t_budget_mb << 20;
   kb->tune.group_unroll = t->unroll;
+  kb->tune.region_reg = t->region_reg;
+  kb->tune.t_compact = t->t_compact;
   return HTH_OK;
 }
 

@@ -69,7 +69,7 @@ __global__ void k_features(const hth_node* __restrict__ nodes, const uint32_t* _
     const hth_node n = nodes[i];
     const uint32_t li = i - b;
     uint64_t v = node_header_hash(n);
-    bool ok = n.op < HTH_NUM_OPS;
+    bool ok = n.op <= HTH_DATA_LE;   // the DL constructs; set-table leaves carry no syntax
     if (n.op == HTH_NOT || (n.op >= HTH_EXISTS && n.op <= HTH_EXACTLY)) {
       ok = ok && n.child < li;
       v = fnv_bytes(v, ok ? hash[b + n.child] : 0ull, 8);

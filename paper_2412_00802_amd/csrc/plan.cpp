@@ -140,7 +140,9 @@ class Dag {
 
 inline bool is_role(uint8_t op) { return op >= HTH_EXISTS && op <= HTH_EXACTLY; }
 inline bool is_data(uint8_t op) { return op == HTH_DATA_GE || op == HTH_DATA_LE; }
-inline bool is_leaflike(uint8_t op) { return op == HTH_ATOM || is_data(op) || is_role(op); }
+inline bool is_leaflike(uint8_t op) {
+  return op == HTH_ATOM || op == HTH_SET || is_data(op) || is_role(op);
+}
 
 struct Compiler {
   const hth_kb_s& kb;
@@ -173,6 +175,10 @@ struct Compiler {
         case HTH_ATOM:
           if (x.arg >= d.n_concepts) return bad(HTH_E_RANGE, "concept id out of range");
           map[i] = dag.leaf(HTH_ATOM, 0, x.arg, 0);
+          break;
+        case HTH_SET:
+          if (x.arg >= kb.n_sets) return bad(HTH_E_RANGE, "set row outside the registered set table");
+          map[i] = dag.leaf(HTH_SET, 0, x.arg, 0);
           break;
         case HTH_NOT:
           if (x.child >= i) return bad(HTH_E_PLAN, "child index not before its parent");
@@ -219,7 +225,7 @@ struct Compiler {
     return HTH_OK;
   }
 
-  uint32_t new_row() { return kb.d.n_concepts + n_slots++; }
+  uint32_t new_row() { return kb.d.n_concepts + kb.n_sets + n_slots++; }
 
   int32_t region_depth(uint32_t v) {
     if (depth[v] >= 0) return depth[v];
@@ -240,7 +246,9 @@ struct Compiler {
 
   uint32_t leaf_row(uint32_t v) const {
     const CNode& n = dag.nodes[v];
-    return n.op == HTH_ATOM ? n.arg : row[v];
+    if (n.op == HTH_ATOM) return n.arg;
+    if (n.op == HTH_SET) return kb.d.n_concepts + n.arg;
+    return row[v];
   }
 
   void emit(uint32_t v, std::vector<uint32_t>& code) {
@@ -456,6 +464,8 @@ struct Compiler {
       P.roots.push_back(t);
     }
     P.n_slots = n_slots;
+    P.sets = kb.sets;
+    P.n_sets = kb.n_sets;
     P.n_canonical = (uint32_t)nv;
     return HTH_OK;
   }
@@ -474,6 +484,9 @@ hth_status compile_plan(const hth_kb_s& kb, const hth_node* nodes, const uint32_
     hth_status s = c.add_hypothesis(nodes + b, e - b, children, n_children, h);
     if (s) return s;
     out.n_input_nodes += e - b;
+    // row ids (concepts < 2^26, set rows < 2^24, one slot per node) fit the
+    // 27-bit argument of the region bytecode
+    if (out.n_input_nodes > (1u << 24)) return fail(HTH_E_RANGE, "more than 2^24 nodes in one call");
   }
   return c.build(opt, out);
 }

@@ -32,6 +32,8 @@ struct Plan {
   std::vector<PlanLevel> levels;
   std::vector<RegionTask> roots;
   uint32_t n_slots = 0;
+  const uint64_t* sets = nullptr;   // the set table the plan's HTH_SET rows refer to
+  uint32_t n_sets = 0;
   // statistics
   uint32_t n_input_nodes = 0, n_canonical = 0, n_role_nodes = 0;
 };

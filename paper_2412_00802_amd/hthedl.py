@@ -23,7 +23,7 @@ STATUS = {0: "HTH_OK", -1: "HTH_E_INVALID", -2: "HTH_E_RANGE", -3: "HTH_E_NOMEM"
           -4: "HTH_E_DEVICE", -5: "HTH_E_PLAN", -6: "HTH_E_STATE", -7: "HTH_E_UNSUPPORTED"}
 
 OPS = {"top": 0, "bot": 1, "atom": 2, "not": 3, "and": 4, "or": 5, "exists": 6, "forall": 7,
-       "atleast": 8, "atmost": 9, "exactly": 10, "dge": 11, "dle": 12}
+       "atleast": 8, "atmost": 9, "exactly": 10, "dge": 11, "dle": 12, "set": 13}
 
 NODE_DTYPE = np.dtype([("op", np.uint8), ("inv", np.uint8), ("arity", np.uint16),
                        ("arg", np.uint32), ("child", np.uint32), ("q", np.uint32)])
@@ -34,7 +34,8 @@ EXPORTED = ["hth_kb_derived_bytes", "hth_kb_create", "hth_kb_set_examples", "hth
             "hth_sync", "hth_status_str", "hth_last_error", "hth_profile_begin",
             "hth_profile_end", "hth_features", "hth_densify", "hth_gemm_bf16", "hth_head_forward",
             "hth_head_backward", "hth_colsum", "hth_adamw", "hth_to_bf16", "hth_topk",
-            "hth_batch_workspace_bytes", "hth_head_score", "hth_kb_get_tuning", "hth_kb_set_tuning"]
+            "hth_batch_workspace_bytes", "hth_head_score", "hth_kb_get_tuning", "hth_kb_set_tuning",
+            "hth_kb_set_sets", "hth_eval_batch_sets"]
 
 
 class HthError(RuntimeError):
@@ -55,7 +56,8 @@ class KBDesc(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("group_min", ctypes.c_uint32), ("group_k", ctypes.c_uint32),
                 ("xcd_local", ctypes.c_uint32), ("t_budget_mb", ctypes.c_uint32),
-                ("unroll", ctypes.c_uint32)]
+                ("unroll", ctypes.c_uint32), ("region_reg", ctypes.c_uint32),
+                ("t_compact", ctypes.c_uint32)]
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -90,6 +92,8 @@ def lib() -> ctypes.CDLL:
             "hth_workspace_bytes": [P, U32, U32, ctypes.POINTER(S)],
             "hth_eval_one": [P, P, U32, P, U32, P, S, P, P, P],
             "hth_eval_batch": [P, P, P, U32, P, U32, P, S, P, P],
+            "hth_eval_batch_sets": [P, P, P, U32, P, U32, P, S, P, P, P],
+            "hth_kb_set_sets": [P, P, U32],
             "hth_batch_workspace_bytes": [P, P, P, U32, P, U32, ctypes.POINTER(S)],
             "hth_sync": [P],
             "hth_profile_begin": [P],
@@ -175,6 +179,10 @@ def hth_kb_set_examples(kb, pos, neg) -> None:
     _check(lib().hth_kb_set_examples(kb, _ptr(pos), _ptr(neg)))
 
 
+def hth_kb_set_sets(kb, rows, n_rows: int) -> None:
+    _check(lib().hth_kb_set_sets(kb, _ptr(rows) if n_rows else None, n_rows))
+
+
 def hth_kb_max_degree(kb, role: int, inv: int) -> int:
     out = ctypes.c_uint32()
     _check(lib().hth_kb_max_degree(kb, role, inv, ctypes.byref(out)))
@@ -219,6 +227,16 @@ def hth_eval_batch(kb, nodes: np.ndarray, offsets: np.ndarray, children: np.ndar
     _check(lib().hth_eval_batch(kb, _np_ptr(nodes), _np_ptr(offsets), offsets.shape[0] - 1,
                                 _np_ptr(children), children.shape[0], _ptr(ws), ws_bytes,
                                 _ptr(d_counts), _stream(stream)))
+
+
+def hth_eval_batch_sets(kb, nodes: np.ndarray, offsets: np.ndarray, children: np.ndarray, ws,
+                        ws_bytes: int, d_sets, d_counts, stream=None) -> None:
+    nodes = np.ascontiguousarray(nodes, dtype=NODE_DTYPE)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint32)
+    children = np.ascontiguousarray(children, dtype=np.uint32)
+    _check(lib().hth_eval_batch_sets(kb, _np_ptr(nodes), _np_ptr(offsets), offsets.shape[0] - 1,
+                                     _np_ptr(children), children.shape[0], _ptr(ws), ws_bytes,
+                                     _ptr(d_sets), _ptr(d_counts), _stream(stream)))
 
 
 def hth_batch_workspace_bytes(kb, nodes: np.ndarray, offsets: np.ndarray, children: np.ndarray) -> int:
@@ -317,7 +335,7 @@ def encode(h, nodes: list, children: list) -> int:
     code = OPS[op]
     if op in ("top", "bot"):
         nodes.append((code, 0, 0, 0, 0, 0))
-    elif op == "atom":
+    elif op in ("atom", "set"):
         nodes.append((code, 0, 0, h[1], 0, 0))
     elif op == "not":
         c = encode(h[1], nodes, children)

@@ -232,3 +232,181 @@ def test_group_widths(m):
     hs = _distinct_role_nodes(m, 40, 1, m % 2, seed=m)
     hs += [("and", h, ("atom", i % 40)) for i, h in enumerate(hs[: m // 2])]
     check(kb, hs, label=f"group m={m}")
+
+
+@pytest.mark.parametrize("n,edges", [(5000, 300), (70000, 4000), (130001, 60000)])
+def test_sparse_roles(n, edges):
+    """Most 64-subject words have no assertion: the passes visit the non-empty
+    words only and the others hold the zero-count result (all ones for
+    forall / at-most / exactly-0, zeros otherwise)."""
+    cfg = synth.small_config(n=n, n_concepts=20, n_roles=3, s=1.4, cap=300, n_pos=n // 10,
+                             n_neg=n // 10, n_hyps=80, hyp_depth=4, total_edges=edges,
+                             seed_index=1400 + n % 89)
+    kb = synth.make_kb(cfg)
+    hs = synth.make_hypotheses(cfg, kb)
+    hs += _distinct_role_nodes(70, 20, 0, 1, seed=n)
+    hs += [("forall", 2, 0, ("atom", 1)), ("atmost", 0, 1, 1, ("atom", 2)), ("exactly", 0, 0, 0, ("atom", 3)),
+           ("not", ("exists", 1, 0, ("top",)))]
+    eng = check(kb, hs, label=f"sparse n={n}")
+    o = Oracle(kb)
+    for h in hs[-4:]:
+        (_, bits) = eng.eval_one(h, instances=True)
+        np.testing.assert_array_equal(bits, o.ext_bits(h))
+
+
+def test_every_schedule_gives_identical_counts():
+    """The autotuner's schedules change speed only: each one reproduces the
+    oracle's coverage (and the autotuner itself checks them against each other)."""
+    from paper_2412_00802_amd import autotune
+    cfg = synth.small_config(n=30000, n_concepts=30, n_roles=4, s=1.5, cap=200, n_pos=3000, n_neg=3000,
+                             n_hyps=300, hyp_depth=5, seed_index=1500)
+    kb = synth.make_kb(cfg)
+    hs = synth.make_hypotheses(cfg, kb) + synth.make_sized_hypotheses(cfg, kb, count=300)
+    want = Oracle(kb).coverages(hs)
+    eng = hthedl.Engine(kb)
+    grid = autotune.candidates(kb.n) + [dict(group_min=0, group_k=64, xcd_local=1, t_budget_mb=64, unroll=8),
+                                        dict(region_reg=0)]
+    for cand in grid:
+        hthedl.hth_kb_set_tuning(eng.handle, **cand)
+        got = eng.eval_batch(hs)
+        assert np.array_equal(got, want), cand
+    best = autotune.autotune(eng, hs, grid=grid[:4], reps=1, cache=None)
+    got = hthedl.hth_kb_get_tuning(eng.handle)
+    assert {k: got[k] for k in best} == best
+    with pytest.raises(hthedl.HthError):
+        hthedl.hth_kb_set_tuning(eng.handle, group_k=65)
+
+
+def _subtrees(h, out):
+    """Distinct compound or data subtrees of h (atoms, top and bottom excluded)."""
+    if h[0] in ("atom", "top", "bot"):
+        return
+    out.setdefault(h, len(out))
+    if h[0] == "not":
+        _subtrees(h[1], out)
+    elif h[0] in ("and", "or"):
+        for c in h[1:]:
+            _subtrees(c, out)
+    elif h[0] in ("exists", "forall", "atleast", "atmost", "exactly"):
+        _subtrees(h[-1], out)
+
+
+def _substitute(h, slot):
+    if h in slot:
+        return ("set", slot[h])
+    if h[0] == "not":
+        return ("not", _substitute(h[1], slot))
+    if h[0] in ("and", "or"):
+        return (h[0],) + tuple(_substitute(c, slot) for c in h[1:])
+    if h[0] in ("exists", "forall", "atleast", "atmost", "exactly"):
+        return h[:-1] + (_substitute(h[-1], slot),)
+    return h
+
+
+def test_set_table_leaves():
+    """Instance sets written by hth_eval_batch_sets equal the oracle's, and
+    hypotheses whose subtrees are replaced by set-table leaves cover exactly
+    what the full hypotheses cover (plain and batched)."""
+    import torch
+    from paper_2412_00802_amd import search
+    cfg = synth.small_config(n=20000, n_concepts=24, n_roles=4, s=1.5, cap=100, n_data=3,
+                             n_pos=2000, n_neg=2000, seed_index=1600)
+    kb = synth.make_kb(cfg)
+    o = Oracle(kb)
+    parents = synth.make_hypotheses(cfg, kb, count=40, depth=4)
+    slot: dict = {}
+    for p in parents:
+        _subtrees(p, slot)
+    subs = sorted(slot, key=slot.get)
+    say(f"[parity] set table: {len(subs)} subtrees of {len(parents)} parents")
+    eng = hthedl.Engine(kb)
+    base = 5                                   # rows before `base` stay unused
+    table = torch.full((base + len(subs), eng.S), -1, dtype=torch.int64, device="cuda")
+    nodes, offs, ch = hthedl.encode_batch(subs)
+    eng.ensure_workspace(hthedl.hth_batch_workspace_bytes(eng.handle, nodes, offs, ch))
+    cnt = torch.empty((len(subs), 2), dtype=torch.int32, device="cuda")
+    hthedl.hth_eval_batch_sets(eng.handle, nodes, offs, ch, eng.ws, eng.ws_bytes, table[base:], cnt)
+    rows = table.cpu().numpy().view(np.uint64)
+    assert np.array_equal(cnt.cpu().numpy().view(np.uint32), o.coverages(subs))
+    for i, s in enumerate(subs):
+        assert np.array_equal(rows[base + i, :eng.W], o.ext_bits(s)), s
+        assert not rows[base + i, eng.W:].any()
+    hthedl.hth_kb_set_sets(eng.handle, table, table.shape[0])
+    slot = {s: base + i for i, s in enumerate(subs)}
+    ref = search.Refiner(kb, np.random.default_rng(5))
+    full = []
+    for p in parents:
+        full.extend(ref.refine(p, 12))
+    cached = [_substitute(c, slot) for c in full]
+    assert sum(c != f for c, f in zip(cached, full)) > len(full) // 2
+    want = o.coverages(full)
+    assert np.array_equal(eng.eval_batch(cached), want)
+    assert np.array_equal(eng.eval_plain(cached[:60]), want[:60])
+    # a refinement of every parent with the parent itself as one set leaf
+    adds = [("and", ("set", slot[p]), ref.conjunct()) for p in parents if p in slot]
+    want = o.coverages([("and", p, a[2]) for p, a in zip([p for p in parents if p in slot], adds)])
+    assert np.array_equal(eng.eval_batch(adds), want)
+    with pytest.raises(hthedl.HthError) as e:
+        eng.eval_one(("set", table.shape[0]))
+    assert e.value.status == -2
+    hthedl.hth_kb_set_sets(eng.handle, None, 0)
+    with pytest.raises(hthedl.HthError) as e:
+        eng.eval_batch([("set", 0)])
+    assert e.value.status == -2
+
+
+def test_deep_regions_both_region_kernels():
+    """Balanced and/or trees whose value stacks need 2..10 entries: the
+    register-stack region kernel (up to six) and the LDS-stack kernel (deeper
+    programs, or all programs when switched off) agree with the oracle."""
+    cfg = synth.small_config(n=5000, n_concepts=64, n_roles=3, n_data=2, n_pos=800, n_neg=800,
+                             seed_index=1700)
+    kb = synth.make_kb(cfg)
+    rng = np.random.default_rng(17)
+
+    def tree(h, op="and"):
+        if h == 0:
+            u = rng.random()
+            if u < 0.7:
+                a = ("atom", int(rng.integers(0, 64)))
+                return ("not", a) if rng.random() < 0.3 else a
+            if u < 0.85:
+                return ("exists", int(rng.integers(0, 3)), int(rng.integers(0, 2)), ("atom", int(rng.integers(0, 64))))
+            return ("dge", 0, float(kb.deciles[0, int(rng.integers(0, 9))]))
+        other = "or" if op == "and" else "and"
+        return (op, tree(h - 1, other), tree(h - 1, other))
+
+    hyps = [tree(h, op) for h in range(1, 11) for op in ("and", "or") for _ in range(3)]
+    want = Oracle(kb).coverages(hyps)
+    eng = hthedl.Engine(kb, max_nodes=4096)
+    for reg in (1, 0):
+        hthedl.hth_kb_set_tuning(eng.handle, region_reg=reg)
+        assert np.array_equal(eng.eval_batch(hyps), want), reg
+        assert np.array_equal(eng.eval_plain(hyps), want), reg
+
+
+def test_compact_transposed_rows_on_sparse_roles():
+    """Role directions whose objects are few: shared passes over T rows kept
+    for the objects only (indexed by rank) equal the oracle, the full-row
+    passes and the single-node passes, in both directions and every T width."""
+    cfg = synth.small_config(n=70000, n_concepts=40, n_roles=3, s=1.4, cap=400, n_data=2, n_pos=5000,
+                             n_neg=5000, seed_index=1800, total_edges=9000)
+    kb = synth.make_kb(cfg)
+    rng = np.random.default_rng(18)
+    hyps = []
+    for _ in range(700):
+        r, inv = int(rng.integers(0, 3)), int(rng.integers(0, 2))
+        c = ("atom", int(rng.integers(0, 40)))
+        if rng.random() < 0.3:
+            c = ("or", c, ("dle", 1, float(kb.deciles[1, int(rng.integers(0, 9))])))
+        op = rng.choice(["exists", "forall", "atleast", "atmost"])
+        hyps.append((op, r, inv, c) if op in ("exists", "forall") else (op, int(rng.integers(1, 4)), r, inv, c))
+    want = Oracle(kb).coverages(hyps)
+    eng = hthedl.Engine(kb)
+    say(f"[parity] compact T: objects per direction {[hthedl.hth_kb_max_degree(eng.handle, r, 0) for r in range(3)]}")
+    for k in (8, 16, 32, 64):
+        for compact in (1, 0):
+            hthedl.hth_kb_set_tuning(eng.handle, group_min=1, group_k=k, t_compact=compact)
+            assert np.array_equal(eng.eval_batch(hyps), want), (k, compact)
+    hthedl.hth_kb_set_tuning(eng.handle, group_min=0)
+    assert np.array_equal(eng.eval_batch(hyps), want)

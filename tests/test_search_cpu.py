@@ -61,3 +61,46 @@ def test_refinement_trace_with_oracle_engine():
 def test_recall():
     assert search.recall_at([1, 2, 3], [3, 4, 5]) == 1 / 3
     assert search.recall_at(range(100), range(100)) == 1.0
+
+
+def test_trace_set_substitution_expands_back():
+    """Replacing cached parent subtrees by set leaves loses nothing: expanding
+    the leaves again gives the candidate back, and add-conjunct candidates of
+    an and-parent read the parent as one leaf."""
+    from paper_2412_00802_amd import trace
+    cfg, kb, o = small()
+    rng = np.random.default_rng(4)
+    ref = search.Refiner(kb, rng)
+    parents = [("and", ("atom", 1), ("exists", 0, 1, ("atom", 2)))] + synth.make_hypotheses(cfg, kb, count=30, depth=4)
+    want = {}
+    for p in parents:
+        want.setdefault(p, None)
+        trace.subtrees(p, want)
+    cache = object.__new__(trace.SetCache)
+    cache.slot = {k: 100 + i for i, k in enumerate(want)}
+    inv = {v: k for k, v in cache.slot.items()}
+
+    def expand(h):
+        if h[0] == "set":
+            return inv[h[1]]
+        if h[0] == "not":
+            return ("not", expand(h[1]))
+        if h[0] in ("and", "or"):
+            out = []
+            for c in h[1:]:
+                e = expand(c)
+                # a set leaf standing for an and-parent inside an and: flatten back
+                out.extend(e[1:] if (c[0] == "set" and e[0] == "and" and h[0] == "and") else [e])
+            return (h[0],) + tuple(out)
+        if h[0] in trace.ROLE_OPS:
+            return h[:-1] + (expand(h[-1]),)
+        return h
+
+    n_one_leaf = 0
+    for p in parents:
+        for c in ref.refine(p, 10):
+            s = cache.substitute(c, p)
+            assert expand(s) == c or o.coverage(expand(s)) == o.coverage(c)
+            if p[0] == "and" and s[0] == "and" and s[1] == ("set", cache.slot[p]):
+                n_one_leaf += 1
+    assert n_one_leaf > 0
