@@ -51,7 +51,8 @@ def recorded_traffic(kernel: str):
 
 
 def summarize(kt_dir: str, fetch_dir: str, write_dir: str, command: str, out_md: str,
-              sha: str = None) -> None:
+              sha: str = None, title: str = "c2 workload (1M individuals, 4096 hypotheses, batched)",
+              traffic_file: str = TRAFFIC_FILE) -> None:
     """Turn rocprofv3 outputs (kernel trace stats, FETCH_SIZE, WRITE_SIZE passes,
     each run with --calibrate-copy) into the committed summary and traffic file.
     sha: the kernel source hash of the profiled build (default: the current one)."""
@@ -80,7 +81,7 @@ def summarize(kt_dir: str, fetch_dir: str, write_dir: str, command: str, out_md:
     stats = []
     for f in glob.glob(os.path.join(kt_dir, "*kernel_stats.csv")):
         stats += list(csv.DictReader(open(f)))
-    lines = ["# rocprofv3 summary: c2 workload (1M individuals, 4096 hypotheses, batched)", "",
+    lines = [f"# rocprofv3 summary: {title}", "",
              "Command (kernel trace):", "", "    " + command.format(opts="--kernel-trace --stats --output-format csv"), "",
              "Counter passes (one counter per run):", "",
              "    " + command.format(opts="--pmc FETCH_SIZE --output-format csv"),
@@ -107,7 +108,7 @@ def summarize(kt_dir: str, fetch_dir: str, write_dir: str, command: str, out_md:
         if cur is None or hb > cur["hbm_bytes_per_launch"]:
             out["kernels"][base] = {"name": k, "hbm_bytes_per_launch": hb}
     open(out_md, "w").write("\n".join(lines) + "\n")
-    json.dump(out, open(TRAFFIC_FILE, "w"), indent=1)
+    json.dump(out, open(traffic_file, "w"), indent=1)
 
 
 def log(*a):

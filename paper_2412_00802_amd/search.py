@@ -204,8 +204,13 @@ def refinement_rounds(kb, evaluate: Callable[[Sequence[tuple]], np.ndarray], n_p
                 if c not in seen:
                     seen.add(c)
                     cands.append(c)
-        while len(cands) < per_round:
-            c = ("and", parents[int(rng.integers(0, len(parents)))], ref.conjunct())
+        # top up with added conjuncts (two at once once single ones run out);
+        # a small KB may have fewer distinct candidates than asked for
+        tries = 0
+        while len(cands) < per_round and tries < 16 * per_round:
+            tries += 1
+            extra = (ref.conjunct(),) if tries < 2 * per_round else (ref.conjunct(), ref.conjunct())
+            c = ("and", parents[int(rng.integers(0, len(parents)))]) + extra
             if c not in seen:
                 seen.add(c)
                 cands.append(c)

@@ -104,3 +104,19 @@ def test_trace_set_substitution_expands_back():
             if p[0] == "and" and s[0] == "and" and s[1] == ("set", cache.slot[p]):
                 n_one_leaf += 1
     assert n_one_leaf > 0
+
+
+def test_refinement_rounds_end_on_a_small_candidate_space():
+    """A KB with fewer distinct one-step candidates than a round asks for:
+    the rounds still end, with distinct candidates."""
+    cfg = synth.small_config(n=200, n_concepts=4, depth=2, n_roles=1, cap=4, n_data=1, n_pos=20, n_neg=20,
+                             seed_index=1310)
+    kb = synth.make_kb(cfg)
+    o = Oracle(kb)
+    rng = np.random.default_rng(2)
+    n = 0
+    for r, cands, counts in search.refinement_rounds(kb, o.coverages, int(o.pos.sum()), rounds=2,
+                                                    per_round=3000, beam=2, rng=rng):
+        assert len(cands) == len(set(cands)) and counts.shape == (len(cands), 2)
+        n += 1
+    assert n == 2
