@@ -52,7 +52,7 @@ def recorded_traffic(kernel: str):
 
 def summarize(kt_dir: str, fetch_dir: str, write_dir: str, command: str, out_md: str,
               sha: str = None, title: str = "c2 workload (1M individuals, 4096 hypotheses, batched)",
-              traffic_file: str = TRAFFIC_FILE) -> None:
+              traffic_file: str = TRAFFIC_FILE, tcc_dir: str = None) -> None:
     """Turn rocprofv3 outputs (kernel trace stats, FETCH_SIZE, WRITE_SIZE passes,
     each run with --calibrate-copy) into the committed summary and traffic file.
     sha: the kernel source hash of the profiled build (default: the current one)."""
@@ -98,15 +98,31 @@ def summarize(kt_dir: str, fetch_dir: str, write_dir: str, command: str, out_md:
               f"{f_fac:.3f} fetched bytes and {w_fac:.3f} written bytes per counted KiB-byte.", "",
               "| kernel | fetch KiB | write KiB | HBM bytes per launch (scaled) |", "|---|---|---|---|"]
     out = {"source_sha": sha, "fetch_factor": f_fac, "write_factor": w_fac, "kernels": {}}
+    agg = {}
     for k in sorted(fetch, key=lambda k: -fetch[k][1]):
         if k not in write:
             continue
         hb = fetch[k][1] * 1024 * f_fac + write[k][1] * 1024 * w_fac
         lines.append(f"| {k[:60]} | {fetch[k][1]:.0f} | {write[k][1]:.0f} | {hb / 1e6:.1f} MB |")
+        # per launch over every instantiation of the kernel, weighted by launches
         base = k.split("<")[0].split("::")[-1]
-        cur = out["kernels"].get(base)
-        if cur is None or hb > cur["hbm_bytes_per_launch"]:
-            out["kernels"][base] = {"name": k, "hbm_bytes_per_launch": hb}
+        a = agg.setdefault(base, [0, 0.0, []])
+        a[0] += fetch[k][0]
+        a[1] += hb * fetch[k][0]
+        a[2].append(k)
+    for base, (n, tot, names) in agg.items():
+        out["kernels"][base] = {"names": names, "launches": n, "hbm_bytes_per_launch": tot / n}
+    lines += ["", "HBM bytes per launch over all instantiations (launch-weighted): " +
+              ", ".join(f"{b} {v['hbm_bytes_per_launch'] / 1e6:.1f} MB" for b, v in
+                        sorted(out["kernels"].items(), key=lambda kv: -kv[1]["hbm_bytes_per_launch"])[:6])]
+    if tcc_dir:
+        hit, miss = counters(tcc_dir, "TCC_HIT_sum"), counters(tcc_dir, "TCC_MISS_sum")
+        lines += ["", "## L2 (TCC_HIT_sum / TCC_MISS_sum per dispatch)", "",
+                  "    " + command.format(opts="--pmc TCC_HIT_sum TCC_MISS_sum --output-format csv"), "",
+                  "| kernel | hits | misses | miss rate |", "|---|---|---|---|"]
+        for k in sorted(miss, key=lambda k: -miss[k][1])[:10]:
+            h, m = hit.get(k, (0, 0.0))[1], miss[k][1]
+            lines.append(f"| {k[:60]} | {h:.3g} | {m:.3g} | {m / max(h + m, 1e-9):.2f} |")
     open(out_md, "w").write("\n".join(lines) + "\n")
     json.dump(out, open(traffic_file, "w"), indent=1)
 
@@ -162,11 +178,13 @@ def main():
     ap.add_argument("--summarize", nargs=3, metavar=("KT_DIR", "FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--summary-out", default=os.path.join(ROOT, "profiles", "k_group_c2.md"))
     ap.add_argument("--summary-sha", default=None, help="kernel source hash of the profiled build")
+    ap.add_argument("--summary-tcc", default=None, help="rocprofv3 output of the L2 hit/miss pass")
     ap.add_argument("--summary-command", default="rocprofv3 {opts} -d OUT -o run -- python3 bench.py "
                     "--steps 2 --warmup 1 --plain 0 --cpu-sample 0 --no-profile --calibrate-copy")
     args = ap.parse_args()
     if args.summarize:
-        summarize(*args.summarize, args.summary_command, args.summary_out, args.summary_sha)
+        summarize(*args.summarize, args.summary_command, args.summary_out, args.summary_sha,
+                  tcc_dir=args.summary_tcc)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is a "
