@@ -25,7 +25,7 @@ KIND_NAMES = {0: "k_threshold", 1: "k_region", 2: "k_role", 3: "k_tbuild", 4: "k
 # the dominant kernel's source: its counters are void once these change
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2412_00802_amd", "csrc", f)
                   for f in ("group_kernels.h", "hth_internal.h")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2.json")   # counters of the c2 workload
 COPY_BYTES = 256 << 20      # elementwise pass used to calibrate the byte counters
 
 
@@ -37,11 +37,11 @@ def source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(kernel: str):
+def recorded_traffic(kernel: str, traffic_file: str = TRAFFIC_FILE):
     """HBM bytes per launch of `kernel` from the committed counter summary, or
     None when the kernel source changed since the counters were taken."""
     try:
-        rec = json.load(open(TRAFFIC_FILE))
+        rec = json.load(open(traffic_file))
     except (OSError, ValueError):
         return None
     if rec.get("source_sha") != source_sha():
@@ -173,6 +173,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--autotune", action="store_true", help="pick the schedule with the autotuner first")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of 256 MiB (byte-counter calibration)")
     ap.add_argument("--summarize", nargs=3, metavar=("KT_DIR", "FETCH_DIR", "WRITE_DIR"))
@@ -213,6 +214,12 @@ def main():
     def step():
         hthedl.hth_eval_batch(eng.handle, nodes, offs, ch, eng.ws, eng.ws_bytes, counts, stream)
 
+    schedule = None
+    if args.autotune:
+        from paper_2412_00802_amd import autotune
+        schedule = autotune.autotune(eng, hyps, reps=1, cache=None, log=log)
+        eng.ensure_workspace(hthedl.hth_batch_workspace_bytes(eng.handle, nodes, offs, ch))
+        log(f"[bench] schedule {schedule}")
     if args.calibrate_copy:
         # one elementwise kernel over memory nothing has touched: reads and
         # writes COPY_BYTES each (the byte-counter calibration)
@@ -252,7 +259,8 @@ def main():
         ach = e["bytes"] / (e["ms"] * 1e-3) / 1e9
         roofline = {"kernel": KIND_NAMES.get(dom), "bound": "hbm", "achieved": round(ach, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                    "traffic": recorded_traffic(KIND_NAMES.get(dom)),
+                    "traffic": recorded_traffic(KIND_NAMES.get(dom)) if args.config == "c2" and not args.autotune
+                    else None,
                     "algorithmic_bytes_per_launch": e["bytes"] / e["launches"],
                     "avg_launch_ms": e["ms"] / e["launches"]}
         log(f"[bench] kernels: {json.dumps(kernels)}")
@@ -294,7 +302,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": describe(args.config, cfg, kb), "n_hyps": H,
                    "n_individuals": cfg.n_individuals, "n_assertions": kb.n_edges,
-                   "mode": "batched"},
+                   "mode": "batched",
+                   "schedule": schedule or hthedl.hth_kb_get_tuning(eng.handle)},
         "roofline": roofline, "cpu_baseline": cpu, "plain": plain, "parity_sample": parity,
         "kernels": kernels,
     }

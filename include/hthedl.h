@@ -149,7 +149,8 @@ hth_status hth_kb_max_degree(hth_kb kb, uint32_t role, uint32_t inv, uint32_t* o
  * xcd_local: 1 = keep each shared pass on one XCD (its L2 holds the pass's
  *   transposed child rows);
  * t_budget_mb: transposed child rows resident per launch (MiB);
- * unroll: assertions in flight per lane (8 or 16);
+ * unroll: assertions in flight per lane in passes over directions with many
+ *   assertions per word (8 or 16; sparse directions always use 8);
  * region_reg: 1 = boolean regions whose value stack fits six entries run with
  *   the stack in registers and four words per lane (0 = the LDS-stack kernel);
  * t_compact: 1 = shared passes over a role direction whose objects (targets)
@@ -277,8 +278,12 @@ hth_status hth_head_forward(const uint16_t* h, int Bn, int Kd, const float* w, c
                             float* z, const float* y, float* dz, float scale, float* loss, void* stream);
 
 /* Screening score from the logits z (fp32 [Bn][2]): the F1 of the predicted
- * coverage, p = sigmoid(z0) n_pos, q = sigmoid(z1) n_neg, 2p / (p + q + n_pos). */
-hth_status hth_head_score(const float* z, int Bn, float n_pos, float n_neg, float* score, void* stream);
+ * coverage, p = sigmoid(z0) P_b, q = sigmoid(z1) N_b, 2p / (p + q + n_pos).
+ * base: NULL, then (P_b, N_b) = (n_pos, n_neg) (the logits predict covered
+ * fractions of the examples); or device uint32 [Bn][2] base coverage per row
+ * (the logits predict the shares of a parent's coverage a refinement keeps). */
+hth_status hth_head_score(const float* z, int Bn, float n_pos, float n_neg, const uint32_t* base,
+                          float* score, void* stream);
 
 /* Backward of the output layer: dw[k][o] = sum_b h[b][k] dz[b][o];
  * dh[b][k] = (dz[b] . w[k]) where h[b][k] > 0, else 0 (ReLU of the layer below). */

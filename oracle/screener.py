@@ -147,10 +147,13 @@ def adamw(p, g, m, v, lr, b1, b2, eps, wd, step):
     return p, m, v
 
 
-def predicted_f1(z: np.ndarray, n_pos: int, n_neg: int) -> np.ndarray:
-    """F1 of the predicted coverage: p = sigmoid(z0) |P|, q = sigmoid(z1) |Ng|,
-    F1 = 2p / (2p + q + (|P| - p))."""
-    p = n_pos / (1.0 + np.exp(-z[:, 0]))
-    q = n_neg / (1.0 + np.exp(-z[:, 1]))
+def predicted_f1(z: np.ndarray, n_pos: int, n_neg: int, base: np.ndarray = None) -> np.ndarray:
+    """F1 of the predicted coverage: p = sigmoid(z0) P_b, q = sigmoid(z1) N_b,
+    F1 = 2p / (2p + q + (|P| - p)); (P_b, N_b) = base[b] (a parent's coverage,
+    when the logits predict the shares of it a refinement keeps), else (|P|, |Ng|)."""
+    bp = np.full(z.shape[0], float(n_pos)) if base is None else np.asarray(base, dtype=np.float64)[:, 0]
+    bn = np.full(z.shape[0], float(n_neg)) if base is None else np.asarray(base, dtype=np.float64)[:, 1]
+    p = bp / (1.0 + np.exp(-z[:, 0]))
+    q = bn / (1.0 + np.exp(-z[:, 1]))
     den = p + q + n_pos
     return np.where(den > 0, 2 * p / np.maximum(den, 1e-30), 0.0)

@@ -37,22 +37,24 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 // ---------------------------------------------------------------------------
 // numeric thresholds
 // ---------------------------------------------------------------------------
+// All thresholds requested on one property in one pass over its column: one
+// lane per individual, one wave ballot per threshold and word.
 __global__ void __launch_bounds__(256)
-k_threshold(DevKB kb, const ThrTask* __restrict__ tasks, uint32_t bpt) {
-  const uint32_t task = blockIdx.x / bpt, b = blockIdx.x % bpt;
-  const ThrTask T = tasks[task];
-  const float* col = kb.data + (size_t)T.prop * kb.N;
-  uint64_t* out = out_ptr(kb, T.out_row);
+k_threshold(DevKB kb, const ThrGroup* __restrict__ groups, const ThrTask* __restrict__ tasks, uint32_t bpt) {
+  const uint32_t gi = blockIdx.x / bpt, b = blockIdx.x % bpt;
+  const ThrGroup G = groups[gi];
+  const float* col = kb.data + (size_t)G.prop * kb.N;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (uint32_t w = b * 4 + wv; w < kb.W; w += bpt * 4) {
     const uint32_t x = w * 64 + lane;
-    bool v = false;
-    if (x < kb.N) {
-      const float f = col[x];
-      v = T.le ? (f <= T.t) : (f >= T.t);   // NaN (no value) compares false
+    const bool in = x < kb.N;
+    const float f = in ? col[x] : 0.0f;
+    for (uint32_t i = 0; i < G.n; ++i) {
+      const ThrTask T = tasks[G.first + i];
+      const bool v = in && (T.le ? (f <= T.t) : (f >= T.t));   // NaN (no value) compares false
+      const uint64_t m = __ballot(v);
+      if (lane == 0) out_ptr(kb, T.out_row)[w] = m;
     }
-    const uint64_t m = __ballot(v);
-    if (lane == 0) out[w] = m;
   }
 }
 
@@ -302,7 +304,36 @@ inline uint64_t t_rows(const hth_kb_s& kb, const GroupTask& g) {
 struct GroupChunk {
   size_t first;
   uint32_t n, wb;
+  uint32_t rounds;     // XCD-local: rounds of the slot table (0 = chip-wide launch)
+  size_t slot_off;     // its first entry in the plan's slot table
 };
+// XCD-local placement of a chunk's groups: longest first onto the least loaded
+// XCD (cost ~ assertions + 64 per visited word); slot (round, xcd) -> group.
+void place_on_xcds(const hth_kb_s& kb, const std::vector<GroupTask>& gs, GroupChunk& c,
+                   std::vector<uint32_t>& xslots) {
+  std::vector<std::pair<double, uint32_t>> cost;
+  for (uint32_t i = 0; i < c.n; ++i) {
+    const GroupTask& g = gs[c.first + i];
+    const double e = (double)(kb.role_base[g.role + 1] - kb.role_base[g.role]);
+    cost.push_back({e + 64.0 * kb.n_words[2 * g.role + g.inv], i});
+  }
+  std::stable_sort(cost.begin(), cost.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+  double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  std::vector<uint32_t> per[8];
+  for (const auto& [w, i] : cost) {
+    const int x = (int)(std::min_element(load, load + 8) - load);
+    load[x] += w;
+    per[x].push_back(i);
+  }
+  size_t rounds = 0;
+  for (int x = 0; x < 8; ++x) rounds = std::max(rounds, per[x].size());
+  c.rounds = (uint32_t)rounds;
+  c.slot_off = xslots.size();
+  xslots.resize(xslots.size() + rounds * 8, kNone);
+  for (int x = 0; x < 8; ++x)
+    for (size_t r = 0; r < per[x].size(); ++r) xslots[c.slot_off + r * 8 + x] = per[x][r];
+}
+
 std::vector<GroupChunk> chunk_groups(const hth_kb_s& kb, std::vector<GroupTask>& gs) {
   std::vector<GroupChunk> out;
   size_t i = 0;
@@ -322,7 +353,7 @@ std::vector<GroupChunk> chunk_groups(const hth_kb_s& kb, std::vector<GroupTask>&
       gs[q].t_off = off;
       off += t_rows(kb, gs[q]);
     }
-    out.push_back({i, (uint32_t)(j - i), wb});
+    out.push_back({i, (uint32_t)(j - i), wb, 0, 0});
     i = j;
   }
   return out;
@@ -345,11 +376,14 @@ size_t table_bound(uint32_t max_nodes, uint32_t max_hyps) {
   const size_t n = max_nodes + 2;
   size_t b = 0;
   b += align_up(n * sizeof(ThrTask), 256);
+  b += align_up(n * sizeof(ThrGroup), 256);
   b += align_up((n + max_hyps) * sizeof(RegionTask), 256);
   b += align_up(n * sizeof(RoleTask), 256);
   b += align_up(n * sizeof(GroupTask), 256);
   b += align_up(n * sizeof(GroupMember), 256);
+  b += align_up(n * sizeof(FillTask), 256);
   b += align_up((4 * n + 16) * sizeof(uint32_t), 256);
+  b += align_up((9 * n + 8) * sizeof(uint32_t), 256);     // XCD slot tables
   return b + 4096;
 }
 
@@ -491,8 +525,10 @@ hth_status launch_roles(Launcher& L, const DevKB& d, const RoleTask* tasks,
 template <typename TW>
 hth_status launch_group_chunk(Launcher& L, const DevKB& d, const GroupTask* groups,
                               const GroupMember* members, const std::vector<GroupTask>& host,
-                              size_t g0, uint32_t n, void* tarea) {
+                              const GroupChunk& c, const uint32_t* xslots_all, void* tarea) {
   const hth_kb_s& kb = L.kb;
+  const size_t g0 = c.first;
+  const uint32_t n = c.n;
   double tb = 0, gb = 0;
   for (uint32_t i = 0; i < n; ++i) {
     const GroupTask& G = host[g0 + i];
@@ -507,46 +543,48 @@ hth_status launch_group_chunk(Launcher& L, const DevKB& d, const GroupTask* grou
                        T, tiles);
   });
   if (s) return s;
-  const uint32_t xcd = kb.tune.xcd_local && n >= 8;
+  const uint32_t* xslots = c.rounds ? xslots_all + c.slot_off : nullptr;
   uint32_t bpg, nblocks;
-  if (xcd) {
+  if (xslots) {
     bpg = std::min<uint32_t>(std::max<uint32_t>(1, kb.n_cu / 8 * 8), (kb.W + 3) / 4);
-    nblocks = 8 * bpg * ((n + 7) / 8);
+    nblocks = 8 * bpg * c.rounds;
   } else {
     bpg = std::max<uint32_t>(1, (8 * kb.n_cu + n - 1) / n);
     bpg = std::min<uint32_t>(bpg, (kb.W + 3) / 4);
     nblocks = bpg * n;
   }
+  // several list words per wave iteration where words hold few assertions
+  double ew = 0, nwd = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    const GroupTask& G = host[g0 + i];
+    ew += (double)(kb.role_base[G.role + 1] - kb.role_base[G.role]);
+    nwd += G.n_words;
+  }
+  const bool multi = nwd > 0 && ew < 96.0 * nwd;
   return L.run(HTH_K_GROUP, gb, [&] {
     const dim3 grid(nblocks), block(256);
-    if (kb.tune.group_unroll >= 16) {
-      if (kb.tune.nontemporal)
-        hipLaunchKernelGGL((k_group<TW, 16, true>), grid, block, 0, L.st, d, groups + g0, members, T,
-                           bpg, n, xcd);
-      else
-        hipLaunchKernelGGL((k_group<TW, 16, false>), grid, block, 0, L.st, d, groups + g0, members, T,
-                           bpg, n, xcd);
+    const bool u16 = kb.tune.group_unroll >= 16;
+    if (multi) {   // few assertions per lane: 8 in flight
+      hipLaunchKernelGGL((k_group<TW, 8, 4>), grid, block, 0, L.st, d, groups + g0, members, T, bpg, xslots);
     } else {
-      if (kb.tune.nontemporal)
-        hipLaunchKernelGGL((k_group<TW, 8, true>), grid, block, 0, L.st, d, groups + g0, members, T,
-                           bpg, n, xcd);
+      if (u16)
+        hipLaunchKernelGGL((k_group<TW, 16, 1>), grid, block, 0, L.st, d, groups + g0, members, T, bpg, xslots);
       else
-        hipLaunchKernelGGL((k_group<TW, 8, false>), grid, block, 0, L.st, d, groups + g0, members, T,
-                           bpg, n, xcd);
+        hipLaunchKernelGGL((k_group<TW, 8, 1>), grid, block, 0, L.st, d, groups + g0, members, T, bpg, xslots);
     }
   });
 }
 
 hth_status launch_groups(Launcher& L, const DevKB& d, const GroupTask* groups,
                          const GroupMember* members, const std::vector<GroupTask>& host,
-                         const std::vector<GroupChunk>& chunks, void* tarea) {
+                         const std::vector<GroupChunk>& chunks, const uint32_t* xslots, void* tarea) {
   for (const GroupChunk& c : chunks) {
     hth_status s;
     switch (c.wb) {
-      case 1: s = launch_group_chunk<uint8_t>(L, d, groups, members, host, c.first, c.n, tarea); break;
-      case 2: s = launch_group_chunk<uint16_t>(L, d, groups, members, host, c.first, c.n, tarea); break;
-      case 4: s = launch_group_chunk<uint32_t>(L, d, groups, members, host, c.first, c.n, tarea); break;
-      default: s = launch_group_chunk<uint64_t>(L, d, groups, members, host, c.first, c.n, tarea); break;
+      case 1: s = launch_group_chunk<uint8_t>(L, d, groups, members, host, c, xslots, tarea); break;
+      case 2: s = launch_group_chunk<uint16_t>(L, d, groups, members, host, c, xslots, tarea); break;
+      case 4: s = launch_group_chunk<uint32_t>(L, d, groups, members, host, c, xslots, tarea); break;
+      default: s = launch_group_chunk<uint64_t>(L, d, groups, members, host, c, xslots, tarea); break;
     }
     if (s) return s;
   }
@@ -567,12 +605,14 @@ size_t plan_workspace_bytes(const hth_kb_s& kb, const Plan& P) {
     max_groups = std::max(max_groups, PL.groups.size());
   }
   add(P.thr.size(), sizeof(ThrTask));
+  add(P.thr.size(), sizeof(ThrGroup));
   add(n_reg, sizeof(RegionTask));
   add(n_role, sizeof(RoleTask));
   add(n_grp, sizeof(GroupTask));
   add(n_mem, sizeof(GroupMember));
   add(n_fill, sizeof(FillTask));
   add(P.code.size(), sizeof(uint32_t));
+  add(9 * n_grp + 8, sizeof(uint32_t));     // XCD slot tables: at most 8 more than groups per chunk
   return align_up(tables, 256) + (size_t)P.n_slots * kb.S * 8 + (max_groups ? t_area_bytes(kb) : 0);
 }
 
@@ -594,6 +634,7 @@ hth_status run_plan(hth_kb_s& kb, const Plan& P, char* ws, size_t ws_bytes, uint
   std::vector<std::vector<RoleTask>> lv_roles(P.levels.size());
   std::vector<std::vector<GroupTask>> lv_groups(P.levels.size());
   std::vector<std::vector<GroupChunk>> lv_chunks(P.levels.size());
+  std::vector<uint32_t> xslots;
   for (size_t L = 0; L < P.levels.size(); ++L) {
     const PlanLevel& PL = P.levels[L];
     at[L] = {regions.size(), roles.size(), groups.size(), fills.size(), 0, 0, 0};
@@ -615,6 +656,8 @@ hth_status run_plan(hth_kb_s& kb, const Plan& P, char* ws, size_t ws_bytes, uint
       lv_groups[L].push_back(g);
     }
     lv_chunks[L] = chunk_groups(kb, lv_groups[L]);
+    for (GroupChunk& c : lv_chunks[L])
+      if (kb.tune.xcd_local && c.n >= 8) place_on_xcds(kb, lv_groups[L], c, xslots);
     groups.insert(groups.end(), lv_groups[L].begin(), lv_groups[L].end());
     members.insert(members.end(), PL.members.begin(), PL.members.end());
     at[L].nrole = roles.size() - at[L].role;
@@ -624,13 +667,25 @@ hth_status run_plan(hth_kb_s& kb, const Plan& P, char* ws, size_t ws_bytes, uint
   const size_t root_at = regions.size();
   regions.insert(regions.end(), P.roots.begin(), P.roots.end());
   Blob blob;
-  const size_t o_thr = blob.add(P.thr);
+  // thresholds grouped by property (at most 32 per group): one column pass each
+  std::vector<ThrTask> thr_tasks(P.thr);
+  std::stable_sort(thr_tasks.begin(), thr_tasks.end(),
+                   [](const ThrTask& a, const ThrTask& b) { return a.prop < b.prop; });
+  std::vector<ThrGroup> thr_groups;
+  for (uint32_t i = 0; i < thr_tasks.size(); ++i) {
+    if (thr_groups.empty() || thr_groups.back().prop != thr_tasks[i].prop || thr_groups.back().n == 32)
+      thr_groups.push_back(ThrGroup{thr_tasks[i].prop, i, 0, 0});
+    thr_groups.back().n++;
+  }
+  const size_t o_thr = blob.add(thr_tasks);
+  const size_t o_thg = blob.add(thr_groups);
   const size_t o_reg = blob.add(regions);
   const size_t o_role = blob.add(roles);
   const size_t o_grp = blob.add(groups);
   const size_t o_mem = blob.add(members);
   const size_t o_fill = blob.add(fills);
   const size_t o_code = blob.add(P.code);
+  const size_t o_xslot = blob.add(xslots);
   const size_t tables = align_up(blob.bytes.size(), 256);
   const size_t slot_bytes = (size_t)kb.S * 8;
   size_t max_groups = 0;
@@ -649,28 +704,10 @@ hth_status run_plan(hth_kb_s& kb, const Plan& P, char* ws, size_t ws_bytes, uint
   d.counts = counts;
   d.instances = instances;
   void* tarea = ws + tables + (size_t)P.n_slots * slot_bytes;
-  {
-    hth_kb_s::Staging& sg = kb.stage[kb.stage_next++ % 4];
-    if (sg.pending) HTH_HIP(hipEventSynchronize(sg.done));
-    sg.pending = false;
-    const size_t nb = blob.bytes.size();
-    if (sg.cap < nb) {
-      if (sg.host) HTH_HIP(hipHostFree(sg.host));
-      sg.host = nullptr;
-      sg.cap = 0;
-      size_t cap = 64 << 10;
-      while (cap < nb) cap <<= 1;
-      HTH_HIP(hipHostMalloc(&sg.host, cap, hipHostMallocDefault));
-      sg.cap = cap;
-    }
-    if (!sg.done) HTH_HIP(hipEventCreateWithFlags(&sg.done, hipEventDisableTiming));
-    std::memcpy(sg.host, blob.bytes.data(), nb);
-    HTH_HIP(hipMemcpyAsync(ws, sg.host, nb, hipMemcpyHostToDevice, st));
-    HTH_HIP(hipEventRecord(sg.done, st));
-    sg.pending = true;
-  }
+  HTH_HIP(hipMemcpyAsync(ws, blob.bytes.data(), blob.bytes.size(), hipMemcpyHostToDevice, st));
   HTH_HIP(hipMemsetAsync(counts, 0, (size_t)n_hyps * 8, st));
   const ThrTask* thr = reinterpret_cast<const ThrTask*>(ws + o_thr);
+  const ThrGroup* thg = reinterpret_cast<const ThrGroup*>(ws + o_thg);
   const RegionTask* reg = reinterpret_cast<const RegionTask*>(ws + o_reg);
   const RoleTask* rol = reinterpret_cast<const RoleTask*>(ws + o_role);
   const GroupTask* grp = reinterpret_cast<const GroupTask*>(ws + o_grp);
@@ -678,13 +715,13 @@ hth_status run_plan(hth_kb_s& kb, const Plan& P, char* ws, size_t ws_bytes, uint
   const FillTask* fil = reinterpret_cast<const FillTask*>(ws + o_fill);
   const uint32_t* code = reinterpret_cast<const uint32_t*>(ws + o_code);
   Launcher Lc{kb, st};
-  if (!P.thr.empty()) {
-    const uint32_t n = (uint32_t)P.thr.size();
+  if (!thr_groups.empty()) {
+    const uint32_t n = (uint32_t)thr_groups.size();
     uint32_t bpt = std::max<uint32_t>(1, (4 * kb.n_cu + n - 1) / n);
     bpt = std::min<uint32_t>(bpt, (kb.W + 3) / 4);
-    const double bytes = n * (4.0 * kb.N + 8.0 * kb.W);
+    const double bytes = n * 4.0 * kb.N + thr_tasks.size() * 8.0 * kb.W;
     hth_status s = Lc.run(HTH_K_THRESHOLD, bytes, [&] {
-      hipLaunchKernelGGL(k_threshold, dim3(bpt * n), dim3(256), 0, st, d, thr, bpt);
+      hipLaunchKernelGGL(k_threshold, dim3(bpt * n), dim3(256), 0, st, d, thg, thr, bpt);
     });
     if (s) return s;
   }
@@ -701,7 +738,8 @@ hth_status run_plan(hth_kb_s& kb, const Plan& P, char* ws, size_t ws_bytes, uint
     }
     s = launch_roles(Lc, d, rol + at[L].role, lv_roles[L]);
     if (s) return s;
-    s = launch_groups(Lc, d, grp + at[L].group, mem, lv_groups[L], lv_chunks[L], tarea);
+    s = launch_groups(Lc, d, grp + at[L].group, mem, lv_groups[L], lv_chunks[L],
+                      reinterpret_cast<const uint32_t*>(ws + o_xslot), tarea);
     if (s) return s;
   }
   return launch_regions(Lc, d, reg + root_at, code, P.roots, P.code);

@@ -118,33 +118,48 @@ __device__ __forceinline__ uint64_t wave_transpose64(uint64_t x, int lane) {
   return x;
 }
 
-// One wave per 64 subjects (one word of every member's output row), all members
-// of the group at once.  The word's assertions are cut into 64 contiguous
-// slices of ceil(E_w / 64), one per lane (balanced whatever the degrees); a lane
-// walks its slice, fetches each object's T row (one load serves every member)
-// and adds it into bit-sliced counters, closing a row's counters when the row
-// ends.  Rows that straddle slices leave a tail partial in each lane they cross;
-// one segmented scan over the lanes adds them up for the lane holding the row's
-// last assertion.  Finally lane x evaluates every member's predicate for
-// subject x from the acceptance masks and the result is transposed by ballots.
-template <typename TW, int U, bool NT>   // U: assertions in flight per lane;
-                                          // NT: stream the CSR past the caches
+// The members' acceptance of a count held in bit-sliced planes: bit j of the
+// result = member j accepts the count of its bit j.
+template <typename TW>
+__device__ __forceinline__ TW accept(const Planes<TW>& p, const TW (&acc)[kGroupMaxCount + 1]) {
+  const TW c0 = p.c0, c1 = p.c1, c2 = p.c2;
+  const TW n0 = ~c0, n1 = ~c1, n2 = ~c2;
+  const TW res = (n2 & n1 & n0 & acc[0]) | (n2 & n1 & c0 & acc[1]) | (n2 & c1 & n0 & acc[2]) |
+                 (n2 & c1 & c0 & acc[3]) | (c2 & n1 & n0 & acc[4]) | (c2 & n1 & c0 & acc[5]) |
+                 (c2 & c1 & n0 & acc[6]) | (c2 & c1 & c0 & acc[7]);
+  return (res & ~p.ov) | (p.ov & acc[8]);
+}
+
+// One wave per MW consecutive entries of the direction's non-empty word list
+// (64 MW subjects: one word of every member's output row per entry), all
+// members of the group at once.  Words between two list entries hold no
+// assertions, so the entries' assertions are one contiguous range; it is cut
+// into 64 contiguous slices of ceil(E / 64), one per lane (balanced whatever
+// the degrees).  A lane walks its slice, fetches each object's T row (one load
+// serves every member) and adds it into bit-sliced counters; a row complete in
+// the slice has its acceptance written to LDS at once.  Rows that straddle
+// slices leave a tail partial in each lane they cross; one segmented scan over
+// the lanes adds them up for the lane holding the row's last assertion.
+// Finally each word's acceptances are transposed by a wave butterfly into one
+// word per member.  MW > 1 serves directions with few assertions per word.
+template <typename TW, int U, int MW>   // U: assertions in flight per lane
 __global__ void __launch_bounds__(256)
 k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __restrict__ members,
-        const TW* __restrict__ tarea, uint32_t bpg, uint32_t n_groups,
-        uint32_t xcd_local) {
-  constexpr uint32_t kStage = 1024;   // assertions of a word staged in LDS
-  __shared__ uint32_t s_ro[4][65];
-  __shared__ TW s_fin[4][4][64];
+        const TW* __restrict__ tarea, uint32_t bpg, const uint32_t* __restrict__ xslots) {
+  constexpr uint32_t kStage = 1024;   // assertions of an iteration staged in LDS
+  constexpr int R = 64 * MW;          // subjects per iteration
+  __shared__ uint32_t s_ro[4][R + 1];
+  __shared__ TW s_res[4][R];
   __shared__ int32_t s_tg[4][kStage];
   uint32_t g, b;
-  if (xcd_local) {
+  if (xslots) {
     // workgroups are dealt to the 8 XCDs round robin: keep every block of a
-    // group on one XCD so that its L2 serves that group's T rows
+    // group on one XCD so that its L2 serves that group's T rows.  xslots
+    // lists each XCD's groups round by round (balanced on the host).
     const uint32_t x = blockIdx.x & 7, j = blockIdx.x >> 3;
-    g = x + 8 * (j / bpg);
+    g = xslots[(j / bpg) * 8 + x];
     b = j % bpg;
-    if (g >= n_groups) return;
+    if (g == kNone) return;
   } else {
     g = blockIdx.x / bpg;
     b = blockIdx.x % bpg;
@@ -159,44 +174,65 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
                       kb.role_base[G->role];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   uint32_t* ro = s_ro[wv];
-  TW(*fin)[64] = s_fin[wv];
+  TW* res = s_res[wv];
   TW acc[kGroupMaxCount + 1];
 #pragma unroll
   for (int v = 0; v <= (int)kGroupMaxCount; ++v) acc[v] = (TW)G->acc[v];
+  const TW res0 = accept(Planes<TW>{0, 0, 0, 0}, acc);
   const uint32_t nw = blockDim.x >> 6;
-  const uint32_t wstep = bpg * nw;
+  const uint32_t istep = bpg * nw;
   const uint32_t* words = kb.words + (size_t)(2 * G->role + G->inv) * kb.W;
   const uint32_t n_words = G->n_words;
-  uint32_t i = b * nw + wv;
-  uint32_t olo_n = 0, ohi_n = 0;     // row offsets of the wave's next word, fetched ahead
-  if (i < n_words) {
-    const uint32_t xn = words[i] * 64 + lane;
-    olo_n = off[xn < kb.N ? xn : kb.N];
-    ohi_n = xn < kb.N ? off[xn + 1] : olo_n;
-  }
-  for (; i < n_words; i += wstep) {
-    const uint32_t w = words[i];
-    const uint32_t x = w * 64 + lane;
-    const bool in = x < kb.N;
-    const uint32_t olo = olo_n, ohi = ohi_n;
-    if (i + wstep < n_words) {
-      const uint32_t xn = words[i + wstep] * 64 + lane;
-      olo_n = off[xn < kb.N ? xn : kb.N];
-      ohi_n = xn < kb.N ? off[xn + 1] : olo_n;
+  const uint32_t n_iter = (n_words + MW - 1) / MW;
+  // row offsets of the wave's next iteration, fetched ahead
+  uint32_t lo_n[MW], hi_n[MW], w_n[MW];
+  auto fetch = [&](uint32_t it) {
+#pragma unroll
+    for (int m = 0; m < MW; ++m) {
+      const uint32_t idx = it * MW + m;
+      w_n[m] = kNone;
+      lo_n[m] = hi_n[m] = 0;
+      if (it < n_iter && idx < n_words) {
+        const uint32_t w = words[idx], x = w * 64 + lane;
+        w_n[m] = w;
+        lo_n[m] = off[x < kb.N ? x : kb.N];
+        hi_n[m] = x < kb.N ? off[x + 1] : lo_n[m];
+      }
     }
-    ro[lane] = olo;
-    if (lane == 63) ro[64] = ohi;
-    fin[0][lane] = fin[1][lane] = fin[2][lane] = fin[3][lane] = 0;
+  };
+  uint32_t it = b * nw + wv;
+  fetch(it);
+  for (; it < n_iter; it += istep) {
+    uint32_t lo[MW], hi[MW], wd[MW];
+#pragma unroll
+    for (int m = 0; m < MW; ++m) {
+      lo[m] = lo_n[m];
+      hi[m] = hi_n[m];
+      wd[m] = w_n[m];
+    }
+    fetch(it + istep);
+    const uint32_t mc = min((uint32_t)MW, n_words - it * MW);   // words in this iteration
+    const uint32_t nr = 64 * mc;
+#pragma unroll
+    for (int m = 0; m < MW; ++m)
+      if ((uint32_t)m < mc) {
+        ro[64 * m + lane] = lo[m];
+        res[64 * m + lane] = res0;
+      }
+    uint32_t hi_last = hi[0];
+#pragma unroll
+    for (int m = 1; m < MW; ++m)
+      if ((uint32_t)m < mc) hi_last = hi[m];
+    if (lane == 63) ro[nr] = hi_last;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const uint32_t E0 = (uint32_t)__shfl((int)olo, 0, 64);
-    const uint32_t E1 = (uint32_t)__shfl((int)ohi, 63, 64);
+    const uint32_t E0 = ro[0], E1 = ro[nr];
     const uint32_t S = (E1 - E0 + 63) >> 6;
     const uint32_t s = E0 + lane * S;
     const uint32_t se = min(s + S, E1);
-    // the word's targets, loaded coalesced into LDS when they fit; lanes then
-    // read their contiguous slices from there
+    // the iteration's targets, loaded coalesced into LDS when they fit; lanes
+    // then read their contiguous slices from there
     int32_t* stg = s_tg[wv];
     const bool staged = E1 - E0 <= kStage;
     if (staged) {
@@ -209,21 +245,18 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
     Planes<TW> cur{0, 0, 0, 0}, hp{0, 0, 0, 0}, tp{0, 0, 0, 0};
     int hp_row = -1, key = -2 - lane;
     if (s < se) {
+      // the row holding assertion s: the last r with ro[r] <= s
       int r = 0;
 #pragma unroll
-      for (int step = 32; step; step >>= 1)
-        if (r + step <= 63 && ro[r + step] <= s) r += step;
+      for (int step = R / 2; step; step >>= 1)
+        if (r + step < (int)nr && ro[r + step] <= s) r += step;
       bool head = ro[r] < s;
       uint32_t rend = ro[r + 1];
       for (uint32_t e0 = s; e0 < se; e0 += U) {
         int32_t t[U];
         TW v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-          t[u] = (e0 + u < se)
-                     ? (staged ? stg[e0 + u - E0]
-                               : (NT ? __builtin_nontemporal_load(tg + e0 + u) : tg[e0 + u]))
-                     : 0;
+        for (int u = 0; u < U; ++u) t[u] = (e0 + u < se) ? (staged ? stg[e0 + u - E0] : tg[e0 + u]) : 0;
 #pragma unroll
         for (int u = 0; u < U; ++u) v[u] = (e0 + u < se) ? T[(uint32_t)t[u]] : (TW)0;
 #pragma unroll
@@ -235,10 +268,7 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
                 hp = cur;
                 hp_row = r;
               } else {
-                fin[0][r] = cur.c0;
-                fin[1][r] = cur.c1;
-                fin[2][r] = cur.c2;
-                fin[3][r] = cur.ov;
+                res[r] = accept(cur, acc);
               }
               cur = Planes<TW>{0, 0, 0, 0};
               head = false;
@@ -256,10 +286,7 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
         hp = cur;
         hp_row = r;
       } else {
-        fin[0][r] = cur.c0;
-        fin[1][r] = cur.c1;
-        fin[2][r] = cur.c2;
-        fin[3][r] = cur.ov;
+        res[r] = accept(cur, acc);
       }
     }
     // segmented inclusive scan of the tail partials, keyed by row; stops once no
@@ -275,25 +302,22 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
       const Planes<TW> pp = planes_shfl_up(tp, 1);
       if (hp_row >= 0) {
         if (lane > 0 && pk == hp_row) planes_add(hp, pp);
-        fin[0][hp_row] = hp.c0;
-        fin[1][hp_row] = hp.c1;
-        fin[2][hp_row] = hp.c2;
-        fin[3][hp_row] = hp.ov;
+        res[hp_row] = accept(hp, acc);
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // predicate of every member for subject x
-    const TW c0 = fin[0][lane], c1 = fin[1][lane], c2 = fin[2][lane], ov = fin[3][lane];
-    const TW n0 = ~c0, n1 = ~c1, n2 = ~c2;
-    TW res = (n2 & n1 & n0 & acc[0]) | (n2 & n1 & c0 & acc[1]) | (n2 & c1 & n0 & acc[2]) |
-             (n2 & c1 & c0 & acc[3]) | (c2 & n1 & n0 & acc[4]) | (c2 & n1 & c0 & acc[5]) |
-             (c2 & c1 & n0 & acc[6]) | (c2 & c1 & c0 & acc[7]);
-    res = (res & ~ov) | (ov & acc[8]);
-    if (!in) res = 0;
-    const uint64_t mine = wave_transpose64((uint64_t)res, lane);
-    if ((uint32_t)lane < k) out_ptr(kb, members[G->first + lane].out_row)[w] = mine;
+    // each word: every member's predicate for subject 64 w + lane, transposed
+#pragma unroll
+    for (int m = 0; m < MW; ++m) {
+      if ((uint32_t)m < mc) {
+        TW rv = res[64 * m + lane];
+        if (wd[m] * 64 + lane >= kb.N) rv = 0;
+        const uint64_t mine = wave_transpose64((uint64_t)rv, lane);
+        if ((uint32_t)lane < k) out_ptr(kb, members[G->first + lane].out_row)[wd[m]] = mine;
+      }
+    }
     __builtin_amdgcn_wave_barrier();
   }
 }

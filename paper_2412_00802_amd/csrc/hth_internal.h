@@ -50,6 +50,14 @@ struct ThrTask {
   uint32_t out_row;
 };
 
+// The thresholds on one property, tasks[first .. first + n) (n <= 32).
+struct ThrGroup {
+  uint32_t prop;
+  uint32_t first;
+  uint32_t n;
+  uint32_t pad;
+};
+
 // One role restriction over one CSR direction, evaluated alone (k = 1).
 //   cnt(x) = #{y in succ(x) : bit(child, y) ^ neg};  result = lo <= cnt <= hi
 //   counting may stop at `sat` (every predicate is decided once cnt >= sat).
@@ -172,22 +180,7 @@ struct hth_kb_s {
   bool prof = false;
   std::vector<ProfRec> prof_recs;
   std::vector<hipEvent_t> event_pool;
-  // pinned staging ring for the plan tables: the copy to the device runs
-  // asynchronously from pinned memory; a slot is reused once its copy is done
-  struct Staging {
-    void* host = nullptr;
-    size_t cap = 0;
-    hipEvent_t done = nullptr;
-    bool pending = false;
-  };
-  Staging stage[4];
-  uint32_t stage_next = 0;
   ~hth_kb_s() {
-    for (Staging& s : stage) {
-      if (s.pending) (void)hipEventSynchronize(s.done);
-      if (s.done) (void)hipEventDestroy(s.done);
-      if (s.host) (void)hipHostFree(s.host);
-    }
     for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
   }
   // schedule choices of the batched executor (defaults, environment overrides
@@ -196,9 +189,8 @@ struct hth_kb_s {
     uint32_t group_min = 4;      // smallest (role, dir, level) bucket run as shared passes
     uint32_t group_k = 64;       // most role nodes per shared pass (T row width)
     uint32_t xcd_local = 1;      // 1: all blocks of a shared pass on one XCD
-    size_t t_budget = 64ull << 20;  // bytes of T rows resident per launch
-    uint32_t group_unroll = 16;  // assertions in flight per lane in a shared pass
-    uint32_t nontemporal = 0;    // 1: CSR targets loaded with the streaming hint
+    size_t t_budget = 64ull << 20;   // bytes of T rows resident per launch
+    uint32_t group_unroll = 16;  // assertions in flight per lane in a dense shared pass
     uint32_t region_reg = 1;     // 1: register-stack region kernel where programs fit
     uint32_t t_compact = 1;      // 1: T rows of objects only where they are <= N/2
   } tune;

@@ -284,38 +284,51 @@ k_object_rank(const int32_t* __restrict__ tg, uint64_t e0, uint64_t n, const uin
 }
 
 struct DerivedLayout {
-  size_t fwd_off, inv_off, inv_tg, cursor, bsum, base, meta, words, objmask, objbase, ctg, total;
+  size_t fwd_off, inv_off, inv_tg, cursor, bsum, base, meta, words, wbase, objmask, objbase, ctg, total;
   uint32_t nb;
 };
 
 // Words (64 consecutive subjects) with at least one assertion, per role and
-// direction: the role passes visit only these.  One block per 256 words; each
-// block appends its non-empty words (in order) at an atomically reserved spot,
-// so the list order across blocks is not fixed (results do not depend on it).
+// direction, in increasing order: the role passes visit only these, and a
+// pass may take several consecutive entries at once (their assertions form
+// one contiguous range).  Three steps per list: per-block counts (256 words a
+// block), an exclusive scan of the block counts, then each block writes its
+// words at its scanned base.
+__device__ __forceinline__ bool word_nonempty(const uint32_t* __restrict__ o, uint32_t N, uint32_t W,
+                                              uint32_t w) {
+  if (w >= W) return false;
+  const uint32_t a = w * 64, b = min(a + 64, N);
+  return o[b] != o[a];
+}
+
 __global__ void __launch_bounds__(256)
-k_nonempty_words(const uint32_t* __restrict__ off, uint32_t N, uint32_t W, uint32_t* __restrict__ list,
+k_nonempty_count(const uint32_t* __restrict__ o, uint32_t N, uint32_t W, uint32_t* __restrict__ bcnt,
                  uint32_t* __restrict__ count) {
-  __shared__ uint32_t wsum[4], base;
-  const uint32_t dir_role = blockIdx.y;                 // 2 * role + direction
-  const uint32_t* o = off + (size_t)dir_role * (N + 1);
+  __shared__ uint32_t wsum[4];
   const uint32_t w = blockIdx.x * 256 + threadIdx.x;
-  bool ne = false;
-  if (w < W) {
-    const uint32_t a = w * 64, b = min(a + 64, N);
-    ne = o[b] != o[a];
+  const uint64_t m = __ballot(word_nonempty(o, N, W, w));
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = (uint32_t)__popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    bcnt[blockIdx.x] = tot;
+    if (tot) atomicAdd(count, tot);
   }
+}
+
+__global__ void __launch_bounds__(256)
+k_nonempty_words(const uint32_t* __restrict__ o, uint32_t N, uint32_t W, const uint32_t* __restrict__ bbase,
+                 uint32_t* __restrict__ list) {
+  __shared__ uint32_t wsum[4];
+  const uint32_t w = blockIdx.x * 256 + threadIdx.x;
+  const bool ne = word_nonempty(o, N, W, w);
   const uint64_t m = __ballot(ne);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (lane == 0) wsum[wv] = (uint32_t)__popcll(m);
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-    base = tot ? atomicAdd(count + dir_role, tot) : 0;
-  }
-  __syncthreads();
-  uint32_t before = base;
+  uint32_t before = bbase[blockIdx.x];
   for (int i = 0; i < wv; ++i) before += wsum[i];
-  if (ne) list[(size_t)dir_role * W + before + (uint32_t)__popcll(m & ((1ull << lane) - 1))] = w;
+  if (ne) list[before + (uint32_t)__popcll(m & ((1ull << lane) - 1))] = w;
 }
 
 static DerivedLayout layout_for(const hth_kb_desc& d) {
@@ -332,6 +345,7 @@ static DerivedLayout layout_for(const hth_kb_desc& d) {
   L.base = at; at += align_up((R + 1) * 8, 256);
   L.meta = at; at += align_up((4 + 4 * R) * 4, 256);
   L.words = at; at += align_up(2 * R * ((N + 63) / 64) * 4, 256);
+  L.wbase = at; at += align_up(2 * R * (((N + 63) / 64 + 255) / 256) * 4, 256);
   L.objmask = at; at += align_up(2 * R * ((N + 63) / 64) * 8, 256);
   L.objbase = at; at += align_up(2 * R * ((N + 63) / 64 + 1) * 4, 256);
   L.ctg = at; at += align_up((size_t)d.n_edges * 8, 256);     // both directions
@@ -453,12 +467,17 @@ static hth_status kb_build(hth_kb_s* kb, char* derived, hipStream_t st) {
     uint32_t* words = reinterpret_cast<uint32_t*>(derived + L.words);
     uint32_t* wcount = meta + 4 + 2 * R;                  // [R][2]
     kb->words = words;
+    const uint32_t nwb = (kb->W + 255) / 256;
+    uint32_t* wbase = reinterpret_cast<uint32_t*>(derived + L.wbase);
     for (int dir = 0; dir < 2; ++dir) {
       const uint32_t* off = dir ? kb->inv_off : kb->fwd_off;
       for (uint32_t r = 0; r < R; ++r) {
-        hipLaunchKernelGGL(k_nonempty_words, dim3((kb->W + 255) / 256, 1), dim3(256), 0, st,
-                           off + (size_t)r * (N + 1), N, kb->W,
-                           words + (size_t)(2 * r + dir) * kb->W, wcount + 2 * r + dir);
+        const uint32_t* o = off + (size_t)r * (N + 1);
+        uint32_t* bb = wbase + (size_t)(2 * r + dir) * nwb;
+        hipLaunchKernelGGL(k_nonempty_count, dim3(nwb), dim3(256), 0, st, o, N, kb->W, bb, wcount + 2 * r + dir);
+        hipLaunchKernelGGL(k_scan_block_sums, dim3(1), dim3(kScanThreads), 0, st, bb, nwb);
+        hipLaunchKernelGGL(k_nonempty_words, dim3(nwb), dim3(256), 0, st, o, N, kb->W, bb,
+                           words + (size_t)(2 * r + dir) * kb->W);
       }
     }
     HTH_HIP(hipGetLastError());
@@ -538,7 +557,6 @@ extern "C" hth_status hth_kb_create(const hth_kb_desc* desc, void* derived, size
   kb->tune.xcd_local = (uint32_t)env_u("HTHEDL_XCD", kb->tune.xcd_local);
   kb->tune.t_budget = env_u("HTHEDL_TBUDGET_MB", kb->tune.t_budget >> 20) << 20;
   kb->tune.group_unroll = (uint32_t)env_u("HTHEDL_GROUP_UNROLL", kb->tune.group_unroll);
-  kb->tune.nontemporal = (uint32_t)env_u("HTHEDL_NT", kb->tune.nontemporal);
   kb->tune.region_reg = (uint32_t)env_u("HTHEDL_REGION_REG", kb->tune.region_reg);
   kb->tune.t_compact = (uint32_t)env_u("HTHEDL_T_COMPACT", kb->tune.t_compact);
   kb->lds_per_block = prop.sharedMemPerBlock;

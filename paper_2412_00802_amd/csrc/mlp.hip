@@ -273,13 +273,16 @@ __global__ void k_head_forward(const __bf16* __restrict__ h, int Bn, int Kd, con
   }
 }
 
-// predicted F1 of each candidate from its two logits: p = sigmoid(z0) |P|,
-// q = sigmoid(z1) |Ng|, F1 = 2p / (p + q + |P|)
+// predicted F1 of each candidate from its two logits: p = sigmoid(z0) P_b,
+// q = sigmoid(z1) N_b, F1 = 2p / (p + q + |P|), where (P_b, N_b) is the
+// candidate's base coverage (its parent's, when the logits predict the share
+// of the parent's coverage it keeps) or (|P|, |Ng|)
 __global__ void k_head_score(const float* __restrict__ z, int Bn, float n_pos, float n_neg,
-                             float* __restrict__ score) {
+                             const uint32_t* __restrict__ base, float* __restrict__ score) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= Bn) return;
-  const float p = n_pos / (1.f + expf(-z[2 * b])), q = n_neg / (1.f + expf(-z[2 * b + 1]));
+  const float bp = base ? (float)base[2 * b] : n_pos, bn = base ? (float)base[2 * b + 1] : n_neg;
+  const float p = bp / (1.f + expf(-z[2 * b])), q = bn / (1.f + expf(-z[2 * b + 1]));
   const float den = p + q + n_pos;
   score[b] = den > 0.f ? 2.f * p / den : 0.f;
 }
@@ -469,12 +472,12 @@ extern "C" hth_status hth_head_forward(const uint16_t* h, int Bn, int Kd, const 
   return HTH_OK;
 }
 
-extern "C" hth_status hth_head_score(const float* z, int Bn, float n_pos, float n_neg, float* score,
-                                     void* stream) {
+extern "C" hth_status hth_head_score(const float* z, int Bn, float n_pos, float n_neg, const uint32_t* base,
+                                     float* score, void* stream) {
   if (!z || !score) return fail(HTH_E_INVALID, "NULL argument");
   if (Bn <= 0) return HTH_OK;
   hipLaunchKernelGGL(k_head_score, dim3((Bn + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream),
-                     z, Bn, n_pos, n_neg, score);
+                     z, Bn, n_pos, n_neg, base, score);
   HTH_HIP(hipGetLastError());
   return HTH_OK;
 }

@@ -103,7 +103,7 @@ def lib() -> ctypes.CDLL:
             "hth_gemm_bf16": [I, I, I, I, I, P, I, P, I, P, I, P, I, P, I, P, I, P],
             "hth_head_forward": [P, I, I, P, P, P, P, P, F, P, P],
             "hth_head_backward": [P, I, I, P, P, P, P, P],
-            "hth_head_score": [P, I, F, F, P, P],
+            "hth_head_score": [P, I, F, F, P, P, P],
             "hth_colsum": [P, I, I, I, P, P],
             "hth_adamw": [P, P, P, P, P, S, F, F, F, F, F, I, P],
             "hth_to_bf16": [P, P, S, P],
@@ -293,8 +293,9 @@ def hth_head_forward(h, Bn: int, Kd: int, w, bias, z, y=None, dz=None, scale: fl
                                   scale, _ptr(loss), _stream(stream)))
 
 
-def hth_head_score(z, Bn: int, n_pos: float, n_neg: float, score, stream=None) -> None:
-    _check(lib().hth_head_score(_ptr(z), Bn, n_pos, n_neg, _ptr(score), _stream(stream)))
+def hth_head_score(z, Bn: int, n_pos: float, n_neg: float, score, stream=None, base=None) -> None:
+    _check(lib().hth_head_score(_ptr(z), Bn, n_pos, n_neg, _ptr(base) if base is not None else None,
+                                _ptr(score), _stream(stream)))
 
 
 def hth_head_backward(h, Bn: int, Kd: int, w, dz, dw, dh, stream=None) -> None:

@@ -27,25 +27,32 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def coverage_targets(counts: np.ndarray, n_pos: int, n_neg: int) -> np.ndarray:
+def coverage_targets(counts: np.ndarray, n_pos: int, n_neg: int, base: np.ndarray = None) -> np.ndarray:
+    """Training targets: covered fractions of the examples, or with base (the
+    parents' coverage) the shares of the parent's coverage each child keeps
+    (0 where the parent covers nothing)."""
     c = counts.astype(np.float64)
-    return np.stack([c[:, 0] / max(1, n_pos), c[:, 1] / max(1, n_neg)], 1).astype(np.float32)
+    if base is None:
+        return np.stack([c[:, 0] / max(1, n_pos), c[:, 1] / max(1, n_neg)], 1).astype(np.float32)
+    b = np.asarray(base, dtype=np.float64)
+    return np.where(b > 0, c / np.maximum(b, 1), 0.0).astype(np.float32)
 
 
 def gather_training_pairs(eng, kb, n_pairs, per_round, beam, rng, chunk):
-    """Refinement rounds from top; every candidate is evaluated exactly."""
+    """Refinement rounds from top; every candidate is evaluated exactly.
+    Returns the candidates, their counts and their parents' counts."""
     hyps: List[tuple] = []
-    counts = []
+    counts, parents = [], []
     ev = lambda hs: eng.eval_batch(hs, chunk=chunk)  # noqa: E731
     rounds = (n_pairs + per_round - 1) // per_round
-    last = None
-    for r, cands, cnt in search.refinement_rounds(kb, ev, eng.n_pos, rounds, per_round, beam, rng):
+    for r, cands, cnt, pc in search.refinement_rounds(kb, ev, eng.n_pos, rounds, per_round, beam, rng,
+                                                      start_counts=[eng.n_pos, eng.n_neg], with_parents=True):
         hyps.extend(cands)
         counts.append(cnt)
-        last = (cands, cnt)
+        parents.append(pc)
         log(f"[screen] training round {r}: {len(hyps)} pairs, best F1 "
             f"{search.f1_float(cnt, eng.n_pos).max():.4f}")
-    return hyps[:n_pairs], np.concatenate(counts)[:n_pairs], last
+    return hyps[:n_pairs], np.concatenate(counts)[:n_pairs], np.concatenate(parents)[:n_pairs]
 
 
 def train(scr: Screener, fb: FeatureBatch, y_dev, n: int, epochs: int, batch: int, rng) -> List[float]:
@@ -64,13 +71,16 @@ def train(scr: Screener, fb: FeatureBatch, y_dev, n: int, epochs: int, batch: in
     return losses
 
 
-def score(scr: Screener, fb: FeatureBatch, n: int, n_pos: int, n_neg: int, out) -> None:
+def score(scr: Screener, fb: FeatureBatch, n: int, n_pos: int, n_neg: int, out, base=None) -> None:
+    """Predicted F1 of candidates [0, n); base (device uint32 [n][2]): the
+    parents' coverage when the screener predicts kept shares."""
     B = scr.batch
     for r0 in range(0, n, B):
         m = min(B, n - r0)
         fb.densify(r0, m, scr.x)
         z = scr.logits(m)
-        hthedl.hth_head_score(z, m, float(n_pos), float(n_neg), out[r0:r0 + m])
+        hthedl.hth_head_score(z, m, float(n_pos), float(n_neg), out[r0:r0 + m],
+                              base=None if base is None else base[r0:r0 + m])
 
 
 def main():
@@ -103,22 +113,26 @@ def main():
 
     # 1. training pairs from the engine
     t = time.perf_counter()
-    hyps, counts, last = gather_training_pairs(eng, kb, args.pairs, per_round, 256, rng, chunk)
+    hyps, counts, pcounts = gather_training_pairs(eng, kb, args.pairs, per_round, 256, rng, chunk)
     t_pairs = time.perf_counter() - t
     order = rng.permutation(len(hyps))
     hyps = [hyps[i] for i in order]
-    counts = counts[order]
+    counts, pcounts = counts[order], pcounts[order]
     n_val = len(hyps) // 10
     n_tr = len(hyps) - n_val
-    enc = hthedl.encode_batch(hyps)
-    fb = FeatureBatch(*enc)
-    y = torch.from_numpy(coverage_targets(counts, eng.n_pos, eng.n_neg)).cuda()
+    fb = FeatureBatch(*hthedl.encode_batch(hyps))
 
-    # 2. training
-    scr = Screener(init_params(seed=11), batch=8192, lr=1e-3)
-    t = time.perf_counter()
-    losses = train(scr, fb, y, n_tr, args.epochs, 1024, rng)
-    t_train = time.perf_counter() - t
+    # 2. training: "relative" predicts the shares of the parent's coverage a
+    # refinement keeps (the parent was evaluated exactly); "absolute" the
+    # covered fractions of the examples
+    models = {}
+    for mode in ("relative", "absolute"):
+        y = torch.from_numpy(coverage_targets(counts, eng.n_pos, eng.n_neg,
+                                              pcounts if mode == "relative" else None)).cuda()
+        scr = Screener(init_params(seed=11), batch=8192, lr=1e-3)
+        t = time.perf_counter()
+        losses = train(scr, fb, y, n_tr, args.epochs, 1024, rng)
+        models[mode] = (scr, losses, time.perf_counter() - t)
 
     # 3. candidates: the best `beam` evaluated so far, each refined
     top = search.top_indices(counts, eng.n_pos, args.candidates_beam)
@@ -137,6 +151,7 @@ def main():
     log(f"[screen] {n:,} candidates from {len(parents)} parents")
     cenc = hthedl.encode_batch(cands, child_offsets=True)
     cfb = FeatureBatch(*cenc[:3])
+    cbase = torch.from_numpy(counts[top][parent_of].astype(np.uint32).view(np.int32)).cuda()
     n_sel = int(round(args.top * n))
     n_aud = int(round(args.audit * n))
     audit = rng.choice(n, size=n_aud, replace=False)           # drawn on the host: an input
@@ -145,21 +160,7 @@ def main():
     work = torch.empty(65538, dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
 
-    # 4. screened: features + scores + top-k + exact evaluation of the selection
-    t0 = time.perf_counter()
-    cfb.recompute()
-    score(scr, cfb, n, eng.n_pos, eng.n_neg, scores)
-    hthedl.hth_topk(scores, n, n_sel, sel, work)
-    chosen = np.union1d(sel.cpu().numpy().astype(np.int64), audit)
-    sub = hthedl.gather_encoded(cenc, chosen)
-    sc = torch.empty((chosen.size, 2), dtype=torch.int32, device="cuda")
-    eng.eval_batch(None, counts=sc, chunk=chunk, encoded=sub)
-    sc_np = sc.cpu().numpy().view(np.uint32)
-    screened_top = chosen[search.top_indices(sc_np, eng.n_pos, args.k)]
-    torch.cuda.synchronize()
-    t_screen = time.perf_counter() - t0
-
-    # 5. exhaustive exact evaluation of every candidate
+    # 4. exhaustive exact evaluation of every candidate (the judge)
     t0 = time.perf_counter()
     allc = torch.empty((n, 2), dtype=torch.int32, device="cuda")
     eng.eval_batch(None, counts=allc, chunk=chunk, encoded=cenc[:3])
@@ -167,30 +168,48 @@ def main():
     exact_top = search.top_indices(all_np, eng.n_pos, args.k)
     torch.cuda.synchronize()
     t_exh = time.perf_counter() - t0
+    f_np = search.f1_float(all_np, eng.n_pos)
 
-    # the exact engine judges the screener's selection
-    assert np.array_equal(all_np[chosen], sc_np), "screened and exhaustive exact counts differ"
-    recall = search.recall_at(screened_top, exact_top)
-    budget = chosen.size
+    # 5. screened: features + scores + top-k + exact evaluation of the selection
+    res = {}
+    for mode, (scr, losses, t_train) in models.items():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cfb.recompute()
+        score(scr, cfb, n, eng.n_pos, eng.n_neg, scores, base=cbase if mode == "relative" else None)
+        hthedl.hth_topk(scores, n, n_sel, sel, work)
+        chosen = np.union1d(sel.cpu().numpy().astype(np.int64), audit)
+        sub = hthedl.gather_encoded(cenc, chosen)
+        sc = torch.empty((chosen.size, 2), dtype=torch.int32, device="cuda")
+        eng.eval_batch(None, counts=sc, chunk=chunk, encoded=sub)
+        sc_np = sc.cpu().numpy().view(np.uint32)
+        screened_top = chosen[search.top_indices(sc_np, eng.n_pos, args.k)]
+        torch.cuda.synchronize()
+        t_screen = time.perf_counter() - t0
+        assert np.array_equal(all_np[chosen], sc_np), "screened and exhaustive exact counts differ"
+        s_np = scores.cpu().numpy()
+        rank_corr = float(np.corrcoef(np.argsort(np.argsort(s_np)), np.argsort(np.argsort(f_np)))[0, 1])
+        res[mode] = {"screened_hyp_per_s": round(n / t_screen, 1), "speedup": round(t_exh / t_screen, 3),
+                     f"recall_at_{args.k}": search.recall_at(screened_top, exact_top),
+                     "score_rank_correlation": round(rank_corr, 4), "exact_budget": int(chosen.size),
+                     "screened_seconds": round(t_screen, 4), "train_seconds": round(t_train, 2),
+                     "train_loss_first_last": [round(losses[0], 5), round(losses[-1], 5)]}
+        log(f"[screen] {mode}: recall@{args.k} {res[mode][f'recall_at_{args.k}']:.2f}, "
+            f"{res[mode]['speedup']}x the exhaustive rate")
+    budget = res["relative"]["exact_budget"]
     rand = rng.choice(n, size=budget, replace=False)
     rand_top = rand[search.top_indices(all_np[rand], eng.n_pos, args.k)]
     pf1 = search.f1_float(counts[top], eng.n_pos)[parent_of]
     heur = np.argsort(-pf1, kind="stable")[:budget]
     heur_top = heur[search.top_indices(all_np[heur], eng.n_pos, args.k)]
-    s_np = scores.cpu().numpy()
-    f_np = search.f1_float(all_np, eng.n_pos)
-    rank_corr = float(np.corrcoef(np.argsort(np.argsort(s_np)), np.argsort(np.argsort(f_np)))[0, 1])
     out = {
         "workload": f"screened search on the {cfg.name} KB ({kb.n:,} individuals)",
-        "candidates": n, "exact_budget": int(budget), "top_fraction": args.top, "audit_fraction": args.audit,
-        "screened_hyp_per_s": round(n / t_screen, 1), "exhaustive_hyp_per_s": round(n / t_exh, 1),
-        "speedup": round(t_exh / t_screen, 3),
-        f"recall_at_{args.k}": recall, f"random_recall_at_{args.k}": search.recall_at(rand_top, exact_top),
+        "candidates": n, "top_fraction": args.top, "audit_fraction": args.audit,
+        "exhaustive_hyp_per_s": round(n / t_exh, 1), "exhaustive_seconds": round(t_exh, 4),
+        "screener": res,
+        f"random_recall_at_{args.k}": search.recall_at(rand_top, exact_top),
         f"parent_f1_recall_at_{args.k}": search.recall_at(heur_top, exact_top),
-        "score_rank_correlation": round(rank_corr, 4),
-        "training_pairs": len(hyps), "pairs_seconds": round(t_pairs, 2), "train_seconds": round(t_train, 2),
-        "train_loss_first_last": [round(losses[0], 5), round(losses[-1], 5)],
-        "screened_seconds": round(t_screen, 4), "exhaustive_seconds": round(t_exh, 4),
+        "training_pairs": len(hyps), "pairs_seconds": round(t_pairs, 2),
     }
     print(json.dumps(out), flush=True)
 

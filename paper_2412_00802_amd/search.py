@@ -189,36 +189,48 @@ class Refiner:
 
 def refinement_rounds(kb, evaluate: Callable[[Sequence[tuple]], np.ndarray], n_pos: int,
                       rounds: int, per_round: int, beam: int, rng: np.random.Generator,
-                      start: Sequence[tuple] = (("top",),)):
+                      start: Sequence[tuple] = (("top",),), start_counts=None, with_parents: bool = False):
     """A refinement trace: each round refines the previous round's top `beam`
     hypotheses into `per_round` candidates and evaluates them exactly.
-    Yields (round, candidates, counts)."""
+    Yields (round, candidates, counts), and with with_parents also each
+    candidate's parent coverage (start_counts for the first round's parents)."""
     ref = Refiner(kb, rng)
     parents = list(start)
+    pcounts = (np.zeros((len(parents), 2), dtype=np.int64) if start_counts is None
+               else np.asarray(start_counts, dtype=np.int64).reshape(len(parents), 2))
     for r in range(rounds):
         per_parent = max(1, per_round // max(1, len(parents)))
         cands = []
+        pidx = []
         seen = set()
-        for p in parents:
+        for pi, p in enumerate(parents):
             for c in ref.refine(p, per_parent):
                 if c not in seen:
                     seen.add(c)
                     cands.append(c)
+                    pidx.append(pi)
         # top up with added conjuncts (two at once once single ones run out);
         # a small KB may have fewer distinct candidates than asked for
         tries = 0
         while len(cands) < per_round and tries < 16 * per_round:
             tries += 1
             extra = (ref.conjunct(),) if tries < 2 * per_round else (ref.conjunct(), ref.conjunct())
-            c = ("and", parents[int(rng.integers(0, len(parents)))]) + extra
+            pi = int(rng.integers(0, len(parents)))
+            c = ("and", parents[pi]) + extra
             if c not in seen:
                 seen.add(c)
                 cands.append(c)
+                pidx.append(pi)
         cands = cands[:per_round]
+        pidx = np.asarray(pidx[:per_round], dtype=np.int64)
         counts = evaluate(cands)
-        yield r, cands, counts
+        if with_parents:
+            yield r, cands, counts, pcounts[pidx]
+        else:
+            yield r, cands, counts
         top = top_indices(counts, n_pos, beam)
         parents = [cands[i] for i in top]
+        pcounts = np.asarray(counts, dtype=np.int64)[top]
 
 
 def recall_at(screened_top: Sequence[int], exhaustive_top: Sequence[int]) -> float:

@@ -360,14 +360,19 @@ def _gen_examples_planted(cfg: KBConfig, ss: np.random.SeedSequence, concept_bit
     return (ids_to_bits(np.concatenate([pa, pb]), n), ids_to_bits(np.concatenate([na, nb]), n))
 
 
-def make_kb(cfg: KBConfig, workers: Optional[int] = None) -> KB:
-    """Build the seeded knowledge base of a workload."""
+def make_kb(cfg: KBConfig, workers: Optional[int] = None, log=None) -> KB:
+    """Build the seeded knowledge base of a workload (log: optional progress
+    callback, called after each stage)."""
     if workers is None:
         workers = max(1, min(16, os.cpu_count() or 1))
+    say = log or (lambda *_: None)
     s_con, s_role, s_data, s_ex, _s_hyp, _s_trace = _streams(cfg)
     bits, parent, level = _gen_concepts(cfg, s_con, workers)
+    say(f"concepts: {cfg.n_concepts} rows")
     offsets, targets = _gen_roles(cfg, s_role, workers)
+    say(f"roles: {targets.shape[0]:,} assertions")
     cols, dec = _gen_data(cfg, s_data, workers)
+    say(f"data: {cfg.n_data} columns")
     if cfg.examples == "planted":
         pos, neg = _gen_examples_planted(cfg, s_ex, bits, level)
     else:

@@ -200,7 +200,7 @@ def main():
         cfg = dataclasses.replace(cfg, name="c4-small", n_individuals=400_000, total_edges=6_000_000,
                                   n_data=16, n_pos=20_000, n_neg=20_000, degree_cap=4096)
     t = time.perf_counter()
-    kb = synth.make_kb(cfg)
+    kb = synth.make_kb(cfg, log=lambda m: log(f"[trace] generated {m} ({time.perf_counter() - t:.1f}s)"))
     log(f"[trace] KB {cfg.name}: N={kb.n:,}, {kb.n_edges:,} assertions, {kb.n_data} properties "
         f"({time.perf_counter() - t:.1f}s)")
     t = time.perf_counter()

@@ -209,3 +209,19 @@ def test_training_lowers_loss(torch):
     ent = -np.mean(y * np.log(y) + (1 - y) * np.log(1 - y))
     say(f"[train] loss {losses[0]:.4f} -> {losses[-1]:.4f} (entropy floor {ent:.4f})")
     assert losses[-1] - ent < 0.3 * (losses[0] - ent)
+
+
+def test_head_score_with_and_without_base(torch):
+    rng = np.random.default_rng(21)
+    n, n_pos, n_neg = 3000, 5000, 7000
+    z = rng.standard_normal((n, 2)).astype(np.float32) * 3
+    base = np.stack([rng.integers(0, n_pos + 1, n), rng.integers(0, n_neg + 1, n)], 1).astype(np.uint32)
+    Z = torch.from_numpy(z).cuda()
+    B = torch.from_numpy(base.view(np.int32)).cuda()
+    out = torch.empty(n, dtype=torch.float32, device="cuda")
+    hthedl.hth_head_score(Z, n, float(n_pos), float(n_neg), out)
+    np.testing.assert_allclose(out.cpu().numpy(), S.predicted_f1(z.astype(np.float64), n_pos, n_neg),
+                               rtol=2e-5, atol=1e-7)
+    hthedl.hth_head_score(Z, n, float(n_pos), float(n_neg), out, base=B)
+    np.testing.assert_allclose(out.cpu().numpy(), S.predicted_f1(z.astype(np.float64), n_pos, n_neg, base),
+                               rtol=2e-5, atol=1e-7)

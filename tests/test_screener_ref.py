@@ -71,3 +71,18 @@ def test_adamw_reference_first_step():
     q, m, v = S.adamw(p, g, np.zeros(2), np.zeros(2), lr=0.1, b1=0.9, b2=0.999, eps=0.0, wd=0.0, step=1)
     # first bias-corrected step moves each weight by lr * sign(g)
     np.testing.assert_allclose(q, p - 0.1 * np.sign(g))
+
+
+def test_predicted_f1_closed_forms():
+    """z = 0 keeps half of the base coverage; very large logits keep all of it;
+    a base equal to (|P|, |Ng|) is the same as no base."""
+    n_pos, n_neg = 100, 300
+    base = np.array([[40, 10], [100, 300], [0, 0]])
+    f = S.predicted_f1(np.zeros((3, 2)), n_pos, n_neg, base)
+    want = [2 * 20 / (20 + 5 + 100), 2 * 50 / (50 + 150 + 100), 0.0]
+    np.testing.assert_allclose(f, want, rtol=1e-12)
+    f = S.predicted_f1(np.full((3, 2), 60.0), n_pos, n_neg, base)
+    np.testing.assert_allclose(f, [2 * 40 / (40 + 10 + 100), 2 * 100 / (100 + 300 + 100), 0.0], rtol=1e-12)
+    z = np.random.default_rng(3).standard_normal((5, 2))
+    np.testing.assert_allclose(S.predicted_f1(z, n_pos, n_neg, np.tile([n_pos, n_neg], (5, 1))),
+                               S.predicted_f1(z, n_pos, n_neg), rtol=1e-12)
