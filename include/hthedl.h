@@ -258,6 +258,15 @@ hth_status hth_features(const hth_node* d_nodes, const uint32_t* d_hyp_node_offs
 hth_status hth_densify(const uint16_t* d_feat, const uint32_t* d_hyp_node_offsets, uint32_t row0,
                        uint32_t n_rows, uint16_t* d_x, void* stream);
 
+/* Feature rows of refinements relative to their parents: d_x[r][f] = (subtrees
+ * of hypothesis row0 + r with feature f) - (subtrees of parent p with feature
+ * f), p = d_parent_index[row0 + r] indexing a second feature set
+ * (d_parent_feat, d_parent_offsets) of the parents.  What the refinement
+ * added is positive, what it replaced negative; unchanged subtrees cancel. */
+hth_status hth_densify_delta(const uint16_t* d_feat, const uint32_t* d_hyp_node_offsets, uint32_t row0,
+                             uint32_t n_rows, const uint16_t* d_parent_feat, const uint32_t* d_parent_offsets,
+                             const uint32_t* d_parent_index, uint16_t* d_x, void* stream);
+
 /* C[M][N] = op(A) op(B) on the MFMA units (bf16 operands, fp32 accumulation).
  * trans_a = 0: A is [M][lda]; 1: A is given transposed as [K][lda].
  * trans_b = 0: B is [K][ldb]; 1: B is given as [N][ldb].  (Both transposed is

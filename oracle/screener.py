@@ -98,6 +98,11 @@ def dense_features(hyps) -> np.ndarray:
     return x
 
 
+def delta_features(children, parents, parent_index) -> np.ndarray:
+    """[H][4096] subtree counts of each child minus those of its parent."""
+    return dense_features(children) - dense_features(parents)[np.asarray(parent_index)]
+
+
 def bf16(x) -> np.ndarray:
     """Round float32 values to bfloat16 (nearest, ties to even); float64 result."""
     a = np.asarray(x, dtype=np.float32)

@@ -96,14 +96,20 @@ __global__ void k_features(const hth_node* __restrict__ nodes, const uint32_t* _
 // whose feature index is f (small integers, exact in bf16)
 __global__ void __launch_bounds__(256)
 k_densify(const uint16_t* __restrict__ feat, const uint32_t* __restrict__ offs, uint32_t row0,
-          uint32_t n_rows, __bf16* __restrict__ x) {
-  __shared__ uint32_t cnt[kFeatDim];
+          uint32_t n_rows, const uint16_t* __restrict__ pfeat, const uint32_t* __restrict__ poffs,
+          const uint32_t* __restrict__ pidx, __bf16* __restrict__ x) {
+  __shared__ int32_t cnt[kFeatDim];
   const uint32_t r = blockIdx.x;
   if (r >= n_rows) return;
   for (uint32_t i = threadIdx.x; i < kFeatDim; i += 256) cnt[i] = 0;
   __syncthreads();
   const uint32_t b = offs[row0 + r], e = offs[row0 + r + 1];
-  for (uint32_t i = b + threadIdx.x; i < e; i += 256) atomicAdd(&cnt[feat[i] & (kFeatDim - 1)], 1u);
+  for (uint32_t i = b + threadIdx.x; i < e; i += 256) atomicAdd(&cnt[feat[i] & (kFeatDim - 1)], 1);
+  if (pidx) {   // minus the parent's subtrees: what the refinement added or changed
+    const uint32_t p = pidx[row0 + r];
+    const uint32_t pb = poffs[p], pe = poffs[p + 1];
+    for (uint32_t i = pb + threadIdx.x; i < pe; i += 256) atomicSub(&cnt[pfeat[i] & (kFeatDim - 1)], 1);
+  }
   __syncthreads();
   __bf16* row = x + (size_t)r * kFeatDim;
   for (uint32_t i = threadIdx.x; i < kFeatDim; i += 256) row[i] = (__bf16)(float)cnt[i];
@@ -428,7 +434,22 @@ extern "C" hth_status hth_densify(const uint16_t* d_feat, const uint32_t* d_hyp_
   if (!d_feat || !d_hyp_node_offsets || !d_x) return fail(HTH_E_INVALID, "NULL argument");
   if (!n_rows) return HTH_OK;
   hipLaunchKernelGGL(k_densify, dim3(n_rows), dim3(256), 0, static_cast<hipStream_t>(stream), d_feat,
-                     d_hyp_node_offsets, row0, n_rows, reinterpret_cast<__bf16*>(d_x));
+                     d_hyp_node_offsets, row0, n_rows, nullptr, nullptr, nullptr,
+                     reinterpret_cast<__bf16*>(d_x));
+  HTH_HIP(hipGetLastError());
+  return HTH_OK;
+}
+
+extern "C" hth_status hth_densify_delta(const uint16_t* d_feat, const uint32_t* d_hyp_node_offsets,
+                                        uint32_t row0, uint32_t n_rows, const uint16_t* d_parent_feat,
+                                        const uint32_t* d_parent_offsets, const uint32_t* d_parent_index,
+                                        uint16_t* d_x, void* stream) {
+  if (!d_feat || !d_hyp_node_offsets || !d_parent_feat || !d_parent_offsets || !d_parent_index || !d_x)
+    return fail(HTH_E_INVALID, "NULL argument");
+  if (!n_rows) return HTH_OK;
+  hipLaunchKernelGGL(k_densify, dim3(n_rows), dim3(256), 0, static_cast<hipStream_t>(stream), d_feat,
+                     d_hyp_node_offsets, row0, n_rows, d_parent_feat, d_parent_offsets, d_parent_index,
+                     reinterpret_cast<__bf16*>(d_x));
   HTH_HIP(hipGetLastError());
   return HTH_OK;
 }

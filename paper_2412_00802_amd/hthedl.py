@@ -35,7 +35,7 @@ EXPORTED = ["hth_kb_derived_bytes", "hth_kb_create", "hth_kb_set_examples", "hth
             "hth_profile_end", "hth_features", "hth_densify", "hth_gemm_bf16", "hth_head_forward",
             "hth_head_backward", "hth_colsum", "hth_adamw", "hth_to_bf16", "hth_topk",
             "hth_batch_workspace_bytes", "hth_head_score", "hth_kb_get_tuning", "hth_kb_set_tuning",
-            "hth_kb_set_sets", "hth_eval_batch_sets"]
+            "hth_kb_set_sets", "hth_eval_batch_sets", "hth_densify_delta"]
 
 
 class HthError(RuntimeError):
@@ -100,6 +100,7 @@ def lib() -> ctypes.CDLL:
             "hth_profile_end": [P, ctypes.POINTER(ProfEntry)],
             "hth_features": [P, P, U32, P, U32, P, P, P, P],
             "hth_densify": [P, P, U32, U32, P, P],
+            "hth_densify_delta": [P, P, U32, U32, P, P, P, P, P],
             "hth_gemm_bf16": [I, I, I, I, I, P, I, P, I, P, I, P, I, P, I, P, I, P],
             "hth_head_forward": [P, I, I, P, P, P, P, P, F, P, P],
             "hth_head_backward": [P, I, I, P, P, P, P, P],
@@ -278,6 +279,12 @@ def hth_features(d_nodes, d_offsets, n_hyps: int, d_children, n_children: int, d
 
 def hth_densify(d_feat, d_offsets, row0: int, n_rows: int, d_x, stream=None) -> None:
     _check(lib().hth_densify(_ptr(d_feat), _ptr(d_offsets), row0, n_rows, _ptr(d_x), _stream(stream)))
+
+
+def hth_densify_delta(d_feat, d_offsets, row0: int, n_rows: int, d_parent_feat, d_parent_offsets,
+                      d_parent_index, d_x, stream=None) -> None:
+    _check(lib().hth_densify_delta(_ptr(d_feat), _ptr(d_offsets), row0, n_rows, _ptr(d_parent_feat),
+                                   _ptr(d_parent_offsets), _ptr(d_parent_index), _ptr(d_x), _stream(stream)))
 
 
 def hth_gemm_bf16(trans_a: int, trans_b: int, M: int, N: int, K: int, A, lda: int, B, ldb: int,

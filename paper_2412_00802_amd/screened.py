@@ -40,22 +40,31 @@ def coverage_targets(counts: np.ndarray, n_pos: int, n_neg: int, base: np.ndarra
 
 def gather_training_pairs(eng, kb, n_pairs, per_round, beam, rng, chunk):
     """Refinement rounds from top; every candidate is evaluated exactly.
-    Returns the candidates, their counts and their parents' counts."""
+    Returns the candidates, their counts, their parents' counts, the parents
+    (distinct, in round order) and each candidate's parent index."""
     hyps: List[tuple] = []
-    counts, parents = [], []
+    counts, pcounts, pidx = [], [], []
+    parents: List[tuple] = []
     ev = lambda hs: eng.eval_batch(hs, chunk=chunk)  # noqa: E731
     rounds = (n_pairs + per_round - 1) // per_round
-    for r, cands, cnt, pc in search.refinement_rounds(kb, ev, eng.n_pos, rounds, per_round, beam, rng,
-                                                      start_counts=[eng.n_pos, eng.n_neg], with_parents=True):
+    for r, cands, cnt, plist, pi, pc in search.refinement_rounds(
+            kb, ev, eng.n_pos, rounds, per_round, beam, rng, start_counts=[eng.n_pos, eng.n_neg],
+            with_parents=True):
         hyps.extend(cands)
         counts.append(cnt)
-        parents.append(pc)
+        pcounts.append(pc)
+        pidx.append(np.asarray(pi) + len(parents))
+        parents.extend(plist)
         log(f"[screen] training round {r}: {len(hyps)} pairs, best F1 "
             f"{search.f1_float(cnt, eng.n_pos).max():.4f}")
-    return hyps[:n_pairs], np.concatenate(counts)[:n_pairs], np.concatenate(parents)[:n_pairs]
+    return (hyps[:n_pairs], np.concatenate(counts)[:n_pairs], np.concatenate(pcounts)[:n_pairs], parents,
+            np.concatenate(pidx)[:n_pairs])
 
 
-def train(scr: Screener, fb: FeatureBatch, y_dev, n: int, epochs: int, batch: int, rng) -> List[float]:
+def train(scr: Screener, fb: FeatureBatch, y_dev, n: int, epochs: int, batch: int, rng,
+          parents: FeatureBatch = None, parent_index=None) -> List[float]:
+    """Epochs of minibatch AdamW over rows [0, n); with parents, the features
+    are relative to each row's parent (hth_densify_delta)."""
     torch = scr.t
     losses = []
     nb = n // batch
@@ -63,7 +72,7 @@ def train(scr: Screener, fb: FeatureBatch, y_dev, n: int, epochs: int, batch: in
         scr.loss.zero_()
         for bi in rng.permutation(nb):
             r0 = int(bi) * batch
-            fb.densify(r0, batch, scr.x)
+            fb.densify(r0, batch, scr.x, parents, parent_index)
             scr.train_step(batch, y_dev[r0:r0 + batch])
         losses.append(scr.loss.item() / (2 * nb * batch))
         log(f"[screen] epoch {ep}: loss {losses[-1]:.5f}")
@@ -71,13 +80,15 @@ def train(scr: Screener, fb: FeatureBatch, y_dev, n: int, epochs: int, batch: in
     return losses
 
 
-def score(scr: Screener, fb: FeatureBatch, n: int, n_pos: int, n_neg: int, out, base=None) -> None:
+def score(scr: Screener, fb: FeatureBatch, n: int, n_pos: int, n_neg: int, out, base=None,
+          parents: FeatureBatch = None, parent_index=None) -> None:
     """Predicted F1 of candidates [0, n); base (device uint32 [n][2]): the
-    parents' coverage when the screener predicts kept shares."""
+    parents' coverage when the screener predicts kept shares; parents: features
+    relative to the parents."""
     B = scr.batch
     for r0 in range(0, n, B):
         m = min(B, n - r0)
-        fb.densify(r0, m, scr.x)
+        fb.densify(r0, m, scr.x, parents, parent_index)
         z = scr.logits(m)
         hthedl.hth_head_score(z, m, float(n_pos), float(n_neg), out[r0:r0 + m],
                               base=None if base is None else base[r0:r0 + m])
@@ -113,25 +124,29 @@ def main():
 
     # 1. training pairs from the engine
     t = time.perf_counter()
-    hyps, counts, pcounts = gather_training_pairs(eng, kb, args.pairs, per_round, 256, rng, chunk)
+    hyps, counts, pcounts, tparents, tpidx = gather_training_pairs(eng, kb, args.pairs, per_round, 256, rng, chunk)
     t_pairs = time.perf_counter() - t
     order = rng.permutation(len(hyps))
     hyps = [hyps[i] for i in order]
-    counts, pcounts = counts[order], pcounts[order]
+    counts, pcounts, tpidx = counts[order], pcounts[order], tpidx[order]
     n_val = len(hyps) // 10
     n_tr = len(hyps) - n_val
     fb = FeatureBatch(*hthedl.encode_batch(hyps))
+    tpfb = FeatureBatch(*hthedl.encode_batch(tparents))
+    tpi = torch.from_numpy(tpidx.astype(np.int32)).cuda()
 
     # 2. training: "relative" predicts the shares of the parent's coverage a
     # refinement keeps (the parent was evaluated exactly); "absolute" the
     # covered fractions of the examples
+    # "delta": shares of the parent's coverage from features relative to the parent
     models = {}
-    for mode in ("relative", "absolute"):
+    for mode in ("delta", "relative", "absolute"):
         y = torch.from_numpy(coverage_targets(counts, eng.n_pos, eng.n_neg,
-                                              pcounts if mode == "relative" else None)).cuda()
+                                              None if mode == "absolute" else pcounts)).cuda()
         scr = Screener(init_params(seed=11), batch=8192, lr=1e-3)
         t = time.perf_counter()
-        losses = train(scr, fb, y, n_tr, args.epochs, 1024, rng)
+        losses = train(scr, fb, y, n_tr, args.epochs, 1024, rng,
+                       *((tpfb, tpi) if mode == "delta" else (None, None)))
         models[mode] = (scr, losses, time.perf_counter() - t)
 
     # 3. candidates: the best `beam` evaluated so far, each refined
@@ -152,6 +167,8 @@ def main():
     cenc = hthedl.encode_batch(cands, child_offsets=True)
     cfb = FeatureBatch(*cenc[:3])
     cbase = torch.from_numpy(counts[top][parent_of].astype(np.uint32).view(np.int32)).cuda()
+    cpfb = FeatureBatch(*hthedl.encode_batch(parents))
+    cpi = torch.from_numpy(parent_of.astype(np.int32)).cuda()
     n_sel = int(round(args.top * n))
     n_aud = int(round(args.audit * n))
     audit = rng.choice(n, size=n_aud, replace=False)           # drawn on the host: an input
@@ -176,7 +193,10 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         cfb.recompute()
-        score(scr, cfb, n, eng.n_pos, eng.n_neg, scores, base=cbase if mode == "relative" else None)
+        if mode == "delta":
+            cpfb.recompute()
+        score(scr, cfb, n, eng.n_pos, eng.n_neg, scores, base=None if mode == "absolute" else cbase,
+              parents=cpfb if mode == "delta" else None, parent_index=cpi if mode == "delta" else None)
         hthedl.hth_topk(scores, n, n_sel, sel, work)
         chosen = np.union1d(sel.cpu().numpy().astype(np.int64), audit)
         sub = hthedl.gather_encoded(cenc, chosen)
@@ -196,7 +216,10 @@ def main():
                      "train_loss_first_last": [round(losses[0], 5), round(losses[-1], 5)]}
         log(f"[screen] {mode}: recall@{args.k} {res[mode][f'recall_at_{args.k}']:.2f}, "
             f"{res[mode]['speedup']}x the exhaustive rate")
-    budget = res["relative"]["exact_budget"]
+    # ties at the k-th exact F1 make part of the exact top-k a matter of the index tie-break
+    kth = np.sort(f_np)[::-1][args.k - 1] if n >= args.k else 0.0
+    ties = int(np.sum(np.isclose(f_np, kth, rtol=0, atol=1e-12)))
+    budget = res["delta"]["exact_budget"]
     rand = rng.choice(n, size=budget, replace=False)
     rand_top = rand[search.top_indices(all_np[rand], eng.n_pos, args.k)]
     pf1 = search.f1_float(counts[top], eng.n_pos)[parent_of]
@@ -206,7 +229,7 @@ def main():
         "workload": f"screened search on the {cfg.name} KB ({kb.n:,} individuals)",
         "candidates": n, "top_fraction": args.top, "audit_fraction": args.audit,
         "exhaustive_hyp_per_s": round(n / t_exh, 1), "exhaustive_seconds": round(t_exh, 4),
-        "screener": res,
+        "screener": res, f"candidates_tied_at_kth_f1": ties,
         f"random_recall_at_{args.k}": search.recall_at(rand_top, exact_top),
         f"parent_f1_recall_at_{args.k}": search.recall_at(heur_top, exact_top),
         "training_pairs": len(hyps), "pairs_seconds": round(t_pairs, 2),

@@ -128,5 +128,11 @@ class FeatureBatch:
         hthedl.hth_features(self.nodes, self.offsets, self.n_hyps, self.children, self.n_children,
                             self.hash, self.feat, self.bad)
 
-    def densify(self, row0: int, n: int, x) -> None:
-        hthedl.hth_densify(self.feat, self.offsets, row0, n, x)
+    def densify(self, row0: int, n: int, x, parents: "FeatureBatch" = None, parent_index=None) -> None:
+        """Rows [row0, row0 + n) into x; with parents (and a device uint32
+        parent_index per hypothesis), minus each parent's features."""
+        if parents is None:
+            hthedl.hth_densify(self.feat, self.offsets, row0, n, x)
+        else:
+            hthedl.hth_densify_delta(self.feat, self.offsets, row0, n, parents.feat, parents.offsets,
+                                     parent_index, x)

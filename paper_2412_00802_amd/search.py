@@ -192,8 +192,9 @@ def refinement_rounds(kb, evaluate: Callable[[Sequence[tuple]], np.ndarray], n_p
                       start: Sequence[tuple] = (("top",),), start_counts=None, with_parents: bool = False):
     """A refinement trace: each round refines the previous round's top `beam`
     hypotheses into `per_round` candidates and evaluates them exactly.
-    Yields (round, candidates, counts), and with with_parents also each
-    candidate's parent coverage (start_counts for the first round's parents)."""
+    Yields (round, candidates, counts), and with with_parents also the round's
+    parents, each candidate's parent index among them and its parent's
+    coverage (start_counts for the first round's parents)."""
     ref = Refiner(kb, rng)
     parents = list(start)
     pcounts = (np.zeros((len(parents), 2), dtype=np.int64) if start_counts is None
@@ -225,7 +226,7 @@ def refinement_rounds(kb, evaluate: Callable[[Sequence[tuple]], np.ndarray], n_p
         pidx = np.asarray(pidx[:per_round], dtype=np.int64)
         counts = evaluate(cands)
         if with_parents:
-            yield r, cands, counts, pcounts[pidx]
+            yield r, cands, counts, list(parents), pidx, pcounts[pidx]
         else:
             yield r, cands, counts
         top = top_indices(counts, n_pos, beam)

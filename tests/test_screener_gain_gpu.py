@@ -27,32 +27,38 @@ def test_screener_beats_random_selection():
     kb = synth.make_kb(cfg)
     eng = hthedl.Engine(kb, max_nodes=64, max_hyps=1)
     rng = np.random.default_rng(19)
-    hyps, counts, pcounts = gather_training_pairs(eng, kb, 16384, 4096, 64, rng, 8192)
+    hyps, counts, pcounts, tparents, tpidx = gather_training_pairs(eng, kb, 16384, 4096, 64, rng, 8192)
     order = rng.permutation(len(hyps))
     hyps = [hyps[i] for i in order]
-    counts, pcounts = counts[order], pcounts[order]
+    counts, pcounts, tpidx = counts[order], pcounts[order], tpidx[order]
     fb = FeatureBatch(*hthedl.encode_batch(hyps))
-    # the screener predicts the shares of the (exactly known) parent coverage a refinement keeps
+    tpfb = FeatureBatch(*hthedl.encode_batch(tparents))
+    tpi = torch.from_numpy(tpidx.astype(np.int32)).cuda()
+    # the screener predicts the shares of the (exactly known) parent coverage a
+    # refinement keeps, from features relative to the parent
     y = torch.from_numpy(coverage_targets(counts, eng.n_pos, eng.n_neg, pcounts)).cuda()
     scr = Screener(init_params(seed=11), batch=4096, lr=1e-3)
-    losses = train(scr, fb, y, len(hyps), 8, 512, rng)
+    losses = train(scr, fb, y, len(hyps), 8, 512, rng, tpfb, tpi)
     say(f"[gain] {len(hyps)} pairs, loss {losses[0]:.4f} -> {losses[-1]:.4f}")
     assert losses[-1] < losses[0]
     # fresh candidates: refinements of the best 128 hypotheses seen
     top = search.top_indices(counts, eng.n_pos, 128)
     ref = search.Refiner(kb, rng)
-    cands, base, seen = [], [], set(hyps)
-    for i in top:
+    cands, base, pidx, seen = [], [], [], set(hyps)
+    for j, i in enumerate(top):
         for c in ref.refine(hyps[i], 96):
             if c not in seen:
                 seen.add(c)
                 cands.append(c)
                 base.append(counts[i])
+                pidx.append(j)
     n = len(cands)
     cfb = FeatureBatch(*hthedl.encode_batch(cands))
+    pfb = FeatureBatch(*hthedl.encode_batch([hyps[i] for i in top]))
     scores = torch.empty(n, dtype=torch.float32, device="cuda")
     base = torch.from_numpy(np.asarray(base, dtype=np.uint32).view(np.int32)).cuda()
-    score(scr, cfb, n, eng.n_pos, eng.n_neg, scores, base=base)
+    score(scr, cfb, n, eng.n_pos, eng.n_neg, scores, base=base, parents=pfb,
+          parent_index=torch.from_numpy(np.asarray(pidx, dtype=np.int32)).cuda())
     exact = eng.eval_batch(cands, chunk=8192)
     k, budget = 50, n // 20
     want = search.top_indices(exact, eng.n_pos, k)

@@ -94,6 +94,21 @@ def test_features_and_densify(torch):
     x = torch.empty((len(hyps), S.FEATURE_DIM), dtype=torch.bfloat16, device="cuda")
     fb.densify(0, len(hyps), x)
     np.testing.assert_array_equal(f64(torch, x), S.dense_features(hyps))
+    # relative to parents: refinements of the first 30 hypotheses, minus their parents' features
+    from paper_2412_00802_amd import search
+    ref = search.Refiner(kb, np.random.default_rng(2))
+    parents = hyps[:30]
+    kids, pidx = [], []
+    for i, p in enumerate(parents):
+        for c in ref.refine(p, 5):
+            kids.append(c)
+            pidx.append(i)
+    kfb, _ = _feature_batch(torch, kids)
+    pfb, _ = _feature_batch(torch, parents)
+    P = torch.from_numpy(np.asarray(pidx, dtype=np.int32)).cuda()
+    xd = torch.empty((len(kids), S.FEATURE_DIM), dtype=torch.bfloat16, device="cuda")
+    kfb.densify(3, len(kids) - 3, xd, parents=pfb, parent_index=P)
+    np.testing.assert_array_equal(f64(torch, xd)[:len(kids) - 3], S.delta_features(kids, parents, pidx)[3:])
 
 
 def test_features_flag_malformed_children(torch):

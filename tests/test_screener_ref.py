@@ -86,3 +86,19 @@ def test_predicted_f1_closed_forms():
     z = np.random.default_rng(3).standard_normal((5, 2))
     np.testing.assert_allclose(S.predicted_f1(z, n_pos, n_neg, np.tile([n_pos, n_neg], (5, 1))),
                                S.predicted_f1(z, n_pos, n_neg), rtol=1e-12)
+
+
+def test_delta_features_cancel_unchanged_subtrees():
+    """A child that adds one conjunct X to an and-parent differs from its parent
+    by X's subtrees plus the new root, minus the old root."""
+    parent = ("and", ("atom", 1), ("exists", 0, 1, ("atom", 2)))
+    x = ("dge", 3, 0.25)
+    child = ("and", ("atom", 1), ("exists", 0, 1, ("atom", 2)), x)
+    d = S.delta_features([child], [parent], [0])[0]
+    want = np.zeros(S.FEATURE_DIM)
+    for _, f in S.subtree_features(x):
+        want[f] += 1
+    want[S.subtree_features(child)[-1][1]] += 1
+    want[S.subtree_features(parent)[-1][1]] -= 1
+    np.testing.assert_array_equal(d, want)
+    assert not S.delta_features([parent], [parent], [0]).any()
