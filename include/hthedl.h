@@ -280,18 +280,20 @@ hth_status hth_gemm_bf16(int trans_a, int trans_b, int M, int N, int K, const ui
                          int ldm, float* c32, int ldc, uint16_t* cbf, int ldcb, void* stream);
 
 /* Output layer of width 2: z[b] = h[b] . w[:, o] + bias[o] (h bf16 [Bn][Kd],
- * w fp32 [Kd][2]).  With targets y (fp32 [Bn][2], the covered fractions
- * pos/|P| and neg/|Ng|): adds the summed BCE-with-logits loss into *loss and
- * writes dz = (sigmoid(z) - y) * scale. */
+ * w fp32 [Kd][2]).  With targets y (fp32 [Bn][2]) it adds the summed loss into
+ * *loss and writes dz = dloss/dz * scale; loss_kind 0: BCE-with-logits (y are
+ * fractions in [0, 1]); 1: squared error (z - y)^2 / 2 (y real). */
 hth_status hth_head_forward(const uint16_t* h, int Bn, int Kd, const float* w, const float* bias,
-                            float* z, const float* y, float* dz, float scale, float* loss, void* stream);
+                            float* z, const float* y, float* dz, float scale, float* loss, int loss_kind,
+                            void* stream);
 
-/* Screening score from the logits z (fp32 [Bn][2]): the F1 of the predicted
- * coverage, p = sigmoid(z0) P_b, q = sigmoid(z1) N_b, 2p / (p + q + n_pos).
- * base: NULL, then (P_b, N_b) = (n_pos, n_neg) (the logits predict covered
- * fractions of the examples); or device uint32 [Bn][2] base coverage per row
- * (the logits predict the shares of a parent's coverage a refinement keeps). */
-hth_status hth_head_score(const float* z, int Bn, float n_pos, float n_neg, const uint32_t* base,
+/* Screening score from the outputs z (fp32 [Bn][2]): the F1 of the predicted
+ * coverage (p, q), 2p / (p + q + n_pos), with (P_b, N_b) the row's base
+ * coverage (device uint32 [Bn][2], e.g. a refinement's parent) or, when base
+ * is NULL, (n_pos, n_neg).  kind 0: p = sigmoid(z0) P_b, q = sigmoid(z1) N_b
+ * (kept shares); kind 1 (needs base): p = P_b - expm1(z0), q = N_b - expm1(z1),
+ * clamped to [0, base] (z = log(1 + removed count)). */
+hth_status hth_head_score(const float* z, int Bn, float n_pos, float n_neg, const uint32_t* base, int kind,
                           float* score, void* stream);
 
 /* Backward of the output layer: dw[k][o] = sum_b h[b][k] dz[b][o];

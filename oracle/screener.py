@@ -116,8 +116,10 @@ def _r(x, rounding: bool):
     return bf16(x) if rounding else np.asarray(x, dtype=np.float64)
 
 
-def forward(p: Dict[str, np.ndarray], x: np.ndarray, y: np.ndarray = None, rounding: bool = False):
-    """Activations (and the summed BCE-with-logits loss when y is given)."""
+def forward(p: Dict[str, np.ndarray], x: np.ndarray, y: np.ndarray = None, rounding: bool = False,
+            loss: str = "bce"):
+    """Activations, and when y is given the summed loss: BCE-with-logits
+    (loss="bce") or the squared error (z - y)^2 / 2 (loss="mse")."""
     w1, w2 = _r(p["w1"], rounding), _r(p["w2"], rounding)
     h1 = _r(np.maximum(x @ w1 + p["b1"], 0.0), rounding)
     h2 = _r(np.maximum(h1 @ w2 + p["b2"], 0.0), rounding)
@@ -125,14 +127,15 @@ def forward(p: Dict[str, np.ndarray], x: np.ndarray, y: np.ndarray = None, round
     acts = {"x": x, "h1": h1, "h2": h2, "z": z}
     if y is None:
         return acts, None
-    loss = float(np.sum(np.maximum(z, 0) - z * y + np.log1p(np.exp(-np.abs(z)))))
-    return acts, loss
+    if loss == "mse":
+        return acts, float(np.sum(0.5 * (z - y) ** 2))
+    return acts, float(np.sum(np.maximum(z, 0) - z * y + np.log1p(np.exp(-np.abs(z)))))
 
 
-def backward(p, acts, y, scale: float, rounding: bool = False):
+def backward(p, acts, y, scale: float, rounding: bool = False, loss: str = "bce"):
     """Gradients of scale * loss."""
     x, h1, h2, z = acts["x"], acts["h1"], acts["h2"], acts["z"]
-    dz = (1.0 / (1.0 + np.exp(-z)) - y) * scale
+    dz = ((z - y) if loss == "mse" else (1.0 / (1.0 + np.exp(-z)) - y)) * scale
     g = {"w3": h2.T @ dz, "b3": dz.sum(0)}
     dh2 = _r((dz @ p["w3"].T) * (h2 > 0), rounding)
     g["w2"] = h1.T @ dh2
@@ -152,13 +155,20 @@ def adamw(p, g, m, v, lr, b1, b2, eps, wd, step):
     return p, m, v
 
 
-def predicted_f1(z: np.ndarray, n_pos: int, n_neg: int, base: np.ndarray = None) -> np.ndarray:
-    """F1 of the predicted coverage: p = sigmoid(z0) P_b, q = sigmoid(z1) N_b,
-    F1 = 2p / (2p + q + (|P| - p)); (P_b, N_b) = base[b] (a parent's coverage,
-    when the logits predict the shares of it a refinement keeps), else (|P|, |Ng|)."""
+def predicted_f1(z: np.ndarray, n_pos: int, n_neg: int, base: np.ndarray = None,
+                 kind: str = "share") -> np.ndarray:
+    """F1 of the predicted coverage (p, q), F1 = 2p / (2p + q + (|P| - p)), with
+    (P_b, N_b) = base[b] (a parent's coverage) or (|P|, |Ng|):
+    kind "share": p = sigmoid(z0) P_b, q = sigmoid(z1) N_b;
+    kind "log_removed": p = P_b - (e^z0 - 1), q = N_b - (e^z1 - 1), with z
+    taken as at least 0 and p, q clamped to [0, base]."""
     bp = np.full(z.shape[0], float(n_pos)) if base is None else np.asarray(base, dtype=np.float64)[:, 0]
     bn = np.full(z.shape[0], float(n_neg)) if base is None else np.asarray(base, dtype=np.float64)[:, 1]
-    p = bp / (1.0 + np.exp(-z[:, 0]))
-    q = bn / (1.0 + np.exp(-z[:, 1]))
+    if kind == "log_removed":
+        p = np.clip(bp - np.expm1(np.maximum(z[:, 0], 0.0)), 0.0, bp)
+        q = np.clip(bn - np.expm1(np.maximum(z[:, 1], 0.0)), 0.0, bn)
+    else:
+        p = bp / (1.0 + np.exp(-z[:, 0]))
+        q = bn / (1.0 + np.exp(-z[:, 1]))
     den = p + q + n_pos
     return np.where(den > 0, 2 * p / np.maximum(den, 1e-30), 0.0)

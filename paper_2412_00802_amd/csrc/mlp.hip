@@ -246,12 +246,14 @@ k_gemm_bf16(int M, int N, int K, const __bf16* __restrict__ A, int lda, const __
 // ---------------------------------------------------------------------------
 // the 2-wide output layer, loss and its gradient
 // ---------------------------------------------------------------------------
-// z[b][o] = sum_k h[b][k] w[k][o] + bias[o]; with targets y: per-element
-// BCE-with-logits and dz = (sigmoid(z) - y) * scale; loss summed into *loss.
+// z[b][o] = sum_k h[b][k] w[k][o] + bias[o]; with targets y: per element
+// either BCE-with-logits, dz = (sigmoid(z) - y) * scale (kind 0), or the
+// squared error (z - y)^2 / 2, dz = (z - y) * scale (kind 1); loss summed
+// into *loss.
 __global__ void k_head_forward(const __bf16* __restrict__ h, int Bn, int Kd, const float* __restrict__ w,
                                const float* __restrict__ bias, float* __restrict__ z,
                                const float* __restrict__ y, float* __restrict__ dz, float scale,
-                               float* __restrict__ loss) {
+                               float* __restrict__ loss, int kind) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   float l = 0.f;
   if (b < Bn) {
@@ -268,8 +270,13 @@ __global__ void k_head_forward(const __bf16* __restrict__ h, int Bn, int Kd, con
       const float zz[2] = {z0, z1};
       for (int o = 0; o < 2; ++o) {
         const float t = y[2 * b + o], v = zz[o];
-        l += fmaxf(v, 0.f) - v * t + log1pf(expf(-fabsf(v)));
-        dz[2 * b + o] = (1.f / (1.f + expf(-v)) - t) * scale;
+        if (kind == 0) {
+          l += fmaxf(v, 0.f) - v * t + log1pf(expf(-fabsf(v)));
+          dz[2 * b + o] = (1.f / (1.f + expf(-v)) - t) * scale;
+        } else {
+          l += 0.5f * (v - t) * (v - t);
+          dz[2 * b + o] = (v - t) * scale;
+        }
       }
     }
   }
@@ -279,16 +286,25 @@ __global__ void k_head_forward(const __bf16* __restrict__ h, int Bn, int Kd, con
   }
 }
 
-// predicted F1 of each candidate from its two logits: p = sigmoid(z0) P_b,
-// q = sigmoid(z1) N_b, F1 = 2p / (p + q + |P|), where (P_b, N_b) is the
-// candidate's base coverage (its parent's, when the logits predict the share
-// of the parent's coverage it keeps) or (|P|, |Ng|)
+// predicted F1 of each candidate from its two outputs, F1 = 2p / (p + q + |P|),
+// with (P_b, N_b) the candidate's base coverage (its parent's) or (|P|, |Ng|):
+//   kind 0: the outputs are logits of the kept shares, p = sigmoid(z0) P_b,
+//           q = sigmoid(z1) N_b;
+//   kind 1: the outputs are log(1 + removed count), p = P_b - expm1(z0) and
+//           q = N_b - expm1(z1), each clamped to [0, base].
 __global__ void k_head_score(const float* __restrict__ z, int Bn, float n_pos, float n_neg,
-                             const uint32_t* __restrict__ base, float* __restrict__ score) {
+                             const uint32_t* __restrict__ base, int kind, float* __restrict__ score) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= Bn) return;
   const float bp = base ? (float)base[2 * b] : n_pos, bn = base ? (float)base[2 * b + 1] : n_neg;
-  const float p = bp / (1.f + expf(-z[2 * b])), q = bn / (1.f + expf(-z[2 * b + 1]));
+  float p, q;
+  if (kind == 0) {
+    p = bp / (1.f + expf(-z[2 * b]));
+    q = bn / (1.f + expf(-z[2 * b + 1]));
+  } else {
+    p = fminf(fmaxf(bp - expm1f(fmaxf(z[2 * b], 0.f)), 0.f), bp);
+    q = fminf(fmaxf(bn - expm1f(fmaxf(z[2 * b + 1], 0.f)), 0.f), bn);
+  }
   const float den = p + q + n_pos;
   score[b] = den > 0.f ? 2.f * p / den : 0.f;
 }
@@ -484,21 +500,24 @@ extern "C" hth_status hth_gemm_bf16(int trans_a, int trans_b, int M, int N, int 
 
 extern "C" hth_status hth_head_forward(const uint16_t* h, int Bn, int Kd, const float* w, const float* bias,
                                        float* z, const float* y, float* dz, float scale, float* loss,
-                                       void* stream) {
+                                       int loss_kind, void* stream) {
   if (!h || !w || !bias || !z || (y && !dz)) return fail(HTH_E_INVALID, "NULL argument");
+  if (loss_kind != 0 && loss_kind != 1) return fail(HTH_E_RANGE, "loss_kind must be 0 or 1");
   if (Bn <= 0) return HTH_OK;
   hipLaunchKernelGGL(k_head_forward, dim3((Bn + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream),
-                     reinterpret_cast<const __bf16*>(h), Bn, Kd, w, bias, z, y, dz, scale, loss);
+                     reinterpret_cast<const __bf16*>(h), Bn, Kd, w, bias, z, y, dz, scale, loss, loss_kind);
   HTH_HIP(hipGetLastError());
   return HTH_OK;
 }
 
 extern "C" hth_status hth_head_score(const float* z, int Bn, float n_pos, float n_neg, const uint32_t* base,
-                                     float* score, void* stream) {
+                                     int kind, float* score, void* stream) {
   if (!z || !score) return fail(HTH_E_INVALID, "NULL argument");
+  if (kind != 0 && kind != 1) return fail(HTH_E_RANGE, "kind must be 0 or 1");
+  if (kind == 1 && !base) return fail(HTH_E_INVALID, "kind 1 needs the base coverage");
   if (Bn <= 0) return HTH_OK;
   hipLaunchKernelGGL(k_head_score, dim3((Bn + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream),
-                     z, Bn, n_pos, n_neg, base, score);
+                     z, Bn, n_pos, n_neg, base, kind, score);
   HTH_HIP(hipGetLastError());
   return HTH_OK;
 }

@@ -102,9 +102,9 @@ def lib() -> ctypes.CDLL:
             "hth_densify": [P, P, U32, U32, P, P],
             "hth_densify_delta": [P, P, U32, U32, P, P, P, P, P],
             "hth_gemm_bf16": [I, I, I, I, I, P, I, P, I, P, I, P, I, P, I, P, I, P],
-            "hth_head_forward": [P, I, I, P, P, P, P, P, F, P, P],
+            "hth_head_forward": [P, I, I, P, P, P, P, P, F, P, I, P],
             "hth_head_backward": [P, I, I, P, P, P, P, P],
-            "hth_head_score": [P, I, F, F, P, P, P],
+            "hth_head_score": [P, I, F, F, P, I, P, P],
             "hth_colsum": [P, I, I, I, P, P],
             "hth_adamw": [P, P, P, P, P, S, F, F, F, F, F, I, P],
             "hth_to_bf16": [P, P, S, P],
@@ -295,13 +295,13 @@ def hth_gemm_bf16(trans_a: int, trans_b: int, M: int, N: int, K: int, A, lda: in
 
 
 def hth_head_forward(h, Bn: int, Kd: int, w, bias, z, y=None, dz=None, scale: float = 1.0, loss=None,
-                     stream=None) -> None:
+                     stream=None, loss_kind: int = 0) -> None:
     _check(lib().hth_head_forward(_ptr(h), Bn, Kd, _ptr(w), _ptr(bias), _ptr(z), _ptr(y), _ptr(dz),
-                                  scale, _ptr(loss), _stream(stream)))
+                                  scale, _ptr(loss), loss_kind, _stream(stream)))
 
 
-def hth_head_score(z, Bn: int, n_pos: float, n_neg: float, score, stream=None, base=None) -> None:
-    _check(lib().hth_head_score(_ptr(z), Bn, n_pos, n_neg, _ptr(base) if base is not None else None,
+def hth_head_score(z, Bn: int, n_pos: float, n_neg: float, score, stream=None, base=None, kind: int = 0) -> None:
+    _check(lib().hth_head_score(_ptr(z), Bn, n_pos, n_neg, _ptr(base) if base is not None else None, kind,
                                 _ptr(score), _stream(stream)))
 
 

@@ -38,6 +38,12 @@ def coverage_targets(counts: np.ndarray, n_pos: int, n_neg: int, base: np.ndarra
     return np.where(b > 0, c / np.maximum(b, 1), 0.0).astype(np.float32)
 
 
+def removal_targets(counts: np.ndarray, base: np.ndarray) -> np.ndarray:
+    """log(1 + positives and negatives a refinement removes from its parent)."""
+    d = np.maximum(np.asarray(base, dtype=np.float64) - counts.astype(np.float64), 0.0)
+    return np.log1p(d).astype(np.float32)
+
+
 def gather_training_pairs(eng, kb, n_pairs, per_round, beam, rng, chunk):
     """Refinement rounds from top; every candidate is evaluated exactly.
     Returns the candidates, their counts, their parents' counts, the parents
@@ -81,17 +87,17 @@ def train(scr: Screener, fb: FeatureBatch, y_dev, n: int, epochs: int, batch: in
 
 
 def score(scr: Screener, fb: FeatureBatch, n: int, n_pos: int, n_neg: int, out, base=None,
-          parents: FeatureBatch = None, parent_index=None) -> None:
+          parents: FeatureBatch = None, parent_index=None, kind: int = 0) -> None:
     """Predicted F1 of candidates [0, n); base (device uint32 [n][2]): the
-    parents' coverage when the screener predicts kept shares; parents: features
-    relative to the parents."""
+    parents' coverage (kept shares, kind 0, or removed counts, kind 1);
+    parents: features relative to the parents."""
     B = scr.batch
     for r0 in range(0, n, B):
         m = min(B, n - r0)
         fb.densify(r0, m, scr.x, parents, parent_index)
         z = scr.logits(m)
         hthedl.hth_head_score(z, m, float(n_pos), float(n_neg), out[r0:r0 + m],
-                              base=None if base is None else base[r0:r0 + m])
+                              base=None if base is None else base[r0:r0 + m], kind=kind)
 
 
 def main():
@@ -104,6 +110,9 @@ def main():
     ap.add_argument("--top", type=float, default=0.02)
     ap.add_argument("--audit", type=float, default=0.005)
     ap.add_argument("--k", type=int, default=100)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--sweep", default="0.02,0.05,0.1",
+                    help="top fractions at which the delta screener's recall and speed are also reported")
     args = ap.parse_args()
     import torch
 
@@ -138,15 +147,20 @@ def main():
     # 2. training: "relative" predicts the shares of the parent's coverage a
     # refinement keeps (the parent was evaluated exactly); "absolute" the
     # covered fractions of the examples
-    # "delta": shares of the parent's coverage from features relative to the parent
+    # "delta": shares of the parent's coverage from features relative to the
+    # parent; "logdelta": log(1 + removed positives / negatives) from the same
+    # features, with the squared error
     models = {}
-    for mode in ("delta", "relative", "absolute"):
-        y = torch.from_numpy(coverage_targets(counts, eng.n_pos, eng.n_neg,
-                                              None if mode == "absolute" else pcounts)).cuda()
-        scr = Screener(init_params(seed=11), batch=8192, lr=1e-3)
+    for mode in ("logdelta", "delta", "relative", "absolute"):
+        if mode == "logdelta":
+            y = torch.from_numpy(removal_targets(counts, pcounts)).cuda()
+        else:
+            y = torch.from_numpy(coverage_targets(counts, eng.n_pos, eng.n_neg,
+                                                  None if mode == "absolute" else pcounts)).cuda()
+        scr = Screener(init_params(seed=11), batch=8192, lr=args.lr, loss="mse" if mode == "logdelta" else "bce")
         t = time.perf_counter()
         losses = train(scr, fb, y, n_tr, args.epochs, 1024, rng,
-                       *((tpfb, tpi) if mode == "delta" else (None, None)))
+                       *((tpfb, tpi) if mode in ("delta", "logdelta") else (None, None)))
         models[mode] = (scr, losses, time.perf_counter() - t)
 
     # 3. candidates: the best `beam` evaluated so far, each refined
@@ -193,10 +207,12 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         cfb.recompute()
-        if mode == "delta":
+        rel = mode in ("delta", "logdelta")
+        if rel:
             cpfb.recompute()
         score(scr, cfb, n, eng.n_pos, eng.n_neg, scores, base=None if mode == "absolute" else cbase,
-              parents=cpfb if mode == "delta" else None, parent_index=cpi if mode == "delta" else None)
+              parents=cpfb if rel else None, parent_index=cpi if rel else None,
+              kind=1 if mode == "logdelta" else 0)
         hthedl.hth_topk(scores, n, n_sel, sel, work)
         chosen = np.union1d(sel.cpu().numpy().astype(np.int64), audit)
         sub = hthedl.gather_encoded(cenc, chosen)
@@ -216,10 +232,41 @@ def main():
                      "train_loss_first_last": [round(losses[0], 5), round(losses[-1], 5)]}
         log(f"[screen] {mode}: recall@{args.k} {res[mode][f'recall_at_{args.k}']:.2f}, "
             f"{res[mode]['speedup']}x the exhaustive rate")
+    # recall and speed of the logdelta screener at other exact budgets (its scores
+    # are computed again: the timing covers the whole screened pipeline)
+    sweep = []
+    scr_d = models["logdelta"][0]
+    for frac in [float(v) for v in args.sweep.split(",") if v]:
+        m_sel = int(round(frac * n))
+        sel_m = torch.empty(m_sel, dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cfb.recompute()
+        cpfb.recompute()
+        score(scr_d, cfb, n, eng.n_pos, eng.n_neg, scores, base=cbase, parents=cpfb, parent_index=cpi, kind=1)
+        hthedl.hth_topk(scores, n, m_sel, sel_m, work)
+        chosen = np.union1d(sel_m.cpu().numpy().astype(np.int64), audit)
+        sc = torch.empty((chosen.size, 2), dtype=torch.int32, device="cuda")
+        eng.eval_batch(None, counts=sc, chunk=chunk, encoded=hthedl.gather_encoded(cenc, chosen))
+        sc_np = sc.cpu().numpy().view(np.uint32)
+        got = chosen[search.top_indices(sc_np, eng.n_pos, args.k)]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        sweep.append({"top_fraction": frac, "exact_budget": int(chosen.size),
+                      f"recall_at_{args.k}": search.recall_at(got, exact_top), "speedup": round(t_exh / dt, 3)})
+        log(f"[screen] logdelta at top {frac}: recall {sweep[-1][f'recall_at_{args.k}']:.2f}, "
+            f"{sweep[-1]['speedup']}x")
+    # where the exact top-k sit in the logdelta screener's order (percentiles)
+    order = np.argsort(-scores.cpu().numpy(), kind="stable")
+    pos_in = np.empty(n, dtype=np.int64)
+    pos_in[order] = np.arange(n)
+    pct = np.sort(pos_in[exact_top] / n * 100.0)
+    log(f"[screen] exact top-{args.k} at screener percentiles: median {np.median(pct):.3f}, "
+        f"worst {', '.join(f'{v:.2f}' for v in pct[-8:])}")
     # ties at the k-th exact F1 make part of the exact top-k a matter of the index tie-break
     kth = np.sort(f_np)[::-1][args.k - 1] if n >= args.k else 0.0
     ties = int(np.sum(np.isclose(f_np, kth, rtol=0, atol=1e-12)))
-    budget = res["delta"]["exact_budget"]
+    budget = res["logdelta"]["exact_budget"]
     rand = rng.choice(n, size=budget, replace=False)
     rand_top = rand[search.top_indices(all_np[rand], eng.n_pos, args.k)]
     pf1 = search.f1_float(counts[top], eng.n_pos)[parent_of]
@@ -229,7 +276,7 @@ def main():
         "workload": f"screened search on the {cfg.name} KB ({kb.n:,} individuals)",
         "candidates": n, "top_fraction": args.top, "audit_fraction": args.audit,
         "exhaustive_hyp_per_s": round(n / t_exh, 1), "exhaustive_seconds": round(t_exh, 4),
-        "screener": res, f"candidates_tied_at_kth_f1": ties,
+        "screener": res, "logdelta_budget_sweep": sweep, f"candidates_tied_at_kth_f1": ties,
         f"random_recall_at_{args.k}": search.recall_at(rand_top, exact_top),
         f"parent_f1_recall_at_{args.k}": search.recall_at(heur_top, exact_top),
         "training_pairs": len(hyps), "pairs_seconds": round(t_pairs, 2),

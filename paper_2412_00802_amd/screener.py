@@ -1,9 +1,11 @@
 """The learned screener: a bf16 MLP over hashed subtree features that ranks
 refinement candidates by predicted F1 (a project extension, not in the paper).
 
-Layers: 4096 -> 1024 -> 256 -> 2 with ReLU; the two outputs are logits of the
-covered fractions pos/|P| and neg/|Ng|, trained with BCE-with-logits and
-AdamW on fp32 master weights.  Every product, activation, loss, gradient and
+Layers: 4096 -> 1024 -> 256 -> 2 with ReLU.  The two outputs are either
+logits of covered fractions (of the examples, or of a parent's coverage),
+trained with BCE-with-logits, or log(1 + positives/negatives a refinement
+removes from its parent), trained with the squared error; AdamW on fp32
+master weights.  Every product, activation, loss, gradient and
 optimiser update runs in the library's kernels (hth_gemm_bf16 on MFMA and
 friends); this module only sequences the calls and owns the device buffers.
 """
@@ -36,9 +38,12 @@ class Screener:
     """Device-resident MLP with its optimiser state and per-batch buffers."""
 
     def __init__(self, params: Dict[str, np.ndarray], batch: int = 1024, device: str = "cuda",
-                 lr: float = 1e-3, weight_decay: float = 1e-4):
+                 lr: float = 1e-3, weight_decay: float = 1e-4, loss: str = "bce"):
+        """loss: "bce" (targets are fractions, BCE-with-logits) or "mse"
+        (real targets, squared error)."""
         import torch
         self.t = torch
+        self.loss_kind = {"bce": 0, "mse": 1}[loss]
         self.dev = torch.device(device)
         self.batch = batch
         self.lr, self.wd = lr, weight_decay
@@ -81,7 +86,7 @@ class Screener:
         G = hthedl.hth_gemm_bf16
         self.forward(n, x)
         hthedl.hth_head_forward(self.h2, n, D_H2, self.p["w3"], self.p["b3"], self.z, y, self.dz,
-                                1.0 / (2 * n), self.loss)
+                                1.0 / (2 * n), self.loss, loss_kind=self.loss_kind)
         hthedl.hth_head_backward(self.h2, n, D_H2, self.p["w3"], self.dz, self.g["w3"], self.dh2)
         hthedl.hth_colsum(self.dz, 0, n, D_OUT, self.g["b3"])
         G(1, 0, D_H1, D_H2, n, self.h1, D_H1, self.dh2, D_H2, c32=self.g["w2"], ldc=D_H2)

@@ -187,7 +187,7 @@ def main():
     ap.add_argument("--rounds", type=int, default=16)
     ap.add_argument("--per-round", type=int, default=16384)
     ap.add_argument("--beam", type=int, default=256)
-    ap.add_argument("--chunk", type=int, default=4096)
+    ap.add_argument("--chunk", type=int, default=16384, help="candidates compiled together (a round by default)")
     ap.add_argument("--cache-rows", type=int, default=4096)
     ap.add_argument("--no-cache", action="store_true")
     ap.add_argument("--compare", action="store_true", help="also run the trace without the set table and "

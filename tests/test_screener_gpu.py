@@ -146,6 +146,16 @@ def test_head_loss_and_backward(torch):
     dzg = dz.cpu().numpy().astype(np.float64)
     np.testing.assert_allclose(dw.cpu().numpy(), hr.T @ dzg, rtol=1e-4, atol=1e-8)
     np.testing.assert_allclose(f64(torch, dh), S.bf16((dzg @ w.T) * (hr > 0)), rtol=1e-2, atol=1e-9)
+    # the squared-error head (regression of log(1 + removed count))
+    yl = (rng.random((Bn, 2)) * 8).astype(np.float32)
+    Yl = torch.from_numpy(yl).cuda()
+    loss.zero_()
+    hthedl.hth_head_forward(H, Bn, Kd, W, Bb, z, Yl, dz, scale, loss, loss_kind=1)
+    lr = 0.5 * np.sum((zr - yl) ** 2)
+    assert abs(loss.item() - lr) <= 1e-4 * abs(lr)
+    np.testing.assert_allclose(dz.cpu().numpy(), (zr - yl) * scale, rtol=1e-4, atol=1e-7)
+    with pytest.raises(hthedl.HthError):
+        hthedl.hth_head_forward(H, Bn, Kd, W, Bb, z, Yl, dz, scale, loss, loss_kind=2)
 
 
 def test_adamw_matches_reference(torch):
@@ -240,3 +250,10 @@ def test_head_score_with_and_without_base(torch):
     hthedl.hth_head_score(Z, n, float(n_pos), float(n_neg), out, base=B)
     np.testing.assert_allclose(out.cpu().numpy(), S.predicted_f1(z.astype(np.float64), n_pos, n_neg, base),
                                rtol=2e-5, atol=1e-7)
+    zl = (rng.random((n, 2)) * 10 - 1).astype(np.float32)       # log(1 + removed), some below 0
+    hthedl.hth_head_score(torch.from_numpy(zl).cuda(), n, float(n_pos), float(n_neg), out, base=B, kind=1)
+    np.testing.assert_allclose(out.cpu().numpy(),
+                               S.predicted_f1(zl.astype(np.float64), n_pos, n_neg, base, kind="log_removed"),
+                               rtol=1e-4, atol=1e-6)
+    with pytest.raises(hthedl.HthError):
+        hthedl.hth_head_score(Z, n, float(n_pos), float(n_neg), out, kind=1)

@@ -12,14 +12,15 @@ def small_params(rng, d_in=24, h1=16, h2=8, scale=0.4):
             "w3": rng.standard_normal((h2, 2)) * scale, "b3": rng.standard_normal(2) * 0.1}
 
 
-def test_gradients_match_central_differences():
+@pytest.mark.parametrize("loss", ["bce", "mse"])
+def test_gradients_match_central_differences(loss):
     rng = np.random.default_rng(0)
     p = small_params(rng)
     x = rng.integers(0, 3, size=(7, 24)).astype(np.float64)
-    y = rng.random((7, 2))
+    y = rng.random((7, 2)) * (5 if loss == "mse" else 1)
     scale = 1.0 / 14
-    acts, _ = S.forward(p, x, y)
-    g = S.backward(p, acts, y, scale)
+    acts, _ = S.forward(p, x, y, loss=loss)
+    g = S.backward(p, acts, y, scale, loss=loss)
     eps = 1e-6
     for name in ("w1", "b1", "w2", "b2", "w3", "b3"):
         flat = p[name].reshape(-1)
@@ -27,9 +28,9 @@ def test_gradients_match_central_differences():
         for i in idx:
             old = flat[i]
             flat[i] = old + eps
-            lp = S.forward(p, x, y)[1] * scale
+            lp = S.forward(p, x, y, loss=loss)[1] * scale
             flat[i] = old - eps
-            lm = S.forward(p, x, y)[1] * scale
+            lm = S.forward(p, x, y, loss=loss)[1] * scale
             flat[i] = old
             num = (lp - lm) / (2 * eps)
             ana = g[name].reshape(-1)[i]
@@ -102,3 +103,14 @@ def test_delta_features_cancel_unchanged_subtrees():
     want[S.subtree_features(parent)[-1][1]] -= 1
     np.testing.assert_array_equal(d, want)
     assert not S.delta_features([parent], [parent], [0]).any()
+
+
+def test_predicted_f1_from_log_removed_counts():
+    """z = log(1 + removed): z = 0 keeps the base; z = log(1 + r) removes r
+    (exactly, up to rounding); removals beyond the base clamp to 0."""
+    n_pos, n_neg = 100, 300
+    base = np.array([[40, 10], [40, 10], [40, 10]])
+    z = np.array([[0.0, 0.0], [np.log1p(5.0), np.log1p(4.0)], [20.0, 20.0]])
+    f = S.predicted_f1(z, n_pos, n_neg, base, kind="log_removed")
+    np.testing.assert_allclose(f, [2 * 40 / (40 + 10 + 100), 2 * 35 / (35 + 6 + 100), 0.0], rtol=1e-12)
+    assert S.predicted_f1(np.array([[-3.0, -1.0]]), n_pos, n_neg, base[:1], kind="log_removed")[0] == f[0]
