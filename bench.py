@@ -127,6 +127,23 @@ def summarize(kt_dir: str, fetch_dir: str, write_dir: str, command: str, out_md:
     json.dump(out, open(traffic_file, "w"), indent=1)
 
 
+def summarize_trace(kt_dir: str, command: str, out_md: str, title: str) -> None:
+    """Kernel-time table of one rocprofv3 --kernel-trace --stats run."""
+    import csv
+    import glob
+    stats = []
+    for f in glob.glob(os.path.join(kt_dir, "*kernel_stats.csv")):
+        stats += list(csv.DictReader(open(f)))
+    lines = [f"# rocprofv3 summary: {title}", "", "Command:", "",
+             "    " + command.format(opts="--kernel-trace --stats --output-format csv"), "",
+             "| kernel | calls | avg us | total ms | total % |", "|---|---|---|---|---|"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:16]:
+        lines.append(f"| {r['Name'].split('(')[0].replace('void ', '')[:60]} | {r['Calls']} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['TotalDurationNs']) / 1e6:.1f} | "
+                     f"{float(r['Percentage']):.1f} |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -180,9 +197,15 @@ def main():
     ap.add_argument("--summary-out", default=os.path.join(ROOT, "profiles", "k_group_c2.md"))
     ap.add_argument("--summary-sha", default=None, help="kernel source hash of the profiled build")
     ap.add_argument("--summary-tcc", default=None, help="rocprofv3 output of the L2 hit/miss pass")
+    ap.add_argument("--summarize-trace", default=None, metavar="KT_DIR",
+                    help="write only the kernel-time table of a kernel-trace run")
+    ap.add_argument("--summary-title", default="")
     ap.add_argument("--summary-command", default="rocprofv3 {opts} -d OUT -o run -- python3 bench.py "
                     "--steps 2 --warmup 1 --plain 0 --cpu-sample 0 --no-profile --calibrate-copy")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.summary_command, args.summary_out, args.summary_title)
+        return
     if args.summarize:
         summarize(*args.summarize, args.summary_command, args.summary_out, args.summary_sha,
                   tcc_dir=args.summary_tcc)

@@ -716,9 +716,9 @@ hth_status run_plan(hth_kb_s& kb, const Plan& P, char* ws, size_t ws_bytes, uint
   const uint32_t* code = reinterpret_cast<const uint32_t*>(ws + o_code);
   Launcher Lc{kb, st};
   if (!thr_groups.empty()) {
+    // about 32 words per wave: enough independent column loads in flight
     const uint32_t n = (uint32_t)thr_groups.size();
-    uint32_t bpt = std::max<uint32_t>(1, (4 * kb.n_cu + n - 1) / n);
-    bpt = std::min<uint32_t>(bpt, (kb.W + 3) / 4);
+    const uint32_t bpt = std::max<uint32_t>(1, (kb.W + 127) / 128);
     const double bytes = n * 4.0 * kb.N + thr_tasks.size() * 8.0 * kb.W;
     hth_status s = Lc.run(HTH_K_THRESHOLD, bytes, [&] {
       hipLaunchKernelGGL(k_threshold, dim3(bpt * n), dim3(256), 0, st, d, thg, thr, bpt);
