@@ -5,13 +5,16 @@ MLP over hashed subtree features that ranks refinement candidates.  These
 references define what its kernels compute:
 
 * ``subtree_features``: the hashed subtree features of a hypothesis given as a
-  nested tuple, node by node in postfix order;
+  nested tuple, node by node in postfix order; ``dense_features`` and
+  ``delta_features`` (a refinement's counts minus its parent's);
 * ``bf16``: float32 -> bfloat16 round-to-nearest-even, returned as float64;
 * ``forward`` / ``backward``: the MLP 4096 -> 1024 -> 256 -> 2 with ReLU and
-  BCE-with-logits on the two covered fractions, in float64, either exact
-  (``rounding=False``, pinned by finite differences in the tests) or with the
-  bf16 roundings the kernels apply to their stored operands and activations;
-* ``adamw``: one AdamW step with decoupled weight decay.
+  either BCE-with-logits (targets are fractions) or the squared error
+  (targets are log(1 + removed counts)), in float64, exact (``rounding=False``,
+  pinned by finite differences in the tests) or with the bf16 roundings the
+  kernels apply to their stored operands and activations;
+* ``adamw``: one AdamW step with decoupled weight decay;
+* ``predicted_f1``: the screening score from the two outputs.
 
 Parity status: the MLP gradients are pinned by central finite differences;
 the feature hash and the optimiser step follow their written definitions.

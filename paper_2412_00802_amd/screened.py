@@ -106,11 +106,11 @@ def main():
     ap.add_argument("--pairs", type=int, default=200_000)
     ap.add_argument("--candidates-beam", type=int, default=4096)
     ap.add_argument("--refinements", type=int, default=256)
-    ap.add_argument("--epochs", type=int, default=10)
+    ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--top", type=float, default=0.02)
     ap.add_argument("--audit", type=float, default=0.005)
     ap.add_argument("--k", type=int, default=100)
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr", type=float, default=5e-4)
     ap.add_argument("--sweep", default="0.02,0.05,0.1",
                     help="top fractions at which the delta screener's recall and speed are also reported")
     args = ap.parse_args()

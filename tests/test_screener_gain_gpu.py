@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from paper_2412_00802_amd import hthedl, search, synth
-from paper_2412_00802_amd.screened import coverage_targets, gather_training_pairs, score, train
+from paper_2412_00802_amd.screened import gather_training_pairs, removal_targets, score, train
 from paper_2412_00802_amd.screener import FeatureBatch, Screener, init_params
 
 pytestmark = pytest.mark.gpu
@@ -34,11 +34,11 @@ def test_screener_beats_random_selection():
     fb = FeatureBatch(*hthedl.encode_batch(hyps))
     tpfb = FeatureBatch(*hthedl.encode_batch(tparents))
     tpi = torch.from_numpy(tpidx.astype(np.int32)).cuda()
-    # the screener predicts the shares of the (exactly known) parent coverage a
-    # refinement keeps, from features relative to the parent
-    y = torch.from_numpy(coverage_targets(counts, eng.n_pos, eng.n_neg, pcounts)).cuda()
-    scr = Screener(init_params(seed=11), batch=4096, lr=1e-3)
-    losses = train(scr, fb, y, len(hyps), 8, 512, rng, tpfb, tpi)
+    # the screener predicts log(1 + positives and negatives a refinement removes
+    # from its exactly evaluated parent), from features relative to the parent
+    y = torch.from_numpy(removal_targets(counts, pcounts)).cuda()
+    scr = Screener(init_params(seed=11), batch=4096, lr=5e-4, loss="mse")
+    losses = train(scr, fb, y, len(hyps), 16, 512, rng, tpfb, tpi)
     say(f"[gain] {len(hyps)} pairs, loss {losses[0]:.4f} -> {losses[-1]:.4f}")
     assert losses[-1] < losses[0]
     # fresh candidates: refinements of the best 128 hypotheses seen
@@ -58,7 +58,7 @@ def test_screener_beats_random_selection():
     scores = torch.empty(n, dtype=torch.float32, device="cuda")
     base = torch.from_numpy(np.asarray(base, dtype=np.uint32).view(np.int32)).cuda()
     score(scr, cfb, n, eng.n_pos, eng.n_neg, scores, base=base, parents=pfb,
-          parent_index=torch.from_numpy(np.asarray(pidx, dtype=np.int32)).cuda())
+          parent_index=torch.from_numpy(np.asarray(pidx, dtype=np.int32)).cuda(), kind=1)
     exact = eng.eval_batch(cands, chunk=8192)
     k, budget = 50, n // 20
     want = search.top_indices(exact, eng.n_pos, k)
