@@ -121,13 +121,9 @@ constexpr int kRegDepth = 6;     // D: most stack entries a program may need
 template <int D, int R>
 __global__ void __launch_bounds__(256)
 k_region_reg(DevKB kb, const RegionTask* __restrict__ tasks, const uint32_t* __restrict__ code,
-             uint32_t n_tasks, uint32_t tiles) {
+             uint32_t n_tasks) {
   __shared__ uint32_t s_pq[2][4];
-  // (tile, task) items, task fastest so that blocks running together share the
-  // tile's example and common leaf words in L2; a grid-stride loop over items
-  const uint64_t n_items = (uint64_t)tiles * n_tasks;
-  for (uint64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-  const uint32_t tile = (uint32_t)(item / n_tasks), task = (uint32_t)(item % n_tasks);
+  const uint32_t tile = blockIdx.x / n_tasks, task = blockIdx.x % n_tasks;
   const RegionTask T = tasks[task];
   const uint32_t tid = threadIdx.x;
   const uint32_t w0 = tile * (256 * R) + tid;
@@ -201,8 +197,6 @@ k_region_reg(DevKB kb, const RegionTask* __restrict__ tasks, const uint32_t* __r
       if (P) atomicAdd(kb.counts + 2 * T.cover, P);
       if (Q) atomicAdd(kb.counts + 2 * T.cover + 1, Q);
     }
-    __syncthreads();   // s_pq is written again by the next item
-  }
   }
 }
 
@@ -495,11 +489,9 @@ hth_status launch_regions(Launcher& L, const DevKB& d, const RegionTask* tasks, 
   }
   if (depth <= kRegDepth && L.kb.tune.region_reg) {
     const uint32_t tiles = (d.S + 256 * kRegWords - 1) / (256 * kRegWords);
-    const uint64_t items = (uint64_t)tiles * n;
-    const uint32_t grid = (uint32_t)std::min<uint64_t>(items, 64ull * L.kb.n_cu);
     return L.run(HTH_K_REGION, bytes, [&] {
-      hipLaunchKernelGGL((k_region_reg<kRegDepth, kRegWords>), dim3(grid), dim3(256), 0, L.st, d,
-                         tasks, code, n, tiles);
+      hipLaunchKernelGGL((k_region_reg<kRegDepth, kRegWords>), dim3(tiles * n), dim3(256), 0, L.st, d,
+                         tasks, code, n);
     });
   }
   const uint32_t tiles = (d.S + kRegionThreads - 1) / kRegionThreads;
