@@ -247,8 +247,9 @@ hth_status hth_profile_end(hth_kb kb, hth_prof_entry* out /* [HTH_K_NUM] */);
  * for NOT and role constructs by the child's hash (8 LE bytes) and for AND/OR
  * by the wrapping sum of splitmix64(child hash) over the children (8 LE bytes,
  * order independent).  d_feat[i] = hash[i] mod 4096.  d_hash: scratch uint64
- * [n_nodes].  A malformed child index sets *d_bad to 1 and hashes the node as
- * 0; nothing traps. */
+ * [n_nodes].  A malformed child index, or an op that is not a DL construct
+ * (HTH_SET leaves carry no syntax to hash), sets *d_bad to 1 and hashes the
+ * node as 0; nothing traps. */
 hth_status hth_features(const hth_node* d_nodes, const uint32_t* d_hyp_node_offsets, uint32_t n_hyps,
                         const uint32_t* d_children, uint32_t n_children, uint64_t* d_hash,
                         uint16_t* d_feat, uint32_t* d_bad, void* stream);

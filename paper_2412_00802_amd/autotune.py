@@ -42,10 +42,10 @@ def candidates(n_individuals: int) -> List[Dict[str, int]]:
             continue
         for budget in sorted({max(64, 8 * t_mb), 64}):
             for unroll in (8, 16):
-                out.append(dict(group_min=4, group_k=k, xcd_local=1, t_budget_mb=max(budget, t_mb),
+                out.append(dict(group_min=2, group_k=k, xcd_local=1, t_budget_mb=max(budget, t_mb),
                                 unroll=unroll))
         for budget in sorted({t_mb, 4 * t_mb}):
-            out.append(dict(group_min=4, group_k=k, xcd_local=0, t_budget_mb=budget, unroll=16))
+            out.append(dict(group_min=2, group_k=k, xcd_local=0, t_budget_mb=budget, unroll=16))
     widest = max((c["group_k"] for c in out), default=8)
     out.append(dict(group_min=1, group_k=widest, xcd_local=1, t_budget_mb=64, unroll=16))
     return out

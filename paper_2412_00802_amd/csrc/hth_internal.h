@@ -186,7 +186,7 @@ struct hth_kb_s {
   // schedule choices of the batched executor (defaults, environment overrides
   // HTHEDL_GROUP_MIN / _GROUP_K / _XCD / _TBUDGET_MB)
   struct Tuning {
-    uint32_t group_min = 4;      // smallest (role, dir, level) bucket run as shared passes
+    uint32_t group_min = 2;      // smallest (role, dir, level) bucket run as shared passes
     uint32_t group_k = 64;       // most role nodes per shared pass (T row width)
     uint32_t xcd_local = 1;      // 1: all blocks of a shared pass on one XCD
     size_t t_budget = 64ull << 20;   // bytes of T rows resident per launch

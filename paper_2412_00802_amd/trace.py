@@ -76,6 +76,13 @@ class SetCache:
         self.half = 0
         self.slot: Dict[tuple, int] = {}
 
+    def close(self) -> None:
+        """Unregister the table (the library must not read it once it is freed)."""
+        if self.table is not None and self.eng.handle is not None:
+            hthedl.hth_kb_set_sets(self.eng.handle, None, 0)
+        self.table = None
+        self.slot = {}
+
     def substitute(self, h, parent=None):
         """h with every cached subtree replaced by its set leaf.  When h adds
         conjuncts to an and-parent, the parent's conjuncts become one leaf."""
@@ -227,8 +234,8 @@ def main():
                 ref_counts.append(counts)
             else:
                 assert np.array_equal(ref_counts[i], counts), f"round {i}: set-table counts differ"
-        if use_cache:
-            hthedl.hth_kb_set_sets(eng.handle, None, 0)
+        if cache is not None:
+            cache.close()
         dev = sum(r["device_ms"] + r["set_fill_ms"] for r in recs) / 1e3
         e2e = sum(r["end_to_end_s"] for r in recs)
         n = sum(r["candidates"] for r in recs)

@@ -36,6 +36,6 @@ def test_trace_rounds_match_oracle():
                     assert rec["nodes_after_sets"] < rec["nodes"]
             got[name].append(counts)
         if cache is not None:
-            hthedl.hth_kb_set_sets(eng.handle, None, 0)
+            cache.close()
     for a, b in zip(got["cached"], got["plain"]):
         assert np.array_equal(a, b)
