@@ -23,7 +23,7 @@
 #include <cstring>
 #include <vector>
 
-#include "hth_internal.h"
+#include "kb_handle.h"
 #include "plan.h"
 
 namespace hth {

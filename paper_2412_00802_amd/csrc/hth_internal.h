@@ -143,72 +143,3 @@ __device__ __forceinline__ uint64_t* out_ptr(const DevKB& kb, uint32_t id) {
 
 }  // namespace hth
 
-// ---------------------------------------------------------------------------
-// the knowledge-base handle
-// ---------------------------------------------------------------------------
-struct hth_kb_s {
-  hth_kb_desc d;
-  uint32_t N = 0, W = 0, S = 0;
-  uint64_t tail = 0;
-  uint32_t* fwd_off = nullptr;
-  uint32_t* inv_off = nullptr;
-  int32_t* inv_tg = nullptr;
-  uint64_t* role_base_dev = nullptr;
-  uint32_t* words = nullptr;           // [R][2][W] non-empty words per role and direction
-  std::vector<uint32_t> n_words;       // [R][2]
-  std::vector<uint64_t> role_base;     // [R+1]
-  std::vector<uint32_t> max_deg[2];    // [R] forward, inverse
-  uint64_t* objmask = nullptr;         // [R][2][W] objects of each role direction
-  uint32_t* objbase = nullptr;         // [R][2][W+1] objects before each word
-  int32_t* ctg_fwd = nullptr;          // [E] object ranks of the forward targets
-  int32_t* ctg_inv = nullptr;          // [E] object ranks of the inverse targets
-  std::vector<uint32_t> n_obj;         // [R][2]; ranks exist where 2 n_obj <= N
-  const uint64_t* pos = nullptr;
-  const uint64_t* neg = nullptr;
-  const uint64_t* sets = nullptr;      // caller's set table (hth_kb_set_sets)
-  uint32_t n_sets = 0;
-  int device = 0;
-  int n_cu = 256;
-  size_t lds_per_block = 65536;
-  std::mutex mu;
-  // measurement (hth_profile_begin/end)
-  struct ProfRec {
-    int kind;
-    double bytes;
-    hipEvent_t a, b;
-  };
-  bool prof = false;
-  std::vector<ProfRec> prof_recs;
-  std::vector<hipEvent_t> event_pool;
-  ~hth_kb_s() {
-    for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
-  }
-  // schedule choices of the batched executor (defaults, environment overrides
-  // HTHEDL_GROUP_MIN / _GROUP_K / _XCD / _TBUDGET_MB)
-  struct Tuning {
-    uint32_t group_min = 2;      // smallest (role, dir, level) bucket run as shared passes
-    uint32_t group_k = 64;       // most role nodes per shared pass (T row width)
-    uint32_t xcd_local = 1;      // 1: all blocks of a shared pass on one XCD
-    size_t t_budget = 64ull << 20;   // bytes of T rows resident per launch
-    uint32_t group_unroll = 16;  // assertions in flight per lane in a dense shared pass
-    uint32_t region_reg = 1;     // 1: register-stack region kernel where programs fit
-    uint32_t t_compact = 1;      // 1: T rows of objects only where they are <= N/2
-  } tune;
-};
-
-namespace hth {
-
-// error reporting (thread-local message)
-void set_error(const std::string& msg);
-hth_status fail(hth_status code, const std::string& msg);
-hth_status hip_fail(hipError_t e, const char* what);
-
-#define HTH_HIP(call)                                   \
-  do {                                                  \
-    hipError_t _e = (call);                             \
-    if (_e != hipSuccess) return ::hth::hip_fail(_e, #call); \
-  } while (0)
-
-inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-
-}  // namespace hth

@@ -14,7 +14,7 @@
 #include <cstring>
 #include <new>
 
-#include "hth_internal.h"
+#include "kb_handle.h"
 
 namespace hth {
 

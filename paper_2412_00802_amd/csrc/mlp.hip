@@ -11,7 +11,7 @@
 #include <cstring>
 #include <vector>
 
-#include "hth_internal.h"
+#include "kb_handle.h"
 
 namespace hth {
 

@@ -8,7 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "hth_internal.h"
+#include "kb_handle.h"
 
 namespace hth {
 
