@@ -152,7 +152,8 @@ hth_status hth_kb_max_degree(hth_kb kb, uint32_t role, uint32_t inv, uint32_t* o
  * unroll: assertions in flight per lane in passes over directions with many
  *   assertions per word (8 or 16; sparse directions always use 8);
  * region_reg: 1 = boolean regions whose value stack fits six entries run with
- *   the stack in registers and four words per lane (0 = the LDS-stack kernel);
+ *   the stack in registers and four words per lane, 2 = eight words per lane
+ *   (0 = the LDS-stack kernel for every region);
  * t_compact: 1 = shared passes over a role direction whose objects (targets)
  *   are at most half of the individuals keep transposed child rows for those
  *   objects only, indexed by object rank (0 = rows for every individual). */

@@ -488,10 +488,15 @@ hth_status launch_regions(Launcher& L, const DevKB& d, const RegionTask* tasks, 
     }
   }
   if (depth <= kRegDepth && L.kb.tune.region_reg) {
-    const uint32_t tiles = (d.S + 256 * kRegWords - 1) / (256 * kRegWords);
+    const uint32_t rw = L.kb.tune.region_reg == 2 ? 2 * kRegWords : kRegWords;
+    const uint32_t tiles = (d.S + 256 * rw - 1) / (256 * rw);
     return L.run(HTH_K_REGION, bytes, [&] {
-      hipLaunchKernelGGL((k_region_reg<kRegDepth, kRegWords>), dim3(tiles * n), dim3(256), 0, L.st, d,
-                         tasks, code, n);
+      if (rw == kRegWords)
+        hipLaunchKernelGGL((k_region_reg<kRegDepth, kRegWords>), dim3(tiles * n), dim3(256), 0, L.st, d,
+                           tasks, code, n);
+      else
+        hipLaunchKernelGGL((k_region_reg<kRegDepth, 2 * kRegWords>), dim3(tiles * n), dim3(256), 0, L.st, d,
+                           tasks, code, n);
     });
   }
   const uint32_t tiles = (d.S + kRegionThreads - 1) / kRegionThreads;

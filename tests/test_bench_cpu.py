@@ -1,0 +1,28 @@
+"""bench.py's contract on the CPU: more than one GPU is refused with a message,
+and the counter summary keeps the profiled kernel's source hash."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+def test_recorded_traffic_is_void_when_the_kernel_changed(tmp_path):
+    sys.path.insert(0, ROOT)
+    import bench
+    f = tmp_path / "traffic.json"
+    f.write_text(json.dumps({"source_sha": bench.source_sha(),
+                             "kernels": {"k_group": {"hbm_bytes_per_launch": 123.0}}}))
+    assert bench.recorded_traffic("k_group", str(f)) == 123.0
+    f.write_text(json.dumps({"source_sha": "0" * 16, "kernels": {"k_group": {"hbm_bytes_per_launch": 123.0}}}))
+    assert bench.recorded_traffic("k_group", str(f)) is None
+    assert bench.recorded_traffic("k_group", str(tmp_path / "missing.json")) is None

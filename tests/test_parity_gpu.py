@@ -265,7 +265,7 @@ def test_every_schedule_gives_identical_counts():
     want = Oracle(kb).coverages(hs)
     eng = hthedl.Engine(kb)
     grid = autotune.candidates(kb.n) + [dict(group_min=0, group_k=64, xcd_local=1, t_budget_mb=64, unroll=8),
-                                        dict(region_reg=0)]
+                                        dict(region_reg=2), dict(region_reg=0)]
     for cand in grid:
         hthedl.hth_kb_set_tuning(eng.handle, **cand)
         got = eng.eval_batch(hs)
@@ -379,7 +379,7 @@ def test_deep_regions_both_region_kernels():
     hyps = [tree(h, op) for h in range(1, 11) for op in ("and", "or") for _ in range(3)]
     want = Oracle(kb).coverages(hyps)
     eng = hthedl.Engine(kb, max_nodes=4096)
-    for reg in (1, 0):
+    for reg in (1, 2, 0):
         hthedl.hth_kb_set_tuning(eng.handle, region_reg=reg)
         assert np.array_equal(eng.eval_batch(hyps), want), reg
         assert np.array_equal(eng.eval_plain(hyps), want), reg
