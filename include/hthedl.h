@@ -151,9 +151,9 @@ hth_status hth_kb_max_degree(hth_kb kb, uint32_t role, uint32_t inv, uint32_t* o
  * t_budget_mb: transposed child rows resident per launch (MiB);
  * unroll: assertions in flight per lane in passes over directions with many
  *   assertions per word (8 or 16; sparse directions always use 8);
- * region_reg: 1 = boolean regions whose value stack fits six entries run with
- *   the stack in registers and four words per lane, 2 = eight words per lane
- *   (0 = the LDS-stack kernel for every region);
+ * region_reg: 1, 2 or 4 = boolean regions whose value stack fits six entries
+ *   run with the stack in registers and that many words per lane (0 = the
+ *   LDS-stack kernel for every region);
  * t_compact: 1 = shared passes over a role direction whose objects (targets)
  *   are at most half of the individuals keep transposed child rows for those
  *   objects only, indexed by object rank (0 = rows for every individual). */
@@ -209,6 +209,24 @@ hth_status hth_eval_batch_sets(hth_kb kb, const hth_node* nodes, const uint32_t*
                                uint32_t n_hyps, const uint32_t* children, uint32_t n_children,
                                void* ws, size_t ws_bytes, uint64_t* d_sets, uint32_t* d_counts,
                                void* stream);
+
+/* Compiled batches for repeated evaluation.  hth_plan_create compiles a batch
+ * as hth_eval_batch does (same arguments, host arrays) and reports the
+ * workspace it needs; the plan keeps the kb's schedule and set table as they
+ * were at creation.  hth_plan_upload copies the plan's tables into a workspace
+ * (once per workspace); hth_plan_launch then runs the plan's kernels on
+ * `stream` with no copy, no allocation and no memset (the counts are cleared
+ * by a kernel), so a caller may capture it in a HIP graph and replay it.  The
+ * KB's rows (concepts, data, examples, set rows) are read at each launch.
+ * Profiling must be off while a launch is captured.  Errors: as hth_eval_batch;
+ * HTH_E_RANGE for an empty batch.  The plan must not outlive its kb. */
+typedef struct hth_plan_s* hth_plan;
+hth_status hth_plan_create(hth_kb kb, const hth_node* nodes, const uint32_t* hyp_node_offsets, uint32_t n_hyps,
+                           const uint32_t* children, uint32_t n_children, hth_plan* out, size_t* ws_bytes);
+hth_status hth_plan_upload(hth_plan plan, void* ws, size_t ws_bytes, void* stream);
+hth_status hth_plan_launch(hth_plan plan, void* ws, size_t ws_bytes, uint32_t* d_counts /* [n_hyps][2] */,
+                           void* stream);
+hth_status hth_plan_destroy(hth_plan plan);
 
 /* Measurement.  Between hth_profile_begin and hth_profile_end every kernel the
  * library launches for this kb is bracketed by two HIP events recorded on the

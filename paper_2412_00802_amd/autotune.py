@@ -33,8 +33,9 @@ def signature(eng) -> str:
 def candidates(n_individuals: int) -> List[Dict[str, int]]:
     """Each T width (8..64 bits) with: XCD-local passes and a budget of one
     group per XCD (and the 64 MiB default), both unrolls; chip-wide passes
-    with one and four groups per launch; and one run without the sharing
-    threshold.  Widths whose T rows exceed 1 GiB per group are left out."""
+    with one and four groups per launch; one run sharing passes from a single
+    node up; and the region kernel at one and four words per lane.  Widths
+    whose T rows exceed 1 GiB per group are left out."""
     out = []
     for k, w in ((8, 1), (16, 2), (32, 4), (64, 8)):
         t_mb = max(1, -(-(n_individuals * w) // (1 << 20)))
@@ -48,6 +49,10 @@ def candidates(n_individuals: int) -> List[Dict[str, int]]:
             out.append(dict(group_min=2, group_k=k, xcd_local=0, t_budget_mb=budget, unroll=16))
     widest = max((c["group_k"] for c in out), default=8)
     out.append(dict(group_min=1, group_k=widest, xcd_local=1, t_budget_mb=64, unroll=16))
+    # words per lane of the region kernel (the others keep the default, 2)
+    out += [dict(group_min=2, group_k=widest, xcd_local=1, t_budget_mb=64, unroll=16, region_reg=r) for r in (1, 4)]
+    for c in out:
+        c.setdefault("region_reg", 2)
     return out
 
 

@@ -116,7 +116,6 @@ k_region(DevKB kb, const RegionTask* __restrict__ tasks, const uint32_t* __restr
 // puts R independent loads in flight per lane and no LDS limits occupancy.
 // Lane t handles words tile*256R + r*256 + t (coalesced per r).  Coverage is
 // reduced over the block and added with one atomic pair per block.
-constexpr int kRegWords = 4;     // R
 constexpr int kRegDepth = 6;     // D: most stack entries a program may need
 template <int D, int R>
 __global__ void __launch_bounds__(256)
@@ -334,6 +333,10 @@ void place_on_xcds(const hth_kb_s& kb, const std::vector<GroupTask>& gs, GroupCh
     for (size_t r = 0; r < per[x].size(); ++r) xslots[c.slot_off + r * 8 + x] = per[x][r];
 }
 
+// groups per launch stay few enough for the pass's grid (at most 8 x 256
+// blocks per XCD round) to stay far below 2^31 work-items
+constexpr size_t kMaxGroupsPerLaunch = 2048;
+
 std::vector<GroupChunk> chunk_groups(const hth_kb_s& kb, std::vector<GroupTask>& gs) {
   std::vector<GroupChunk> out;
   size_t i = 0;
@@ -341,7 +344,7 @@ std::vector<GroupChunk> chunk_groups(const hth_kb_s& kb, std::vector<GroupTask>&
     uint32_t wb = t_width_bytes(gs[i].k);
     uint64_t rows = t_rows(kb, gs[i]);
     size_t j = i + 1;
-    while (j < gs.size()) {
+    while (j < gs.size() && j - i < kMaxGroupsPerLaunch) {
       const uint32_t nwb = std::max(wb, t_width_bytes(gs[j].k));
       if ((rows + t_rows(kb, gs[j])) * nwb > kb.tune.t_budget) break;
       rows += t_rows(kb, gs[j]);
@@ -445,6 +448,23 @@ struct Launcher {
   }
 };
 
+// Launches of `items` work items, `per` blocks of `threads` lanes each, split
+// so that no dispatch holds 2^31 work-items or more (a dispatch counts its
+// grid in work-items in 32 bits; a larger grid would wrap, not fail).
+// launch(first_item, item_count, blocks) issues one of them.
+template <class F>
+hth_status split_launch(Launcher& L, int kind, double bytes, uint64_t items, uint64_t per, uint32_t threads,
+                        F&& launch) {
+  const uint64_t max_blocks = (1ull << 31) / threads - 1;
+  const uint64_t chunk = std::max<uint64_t>(1, max_blocks / std::max<uint64_t>(per, 1));
+  for (uint64_t i0 = 0; i0 < items; i0 += chunk) {
+    const uint64_t m = std::min(chunk, items - i0);
+    hth_status s = L.run(kind, i0 ? 0.0 : bytes, [&] { launch((uint32_t)i0, (uint32_t)m, (uint32_t)(per * m)); });
+    if (s) return s;
+  }
+  return HTH_OK;
+}
+
 // algorithmic bytes of a region task: every distinct row it reads once, its
 // output row once, the two example rows when it counts coverage
 double region_bytes(const hth_kb_s& kb, const RegionTask& t, const std::vector<uint32_t>& code) {
@@ -488,20 +508,21 @@ hth_status launch_regions(Launcher& L, const DevKB& d, const RegionTask* tasks, 
     }
   }
   if (depth <= kRegDepth && L.kb.tune.region_reg) {
-    const uint32_t rw = L.kb.tune.region_reg == 2 ? 2 * kRegWords : kRegWords;
+    const uint32_t rw = L.kb.tune.region_reg;     // words per lane: 1, 2 or 4
     const uint32_t tiles = (d.S + 256 * rw - 1) / (256 * rw);
-    return L.run(HTH_K_REGION, bytes, [&] {
-      if (rw == kRegWords)
-        hipLaunchKernelGGL((k_region_reg<kRegDepth, kRegWords>), dim3(tiles * n), dim3(256), 0, L.st, d,
-                           tasks, code, n);
+    return split_launch(L, HTH_K_REGION, bytes, n, tiles, 256, [&](uint32_t t0, uint32_t m, uint32_t blocks) {
+      const dim3 grid(blocks), block(256);
+      if (rw == 1)
+        hipLaunchKernelGGL((k_region_reg<kRegDepth, 1>), grid, block, 0, L.st, d, tasks + t0, code, m);
+      else if (rw == 2)
+        hipLaunchKernelGGL((k_region_reg<kRegDepth, 2>), grid, block, 0, L.st, d, tasks + t0, code, m);
       else
-        hipLaunchKernelGGL((k_region_reg<kRegDepth, 2 * kRegWords>), dim3(tiles * n), dim3(256), 0, L.st, d,
-                           tasks, code, n);
+        hipLaunchKernelGGL((k_region_reg<kRegDepth, 4>), grid, block, 0, L.st, d, tasks + t0, code, m);
     });
   }
   const uint32_t tiles = (d.S + kRegionThreads - 1) / kRegionThreads;
-  return L.run(HTH_K_REGION, bytes, [&] {
-    hipLaunchKernelGGL(k_region, dim3(tiles * n), dim3(kRegionThreads), 0, L.st, d, tasks, code, n);
+  return split_launch(L, HTH_K_REGION, bytes, n, tiles, kRegionThreads, [&](uint32_t t0, uint32_t m, uint32_t blocks) {
+    hipLaunchKernelGGL(k_region, dim3(blocks), dim3(kRegionThreads), 0, L.st, d, tasks + t0, code, m);
   });
 }
 
@@ -516,14 +537,14 @@ hth_status launch_roles(Launcher& L, const DevKB& d, const RoleTask* tasks,
   if (lds <= kb.lds_per_block) {
     uint32_t bpt = std::max<uint32_t>(1, (2 * kb.n_cu + n - 1) / n);
     bpt = std::min<uint32_t>(bpt, (kb.W + 15) / 16);
-    return L.run(HTH_K_ROLE, bytes, [&] {
-      hipLaunchKernelGGL(k_role<true>, dim3(bpt * n), dim3(1024), lds, L.st, d, tasks, bpt);
+    return split_launch(L, HTH_K_ROLE, bytes, n, bpt, 1024, [&](uint32_t t0, uint32_t, uint32_t blocks) {
+      hipLaunchKernelGGL(k_role<true>, dim3(blocks), dim3(1024), lds, L.st, d, tasks + t0, bpt);
     });
   }
   uint32_t bpt = std::max<uint32_t>(1, (8 * kb.n_cu + n - 1) / n);
   bpt = std::min<uint32_t>(bpt, (kb.W + 3) / 4);
-  return L.run(HTH_K_ROLE, bytes, [&] {
-    hipLaunchKernelGGL(k_role<false>, dim3(bpt * n), dim3(256), 0, L.st, d, tasks, bpt);
+  return split_launch(L, HTH_K_ROLE, bytes, n, bpt, 256, [&](uint32_t t0, uint32_t, uint32_t blocks) {
+    hipLaunchKernelGGL(k_role<false>, dim3(blocks), dim3(256), 0, L.st, d, tasks + t0, bpt);
   });
 }
 
@@ -543,9 +564,8 @@ hth_status launch_group_chunk(Launcher& L, const DevKB& d, const GroupTask* grou
   }
   TW* T = static_cast<TW*>(tarea);
   const uint32_t tiles = (kb.W + 255) / 256;
-  hth_status s = L.run(HTH_K_TBUILD, tb, [&] {
-    hipLaunchKernelGGL(k_tbuild<TW>, dim3(tiles * n), dim3(256), 0, L.st, d, groups + g0, members,
-                       T, tiles);
+  hth_status s = split_launch(L, HTH_K_TBUILD, tb, n, tiles, 256, [&](uint32_t i0, uint32_t, uint32_t blocks) {
+    hipLaunchKernelGGL(k_tbuild<TW>, dim3(blocks), dim3(256), 0, L.st, d, groups + g0 + i0, members, T, tiles);
   });
   if (s) return s;
   const uint32_t* xslots = c.rounds ? xslots_all + c.slot_off : nullptr;
@@ -623,32 +643,48 @@ size_t plan_workspace_bytes(const hth_kb_s& kb, const Plan& P) {
 
 std::once_flag g_attr_once;
 
-hth_status run_plan(hth_kb_s& kb, const Plan& P, char* ws, size_t ws_bytes, uint32_t* counts,
-                    uint32_t n_hyps, uint64_t* instances, hipStream_t st) {
-  std::call_once(g_attr_once, [&] {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_role<true>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kb.lds_per_block);
-  });
+// A compiled plan laid out for the device: the table blob with its offsets and
+// the host side of the launch sequence.  Built once; uploaded into a workspace
+// with one copy; launched any number of times (kernels only).
+struct Prepared {
+  Plan P;
+  Blob blob;
+  struct LevelAt { size_t mat, role, group, fill, nrole, ngroup, nfill; };
+  std::vector<LevelAt> at;
+  size_t root_at = 0;
+  std::vector<std::vector<RoleTask>> lv_roles;
+  std::vector<std::vector<GroupTask>> lv_groups;
+  std::vector<std::vector<GroupChunk>> lv_chunks;
+  size_t n_thr_groups = 0, n_thr_tasks = 0;
+  size_t o_thr = 0, o_thg = 0, o_reg = 0, o_role = 0, o_grp = 0, o_mem = 0, o_fill = 0, o_code = 0, o_xslot = 0;
+  size_t tables = 0, need = 0;
+  uint32_t n_hyps = 0;
+};
+
+void prepare(const hth_kb_s& kb, Plan&& plan, uint32_t n_hyps, Prepared& X) {
+  X.P = std::move(plan);
+  const Plan& P = X.P;
+  X.n_hyps = n_hyps;
   std::vector<RegionTask> regions;
   std::vector<RoleTask> roles;
   std::vector<GroupTask> groups;
   std::vector<GroupMember> members;
   std::vector<FillTask> fills;
-  struct LevelAt { size_t mat, role, group, fill, nrole, ngroup, nfill; };
-  std::vector<LevelAt> at(P.levels.size());
-  std::vector<std::vector<RoleTask>> lv_roles(P.levels.size());
-  std::vector<std::vector<GroupTask>> lv_groups(P.levels.size());
-  std::vector<std::vector<GroupChunk>> lv_chunks(P.levels.size());
   std::vector<uint32_t> xslots;
-  for (size_t L = 0; L < P.levels.size(); ++L) {
+  const size_t NL = P.levels.size();
+  X.at.assign(NL, {});
+  X.lv_roles.assign(NL, {});
+  X.lv_groups.assign(NL, {});
+  X.lv_chunks.assign(NL, {});
+  for (size_t L = 0; L < NL; ++L) {
     const PlanLevel& PL = P.levels[L];
-    at[L] = {regions.size(), roles.size(), groups.size(), fills.size(), 0, 0, 0};
+    X.at[L] = {regions.size(), roles.size(), groups.size(), fills.size(), 0, 0, 0};
     regions.insert(regions.end(), PL.mat.begin(), PL.mat.end());
     for (RoleTask t : PL.roles) {
       t.n_words = kb.n_words[2 * t.role + t.inv];
       if (t.n_words < kb.W) fills.push_back(FillTask{t.out_row, t.lo == 0 ? 1u : 0u});
       roles.push_back(t);
-      lv_roles[L].push_back(t);
+      X.lv_roles[L].push_back(t);
     }
     const uint32_t mbase = (uint32_t)members.size();
     for (GroupTask g : PL.groups) {
@@ -658,20 +694,19 @@ hth_status run_plan(hth_kb_s& kb, const Plan& P, char* ws, size_t ws_bytes, uint
           fills.push_back(FillTask{PL.members[g.first + j].out_row, (uint32_t)((g.acc[0] >> j) & 1)});
       g.first += mbase;
       g.compact = kb.tune.t_compact && 2ull * kb.n_obj[2 * g.role + g.inv] <= kb.N;
-      lv_groups[L].push_back(g);
+      X.lv_groups[L].push_back(g);
     }
-    lv_chunks[L] = chunk_groups(kb, lv_groups[L]);
-    for (GroupChunk& c : lv_chunks[L])
-      if (kb.tune.xcd_local && c.n >= 8) place_on_xcds(kb, lv_groups[L], c, xslots);
-    groups.insert(groups.end(), lv_groups[L].begin(), lv_groups[L].end());
+    X.lv_chunks[L] = chunk_groups(kb, X.lv_groups[L]);
+    for (GroupChunk& c : X.lv_chunks[L])
+      if (kb.tune.xcd_local && c.n >= 8) place_on_xcds(kb, X.lv_groups[L], c, xslots);
+    groups.insert(groups.end(), X.lv_groups[L].begin(), X.lv_groups[L].end());
     members.insert(members.end(), PL.members.begin(), PL.members.end());
-    at[L].nrole = roles.size() - at[L].role;
-    at[L].ngroup = groups.size() - at[L].group;
-    at[L].nfill = fills.size() - at[L].fill;
+    X.at[L].nrole = roles.size() - X.at[L].role;
+    X.at[L].ngroup = groups.size() - X.at[L].group;
+    X.at[L].nfill = fills.size() - X.at[L].fill;
   }
-  const size_t root_at = regions.size();
+  X.root_at = regions.size();
   regions.insert(regions.end(), P.roots.begin(), P.roots.end());
-  Blob blob;
   // thresholds grouped by property (at most 32 per group): one column pass each
   std::vector<ThrTask> thr_tasks(P.thr);
   std::stable_sort(thr_tasks.begin(), thr_tasks.end(),
@@ -682,72 +717,104 @@ hth_status run_plan(hth_kb_s& kb, const Plan& P, char* ws, size_t ws_bytes, uint
       thr_groups.push_back(ThrGroup{thr_tasks[i].prop, i, 0, 0});
     thr_groups.back().n++;
   }
-  const size_t o_thr = blob.add(thr_tasks);
-  const size_t o_thg = blob.add(thr_groups);
-  const size_t o_reg = blob.add(regions);
-  const size_t o_role = blob.add(roles);
-  const size_t o_grp = blob.add(groups);
-  const size_t o_mem = blob.add(members);
-  const size_t o_fill = blob.add(fills);
-  const size_t o_code = blob.add(P.code);
-  const size_t o_xslot = blob.add(xslots);
-  const size_t tables = align_up(blob.bytes.size(), 256);
-  const size_t slot_bytes = (size_t)kb.S * 8;
+  X.n_thr_groups = thr_groups.size();
+  X.n_thr_tasks = thr_tasks.size();
+  X.o_thr = X.blob.add(thr_tasks);
+  X.o_thg = X.blob.add(thr_groups);
+  X.o_reg = X.blob.add(regions);
+  X.o_role = X.blob.add(roles);
+  X.o_grp = X.blob.add(groups);
+  X.o_mem = X.blob.add(members);
+  X.o_fill = X.blob.add(fills);
+  X.o_code = X.blob.add(P.code);
+  X.o_xslot = X.blob.add(xslots);
+  X.tables = align_up(X.blob.bytes.size(), 256);
   size_t max_groups = 0;
   for (const PlanLevel& PL : P.levels) max_groups = std::max(max_groups, PL.groups.size());
-  const size_t t_bytes = max_groups ? t_area_bytes(kb) : 0;
-  const size_t need = tables + (size_t)P.n_slots * slot_bytes + t_bytes;
-  if (need > ws_bytes)
-    return fail(HTH_E_NOMEM, "workspace too small: need " + std::to_string(need) + " bytes, have " +
+  X.need = X.tables + (size_t)P.n_slots * kb.S * 8 + (max_groups ? t_area_bytes(kb) : 0);
+}
+
+hth_status check_ws(const Prepared& X, const char* ws, size_t ws_bytes) {
+  if (X.need > ws_bytes)
+    return fail(HTH_E_NOMEM, "workspace too small: need " + std::to_string(X.need) + " bytes, have " +
                                  std::to_string(ws_bytes));
   if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(HTH_E_INVALID, "workspace must be 256-byte aligned");
+  return HTH_OK;
+}
 
+__global__ void k_zero_u32(uint32_t* __restrict__ p, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// The kernels of a prepared plan whose tables are in ws: no copies, no
+// allocation and no memset (the counts are cleared by a kernel).
+hth_status launch_prepared(hth_kb_s& kb, const Prepared& X, char* ws, uint32_t* counts, uint64_t* instances,
+                           hipStream_t st) {
+  std::call_once(g_attr_once, [&] {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_role<true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kb.lds_per_block);
+  });
+  const Plan& P = X.P;
+  const size_t slot_bytes = (size_t)kb.S * 8;
   DevKB d = dev_view(kb);
   d.sets = P.sets;
   d.n_fixed = kb.d.n_concepts + P.n_sets;
-  d.slots = reinterpret_cast<uint64_t*>(ws + tables);
+  d.slots = reinterpret_cast<uint64_t*>(ws + X.tables);
   d.counts = counts;
   d.instances = instances;
-  void* tarea = ws + tables + (size_t)P.n_slots * slot_bytes;
-  HTH_HIP(hipMemcpyAsync(ws, blob.bytes.data(), blob.bytes.size(), hipMemcpyHostToDevice, st));
-  HTH_HIP(hipMemsetAsync(counts, 0, (size_t)n_hyps * 8, st));
-  const ThrTask* thr = reinterpret_cast<const ThrTask*>(ws + o_thr);
-  const ThrGroup* thg = reinterpret_cast<const ThrGroup*>(ws + o_thg);
-  const RegionTask* reg = reinterpret_cast<const RegionTask*>(ws + o_reg);
-  const RoleTask* rol = reinterpret_cast<const RoleTask*>(ws + o_role);
-  const GroupTask* grp = reinterpret_cast<const GroupTask*>(ws + o_grp);
-  const GroupMember* mem = reinterpret_cast<const GroupMember*>(ws + o_mem);
-  const FillTask* fil = reinterpret_cast<const FillTask*>(ws + o_fill);
-  const uint32_t* code = reinterpret_cast<const uint32_t*>(ws + o_code);
+  void* tarea = ws + X.tables + (size_t)P.n_slots * slot_bytes;
+  const uint32_t nc = 2 * X.n_hyps;
+  hipLaunchKernelGGL(k_zero_u32, dim3((nc + 255) / 256), dim3(256), 0, st, counts, nc);
+  HTH_HIP(hipGetLastError());
+  const ThrTask* thr = reinterpret_cast<const ThrTask*>(ws + X.o_thr);
+  const ThrGroup* thg = reinterpret_cast<const ThrGroup*>(ws + X.o_thg);
+  const RegionTask* reg = reinterpret_cast<const RegionTask*>(ws + X.o_reg);
+  const RoleTask* rol = reinterpret_cast<const RoleTask*>(ws + X.o_role);
+  const GroupTask* grp = reinterpret_cast<const GroupTask*>(ws + X.o_grp);
+  const GroupMember* mem = reinterpret_cast<const GroupMember*>(ws + X.o_mem);
+  const FillTask* fil = reinterpret_cast<const FillTask*>(ws + X.o_fill);
+  const uint32_t* code = reinterpret_cast<const uint32_t*>(ws + X.o_code);
   Launcher Lc{kb, st};
-  if (!thr_groups.empty()) {
+  if (X.n_thr_groups) {
     // about 32 words per wave: enough independent column loads in flight
-    const uint32_t n = (uint32_t)thr_groups.size();
+    const uint32_t n = (uint32_t)X.n_thr_groups;
     const uint32_t bpt = std::max<uint32_t>(1, (kb.W + 127) / 128);
-    const double bytes = n * 4.0 * kb.N + thr_tasks.size() * 8.0 * kb.W;
-    hth_status s = Lc.run(HTH_K_THRESHOLD, bytes, [&] {
-      hipLaunchKernelGGL(k_threshold, dim3(bpt * n), dim3(256), 0, st, d, thg, thr, bpt);
+    const double bytes = n * 4.0 * kb.N + X.n_thr_tasks * 8.0 * kb.W;
+    hth_status s = split_launch(Lc, HTH_K_THRESHOLD, bytes, n, bpt, 256, [&](uint32_t i0, uint32_t, uint32_t blocks) {
+      hipLaunchKernelGGL(k_threshold, dim3(blocks), dim3(256), 0, st, d, thg + i0, thr, bpt);
     });
     if (s) return s;
   }
   for (size_t L = 0; L < P.levels.size(); ++L) {
     const PlanLevel& PL = P.levels[L];
-    hth_status s = launch_regions(Lc, d, reg + at[L].mat, code, PL.mat, P.code);
+    const Prepared::LevelAt& at = X.at[L];
+    hth_status s = launch_regions(Lc, d, reg + at.mat, code, PL.mat, P.code);
     if (s) return s;
-    if (at[L].nfill) {
-      const uint32_t n = (uint32_t)at[L].nfill, tiles = (kb.S + 255) / 256;
-      s = Lc.run(HTH_K_FILL, (double)n * kb.W * 8, [&] {
-        hipLaunchKernelGGL(k_fill_rows, dim3(tiles * n), dim3(256), 0, st, d, fil + at[L].fill, tiles);
+    if (at.nfill) {
+      const uint32_t n = (uint32_t)at.nfill, tiles = (kb.S + 255) / 256;
+      s = split_launch(Lc, HTH_K_FILL, (double)n * kb.W * 8, n, tiles, 256, [&](uint32_t i0, uint32_t, uint32_t blocks) {
+        hipLaunchKernelGGL(k_fill_rows, dim3(blocks), dim3(256), 0, st, d, fil + at.fill + i0, tiles);
       });
       if (s) return s;
     }
-    s = launch_roles(Lc, d, rol + at[L].role, lv_roles[L]);
+    s = launch_roles(Lc, d, rol + at.role, X.lv_roles[L]);
     if (s) return s;
-    s = launch_groups(Lc, d, grp + at[L].group, mem, lv_groups[L], lv_chunks[L],
-                      reinterpret_cast<const uint32_t*>(ws + o_xslot), tarea);
+    s = launch_groups(Lc, d, grp + at.group, mem, X.lv_groups[L], X.lv_chunks[L],
+                      reinterpret_cast<const uint32_t*>(ws + X.o_xslot), tarea);
     if (s) return s;
   }
-  return launch_regions(Lc, d, reg + root_at, code, P.roots, P.code);
+  return launch_regions(Lc, d, reg + X.root_at, code, P.roots, P.code);
+}
+
+hth_status run_plan(hth_kb_s& kb, Plan&& P, char* ws, size_t ws_bytes, uint32_t* counts, uint32_t n_hyps,
+                    uint64_t* instances, hipStream_t st) {
+  Prepared X;
+  prepare(kb, std::move(P), n_hyps, X);
+  hth_status s = check_ws(X, ws, ws_bytes);
+  if (s) return s;
+  HTH_HIP(hipMemcpyAsync(ws, X.blob.bytes.data(), X.blob.bytes.size(), hipMemcpyHostToDevice, st));
+  return launch_prepared(kb, X, ws, counts, instances, st);
 }
 
 }  // namespace
@@ -777,7 +844,7 @@ extern "C" hth_status hth_eval_one(hth_kb kb, const hth_node* nodes, uint32_t n_
   hth_status s = compile_plan(*kb, nodes, offs, 1, children, n_children, opt, P);
   if (s) return s;
   std::lock_guard<std::mutex> g(kb->mu);
-  return run_plan(*kb, P, static_cast<char*>(ws), ws_bytes, d_counts, 1, d_instances,
+  return run_plan(*kb, std::move(P), static_cast<char*>(ws), ws_bytes, d_counts, 1, d_instances,
                   static_cast<hipStream_t>(stream));
 }
 
@@ -798,7 +865,7 @@ hth_status eval_batch_impl(hth_kb kb, const hth_node* nodes, const uint32_t* hyp
   hth_status s = compile_plan(*kb, nodes, hyp_node_offsets, n_hyps, children, n_children, opt, P);
   if (s) return s;
   std::lock_guard<std::mutex> g(kb->mu);
-  return run_plan(*kb, P, static_cast<char*>(ws), ws_bytes, d_counts, n_hyps, d_sets,
+  return run_plan(*kb, std::move(P), static_cast<char*>(ws), ws_bytes, d_counts, n_hyps, d_sets,
                   static_cast<hipStream_t>(stream));
 }
 }  // namespace
@@ -818,6 +885,58 @@ extern "C" hth_status hth_eval_batch_sets(hth_kb kb, const hth_node* nodes,
   if (!d_sets) return fail(HTH_E_INVALID, "d_sets is NULL");
   return eval_batch_impl(kb, nodes, hyp_node_offsets, n_hyps, children, n_children, ws, ws_bytes,
                          d_sets, d_counts, stream);
+}
+
+// A compiled batch kept for repeated launches (hth_plan_*).
+struct hth_plan_s {
+  hth_kb kb = nullptr;
+  hth::Prepared X;
+};
+
+extern "C" hth_status hth_plan_create(hth_kb kb, const hth_node* nodes, const uint32_t* hyp_node_offsets,
+                                      uint32_t n_hyps, const uint32_t* children, uint32_t n_children,
+                                      hth_plan* out, size_t* ws_bytes) {
+  if (!kb || !nodes || !hyp_node_offsets || !out || !ws_bytes) return fail(HTH_E_INVALID, "NULL argument");
+  if (n_children && !children) return fail(HTH_E_INVALID, "children is NULL");
+  if (n_hyps == 0) return fail(HTH_E_RANGE, "a plan needs at least one hypothesis");
+  if (hyp_node_offsets[0] != 0) return fail(HTH_E_INVALID, "hyp_node_offsets[0] must be 0");
+  PlanOptions opt;
+  opt.group_min = kb->tune.group_min ? kb->tune.group_min : 0xFFFFFFFFu;
+  opt.group_k = kb->tune.group_k;
+  Plan P;
+  hth_status s = compile_plan(*kb, nodes, hyp_node_offsets, n_hyps, children, n_children, opt, P);
+  if (s) return s;
+  hth_plan_s* pl = new (std::nothrow) hth_plan_s();
+  if (!pl) return fail(HTH_E_NOMEM, "host allocation failed");
+  pl->kb = kb;
+  prepare(*kb, std::move(P), n_hyps, pl->X);
+  *out = pl;
+  *ws_bytes = pl->X.need;
+  return HTH_OK;
+}
+
+extern "C" hth_status hth_plan_upload(hth_plan plan, void* ws, size_t ws_bytes, void* stream) {
+  if (!plan || !ws) return fail(HTH_E_INVALID, "NULL argument");
+  hth_status s = check_ws(plan->X, static_cast<char*>(ws), ws_bytes);
+  if (s) return s;
+  HTH_HIP(hipMemcpyAsync(ws, plan->X.blob.bytes.data(), plan->X.blob.bytes.size(), hipMemcpyHostToDevice,
+                         static_cast<hipStream_t>(stream)));
+  return HTH_OK;
+}
+
+extern "C" hth_status hth_plan_launch(hth_plan plan, void* ws, size_t ws_bytes, uint32_t* d_counts,
+                                      void* stream) {
+  if (!plan || !ws || !d_counts) return fail(HTH_E_INVALID, "NULL argument");
+  hth_status s = check_ws(plan->X, static_cast<char*>(ws), ws_bytes);
+  if (s) return s;
+  std::lock_guard<std::mutex> g(plan->kb->mu);
+  return launch_prepared(*plan->kb, plan->X, static_cast<char*>(ws), d_counts, nullptr,
+                         static_cast<hipStream_t>(stream));
+}
+
+extern "C" hth_status hth_plan_destroy(hth_plan plan) {
+  delete plan;
+  return HTH_OK;
 }
 
 extern "C" hth_status hth_batch_workspace_bytes(hth_kb kb, const hth_node* nodes,

@@ -611,7 +611,8 @@ extern "C" hth_status hth_kb_get_tuning(hth_kb kb, hth_tuning* out) {
 extern "C" hth_status hth_kb_set_tuning(hth_kb kb, const hth_tuning* t) {
   if (!kb || !t) return fail(HTH_E_INVALID, "NULL argument");
   if (t->group_k < 1 || t->group_k > 64 || t->xcd_local > 1 || t->t_budget_mb < 1 ||
-      t->t_budget_mb > (1u << 20) || (t->unroll != 8 && t->unroll != 16) || t->region_reg > 2 ||
+      t->t_budget_mb > (1u << 20) || (t->unroll != 8 && t->unroll != 16) ||
+      (t->region_reg != 0 && t->region_reg != 1 && t->region_reg != 2 && t->region_reg != 4) ||
       t->t_compact > 1)
     return fail(HTH_E_RANGE, "tuning value out of range");
   std::lock_guard<std::mutex> g(kb->mu);

@@ -56,7 +56,7 @@ struct hth_kb_s {
     uint32_t xcd_local = 1;      // 1: all blocks of a shared pass on one XCD
     size_t t_budget = 64ull << 20;   // bytes of T rows resident per launch
     uint32_t group_unroll = 16;  // assertions in flight per lane in a dense shared pass
-    uint32_t region_reg = 1;     // 1: register-stack region kernel where programs fit
+    uint32_t region_reg = 2;     // words per lane of the register-stack region kernel (0: LDS kernel)
     uint32_t t_compact = 1;      // 1: T rows of objects only where they are <= N/2
   } tune;
 };

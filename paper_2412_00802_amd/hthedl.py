@@ -35,7 +35,8 @@ EXPORTED = ["hth_kb_derived_bytes", "hth_kb_create", "hth_kb_set_examples", "hth
             "hth_profile_end", "hth_features", "hth_densify", "hth_gemm_bf16", "hth_head_forward",
             "hth_head_backward", "hth_colsum", "hth_adamw", "hth_to_bf16", "hth_topk",
             "hth_batch_workspace_bytes", "hth_head_score", "hth_kb_get_tuning", "hth_kb_set_tuning",
-            "hth_kb_set_sets", "hth_eval_batch_sets", "hth_densify_delta"]
+            "hth_kb_set_sets", "hth_eval_batch_sets", "hth_densify_delta", "hth_plan_create",
+            "hth_plan_upload", "hth_plan_launch", "hth_plan_destroy"]
 
 
 class HthError(RuntimeError):
@@ -94,6 +95,10 @@ def lib() -> ctypes.CDLL:
             "hth_eval_batch": [P, P, P, U32, P, U32, P, S, P, P],
             "hth_eval_batch_sets": [P, P, P, U32, P, U32, P, S, P, P, P],
             "hth_kb_set_sets": [P, P, U32],
+            "hth_plan_create": [P, P, P, U32, P, U32, ctypes.POINTER(P), ctypes.POINTER(S)],
+            "hth_plan_upload": [P, P, S, P],
+            "hth_plan_launch": [P, P, S, P, P],
+            "hth_plan_destroy": [P],
             "hth_batch_workspace_bytes": [P, P, P, U32, P, U32, ctypes.POINTER(S)],
             "hth_sync": [P],
             "hth_profile_begin": [P],
@@ -238,6 +243,29 @@ def hth_eval_batch_sets(kb, nodes: np.ndarray, offsets: np.ndarray, children: np
     _check(lib().hth_eval_batch_sets(kb, _np_ptr(nodes), _np_ptr(offsets), offsets.shape[0] - 1,
                                      _np_ptr(children), children.shape[0], _ptr(ws), ws_bytes,
                                      _ptr(d_sets), _ptr(d_counts), _stream(stream)))
+
+
+def hth_plan_create(kb, nodes: np.ndarray, offsets: np.ndarray, children: np.ndarray):
+    """-> (plan handle, workspace bytes)."""
+    nodes = np.ascontiguousarray(nodes, dtype=NODE_DTYPE)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint32)
+    children = np.ascontiguousarray(children, dtype=np.uint32)
+    h, nb = ctypes.c_void_p(), ctypes.c_size_t()
+    _check(lib().hth_plan_create(kb, _np_ptr(nodes), _np_ptr(offsets), offsets.shape[0] - 1, _np_ptr(children),
+                                 children.shape[0], ctypes.byref(h), ctypes.byref(nb)))
+    return h, nb.value
+
+
+def hth_plan_upload(plan, ws, ws_bytes: int, stream=None) -> None:
+    _check(lib().hth_plan_upload(plan, _ptr(ws), ws_bytes, _stream(stream)))
+
+
+def hth_plan_launch(plan, ws, ws_bytes: int, d_counts, stream=None) -> None:
+    _check(lib().hth_plan_launch(plan, _ptr(ws), ws_bytes, _ptr(d_counts), _stream(stream)))
+
+
+def hth_plan_destroy(plan) -> None:
+    _check(lib().hth_plan_destroy(plan))
 
 
 def hth_batch_workspace_bytes(kb, nodes: np.ndarray, offsets: np.ndarray, children: np.ndarray) -> int:

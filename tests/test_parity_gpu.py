@@ -265,7 +265,7 @@ def test_every_schedule_gives_identical_counts():
     want = Oracle(kb).coverages(hs)
     eng = hthedl.Engine(kb)
     grid = autotune.candidates(kb.n) + [dict(group_min=0, group_k=64, xcd_local=1, t_budget_mb=64, unroll=8),
-                                        dict(region_reg=2), dict(region_reg=0)]
+                                        dict(region_reg=1), dict(region_reg=4), dict(region_reg=0)]
     for cand in grid:
         hthedl.hth_kb_set_tuning(eng.handle, **cand)
         got = eng.eval_batch(hs)
@@ -379,7 +379,7 @@ def test_deep_regions_both_region_kernels():
     hyps = [tree(h, op) for h in range(1, 11) for op in ("and", "or") for _ in range(3)]
     want = Oracle(kb).coverages(hyps)
     eng = hthedl.Engine(kb, max_nodes=4096)
-    for reg in (1, 2, 0):
+    for reg in (1, 2, 4, 0):
         hthedl.hth_kb_set_tuning(eng.handle, region_reg=reg)
         assert np.array_equal(eng.eval_batch(hyps), want), reg
         assert np.array_equal(eng.eval_plain(hyps), want), reg
@@ -410,3 +410,71 @@ def test_compact_transposed_rows_on_sparse_roles():
             assert np.array_equal(eng.eval_batch(hyps), want), (k, compact)
     hthedl.hth_kb_set_tuning(eng.handle, group_min=0)
     assert np.array_equal(eng.eval_batch(hyps), want)
+
+
+def test_plan_reuse_and_graph_replay():
+    """A compiled plan launched repeatedly, and captured in a HIP graph and
+    replayed with eager work in between, gives the oracle's counts every time
+    (the counts are cleared by a kernel, not a memset)."""
+    import torch
+    cfg = synth.small_config(n=20000, n_concepts=30, n_roles=4, s=1.5, cap=200, n_pos=2500, n_neg=2500,
+                             n_hyps=200, hyp_depth=5, seed_index=2000)
+    kb = synth.make_kb(cfg)
+    hyps = synth.make_hypotheses(cfg, kb)
+    want = Oracle(kb).coverages(hyps)
+    eng = hthedl.Engine(kb)
+    nodes, offs, ch = hthedl.encode_batch(hyps)
+    plan, nb = hthedl.hth_plan_create(eng.handle, nodes, offs, ch)
+    try:
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        hthedl.hth_plan_upload(plan, ws, nb)
+        counts = torch.full((len(hyps), 2), -1, dtype=torch.int32, device="cuda")
+        for _ in range(3):
+            hthedl.hth_plan_launch(plan, ws, nb, counts)
+            assert np.array_equal(counts.cpu().numpy().view(np.uint32), want)
+        with pytest.raises(hthedl.HthError):
+            hthedl.hth_plan_launch(plan, ws, nb - 256, counts)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            hthedl.hth_plan_launch(plan, ws, nb, counts, stream=torch.cuda.current_stream())
+        other = hyps[:25]
+        for rep in range(4):
+            counts.fill_(-1)
+            assert np.array_equal(eng.eval_batch(other), want[:25])      # eager work between replays
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert np.array_equal(counts.cpu().numpy().view(np.uint32), want), rep
+        del g
+    finally:
+        hthedl.hth_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("region_reg", [1, 2, 0])
+def test_grids_beyond_one_dispatch(region_reg):
+    """70,000 root regions over 4M individuals need more work-items than one
+    dispatch holds (about 17M blocks of 256 lanes at one word per lane): the
+    launches are split, and the counts equal those of small batches and the
+    oracle's."""
+    cfg = synth.small_config(n=4_000_000, n_concepts=64, depth=4, n_roles=2, n_data=2, n_pos=100_000,
+                             n_neg=100_000, seed_index=2100, total_edges=40_000)
+    kb = synth.make_kb(cfg)
+    rng = np.random.default_rng(21)
+    ops = ("and", "or")
+    hyps = []
+    seen = set()
+    while len(hyps) < 70_000:
+        leaves = tuple(("not", ("atom", int(v))) if rng.random() < 0.5 else ("atom", int(v))
+                       for v in rng.integers(0, 64, 3))
+        h = (ops[int(rng.integers(0, 2))],) + leaves
+        if h not in seen:
+            seen.add(h)
+            hyps.append(h)
+    eng = hthedl.Engine(kb)
+    hthedl.hth_kb_set_tuning(eng.handle, region_reg=region_reg)
+    say(f"[parity] {len(hyps)} regions over N={kb.n}, region_reg={region_reg}")
+    whole = eng.eval_batch(hyps)
+    parts = eng.eval_batch(hyps, chunk=4096)
+    assert np.array_equal(whole, parts)
+    pick = rng.choice(len(hyps), size=40, replace=False)
+    assert np.array_equal(whole[pick], Oracle(kb).coverages([hyps[i] for i in pick]))
