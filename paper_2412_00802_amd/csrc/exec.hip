@@ -38,22 +38,36 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 // numeric thresholds
 // ---------------------------------------------------------------------------
 // All thresholds requested on one property in one pass over its column: one
-// lane per individual, one wave ballot per threshold and word.
+// lane per individual over 8 consecutive words (values loaded once, kept in
+// registers), one wave ballot per threshold and word; lanes 0..7 then store
+// the 8 words of a threshold's row together (a full 64-byte line).
 __global__ void __launch_bounds__(256)
 k_threshold(DevKB kb, const ThrGroup* __restrict__ groups, const ThrTask* __restrict__ tasks, uint32_t bpt) {
   const uint32_t gi = blockIdx.x / bpt, b = blockIdx.x % bpt;
   const ThrGroup G = groups[gi];
   const float* col = kb.data + (size_t)G.prop * kb.N;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (uint32_t w = b * 4 + wv; w < kb.W; w += bpt * 4) {
-    const uint32_t x = w * 64 + lane;
-    const bool in = x < kb.N;
-    const float f = in ? col[x] : 0.0f;
+  const uint32_t n_blk = (kb.W + 7) / 8;
+  for (uint32_t blk = b * 4 + wv; blk < n_blk; blk += bpt * 4) {
+    const uint32_t w0 = blk * 8;
+    float f[8];
+    bool in[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t x = (w0 + j) * 64 + lane;
+      in[j] = w0 + j < kb.W && x < kb.N;
+      f[j] = in[j] ? col[x] : 0.0f;
+    }
     for (uint32_t i = 0; i < G.n; ++i) {
       const ThrTask T = tasks[G.first + i];
-      const bool v = in && (T.le ? (f <= T.t) : (f >= T.t));   // NaN (no value) compares false
-      const uint64_t m = __ballot(v);
-      if (lane == 0) out_ptr(kb, T.out_row)[w] = m;
+      uint64_t mine = 0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        // NaN (no value) compares false
+        const uint64_t m = __ballot(in[j] && (T.le ? (f[j] <= T.t) : (f[j] >= T.t)));
+        if (lane == j) mine = m;
+      }
+      if (lane < 8 && w0 + lane < kb.W) out_ptr(kb, T.out_row)[w0 + lane] = mine;
     }
   }
 }
