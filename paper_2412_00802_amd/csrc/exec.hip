@@ -226,7 +226,9 @@ __device__ __forceinline__ void role_word(const DevKB& kb, const uint32_t* __res
   const bool in = x < kb.N;
   const uint32_t xe = in ? x : kb.N;
   const uint32_t olo = off[xe];
-  const uint32_t ohi = in ? off[x + 1] : olo;
+  uint32_t ohi = in ? off[x + 1] : olo;
+  const bool heavy = ohi - olo > kb.heavy_min;   // counted by k_role_heavy instead
+  if (heavy) ohi = olo;
   const uint32_t ee = (uint32_t)__shfl((int)ohi, 63, 64);
   uint32_t i0 = (uint32_t)__shfl((int)olo, 0, 64);
   uint32_t cnt = 0;
@@ -251,7 +253,7 @@ __device__ __forceinline__ void role_word(const DevKB& kb, const uint32_t* __res
     const uint32_t nxt = (uint32_t)__shfl((int)olo, l, 64);
     i0 = max(i0 + 64, nxt);
   }
-  const bool res = in && cnt >= lo && cnt <= hi;
+  const bool res = in && !heavy && cnt >= lo && cnt <= hi;
   const uint64_t word = __ballot(res);
   if (lane == 0) out[w] = word;
 }
@@ -279,6 +281,77 @@ k_role(DevKB kb, const RoleTask* __restrict__ tasks, uint32_t bpt) {
     role_word<STAGE>(kb, off, tg, child, T.neg, T.lo, T.hi, T.sat, out, words[i], lane);
 }
 
+// The task of heavy-row block b or counter i: the last task whose first block
+// (counter) is <= b; tasks without heavy rows own empty ranges.
+template <bool BLOCKS>
+__device__ __forceinline__ uint32_t heavy_task(const RoleTask* __restrict__ tasks, uint32_t n, uint32_t b) {
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if ((BLOCKS ? tasks[mid].h_first : tasks[mid].c_first) <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// One chunk of kHeavyChunk assertions of one heavy row per block: the count
+// of child members among them goes to partial[block] (no early exit: every
+// chunk is counted, so that no two blocks touch the same word).
+__global__ void __launch_bounds__(256)
+k_role_heavy(DevKB kb, const RoleTask* __restrict__ tasks, uint32_t n_tasks, uint32_t b0,
+             uint32_t* __restrict__ partial) {
+  __shared__ uint32_t s_part[4];
+  const uint32_t b = b0 + blockIdx.x;
+  const RoleTask T = tasks[heavy_task<true>(tasks, n_tasks, b)];
+  const HeavyChunk c = kb.heavy_chunks[T.hc0 + (b - T.h_first)];
+  const uint32_t x = kb.heavy_rows[c.hrow];
+  const uint32_t* off = (T.inv ? kb.inv_off : kb.fwd_off) + (size_t)T.role * (kb.N + 1);
+  const int32_t* tg = (T.inv ? kb.inv_tg : kb.fwd_tg) + kb.role_base[T.role];
+  const uint64_t* child = row_ptr(kb, T.child_row);
+  const uint32_t e0 = off[x] + c.k * kHeavyChunk;
+  const uint32_t e1 = min(off[x + 1], e0 + kHeavyChunk);
+  uint32_t cnt = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < kHeavyChunk / 256; ++j) {
+    const uint32_t e = e0 + j * 256 + threadIdx.x;
+    if (e < e1) {
+      const uint32_t t = (uint32_t)tg[e];
+      cnt += ((uint32_t)(child[t >> 6] >> (t & 63)) & 1u) ^ T.neg;
+    }
+  }
+  cnt = wave_sum(cnt);
+  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[b] = s_part[0] + s_part[1] + s_part[2] + s_part[3];
+}
+
+// One block per (task, heavy row): the sum of the row's chunk partials gives
+// the row's bit.  Runs after k_role has written the rows' words (with the
+// heavy bits clear).
+__global__ void __launch_bounds__(256)
+k_role_heavy_fix(DevKB kb, const RoleTask* __restrict__ tasks, uint32_t n_tasks, uint32_t i0,
+                 const uint32_t* __restrict__ partial) {
+  __shared__ uint32_t s_part[4];
+  const uint32_t i = i0 + blockIdx.x;
+  const RoleTask T = tasks[heavy_task<false>(tasks, n_tasks, i)];
+  const uint32_t hrow = T.hr0 + (i - T.c_first);
+  const uint32_t c0 = kb.heavy_chunk0[hrow], n = kb.heavy_chunk0[hrow + 1] - c0;
+  const uint32_t* p = partial + T.h_first + (c0 - T.hc0);
+  uint32_t cnt = 0;
+#pragma unroll 8
+  for (uint32_t c = threadIdx.x; c < n; c += 256) cnt += p[c];
+  cnt = wave_sum(cnt);
+  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    cnt = s_part[0] + s_part[1] + s_part[2] + s_part[3];
+    const uint32_t x = kb.heavy_rows[hrow];
+    const unsigned long long bit = 1ull << (x & 63);
+    unsigned long long* word = reinterpret_cast<unsigned long long*>(out_ptr(kb, T.out_row) + (x >> 6));
+    if (cnt >= T.lo && cnt <= T.hi) atomicOr(word, bit);
+    else atomicAnd(word, ~bit);
+  }
+}
 
 // Zero-count results for the words of a role direction without assertions.
 __global__ void __launch_bounds__(256)
@@ -418,6 +491,10 @@ DevKB dev_view(const hth_kb_s& kb) {
   d.objbase = kb.objbase;
   d.ctg_fwd = kb.ctg_fwd;
   d.ctg_inv = kb.ctg_inv;
+  d.heavy_rows = kb.heavy_rows;
+  d.heavy_chunks = kb.heavy_chunks;
+  d.heavy_chunk0 = kb.heavy_chunk0;
+  d.heavy_min = kb.heavy_min;
   d.pos = kb.pos;
   d.neg = kb.neg;
   d.n_concepts = kb.d.n_concepts;
@@ -630,6 +707,19 @@ hth_status launch_groups(Launcher& L, const DevKB& d, const GroupTask* groups,
   return HTH_OK;
 }
 
+// heavy-row scratch of a plan: a partial count per (role task, chunk of its
+// direction), the largest level's worth (levels run one after the other)
+size_t heavy_counter_bytes(const hth_kb_s& kb, const Plan& P) {
+  size_t most = 0;
+  for (const PlanLevel& PL : P.levels) {
+    size_t nb = 0;
+    for (const RoleTask& t : PL.roles)
+      nb += kb.chunk_first[2 * t.role + t.inv + 1] - kb.chunk_first[2 * t.role + t.inv];
+    most = std::max(most, nb);
+  }
+  return align_up(most * 4, 256);
+}
+
 // bytes of the packed tables plus slots plus T area for a plan
 size_t plan_workspace_bytes(const hth_kb_s& kb, const Plan& P) {
   size_t tables = 0;
@@ -652,7 +742,8 @@ size_t plan_workspace_bytes(const hth_kb_s& kb, const Plan& P) {
   add(n_fill, sizeof(FillTask));
   add(P.code.size(), sizeof(uint32_t));
   add(9 * n_grp + 8, sizeof(uint32_t));     // XCD slot tables: at most 8 more than groups per chunk
-  return align_up(tables, 256) + (size_t)P.n_slots * kb.S * 8 + (max_groups ? t_area_bytes(kb) : 0);
+  return align_up(tables, 256) + (size_t)P.n_slots * kb.S * 8 + (max_groups ? t_area_bytes(kb) : 0) +
+         heavy_counter_bytes(kb, P);
 }
 
 std::once_flag g_attr_once;
@@ -663,7 +754,7 @@ std::once_flag g_attr_once;
 struct Prepared {
   Plan P;
   Blob blob;
-  struct LevelAt { size_t mat, role, group, fill, nrole, ngroup, nfill; };
+  struct LevelAt { size_t mat, role, group, fill, nrole, ngroup, nfill, nhb, nhc; };
   std::vector<LevelAt> at;
   size_t root_at = 0;
   std::vector<std::vector<RoleTask>> lv_roles;
@@ -671,6 +762,7 @@ struct Prepared {
   std::vector<std::vector<GroupChunk>> lv_chunks;
   size_t n_thr_groups = 0, n_thr_tasks = 0;
   size_t o_thr = 0, o_thg = 0, o_reg = 0, o_role = 0, o_grp = 0, o_mem = 0, o_fill = 0, o_code = 0, o_xslot = 0;
+  size_t o_hcnt = 0;   // heavy-row counters (workspace offset)
   size_t tables = 0, need = 0;
   uint32_t n_hyps = 0;
 };
@@ -692,10 +784,17 @@ void prepare(const hth_kb_s& kb, Plan&& plan, uint32_t n_hyps, Prepared& X) {
   X.lv_chunks.assign(NL, {});
   for (size_t L = 0; L < NL; ++L) {
     const PlanLevel& PL = P.levels[L];
-    X.at[L] = {regions.size(), roles.size(), groups.size(), fills.size(), 0, 0, 0};
+    X.at[L] = {regions.size(), roles.size(), groups.size(), fills.size(), 0, 0, 0, 0, 0};
     regions.insert(regions.end(), PL.mat.begin(), PL.mat.end());
     for (RoleTask t : PL.roles) {
-      t.n_words = kb.n_words[2 * t.role + t.inv];
+      const uint32_t rd = 2 * t.role + t.inv;
+      t.n_words = kb.n_words[rd];
+      t.hr0 = kb.heavy_first[rd];
+      t.hc0 = kb.chunk_first[rd];
+      t.h_first = (uint32_t)X.at[L].nhb;
+      t.c_first = (uint32_t)X.at[L].nhc;
+      X.at[L].nhb += kb.chunk_first[rd + 1] - kb.chunk_first[rd];
+      X.at[L].nhc += kb.heavy_first[rd + 1] - kb.heavy_first[rd];
       if (t.n_words < kb.W) fills.push_back(FillTask{t.out_row, t.lo == 0 ? 1u : 0u});
       roles.push_back(t);
       X.lv_roles[L].push_back(t);
@@ -745,7 +844,8 @@ void prepare(const hth_kb_s& kb, Plan&& plan, uint32_t n_hyps, Prepared& X) {
   X.tables = align_up(X.blob.bytes.size(), 256);
   size_t max_groups = 0;
   for (const PlanLevel& PL : P.levels) max_groups = std::max(max_groups, PL.groups.size());
-  X.need = X.tables + (size_t)P.n_slots * kb.S * 8 + (max_groups ? t_area_bytes(kb) : 0);
+  X.o_hcnt = X.tables + (size_t)P.n_slots * kb.S * 8 + (max_groups ? t_area_bytes(kb) : 0);
+  X.need = X.o_hcnt + heavy_counter_bytes(kb, P);
 }
 
 hth_status check_ws(const Prepared& X, const char* ws, size_t ws_bytes) {
@@ -814,6 +914,18 @@ hth_status launch_prepared(hth_kb_s& kb, const Prepared& X, char* ws, uint32_t* 
     }
     s = launch_roles(Lc, d, rol + at.role, X.lv_roles[L]);
     if (s) return s;
+    if (at.nhc) {   // heavy rows: chunk partials, then the rows' bits
+      uint32_t* partial = reinterpret_cast<uint32_t*>(ws + X.o_hcnt);
+      const uint32_t nt = (uint32_t)at.nrole;
+      s = split_launch(Lc, HTH_K_ROLE, 0.0, at.nhb, 1, 256, [&](uint32_t b0, uint32_t, uint32_t blocks) {
+        hipLaunchKernelGGL(k_role_heavy, dim3(blocks), dim3(256), 0, st, d, rol + at.role, nt, b0, partial);
+      });
+      if (s) return s;
+      s = split_launch(Lc, HTH_K_ROLE, 0.0, at.nhc, 1, 256, [&](uint32_t i0, uint32_t, uint32_t blocks) {
+        hipLaunchKernelGGL(k_role_heavy_fix, dim3(blocks), dim3(256), 0, st, d, rol + at.role, nt, i0, partial);
+      });
+      if (s) return s;
+    }
     s = launch_groups(Lc, d, grp + at.group, mem, X.lv_groups[L], X.lv_chunks[L],
                       reinterpret_cast<const uint32_t*>(ws + X.o_xslot), tarea);
     if (s) return s;
@@ -841,7 +953,7 @@ extern "C" hth_status hth_workspace_bytes(hth_kb kb, uint32_t max_nodes, uint32_
   if (!kb || !bytes) return fail(HTH_E_INVALID, "NULL argument");
   if (max_hyps == 0 || max_nodes < max_hyps) return fail(HTH_E_RANGE, "need max_nodes >= max_hyps >= 1");
   *bytes = align_up(table_bound(max_nodes, max_hyps), 256) + (size_t)(max_nodes + 2) * kb->S * 8 +
-           t_area_bytes(*kb);
+           t_area_bytes(*kb) + align_up((size_t)(max_nodes + 2) * kb->chunk_most * 4, 256);
   return HTH_OK;
 }
 

@@ -69,7 +69,25 @@ struct RoleTask {
   uint32_t lo, hi, sat;
   uint32_t out_row;    // n_concepts + slot
   uint32_t n_words;    // non-empty words of (role, inv), set at launch
-  uint32_t pad;
+  // heavy rows of (role, inv), set at launch (see HeavyChunk)
+  uint32_t h_first;    // first block of this task in its level's heavy-row launch
+  uint32_t c_first;    // first (task, heavy row) pair of this task in its level
+  uint32_t hc0;        // first chunk of the direction in the chunk table
+  uint32_t hr0;        // first heavy row of the direction in the heavy-row table
+};
+
+// Subjects with more than DevKB::heavy_min assertions in a direction ("heavy
+// rows") are left out of the one-wave-per-word pass: their assertions are cut
+// into chunks of kHeavyChunk, every chunk is counted by one block into a
+// partial count of its own, and a last kernel sums the partials of each
+// (task, heavy row) and sets the row's bit.  The chunk table lists, per
+// direction, chunk k of heavy row `hrow` (an index into the heavy-row table,
+// which holds the subjects); heavy_chunk0[hrow] is the row's first chunk.
+constexpr uint32_t kHeavyChunk = 4096;
+constexpr uint32_t kHeavyMinFloor = 1024;   // smallest heavy-row threshold
+struct HeavyChunk {
+  uint32_t hrow;
+  uint32_t k;
 };
 
 // Output rows of role nodes whose (role, direction) has words without any
@@ -120,6 +138,9 @@ struct DevKB {
   const uint32_t* objbase;    // [R][2][W+1] objects before each word
   const int32_t* ctg_fwd;     // [E] object ranks of the forward targets
   const int32_t* ctg_inv;     // [E] object ranks of the inverse targets
+  const uint32_t* heavy_rows; // subjects of the heavy rows, by direction 2r + dir, increasing
+  const HeavyChunk* heavy_chunks;  // by direction, then heavy row, then k
+  const uint32_t* heavy_chunk0;    // [heavy rows + 1] first chunk of each heavy row
   const uint64_t* pos;        // [S]
   const uint64_t* neg;        // [S]
   uint32_t* counts;           // [n_hyps][2]
@@ -127,6 +148,7 @@ struct DevKB {
   uint32_t n_concepts;
   uint32_t n_fixed;           // n_concepts + n_sets: first workspace slot row
   uint32_t N, W, S;
+  uint32_t heavy_min;         // rows with more assertions are heavy rows
   uint64_t tail;              // valid-bit mask of word W-1
 };
 

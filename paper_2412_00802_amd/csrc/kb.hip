@@ -49,9 +49,11 @@ __global__ void k_gather_bases(const int64_t* __restrict__ off, uint32_t R, uint
 }
 
 // One thread per (role, subject): check the row, write its relative offset,
-// count its assertions per object into inv_off[r][y + 1].
+// count its assertions per object into inv_off[r][y + 1].  Rows with more
+// than hmin assertions (heavy rows) only get their offsets checked here; their
+// assertions are checked and counted chunk by chunk by k_validate_heavy.
 __global__ void k_validate_rows(const int64_t* __restrict__ off, const int32_t* __restrict__ tg,
-                                const uint64_t* __restrict__ base, uint32_t N,
+                                const uint64_t* __restrict__ base, uint32_t N, uint32_t hmin,
                                 uint32_t* __restrict__ fwd_off, uint32_t* __restrict__ inv_cnt,
                                 uint32_t* __restrict__ maxdeg, uint32_t* __restrict__ flags) {
   uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -68,6 +70,7 @@ __global__ void k_validate_rows(const int64_t* __restrict__ off, const int32_t* 
   fo[x] = (uint32_t)(o0 - b0);
   if (x == N - 1) fo[N] = (uint32_t)(o1 - b0);
   atomicMax(maxdeg + r, (uint32_t)(o1 - o0));
+  if (o1 - o0 > (int64_t)hmin) return;
   uint32_t* cnt = inv_cnt + (size_t)r * (N + 1);
   int32_t prev = -1;
   uint32_t bad = 0;
@@ -220,13 +223,15 @@ k_scan_apply(uint32_t* __restrict__ a, uint32_t N, uint32_t nb, const uint32_t* 
 // Scatter: assertion (x, y) of role r becomes (y, x) of r^-.  Row order inside
 // an inverse row follows the atomics and is not fixed; evaluation results do
 // not depend on it.
+// Heavy rows (more than hmin assertions) are scattered by k_scatter_heavy.
 __global__ void k_scatter_inverse(const uint32_t* __restrict__ fwd_off, const int32_t* __restrict__ tg,
-                                  const uint64_t* __restrict__ base, uint32_t N,
+                                  const uint64_t* __restrict__ base, uint32_t N, uint32_t hmin,
                                   uint32_t* __restrict__ cursor, int32_t* __restrict__ inv_tg) {
   uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t r = blockIdx.y;
   if (x >= N) return;
   const uint32_t* fo = fwd_off + (size_t)r * (N + 1);
+  if (fo[x + 1] - fo[x] > hmin) return;
   const int32_t* t = tg + base[r];
   int32_t* it = inv_tg + base[r];
   uint32_t* cur = cursor + (size_t)r * (N + 1);
@@ -234,6 +239,44 @@ __global__ void k_scatter_inverse(const uint32_t* __restrict__ fwd_off, const in
     uint32_t y = (uint32_t)t[e];
     uint32_t pos = atomicAdd(cur + y, 1u);
     it[pos] = (int32_t)x;
+  }
+}
+
+// The assertions of the forward heavy rows of one role, one block per chunk of
+// kHeavyChunk (tg and fo: the role's targets and relative offsets, inv_cnt and
+// cursor its inverse rows).  Validation: every target in [0, N), strictly
+// increasing inside the row; each assertion counted for its object.
+__global__ void __launch_bounds__(256)
+k_validate_heavy(const int32_t* __restrict__ tg, const uint32_t* __restrict__ fo, const uint32_t* __restrict__ rows,
+                 const HeavyChunk* __restrict__ chunks, uint32_t N, uint32_t* __restrict__ inv_cnt,
+                 uint32_t* __restrict__ flags) {
+  const HeavyChunk c = chunks[blockIdx.x];
+  const uint32_t x = rows[c.hrow];
+  const uint32_t end = fo[x + 1];
+  const uint32_t e0 = fo[x] + c.k * kHeavyChunk, e1 = min(end, e0 + kHeavyChunk);
+  uint32_t bad = 0;
+  for (uint32_t e = e0 + threadIdx.x; e < e1; e += 256) {
+    const int32_t t = tg[e];
+    if (t < 0 || (uint32_t)t >= N) {
+      bad |= F_TARGET;
+      continue;
+    }
+    if (e + 1 < end && tg[e + 1] <= t) bad |= F_ORDER;
+    atomicAdd(inv_cnt + t + 1, 1u);
+  }
+  if (bad) atomicOr(flags, bad);
+}
+
+// Scatter of the forward heavy rows' assertions (after validation).
+__global__ void __launch_bounds__(256)
+k_scatter_heavy(const int32_t* __restrict__ tg, const uint32_t* __restrict__ fo, const uint32_t* __restrict__ rows,
+                const HeavyChunk* __restrict__ chunks, uint32_t* __restrict__ cursor, int32_t* __restrict__ inv_tg) {
+  const HeavyChunk c = chunks[blockIdx.x];
+  const uint32_t x = rows[c.hrow];
+  const uint32_t e0 = fo[x] + c.k * kHeavyChunk, e1 = min(fo[x + 1], e0 + kHeavyChunk);
+  for (uint32_t e = e0 + threadIdx.x; e < e1; e += 256) {
+    const uint32_t y = (uint32_t)tg[e];
+    inv_tg[atomicAdd(cursor + y, 1u)] = (int32_t)x;
   }
 }
 
@@ -284,9 +327,31 @@ k_object_rank(const int32_t* __restrict__ tg, uint64_t e0, uint64_t n, const uin
 }
 
 struct DerivedLayout {
-  size_t fwd_off, inv_off, inv_tg, cursor, bsum, base, meta, words, wbase, objmask, objbase, ctg, total;
+  size_t fwd_off, inv_off, inv_tg, cursor, bsum, base, meta, words, wbase, objmask, objbase, ctg;
+  size_t heavy, hchunk, hchunk0, total;
   uint32_t nb;
+  size_t heavy_cap, chunk_cap;   // entries
 };
+
+// Heavy rows of one direction (more than hmin assertions), appended in any
+// order as (direction 2r + dir, subject, degree); the host sorts them and
+// writes the heavy-row and chunk tables.  A direction holds at most
+// E_dir / (hmin + 1) of them, so `cap` (from the floor of hmin) is never
+// reached; the check keeps the writes in bounds regardless.
+__global__ void __launch_bounds__(256)
+k_heavy_rows(const uint32_t* __restrict__ o, uint32_t N, uint32_t hmin, uint32_t rd, uint32_t cap,
+             uint32_t* __restrict__ count, uint32_t* __restrict__ out) {
+  const uint32_t x = blockIdx.x * 256 + threadIdx.x;
+  if (x >= N) return;
+  const uint32_t deg = o[x + 1] - o[x];
+  if (deg <= hmin) return;
+  const uint32_t slot = atomicAdd(count, 1u);
+  if (slot < cap) {
+    out[3 * (size_t)slot] = rd;
+    out[3 * (size_t)slot + 1] = x;
+    out[3 * (size_t)slot + 2] = deg;
+  }
+}
 
 // Words (64 consecutive subjects) with at least one assertion, per role and
 // direction, in increasing order: the role passes visit only these, and a
@@ -349,6 +414,11 @@ static DerivedLayout layout_for(const hth_kb_desc& d) {
   L.objmask = at; at += align_up(2 * R * ((N + 63) / 64) * 8, 256);
   L.objbase = at; at += align_up(2 * R * ((N + 63) / 64 + 1) * 4, 256);
   L.ctg = at; at += align_up((size_t)d.n_edges * 8, 256);     // both directions
+  L.heavy_cap = 2 * (d.n_edges / (kHeavyMinFloor + 1)) + 2;
+  L.chunk_cap = 2 * (d.n_edges / kHeavyChunk) + L.heavy_cap + 2;
+  L.heavy = at; at += align_up(L.heavy_cap * 12, 256);
+  L.hchunk = at; at += align_up(L.chunk_cap * sizeof(HeavyChunk), 256);
+  L.hchunk0 = at; at += align_up((L.heavy_cap + 1) * 4, 256);
   L.total = at;
   return L;
 }
@@ -380,6 +450,93 @@ extern "C" hth_status hth_kb_derived_bytes(const hth_kb_desc* desc, size_t* byte
   if (s) return s;
   if (!bytes) return fail(HTH_E_INVALID, "bytes is NULL");
   *bytes = layout_for(*desc).total;
+  return HTH_OK;
+}
+
+// A device error flag word -> HTH_E_INVALID with the reasons.
+static hth_status check_flags(const uint32_t* flags, hipStream_t st) {
+  uint32_t hflags = 0;
+  HTH_HIP(hipMemcpyAsync(&hflags, flags, 4, hipMemcpyDeviceToHost, st));
+  HTH_HIP(hipStreamSynchronize(st));
+  if (!hflags) return HTH_OK;
+  std::string m = "invalid knowledge base:";
+  if (hflags & F_NONMONO) m += " role offsets not monotone;";
+  if (hflags & F_TARGET) m += " role target outside [0, N);";
+  if (hflags & F_ORDER) m += " role targets not strictly increasing in a row;";
+  if (hflags & F_PAD) m += " padding bits set in a bit row;";
+  return fail(HTH_E_INVALID, m);
+}
+
+// Appends to `trip` the heavy rows of direction `dir` of every role whose
+// largest degree there exceeds heavy_min, as (2r + dir, subject, degree).
+static hth_status find_heavy(hth_kb_s* kb, const DerivedLayout& L, int dir, uint32_t* count,
+                             std::vector<uint32_t>& trip, hipStream_t st) {
+  const uint32_t R = kb->d.n_roles, N = kb->N;
+  bool any = false;
+  for (uint32_t r = 0; r < R; ++r) any |= kb->max_deg[dir][r] > kb->heavy_min;
+  if (!any) return HTH_OK;
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, count, (size_t)1, 0u);
+  for (uint32_t r = 0; r < R; ++r)
+    if (kb->max_deg[dir][r] > kb->heavy_min)
+      hipLaunchKernelGGL(k_heavy_rows, dim3((N + 255) / 256), dim3(256), 0, st,
+                         (dir ? kb->inv_off : kb->fwd_off) + (size_t)r * (N + 1), N, kb->heavy_min,
+                         2 * r + dir, (uint32_t)L.heavy_cap, count, kb->heavy_rows);
+  HTH_HIP(hipGetLastError());
+  uint32_t nh = 0;
+  HTH_HIP(hipMemcpyAsync(&nh, count, 4, hipMemcpyDeviceToHost, st));
+  HTH_HIP(hipStreamSynchronize(st));
+  if (nh > L.heavy_cap || trip.size() / 3 + nh > L.heavy_cap) return fail(HTH_E_RANGE, "heavy-row table overflow");
+  const size_t at = trip.size();
+  trip.resize(at + 3 * (size_t)nh);
+  HTH_HIP(hipMemcpyAsync(trip.data() + at, kb->heavy_rows, 3 * (size_t)nh * 4, hipMemcpyDeviceToHost, st));
+  HTH_HIP(hipStreamSynchronize(st));
+  return HTH_OK;
+}
+
+struct HeavyTables {
+  std::vector<uint32_t> heavy_first, chunk_first;   // [2R+1]
+  uint32_t heavy_most = 0, chunk_most = 0;
+};
+
+// Sorts the heavy rows by (direction, subject) and writes the heavy-row,
+// chunk and first-chunk tables to the device.
+static hth_status upload_heavy(hth_kb_s* kb, const DerivedLayout& L, const std::vector<uint32_t>& trip,
+                               HeavyTables& T, hipStream_t st) {
+  const uint32_t R = kb->d.n_roles;
+  const uint32_t nh = (uint32_t)(trip.size() / 3);
+  T.heavy_first.assign(2 * R + 1, 0);
+  T.chunk_first.assign(2 * R + 1, 0);
+  if (!nh) return HTH_OK;
+  std::vector<uint32_t> ord(nh);
+  for (uint32_t i = 0; i < nh; ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) {
+    return trip[3 * a] != trip[3 * b] ? trip[3 * a] < trip[3 * b] : trip[3 * a + 1] < trip[3 * b + 1];
+  });
+  std::vector<uint32_t> rows(nh), chunk0(nh + 1);
+  std::vector<HeavyChunk> chunks;
+  std::vector<uint32_t> per(2 * R, 0), cper(2 * R, 0);
+  for (uint32_t i = 0; i < nh; ++i) {
+    const uint32_t* t = &trip[3 * (size_t)ord[i]];
+    rows[i] = t[1];
+    per[t[0]]++;
+    const uint32_t nc = (t[2] + kHeavyChunk - 1) / kHeavyChunk;
+    cper[t[0]] += nc;
+    chunk0[i] = (uint32_t)chunks.size();
+    for (uint32_t k = 0; k < nc; ++k) chunks.push_back(HeavyChunk{i, k});
+  }
+  chunk0[nh] = (uint32_t)chunks.size();
+  if (chunks.size() > L.chunk_cap) return fail(HTH_E_RANGE, "heavy chunk table overflow");
+  for (uint32_t rd = 0; rd < 2 * R; ++rd) {
+    T.heavy_first[rd + 1] = T.heavy_first[rd] + per[rd];
+    T.chunk_first[rd + 1] = T.chunk_first[rd] + cper[rd];
+    T.heavy_most = std::max(T.heavy_most, per[rd]);
+    T.chunk_most = std::max(T.chunk_most, cper[rd]);
+  }
+  HTH_HIP(hipMemcpyAsync(kb->heavy_rows, rows.data(), rows.size() * 4, hipMemcpyHostToDevice, st));
+  HTH_HIP(hipMemcpyAsync(kb->heavy_chunks, chunks.data(), chunks.size() * sizeof(HeavyChunk),
+                         hipMemcpyHostToDevice, st));
+  HTH_HIP(hipMemcpyAsync(kb->heavy_chunk0, chunk0.data(), chunk0.size() * 4, hipMemcpyHostToDevice, st));
+  HTH_HIP(hipStreamSynchronize(st));
   return HTH_OK;
 }
 
@@ -435,19 +592,30 @@ static hth_status kb_build(hth_kb_s* kb, char* derived, hipStream_t st) {
     fill(kb->inv_off, offs, 0);
     dim3 g((N + tb - 1) / tb, R);
     hipLaunchKernelGGL(k_validate_rows, g, dim3(tb), 0, st, d.role_offsets, d.role_targets, base,
-                       N, kb->fwd_off, kb->inv_off, maxdeg, flags);
+                       N, kb->heavy_min, kb->fwd_off, kb->inv_off, maxdeg, flags);
     HTH_HIP(hipGetLastError());
-    uint32_t hflags = 0;
-    HTH_HIP(hipMemcpyAsync(&hflags, flags, 4, hipMemcpyDeviceToHost, st));
-    HTH_HIP(hipStreamSynchronize(st));
-    if (hflags) {
-      std::string m = "invalid knowledge base:";
-      if (hflags & F_NONMONO) m += " role offsets not monotone;";
-      if (hflags & F_TARGET) m += " role target outside [0, N);";
-      if (hflags & F_ORDER) m += " role targets not strictly increasing in a row;";
-      if (hflags & F_PAD) m += " padding bits set in a bit row;";
-      return fail(HTH_E_INVALID, m);
-    }
+    HTH_HIP(hipMemcpyAsync(kb->max_deg[0].data(), maxdeg, R * 4, hipMemcpyDeviceToHost, st));
+    hth_status fs = check_flags(flags, st);
+    if (fs) return fs;
+    // forward heavy rows: checked, counted and later scattered chunk by chunk
+    // (tables of the forward direction only until the inverse exists)
+    kb->heavy_rows = reinterpret_cast<uint32_t*>(derived + L.heavy);
+    kb->heavy_chunks = reinterpret_cast<HeavyChunk*>(derived + L.hchunk);
+    kb->heavy_chunk0 = reinterpret_cast<uint32_t*>(derived + L.hchunk0);
+    std::vector<uint32_t> trip;
+    fs = find_heavy(kb, L, 0, meta + 1, trip, st);
+    if (fs) return fs;
+    HeavyTables fwd;
+    fs = upload_heavy(kb, L, trip, fwd, st);
+    if (fs) return fs;
+    for (uint32_t r = 0; r < R; ++r)
+      if (uint32_t nc = fwd.chunk_first[2 * r + 1] - fwd.chunk_first[2 * r])
+        hipLaunchKernelGGL(k_validate_heavy, dim3(nc), dim3(256), 0, st, d.role_targets + kb->role_base[r],
+                           kb->fwd_off + (size_t)r * (N + 1), kb->heavy_rows,
+                           kb->heavy_chunks + fwd.chunk_first[2 * r], N, kb->inv_off + (size_t)r * (N + 1), flags);
+    HTH_HIP(hipGetLastError());
+    fs = check_flags(flags, st);
+    if (fs) return fs;
     dim3 gs(L.nb, R);
     hipLaunchKernelGGL(k_scan_sums, gs, dim3(kScanThreads), 0, st, kb->inv_off, N, L.nb, bsum,
                        maxdeg + R);
@@ -458,9 +626,14 @@ static hth_status kb_build(hth_kb_s* kb, char* derived, hipStream_t st) {
       hipLaunchKernelGGL(k_copy_u32, dim3(gg), dim3(256), 0, st, kb->inv_off, cursor, offs);
     }
     hipLaunchKernelGGL(k_scatter_inverse, g, dim3(tb), 0, st, kb->fwd_off, d.role_targets, base,
-                       N, cursor, kb->inv_tg);
+                       N, kb->heavy_min, cursor, kb->inv_tg);
+    for (uint32_t r = 0; r < R; ++r)
+      if (uint32_t nc = fwd.chunk_first[2 * r + 1] - fwd.chunk_first[2 * r])
+        hipLaunchKernelGGL(k_scatter_heavy, dim3(nc), dim3(256), 0, st, d.role_targets + kb->role_base[r],
+                           kb->fwd_off + (size_t)r * (N + 1), kb->heavy_rows,
+                           kb->heavy_chunks + fwd.chunk_first[2 * r], cursor + (size_t)r * (N + 1),
+                           kb->inv_tg + kb->role_base[r]);
     HTH_HIP(hipGetLastError());
-    HTH_HIP(hipMemcpyAsync(kb->max_deg[0].data(), maxdeg, R * 4, hipMemcpyDeviceToHost, st));
     HTH_HIP(hipMemcpyAsync(kb->max_deg[1].data(), maxdeg + R, R * 4, hipMemcpyDeviceToHost, st));
     // non-empty word lists; the two directions' offsets are [R][N+1] each, so
     // run the kernel once per direction with list rows 2r + dir
@@ -513,6 +686,16 @@ static hth_status kb_build(hth_kb_s* kb, char* derived, hipStream_t st) {
       }
     }
     HTH_HIP(hipGetLastError());
+    // the heavy-row tables of both directions
+    fs = find_heavy(kb, L, 1, meta + 1, trip, st);
+    if (fs) return fs;
+    HeavyTables all;
+    fs = upload_heavy(kb, L, trip, all, st);
+    if (fs) return fs;
+    kb->heavy_first = all.heavy_first;
+    kb->chunk_first = all.chunk_first;
+    kb->heavy_most = all.heavy_most;
+    kb->chunk_most = all.chunk_most;
   }
   uint32_t hflags = 0;
   HTH_HIP(hipMemcpyAsync(&hflags, flags, 4, hipMemcpyDeviceToHost, st));
@@ -559,6 +742,8 @@ extern "C" hth_status hth_kb_create(const hth_kb_desc* desc, void* derived, size
   kb->tune.group_unroll = (uint32_t)env_u("HTHEDL_GROUP_UNROLL", kb->tune.group_unroll);
   kb->tune.region_reg = (uint32_t)env_u("HTHEDL_REGION_REG", kb->tune.region_reg);
   kb->tune.t_compact = (uint32_t)env_u("HTHEDL_T_COMPACT", kb->tune.t_compact);
+  kb->heavy_min = (uint32_t)std::min<uint64_t>(
+      1u << 30, std::max<uint64_t>(kHeavyMinFloor, env_u("HTHEDL_HEAVY_MIN", kb->heavy_min)));
   kb->lds_per_block = prop.sharedMemPerBlock;
   s = kb_build(kb, static_cast<char*>(derived), static_cast<hipStream_t>(stream));
   if (s) {

@@ -28,6 +28,14 @@ struct hth_kb_s {
   int32_t* ctg_fwd = nullptr;          // [E] object ranks of the forward targets
   int32_t* ctg_inv = nullptr;          // [E] object ranks of the inverse targets
   std::vector<uint32_t> n_obj;         // [R][2]; ranks exist where 2 n_obj <= N
+  uint32_t heavy_min = 2048;           // rows with more assertions are heavy rows
+  uint32_t* heavy_rows = nullptr;      // subjects of the heavy rows, by direction
+  hth::HeavyChunk* heavy_chunks = nullptr;
+  uint32_t* heavy_chunk0 = nullptr;    // first chunk of each heavy row, then the total
+  std::vector<uint32_t> heavy_first;   // [2R+1] first heavy row of direction 2r + dir
+  std::vector<uint32_t> chunk_first;   // [2R+1] first chunk of direction 2r + dir
+  uint32_t heavy_most = 0;             // most heavy rows in one direction
+  uint32_t chunk_most = 0;             // most heavy chunks in one direction
   const uint64_t* pos = nullptr;
   const uint64_t* neg = nullptr;
   const uint64_t* sets = nullptr;      // caller's set table (hth_kb_set_sets)

@@ -196,6 +196,29 @@ def test_kb_validation(gpu):
     assert "padding" in str(e.value)
 
 
+def test_kb_validation_heavy_rows(gpu):
+    """Rows above the heavy-row threshold are checked chunk by chunk at load:
+    an unsorted pair, a duplicate across a chunk boundary and a target out of
+    range are each found; a valid heavy row loads."""
+    n = 20000
+    row = np.arange(0, 3 * 4096 + 10) + 50                # subject 7, degree 12298: 4 chunks
+    edges = [(7, int(t)) for t in row] + [(8, 1), (8, 3)]
+    good = synth.kb_from_edges(n, [[1, 2, 3]], [edges])
+    hthedl.Engine(good).close()
+    off0 = int(good.role_offsets[0, 7])
+    for pos, val, msg in ((100, 50 + 99, "strictly increasing"),      # equals its predecessor
+                          (4096, 50 + 4095, "strictly increasing"),   # first of chunk 1 = last of chunk 0
+                          (8191, 50 + 8193, "strictly increasing"),   # last of chunk 1 above its successor
+                          (5000, n, "outside"),
+                          (12297, -1, "outside")):
+        bad = synth.kb_from_edges(n, [[1, 2, 3]], [edges])
+        bad.role_targets = bad.role_targets.copy()
+        bad.role_targets[off0 + pos] = val
+        with pytest.raises(hthedl.HthError) as e:
+            hthedl.Engine(bad)
+        assert msg in str(e.value), (pos, val)
+
+
 def test_max_degrees_and_inverse(gpu):
     cfg = synth.small_config(n=7000, n_roles=3, cap=200, seed_index=800)
     kb = synth.make_kb(cfg)
@@ -478,3 +501,74 @@ def test_grids_beyond_one_dispatch(region_reg):
     assert np.array_equal(whole, parts)
     pick = rng.choice(len(hyps), size=40, replace=False)
     assert np.array_equal(whole[pick], Oracle(kb).coverages([hyps[i] for i in pick]))
+
+
+def heavy_kb(n=60000, seed=7):
+    """Roles whose rows straddle the heavy-row threshold: role 0 has subjects
+    of degree 1025 .. 30000 (some sharing a word with light subjects, some in
+    adjacent words) over light rows of degree 0..40; role 1 has a few objects
+    with thousands of subjects (heavy rows of the inverse direction)."""
+    rnd = np.random.default_rng(seed)
+    edges0 = set()
+    heavy = {64 * 3 + 5: 1025, 64 * 3 + 6: 2048, 64 * 3 + 63: 2049, 64 * 4: 4096, 64 * 9 + 31: 4097,
+             64 * 200 + 1: 9000, n - 1: 30000, 64 * 500 + 2: 12288}
+    for s, d in heavy.items():
+        for t in rnd.choice(n, size=d, replace=False):
+            edges0.add((s, int(t)))
+    for s in range(0, n, 3):
+        if s not in heavy:
+            for t in rnd.choice(n, size=int(rnd.integers(0, 41)), replace=False):
+                edges0.add((s, int(t)))
+    edges1 = set()
+    for obj, d in ((11, 5000), (12, 1500), (64 * 7, 20000)):
+        for s in rnd.choice(n, size=d, replace=False):
+            edges1.add((int(s), obj))
+    for s in rnd.choice(n, size=20000):
+        edges1.add((int(s), int(rnd.integers(0, n))))
+    hit = np.zeros(n, bool)
+    for s, t in edges0:
+        if s in heavy:
+            hit[t] = True
+    concepts = [list(rnd.choice(n, size=n // 2, replace=False)),
+                list(rnd.choice(n, size=n // 100, replace=False)),
+                list(np.flatnonzero(~hit))]
+    return synth.kb_from_edges(n, concepts, [sorted(edges0), sorted(edges1)], None,
+                               pos=list(range(0, n, 2)), neg=list(range(1, n, 3)))
+
+
+def heavy_zoo():
+    fillers = [("atom", 0), ("atom", 1), ("atom", 2), ("not", ("atom", 2)), ("top",),
+               ("atleast", 2, 1, 1, ("atom", 0))]
+    hs = []
+    for r in (0, 1):
+        for inv in (0, 1):
+            for c in fillers:
+                hs.append(("exists", r, inv, c))
+                hs.append(("forall", r, inv, c))
+                for k in (0, 1, 2, 512, 1024, 1025, 2048, 2049, 4096, 4097, 8999, 9000, 30000, 30001):
+                    hs.append(("atleast", k, r, inv, c))
+                    hs.append(("atmost", k, r, inv, c))
+                hs.append(("exactly", 1025, r, inv, c))
+                hs.append(("exactly", 2 * 1500 // 3, r, inv, c))
+    hs.append(("and", ("exists", 0, 0, ("atom", 2)), ("atleast", 5000, 1, 1, ("top",))))
+    return hs
+
+
+@pytest.mark.parametrize("heavy_min", [None, 1024, 100000])
+def test_heavy_rows(monkeypatch, heavy_min):
+    """Rows above the heavy-row threshold are counted chunk by chunk on many
+    blocks; the counts equal the oracle's at every threshold (100000: no row
+    is heavy), in the plain path, the batch with shared passes, and the batch
+    with every role node on its own."""
+    if heavy_min is not None:
+        monkeypatch.setenv("HTHEDL_HEAVY_MIN", str(heavy_min))
+    kb = heavy_kb()
+    hs = heavy_zoo()
+    eng = check(kb, hs, label=f"heavy rows, threshold {heavy_min}")
+    hthedl.hth_kb_set_tuning(eng.handle, group_min=0)
+    want = Oracle(kb).coverages(hs)
+    assert np.array_equal(eng.eval_batch(hs), want)
+    o = Oracle(kb)
+    for h in (("exists", 0, 0, ("atom", 2)), ("atleast", 2049, 0, 0, ("top",)), ("forall", 1, 1, ("atom", 0))):
+        (p, q), bits = eng.eval_one(h, instances=True)
+        np.testing.assert_array_equal(bits, o.ext_bits(h))
