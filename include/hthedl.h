@@ -156,7 +156,11 @@ hth_status hth_kb_max_degree(hth_kb kb, uint32_t role, uint32_t inv, uint32_t* o
  *   LDS-stack kernel for every region);
  * t_compact: 1 = shared passes over a role direction whose objects (targets)
  *   are at most half of the individuals keep transposed child rows for those
- *   objects only, indexed by object rank (0 = rows for every individual). */
+ *   objects only, indexed by object rank (0 = rows for every individual);
+ * t_segment_kb: KiB of transposed child rows fetched per pass: a shared pass
+ *   whose rows are larger runs as 2..4 passes over consecutive row ranges,
+ *   carrying each subject's partial counts between them, so that each pass's
+ *   rows fit one XCD's L2 (0 = one pass over all rows; at most 2^22). */
 typedef struct {
   uint32_t group_min;
   uint32_t group_k;
@@ -165,6 +169,7 @@ typedef struct {
   uint32_t unroll;
   uint32_t region_reg;
   uint32_t t_compact;
+  uint32_t t_segment_kb;
 } hth_tuning;
 hth_status hth_kb_get_tuning(hth_kb kb, hth_tuning* out);
 hth_status hth_kb_set_tuning(hth_kb kb, const hth_tuning* t);   /* HTH_E_RANGE if out of range */

@@ -449,6 +449,28 @@ std::vector<GroupChunk> chunk_groups(const hth_kb_s& kb, std::vector<GroupTask>&
   return out;
 }
 
+// Target segments of a chunk: its passes cover T rows in ranges of at most
+// t_segment bytes (at the chunk's T width), when that takes 2..kMaxSegments
+// passes; otherwise one pass over all rows.  seg_rows: T rows per pass.
+constexpr uint32_t kMaxSegments = 4;
+uint32_t chunk_segments(const hth_kb_s& kb, const std::vector<GroupTask>& gs, const GroupChunk& c,
+                        uint64_t* seg_rows) {
+  uint64_t rows = 0;
+  for (uint32_t i = 0; i < c.n; ++i) rows = std::max(rows, t_rows(kb, gs[c.first + i]));
+  *seg_rows = rows;
+  const uint64_t seg = (uint64_t)kb.tune.t_segment_kb << 10;
+  if (!seg || rows * c.wb <= seg) return 1;
+  const uint64_t P = (rows * c.wb + seg - 1) / seg;
+  if (P > kMaxSegments) return 1;
+  *seg_rows = align_up((rows + P - 1) / P, 64);
+  return (uint32_t)P;
+}
+// partial counts carried between the passes of a segmented chunk
+inline size_t chunk_partial_bytes(const hth_kb_s& kb, const std::vector<GroupTask>& gs, const GroupChunk& c) {
+  uint64_t sr;
+  return chunk_segments(kb, gs, c, &sr) > 1 ? (size_t)c.n * kb.W * 256 * c.wb : 0;
+}
+
 namespace {
 
 struct Blob {
@@ -642,7 +664,7 @@ hth_status launch_roles(Launcher& L, const DevKB& d, const RoleTask* tasks,
 template <typename TW>
 hth_status launch_group_chunk(Launcher& L, const DevKB& d, const GroupTask* groups,
                               const GroupMember* members, const std::vector<GroupTask>& host,
-                              const GroupChunk& c, const uint32_t* xslots_all, void* tarea) {
+                              const GroupChunk& c, const uint32_t* xslots_all, void* tarea, void* parea) {
   const hth_kb_s& kb = L.kb;
   const size_t g0 = c.first;
   const uint32_t n = c.n;
@@ -677,30 +699,45 @@ hth_status launch_group_chunk(Launcher& L, const DevKB& d, const GroupTask* grou
     nwd += G.n_words;
   }
   const bool multi = nwd > 0 && ew < 96.0 * nwd;
-  return L.run(HTH_K_GROUP, gb, [&] {
-    const dim3 grid(nblocks), block(256);
-    const bool u16 = kb.tune.group_unroll >= 16;
-    if (multi) {   // few assertions per lane: 8 in flight
-      hipLaunchKernelGGL((k_group<TW, 8, 4>), grid, block, 0, L.st, d, groups + g0, members, T, bpg, xslots);
-    } else {
-      if (u16)
-        hipLaunchKernelGGL((k_group<TW, 16, 1>), grid, block, 0, L.st, d, groups + g0, members, T, bpg, xslots);
-      else
-        hipLaunchKernelGGL((k_group<TW, 8, 1>), grid, block, 0, L.st, d, groups + g0, members, T, bpg, xslots);
+  uint64_t seg_rows;
+  const uint32_t P = chunk_segments(kb, host, c, &seg_rows);
+  for (uint32_t sg = 0; sg < P; ++sg) {
+    SegPass<TW> sp{0, 0xFFFFFFFFu, 1, 1, nullptr, (size_t)kb.W * 256};
+    if (P > 1) {
+      sp.lo = (uint32_t)(sg * seg_rows);
+      sp.hi = (uint32_t)std::min<uint64_t>((sg + 1) * seg_rows, 0xFFFFFFFFu);
+      sp.first = sg == 0;
+      sp.last = sg == P - 1;
+      sp.part = static_cast<TW*>(parea);
     }
-  });
+    s = L.run(HTH_K_GROUP, sg ? 0.0 : gb, [&] {
+      const dim3 grid(nblocks), block(256);
+      const bool u16 = kb.tune.group_unroll >= 16;
+      if (multi) {   // few assertions per lane: 8 in flight
+        hipLaunchKernelGGL((k_group<TW, 8, 4>), grid, block, 0, L.st, d, groups + g0, members, T, bpg, xslots, sp);
+      } else {
+        if (u16)
+          hipLaunchKernelGGL((k_group<TW, 16, 1>), grid, block, 0, L.st, d, groups + g0, members, T, bpg, xslots, sp);
+        else
+          hipLaunchKernelGGL((k_group<TW, 8, 1>), grid, block, 0, L.st, d, groups + g0, members, T, bpg, xslots, sp);
+      }
+    });
+    if (s) return s;
+  }
+  return HTH_OK;
 }
 
 hth_status launch_groups(Launcher& L, const DevKB& d, const GroupTask* groups,
                          const GroupMember* members, const std::vector<GroupTask>& host,
-                         const std::vector<GroupChunk>& chunks, const uint32_t* xslots, void* tarea) {
+                         const std::vector<GroupChunk>& chunks, const uint32_t* xslots, void* tarea,
+                         void* parea) {
   for (const GroupChunk& c : chunks) {
     hth_status s;
     switch (c.wb) {
-      case 1: s = launch_group_chunk<uint8_t>(L, d, groups, members, host, c, xslots, tarea); break;
-      case 2: s = launch_group_chunk<uint16_t>(L, d, groups, members, host, c, xslots, tarea); break;
-      case 4: s = launch_group_chunk<uint32_t>(L, d, groups, members, host, c, xslots, tarea); break;
-      default: s = launch_group_chunk<uint64_t>(L, d, groups, members, host, c, xslots, tarea); break;
+      case 1: s = launch_group_chunk<uint8_t>(L, d, groups, members, host, c, xslots, tarea, parea); break;
+      case 2: s = launch_group_chunk<uint16_t>(L, d, groups, members, host, c, xslots, tarea, parea); break;
+      case 4: s = launch_group_chunk<uint32_t>(L, d, groups, members, host, c, xslots, tarea, parea); break;
+      default: s = launch_group_chunk<uint64_t>(L, d, groups, members, host, c, xslots, tarea, parea); break;
     }
     if (s) return s;
   }
@@ -718,6 +755,27 @@ size_t heavy_counter_bytes(const hth_kb_s& kb, const Plan& P) {
     most = std::max(most, nb);
   }
   return align_up(most * 4, 256);
+}
+
+// The shared passes of a level as launched: word counts and T layout set.
+std::vector<GroupTask> level_groups(const hth_kb_s& kb, const PlanLevel& PL) {
+  std::vector<GroupTask> out;
+  for (GroupTask g : PL.groups) {
+    g.n_words = kb.n_words[2 * g.role + g.inv];
+    g.compact = kb.tune.t_compact && 2ull * kb.n_obj[2 * g.role + g.inv] <= kb.N;
+    out.push_back(g);
+  }
+  return out;
+}
+
+// partial counts of the segmented chunks of a plan (the largest chunk's worth)
+size_t partial_bytes(const hth_kb_s& kb, const Plan& P) {
+  size_t most = 0;
+  for (const PlanLevel& PL : P.levels) {
+    std::vector<GroupTask> gs = level_groups(kb, PL);
+    for (const GroupChunk& c : chunk_groups(kb, gs)) most = std::max(most, chunk_partial_bytes(kb, gs, c));
+  }
+  return align_up(most, 256);
 }
 
 // bytes of the packed tables plus slots plus T area for a plan
@@ -743,7 +801,7 @@ size_t plan_workspace_bytes(const hth_kb_s& kb, const Plan& P) {
   add(P.code.size(), sizeof(uint32_t));
   add(9 * n_grp + 8, sizeof(uint32_t));     // XCD slot tables: at most 8 more than groups per chunk
   return align_up(tables, 256) + (size_t)P.n_slots * kb.S * 8 + (max_groups ? t_area_bytes(kb) : 0) +
-         heavy_counter_bytes(kb, P);
+         heavy_counter_bytes(kb, P) + partial_bytes(kb, P);
 }
 
 std::once_flag g_attr_once;
@@ -763,6 +821,7 @@ struct Prepared {
   size_t n_thr_groups = 0, n_thr_tasks = 0;
   size_t o_thr = 0, o_thg = 0, o_reg = 0, o_role = 0, o_grp = 0, o_mem = 0, o_fill = 0, o_code = 0, o_xslot = 0;
   size_t o_hcnt = 0;   // heavy-row counters (workspace offset)
+  size_t o_part = 0;   // partial counts of segmented shared passes (workspace offset)
   size_t tables = 0, need = 0;
   uint32_t n_hyps = 0;
 };
@@ -800,13 +859,11 @@ void prepare(const hth_kb_s& kb, Plan&& plan, uint32_t n_hyps, Prepared& X) {
       X.lv_roles[L].push_back(t);
     }
     const uint32_t mbase = (uint32_t)members.size();
-    for (GroupTask g : PL.groups) {
-      g.n_words = kb.n_words[2 * g.role + g.inv];
+    for (GroupTask g : level_groups(kb, PL)) {
       if (g.n_words < kb.W)
         for (uint32_t j = 0; j < g.k; ++j)
           fills.push_back(FillTask{PL.members[g.first + j].out_row, (uint32_t)((g.acc[0] >> j) & 1)});
       g.first += mbase;
-      g.compact = kb.tune.t_compact && 2ull * kb.n_obj[2 * g.role + g.inv] <= kb.N;
       X.lv_groups[L].push_back(g);
     }
     X.lv_chunks[L] = chunk_groups(kb, X.lv_groups[L]);
@@ -845,7 +902,11 @@ void prepare(const hth_kb_s& kb, Plan&& plan, uint32_t n_hyps, Prepared& X) {
   size_t max_groups = 0;
   for (const PlanLevel& PL : P.levels) max_groups = std::max(max_groups, PL.groups.size());
   X.o_hcnt = X.tables + (size_t)P.n_slots * kb.S * 8 + (max_groups ? t_area_bytes(kb) : 0);
-  X.need = X.o_hcnt + heavy_counter_bytes(kb, P);
+  X.o_part = X.o_hcnt + heavy_counter_bytes(kb, P);
+  size_t part = 0;
+  for (size_t L = 0; L < NL; ++L)
+    for (const GroupChunk& c : X.lv_chunks[L]) part = std::max(part, chunk_partial_bytes(kb, X.lv_groups[L], c));
+  X.need = X.o_part + align_up(part, 256);
 }
 
 hth_status check_ws(const Prepared& X, const char* ws, size_t ws_bytes) {
@@ -927,7 +988,7 @@ hth_status launch_prepared(hth_kb_s& kb, const Prepared& X, char* ws, uint32_t* 
       if (s) return s;
     }
     s = launch_groups(Lc, d, grp + at.group, mem, X.lv_groups[L], X.lv_chunks[L],
-                      reinterpret_cast<const uint32_t*>(ws + X.o_xslot), tarea);
+                      reinterpret_cast<const uint32_t*>(ws + X.o_xslot), tarea, ws + X.o_part);
     if (s) return s;
   }
   return launch_regions(Lc, d, reg + X.root_at, code, P.roots, P.code);

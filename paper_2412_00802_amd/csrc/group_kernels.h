@@ -130,6 +130,21 @@ __device__ __forceinline__ TW accept(const Planes<TW>& p, const TW (&acc)[kGroup
   return (res & ~p.ov) | (p.ov & acc[8]);
 }
 
+// A shared pass cut by T row ("target segments"), so that the T rows one pass
+// fetches fit an XCD's L2: pass s counts only the assertions whose T row is in
+// [lo, hi).  Every pass walks the same rows; the counts of a row finished in
+// an earlier pass come in through `part` (bit-sliced planes per subject, for
+// the group at index g of the launch at part + g * stride: W words x 4 planes
+// x 64 subjects) and go out to it for the next pass; the last pass writes the
+// members' output words.  One pass: lo = 0, hi = ~0, first = last = 1.
+template <typename TW>
+struct SegPass {
+  uint32_t lo, hi;
+  uint32_t first, last;
+  TW* part;
+  size_t stride;   // TW elements per group
+};
+
 // One wave per MW consecutive entries of the direction's non-empty word list
 // (64 MW subjects: one word of every member's output row per entry), all
 // members of the group at once.  Words between two list entries hold no
@@ -139,18 +154,19 @@ __device__ __forceinline__ TW accept(const Planes<TW>& p, const TW (&acc)[kGroup
 // serves every member) and adds it into bit-sliced counters; a row complete in
 // the slice has its acceptance written to LDS at once.  Rows that straddle
 // slices leave a tail partial in each lane they cross; one segmented scan over
-// the lanes adds them up for the lane holding the row's last assertion.
-// Finally each word's acceptances are transposed by a wave butterfly into one
-// word per member.  MW > 1 serves directions with few assertions per word.
+// the lanes adds them up for the lane holding the row's last assertion.  A
+// finished row's counters go to LDS (a few stores, so that lanes crossing a
+// row boundary at different steps stay cheap); afterwards every lane turns
+// its own subject's counters into the members' predicates at once, and each
+// word's predicates are transposed by a wave butterfly into one word per
+// member.  MW > 1 serves directions with few assertions per word.
 template <typename TW, int U, int MW>   // U: assertions in flight per lane
 __global__ void __launch_bounds__(256)
 k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __restrict__ members,
-        const TW* __restrict__ tarea, uint32_t bpg, const uint32_t* __restrict__ xslots) {
-  constexpr uint32_t kStage = 1024;   // assertions of an iteration staged in LDS
+        const TW* __restrict__ tarea, uint32_t bpg, const uint32_t* __restrict__ xslots, SegPass<TW> sp) {
   constexpr int R = 64 * MW;          // subjects per iteration
   __shared__ uint32_t s_ro[4][R + 1];
-  __shared__ TW s_res[4][R];
-  __shared__ int32_t s_tg[4][kStage];
+  __shared__ TW s_pl[4][4][R];        // counters of the rows finished in this iteration
   uint32_t g, b;
   if (xslots) {
     // workgroups are dealt to the 8 XCDs round robin: keep every block of a
@@ -166,6 +182,7 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
   }
   const GroupTask* G = groups + g;
   const uint32_t k = G->k;
+  TW* part = sp.first && sp.last ? nullptr : sp.part + (size_t)g * sp.stride;
   const TW* T = tarea + G->t_off;
   const size_t roff = (size_t)G->role * (kb.N + 1);
   const uint32_t* off = (G->inv ? kb.inv_off : kb.fwd_off) + roff;
@@ -174,74 +191,106 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
                       kb.role_base[G->role];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   uint32_t* ro = s_ro[wv];
-  TW* res = s_res[wv];
+  TW (*pl)[R] = s_pl[wv];
   TW acc[kGroupMaxCount + 1];
 #pragma unroll
   for (int v = 0; v <= (int)kGroupMaxCount; ++v) acc[v] = (TW)G->acc[v];
-  const TW res0 = accept(Planes<TW>{0, 0, 0, 0}, acc);
+  const uint32_t seg_n = sp.hi - sp.lo;
+  uint64_t* const my_out = (uint32_t)lane < k ? out_ptr(kb, members[G->first + lane].out_row) : nullptr;
   const uint32_t nw = blockDim.x >> 6;
   const uint32_t istep = bpg * nw;
   const uint32_t* words = kb.words + (size_t)(2 * G->role + G->inv) * kb.W;
   const uint32_t n_words = G->n_words;
   const uint32_t n_iter = (n_words + MW - 1) / MW;
-  // row offsets of the wave's next iteration, fetched ahead
-  uint32_t lo_n[MW], hi_n[MW], w_n[MW];
-  auto fetch = [&](uint32_t it) {
+
+  // Software pipeline over the wave's iterations: while iteration i is walked,
+  // the row offsets of i + 2 and the slice targets of i + 1 are in flight, and
+  // the T rows of i + 1 are fetched before i's counters are turned into
+  // predicates.  A slice longer than U fetches its further blocks in place.
+  struct Rows {
+    uint32_t lo[MW], hi[MW], wd[MW];
+  };
+  auto fetch = [&](uint32_t it, Rows& q) {
 #pragma unroll
     for (int m = 0; m < MW; ++m) {
       const uint32_t idx = it * MW + m;
-      w_n[m] = kNone;
-      lo_n[m] = hi_n[m] = 0;
+      q.wd[m] = kNone;
+      q.lo[m] = q.hi[m] = 0;
       if (it < n_iter && idx < n_words) {
         const uint32_t w = words[idx], x = w * 64 + lane;
-        w_n[m] = w;
-        lo_n[m] = off[x < kb.N ? x : kb.N];
-        hi_n[m] = x < kb.N ? off[x + 1] : lo_n[m];
+        q.wd[m] = w;
+        q.lo[m] = off[x < kb.N ? x : kb.N];
+        q.hi[m] = x < kb.N ? off[x + 1] : q.lo[m];
       }
     }
   };
-  uint32_t it = b * nw + wv;
-  fetch(it);
-  for (; it < n_iter; it += istep) {
-    uint32_t lo[MW], hi[MW], wd[MW];
+  auto words_in = [&](uint32_t it) { return it < n_iter ? min((uint32_t)MW, n_words - it * MW) : 0u; };
+  // the lane's slice [s, se) of the iteration's contiguous assertion range
+  auto slice = [&](const Rows& q, uint32_t it, uint32_t& s, uint32_t& se) {
+    const uint32_t mc = words_in(it);
+    uint32_t hl = q.hi[0];
 #pragma unroll
-    for (int m = 0; m < MW; ++m) {
-      lo[m] = lo_n[m];
-      hi[m] = hi_n[m];
-      wd[m] = w_n[m];
-    }
-    fetch(it + istep);
-    const uint32_t mc = min((uint32_t)MW, n_words - it * MW);   // words in this iteration
+    for (int m = 1; m < MW; ++m)
+      if ((uint32_t)m < mc) hl = q.hi[m];
+    const uint32_t E0 = (uint32_t)__shfl((int)q.lo[0], 0, 64), E1 = (uint32_t)__shfl((int)hl, 63, 64);
+    const uint32_t S = (E1 - E0 + 63) >> 6;
+    s = mc ? E0 + lane * S : 0;
+    se = mc ? min(s + S, E1) : 0;
+    if (se < s) se = s;
+  };
+  auto load_t = [&](uint32_t e0, uint32_t se, int32_t (&t)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) t[u] = (e0 + u < se) ? tg[e0 + u] : 0;
+  };
+  auto gather = [&](uint32_t e0, uint32_t se, const int32_t (&t)[U], TW (&v)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      v[u] = (e0 + u < se && (uint32_t)t[u] - sp.lo < seg_n) ? T[(uint32_t)t[u]] : (TW)0;
+  };
+
+  uint32_t it = b * nw + wv;
+  Rows rw, rn;
+  fetch(it, rw);
+  fetch(it + istep, rn);
+  uint32_t s, se;
+  slice(rw, it, s, se);
+  int32_t t[U];
+  TW v[U];
+  load_t(s, se, t);
+  gather(s, se, t, v);
+  for (; it < n_iter; it += istep) {
+    const uint32_t mc = words_in(it);
     const uint32_t nr = 64 * mc;
 #pragma unroll
     for (int m = 0; m < MW; ++m)
       if ((uint32_t)m < mc) {
-        ro[64 * m + lane] = lo[m];
-        res[64 * m + lane] = res0;
+        ro[64 * m + lane] = rw.lo[m];
+        pl[0][64 * m + lane] = pl[1][64 * m + lane] = pl[2][64 * m + lane] = pl[3][64 * m + lane] = (TW)0;
       }
-    uint32_t hi_last = hi[0];
+    {
+      uint32_t hl = rw.hi[0];
 #pragma unroll
-    for (int m = 1; m < MW; ++m)
-      if ((uint32_t)m < mc) hi_last = hi[m];
-    if (lane == 63) ro[nr] = hi_last;
+      for (int m = 1; m < MW; ++m)
+        if ((uint32_t)m < mc) hl = rw.hi[m];
+      if (lane == 63) ro[nr] = hl;
+    }
+    // the pipeline's next stages: offsets of it + 2 istep, targets of it + istep
+    Rows rnn;
+    fetch(it + 2 * istep, rnn);
+    uint32_t ns, nse;
+    slice(rn, it + istep, ns, nse);
+    int32_t nt[U];
+    load_t(ns, nse, nt);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const uint32_t E0 = ro[0], E1 = ro[nr];
-    const uint32_t S = (E1 - E0 + 63) >> 6;
-    const uint32_t s = E0 + lane * S;
-    const uint32_t se = min(s + S, E1);
-    // the iteration's targets, loaded coalesced into LDS when they fit; lanes
-    // then read their contiguous slices from there
-    int32_t* stg = s_tg[wv];
-    const bool staged = E1 - E0 <= kStage;
-    if (staged) {
-#pragma unroll 4
-      for (uint32_t i = lane; i < E1 - E0; i += 64) stg[i] = tg[E0 + i];
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
+    // a row's count is complete in this slice walk
+    auto finish = [&](int r, const Planes<TW>& p) {
+      pl[0][r] = p.c0;
+      pl[1][r] = p.c1;
+      pl[2][r] = p.c2;
+      pl[3][r] = p.ov;
+    };
     Planes<TW> cur{0, 0, 0, 0}, hp{0, 0, 0, 0}, tp{0, 0, 0, 0};
     int hp_row = -1, key = -2 - lane;
     if (s < se) {
@@ -253,12 +302,10 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
       bool head = ro[r] < s;
       uint32_t rend = ro[r + 1];
       for (uint32_t e0 = s; e0 < se; e0 += U) {
-        int32_t t[U];
-        TW v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) t[u] = (e0 + u < se) ? (staged ? stg[e0 + u - E0] : tg[e0 + u]) : 0;
-#pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = (e0 + u < se) ? T[(uint32_t)t[u]] : (TW)0;
+        if (e0 != s) {                   // beyond the prefetched block
+          load_t(e0, se, t);
+          gather(e0, se, t, v);
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const uint32_t e = e0 + u;
@@ -268,7 +315,7 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
                 hp = cur;
                 hp_row = r;
               } else {
-                res[r] = accept(cur, acc);
+                finish(r, cur);
               }
               cur = Planes<TW>{0, 0, 0, 0};
               head = false;
@@ -286,7 +333,7 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
         hp = cur;
         hp_row = r;
       } else {
-        res[r] = accept(cur, acc);
+        finish(r, cur);
       }
     }
     // segmented inclusive scan of the tail partials, keyed by row; stops once no
@@ -302,23 +349,47 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
       const Planes<TW> pp = planes_shfl_up(tp, 1);
       if (hp_row >= 0) {
         if (lane > 0 && pk == hp_row) planes_add(hp, pp);
-        res[hp_row] = accept(hp, acc);
+        finish(hp_row, hp);
       }
     }
+    // the next iteration's T rows, in flight while this one's words are written
+    gather(ns, nse, nt, v);
+#pragma unroll
+    for (int u = 0; u < U; ++u) t[u] = nt[u];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // each word: every member's predicate for subject 64 w + lane, transposed
+    // each word: lane l's subject 64 w + l.  Its counts go on to the next
+    // pass of a cut shared pass, or become every member's predicate,
+    // transposed into one output word per member.
 #pragma unroll
     for (int m = 0; m < MW; ++m) {
       if ((uint32_t)m < mc) {
-        TW rv = res[64 * m + lane];
-        if (wd[m] * 64 + lane >= kb.N) rv = 0;
-        const uint64_t mine = wave_transpose64((uint64_t)rv, lane);
-        if ((uint32_t)lane < k) out_ptr(kb, members[G->first + lane].out_row)[wd[m]] = mine;
+        const int r = 64 * m + lane;
+        Planes<TW> p{pl[0][r], pl[1][r], pl[2][r], pl[3][r]};
+        if (part) {
+          TW* q = part + (size_t)rw.wd[m] * 256 + lane;
+          if (!sp.first) planes_add(p, Planes<TW>{q[0], q[64], q[128], q[192]});
+          if (!sp.last) {
+            q[0] = p.c0;
+            q[64] = p.c1;
+            q[128] = p.c2;
+            q[192] = p.ov;
+          }
+        }
+        if (sp.last) {
+          TW rv = accept(p, acc);
+          if (rw.wd[m] * 64 + lane >= kb.N) rv = 0;
+          const uint64_t mine = wave_transpose64((uint64_t)rv, lane);
+          if (my_out) my_out[rw.wd[m]] = mine;
+        }
       }
     }
     __builtin_amdgcn_wave_barrier();
+    rw = rn;
+    rn = rnn;
+    s = ns;
+    se = nse;
   }
 }
 

@@ -66,6 +66,7 @@ struct hth_kb_s {
     uint32_t group_unroll = 16;  // assertions in flight per lane in a dense shared pass
     uint32_t region_reg = 2;     // words per lane of the register-stack region kernel (0: LDS kernel)
     uint32_t t_compact = 1;      // 1: T rows of objects only where they are <= N/2
+    uint32_t t_segment_kb = 0;   // T bytes per pass of a shared pass (0: one pass over all rows)
   } tune;
 };
 

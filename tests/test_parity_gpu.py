@@ -257,6 +257,29 @@ def test_group_widths(m):
     check(kb, hs, label=f"group m={m}")
 
 
+@pytest.mark.parametrize("seg_kb", [0, 16, 40, 64, 128, 100000])
+def test_segmented_shared_passes(seg_kb):
+    """Shared passes cut into 2..4 passes over T-row ranges (partial counts
+    carried between them) give the oracle's counts for every T width, full and
+    compact T rows, dense and sparse directions, and nested role nodes; sizes
+    whose cut would need more than four passes run as one pass."""
+    cfg = synth.small_config(n=30011, n_concepts=40, n_roles=4, s=1.4, cap=600, n_pos=3000, n_neg=2500,
+                             n_hyps=200, hyp_depth=5, seed_index=1700)
+    kb = synth.make_kb(cfg)
+    hs = synth.make_hypotheses(cfg, kb)
+    for m, role, inv in ((70, 0, 0), (40, 1, 1), (20, 2, 0), (9, 3, 1)):
+        hs += _distinct_role_nodes(m, 40, role, inv, seed=m + seg_kb)
+    hs += [("exists", 0, 0, ("atleast", 2, 1, 1, ("atom", i))) for i in range(12)]
+    want = Oracle(kb).coverages(hs)
+    eng = hthedl.Engine(kb)
+    hthedl.hth_kb_set_tuning(eng.handle, t_segment_kb=seg_kb)
+    for compact in (1, 0):
+        hthedl.hth_kb_set_tuning(eng.handle, t_compact=compact)
+        got = eng.eval_batch(hs)
+        bad = np.flatnonzero((got != want).any(axis=1))
+        assert bad.size == 0, f"t_segment_kb={seg_kb} compact={compact}: {hs[bad[0]]} {got[bad[0]]} {want[bad[0]]}"
+
+
 @pytest.mark.parametrize("n,edges", [(5000, 300), (70000, 4000), (130001, 60000)])
 def test_sparse_roles(n, edges):
     """Most 64-subject words have no assertion: the passes visit the non-empty
