@@ -160,7 +160,13 @@ hth_status hth_kb_max_degree(hth_kb kb, uint32_t role, uint32_t inv, uint32_t* o
  * t_segment_kb: KiB of transposed child rows fetched per pass: a shared pass
  *   whose rows are larger runs as 2..4 passes over consecutive row ranges,
  *   carrying each subject's partial counts between them, so that each pass's
- *   rows fit one XCD's L2 (0 = one pass over all rows; at most 2^22). */
+ *   rows fit one XCD's L2 (0 = one pass over all rows; at most 2^22);
+ * push_pct: an existential restriction over an atomic concept evaluated on
+ *   its own (not in a shared pass) whose concept holds under this percentage
+ *   of the individuals is evaluated from the concept's members: each marks
+ *   the subjects that reach it, where no row of the other direction holds
+ *   more than 64 assertions (0 = always count per subject; at most 100;
+ *   default 2). */
 typedef struct {
   uint32_t group_min;
   uint32_t group_k;
@@ -170,6 +176,7 @@ typedef struct {
   uint32_t region_reg;
   uint32_t t_compact;
   uint32_t t_segment_kb;
+  uint32_t push_pct;
 } hth_tuning;
 hth_status hth_kb_get_tuning(hth_kb kb, hth_tuning* out);
 hth_status hth_kb_set_tuning(hth_kb kb, const hth_tuning* t);   /* HTH_E_RANGE if out of range */

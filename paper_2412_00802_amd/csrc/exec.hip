@@ -353,6 +353,37 @@ k_role_heavy_fix(DevKB kb, const RoleTask* __restrict__ tasks, uint32_t n_tasks,
   }
 }
 
+// A single ∃ρ.A (lo = 1, hi unbounded) or ¬∃ρ.A (lo = hi = 0) whose atomic
+// child A is sparse, pushed from A's members: every y in A takes the subjects
+// x that reach it (its row in the opposite direction) and sets (∃) or clears
+// (¬∃) their bits in the output row, which a fill task has set to all zeros
+// or all ones before.  One wave per word of A, a lane per member walking its
+// row alone, so it is only chosen where every row of the opposite direction
+// is short (kPushMaxDeg).
+__global__ void __launch_bounds__(256)
+k_push(DevKB kb, const RoleTask* __restrict__ tasks, uint32_t tiles) {
+  const uint32_t t = blockIdx.x / tiles, tile = blockIdx.x % tiles;
+  const uint32_t w = tile * 4 + (threadIdx.x >> 6);
+  if (w >= kb.W) return;
+  const RoleTask T = tasks[t];
+  const int lane = threadIdx.x & 63;
+  const uint64_t cw = row_ptr(kb, T.child_row)[w];
+  if (!((cw >> lane) & 1ull)) return;
+  const uint32_t y = w * 64 + lane;
+  const uint32_t* off = (T.inv ? kb.fwd_off : kb.inv_off) + (size_t)T.role * (kb.N + 1);
+  const int32_t* tg = (T.inv ? kb.fwd_tg : kb.inv_tg) + kb.role_base[T.role];
+  unsigned long long* out = reinterpret_cast<unsigned long long*>(out_ptr(kb, T.out_row));
+  const uint32_t e1 = off[y + 1];
+  const bool mark = T.lo == 1;
+#pragma unroll 4
+  for (uint32_t e = off[y]; e < e1; ++e) {
+    const uint32_t x = (uint32_t)tg[e];
+    const unsigned long long bit = 1ull << (x & 63);
+    if (mark) atomicOr(out + (x >> 6), bit);
+    else atomicAnd(out + (x >> 6), ~bit);
+  }
+}
+
 // Zero-count results for the words of a role direction without assertions.
 __global__ void __launch_bounds__(256)
 k_fill_rows(DevKB kb, const FillTask* __restrict__ tasks, uint32_t tiles) {
@@ -491,6 +522,7 @@ size_t table_bound(uint32_t max_nodes, uint32_t max_hyps) {
   b += align_up(n * sizeof(ThrGroup), 256);
   b += align_up((n + max_hyps) * sizeof(RegionTask), 256);
   b += align_up(n * sizeof(RoleTask), 256);
+  b += align_up(n * sizeof(RoleTask), 256);                // pushed role tasks
   b += align_up(n * sizeof(GroupTask), 256);
   b += align_up(n * sizeof(GroupMember), 256);
   b += align_up(n * sizeof(FillTask), 256);
@@ -757,6 +789,19 @@ size_t heavy_counter_bytes(const hth_kb_s& kb, const Plan& P) {
   return align_up(most * 4, 256);
 }
 
+// A single role node evaluated by k_push: ∃ρ.A or ¬∃ρ.A over an atomic A with
+// fewer than push_pct percent of the individuals, where no row of the
+// opposite direction is longer than kPushMaxDeg (a member's row is walked by
+// one lane).  Otherwise it is counted per subject (k_role).
+constexpr uint32_t kPushMaxDeg = 64;
+inline bool pushed(const hth_kb_s& kb, const RoleTask& t) {
+  if (!kb.tune.push_pct || t.neg || t.child_row >= kb.d.n_concepts) return false;
+  const bool exists = t.lo == 1 && t.hi == 0xFFFFFFFFu, none = t.lo == 0 && t.hi == 0;
+  if (!exists && !none) return false;
+  if (kb.max_deg[t.inv ? 0 : 1][t.role] > kPushMaxDeg) return false;
+  return (uint64_t)kb.concept_pop[t.child_row] * 100 < (uint64_t)kb.tune.push_pct * kb.N;
+}
+
 // The shared passes of a level as launched: word counts and T layout set.
 std::vector<GroupTask> level_groups(const hth_kb_s& kb, const PlanLevel& PL) {
   std::vector<GroupTask> out;
@@ -795,6 +840,7 @@ size_t plan_workspace_bytes(const hth_kb_s& kb, const Plan& P) {
   add(P.thr.size(), sizeof(ThrGroup));
   add(n_reg, sizeof(RegionTask));
   add(n_role, sizeof(RoleTask));
+  add(n_role, sizeof(RoleTask));            // pushed role tasks (a subset of the role nodes)
   add(n_grp, sizeof(GroupTask));
   add(n_mem, sizeof(GroupMember));
   add(n_fill, sizeof(FillTask));
@@ -812,14 +858,16 @@ std::once_flag g_attr_once;
 struct Prepared {
   Plan P;
   Blob blob;
-  struct LevelAt { size_t mat, role, group, fill, nrole, ngroup, nfill, nhb, nhc; };
+  struct LevelAt { size_t mat, role, group, fill, nrole, ngroup, nfill, nhb, nhc, push, npush; };
   std::vector<LevelAt> at;
   size_t root_at = 0;
   std::vector<std::vector<RoleTask>> lv_roles;
+  std::vector<std::vector<RoleTask>> lv_push;
   std::vector<std::vector<GroupTask>> lv_groups;
   std::vector<std::vector<GroupChunk>> lv_chunks;
   size_t n_thr_groups = 0, n_thr_tasks = 0;
   size_t o_thr = 0, o_thg = 0, o_reg = 0, o_role = 0, o_grp = 0, o_mem = 0, o_fill = 0, o_code = 0, o_xslot = 0;
+  size_t o_push = 0;
   size_t o_hcnt = 0;   // heavy-row counters (workspace offset)
   size_t o_part = 0;   // partial counts of segmented shared passes (workspace offset)
   size_t tables = 0, need = 0;
@@ -835,19 +883,27 @@ void prepare(const hth_kb_s& kb, Plan&& plan, uint32_t n_hyps, Prepared& X) {
   std::vector<GroupTask> groups;
   std::vector<GroupMember> members;
   std::vector<FillTask> fills;
+  std::vector<RoleTask> pushes;
   std::vector<uint32_t> xslots;
   const size_t NL = P.levels.size();
   X.at.assign(NL, {});
   X.lv_roles.assign(NL, {});
+  X.lv_push.assign(NL, {});
   X.lv_groups.assign(NL, {});
   X.lv_chunks.assign(NL, {});
   for (size_t L = 0; L < NL; ++L) {
     const PlanLevel& PL = P.levels[L];
-    X.at[L] = {regions.size(), roles.size(), groups.size(), fills.size(), 0, 0, 0, 0, 0};
+    X.at[L] = {regions.size(), roles.size(), groups.size(), fills.size(), 0, 0, 0, 0, 0, pushes.size(), 0};
     regions.insert(regions.end(), PL.mat.begin(), PL.mat.end());
     for (RoleTask t : PL.roles) {
       const uint32_t rd = 2 * t.role + t.inv;
       t.n_words = kb.n_words[rd];
+      if (pushed(kb, t)) {
+        fills.push_back(FillTask{t.out_row, t.lo == 0 ? 1u : 0u});
+        pushes.push_back(t);
+        X.lv_push[L].push_back(t);
+        continue;
+      }
       t.hr0 = kb.heavy_first[rd];
       t.hc0 = kb.chunk_first[rd];
       t.h_first = (uint32_t)X.at[L].nhb;
@@ -874,6 +930,7 @@ void prepare(const hth_kb_s& kb, Plan&& plan, uint32_t n_hyps, Prepared& X) {
     X.at[L].nrole = roles.size() - X.at[L].role;
     X.at[L].ngroup = groups.size() - X.at[L].group;
     X.at[L].nfill = fills.size() - X.at[L].fill;
+    X.at[L].npush = pushes.size() - X.at[L].push;
   }
   X.root_at = regions.size();
   regions.insert(regions.end(), P.roots.begin(), P.roots.end());
@@ -898,6 +955,7 @@ void prepare(const hth_kb_s& kb, Plan&& plan, uint32_t n_hyps, Prepared& X) {
   X.o_fill = X.blob.add(fills);
   X.o_code = X.blob.add(P.code);
   X.o_xslot = X.blob.add(xslots);
+  X.o_push = X.blob.add(pushes);
   X.tables = align_up(X.blob.bytes.size(), 256);
   size_t max_groups = 0;
   for (const PlanLevel& PL : P.levels) max_groups = std::max(max_groups, PL.groups.size());
@@ -970,6 +1028,19 @@ hth_status launch_prepared(hth_kb_s& kb, const Prepared& X, char* ws, uint32_t* 
       const uint32_t n = (uint32_t)at.nfill, tiles = (kb.S + 255) / 256;
       s = split_launch(Lc, HTH_K_FILL, (double)n * kb.W * 8, n, tiles, 256, [&](uint32_t i0, uint32_t, uint32_t blocks) {
         hipLaunchKernelGGL(k_fill_rows, dim3(blocks), dim3(256), 0, st, d, fil + at.fill + i0, tiles);
+      });
+      if (s) return s;
+    }
+    if (at.npush) {   // after the fills that set their rows to all zeros / all ones
+      const uint32_t n = (uint32_t)at.npush, tiles = (kb.W + 3) / 4;
+      const RoleTask* pt = reinterpret_cast<const RoleTask*>(ws + X.o_push) + at.push;
+      double bytes = 0;
+      for (const RoleTask& t : X.lv_push[L])
+        bytes += (double)kb.W * 8 * 2 + 8.0 * kb.concept_pop[t.child_row] +
+                 4.0 * kb.concept_pop[t.child_row] *
+                     ((double)(kb.role_base[t.role + 1] - kb.role_base[t.role]) / kb.N);
+      s = split_launch(Lc, HTH_K_ROLE, bytes, n, tiles, 256, [&](uint32_t i0, uint32_t, uint32_t blocks) {
+        hipLaunchKernelGGL(k_push, dim3(blocks), dim3(256), 0, st, d, pt + i0, tiles);
       });
       if (s) return s;
     }

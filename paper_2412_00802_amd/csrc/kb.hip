@@ -87,6 +87,20 @@ __global__ void k_validate_rows(const int64_t* __restrict__ off, const int32_t* 
   if (bad) atomicOr(flags, bad);
 }
 
+// Members of each row (one block per row): the plan's push/pull choice.
+__global__ void __launch_bounds__(256)
+k_row_pop(const uint64_t* __restrict__ rows, uint32_t W, uint32_t S, uint32_t* __restrict__ out) {
+  __shared__ uint32_t part[4];
+  const uint64_t* p = rows + (size_t)blockIdx.x * S;
+  uint32_t c = 0;
+  for (uint32_t w = threadIdx.x; w < W; w += 256) c += (uint32_t)__popcll(p[w]);
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+}
+
 // Bits past N in word W-1 and words W..S-1 of every bit row must be zero.
 __global__ void k_check_padding(const uint64_t* __restrict__ rows, uint32_t n_rows, uint32_t W,
                                 uint32_t S, uint64_t tail, uint32_t* __restrict__ flags) {
@@ -328,7 +342,7 @@ k_object_rank(const int32_t* __restrict__ tg, uint64_t e0, uint64_t n, const uin
 
 struct DerivedLayout {
   size_t fwd_off, inv_off, inv_tg, cursor, bsum, base, meta, words, wbase, objmask, objbase, ctg;
-  size_t heavy, hchunk, hchunk0, total;
+  size_t heavy, hchunk, hchunk0, cpop, total;
   uint32_t nb;
   size_t heavy_cap, chunk_cap;   // entries
 };
@@ -419,6 +433,7 @@ static DerivedLayout layout_for(const hth_kb_desc& d) {
   L.heavy = at; at += align_up(L.heavy_cap * 12, 256);
   L.hchunk = at; at += align_up(L.chunk_cap * sizeof(HeavyChunk), 256);
   L.hchunk0 = at; at += align_up((L.heavy_cap + 1) * 4, 256);
+  L.cpop = at; at += align_up((size_t)d.n_concepts * 4 + 4, 256);
   L.total = at;
   return L;
 }
@@ -571,6 +586,13 @@ static hth_status kb_build(hth_kb_s* kb, char* derived, hipStream_t st) {
                      kb->tail, flags);
   hipLaunchKernelGGL(k_check_padding, dim3(1), dim3(1), 0, st, d.neg_bits, 1u, kb->W, kb->S,
                      kb->tail, flags);
+  kb->concept_pop.assign(d.n_concepts, 0);
+  if (d.n_concepts) {
+    uint32_t* cpop = reinterpret_cast<uint32_t*>(derived + L.cpop);
+    hipLaunchKernelGGL(k_row_pop, dim3(d.n_concepts), dim3(256), 0, st, d.concept_bits, kb->W, kb->S, cpop);
+    HTH_HIP(hipGetLastError());
+    HTH_HIP(hipMemcpyAsync(kb->concept_pop.data(), cpop, (size_t)d.n_concepts * 4, hipMemcpyDeviceToHost, st));
+  }
   kb->role_base.assign(R + 1, 0);
   kb->max_deg[0].assign(R, 0);
   kb->max_deg[1].assign(R, 0);
@@ -743,6 +765,7 @@ extern "C" hth_status hth_kb_create(const hth_kb_desc* desc, void* derived, size
   kb->tune.region_reg = (uint32_t)env_u("HTHEDL_REGION_REG", kb->tune.region_reg);
   kb->tune.t_compact = (uint32_t)env_u("HTHEDL_T_COMPACT", kb->tune.t_compact);
   kb->tune.t_segment_kb = (uint32_t)std::min<uint64_t>(1u << 22, env_u("HTHEDL_TSEG_KB", kb->tune.t_segment_kb));
+  kb->tune.push_pct = (uint32_t)std::min<uint64_t>(100, env_u("HTHEDL_PUSH_PCT", kb->tune.push_pct));
   kb->heavy_min = (uint32_t)std::min<uint64_t>(
       1u << 30, std::max<uint64_t>(kHeavyMinFloor, env_u("HTHEDL_HEAVY_MIN", kb->heavy_min)));
   kb->lds_per_block = prop.sharedMemPerBlock;
@@ -792,6 +815,7 @@ extern "C" hth_status hth_kb_get_tuning(hth_kb kb, hth_tuning* out) {
   out->region_reg = kb->tune.region_reg;
   out->t_compact = kb->tune.t_compact;
   out->t_segment_kb = kb->tune.t_segment_kb;
+  out->push_pct = kb->tune.push_pct;
   return HTH_OK;
 }
 
@@ -800,7 +824,7 @@ extern "C" hth_status hth_kb_set_tuning(hth_kb kb, const hth_tuning* t) {
   if (t->group_k < 1 || t->group_k > 64 || t->xcd_local > 1 || t->t_budget_mb < 1 ||
       t->t_budget_mb > (1u << 20) || (t->unroll != 8 && t->unroll != 16) ||
       (t->region_reg != 0 && t->region_reg != 1 && t->region_reg != 2 && t->region_reg != 4) ||
-      t->t_compact > 1 || t->t_segment_kb > (1u << 22))
+      t->t_compact > 1 || t->t_segment_kb > (1u << 22) || t->push_pct > 100)
     return fail(HTH_E_RANGE, "tuning value out of range");
   std::lock_guard<std::mutex> g(kb->mu);
   kb->tune.group_min = t->group_min;
@@ -811,6 +835,7 @@ extern "C" hth_status hth_kb_set_tuning(hth_kb kb, const hth_tuning* t) {
   kb->tune.region_reg = t->region_reg;
   kb->tune.t_compact = t->t_compact;
   kb->tune.t_segment_kb = t->t_segment_kb;
+  kb->tune.push_pct = t->push_pct;
   return HTH_OK;
 }
 

@@ -36,6 +36,7 @@ struct hth_kb_s {
   std::vector<uint32_t> chunk_first;   // [2R+1] first chunk of direction 2r + dir
   uint32_t heavy_most = 0;             // most heavy rows in one direction
   uint32_t chunk_most = 0;             // most heavy chunks in one direction
+  std::vector<uint32_t> concept_pop;   // [C] members of each concept
   const uint64_t* pos = nullptr;
   const uint64_t* neg = nullptr;
   const uint64_t* sets = nullptr;      // caller's set table (hth_kb_set_sets)
@@ -67,6 +68,7 @@ struct hth_kb_s {
     uint32_t region_reg = 2;     // words per lane of the register-stack region kernel (0: LDS kernel)
     uint32_t t_compact = 1;      // 1: T rows of objects only where they are <= N/2
     uint32_t t_segment_kb = 0;   // T bytes per pass of a shared pass (0: one pass over all rows)
+    uint32_t push_pct = 2;       // single ∃ρ.A with A under this % of N: pushed from A's members (0: never)
   } tune;
 };
 

@@ -58,7 +58,8 @@ class Tuning(ctypes.Structure):
     _fields_ = [("group_min", ctypes.c_uint32), ("group_k", ctypes.c_uint32),
                 ("xcd_local", ctypes.c_uint32), ("t_budget_mb", ctypes.c_uint32),
                 ("unroll", ctypes.c_uint32), ("region_reg", ctypes.c_uint32),
-                ("t_compact", ctypes.c_uint32), ("t_segment_kb", ctypes.c_uint32)]
+                ("t_compact", ctypes.c_uint32), ("t_segment_kb", ctypes.c_uint32),
+                ("push_pct", ctypes.c_uint32)]
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

@@ -280,6 +280,50 @@ def test_segmented_shared_passes(seg_kb):
         assert bad.size == 0, f"t_segment_kb={seg_kb} compact={compact}: {hs[bad[0]]} {got[bad[0]]} {want[bad[0]]}"
 
 
+@pytest.mark.parametrize("push_pct", [0, 3, 100])
+def test_pushed_restrictions(push_pct):
+    """Single existential restrictions (and their negations, via forall and
+    at-most-0) over sparse atomic concepts, evaluated from the concept's
+    members over the opposite direction: the counts equal the oracle's at every
+    push threshold, in both directions, next to nodes that cannot be pushed
+    (computed children, at-least-2, a direction with heavy rows)."""
+    cfg = synth.small_config(n=40013, n_concepts=48, n_roles=3, s=1.6, cap=300, n_pos=4000, n_neg=3500,
+                             n_hyps=120, hyp_depth=4, seed_index=1800)
+    kb = synth.make_kb(cfg)
+    rnd = np.random.default_rng(18)
+    hs = synth.make_hypotheses(cfg, kb)
+    for a in range(48):
+        r, inv = a % 3, (a // 3) % 2
+        hs += [("exists", r, inv, ("atom", a)), ("forall", r, inv, ("not", ("atom", a))),
+               ("atmost", 0, r, inv, ("atom", a)), ("atleast", 2, r, inv, ("atom", a)),
+               ("and", ("atom", int(rnd.integers(0, 48))), ("exists", r, 1 - inv, ("atom", a)))]
+    hs += [("exists", 0, 0, ("exists", 1, 1, ("atom", 7))), ("not", ("exists", 2, 1, ("atom", 40)))]
+    want = Oracle(kb).coverages(hs)
+    eng = hthedl.Engine(kb, max_hyps=len(hs))
+    hthedl.hth_kb_set_tuning(eng.handle, push_pct=push_pct)
+    got = eng.eval_plain(hs)
+    bad = np.flatnonzero((got != want).any(axis=1))
+    assert bad.size == 0, f"plain, push {push_pct}%: {hs[bad[0]]} {got[bad[0]]} {want[bad[0]]}"
+    hthedl.hth_kb_set_tuning(eng.handle, group_min=0)
+    got = eng.eval_batch(hs)
+    bad = np.flatnonzero((got != want).any(axis=1))
+    assert bad.size == 0, f"batch, push {push_pct}%: {hs[bad[0]]} {got[bad[0]]} {want[bad[0]]}"
+    o = Oracle(kb)
+    for h in (("exists", 1, 0, ("atom", 45)), ("forall", 2, 1, ("not", ("atom", 46)))):
+        (p, q), bits = eng.eval_one(h, instances=True)
+        np.testing.assert_array_equal(bits, o.ext_bits(h))
+
+
+def test_pushed_restrictions_skip_heavy_directions(monkeypatch):
+    """No push over a direction with heavy rows: counted per subject there."""
+    kb = heavy_kb()
+    hs = [("exists", r, inv, ("atom", 1)) for r in (0, 1) for inv in (0, 1)]
+    hs += [("forall", r, inv, ("not", ("atom", 1))) for r in (0, 1) for inv in (0, 1)]
+    eng = hthedl.Engine(kb)
+    hthedl.hth_kb_set_tuning(eng.handle, push_pct=100)
+    assert np.array_equal(eng.eval_plain(hs), Oracle(kb).coverages(hs))
+
+
 @pytest.mark.parametrize("n,edges", [(5000, 300), (70000, 4000), (130001, 60000)])
 def test_sparse_roles(n, edges):
     """Most 64-subject words have no assertion: the passes visit the non-empty
