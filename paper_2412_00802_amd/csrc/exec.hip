@@ -9,13 +9,15 @@
 //                the example rows, wave reduction, one atomic per wave.
 //   k_role       role restrictions (Algorithms 3-8) over a CSR direction: one
 //                wave per 64 consecutive subjects; the wave walks the subjects'
-//                concatenated assertion range 64 at a time (coalesced target
-//                loads), tests each object against the child row, and each
-//                subject lane counts its own assertions in the chunk as
-//                popcount(ballot & its lane range).  Skewed degrees are balanced
-//                inside the wave by construction; rows stop contributing once
-//                their count decides the predicate, and the walk jumps past
-//                chunks that hold only decided rows.
+//                concatenated assertion range in chunks of 64 (coalesced target
+//                loads, eight chunks' loads in flight), tests each object against
+//                the child row, and each subject lane counts its own assertions
+//                in a chunk as popcount(ballot & its lane range).  Skewed degrees
+//                are balanced inside the wave by construction; rows stop
+//                contributing once their count decides the predicate, and the
+//                walk jumps past chunks that hold only decided rows.  Rows above
+//                the heavy-row threshold are counted on many blocks instead
+//                (k_role_heavy).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -216,6 +218,7 @@ k_region_reg(DevKB kb, const RegionTask* __restrict__ tasks, const uint32_t* __r
 // ---------------------------------------------------------------------------
 // single role restriction, one wave per 64 subjects
 // ---------------------------------------------------------------------------
+constexpr int kRoleChunks = 8;   // 64-assertion chunks whose loads a wave issues together
 template <bool STAGE>
 __device__ __forceinline__ void role_word(const DevKB& kb, const uint32_t* __restrict__ off,
                                           const int32_t* __restrict__ tg,
@@ -233,25 +236,35 @@ __device__ __forceinline__ void role_word(const DevKB& kb, const uint32_t* __res
   uint32_t i0 = (uint32_t)__shfl((int)olo, 0, 64);
   uint32_t cnt = 0;
   while (i0 < ee) {
-    const uint32_t e = i0 + lane;
-    bool v = false;
-    if (e < ee) {
-      const uint32_t t = (uint32_t)tg[e];
-      const uint64_t word = child[t >> 6];
-      v = ((uint32_t)(word >> (t & 63)) & 1u) ^ neg;
+    // kRoleChunks consecutive chunks of 64 assertions: all target loads first
+    int32_t t[kRoleChunks];
+#pragma unroll
+    for (int c = 0; c < kRoleChunks; ++c) {
+      const uint32_t e = i0 + 64 * c + lane;
+      t[c] = e < ee ? tg[e] : -1;
     }
-    const uint64_t m = __ballot(v);
-    const uint32_t a = olo > i0 ? min(olo - i0, 64u) : 0u;
-    const uint32_t b = ohi > i0 ? min(ohi - i0, 64u) : 0u;
-    if (b > a) {
-      const uint64_t rm = (b - a == 64) ? ~0ull : (((1ull << (b - a)) - 1ull) << a);
-      cnt += (uint32_t)__popcll(m & rm);
+#pragma unroll
+    for (int c = 0; c < kRoleChunks; ++c) {
+      const uint32_t base = i0 + 64 * c;
+      bool v = false;
+      if (t[c] >= 0) {
+        const uint32_t y = (uint32_t)t[c];
+        v = ((uint32_t)(child[y >> 6] >> (y & 63)) & 1u) ^ neg;
+      }
+      const uint64_t m = __ballot(v);
+      const uint32_t a = olo > base ? min(olo - base, 64u) : 0u;
+      const uint32_t b = ohi > base ? min(ohi - base, 64u) : 0u;
+      if (b > a) {
+        const uint64_t rm = (b - a == 64) ? ~0ull : (((1ull << (b - a)) - 1ull) << a);
+        cnt += (uint32_t)__popcll(m & rm);
+      }
     }
-    const uint64_t pend = __ballot(in && cnt < sat && ohi > i0 + 64);
+    const uint32_t step = 64 * kRoleChunks;
+    const uint64_t pend = __ballot(in && cnt < sat && ohi > i0 + step);
     if (!pend) break;
     const int l = __ffsll((unsigned long long)pend) - 1;
     const uint32_t nxt = (uint32_t)__shfl((int)olo, l, 64);
-    i0 = max(i0 + 64, nxt);
+    i0 = max(i0 + step, nxt);
   }
   const bool res = in && !heavy && cnt >= lo && cnt <= hi;
   const uint64_t word = __ballot(res);
@@ -680,7 +693,9 @@ hth_status launch_roles(Launcher& L, const DevKB& d, const RoleTask* tasks,
   for (const RoleTask& t : host) bytes += csr_bytes(kb, t.role, t.inv) + 2.0 * kb.W * 8;
   const size_t lds = (size_t)kb.W * 8;
   if (lds <= kb.lds_per_block) {
-    uint32_t bpt = std::max<uint32_t>(1, (2 * kb.n_cu + n - 1) / n);
+    // one 1024-lane block per CU holds the child row in LDS: one round of blocks,
+    // so that each CU stages the row once
+    uint32_t bpt = std::max<uint32_t>(1, (kb.n_cu + n - 1) / n);
     bpt = std::min<uint32_t>(bpt, (kb.W + 15) / 16);
     return split_launch(L, HTH_K_ROLE, bytes, n, bpt, 1024, [&](uint32_t t0, uint32_t, uint32_t blocks) {
       hipLaunchKernelGGL(k_role<true>, dim3(blocks), dim3(1024), lds, L.st, d, tasks + t0, bpt);
