@@ -34,7 +34,8 @@ def candidates(n_individuals: int) -> List[Dict[str, int]]:
     """Each T width (8..64 bits) with: XCD-local passes and a budget of one
     group per XCD (and the 64 MiB default), both unrolls; chip-wide passes
     with one and four groups per launch; one run sharing passes from a single
-    node up; and the region kernel at one and four words per lane.  Widths
+    node up; the region kernel at one and four words per lane; and the push
+    threshold of single existential restrictions at 0 (never) and 8%.  Widths
     whose T rows exceed 1 GiB per group are left out."""
     out = []
     for k, w in ((8, 1), (16, 2), (32, 4), (64, 8)):
@@ -51,8 +52,11 @@ def candidates(n_individuals: int) -> List[Dict[str, int]]:
     out.append(dict(group_min=1, group_k=widest, xcd_local=1, t_budget_mb=64, unroll=16))
     # words per lane of the region kernel (the others keep the default, 2)
     out += [dict(group_min=2, group_k=widest, xcd_local=1, t_budget_mb=64, unroll=16, region_reg=r) for r in (1, 4)]
+    # the push/pull density switch of single existential restrictions (default 2%)
+    out += [dict(group_min=2, group_k=widest, xcd_local=1, t_budget_mb=64, unroll=16, push_pct=p) for p in (0, 8)]
     for c in out:
         c.setdefault("region_reg", 2)
+        c.setdefault("push_pct", 2)
     return out
 
 
