@@ -22,7 +22,11 @@ Readings of the paper taken here (each also listed in the design notes):
 * empty conjunction = top, empty disjunction = bottom; >= 0 r.C = top;
 * a numeric restriction holds when the individual has a value and the float32
   comparison holds (existential concrete-role semantics of Section 3.2.3);
-  a missing value (NaN) satisfies neither >= t nor <= t;
+  a missing value (NaN) satisfies neither >= t nor <= t nor == t;
+* a multi-valued numeric concrete role (Section 3.1: a subject may hold many
+  assertions of one concrete role) gives x to its restriction when some value
+  of x passes the comparison (MIN >=, MAX <=, EXACT ==, Algorithms 9/10); an
+  individual without values of that role passes none;
 * the inverse role swaps the subject and object of every assertion
   (end of Section 3.2.2).
 
@@ -42,7 +46,9 @@ class Oracle:
 
     ``kb`` needs the attributes ``n``, ``concept_bits`` (uint64 [C][W]),
     ``role_offsets`` (int64 [R][N+1], absolute), ``role_targets`` (int32 [E]),
-    ``data`` (float32 [D][N]), ``pos_bits`` and ``neg_bits`` (uint64 [W]).
+    ``data`` (float32 [D][N]), ``pos_bits`` and ``neg_bits`` (uint64 [W]);
+    optionally ``num_offsets`` (int64 [P][N+1], absolute) and ``num_values``
+    (float32 [V]) for multi-valued numeric concrete roles.
     """
 
     def __init__(self, kb):
@@ -51,6 +57,10 @@ class Oracle:
         self._off = np.asarray(kb.role_offsets, dtype=np.int64)
         self._tg = np.asarray(kb.role_targets, dtype=np.int64)
         self._data = np.asarray(kb.data, dtype=np.float32)
+        no = getattr(kb, "num_offsets", None)
+        self._noff = np.zeros((0, self.n + 1), np.int64) if no is None else np.asarray(no, dtype=np.int64)
+        nv = getattr(kb, "num_values", None)
+        self._nval = np.zeros(0, np.float32) if nv is None else np.asarray(nv, dtype=np.float32)
         self.pos = self._unpack(np.asarray(kb.pos_bits, dtype=np.uint64))
         self.neg = self._unpack(np.asarray(kb.neg_bits, dtype=np.uint64))
         self._edges: Dict[int, Tuple[np.ndarray, np.ndarray]] = {}
@@ -103,6 +113,24 @@ class Oracle:
     def data_le(self, p: int, t: float) -> np.ndarray:
         return self._data[p] <= np.float32(t)
 
+    def data_eq(self, p: int, t: float) -> np.ndarray:
+        return self._data[p] == np.float32(t)
+
+    def num_values(self, p: int) -> Tuple[np.ndarray, np.ndarray]:
+        """(subject, value) of every assertion of numeric concrete role p."""
+        off = self._noff[p]
+        subj = np.repeat(np.arange(self.n, dtype=np.int64), np.diff(off))
+        return subj, self._nval[int(off[0]):int(off[-1])]
+
+    def num_some(self, p: int, cmp: str, t: float) -> np.ndarray:
+        """{x : some value v of x in role p with v cmp t}, cmp in ge / le / eq."""
+        subj, val = self.num_values(p)
+        t = np.float32(t)
+        ok = val >= t if cmp == "ge" else val <= t if cmp == "le" else val == t
+        out = np.zeros(self.n, dtype=bool)
+        out[subj[ok]] = True
+        return out
+
     # -- recursive evaluation ---------------------------------------------
 
     def ext(self, h) -> np.ndarray:
@@ -145,6 +173,10 @@ class Oracle:
             return self.data_ge(h[1], h[2])
         if op == "dle":
             return self.data_le(h[1], h[2])
+        if op == "deq":
+            return self.data_eq(h[1], h[2])
+        if op in ("nge", "nle", "neq"):
+            return self.num_some(h[1], op[1:], h[2])
         raise ValueError(f"unknown construct {op!r}")
 
     def coverage(self, h) -> Tuple[int, int]:

@@ -112,6 +112,9 @@ class KB:
     concept_parent: np.ndarray   # int32 [C], -1 for roots
     concept_level: np.ndarray    # int32 [C]
     deciles: np.ndarray          # float32 [D][9]
+    # multi-valued numeric concrete roles (optional)
+    num_offsets: Optional[np.ndarray] = None   # int64 [P][N+1], absolute into num_values
+    num_values: Optional[np.ndarray] = None    # float32 [V]
 
     @property
     def words(self) -> int:
@@ -539,6 +542,64 @@ def hyp_size(h) -> int:
     if op in ("and", "or"):
         return 1 + sum(hyp_size(c) for c in h[1:])
     return 1 + hyp_size(h[-1])
+
+
+def numeric_roles(n: int, n_roles: int, seed: int, p_subj: float = 0.5, zipf_s: float = 1.6,
+                  cap: int = 64, step: float = 1.0 / 16) -> Tuple[np.ndarray, np.ndarray]:
+    """Multi-valued numeric concrete roles: each individual is a subject of a
+    role with probability p_subj, with a Zipf(zipf_s) number of values capped
+    at cap; values ~ N(0, 1) rounded to multiples of `step` (so that equal
+    values, and EXACT matches, occur).  -> (offsets int64 [R][N+1], values
+    float32 [V]), roles stored one after the other."""
+    rng = np.random.default_rng(seed)
+    pmf = 1.0 / np.arange(1, cap + 1, dtype=np.float64) ** zipf_s
+    pmf /= pmf.sum()
+    offs = np.zeros((n_roles, n + 1), dtype=np.int64)
+    vals = []
+    base = 0
+    for r in range(n_roles):
+        subj = rng.random(n) < p_subj
+        deg = np.where(subj, rng.choice(np.arange(1, cap + 1), size=n, p=pmf), 0).astype(np.int64)
+        offs[r, 0] = base
+        offs[r, 1:] = base + np.cumsum(deg)
+        v = np.round(rng.standard_normal(int(deg.sum())) / step) * step
+        vals.append(v.astype(np.float32))
+        base += int(deg.sum())
+    return offs, (np.concatenate(vals) if vals else np.zeros(0, np.float32))
+
+
+def with_numeric_roles(kb: KB, offsets: np.ndarray, values: np.ndarray) -> KB:
+    """The same KB with multi-valued numeric concrete roles attached."""
+    import dataclasses
+    return dataclasses.replace(kb, num_offsets=np.asarray(offsets, dtype=np.int64),
+                               num_values=np.asarray(values, dtype=np.float32))
+
+
+def make_numeric_hypotheses(kb: KB, count: int, seed: int) -> List[tuple]:
+    """Hypotheses over the numeric concrete roles: MIN / MAX / EXACT at
+    values drawn from each role (ties and exact matches exercised), alone and
+    inside conjunctions, negations and role restrictions."""
+    rng = np.random.default_rng(seed)
+    P = kb.num_offsets.shape[0]
+    out: List[tuple] = []
+    for _ in range(count):
+        p = int(rng.integers(0, P))
+        lo, hi = int(kb.num_offsets[p, 0]), int(kb.num_offsets[p, -1])
+        t = float(kb.num_values[int(rng.integers(lo, hi))]) if hi > lo else float(rng.standard_normal())
+        leaf = (["nge", "nle", "neq"][int(rng.integers(0, 3))], p, t)
+        k = int(rng.integers(0, 5))
+        if k == 0:
+            out.append(leaf)
+        elif k == 1:
+            out.append(("not", leaf))
+        elif k == 2:
+            out.append(("and", leaf, ("atom", int(rng.integers(0, kb.n_concepts)))))
+        elif k == 3 and kb.n_roles:
+            out.append(("exists", int(rng.integers(0, kb.n_roles)), int(rng.integers(0, 2)), leaf))
+        else:
+            q = int(rng.integers(0, P))
+            out.append(("or", leaf, ("neq", q, 0.0)))
+    return out
 
 
 def kb_from_edges(n: int, concept_sets: Sequence[Sequence[int]],
