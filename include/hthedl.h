@@ -70,7 +70,12 @@ enum {
   HTH_SET = 13,     /* arg = row of the set table registered with hth_kb_set_sets: an
                        instance set the caller computed earlier (for example the
                        unchanged subtrees of a refined parent), used as a leaf */
-  HTH_NUM_OPS = 14
+  HTH_DATA_EQ = 14, /* {x : value of property arg defined and == t} (EXACT, Algorithms 9/10) */
+  HTH_NUM_GE = 15,  /* {x : some value of numeric concrete role arg is >= t} (MIN,
+                       Section 3.2.3, Algorithms 9/10; roles from hth_kb_set_numeric) */
+  HTH_NUM_LE = 16,  /* {x : some value of numeric concrete role arg is <= t} (MAX) */
+  HTH_NUM_EQ = 17,  /* {x : some value of numeric concrete role arg is == t} (EXACT) */
+  HTH_NUM_OPS = 18
 };
 
 /* One node of a hypothesis, 16 bytes.  Nodes are in postfix order: every child
@@ -80,12 +85,13 @@ typedef struct {
   uint8_t op;       /* HTH_* construct */
   uint8_t inv;      /* role constructs: 1 = inverse role r^- (subject and object swapped) */
   uint16_t arity;   /* AND/OR: number of children; 0 otherwise */
-  uint32_t arg;     /* ATOM: concept id; role constructs: role id; DATA_*: property id */
+  uint32_t arg;     /* ATOM: concept id; role constructs: role id; DATA_*: property id;
+                       NUM_*: numeric concrete role id */
   uint32_t child;   /* NOT and role constructs: child node index (local to the
                        hypothesis); AND/OR: first entry in the children array */
   union {
     uint32_t n;     /* ATLEAST/ATMOST/EXACTLY: n (<= 2^31 - 1) */
-    float t;        /* DATA_GE/DATA_LE: threshold (not NaN; +-inf allowed) */
+    float t;        /* DATA_* and NUM_*: threshold (not NaN; +-inf allowed) */
   } q;
 } hth_node;
 
@@ -137,6 +143,27 @@ hth_status hth_kb_set_examples(hth_kb kb, const uint64_t* pos_bits, const uint64
  * Must not run concurrently with an evaluation on the same kb.  Errors:
  * HTH_E_INVALID (NULL rows with n_rows > 0), HTH_E_RANGE (n_rows >= 2^24). */
 hth_status hth_kb_set_sets(hth_kb kb, const uint64_t* rows, uint32_t n_rows);
+
+/* Multi-valued numeric concrete roles (Section 3.1: a concrete role is a list
+ * of (subject, value) assertions, a subject may hold many; Section 3.2.3).
+ * offsets: device int64 [n_roles][N+1], absolute into values: role p's values
+ * of subject x are values[offsets[p][x] .. offsets[p][x+1]), with
+ * offsets[0][0] = 0, offsets[p][0] = offsets[p-1][N] and
+ * offsets[n_roles-1][N] = n_values.  values: device float32 [n_values], none
+ * NaN (an absent value is an absent assertion).  Both stay the caller's and
+ * must outlive every evaluation that uses them.  derived: device memory of at
+ * least hth_numeric_derived_bytes (256-byte aligned, caller-owned) for the
+ * library's tables of heavy rows (subjects above the heavy-row threshold).
+ * Validates on the device and returns after `stream` has finished.  Replaces
+ * the previous registration (n_roles = 0 removes it); plans compiled before
+ * keep the registration they were compiled with.  Must not run concurrently
+ * with an evaluation on the same kb.  Errors: HTH_E_INVALID (NULL arrays,
+ * offsets not monotone or not chained as above, NaN values, misaligned
+ * derived), HTH_E_NOMEM (derived too small), HTH_E_RANGE (n_roles >= 2^16,
+ * n_values >= 2^40 or a role with 2^32 or more values). */
+hth_status hth_numeric_derived_bytes(hth_kb kb, uint32_t n_roles, uint64_t n_values, size_t* bytes);
+hth_status hth_kb_set_numeric(hth_kb kb, uint32_t n_roles, const int64_t* offsets, const float* values,
+                              uint64_t n_values, void* derived, size_t derived_bytes, void* stream);
 
 /* Largest out-degree of role r in direction inv (0 = forward, 1 = inverse). */
 hth_status hth_kb_max_degree(hth_kb kb, uint32_t role, uint32_t inv, uint32_t* out);

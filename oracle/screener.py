@@ -32,7 +32,8 @@ MASK64 = (1 << 64) - 1
 FEATURE_DIM = 4096
 
 _OPS = {"top": 0, "bot": 1, "atom": 2, "not": 3, "and": 4, "or": 5, "exists": 6, "forall": 7,
-        "atleast": 8, "atmost": 9, "exactly": 10, "dge": 11, "dle": 12}
+        "atleast": 8, "atmost": 9, "exactly": 10, "dge": 11, "dle": 12,
+        "deq": 14, "nge": 15, "nle": 16, "neq": 17}
 
 
 def _fnv(h: int, data: bytes) -> int:
@@ -68,7 +69,7 @@ def subtree_features(h) -> List[Tuple[int, int]]:
             v = _fnv(FNV_OFFSET, _header(op))
         elif op == "atom":
             v = _fnv(FNV_OFFSET, _header(op, arg=t[1]))
-        elif op in ("dge", "dle"):
+        elif op in ("dge", "dle", "deq", "nge", "nle", "neq"):
             v = _fnv(FNV_OFFSET, _header(op, arg=t[1], q=_f32_bits(t[2])))
         elif op == "not":
             c = visit(t[1])

@@ -66,12 +66,106 @@ k_threshold(DevKB kb, const ThrGroup* __restrict__ groups, const ThrTask* __rest
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         // NaN (no value) compares false
-        const uint64_t m = __ballot(in[j] && (T.le ? (f[j] <= T.t) : (f[j] >= T.t)));
+        const bool pass = T.cmp == 0 ? f[j] >= T.t : T.cmp == 1 ? f[j] <= T.t : f[j] == T.t;
+        const uint64_t m = __ballot(in[j] && pass);
         if (lane == j) mine = m;
       }
       if (lane < 8 && w0 + lane < kb.W) out_ptr(kb, T.out_row)[w0 + lane] = mine;
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// multi-valued numeric concrete roles (Algorithms 9/10)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool num_pass(float v, uint32_t cmp, float t) {
+  return cmp == 0 ? v >= t : cmp == 1 ? v <= t : v == t;
+}
+
+// One wave per 64 consecutive subjects, as in the role pass: the wave walks the
+// subjects' concatenated values in chunks of 64 (eight chunks' loads in
+// flight), each subject lane takes its own values in a chunk from the ballot
+// of passing values, and the walk stops once every subject with values left
+// has found one.  Rows above the heavy-row threshold are left to
+// k_numrole_heavy (their bits here are 0).
+constexpr int kNumChunks = 8;
+__global__ void __launch_bounds__(256)
+k_numrole(DevKB kb, const NumTask* __restrict__ tasks, uint32_t bpt) {
+  const uint32_t task = blockIdx.x / bpt, b = blockIdx.x % bpt;
+  const NumTask T = tasks[task];
+  const int64_t* off = kb.num_off + (size_t)T.role * (kb.N + 1);
+  uint64_t* out = out_ptr(kb, T.out_row);
+  const int lane = threadIdx.x & 63;
+  for (uint32_t w = b * 4 + (threadIdx.x >> 6); w < kb.W; w += bpt * 4) {
+    const uint32_t x = w * 64 + lane;
+    const bool in = x < kb.N;
+    const int64_t olo = off[in ? x : kb.N];
+    int64_t ohi = in ? off[x + 1] : olo;
+    const bool heavy = (uint64_t)(ohi - olo) > kb.heavy_min;
+    if (heavy) ohi = olo;
+    const int64_t ee = __shfl((long long)ohi, 63, 64);
+    int64_t i0 = __shfl((long long)olo, 0, 64);
+    bool hit = false;
+    while (i0 < ee) {
+      float v[kNumChunks];
+#pragma unroll
+      for (int c = 0; c < kNumChunks; ++c) {
+        const int64_t e = i0 + 64 * c + lane;
+        v[c] = e < ee ? kb.num_val[e] : 0.0f;
+      }
+#pragma unroll
+      for (int c = 0; c < kNumChunks; ++c) {
+        const int64_t base = i0 + 64 * c;
+        const uint64_t m = __ballot(base + lane < ee && num_pass(v[c], T.cmp, T.t));
+        const int64_t a = olo > base ? min(olo - base, (int64_t)64) : 0;
+        const int64_t bb = ohi > base ? min(ohi - base, (int64_t)64) : 0;
+        if (bb > a) {
+          const uint64_t rm = (bb - a == 64) ? ~0ull : (((1ull << (bb - a)) - 1ull) << a);
+          hit |= (m & rm) != 0;
+        }
+      }
+      const int64_t step = 64 * kNumChunks;
+      const uint64_t pend = __ballot(in && !hit && ohi > i0 + step);
+      if (!pend) break;
+      const int l = __ffsll((unsigned long long)pend) - 1;
+      const int64_t nxt = __shfl((long long)olo, l, 64);
+      i0 = max(i0 + step, nxt);
+    }
+    const uint64_t word = __ballot(in && !heavy && hit);
+    if (lane == 0) out[w] = word;
+  }
+}
+
+// One chunk of kHeavyChunk values of one heavy row per block: a passing value
+// sets the row's bit (after k_numrole wrote the word; an existential result
+// only ever gains bits, so blocks need no ordering among themselves).
+__global__ void __launch_bounds__(256)
+k_numrole_heavy(DevKB kb, const NumTask* __restrict__ tasks, uint32_t n_tasks, uint32_t b0) {
+  __shared__ uint32_t s_any[4];
+  const uint32_t b = b0 + blockIdx.x;
+  uint32_t lo = 0, hi = n_tasks;   // the last task whose first block is <= b
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (tasks[mid].h_first <= b) lo = mid;
+    else hi = mid;
+  }
+  const NumTask T = tasks[lo];
+  const HeavyChunk c = kb.num_heavy_chunks[T.hc0 + (b - T.h_first)];
+  const uint32_t x = kb.num_heavy_rows[c.hrow];
+  const int64_t* off = kb.num_off + (size_t)T.role * (kb.N + 1);
+  const int64_t e0 = off[x] + (int64_t)c.k * kHeavyChunk;
+  const int64_t e1 = min(off[x + 1], e0 + (int64_t)kHeavyChunk);
+  bool any = false;
+#pragma unroll
+  for (uint32_t j = 0; j < kHeavyChunk / 256; ++j) {
+    const int64_t e = e0 + j * 256 + threadIdx.x;
+    if (e < e1) any |= num_pass(kb.num_val[e], T.cmp, T.t);
+  }
+  const uint64_t m = __ballot(any);
+  if ((threadIdx.x & 63) == 0) s_any[threadIdx.x >> 6] = m != 0;
+  __syncthreads();
+  if (threadIdx.x == 0 && (s_any[0] | s_any[1] | s_any[2] | s_any[3]))
+    atomicOr(reinterpret_cast<unsigned long long*>(out_ptr(kb, T.out_row)) + (x >> 6), 1ull << (x & 63));
 }
 
 // ---------------------------------------------------------------------------
@@ -533,6 +627,7 @@ size_t table_bound(uint32_t max_nodes, uint32_t max_hyps) {
   size_t b = 0;
   b += align_up(n * sizeof(ThrTask), 256);
   b += align_up(n * sizeof(ThrGroup), 256);
+  b += align_up(n * sizeof(NumTask), 256);
   b += align_up((n + max_hyps) * sizeof(RegionTask), 256);
   b += align_up(n * sizeof(RoleTask), 256);
   b += align_up(n * sizeof(RoleTask), 256);                // pushed role tasks
@@ -853,6 +948,7 @@ size_t plan_workspace_bytes(const hth_kb_s& kb, const Plan& P) {
   }
   add(P.thr.size(), sizeof(ThrTask));
   add(P.thr.size(), sizeof(ThrGroup));
+  add(P.num.size(), sizeof(NumTask));
   add(n_reg, sizeof(RegionTask));
   add(n_role, sizeof(RoleTask));
   add(n_role, sizeof(RoleTask));            // pushed role tasks (a subset of the role nodes)
@@ -883,6 +979,7 @@ struct Prepared {
   size_t n_thr_groups = 0, n_thr_tasks = 0;
   size_t o_thr = 0, o_thg = 0, o_reg = 0, o_role = 0, o_grp = 0, o_mem = 0, o_fill = 0, o_code = 0, o_xslot = 0;
   size_t o_push = 0;
+  size_t o_num = 0, n_num_blocks = 0;   // numeric concrete-role tasks, their heavy-row blocks
   size_t o_hcnt = 0;   // heavy-row counters (workspace offset)
   size_t o_part = 0;   // partial counts of segmented shared passes (workspace offset)
   size_t tables = 0, need = 0;
@@ -959,6 +1056,13 @@ void prepare(const hth_kb_s& kb, Plan&& plan, uint32_t n_hyps, Prepared& X) {
       thr_groups.push_back(ThrGroup{thr_tasks[i].prop, i, 0, 0});
     thr_groups.back().n++;
   }
+  std::vector<NumTask> num(P.num);
+  for (NumTask& t : num) {
+    t.h_first = (uint32_t)X.n_num_blocks;
+    t.hc0 = P.num_chunk_first[t.role];
+    X.n_num_blocks += P.num_chunk_first[t.role + 1] - P.num_chunk_first[t.role];
+  }
+  X.o_num = X.blob.add(num);
   X.n_thr_groups = thr_groups.size();
   X.n_thr_tasks = thr_tasks.size();
   X.o_thr = X.blob.add(thr_tasks);
@@ -1008,6 +1112,10 @@ hth_status launch_prepared(hth_kb_s& kb, const Prepared& X, char* ws, uint32_t* 
   DevKB d = dev_view(kb);
   d.sets = P.sets;
   d.n_fixed = kb.d.n_concepts + P.n_sets;
+  d.num_off = P.num_off;
+  d.num_val = P.num_val;
+  d.num_heavy_rows = P.num_heavy_rows;
+  d.num_heavy_chunks = P.num_heavy_chunks;
   d.slots = reinterpret_cast<uint64_t*>(ws + X.tables);
   d.counts = counts;
   d.instances = instances;
@@ -1024,6 +1132,24 @@ hth_status launch_prepared(hth_kb_s& kb, const Prepared& X, char* ws, uint32_t* 
   const FillTask* fil = reinterpret_cast<const FillTask*>(ws + X.o_fill);
   const uint32_t* code = reinterpret_cast<const uint32_t*>(ws + X.o_code);
   Launcher Lc{kb, st};
+  if (!P.num.empty()) {
+    const uint32_t n = (uint32_t)P.num.size();
+    const NumTask* nt = reinterpret_cast<const NumTask*>(ws + X.o_num);
+    const uint32_t bpt = std::max<uint32_t>(1, std::min<uint32_t>((kb.W + 7) / 8, (8 * kb.n_cu + n - 1) / n));
+    double bytes = 0;   // per task: the role's offsets and values once, its row out
+    for (const NumTask& t : P.num)
+      bytes += 8.0 * (kb.N + 1) + 4.0 * (double)(P.num_bounds[t.role + 1] - P.num_bounds[t.role]) + 8.0 * kb.W;
+    hth_status s = split_launch(Lc, HTH_K_THRESHOLD, bytes, n, bpt, 256, [&](uint32_t i0, uint32_t, uint32_t blocks) {
+      hipLaunchKernelGGL(k_numrole, dim3(blocks), dim3(256), 0, st, d, nt + i0, bpt);
+    });
+    if (s) return s;
+    if (X.n_num_blocks) {
+      s = split_launch(Lc, HTH_K_THRESHOLD, 0.0, X.n_num_blocks, 1, 256, [&](uint32_t b0, uint32_t, uint32_t blocks) {
+        hipLaunchKernelGGL(k_numrole_heavy, dim3(blocks), dim3(256), 0, st, d, nt, n, b0);
+      });
+      if (s) return s;
+    }
+  }
   if (X.n_thr_groups) {
     // about 32 words per wave: enough independent column loads in flight
     const uint32_t n = (uint32_t)X.n_thr_groups;

@@ -42,12 +42,26 @@ struct RegionTask {
 };
 constexpr uint32_t kInstances = 0xFFFFFFFEu;   // out_row: the caller's instance buffer
 
-// One numeric threshold row: bit x = value_p(x) >= t (or <= t), NaN -> 0.
+// One numeric threshold row: bit x = value_p(x) >= t (cmp 0), <= t (cmp 1)
+// or == t (cmp 2); NaN -> 0.
 struct ThrTask {
   uint32_t prop;
-  uint32_t le;
+  uint32_t cmp;
   float t;
   uint32_t out_row;
+};
+
+// One restriction on a multi-valued numeric concrete role: bit x = some value
+// of x in role `role` is >= t (cmp 0), <= t (cmp 1) or == t (cmp 2).  Heavy
+// rows of the role (see HeavyChunk; numeric tables) are tested chunk by chunk.
+struct NumTask {
+  uint32_t role;
+  uint32_t cmp;
+  float t;
+  uint32_t out_row;
+  uint32_t h_first;    // first block of this task in its heavy-row launch
+  uint32_t hc0;        // first chunk of the role in the numeric chunk table
+  uint32_t pad0, pad1;
 };
 
 // The thresholds on one property, tasks[first .. first + n) (n <= 32).
@@ -141,6 +155,10 @@ struct DevKB {
   const uint32_t* heavy_rows; // subjects of the heavy rows, by direction 2r + dir, increasing
   const HeavyChunk* heavy_chunks;  // by direction, then heavy row, then k
   const uint32_t* heavy_chunk0;    // [heavy rows + 1] first chunk of each heavy row
+  const int64_t* num_off;          // [P][N+1] numeric concrete roles, absolute into num_val
+  const float* num_val;            // [V]
+  const uint32_t* num_heavy_rows;  // subjects of the numeric roles' heavy rows, by role
+  const HeavyChunk* num_heavy_chunks;
   const uint64_t* pos;        // [S]
   const uint64_t* neg;        // [S]
   uint32_t* counts;           // [n_hyps][2]

@@ -778,6 +778,181 @@ extern "C" hth_status hth_kb_create(const hth_kb_desc* desc, void* derived, size
   return HTH_OK;
 }
 
+// ---------------------------------------------------------------------------
+// multi-valued numeric concrete roles
+// ---------------------------------------------------------------------------
+namespace hth {
+
+struct NumLayout {
+  size_t heavy, hchunk, hchunk0, meta, total;
+  size_t heavy_cap, chunk_cap;
+};
+static NumLayout num_layout(uint32_t n_roles, uint64_t n_values) {
+  NumLayout L{};
+  L.heavy_cap = n_values / (kHeavyMinFloor + 1) + 2;
+  L.chunk_cap = n_values / kHeavyChunk + L.heavy_cap + 2;
+  size_t at = 0;
+  L.heavy = at; at += align_up(L.heavy_cap * 12, 256);
+  L.hchunk = at; at += align_up(L.chunk_cap * sizeof(HeavyChunk), 256);
+  L.hchunk0 = at; at += align_up((L.heavy_cap + 1) * 4, 256);
+  L.meta = at; at += align_up((4 + (size_t)n_roles) * 4, 256);
+  L.total = at;
+  return L;
+}
+
+// One thread per (role, subject): offsets within [lo, hi] and non-decreasing;
+// the role's largest degree.
+__global__ void k_validate_num_rows(const int64_t* __restrict__ off, uint32_t N, uint64_t n_values,
+                                    uint32_t* __restrict__ maxdeg, uint32_t* __restrict__ flags) {
+  const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+  if (x >= N) return;
+  const int64_t* o = off + (size_t)r * (N + 1);
+  const int64_t a = o[x], b = o[x + 1];
+  if (a < 0 || b < a || (uint64_t)b > n_values) {
+    atomicOr(flags, F_NONMONO);
+    return;
+  }
+  if (b - a >= (1ll << 32)) {
+    atomicOr(flags, F_NONMONO);
+    return;
+  }
+  atomicMax(maxdeg + r, (uint32_t)(b - a));
+}
+
+__global__ void k_check_values(const float* __restrict__ v, uint64_t n, uint32_t* __restrict__ flags) {
+  bool bad = false;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256)
+    bad |= v[i] != v[i];
+  if (bad) atomicOr(flags, F_TARGET);
+}
+
+// Heavy rows of numeric role r (more than hmin values) as (r, subject, degree).
+__global__ void __launch_bounds__(256)
+k_heavy_rows64(const int64_t* __restrict__ o, uint32_t N, uint32_t hmin, uint32_t r, uint32_t cap,
+               uint32_t* __restrict__ count, uint32_t* __restrict__ out) {
+  const uint32_t x = blockIdx.x * 256 + threadIdx.x;
+  if (x >= N) return;
+  const uint64_t deg = (uint64_t)(o[x + 1] - o[x]);
+  if (deg <= hmin) return;
+  const uint32_t slot = atomicAdd(count, 1u);
+  if (slot < cap) {
+    out[3 * (size_t)slot] = r;
+    out[3 * (size_t)slot + 1] = x;
+    out[3 * (size_t)slot + 2] = (uint32_t)deg;
+  }
+}
+
+}  // namespace hth
+
+extern "C" hth_status hth_numeric_derived_bytes(hth_kb kb, uint32_t n_roles, uint64_t n_values, size_t* bytes) {
+  if (!kb || !bytes) return fail(HTH_E_INVALID, "NULL argument");
+  if (n_roles >= (1u << 16) || n_values >= (1ull << 40)) return fail(HTH_E_RANGE, "too many numeric roles or values");
+  *bytes = num_layout(n_roles, n_values).total;
+  return HTH_OK;
+}
+
+extern "C" hth_status hth_kb_set_numeric(hth_kb kb, uint32_t n_roles, const int64_t* offsets, const float* values,
+                                         uint64_t n_values, void* derived, size_t derived_bytes, void* stream) {
+  if (!kb) return fail(HTH_E_INVALID, "kb is NULL");
+  std::lock_guard<std::mutex> g(kb->mu);
+  if (n_roles == 0) {
+    kb->n_num = 0;
+    kb->num_off = nullptr;
+    kb->num_val = nullptr;
+    kb->num_chunk_first.assign(1, 0);
+    return HTH_OK;
+  }
+  if (!offsets || (n_values && !values) || !derived) return fail(HTH_E_INVALID, "NULL argument");
+  if (n_roles >= (1u << 16) || n_values >= (1ull << 40)) return fail(HTH_E_RANGE, "too many numeric roles or values");
+  const NumLayout L = num_layout(n_roles, n_values);
+  if (derived_bytes < L.total) return fail(HTH_E_NOMEM, "numeric derived buffer smaller than hth_numeric_derived_bytes");
+  if (reinterpret_cast<uintptr_t>(derived) % 256) return fail(HTH_E_INVALID, "derived buffer must be 256-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const uint32_t N = kb->N;
+  char* dv = static_cast<char*>(derived);
+  uint32_t* meta = reinterpret_cast<uint32_t*>(dv + L.meta);
+  uint32_t* flags = meta;
+  uint32_t* count = meta + 1;
+  uint32_t* maxdeg = meta + 4;
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, meta, (size_t)4 + n_roles, 0u);
+  // the chain of role ranges: offsets[0][0] = 0, offsets[p][0] = offsets[p-1][N], last = n_values
+  std::vector<int64_t> ends(2 * (size_t)n_roles);
+  for (uint32_t r = 0; r < n_roles; ++r) {
+    HTH_HIP(hipMemcpyAsync(&ends[2 * r], offsets + (size_t)r * (N + 1), 8, hipMemcpyDeviceToHost, st));
+    HTH_HIP(hipMemcpyAsync(&ends[2 * r + 1], offsets + (size_t)r * (N + 1) + N, 8, hipMemcpyDeviceToHost, st));
+  }
+  HTH_HIP(hipStreamSynchronize(st));
+  if (ends[0] != 0) return fail(HTH_E_INVALID, "numeric offsets[0][0] must be 0");
+  for (uint32_t r = 1; r < n_roles; ++r)
+    if (ends[2 * r] != ends[2 * r - 1]) return fail(HTH_E_INVALID, "numeric role ranges must follow one another");
+  if ((uint64_t)ends[2 * (size_t)n_roles - 1] != n_values)
+    return fail(HTH_E_INVALID, "numeric offsets[n_roles-1][N] must equal n_values");
+  hipLaunchKernelGGL(k_validate_num_rows, dim3((N + 255) / 256, n_roles), dim3(256), 0, st, offsets, N, n_values,
+                     maxdeg, flags);
+  if (n_values) {
+    const unsigned gg = (unsigned)std::min<uint64_t>((n_values + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_check_values, dim3(gg), dim3(256), 0, st, values, n_values, flags);
+  }
+  HTH_HIP(hipGetLastError());
+  uint32_t hflags = 0;
+  std::vector<uint32_t> md(n_roles);
+  HTH_HIP(hipMemcpyAsync(&hflags, flags, 4, hipMemcpyDeviceToHost, st));
+  HTH_HIP(hipMemcpyAsync(md.data(), maxdeg, (size_t)n_roles * 4, hipMemcpyDeviceToHost, st));
+  HTH_HIP(hipStreamSynchronize(st));
+  if (hflags & F_NONMONO) return fail(HTH_E_INVALID, "numeric role offsets not monotone or out of range");
+  if (hflags & F_TARGET) return fail(HTH_E_INVALID, "a numeric value is NaN");
+  // heavy rows, sorted by (role, subject), and their chunk tables
+  uint32_t* rows = reinterpret_cast<uint32_t*>(dv + L.heavy);
+  HeavyChunk* chunks_dev = reinterpret_cast<HeavyChunk*>(dv + L.hchunk);
+  std::vector<uint32_t> chunk_first(n_roles + 1, 0);
+  bool any = false;
+  for (uint32_t r = 0; r < n_roles; ++r)
+    if (md[r] > kb->heavy_min) {
+      any = true;
+      hipLaunchKernelGGL(k_heavy_rows64, dim3((N + 255) / 256), dim3(256), 0, st, offsets + (size_t)r * (N + 1), N,
+                         kb->heavy_min, r, (uint32_t)L.heavy_cap, count, rows);
+    }
+  HTH_HIP(hipGetLastError());
+  if (any) {
+    uint32_t nh = 0;
+    HTH_HIP(hipMemcpyAsync(&nh, count, 4, hipMemcpyDeviceToHost, st));
+    HTH_HIP(hipStreamSynchronize(st));
+    if (nh > L.heavy_cap) return fail(HTH_E_RANGE, "numeric heavy-row table overflow");
+    std::vector<uint32_t> trip(3 * (size_t)nh);
+    HTH_HIP(hipMemcpyAsync(trip.data(), rows, trip.size() * 4, hipMemcpyDeviceToHost, st));
+    HTH_HIP(hipStreamSynchronize(st));
+    std::vector<uint32_t> ord(nh);
+    for (uint32_t i = 0; i < nh; ++i) ord[i] = i;
+    std::sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) {
+      return trip[3 * a] != trip[3 * b] ? trip[3 * a] < trip[3 * b] : trip[3 * a + 1] < trip[3 * b + 1];
+    });
+    std::vector<uint32_t> hrows(nh);
+    std::vector<HeavyChunk> chunks;
+    std::vector<uint32_t> cper(n_roles, 0);
+    for (uint32_t i = 0; i < nh; ++i) {
+      const uint32_t* t = &trip[3 * (size_t)ord[i]];
+      hrows[i] = t[1];
+      const uint32_t nc = (t[2] + kHeavyChunk - 1) / kHeavyChunk;
+      cper[t[0]] += nc;
+      for (uint32_t k = 0; k < nc; ++k) chunks.push_back(HeavyChunk{i, k});
+    }
+    if (chunks.size() > L.chunk_cap) return fail(HTH_E_RANGE, "numeric heavy chunk table overflow");
+    for (uint32_t r = 0; r < n_roles; ++r) chunk_first[r + 1] = chunk_first[r] + cper[r];
+    HTH_HIP(hipMemcpyAsync(rows, hrows.data(), hrows.size() * 4, hipMemcpyHostToDevice, st));
+    HTH_HIP(hipMemcpyAsync(chunks_dev, chunks.data(), chunks.size() * sizeof(HeavyChunk), hipMemcpyHostToDevice, st));
+    HTH_HIP(hipStreamSynchronize(st));
+  }
+  kb->n_num = n_roles;
+  kb->num_off = offsets;
+  kb->num_val = values;
+  kb->num_heavy_rows = rows;
+  kb->num_heavy_chunks = chunks_dev;
+  kb->num_chunk_first = chunk_first;
+  kb->num_bounds.assign(n_roles + 1, 0);
+  for (uint32_t r = 0; r < n_roles; ++r) kb->num_bounds[r + 1] = (uint64_t)ends[2 * r + 1];
+  return HTH_OK;
+}
+
 extern "C" hth_status hth_kb_set_examples(hth_kb kb, const uint64_t* pos, const uint64_t* neg) {
   if (!kb) return fail(HTH_E_INVALID, "kb is NULL");
   if (!pos || !neg) return fail(HTH_E_INVALID, "example rows are NULL");

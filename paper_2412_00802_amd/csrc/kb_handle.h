@@ -37,6 +37,14 @@ struct hth_kb_s {
   uint32_t heavy_most = 0;             // most heavy rows in one direction
   uint32_t chunk_most = 0;             // most heavy chunks in one direction
   std::vector<uint32_t> concept_pop;   // [C] members of each concept
+  // multi-valued numeric concrete roles (hth_kb_set_numeric): caller's arrays
+  uint32_t n_num = 0;
+  const int64_t* num_off = nullptr;    // [n_num][N+1]
+  const float* num_val = nullptr;
+  uint32_t* num_heavy_rows = nullptr;  // in the caller's numeric derived buffer
+  hth::HeavyChunk* num_heavy_chunks = nullptr;
+  std::vector<uint32_t> num_chunk_first;   // [n_num+1] first chunk of each role
+  std::vector<uint64_t> num_bounds;        // [n_num+1] first value of each role
   const uint64_t* pos = nullptr;
   const uint64_t* neg = nullptr;
   const uint64_t* sets = nullptr;      // caller's set table (hth_kb_set_sets)

@@ -41,8 +41,10 @@ __device__ __forceinline__ uint64_t mix64(uint64_t x) {   // splitmix64 finalise
 // fields a construct does not use set to zero
 __device__ __forceinline__ uint64_t node_header_hash(const hth_node& n) {
   const uint32_t op = n.op;
-  const bool uses_arg = op == HTH_ATOM || (op >= HTH_EXISTS && op <= HTH_DATA_LE);
-  const bool uses_q = (op >= HTH_ATLEAST && op <= HTH_EXACTLY) || op == HTH_DATA_GE || op == HTH_DATA_LE;
+  const bool value_op = op >= HTH_DATA_EQ && op <= HTH_NUM_EQ;   // EXACT and numeric concrete roles
+  const bool uses_arg = op == HTH_ATOM || (op >= HTH_EXISTS && op <= HTH_DATA_LE) || value_op;
+  const bool uses_q = (op >= HTH_ATLEAST && op <= HTH_EXACTLY) || op == HTH_DATA_GE || op == HTH_DATA_LE ||
+                      value_op;
   const bool uses_inv = op >= HTH_EXISTS && op <= HTH_EXACTLY;
   const uint32_t arity = (op == HTH_AND || op == HTH_OR) ? n.arity : 0;
   uint32_t q;
@@ -69,7 +71,8 @@ __global__ void k_features(const hth_node* __restrict__ nodes, const uint32_t* _
     const hth_node n = nodes[i];
     const uint32_t li = i - b;
     uint64_t v = node_header_hash(n);
-    bool ok = n.op <= HTH_DATA_LE;   // the DL constructs; set-table leaves carry no syntax
+    // the DL constructs; set-table leaves carry no syntax
+    bool ok = n.op <= HTH_DATA_LE || (n.op >= HTH_DATA_EQ && n.op <= HTH_NUM_EQ);
     if (n.op == HTH_NOT || (n.op >= HTH_EXISTS && n.op <= HTH_EXACTLY)) {
       ok = ok && n.child < li;
       v = fnv_bytes(v, ok ? hash[b + n.child] : 0ull, 8);

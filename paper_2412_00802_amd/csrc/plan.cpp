@@ -139,7 +139,9 @@ class Dag {
 };
 
 inline bool is_role(uint8_t op) { return op >= HTH_EXISTS && op <= HTH_EXACTLY; }
-inline bool is_data(uint8_t op) { return op == HTH_DATA_GE || op == HTH_DATA_LE; }
+inline bool is_column(uint8_t op) { return op == HTH_DATA_GE || op == HTH_DATA_LE || op == HTH_DATA_EQ; }
+inline bool is_numeric(uint8_t op) { return op == HTH_NUM_GE || op == HTH_NUM_LE || op == HTH_NUM_EQ; }
+inline bool is_data(uint8_t op) { return is_column(op) || is_numeric(op); }
 inline bool is_leaflike(uint8_t op) {
   return op == HTH_ATOM || op == HTH_SET || is_data(op) || is_role(op);
 }
@@ -209,8 +211,14 @@ struct Compiler {
           map[i] = dag.mk_role(x.op, x.inv, x.arg, x.q.n, map[x.child]);
           break;
         case HTH_DATA_GE:
-        case HTH_DATA_LE: {
-          if (x.arg >= d.n_data) return bad(HTH_E_RANGE, "property id out of range");
+        case HTH_DATA_LE:
+        case HTH_DATA_EQ:
+        case HTH_NUM_GE:
+        case HTH_NUM_LE:
+        case HTH_NUM_EQ: {
+          if (is_column(x.op) && x.arg >= d.n_data) return bad(HTH_E_RANGE, "property id out of range");
+          if (is_numeric(x.op) && x.arg >= kb.n_num)
+            return bad(HTH_E_RANGE, "numeric concrete role id outside the registered roles");
           if (std::isnan(x.q.t)) return bad(HTH_E_INVALID, "threshold is NaN");
           uint32_t bits;
           std::memcpy(&bits, &x.q.t, 4);
@@ -319,14 +327,22 @@ struct Compiler {
     for (uint32_t v = 0; v < nv; ++v) {
       if (!live[v]) continue;
       const CNode& n = dag.nodes[v];
-      if (is_data(n.op)) {
+      if (is_column(n.op)) {
         row[v] = new_row();
         ThrTask t;
         t.prop = n.arg;
-        t.le = n.op == HTH_DATA_LE;
+        t.cmp = n.op == HTH_DATA_GE ? 0 : n.op == HTH_DATA_LE ? 1 : 2;
         std::memcpy(&t.t, &n.q, 4);
         t.out_row = row[v];
         P.thr.push_back(t);
+      } else if (is_numeric(n.op)) {
+        row[v] = new_row();
+        NumTask t{};
+        t.role = n.arg;
+        t.cmp = n.op == HTH_NUM_GE ? 0 : n.op == HTH_NUM_LE ? 1 : 2;
+        std::memcpy(&t.t, &n.q, 4);
+        t.out_row = row[v];
+        P.num.push_back(t);
       } else if (is_role(n.op)) {
         row[v] = new_row();
         max_level = std::max(max_level, height[v]);
@@ -466,6 +482,14 @@ struct Compiler {
     P.n_slots = n_slots;
     P.sets = kb.sets;
     P.n_sets = kb.n_sets;
+    if (!P.num.empty()) {
+      P.num_off = kb.num_off;
+      P.num_val = kb.num_val;
+      P.num_heavy_rows = kb.num_heavy_rows;
+      P.num_heavy_chunks = kb.num_heavy_chunks;
+      P.num_chunk_first = kb.num_chunk_first;
+      P.num_bounds = kb.num_bounds;
+    }
     P.n_canonical = (uint32_t)nv;
     return HTH_OK;
   }

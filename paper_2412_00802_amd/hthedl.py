@@ -23,7 +23,8 @@ STATUS = {0: "HTH_OK", -1: "HTH_E_INVALID", -2: "HTH_E_RANGE", -3: "HTH_E_NOMEM"
           -4: "HTH_E_DEVICE", -5: "HTH_E_PLAN", -6: "HTH_E_STATE", -7: "HTH_E_UNSUPPORTED"}
 
 OPS = {"top": 0, "bot": 1, "atom": 2, "not": 3, "and": 4, "or": 5, "exists": 6, "forall": 7,
-       "atleast": 8, "atmost": 9, "exactly": 10, "dge": 11, "dle": 12, "set": 13}
+       "atleast": 8, "atmost": 9, "exactly": 10, "dge": 11, "dle": 12, "set": 13,
+       "deq": 14, "nge": 15, "nle": 16, "neq": 17}
 
 NODE_DTYPE = np.dtype([("op", np.uint8), ("inv", np.uint8), ("arity", np.uint16),
                        ("arg", np.uint32), ("child", np.uint32), ("q", np.uint32)])
@@ -36,7 +37,8 @@ EXPORTED = ["hth_kb_derived_bytes", "hth_kb_create", "hth_kb_set_examples", "hth
             "hth_head_backward", "hth_colsum", "hth_adamw", "hth_to_bf16", "hth_topk",
             "hth_batch_workspace_bytes", "hth_head_score", "hth_kb_get_tuning", "hth_kb_set_tuning",
             "hth_kb_set_sets", "hth_eval_batch_sets", "hth_densify_delta", "hth_plan_create",
-            "hth_plan_upload", "hth_plan_launch", "hth_plan_destroy"]
+            "hth_plan_upload", "hth_plan_launch", "hth_plan_destroy", "hth_numeric_derived_bytes",
+            "hth_kb_set_numeric"]
 
 
 class HthError(RuntimeError):
@@ -96,6 +98,8 @@ def lib() -> ctypes.CDLL:
             "hth_eval_batch": [P, P, P, U32, P, U32, P, S, P, P],
             "hth_eval_batch_sets": [P, P, P, U32, P, U32, P, S, P, P, P],
             "hth_kb_set_sets": [P, P, U32],
+            "hth_numeric_derived_bytes": [P, U32, U64, ctypes.POINTER(S)],
+            "hth_kb_set_numeric": [P, U32, P, P, U64, P, S, P],
             "hth_plan_create": [P, P, P, U32, P, U32, ctypes.POINTER(P), ctypes.POINTER(S)],
             "hth_plan_upload": [P, P, S, P],
             "hth_plan_launch": [P, P, S, P, P],
@@ -188,6 +192,21 @@ def hth_kb_set_examples(kb, pos, neg) -> None:
 
 def hth_kb_set_sets(kb, rows, n_rows: int) -> None:
     _check(lib().hth_kb_set_sets(kb, _ptr(rows) if n_rows else None, n_rows))
+
+
+def hth_numeric_derived_bytes(kb, n_roles: int, n_values: int) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().hth_numeric_derived_bytes(kb, n_roles, n_values, ctypes.byref(out)))
+    return out.value
+
+
+def hth_kb_set_numeric(kb, n_roles: int, offsets, values, n_values: int, derived, derived_bytes: int,
+                       stream=None) -> None:
+    """Register multi-valued numeric concrete roles (device int64 offsets
+    [n_roles][N+1] and float32 values); n_roles = 0 removes them."""
+    _check(lib().hth_kb_set_numeric(kb, n_roles, _ptr(offsets) if n_roles else None,
+                                    _ptr(values) if n_values else None, n_values,
+                                    _ptr(derived) if n_roles else None, derived_bytes, _stream(stream)))
 
 
 def hth_kb_max_degree(kb, role: int, inv: int) -> int:
@@ -390,7 +409,7 @@ def encode(h, nodes: list, children: list) -> int:
         _, k, r, inv, c = h
         ci = encode(c, nodes, children)
         nodes.append((code, inv, 0, r, ci, k))
-    elif op in ("dge", "dle"):
+    elif op in ("dge", "dle", "deq", "nge", "nle", "neq"):
         nodes.append((code, 0, 0, h[1], 0, _f32_bits(h[2])))
     else:
         raise ValueError(op)
@@ -516,6 +535,16 @@ class Engine:
         nbytes = hth_kb_derived_bytes(d)
         self.derived = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
         self.handle = hth_kb_create(d, self.derived, nbytes)
+        no = getattr(kb, "num_offsets", None)
+        if no is not None and len(no):
+            # multi-valued numeric concrete roles
+            self.num_offsets = torch.from_numpy(np.ascontiguousarray(no, dtype=np.int64)).to(dev)
+            vals = np.ascontiguousarray(kb.num_values, dtype=np.float32)
+            self.num_values = torch.from_numpy(vals if vals.size else np.zeros(1, np.float32)).to(dev)
+            P, V = int(no.shape[0]), int(vals.size)
+            nb = hth_numeric_derived_bytes(self.handle, P, V)
+            self.num_derived = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
+            hth_kb_set_numeric(self.handle, P, self.num_offsets, self.num_values, V, self.num_derived, nb)
         self.ws = None
         self.ws_bytes = 0
         self.reserve(max_nodes, max_hyps)

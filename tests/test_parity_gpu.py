@@ -639,3 +639,97 @@ def test_heavy_rows(monkeypatch, heavy_min):
     for h in (("exists", 0, 0, ("atom", 2)), ("atleast", 2049, 0, 0, ("top",)), ("forall", 1, 1, ("atom", 0))):
         (p, q), bits = eng.eval_one(h, instances=True)
         np.testing.assert_array_equal(bits, o.ext_bits(h))
+
+
+def numeric_kb(n=50000, seed=21):
+    """Concepts and roles from the small generator plus three numeric concrete
+    roles: Zipf value counts, values on a 1/16 grid (exact matches and ties),
+    and two subjects above the heavy-row threshold (1,500 and 9,000 values)."""
+    cfg = synth.small_config(n=n, n_concepts=24, n_roles=3, cap=40, n_pos=n // 10, n_neg=n // 12,
+                             seed_index=seed)
+    kb = synth.make_kb(cfg)
+    offs, vals = synth.numeric_roles(n, 3, seed=seed, cap=48)
+    # splice two long rows into role 1: subjects 777 and n - 1
+    rows = [list(vals[offs[1, x]:offs[1, x + 1]]) for x in range(n)]
+    rng = np.random.default_rng(seed)
+    rows[777] = list(np.round(rng.standard_normal(1500) * 16) / 16)
+    rows[n - 1] = list(np.round(rng.standard_normal(9000) * 16) / 16) + [7.5]
+    base = offs[1, 0]
+    new1 = np.zeros(n + 1, np.int64)
+    new1[0] = base
+    new1[1:] = base + np.cumsum([len(r) for r in rows])
+    v1 = np.asarray([v for r in rows for v in r], np.float32)
+    shift = new1[-1] - offs[1, -1]
+    offs = offs.copy()
+    offs[1] = new1
+    offs[2] += shift
+    vals = np.concatenate([vals[: offs[0, -1]], v1, vals[offs[2, 0] - shift:]]).astype(np.float32)
+    return synth.with_numeric_roles(kb, offs, vals), cfg
+
+
+@pytest.mark.parametrize("heavy_min", [None, 1024])
+def test_numeric_concrete_roles(monkeypatch, heavy_min):
+    """MIN / MAX / EXACT over multi-valued numeric concrete roles, alone and
+    nested, equal the oracle in the plain path and the batch, with heavy rows
+    counted chunk by chunk (threshold 1,024) or in the wave walk (2,048 for
+    the 1,500-value row)."""
+    if heavy_min is not None:
+        monkeypatch.setenv("HTHEDL_HEAVY_MIN", str(heavy_min))
+    kb, cfg = numeric_kb()
+    hs = synth.make_numeric_hypotheses(kb, 300, seed=5)
+    for p in range(3):
+        for t in (float("-inf"), -0.0, 0.0, 0.0625, 7.5, 1e30, float("inf")):
+            hs += [("nge", p, t), ("nle", p, t), ("neq", p, t)]
+    hs += [("not", ("neq", 1, 7.5)), ("exists", 0, 1, ("nge", 1, 3.0)),
+           ("and", ("nle", 0, -1.0), ("nge", 2, 1.0), ("atom", 3)), ("forall", 2, 0, ("nle", 1, 0.5))]
+    eng = check(kb, hs, label=f"numeric roles, heavy {heavy_min}")
+    o = Oracle(kb)
+    for h in (("nge", 1, 2.0), ("neq", 1, 7.5), ("nle", 2, -2.0)):
+        (p, q), bits = eng.eval_one(h, instances=True)
+        np.testing.assert_array_equal(bits, o.ext_bits(h))
+
+
+def test_data_exact():
+    """EXACT on single-valued columns: NaN never equal, +0 == -0, ties at deciles."""
+    cfg = synth.small_config(n=20011, n_concepts=16, n_roles=2, cap=20, n_data=3, n_hyps=10, seed_index=2100)
+    kb = synth.make_kb(cfg)
+    hs = []
+    for p in range(3):
+        for t in list(kb.deciles[p]) + [0.0, -0.0, 1e9, float("-inf")]:
+            hs += [("deq", p, float(t)), ("not", ("deq", p, float(t))),
+                   ("and", ("deq", p, float(t)), ("dge", p, float(t)))]
+    check(kb, hs, label="data exact")
+
+
+def test_numeric_registration_errors(gpu):
+    torch = gpu
+    kb, _ = numeric_kb(n=3000)
+    eng = hthedl.Engine(kb)
+    P = kb.num_offsets.shape[0]
+    good_off = torch.from_numpy(kb.num_offsets.copy()).cuda()
+    V = int(kb.num_values.shape[0])
+    nb = hthedl.hth_numeric_derived_bytes(eng.handle, P, V)
+    der = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    bad_vals = kb.num_values.copy()
+    bad_vals[5] = np.nan
+    with pytest.raises(hthedl.HthError, match="NaN"):
+        hthedl.hth_kb_set_numeric(eng.handle, P, good_off, torch.from_numpy(bad_vals).cuda(), V, der, nb)
+    off = kb.num_offsets.copy()
+    off[1, 10], off[1, 11] = off[1, 11] + 1, off[1, 10]       # a row that runs backwards
+    with pytest.raises(hthedl.HthError, match="monotone"):
+        hthedl.hth_kb_set_numeric(eng.handle, P, torch.from_numpy(off).cuda(),
+                                  torch.from_numpy(kb.num_values).cuda(), V, der, nb)
+    off = kb.num_offsets.copy()
+    off[2] += 1                                               # role 2 does not start where role 1 ends
+    with pytest.raises(hthedl.HthError):
+        hthedl.hth_kb_set_numeric(eng.handle, P, torch.from_numpy(off).cuda(),
+                                  torch.from_numpy(kb.num_values).cuda(), V, der, nb)
+    with pytest.raises(hthedl.HthError, match="NOMEM|smaller"):
+        hthedl.hth_kb_set_numeric(eng.handle, P, good_off, torch.from_numpy(kb.num_values).cuda(), V, der, 256)
+    # the failed calls left the earlier registration in place
+    assert eng.eval_plain([("nge", 1, 0.0)]).tolist() == [list(Oracle(kb).coverage(("nge", 1, 0.0)))]
+    with pytest.raises(hthedl.HthError, match="numeric concrete role id"):
+        eng.eval_plain([("nge", 3, 0.0)])
+    hthedl.hth_kb_set_numeric(eng.handle, 0, None, None, 0, None, 0)
+    with pytest.raises(hthedl.HthError):
+        eng.eval_plain([("nge", 0, 0.0)])
