@@ -164,8 +164,13 @@ k_numrole_heavy(DevKB kb, const NumTask* __restrict__ tasks, uint32_t n_tasks, u
   const uint64_t m = __ballot(any);
   if ((threadIdx.x & 63) == 0) s_any[threadIdx.x >> 6] = m != 0;
   __syncthreads();
-  if (threadIdx.x == 0 && (s_any[0] | s_any[1] | s_any[2] | s_any[3]))
-    atomicOr(reinterpret_cast<unsigned long long*>(out_ptr(kb, T.out_row)) + (x >> 6), 1ull << (x & 63));
+  if (threadIdx.x == 0 && (s_any[0] | s_any[1] | s_any[2] | s_any[3])) {
+    // many chunks of one row pass at once: only the ones that find the bit
+    // still clear go to the atomic (a set bit is never cleared here)
+    unsigned long long* word = reinterpret_cast<unsigned long long*>(out_ptr(kb, T.out_row)) + (x >> 6);
+    const unsigned long long bit = 1ull << (x & 63);
+    if (!(__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bit)) atomicOr(word, bit);
+  }
 }
 
 // ---------------------------------------------------------------------------

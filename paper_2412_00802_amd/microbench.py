@@ -6,7 +6,9 @@ M1 (Table 2's shape): a conjunction of five atomic concepts at N from 10k to
 32M individuals.  M2 (Table 4 and the cardinality table's shapes): one role
 with either a single subject of degree E ("single subject") or E subjects of
 degree 1 ("unique subject"), E up to 10M, evaluated as an existential and as
-an at-least-2 restriction.  Each operation is compiled once (hth_plan_create),
+an at-least-2 restriction.  M3 (Table 8's shape): one numeric concrete role
+with the same two layouts and every value 1.0, under MIN at 0.5 (every
+subject decided by its first value) and at 2.0 (every value read).  Each operation is compiled once (hth_plan_create),
 uploaded once and launched repeatedly; the time is the device time per launch
 (HIP events on the launch stream).  Prints one JSON line per case.
 """
@@ -121,14 +123,37 @@ def main():
                 emit({"case": f"M2 {shape}, {op}", "assertions": e, "individuals": n,
                       "us_per_op": round(ms * 1e3, 2), "GBps": round(byts / (ms * 1e-3) / 1e9, 1)})
             eng.close()
+    # M3: numeric concrete role, single subject and unique subject, values 1.0
+    for e in edges:
+        n = max(1_000_000, 2 * e)
+        for shape in ("single subject", "unique subject"):
+            deg = np.zeros(n, dtype=np.int64)
+            if shape == "single subject":
+                deg[0] = e
+            else:
+                deg[np.sort(rng.choice(n, size=e, replace=False))] = 1
+            offs = np.zeros((1, n + 1), dtype=np.int64)
+            np.cumsum(deg, out=offs[0, 1:])
+            kb = synth.with_numeric_roles(make_kb(n, 1, np.zeros(0, np.int64), np.zeros(0, np.int32), seed=3),
+                                          offs, np.ones(e, dtype=np.float32))
+            eng = hthedl.Engine(kb, max_nodes=16, max_hyps=1)
+            w8 = 8 * ((n + 63) // 64)
+            for op, h in (("MIN 0.5, decided by the first value", ("nge", 0, 0.5)),
+                          ("MIN 2.0, every value read", ("nge", 0, 2.0))):
+                ms = time_op(eng, h, args.reps)
+                byts = 4.0 * e + 8.0 * (n + 1) + 2 * w8
+                emit({"case": f"M3 numeric {shape}, {op}", "assertions": e, "individuals": n,
+                      "us_per_op": round(ms * 1e3, 2), "GBps": round(byts / (ms * 1e-3) / 1e9, 1)})
+            eng.close()
     if args.markdown:
         cmd = "python -m paper_2412_00802_amd.microbench " + " ".join(sys.argv[1:])
-        lines = ["# Per-operation microbenchmarks (M1: five-concept conjunction; M2: one role, single "
-                 "subject / unique subject)", "", "Command:", "", "    " + cmd, "",
+        lines = ["# Per-operation microbenchmarks (M1: five-concept conjunction; M2: one role, M3: one "
+                 "numeric concrete role, single subject / unique subject)", "", "Command:", "", "    " + cmd, "",
                  "Device time per launch of a compiled one-hypothesis plan (all of its kernels: count "
                  "clearing, the operation, coverage), HIP events around back-to-back launches.  GB/s "
                  "counts algorithmic bytes: M1 the five rows read, the example rows and the output; M2 "
                  "the assertions' targets (4 B each), the row offsets (4 B per individual) and two bit "
+                 "rows; M3 the values (4 B each), the int64 offsets (8 B per individual) and two bit "
                  "rows.", "",
                  "| case | individuals | assertions | us per op | GB/s |", "|---|---|---|---|---|"]
         for r in results:
