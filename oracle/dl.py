@@ -27,6 +27,11 @@ Readings of the paper taken here (each also listed in the design notes):
   assertions of one concrete role) gives x to its restriction when some value
   of x passes the comparison (MIN >=, MAX <=, EXACT ==, Algorithms 9/10); an
   individual without values of that role passes none;
+* string concrete roles work the same way over strings: EQUAL holds when some
+  value of x is the query string, CONTAIN when some value has the pattern as
+  a substring (Algorithms 11-14; the empty pattern is a substring of every
+  string); a query string absent from the knowledge base's strings matches
+  nothing (the short-circuit of Algorithms 11/12);
 * the inverse role swaps the subject and object of every assertion
   (end of Section 3.2.2).
 
@@ -48,7 +53,9 @@ class Oracle:
     ``role_offsets`` (int64 [R][N+1], absolute), ``role_targets`` (int32 [E]),
     ``data`` (float32 [D][N]), ``pos_bits`` and ``neg_bits`` (uint64 [W]);
     optionally ``num_offsets`` (int64 [P][N+1], absolute) and ``num_values``
-    (float32 [V]) for multi-valued numeric concrete roles.
+    (float32 [V]) for multi-valued numeric concrete roles, and ``str_offsets``
+    (int64 [Q][N+1]), ``str_ids`` (int32 [V']) and ``strings`` (list of bytes:
+    the distinct strings, indexed by id) for string concrete roles.
     """
 
     def __init__(self, kb):
@@ -61,6 +68,11 @@ class Oracle:
         self._noff = np.zeros((0, self.n + 1), np.int64) if no is None else np.asarray(no, dtype=np.int64)
         nv = getattr(kb, "num_values", None)
         self._nval = np.zeros(0, np.float32) if nv is None else np.asarray(nv, dtype=np.float32)
+        so = getattr(kb, "str_offsets", None)
+        self._soff = np.zeros((0, self.n + 1), np.int64) if so is None else np.asarray(so, dtype=np.int64)
+        si = getattr(kb, "str_ids", None)
+        self._sids = np.zeros(0, np.int64) if si is None else np.asarray(si, dtype=np.int64)
+        self._strings = list(getattr(kb, "strings", None) or [])
         self.pos = self._unpack(np.asarray(kb.pos_bits, dtype=np.uint64))
         self.neg = self._unpack(np.asarray(kb.neg_bits, dtype=np.uint64))
         self._edges: Dict[int, Tuple[np.ndarray, np.ndarray]] = {}
@@ -131,6 +143,22 @@ class Oracle:
         out[subj[ok]] = True
         return out
 
+    def str_values(self, p: int) -> Tuple[np.ndarray, List[bytes]]:
+        """(subject, string) of every assertion of string concrete role p."""
+        off = self._soff[p]
+        subj = np.repeat(np.arange(self.n, dtype=np.int64), np.diff(off))
+        ids = self._sids[int(off[0]):int(off[-1])]
+        return subj, [self._strings[i] for i in ids]
+
+    def str_some(self, p: int, test) -> np.ndarray:
+        """{x : some string value s of x in role p with test(s)}."""
+        subj, vals = self.str_values(p)
+        out = np.zeros(self.n, dtype=bool)
+        for x, v in zip(subj.tolist(), vals):
+            if test(v):
+                out[x] = True
+        return out
+
     # -- recursive evaluation ---------------------------------------------
 
     def ext(self, h) -> np.ndarray:
@@ -177,6 +205,12 @@ class Oracle:
             return self.data_eq(h[1], h[2])
         if op in ("nge", "nle", "neq"):
             return self.num_some(h[1], op[1:], h[2])
+        if op == "sequal":                                # Algorithms 11/12
+            q = bytes(h[2])
+            return self.str_some(h[1], lambda v: v == q)
+        if op == "scontains":                             # Algorithms 13/14
+            q = bytes(h[2])
+            return self.str_some(h[1], lambda v: q in v)
         raise ValueError(f"unknown construct {op!r}")
 
     def coverage(self, h) -> Tuple[int, int]:

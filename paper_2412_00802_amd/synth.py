@@ -115,6 +115,10 @@ class KB:
     # multi-valued numeric concrete roles (optional)
     num_offsets: Optional[np.ndarray] = None   # int64 [P][N+1], absolute into num_values
     num_values: Optional[np.ndarray] = None    # float32 [V]
+    # string concrete roles (optional): values are ids into `strings`
+    str_offsets: Optional[np.ndarray] = None   # int64 [Q][N+1], absolute into str_ids
+    str_ids: Optional[np.ndarray] = None       # int32 [V']
+    strings: Optional[List[bytes]] = None      # the distinct strings
 
     @property
     def words(self) -> int:
@@ -573,6 +577,80 @@ def with_numeric_roles(kb: KB, offsets: np.ndarray, values: np.ndarray) -> KB:
     import dataclasses
     return dataclasses.replace(kb, num_offsets=np.asarray(offsets, dtype=np.int64),
                                num_values=np.asarray(values, dtype=np.float32))
+
+
+def string_roles(n: int, n_roles: int, seed: int, n_strings: int = 2000, p_subj: float = 0.4,
+                 zipf_s: float = 1.8, cap: int = 16, alphabet: bytes = b"abcdef",
+                 max_len: int = 12) -> Tuple[np.ndarray, np.ndarray, List[bytes]]:
+    """String concrete roles over a dictionary of n_strings distinct random
+    words (lengths 1..max_len over a small alphabet, so that substrings
+    recur): each individual is a subject with probability p_subj, with a
+    Zipf number of values capped at cap, each a uniform dictionary id.
+    -> (offsets int64 [R][N+1], ids int32 [V], strings)."""
+    rng = np.random.default_rng(seed)
+    seen = set()
+    strings: List[bytes] = []
+    while len(strings) < n_strings:
+        k = int(rng.integers(1, max_len + 1))
+        w = bytes(alphabet[int(i)] for i in rng.integers(0, len(alphabet), size=k))
+        if w not in seen:
+            seen.add(w)
+            strings.append(w)
+    pmf = 1.0 / np.arange(1, cap + 1, dtype=np.float64) ** zipf_s
+    pmf /= pmf.sum()
+    offs = np.zeros((n_roles, n + 1), dtype=np.int64)
+    ids = []
+    base = 0
+    for r in range(n_roles):
+        subj = rng.random(n) < p_subj
+        deg = np.where(subj, rng.choice(np.arange(1, cap + 1), size=n, p=pmf), 0).astype(np.int64)
+        offs[r, 0] = base
+        offs[r, 1:] = base + np.cumsum(deg)
+        ids.append(rng.integers(0, n_strings, size=int(deg.sum())).astype(np.int32))
+        base += int(deg.sum())
+    return offs, (np.concatenate(ids) if ids else np.zeros(0, np.int32)), strings
+
+
+def with_string_roles(kb: KB, offsets: np.ndarray, ids: np.ndarray, strings: List[bytes]) -> KB:
+    """The same KB with string concrete roles attached."""
+    import dataclasses
+    return dataclasses.replace(kb, str_offsets=np.asarray(offsets, dtype=np.int64),
+                               str_ids=np.asarray(ids, dtype=np.int32), strings=list(strings))
+
+
+def make_string_hypotheses(kb: KB, count: int, seed: int) -> List[tuple]:
+    """EQUAL at dictionary strings and at absent ones; CONTAIN at short
+    patterns (often substrings), the empty pattern and absent ones; alone and
+    inside negations, conjunctions and role restrictions."""
+    rng = np.random.default_rng(seed)
+    Q = kb.str_offsets.shape[0]
+    out: List[tuple] = []
+    for _ in range(count):
+        p = int(rng.integers(0, Q))
+        u = rng.random()
+        if u < 0.35:
+            leaf = ("sequal", p, kb.strings[int(rng.integers(0, len(kb.strings)))])
+        elif u < 0.4:
+            leaf = ("sequal", p, b"zz" + bytes([97 + int(rng.integers(0, 6))]))
+        elif u < 0.9:
+            s = kb.strings[int(rng.integers(0, len(kb.strings)))]
+            a = int(rng.integers(0, len(s)))
+            leaf = ("scontains", p, s[a:a + int(rng.integers(1, 4))])
+        elif u < 0.95:
+            leaf = ("scontains", p, b"")
+        else:
+            leaf = ("scontains", p, b"fedcbafedcbafedcba")
+        k = int(rng.integers(0, 4))
+        if k == 0:
+            out.append(leaf)
+        elif k == 1:
+            out.append(("not", leaf))
+        elif k == 2:
+            out.append(("and", leaf, ("atom", int(rng.integers(0, kb.n_concepts)))))
+        else:
+            out.append(("exists", int(rng.integers(0, kb.n_roles)), int(rng.integers(0, 2)), leaf)
+                       if kb.n_roles else leaf)
+    return out
 
 
 def make_numeric_hypotheses(kb: KB, count: int, seed: int) -> List[tuple]:
