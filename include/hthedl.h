@@ -75,7 +75,12 @@ enum {
                        Section 3.2.3, Algorithms 9/10; roles from hth_kb_set_numeric) */
   HTH_NUM_LE = 16,  /* {x : some value of numeric concrete role arg is <= t} (MAX) */
   HTH_NUM_EQ = 17,  /* {x : some value of numeric concrete role arg is == t} (EXACT) */
-  HTH_NUM_OPS = 18
+  HTH_STR_EQ = 18,  /* {x : some value of string concrete role arg is dictionary string q.n}
+                       (EQUAL, Algorithms 11/12; roles from hth_kb_set_strings);
+                       q.n = 0xFFFFFFFF: a string absent from the dictionary, no individual */
+  HTH_STR_CONTAINS = 19, /* {x : some value of string concrete role arg has pattern q.n as a
+                       substring} (CONTAIN, Algorithms 13/14; patterns from hth_kb_set_patterns) */
+  HTH_NUM_OPS = 20
 };
 
 /* One node of a hypothesis, 16 bytes.  Nodes are in postfix order: every child
@@ -86,11 +91,12 @@ typedef struct {
   uint8_t inv;      /* role constructs: 1 = inverse role r^- (subject and object swapped) */
   uint16_t arity;   /* AND/OR: number of children; 0 otherwise */
   uint32_t arg;     /* ATOM: concept id; role constructs: role id; DATA_*: property id;
-                       NUM_*: numeric concrete role id */
+                       NUM_*: numeric concrete role id; STR_*: string concrete role id */
   uint32_t child;   /* NOT and role constructs: child node index (local to the
                        hypothesis); AND/OR: first entry in the children array */
   union {
-    uint32_t n;     /* ATLEAST/ATMOST/EXACTLY: n (<= 2^31 - 1) */
+    uint32_t n;     /* ATLEAST/ATMOST/EXACTLY: n (<= 2^31 - 1); STR_EQ: string id; STR_CONTAINS:
+                       pattern id */
     float t;        /* DATA_* and NUM_*: threshold (not NaN; +-inf allowed) */
   } q;
 } hth_node;
@@ -164,6 +170,34 @@ hth_status hth_kb_set_sets(hth_kb kb, const uint64_t* rows, uint32_t n_rows);
 hth_status hth_numeric_derived_bytes(hth_kb kb, uint32_t n_roles, uint64_t n_values, size_t* bytes);
 hth_status hth_kb_set_numeric(hth_kb kb, uint32_t n_roles, const int64_t* offsets, const float* values,
                               uint64_t n_values, void* derived, size_t derived_bytes, void* stream);
+
+/* String concrete roles (Section 3.1: (subject, string) assertions; Section
+ * 3.2.3).  The strings are interned: a dictionary of n_strings distinct
+ * strings, string s = chars[str_offsets[s] .. str_offsets[s+1]) (device int64
+ * [n_strings+1], non-decreasing from 0; device bytes), and every assertion
+ * holds a dictionary id.  offsets: device int64 [n_roles][N+1], absolute into
+ * ids and chained as for hth_kb_set_numeric; ids: device int32 [n_values] in
+ * [0, n_strings).  All arrays stay the caller's.  derived: device memory of at
+ * least hth_string_derived_bytes (256-byte aligned) for heavy-row tables.
+ * Validates on the device and returns after `stream` has finished; replaces
+ * the previous registration (n_roles = 0 removes it; plans compiled before
+ * keep theirs).  Errors as for hth_kb_set_numeric, plus HTH_E_INVALID for an
+ * id out of range or non-monotone string offsets, and HTH_E_RANGE for
+ * n_strings >= 2^31. */
+hth_status hth_string_derived_bytes(hth_kb kb, uint32_t n_roles, uint64_t n_values, size_t* bytes);
+hth_status hth_kb_set_strings(hth_kb kb, uint32_t n_roles, const int64_t* offsets, const int32_t* ids,
+                              uint64_t n_values, uint32_t n_strings, const int64_t* str_offsets,
+                              const uint8_t* chars, void* derived, size_t derived_bytes, void* stream);
+
+/* The CONTAIN patterns that HTH_STR_CONTAINS nodes name by index: pattern k =
+ * chars[offsets[k] .. offsets[k+1]) (device int64 [n_patterns+1],
+ * non-decreasing; device bytes; the empty pattern is a substring of every
+ * string).  Owned by the caller and read by later evaluations; plans compiled
+ * before keep the table they were compiled with.  n_patterns = 0 removes it.
+ * The offsets are checked on `stream` (synchronous).  Errors: HTH_E_INVALID
+ * (NULL arrays with n_patterns > 0, offsets not non-decreasing from 0). */
+hth_status hth_kb_set_patterns(hth_kb kb, uint32_t n_patterns, const int64_t* offsets, const uint8_t* chars,
+                               void* stream);
 
 /* Largest out-degree of role r in direction inv (0 = forward, 1 = inverse). */
 hth_status hth_kb_max_degree(hth_kb kb, uint32_t role, uint32_t inv, uint32_t* out);

@@ -82,19 +82,17 @@ __device__ __forceinline__ bool num_pass(float v, uint32_t cmp, float t) {
   return cmp == 0 ? v >= t : cmp == 1 ? v <= t : v == t;
 }
 
-// One wave per 64 consecutive subjects, as in the role pass: the wave walks the
-// subjects' concatenated values in chunks of 64 (eight chunks' loads in
-// flight), each subject lane takes its own values in a chunk from the ballot
-// of passing values, and the walk stops once every subject with values left
-// has found one.  Rows above the heavy-row threshold are left to
-// k_numrole_heavy (their bits here are 0).
+// Value roles (numeric and string concrete roles): one wave per 64 consecutive
+// subjects, as in the role pass.  The wave walks the subjects' concatenated
+// values in chunks of 64 (eight chunks' loads in flight), each subject lane
+// takes its own values in a chunk from the ballot of passing values, and the
+// walk stops once every subject with values left has found one.  Rows above
+// the heavy-row threshold are left to value_heavy (their bits here are 0).
 constexpr int kNumChunks = 8;
-__global__ void __launch_bounds__(256)
-k_numrole(DevKB kb, const NumTask* __restrict__ tasks, uint32_t bpt) {
-  const uint32_t task = blockIdx.x / bpt, b = blockIdx.x % bpt;
-  const NumTask T = tasks[task];
-  const int64_t* off = kb.num_off + (size_t)T.role * (kb.N + 1);
-  uint64_t* out = out_ptr(kb, T.out_row);
+template <typename V, class Pass>
+__device__ __forceinline__ void value_walk(const DevKB& kb, const int64_t* __restrict__ off,
+                                           const V* __restrict__ vals, Pass pass, uint64_t* __restrict__ out,
+                                           uint32_t b, uint32_t bpt) {
   const int lane = threadIdx.x & 63;
   for (uint32_t w = b * 4 + (threadIdx.x >> 6); w < kb.W; w += bpt * 4) {
     const uint32_t x = w * 64 + lane;
@@ -107,16 +105,16 @@ k_numrole(DevKB kb, const NumTask* __restrict__ tasks, uint32_t bpt) {
     int64_t i0 = __shfl((long long)olo, 0, 64);
     bool hit = false;
     while (i0 < ee) {
-      float v[kNumChunks];
+      V v[kNumChunks];
 #pragma unroll
       for (int c = 0; c < kNumChunks; ++c) {
         const int64_t e = i0 + 64 * c + lane;
-        v[c] = e < ee ? kb.num_val[e] : 0.0f;
+        v[c] = e < ee ? vals[e] : V(0);
       }
 #pragma unroll
       for (int c = 0; c < kNumChunks; ++c) {
         const int64_t base = i0 + 64 * c;
-        const uint64_t m = __ballot(base + lane < ee && num_pass(v[c], T.cmp, T.t));
+        const uint64_t m = __ballot(base + lane < ee && pass(v[c]));
         const int64_t a = olo > base ? min(olo - base, (int64_t)64) : 0;
         const int64_t bb = ohi > base ? min(ohi - base, (int64_t)64) : 0;
         if (bb > a) {
@@ -137,39 +135,115 @@ k_numrole(DevKB kb, const NumTask* __restrict__ tasks, uint32_t bpt) {
 }
 
 // One chunk of kHeavyChunk values of one heavy row per block: a passing value
-// sets the row's bit (after k_numrole wrote the word; an existential result
-// only ever gains bits, so blocks need no ordering among themselves).
-__global__ void __launch_bounds__(256)
-k_numrole_heavy(DevKB kb, const NumTask* __restrict__ tasks, uint32_t n_tasks, uint32_t b0) {
+// sets the row's bit (after the walk wrote the word; an existential result
+// only ever gains bits, so blocks need no ordering among themselves).  Chunk
+// blocks that find the bit already set skip the atomic.
+template <typename V, class Pass>
+__device__ __forceinline__ void value_heavy(const DevKB& kb, const int64_t* __restrict__ off,
+                                            const V* __restrict__ vals, Pass pass, uint64_t* __restrict__ out,
+                                            uint32_t x, uint32_t k) {
   __shared__ uint32_t s_any[4];
-  const uint32_t b = b0 + blockIdx.x;
-  uint32_t lo = 0, hi = n_tasks;   // the last task whose first block is <= b
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (tasks[mid].h_first <= b) lo = mid;
-    else hi = mid;
-  }
-  const NumTask T = tasks[lo];
-  const HeavyChunk c = kb.num_heavy_chunks[T.hc0 + (b - T.h_first)];
-  const uint32_t x = kb.num_heavy_rows[c.hrow];
-  const int64_t* off = kb.num_off + (size_t)T.role * (kb.N + 1);
-  const int64_t e0 = off[x] + (int64_t)c.k * kHeavyChunk;
+  const int64_t e0 = off[x] + (int64_t)k * kHeavyChunk;
   const int64_t e1 = min(off[x + 1], e0 + (int64_t)kHeavyChunk);
   bool any = false;
 #pragma unroll
   for (uint32_t j = 0; j < kHeavyChunk / 256; ++j) {
     const int64_t e = e0 + j * 256 + threadIdx.x;
-    if (e < e1) any |= num_pass(kb.num_val[e], T.cmp, T.t);
+    if (e < e1) any |= pass(vals[e]);
   }
   const uint64_t m = __ballot(any);
   if ((threadIdx.x & 63) == 0) s_any[threadIdx.x >> 6] = m != 0;
   __syncthreads();
   if (threadIdx.x == 0 && (s_any[0] | s_any[1] | s_any[2] | s_any[3])) {
-    // many chunks of one row pass at once: only the ones that find the bit
-    // still clear go to the atomic (a set bit is never cleared here)
-    unsigned long long* word = reinterpret_cast<unsigned long long*>(out_ptr(kb, T.out_row)) + (x >> 6);
+    unsigned long long* word = reinterpret_cast<unsigned long long*>(out) + (x >> 6);
     const unsigned long long bit = 1ull << (x & 63);
     if (!(__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bit)) atomicOr(word, bit);
+  }
+}
+
+// the task of heavy block b: the last task whose first block is <= b
+template <class Task>
+__device__ __forceinline__ uint32_t value_task(const Task* __restrict__ tasks, uint32_t n, uint32_t b) {
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (tasks[mid].h_first <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(256)
+k_numrole(DevKB kb, const NumTask* __restrict__ tasks, uint32_t bpt) {
+  const NumTask T = tasks[blockIdx.x / bpt];
+  value_walk<float>(kb, kb.num_off + (size_t)T.role * (kb.N + 1), kb.num_val,
+                    [&](float v) { return num_pass(v, T.cmp, T.t); }, out_ptr(kb, T.out_row), blockIdx.x % bpt, bpt);
+}
+
+__global__ void __launch_bounds__(256)
+k_numrole_heavy(DevKB kb, const NumTask* __restrict__ tasks, uint32_t n_tasks, uint32_t b0) {
+  const uint32_t b = b0 + blockIdx.x;
+  const NumTask T = tasks[value_task(tasks, n_tasks, b)];
+  const HeavyChunk c = kb.num_heavy_chunks[T.hc0 + (b - T.h_first)];
+  value_heavy<float>(kb, kb.num_off + (size_t)T.role * (kb.N + 1), kb.num_val,
+                     [&](float v) { return num_pass(v, T.cmp, T.t); }, out_ptr(kb, T.out_row),
+                     kb.num_heavy_rows[c.hrow], c.k);
+}
+
+// CONTAIN, first step: for every dictionary string, whether it holds the
+// task's pattern (one lane per string, a plain scan of the string; the empty
+// pattern is in every string).  A wave ballot writes one word of the task's
+// id set per 64 strings.  The per-assertion test then reads one bit.
+__global__ void __launch_bounds__(256)
+k_contains(DevKB kb, const StrTask* __restrict__ tasks, uint32_t tiles) {
+  const StrTask T = tasks[blockIdx.x / tiles];
+  const uint32_t s = (blockIdx.x % tiles) * 256 + threadIdx.x;
+  const int64_t p0 = kb.pat_off[T.q], pl = kb.pat_off[T.q + 1] - p0;
+  const uint8_t* pat = kb.pat_chars + p0;
+  bool hit = false;
+  if (s < kb.n_strings) {
+    const int64_t s0 = kb.dict_off[s], sl = kb.dict_off[s + 1] - s0;
+    const uint8_t* str = kb.dict_chars + s0;
+    for (int64_t i = 0; i + pl <= sl && !hit; ++i) {
+      int64_t j = 0;
+      while (j < pl && str[i + j] == pat[j]) ++j;
+      hit = j == pl;
+    }
+  }
+  const uint64_t m = __ballot(hit);
+  const uint32_t w = s >> 6;
+  if ((threadIdx.x & 63) == 0 && (uint64_t)w * 64 < kb.n_strings) kb.idsets[T.set_word + w] = m;
+}
+
+__global__ void __launch_bounds__(256)
+k_strrole(DevKB kb, const StrTask* __restrict__ tasks, uint32_t bpt) {
+  const StrTask T = tasks[blockIdx.x / bpt];
+  const int64_t* off = kb.str_off + (size_t)T.role * (kb.N + 1);
+  uint64_t* out = out_ptr(kb, T.out_row);
+  if (T.kind == 0) {
+    value_walk<int32_t>(kb, off, kb.str_ids, [&](int32_t id) { return (uint32_t)id == T.q; }, out,
+                        blockIdx.x % bpt, bpt);
+  } else {
+    const uint64_t* set = kb.idsets + T.set_word;
+    value_walk<int32_t>(kb, off, kb.str_ids, [&](int32_t id) { return (set[(uint32_t)id >> 6] >> (id & 63)) & 1; },
+                        out, blockIdx.x % bpt, bpt);
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_strrole_heavy(DevKB kb, const StrTask* __restrict__ tasks, uint32_t n_tasks, uint32_t b0) {
+  const uint32_t b = b0 + blockIdx.x;
+  const StrTask T = tasks[value_task(tasks, n_tasks, b)];
+  const HeavyChunk c = kb.str_heavy_chunks[T.hc0 + (b - T.h_first)];
+  const int64_t* off = kb.str_off + (size_t)T.role * (kb.N + 1);
+  const uint32_t x = kb.str_heavy_rows[c.hrow];
+  uint64_t* out = out_ptr(kb, T.out_row);
+  if (T.kind == 0) {
+    value_heavy<int32_t>(kb, off, kb.str_ids, [&](int32_t id) { return (uint32_t)id == T.q; }, out, x, c.k);
+  } else {
+    const uint64_t* set = kb.idsets + T.set_word;
+    value_heavy<int32_t>(kb, off, kb.str_ids, [&](int32_t id) { return (set[(uint32_t)id >> 6] >> (id & 63)) & 1; },
+                         out, x, c.k);
   }
 }
 
@@ -633,6 +707,7 @@ size_t table_bound(uint32_t max_nodes, uint32_t max_hyps) {
   b += align_up(n * sizeof(ThrTask), 256);
   b += align_up(n * sizeof(ThrGroup), 256);
   b += align_up(n * sizeof(NumTask), 256);
+  b += align_up(n * sizeof(StrTask), 256);
   b += align_up((n + max_hyps) * sizeof(RegionTask), 256);
   b += align_up(n * sizeof(RoleTask), 256);
   b += align_up(n * sizeof(RoleTask), 256);                // pushed role tasks
@@ -938,6 +1013,14 @@ size_t partial_bytes(const hth_kb_s& kb, const Plan& P) {
   return align_up(most, 256);
 }
 
+// the id sets of a plan's CONTAIN restrictions: one bit per dictionary string each
+inline size_t idset_words(uint32_t n_strings) { return align_up(((size_t)n_strings + 63) / 64, 8); }
+size_t idset_bytes(const Plan& P) {
+  size_t n = 0;
+  for (const StrTask& t : P.str) n += t.kind == 1;
+  return align_up(n * idset_words(P.n_strings) * 8, 256);
+}
+
 // bytes of the packed tables plus slots plus T area for a plan
 size_t plan_workspace_bytes(const hth_kb_s& kb, const Plan& P) {
   size_t tables = 0;
@@ -954,6 +1037,7 @@ size_t plan_workspace_bytes(const hth_kb_s& kb, const Plan& P) {
   add(P.thr.size(), sizeof(ThrTask));
   add(P.thr.size(), sizeof(ThrGroup));
   add(P.num.size(), sizeof(NumTask));
+  add(P.str.size(), sizeof(StrTask));
   add(n_reg, sizeof(RegionTask));
   add(n_role, sizeof(RoleTask));
   add(n_role, sizeof(RoleTask));            // pushed role tasks (a subset of the role nodes)
@@ -963,7 +1047,7 @@ size_t plan_workspace_bytes(const hth_kb_s& kb, const Plan& P) {
   add(P.code.size(), sizeof(uint32_t));
   add(9 * n_grp + 8, sizeof(uint32_t));     // XCD slot tables: at most 8 more than groups per chunk
   return align_up(tables, 256) + (size_t)P.n_slots * kb.S * 8 + (max_groups ? t_area_bytes(kb) : 0) +
-         heavy_counter_bytes(kb, P) + partial_bytes(kb, P);
+         heavy_counter_bytes(kb, P) + partial_bytes(kb, P) + idset_bytes(P);
 }
 
 std::once_flag g_attr_once;
@@ -985,6 +1069,8 @@ struct Prepared {
   size_t o_thr = 0, o_thg = 0, o_reg = 0, o_role = 0, o_grp = 0, o_mem = 0, o_fill = 0, o_code = 0, o_xslot = 0;
   size_t o_push = 0;
   size_t o_num = 0, n_num_blocks = 0;   // numeric concrete-role tasks, their heavy-row blocks
+  size_t o_str = 0, n_str_blocks = 0, n_contains = 0;   // string concrete-role tasks
+  size_t o_idset = 0;                   // the CONTAIN id sets (workspace offset)
   size_t o_hcnt = 0;   // heavy-row counters (workspace offset)
   size_t o_part = 0;   // partial counts of segmented shared passes (workspace offset)
   size_t tables = 0, need = 0;
@@ -1068,6 +1154,30 @@ void prepare(const hth_kb_s& kb, Plan&& plan, uint32_t n_hyps, Prepared& X) {
     X.n_num_blocks += P.num_chunk_first[t.role + 1] - P.num_chunk_first[t.role];
   }
   X.o_num = X.blob.add(num);
+  std::vector<StrTask> str(P.str);
+  {
+    size_t sw = 0;
+    for (StrTask& t : str) {
+      t.h_first = (uint32_t)X.n_str_blocks;
+      t.hc0 = P.str_chunk_first[t.role];
+      X.n_str_blocks += P.str_chunk_first[t.role + 1] - P.str_chunk_first[t.role];
+      if (t.kind == 1) {
+        t.set_word = (uint32_t)sw;
+        sw += idset_words(P.n_strings);
+        X.n_contains++;
+      }
+    }
+  }
+  // CONTAIN tasks first in their own table, so that k_contains takes a range
+  std::stable_partition(str.begin(), str.end(), [](const StrTask& t) { return t.kind == 1; });
+  {   // the heavy-block numbering must follow the table order
+    size_t hb = 0;
+    for (StrTask& t : str) {
+      t.h_first = (uint32_t)hb;
+      hb += P.str_chunk_first[t.role + 1] - P.str_chunk_first[t.role];
+    }
+  }
+  X.o_str = X.blob.add(str);
   X.n_thr_groups = thr_groups.size();
   X.n_thr_tasks = thr_tasks.size();
   X.o_thr = X.blob.add(thr_tasks);
@@ -1085,10 +1195,12 @@ void prepare(const hth_kb_s& kb, Plan&& plan, uint32_t n_hyps, Prepared& X) {
   for (const PlanLevel& PL : P.levels) max_groups = std::max(max_groups, PL.groups.size());
   X.o_hcnt = X.tables + (size_t)P.n_slots * kb.S * 8 + (max_groups ? t_area_bytes(kb) : 0);
   X.o_part = X.o_hcnt + heavy_counter_bytes(kb, P);
+  X.o_idset = 0;   // set below, after the partial counts
   size_t part = 0;
   for (size_t L = 0; L < NL; ++L)
     for (const GroupChunk& c : X.lv_chunks[L]) part = std::max(part, chunk_partial_bytes(kb, X.lv_groups[L], c));
-  X.need = X.o_part + align_up(part, 256);
+  X.o_idset = X.o_part + align_up(part, 256);
+  X.need = X.o_idset + idset_bytes(P);
 }
 
 hth_status check_ws(const Prepared& X, const char* ws, size_t ws_bytes) {
@@ -1121,6 +1233,16 @@ hth_status launch_prepared(hth_kb_s& kb, const Prepared& X, char* ws, uint32_t* 
   d.num_val = P.num_val;
   d.num_heavy_rows = P.num_heavy_rows;
   d.num_heavy_chunks = P.num_heavy_chunks;
+  d.str_off = P.str_off;
+  d.str_ids = P.str_ids;
+  d.str_heavy_rows = P.str_heavy_rows;
+  d.str_heavy_chunks = P.str_heavy_chunks;
+  d.dict_off = P.dict_off;
+  d.dict_chars = P.dict_chars;
+  d.pat_off = P.pat_off;
+  d.pat_chars = P.pat_chars;
+  d.n_strings = P.n_strings;
+  d.idsets = reinterpret_cast<uint64_t*>(ws + X.o_idset);
   d.slots = reinterpret_cast<uint64_t*>(ws + X.tables);
   d.counts = counts;
   d.instances = instances;
@@ -1151,6 +1273,32 @@ hth_status launch_prepared(hth_kb_s& kb, const Prepared& X, char* ws, uint32_t* 
     if (X.n_num_blocks) {
       s = split_launch(Lc, HTH_K_THRESHOLD, 0.0, X.n_num_blocks, 1, 256, [&](uint32_t b0, uint32_t, uint32_t blocks) {
         hipLaunchKernelGGL(k_numrole_heavy, dim3(blocks), dim3(256), 0, st, d, nt, n, b0);
+      });
+      if (s) return s;
+    }
+  }
+  if (!P.str.empty()) {
+    const uint32_t n = (uint32_t)P.str.size();
+    const StrTask* sk = reinterpret_cast<const StrTask*>(ws + X.o_str);
+    hth_status s = HTH_OK;
+    if (X.n_contains) {   // the id sets: the dictionary strings holding each pattern
+      const uint32_t tiles = std::max<uint32_t>(1, (P.n_strings + 255) / 256);
+      s = split_launch(Lc, HTH_K_THRESHOLD, 0.0, X.n_contains, tiles, 256, [&](uint32_t i0, uint32_t, uint32_t blocks) {
+        hipLaunchKernelGGL(k_contains, dim3(blocks), dim3(256), 0, st, d, sk + i0, tiles);
+      });
+      if (s) return s;
+    }
+    const uint32_t bpt = std::max<uint32_t>(1, std::min<uint32_t>((kb.W + 7) / 8, (8 * kb.n_cu + n - 1) / n));
+    double bytes = 0;   // per task: the role's offsets and ids once, its row out
+    for (const StrTask& t : P.str)
+      bytes += 8.0 * (kb.N + 1) + 4.0 * (double)(P.str_bounds[t.role + 1] - P.str_bounds[t.role]) + 8.0 * kb.W;
+    s = split_launch(Lc, HTH_K_THRESHOLD, bytes, n, bpt, 256, [&](uint32_t i0, uint32_t, uint32_t blocks) {
+      hipLaunchKernelGGL(k_strrole, dim3(blocks), dim3(256), 0, st, d, sk + i0, bpt);
+    });
+    if (s) return s;
+    if (X.n_str_blocks) {
+      s = split_launch(Lc, HTH_K_THRESHOLD, 0.0, X.n_str_blocks, 1, 256, [&](uint32_t b0, uint32_t, uint32_t blocks) {
+        hipLaunchKernelGGL(k_strrole_heavy, dim3(blocks), dim3(256), 0, st, d, sk, n, b0);
       });
       if (s) return s;
     }
@@ -1231,7 +1379,8 @@ extern "C" hth_status hth_workspace_bytes(hth_kb kb, uint32_t max_nodes, uint32_
   if (!kb || !bytes) return fail(HTH_E_INVALID, "NULL argument");
   if (max_hyps == 0 || max_nodes < max_hyps) return fail(HTH_E_RANGE, "need max_nodes >= max_hyps >= 1");
   *bytes = align_up(table_bound(max_nodes, max_hyps), 256) + (size_t)(max_nodes + 2) * kb->S * 8 +
-           t_area_bytes(*kb) + align_up((size_t)(max_nodes + 2) * kb->chunk_most * 4, 256);
+           t_area_bytes(*kb) + align_up((size_t)(max_nodes + 2) * kb->chunk_most * 4, 256) +
+           align_up((size_t)(max_nodes + 2) * idset_words(kb->n_strings) * 8, 256);
   return HTH_OK;
 }
 

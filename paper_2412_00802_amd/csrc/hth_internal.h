@@ -64,6 +64,21 @@ struct NumTask {
   uint32_t pad0, pad1;
 };
 
+// One restriction on a string concrete role: bit x = some value id of x in
+// role `role` equals q (kind 0, EQUAL) or lies in the id set at word
+// `set_word` of the plan's id-set area (kind 1, CONTAIN: the dictionary ids
+// whose string holds pattern q, written first by k_contains).
+struct StrTask {
+  uint32_t role;
+  uint32_t kind;
+  uint32_t q;
+  uint32_t out_row;
+  uint32_t h_first;    // first block of this task in its heavy-row launch
+  uint32_t hc0;        // first chunk of the role in the string chunk table
+  uint32_t set_word;
+  uint32_t pad;
+};
+
 // The thresholds on one property, tasks[first .. first + n) (n <= 32).
 struct ThrGroup {
   uint32_t prop;
@@ -159,6 +174,16 @@ struct DevKB {
   const float* num_val;            // [V]
   const uint32_t* num_heavy_rows;  // subjects of the numeric roles' heavy rows, by role
   const HeavyChunk* num_heavy_chunks;
+  const int64_t* str_off;          // [Q][N+1] string concrete roles, absolute into str_ids
+  const int32_t* str_ids;          // [V'] dictionary ids
+  const uint32_t* str_heavy_rows;
+  const HeavyChunk* str_heavy_chunks;
+  const int64_t* dict_off;         // [n_strings+1] the dictionary
+  const uint8_t* dict_chars;
+  const int64_t* pat_off;          // [n_patterns+1] CONTAIN patterns
+  const uint8_t* pat_chars;
+  uint64_t* idsets;                // the plan's id-set area (workspace)
+  uint32_t n_strings;
   const uint64_t* pos;        // [S]
   const uint64_t* neg;        // [S]
   uint32_t* counts;           // [n_hyps][2]

@@ -851,75 +851,87 @@ extern "C" hth_status hth_numeric_derived_bytes(hth_kb kb, uint32_t n_roles, uin
   return HTH_OK;
 }
 
-extern "C" hth_status hth_kb_set_numeric(hth_kb kb, uint32_t n_roles, const int64_t* offsets, const float* values,
-                                         uint64_t n_values, void* derived, size_t derived_bytes, void* stream) {
-  if (!kb) return fail(HTH_E_INVALID, "kb is NULL");
-  std::lock_guard<std::mutex> g(kb->mu);
-  if (n_roles == 0) {
-    kb->n_num = 0;
-    kb->num_off = nullptr;
-    kb->num_val = nullptr;
-    kb->num_chunk_first.assign(1, 0);
-    return HTH_OK;
-  }
-  if (!offsets || (n_values && !values) || !derived) return fail(HTH_E_INVALID, "NULL argument");
-  if (n_roles >= (1u << 16) || n_values >= (1ull << 40)) return fail(HTH_E_RANGE, "too many numeric roles or values");
-  const NumLayout L = num_layout(n_roles, n_values);
-  if (derived_bytes < L.total) return fail(HTH_E_NOMEM, "numeric derived buffer smaller than hth_numeric_derived_bytes");
-  if (reinterpret_cast<uintptr_t>(derived) % 256) return fail(HTH_E_INVALID, "derived buffer must be 256-byte aligned");
-  hipStream_t st = static_cast<hipStream_t>(stream);
+namespace hth {
+
+// Ids in [0, n) and non-decreasing offsets from 0 (string dictionary, patterns).
+__global__ void k_check_ids(const int32_t* __restrict__ ids, uint64_t n, uint32_t n_strings,
+                            uint32_t* __restrict__ flags) {
+  bool bad = false;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256)
+    bad |= ids[i] < 0 || (uint32_t)ids[i] >= n_strings;
+  if (bad) atomicOr(flags, F_TARGET);
+}
+__global__ void k_check_monotone64(const int64_t* __restrict__ o, uint64_t n, uint32_t* __restrict__ flags) {
+  bool bad = false;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256)
+    bad |= (i == 0 && o[0] != 0) || (i > 0 && o[i] < o[i - 1]);
+  if (bad) atomicOr(flags, F_ORDER);
+}
+
+// The tables of a registration of value roles (numeric or string): heavy rows
+// and their chunks in the caller's derived buffer, per-role first chunk and
+// first value on the host.
+struct ValueRoles {
+  uint32_t* rows = nullptr;
+  HeavyChunk* chunks = nullptr;
+  std::vector<uint32_t> chunk_first;
+  std::vector<uint64_t> bounds;
+};
+
+// Validates the chain and monotonicity of offsets [n_roles][N+1] against
+// n_values; `extra` (run on the stream before the check) adds the kind's own
+// value checks into flags.  Then builds the heavy-row tables.
+template <class Extra>
+static hth_status value_roles(hth_kb_s* kb, uint32_t n_roles, const int64_t* offsets, uint64_t n_values,
+                              char* dv, const NumLayout& L, hipStream_t st, Extra&& extra, ValueRoles& out) {
   const uint32_t N = kb->N;
-  char* dv = static_cast<char*>(derived);
   uint32_t* meta = reinterpret_cast<uint32_t*>(dv + L.meta);
   uint32_t* flags = meta;
   uint32_t* count = meta + 1;
   uint32_t* maxdeg = meta + 4;
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, meta, (size_t)4 + n_roles, 0u);
-  // the chain of role ranges: offsets[0][0] = 0, offsets[p][0] = offsets[p-1][N], last = n_values
   std::vector<int64_t> ends(2 * (size_t)n_roles);
   for (uint32_t r = 0; r < n_roles; ++r) {
     HTH_HIP(hipMemcpyAsync(&ends[2 * r], offsets + (size_t)r * (N + 1), 8, hipMemcpyDeviceToHost, st));
     HTH_HIP(hipMemcpyAsync(&ends[2 * r + 1], offsets + (size_t)r * (N + 1) + N, 8, hipMemcpyDeviceToHost, st));
   }
   HTH_HIP(hipStreamSynchronize(st));
-  if (ends[0] != 0) return fail(HTH_E_INVALID, "numeric offsets[0][0] must be 0");
+  if (ends[0] != 0) return fail(HTH_E_INVALID, "value role offsets[0][0] must be 0");
   for (uint32_t r = 1; r < n_roles; ++r)
-    if (ends[2 * r] != ends[2 * r - 1]) return fail(HTH_E_INVALID, "numeric role ranges must follow one another");
+    if (ends[2 * r] != ends[2 * r - 1]) return fail(HTH_E_INVALID, "value role ranges must follow one another");
   if ((uint64_t)ends[2 * (size_t)n_roles - 1] != n_values)
-    return fail(HTH_E_INVALID, "numeric offsets[n_roles-1][N] must equal n_values");
+    return fail(HTH_E_INVALID, "value role offsets[n_roles-1][N] must equal n_values");
   hipLaunchKernelGGL(k_validate_num_rows, dim3((N + 255) / 256, n_roles), dim3(256), 0, st, offsets, N, n_values,
                      maxdeg, flags);
-  if (n_values) {
-    const unsigned gg = (unsigned)std::min<uint64_t>((n_values + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_check_values, dim3(gg), dim3(256), 0, st, values, n_values, flags);
-  }
+  extra(flags);
   HTH_HIP(hipGetLastError());
   uint32_t hflags = 0;
   std::vector<uint32_t> md(n_roles);
   HTH_HIP(hipMemcpyAsync(&hflags, flags, 4, hipMemcpyDeviceToHost, st));
   HTH_HIP(hipMemcpyAsync(md.data(), maxdeg, (size_t)n_roles * 4, hipMemcpyDeviceToHost, st));
   HTH_HIP(hipStreamSynchronize(st));
-  if (hflags & F_NONMONO) return fail(HTH_E_INVALID, "numeric role offsets not monotone or out of range");
-  if (hflags & F_TARGET) return fail(HTH_E_INVALID, "a numeric value is NaN");
+  if (hflags & F_NONMONO) return fail(HTH_E_INVALID, "value role offsets not monotone or out of range");
+  if (hflags & F_TARGET) return fail(HTH_E_INVALID, "a value is NaN or a string id is out of range");
+  if (hflags & F_ORDER) return fail(HTH_E_INVALID, "string or pattern offsets not non-decreasing from 0");
   // heavy rows, sorted by (role, subject), and their chunk tables
-  uint32_t* rows = reinterpret_cast<uint32_t*>(dv + L.heavy);
-  HeavyChunk* chunks_dev = reinterpret_cast<HeavyChunk*>(dv + L.hchunk);
-  std::vector<uint32_t> chunk_first(n_roles + 1, 0);
+  out.rows = reinterpret_cast<uint32_t*>(dv + L.heavy);
+  out.chunks = reinterpret_cast<HeavyChunk*>(dv + L.hchunk);
+  out.chunk_first.assign(n_roles + 1, 0);
   bool any = false;
   for (uint32_t r = 0; r < n_roles; ++r)
     if (md[r] > kb->heavy_min) {
       any = true;
       hipLaunchKernelGGL(k_heavy_rows64, dim3((N + 255) / 256), dim3(256), 0, st, offsets + (size_t)r * (N + 1), N,
-                         kb->heavy_min, r, (uint32_t)L.heavy_cap, count, rows);
+                         kb->heavy_min, r, (uint32_t)L.heavy_cap, count, out.rows);
     }
   HTH_HIP(hipGetLastError());
   if (any) {
     uint32_t nh = 0;
     HTH_HIP(hipMemcpyAsync(&nh, count, 4, hipMemcpyDeviceToHost, st));
     HTH_HIP(hipStreamSynchronize(st));
-    if (nh > L.heavy_cap) return fail(HTH_E_RANGE, "numeric heavy-row table overflow");
+    if (nh > L.heavy_cap) return fail(HTH_E_RANGE, "heavy-row table overflow");
     std::vector<uint32_t> trip(3 * (size_t)nh);
-    HTH_HIP(hipMemcpyAsync(trip.data(), rows, trip.size() * 4, hipMemcpyDeviceToHost, st));
+    HTH_HIP(hipMemcpyAsync(trip.data(), out.rows, trip.size() * 4, hipMemcpyDeviceToHost, st));
     HTH_HIP(hipStreamSynchronize(st));
     std::vector<uint32_t> ord(nh);
     for (uint32_t i = 0; i < nh; ++i) ord[i] = i;
@@ -936,20 +948,116 @@ extern "C" hth_status hth_kb_set_numeric(hth_kb kb, uint32_t n_roles, const int6
       cper[t[0]] += nc;
       for (uint32_t k = 0; k < nc; ++k) chunks.push_back(HeavyChunk{i, k});
     }
-    if (chunks.size() > L.chunk_cap) return fail(HTH_E_RANGE, "numeric heavy chunk table overflow");
-    for (uint32_t r = 0; r < n_roles; ++r) chunk_first[r + 1] = chunk_first[r] + cper[r];
-    HTH_HIP(hipMemcpyAsync(rows, hrows.data(), hrows.size() * 4, hipMemcpyHostToDevice, st));
-    HTH_HIP(hipMemcpyAsync(chunks_dev, chunks.data(), chunks.size() * sizeof(HeavyChunk), hipMemcpyHostToDevice, st));
+    if (chunks.size() > L.chunk_cap) return fail(HTH_E_RANGE, "heavy chunk table overflow");
+    for (uint32_t r = 0; r < n_roles; ++r) out.chunk_first[r + 1] = out.chunk_first[r] + cper[r];
+    HTH_HIP(hipMemcpyAsync(out.rows, hrows.data(), hrows.size() * 4, hipMemcpyHostToDevice, st));
+    HTH_HIP(hipMemcpyAsync(out.chunks, chunks.data(), chunks.size() * sizeof(HeavyChunk), hipMemcpyHostToDevice, st));
     HTH_HIP(hipStreamSynchronize(st));
   }
+  out.bounds.assign(n_roles + 1, 0);
+  for (uint32_t r = 0; r < n_roles; ++r) out.bounds[r + 1] = (uint64_t)ends[2 * r + 1];
+  return HTH_OK;
+}
+
+static unsigned grid_for(uint64_t n) { return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, 65536)); }
+
+}  // namespace hth
+
+extern "C" hth_status hth_kb_set_numeric(hth_kb kb, uint32_t n_roles, const int64_t* offsets, const float* values,
+                                         uint64_t n_values, void* derived, size_t derived_bytes, void* stream) {
+  if (!kb) return fail(HTH_E_INVALID, "kb is NULL");
+  std::lock_guard<std::mutex> g(kb->mu);
+  if (n_roles == 0) {
+    kb->n_num = 0;
+    kb->num_off = nullptr;
+    kb->num_val = nullptr;
+    kb->num_chunk_first.assign(1, 0);
+    kb->num_bounds.assign(1, 0);
+    return HTH_OK;
+  }
+  if (!offsets || (n_values && !values) || !derived) return fail(HTH_E_INVALID, "NULL argument");
+  if (n_roles >= (1u << 16) || n_values >= (1ull << 40)) return fail(HTH_E_RANGE, "too many numeric roles or values");
+  const NumLayout L = num_layout(n_roles, n_values);
+  if (derived_bytes < L.total) return fail(HTH_E_NOMEM, "numeric derived buffer smaller than hth_numeric_derived_bytes");
+  if (reinterpret_cast<uintptr_t>(derived) % 256) return fail(HTH_E_INVALID, "derived buffer must be 256-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  ValueRoles V;
+  hth_status s = value_roles(kb, n_roles, offsets, n_values, static_cast<char*>(derived), L, st, [&](uint32_t* flags) {
+    if (n_values) hipLaunchKernelGGL(k_check_values, dim3(grid_for(n_values)), dim3(256), 0, st, values, n_values, flags);
+  }, V);
+  if (s) return s;
   kb->n_num = n_roles;
   kb->num_off = offsets;
   kb->num_val = values;
-  kb->num_heavy_rows = rows;
-  kb->num_heavy_chunks = chunks_dev;
-  kb->num_chunk_first = chunk_first;
-  kb->num_bounds.assign(n_roles + 1, 0);
-  for (uint32_t r = 0; r < n_roles; ++r) kb->num_bounds[r + 1] = (uint64_t)ends[2 * r + 1];
+  kb->num_heavy_rows = V.rows;
+  kb->num_heavy_chunks = V.chunks;
+  kb->num_chunk_first = V.chunk_first;
+  kb->num_bounds = V.bounds;
+  return HTH_OK;
+}
+
+extern "C" hth_status hth_string_derived_bytes(hth_kb kb, uint32_t n_roles, uint64_t n_values, size_t* bytes) {
+  return hth_numeric_derived_bytes(kb, n_roles, n_values, bytes);
+}
+
+extern "C" hth_status hth_kb_set_strings(hth_kb kb, uint32_t n_roles, const int64_t* offsets, const int32_t* ids,
+                                         uint64_t n_values, uint32_t n_strings, const int64_t* str_offsets,
+                                         const uint8_t* chars, void* derived, size_t derived_bytes, void* stream) {
+  if (!kb) return fail(HTH_E_INVALID, "kb is NULL");
+  std::lock_guard<std::mutex> g(kb->mu);
+  if (n_roles == 0) {
+    kb->n_str = 0;
+    kb->str_off = nullptr;
+    kb->str_ids = nullptr;
+    kb->str_chunk_first.assign(1, 0);
+    kb->str_bounds.assign(1, 0);
+    return HTH_OK;
+  }
+  if (!offsets || (n_values && !ids) || !derived || !str_offsets) return fail(HTH_E_INVALID, "NULL argument");
+  if (n_roles >= (1u << 16) || n_values >= (1ull << 40)) return fail(HTH_E_RANGE, "too many string roles or values");
+  if (n_strings >= (1u << 31)) return fail(HTH_E_RANGE, "n_strings >= 2^31");
+  const NumLayout L = num_layout(n_roles, n_values);
+  if (derived_bytes < L.total) return fail(HTH_E_NOMEM, "string derived buffer smaller than hth_string_derived_bytes");
+  if (reinterpret_cast<uintptr_t>(derived) % 256) return fail(HTH_E_INVALID, "derived buffer must be 256-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  ValueRoles V;
+  hth_status s = value_roles(kb, n_roles, offsets, n_values, static_cast<char*>(derived), L, st, [&](uint32_t* flags) {
+    if (n_values) hipLaunchKernelGGL(k_check_ids, dim3(grid_for(n_values)), dim3(256), 0, st, ids, n_values, n_strings, flags);
+    hipLaunchKernelGGL(k_check_monotone64, dim3(grid_for((uint64_t)n_strings + 1)), dim3(256), 0, st, str_offsets,
+                       (uint64_t)n_strings + 1, flags);
+  }, V);
+  if (s) return s;
+  kb->n_str = n_roles;
+  kb->n_strings = n_strings;
+  kb->str_off = offsets;
+  kb->str_ids = ids;
+  kb->dict_off = str_offsets;
+  kb->dict_chars = chars;
+  kb->str_heavy_rows = V.rows;
+  kb->str_heavy_chunks = V.chunks;
+  kb->str_chunk_first = V.chunk_first;
+  kb->str_bounds = V.bounds;
+  return HTH_OK;
+}
+
+extern "C" hth_status hth_kb_set_patterns(hth_kb kb, uint32_t n_patterns, const int64_t* offsets, const uint8_t* chars,
+                                          void* stream) {
+  if (!kb) return fail(HTH_E_INVALID, "kb is NULL");
+  if (n_patterns && !offsets) return fail(HTH_E_INVALID, "NULL argument");
+  std::lock_guard<std::mutex> g(kb->mu);
+  if (n_patterns) {   // a short table: its offsets are checked on the host
+    std::vector<int64_t> o((size_t)n_patterns + 1);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HTH_HIP(hipMemcpyAsync(o.data(), offsets, o.size() * 8, hipMemcpyDeviceToHost, st));
+    HTH_HIP(hipStreamSynchronize(st));
+    if (o[0] != 0) return fail(HTH_E_INVALID, "pattern offsets[0] must be 0");
+    for (size_t i = 1; i < o.size(); ++i)
+      if (o[i] < o[i - 1]) return fail(HTH_E_INVALID, "pattern offsets must be non-decreasing");
+    if (o.back() > 0 && !chars) return fail(HTH_E_INVALID, "pattern chars are NULL");
+  }
+  kb->n_patterns = n_patterns;
+  kb->pat_off = n_patterns ? offsets : nullptr;
+  kb->pat_chars = n_patterns ? chars : nullptr;
   return HTH_OK;
 }
 

@@ -45,6 +45,18 @@ struct hth_kb_s {
   hth::HeavyChunk* num_heavy_chunks = nullptr;
   std::vector<uint32_t> num_chunk_first;   // [n_num+1] first chunk of each role
   std::vector<uint64_t> num_bounds;        // [n_num+1] first value of each role
+  // string concrete roles (hth_kb_set_strings) and CONTAIN patterns
+  uint32_t n_str = 0, n_strings = 0, n_patterns = 0;
+  const int64_t* str_off = nullptr;
+  const int32_t* str_ids = nullptr;
+  const int64_t* dict_off = nullptr;
+  const uint8_t* dict_chars = nullptr;
+  const int64_t* pat_off = nullptr;
+  const uint8_t* pat_chars = nullptr;
+  uint32_t* str_heavy_rows = nullptr;
+  hth::HeavyChunk* str_heavy_chunks = nullptr;
+  std::vector<uint32_t> str_chunk_first;   // [n_str+1]
+  std::vector<uint64_t> str_bounds;        // [n_str+1]
   const uint64_t* pos = nullptr;
   const uint64_t* neg = nullptr;
   const uint64_t* sets = nullptr;      // caller's set table (hth_kb_set_sets)

@@ -141,7 +141,8 @@ class Dag {
 inline bool is_role(uint8_t op) { return op >= HTH_EXISTS && op <= HTH_EXACTLY; }
 inline bool is_column(uint8_t op) { return op == HTH_DATA_GE || op == HTH_DATA_LE || op == HTH_DATA_EQ; }
 inline bool is_numeric(uint8_t op) { return op == HTH_NUM_GE || op == HTH_NUM_LE || op == HTH_NUM_EQ; }
-inline bool is_data(uint8_t op) { return is_column(op) || is_numeric(op); }
+inline bool is_string(uint8_t op) { return op == HTH_STR_EQ || op == HTH_STR_CONTAINS; }
+inline bool is_data(uint8_t op) { return is_column(op) || is_numeric(op) || is_string(op); }
 inline bool is_leaflike(uint8_t op) {
   return op == HTH_ATOM || op == HTH_SET || is_data(op) || is_role(op);
 }
@@ -225,6 +226,18 @@ struct Compiler {
           map[i] = dag.leaf(x.op, 0, x.arg, bits);
           break;
         }
+        case HTH_STR_EQ:
+        case HTH_STR_CONTAINS:
+          if (x.arg >= kb.n_str) return bad(HTH_E_RANGE, "string concrete role id outside the registered roles");
+          if (x.op == HTH_STR_EQ && x.q.n == 0xFFFFFFFFu) {   // a string absent from the dictionary
+            map[i] = dag.bot();
+            break;
+          }
+          if (x.op == HTH_STR_EQ && x.q.n >= kb.n_strings) return bad(HTH_E_RANGE, "string id out of range");
+          if (x.op == HTH_STR_CONTAINS && x.q.n >= kb.n_patterns)
+            return bad(HTH_E_RANGE, "pattern id outside the registered patterns");
+          map[i] = dag.leaf(x.op, 0, x.arg, x.q.n);
+          break;
         default:
           return bad(HTH_E_INVALID, "unknown op");
       }
@@ -343,6 +356,14 @@ struct Compiler {
         std::memcpy(&t.t, &n.q, 4);
         t.out_row = row[v];
         P.num.push_back(t);
+      } else if (is_string(n.op)) {
+        row[v] = new_row();
+        StrTask t{};
+        t.role = n.arg;
+        t.kind = n.op == HTH_STR_CONTAINS ? 1 : 0;
+        std::memcpy(&t.q, &n.q, 4);
+        t.out_row = row[v];
+        P.str.push_back(t);
       } else if (is_role(n.op)) {
         row[v] = new_row();
         max_level = std::max(max_level, height[v]);
@@ -489,6 +510,19 @@ struct Compiler {
       P.num_heavy_chunks = kb.num_heavy_chunks;
       P.num_chunk_first = kb.num_chunk_first;
       P.num_bounds = kb.num_bounds;
+    }
+    if (!P.str.empty()) {
+      P.str_off = kb.str_off;
+      P.str_ids = kb.str_ids;
+      P.str_heavy_rows = kb.str_heavy_rows;
+      P.str_heavy_chunks = kb.str_heavy_chunks;
+      P.str_chunk_first = kb.str_chunk_first;
+      P.str_bounds = kb.str_bounds;
+      P.dict_off = kb.dict_off;
+      P.dict_chars = kb.dict_chars;
+      P.pat_off = kb.pat_off;
+      P.pat_chars = kb.pat_chars;
+      P.n_strings = kb.n_strings;
     }
     P.n_canonical = (uint32_t)nv;
     return HTH_OK;

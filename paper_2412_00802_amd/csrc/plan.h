@@ -36,6 +36,18 @@ struct Plan {
   const HeavyChunk* num_heavy_chunks = nullptr;
   std::vector<uint32_t> num_chunk_first;
   std::vector<uint64_t> num_bounds;        // [P+1] first value of each numeric role
+  std::vector<StrTask> str;                // restrictions on string concrete roles
+  const int64_t* str_off = nullptr;
+  const int32_t* str_ids = nullptr;
+  const uint32_t* str_heavy_rows = nullptr;
+  const HeavyChunk* str_heavy_chunks = nullptr;
+  std::vector<uint32_t> str_chunk_first;
+  std::vector<uint64_t> str_bounds;
+  const int64_t* dict_off = nullptr;
+  const uint8_t* dict_chars = nullptr;
+  const int64_t* pat_off = nullptr;
+  const uint8_t* pat_chars = nullptr;
+  uint32_t n_strings = 0;
   std::vector<uint32_t> code;
   std::vector<PlanLevel> levels;
   std::vector<RegionTask> roots;

@@ -24,7 +24,7 @@ STATUS = {0: "HTH_OK", -1: "HTH_E_INVALID", -2: "HTH_E_RANGE", -3: "HTH_E_NOMEM"
 
 OPS = {"top": 0, "bot": 1, "atom": 2, "not": 3, "and": 4, "or": 5, "exists": 6, "forall": 7,
        "atleast": 8, "atmost": 9, "exactly": 10, "dge": 11, "dle": 12, "set": 13,
-       "deq": 14, "nge": 15, "nle": 16, "neq": 17}
+       "deq": 14, "nge": 15, "nle": 16, "neq": 17, "sequal": 18, "scontains": 19}
 
 NODE_DTYPE = np.dtype([("op", np.uint8), ("inv", np.uint8), ("arity", np.uint16),
                        ("arg", np.uint32), ("child", np.uint32), ("q", np.uint32)])
@@ -38,7 +38,7 @@ EXPORTED = ["hth_kb_derived_bytes", "hth_kb_create", "hth_kb_set_examples", "hth
             "hth_batch_workspace_bytes", "hth_head_score", "hth_kb_get_tuning", "hth_kb_set_tuning",
             "hth_kb_set_sets", "hth_eval_batch_sets", "hth_densify_delta", "hth_plan_create",
             "hth_plan_upload", "hth_plan_launch", "hth_plan_destroy", "hth_numeric_derived_bytes",
-            "hth_kb_set_numeric"]
+            "hth_kb_set_numeric", "hth_string_derived_bytes", "hth_kb_set_strings", "hth_kb_set_patterns"]
 
 
 class HthError(RuntimeError):
@@ -100,6 +100,9 @@ def lib() -> ctypes.CDLL:
             "hth_kb_set_sets": [P, P, U32],
             "hth_numeric_derived_bytes": [P, U32, U64, ctypes.POINTER(S)],
             "hth_kb_set_numeric": [P, U32, P, P, U64, P, S, P],
+            "hth_string_derived_bytes": [P, U32, U64, ctypes.POINTER(S)],
+            "hth_kb_set_strings": [P, U32, P, P, U64, U32, P, P, P, S, P],
+            "hth_kb_set_patterns": [P, U32, P, P, P],
             "hth_plan_create": [P, P, P, U32, P, U32, ctypes.POINTER(P), ctypes.POINTER(S)],
             "hth_plan_upload": [P, P, S, P],
             "hth_plan_launch": [P, P, S, P, P],
@@ -207,6 +210,34 @@ def hth_kb_set_numeric(kb, n_roles: int, offsets, values, n_values: int, derived
     _check(lib().hth_kb_set_numeric(kb, n_roles, _ptr(offsets) if n_roles else None,
                                     _ptr(values) if n_values else None, n_values,
                                     _ptr(derived) if n_roles else None, derived_bytes, _stream(stream)))
+
+
+def hth_string_derived_bytes(kb, n_roles: int, n_values: int) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().hth_string_derived_bytes(kb, n_roles, n_values, ctypes.byref(out)))
+    return out.value
+
+
+def hth_kb_set_strings(kb, n_roles: int, offsets, ids, n_values: int, n_strings: int, str_offsets, chars,
+                       derived, derived_bytes: int, stream=None) -> None:
+    """Register string concrete roles (device int64 offsets [n_roles][N+1],
+    int32 dictionary ids, and the dictionary as int64 offsets + bytes)."""
+    _check(lib().hth_kb_set_strings(kb, n_roles, _ptr(offsets) if n_roles else None,
+                                    _ptr(ids) if n_values else None, n_values, n_strings,
+                                    _ptr(str_offsets) if n_roles else None, _ptr(chars) if n_roles else None,
+                                    _ptr(derived) if n_roles else None, derived_bytes, _stream(stream)))
+
+
+def hth_kb_set_patterns(kb, n_patterns: int, offsets, chars, stream=None) -> None:
+    _check(lib().hth_kb_set_patterns(kb, n_patterns, _ptr(offsets) if n_patterns else None,
+                                     _ptr(chars) if n_patterns else None, _stream(stream)))
+
+
+def _concat_bytes(items):
+    offs = np.zeros(len(items) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum([len(b) for b in items])
+    chars = np.frombuffer(b"".join(items), dtype=np.uint8) if offs[-1] else np.zeros(0, np.uint8)
+    return offs, chars
 
 
 def hth_kb_max_degree(kb, role: int, inv: int) -> int:
@@ -411,6 +442,12 @@ def encode(h, nodes: list, children: list) -> int:
         nodes.append((code, inv, 0, r, ci, k))
     elif op in ("dge", "dle", "deq", "nge", "nle", "neq"):
         nodes.append((code, 0, 0, h[1], 0, _f32_bits(h[2])))
+    elif op in ("sequal", "scontains"):
+        # the query as an id: a dictionary string id (-1: absent) or a pattern
+        # id; Engine.intern turns the strings of a hypothesis into these
+        if not isinstance(h[2], (int, np.integer)):
+            raise ValueError("string restrictions need ids here: use Engine.intern first")
+        nodes.append((code, 0, 0, h[1], 0, int(h[2]) & 0xFFFFFFFF))
     else:
         raise ValueError(op)
     return len(nodes) - 1
@@ -545,6 +582,24 @@ class Engine:
             nb = hth_numeric_derived_bytes(self.handle, P, V)
             self.num_derived = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
             hth_kb_set_numeric(self.handle, P, self.num_offsets, self.num_values, V, self.num_derived, nb)
+        self._str_id = None
+        so = getattr(kb, "str_offsets", None)
+        if so is not None and len(so):
+            # string concrete roles: assertions hold ids into the dictionary
+            strings = list(kb.strings)
+            self._str_id = {s: i for i, s in enumerate(strings)}
+            self.str_offsets = torch.from_numpy(np.ascontiguousarray(so, dtype=np.int64)).to(dev)
+            ids = np.ascontiguousarray(kb.str_ids, dtype=np.int32)
+            self.str_ids = torch.from_numpy(ids if ids.size else np.zeros(1, np.int32)).to(dev)
+            doff, dchars = _concat_bytes(strings)
+            self.dict_offsets = torch.from_numpy(doff).to(dev)
+            self.dict_chars = torch.from_numpy(dchars.copy() if dchars.size else np.zeros(1, np.uint8)).to(dev)
+            Q, V = int(so.shape[0]), int(ids.size)
+            nb = hth_string_derived_bytes(self.handle, Q, V)
+            self.str_derived = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
+            hth_kb_set_strings(self.handle, Q, self.str_offsets, self.str_ids, V, len(strings), self.dict_offsets,
+                               self.dict_chars, self.str_derived, nb)
+            self._patterns: dict = {}
         self.ws = None
         self.ws_bytes = 0
         self.reserve(max_nodes, max_hyps)
@@ -569,11 +624,34 @@ class Engine:
 
     # -- evaluation ---------------------------------------------------------
 
+    def intern(self, h):
+        """Hypothesis h with its string queries as ids: EQUAL strings as
+        dictionary ids (-1 when absent), CONTAIN patterns as ids of the
+        registered pattern table (new patterns are added and the table is
+        registered again)."""
+        if self._str_id is None or not isinstance(h, tuple):
+            return h
+        op = h[0]
+        if op == "sequal" and isinstance(h[2], (bytes, bytearray)):
+            return ("sequal", h[1], self._str_id.get(bytes(h[2]), -1))
+        if op == "scontains" and isinstance(h[2], (bytes, bytearray)):
+            pat = bytes(h[2])
+            if pat not in self._patterns:
+                self._patterns[pat] = len(self._patterns)
+                pats = sorted(self._patterns, key=self._patterns.get)
+                poff, pchars = _concat_bytes(pats)
+                self.pat_offsets = self.torch.from_numpy(poff).to(self.device)
+                self.pat_chars = self.torch.from_numpy(pchars.copy() if pchars.size else np.zeros(1, np.uint8)).to(
+                    self.device)
+                hth_kb_set_patterns(self.handle, len(pats), self.pat_offsets, self.pat_chars)
+            return ("scontains", h[1], self._patterns[pat])
+        return tuple(self.intern(c) if isinstance(c, tuple) else c for c in h)
+
     def eval_one(self, h, instances: bool = False, counts=None, stream=None):
         """Coverage (and optionally the instance bits) of one hypothesis.
         With `counts` given (a device uint32 [2] view) nothing is synchronised."""
         torch = self.torch
-        nodes, ch = encode_one(h)
+        nodes, ch = encode_one(self.intern(h))
         self.reserve(nodes.shape[0], 1)
         out = counts if counts is not None else torch.empty(2, dtype=torch.int32, device=self.device)
         inst = torch.empty(self.S, dtype=torch.int64, device=self.device) if instances else None
@@ -610,7 +688,7 @@ class Engine:
         for a in range(0, H, chunk):
             b = min(H, a + chunk)
             if encoded is None:
-                nodes, offs, ch = encode_batch(hyps[a:b])
+                nodes, offs, ch = encode_batch([self.intern(h) for h in hyps[a:b]] if self._str_id else hyps[a:b])
             else:
                 nodes, offs, ch = slice_encoded(encoded, a, b)
             self.ensure_workspace(hth_batch_workspace_bytes(self.handle, nodes, offs, ch))

@@ -733,3 +733,71 @@ def test_numeric_registration_errors(gpu):
     hthedl.hth_kb_set_numeric(eng.handle, 0, None, None, 0, None, 0)
     with pytest.raises(hthedl.HthError):
         eng.eval_plain([("nge", 0, 0.0)])
+
+
+def string_kb(n=40000, seed=31):
+    """String concrete roles over a 3,000-word dictionary, with one subject of
+    role 1 holding 3,000 values and one holding 1,500 (heavy at 1,024)."""
+    cfg = synth.small_config(n=n, n_concepts=20, n_roles=2, cap=30, n_pos=n // 10, n_neg=n // 12,
+                             seed_index=seed)
+    kb = synth.make_kb(cfg)
+    offs, ids, strings = synth.string_roles(n, 2, seed=seed, n_strings=3000)
+    rng = np.random.default_rng(seed)
+    rows = [list(ids[offs[1, x]:offs[1, x + 1]]) for x in range(n)]
+    rows[123] = list(rng.integers(0, 3000, size=1500))
+    rows[n - 2] = list(rng.integers(0, 3000, size=3000))
+    base = offs[1, 0]
+    new1 = np.zeros(n + 1, np.int64)
+    new1[0] = base
+    new1[1:] = base + np.cumsum([len(r) for r in rows])
+    offs = offs.copy()
+    offs[1] = new1
+    ids = np.concatenate([ids[: offs[0, -1]], np.asarray([v for r in rows for v in r], np.int32)]).astype(np.int32)
+    return synth.with_string_roles(kb, offs, ids, strings)
+
+
+@pytest.mark.parametrize("heavy_min", [None, 1024])
+def test_string_concrete_roles(monkeypatch, heavy_min):
+    """EQUAL and CONTAIN over string concrete roles equal the oracle (plain,
+    batch, instance bits), with absent strings, the empty pattern, patterns
+    longer than any string and heavy rows."""
+    if heavy_min is not None:
+        monkeypatch.setenv("HTHEDL_HEAVY_MIN", str(heavy_min))
+    kb = string_kb()
+    hs = synth.make_string_hypotheses(kb, 300, seed=7)
+    hs += [("sequal", 0, kb.strings[0]), ("sequal", 1, b"not-a-word"), ("scontains", 1, b""),
+           ("scontains", 0, b"abcdefabcdefabcdef"), ("scontains", 1, kb.strings[5]),
+           ("not", ("scontains", 0, b"a")), ("forall", 1, 0, ("scontains", 1, b"ab")),
+           ("and", ("scontains", 0, b"fe"), ("sequal", 1, kb.strings[9]))]
+    eng = check(kb, hs, label=f"string roles, heavy {heavy_min}")
+    o = Oracle(kb)
+    for h in (("scontains", 1, b"cd"), ("sequal", 1, kb.strings[3])):
+        (p, q), bits = eng.eval_one(h, instances=True)
+        np.testing.assert_array_equal(bits, o.ext_bits(h))
+
+
+def test_string_registration_errors(gpu):
+    torch = gpu
+    kb = string_kb(n=4000)
+    eng = hthedl.Engine(kb)
+    Q, V = kb.str_offsets.shape[0], int(kb.str_ids.shape[0])
+    nb = hthedl.hth_string_derived_bytes(eng.handle, Q, V)
+    der = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    off = torch.from_numpy(kb.str_offsets.copy()).cuda()
+    bad = kb.str_ids.copy()
+    bad[7] = 3000                                             # one past the dictionary
+    with pytest.raises(hthedl.HthError, match="out of range"):
+        hthedl.hth_kb_set_strings(eng.handle, Q, off, torch.from_numpy(bad).cuda(), V, 3000,
+                                  eng.dict_offsets, eng.dict_chars, der, nb)
+    doff = eng.dict_offsets.clone()
+    doff[10] = doff[9] - 1                                    # a dictionary entry that runs backwards
+    with pytest.raises(hthedl.HthError, match="non-decreasing"):
+        hthedl.hth_kb_set_strings(eng.handle, Q, off, eng.str_ids, V, 3000, doff, eng.dict_chars, der, nb)
+    pat = torch.tensor([0, 3, 2], dtype=torch.int64, device="cuda")
+    with pytest.raises(hthedl.HthError, match="non-decreasing"):
+        hthedl.hth_kb_set_patterns(eng.handle, 2, pat, eng.dict_chars)
+    # the registration in place still answers
+    h = ("scontains", 0, b"ab")
+    assert eng.eval_plain([h]).tolist() == [list(Oracle(kb).coverage(h))]
+    with pytest.raises(hthedl.HthError, match="string concrete role id"):
+        eng.eval_plain([("sequal", 2, kb.strings[0])])
