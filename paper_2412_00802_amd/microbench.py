@@ -8,7 +8,10 @@ with either a single subject of degree E ("single subject") or E subjects of
 degree 1 ("unique subject"), E up to 10M, evaluated as an existential and as
 an at-least-2 restriction.  M3 (Table 8's shape): one numeric concrete role
 with the same two layouts and every value 1.0, under MIN at 0.5 (every
-subject decided by its first value) and at 2.0 (every value read).  Each operation is compiled once (hth_plan_create),
+subject decided by its first value) and at 2.0 (every value read).  M4
+(Table 8's string rows): one string concrete role in the same two layouts,
+every value the same 8-byte word of a 1,000-word dictionary, under EQUAL and
+CONTAIN with a query that matches and one that does not.  Each operation is compiled once (hth_plan_create),
 uploaded once and launched repeatedly; the time is the device time per launch
 (HIP events on the launch stream).  Prints one JSON line per case.
 """
@@ -145,16 +148,42 @@ def main():
                 emit({"case": f"M3 numeric {shape}, {op}", "assertions": e, "individuals": n,
                       "us_per_op": round(ms * 1e3, 2), "GBps": round(byts / (ms * 1e-3) / 1e9, 1)})
             eng.close()
+    # M4: string concrete role, single subject and unique subject, one repeated value
+    words = [b"w%07d" % i for i in range(1000)]
+    for e in edges:
+        n = max(1_000_000, 2 * e)
+        for shape in ("single subject", "unique subject"):
+            deg = np.zeros(n, dtype=np.int64)
+            if shape == "single subject":
+                deg[0] = e
+            else:
+                deg[np.sort(rng.choice(n, size=e, replace=False))] = 1
+            offs = np.zeros((1, n + 1), dtype=np.int64)
+            np.cumsum(deg, out=offs[0, 1:])
+            kb = synth.with_string_roles(make_kb(n, 1, np.zeros(0, np.int64), np.zeros(0, np.int32), seed=4),
+                                         offs, np.full(e, 7, dtype=np.int32), words)
+            eng = hthedl.Engine(kb, max_nodes=16, max_hyps=1)
+            w8 = 8 * ((n + 63) // 64)
+            for op, h in (("EQUAL, matching", ("sequal", 0, words[7])),
+                          ("EQUAL, no match", ("sequal", 0, words[8])),
+                          ("CONTAIN, matching", ("scontains", 0, b"0007")),
+                          ("CONTAIN, no match", ("scontains", 0, b"0008"))):
+                ms = time_op(eng, eng.intern(h), args.reps)
+                byts = 4.0 * e + 8.0 * (n + 1) + 2 * w8
+                emit({"case": f"M4 string {shape}, {op}", "assertions": e, "individuals": n,
+                      "us_per_op": round(ms * 1e3, 2), "GBps": round(byts / (ms * 1e-3) / 1e9, 1)})
+            eng.close()
     if args.markdown:
         cmd = "python -m paper_2412_00802_amd.microbench " + " ".join(sys.argv[1:])
         lines = ["# Per-operation microbenchmarks (M1: five-concept conjunction; M2: one role, M3: one "
-                 "numeric concrete role, single subject / unique subject)", "", "Command:", "", "    " + cmd, "",
+                 "numeric and M4: one string concrete role, single subject / unique subject)", "", "Command:", "",
+                 "    " + cmd, "",
                  "Device time per launch of a compiled one-hypothesis plan (all of its kernels: count "
                  "clearing, the operation, coverage), HIP events around back-to-back launches.  GB/s "
                  "counts algorithmic bytes: M1 the five rows read, the example rows and the output; M2 "
                  "the assertions' targets (4 B each), the row offsets (4 B per individual) and two bit "
-                 "rows; M3 the values (4 B each), the int64 offsets (8 B per individual) and two bit "
-                 "rows.", "",
+                 "rows; M3 and M4 the values or string ids (4 B each), the int64 offsets (8 B per "
+                 "individual) and two bit rows.", "",
                  "| case | individuals | assertions | us per op | GB/s |", "|---|---|---|---|---|"]
         for r in results:
             lines.append(f"| {r['case']} | {r['individuals']:,} | {r.get('assertions', '')} | "
