@@ -801,3 +801,27 @@ def test_string_registration_errors(gpu):
     assert eng.eval_plain([h]).tolist() == [list(Oracle(kb).coverage(h))]
     with pytest.raises(hthedl.HthError, match="string concrete role id"):
         eng.eval_plain([("sequal", 2, kb.strings[0])])
+
+
+def test_value_roles_in_compiled_plans():
+    """Numeric and string restrictions in a compiled plan (their tasks, heavy
+    rows and CONTAIN id sets in the plan's workspace), launched twice."""
+    import torch
+    kb = string_kb(n=30000)
+    offs, vals = synth.numeric_roles(kb.n, 2, seed=12)
+    kb = synth.with_numeric_roles(kb, offs, vals)
+    hs = synth.make_string_hypotheses(kb, 60, seed=3) + synth.make_numeric_hypotheses(kb, 60, seed=4)
+    want = Oracle(kb).coverages(hs)
+    eng = hthedl.Engine(kb)
+    nodes, offs_, ch = hthedl.encode_batch([eng.intern(h) for h in hs])
+    plan, nb = hthedl.hth_plan_create(eng.handle, nodes, offs_, ch)
+    try:
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        hthedl.hth_plan_upload(plan, ws, nb)
+        for _ in range(2):
+            counts = torch.full((len(hs), 2), 7, dtype=torch.int32, device="cuda")
+            hthedl.hth_plan_launch(plan, ws, nb, counts)
+            torch.cuda.synchronize()
+            assert np.array_equal(counts.cpu().numpy().view(np.uint32), want)
+    finally:
+        hthedl.hth_plan_destroy(plan)

@@ -82,6 +82,9 @@ def test_features_and_densify(torch):
     hyps = synth.make_hypotheses(cfg, kb, count=200, depth=5)
     hyps += synth.make_sized_hypotheses(cfg, kb, count=200)
     hyps += [("and",), ("or", ("atom", 1)), ("exactly", 3, 2, 1, ("dle", 1, -0.5)), ("top",)]
+    # EXACT on columns and numeric concrete roles hash like the other value leaves
+    hyps += [("deq", 2, 0.25), ("nge", 0, -1.5), ("and", ("nle", 1, 2.0), ("neq", 0, 0.0)),
+             ("exists", 1, 0, ("nge", 3, 1.0))]
     fb, nodes = _feature_batch(torch, hyps)
     torch.cuda.synchronize()
     assert int(fb.bad.item()) == 0
