@@ -89,45 +89,46 @@ __device__ __forceinline__ bool num_pass(float v, uint32_t cmp, float t) {
 // walk stops once every subject with values left has found one.  Rows above
 // the heavy-row threshold are left to value_heavy (their bits here are 0).
 constexpr int kNumChunks = 8;
+// off: the role's 32-bit offsets relative to vals, its first value.
 template <typename V, class Pass>
-__device__ __forceinline__ void value_walk(const DevKB& kb, const int64_t* __restrict__ off,
+__device__ __forceinline__ void value_walk(const DevKB& kb, const uint32_t* __restrict__ off,
                                            const V* __restrict__ vals, Pass pass, uint64_t* __restrict__ out,
                                            uint32_t b, uint32_t bpt) {
   const int lane = threadIdx.x & 63;
   for (uint32_t w = b * 4 + (threadIdx.x >> 6); w < kb.W; w += bpt * 4) {
     const uint32_t x = w * 64 + lane;
     const bool in = x < kb.N;
-    const int64_t olo = off[in ? x : kb.N];
-    int64_t ohi = in ? off[x + 1] : olo;
-    const bool heavy = (uint64_t)(ohi - olo) > kb.heavy_min;
+    const uint32_t olo = off[in ? x : kb.N];
+    uint32_t ohi = in ? off[x + 1] : olo;
+    const bool heavy = ohi - olo > kb.heavy_min;
     if (heavy) ohi = olo;
-    const int64_t ee = __shfl((long long)ohi, 63, 64);
-    int64_t i0 = __shfl((long long)olo, 0, 64);
+    const uint32_t ee = (uint32_t)__shfl((int)ohi, 63, 64);
+    uint32_t i0 = (uint32_t)__shfl((int)olo, 0, 64);
     bool hit = false;
     while (i0 < ee) {
       V v[kNumChunks];
 #pragma unroll
       for (int c = 0; c < kNumChunks; ++c) {
-        const int64_t e = i0 + 64 * c + lane;
+        const uint64_t e = (uint64_t)i0 + 64 * c + lane;
         v[c] = e < ee ? vals[e] : V(0);
       }
 #pragma unroll
       for (int c = 0; c < kNumChunks; ++c) {
-        const int64_t base = i0 + 64 * c;
+        const uint64_t base = (uint64_t)i0 + 64 * c;
         const uint64_t m = __ballot(base + lane < ee && pass(v[c]));
-        const int64_t a = olo > base ? min(olo - base, (int64_t)64) : 0;
-        const int64_t bb = ohi > base ? min(ohi - base, (int64_t)64) : 0;
+        const uint64_t a = olo > base ? min((uint64_t)olo - base, (uint64_t)64) : 0;
+        const uint64_t bb = ohi > base ? min((uint64_t)ohi - base, (uint64_t)64) : 0;
         if (bb > a) {
           const uint64_t rm = (bb - a == 64) ? ~0ull : (((1ull << (bb - a)) - 1ull) << a);
           hit |= (m & rm) != 0;
         }
       }
-      const int64_t step = 64 * kNumChunks;
+      const uint64_t step = 64 * kNumChunks;
       const uint64_t pend = __ballot(in && !hit && ohi > i0 + step);
       if (!pend) break;
       const int l = __ffsll((unsigned long long)pend) - 1;
-      const int64_t nxt = __shfl((long long)olo, l, 64);
-      i0 = max(i0 + step, nxt);
+      const uint32_t nxt = (uint32_t)__shfl((int)olo, l, 64);
+      i0 = (uint32_t)max((uint64_t)i0 + step, (uint64_t)nxt);
     }
     const uint64_t word = __ballot(in && !heavy && hit);
     if (lane == 0) out[w] = word;
@@ -139,16 +140,16 @@ __device__ __forceinline__ void value_walk(const DevKB& kb, const int64_t* __res
 // only ever gains bits, so blocks need no ordering among themselves).  Chunk
 // blocks that find the bit already set skip the atomic.
 template <typename V, class Pass>
-__device__ __forceinline__ void value_heavy(const DevKB& kb, const int64_t* __restrict__ off,
+__device__ __forceinline__ void value_heavy(const DevKB& kb, const uint32_t* __restrict__ off,
                                             const V* __restrict__ vals, Pass pass, uint64_t* __restrict__ out,
                                             uint32_t x, uint32_t k) {
   __shared__ uint32_t s_any[4];
-  const int64_t e0 = off[x] + (int64_t)k * kHeavyChunk;
-  const int64_t e1 = min(off[x + 1], e0 + (int64_t)kHeavyChunk);
+  const uint32_t e0 = off[x] + k * kHeavyChunk;
+  const uint32_t e1 = min(off[x + 1], e0 + kHeavyChunk);
   bool any = false;
 #pragma unroll
   for (uint32_t j = 0; j < kHeavyChunk / 256; ++j) {
-    const int64_t e = e0 + j * 256 + threadIdx.x;
+    const uint32_t e = e0 + j * 256 + threadIdx.x;
     if (e < e1) any |= pass(vals[e]);
   }
   const uint64_t m = __ballot(any);
@@ -176,7 +177,8 @@ __device__ __forceinline__ uint32_t value_task(const Task* __restrict__ tasks, u
 __global__ void __launch_bounds__(256)
 k_numrole(DevKB kb, const NumTask* __restrict__ tasks, uint32_t bpt) {
   const NumTask T = tasks[blockIdx.x / bpt];
-  value_walk<float>(kb, kb.num_off + (size_t)T.role * (kb.N + 1), kb.num_val,
+  const float* vals = kb.num_val + ((uint64_t)T.base_hi << 32 | T.base_lo);
+  value_walk<float>(kb, kb.num_roff + (size_t)T.role * (kb.N + 1), vals,
                     [&](float v) { return num_pass(v, T.cmp, T.t); }, out_ptr(kb, T.out_row), blockIdx.x % bpt, bpt);
 }
 
@@ -185,7 +187,8 @@ k_numrole_heavy(DevKB kb, const NumTask* __restrict__ tasks, uint32_t n_tasks, u
   const uint32_t b = b0 + blockIdx.x;
   const NumTask T = tasks[value_task(tasks, n_tasks, b)];
   const HeavyChunk c = kb.num_heavy_chunks[T.hc0 + (b - T.h_first)];
-  value_heavy<float>(kb, kb.num_off + (size_t)T.role * (kb.N + 1), kb.num_val,
+  const float* vals = kb.num_val + ((uint64_t)T.base_hi << 32 | T.base_lo);
+  value_heavy<float>(kb, kb.num_roff + (size_t)T.role * (kb.N + 1), vals,
                      [&](float v) { return num_pass(v, T.cmp, T.t); }, out_ptr(kb, T.out_row),
                      kb.num_heavy_rows[c.hrow], c.k);
 }
@@ -218,14 +221,15 @@ k_contains(DevKB kb, const StrTask* __restrict__ tasks, uint32_t tiles) {
 __global__ void __launch_bounds__(256)
 k_strrole(DevKB kb, const StrTask* __restrict__ tasks, uint32_t bpt) {
   const StrTask T = tasks[blockIdx.x / bpt];
-  const int64_t* off = kb.str_off + (size_t)T.role * (kb.N + 1);
+  const uint32_t* off = kb.str_roff + (size_t)T.role * (kb.N + 1);
+  const int32_t* ids = kb.str_ids + ((uint64_t)T.base_hi << 32 | T.base_lo);
   uint64_t* out = out_ptr(kb, T.out_row);
   if (T.kind == 0) {
-    value_walk<int32_t>(kb, off, kb.str_ids, [&](int32_t id) { return (uint32_t)id == T.q; }, out,
+    value_walk<int32_t>(kb, off, ids, [&](int32_t id) { return (uint32_t)id == T.q; }, out,
                         blockIdx.x % bpt, bpt);
   } else {
     const uint64_t* set = kb.idsets + T.set_word;
-    value_walk<int32_t>(kb, off, kb.str_ids, [&](int32_t id) { return (set[(uint32_t)id >> 6] >> (id & 63)) & 1; },
+    value_walk<int32_t>(kb, off, ids, [&](int32_t id) { return (set[(uint32_t)id >> 6] >> (id & 63)) & 1; },
                         out, blockIdx.x % bpt, bpt);
   }
 }
@@ -235,14 +239,15 @@ k_strrole_heavy(DevKB kb, const StrTask* __restrict__ tasks, uint32_t n_tasks, u
   const uint32_t b = b0 + blockIdx.x;
   const StrTask T = tasks[value_task(tasks, n_tasks, b)];
   const HeavyChunk c = kb.str_heavy_chunks[T.hc0 + (b - T.h_first)];
-  const int64_t* off = kb.str_off + (size_t)T.role * (kb.N + 1);
+  const uint32_t* off = kb.str_roff + (size_t)T.role * (kb.N + 1);
+  const int32_t* ids = kb.str_ids + ((uint64_t)T.base_hi << 32 | T.base_lo);
   const uint32_t x = kb.str_heavy_rows[c.hrow];
   uint64_t* out = out_ptr(kb, T.out_row);
   if (T.kind == 0) {
-    value_heavy<int32_t>(kb, off, kb.str_ids, [&](int32_t id) { return (uint32_t)id == T.q; }, out, x, c.k);
+    value_heavy<int32_t>(kb, off, ids, [&](int32_t id) { return (uint32_t)id == T.q; }, out, x, c.k);
   } else {
     const uint64_t* set = kb.idsets + T.set_word;
-    value_heavy<int32_t>(kb, off, kb.str_ids, [&](int32_t id) { return (set[(uint32_t)id >> 6] >> (id & 63)) & 1; },
+    value_heavy<int32_t>(kb, off, ids, [&](int32_t id) { return (set[(uint32_t)id >> 6] >> (id & 63)) & 1; },
                          out, x, c.k);
   }
 }
@@ -1149,6 +1154,8 @@ void prepare(const hth_kb_s& kb, Plan&& plan, uint32_t n_hyps, Prepared& X) {
   }
   std::vector<NumTask> num(P.num);
   for (NumTask& t : num) {
+    t.base_lo = (uint32_t)P.num_bounds[t.role];
+    t.base_hi = (uint32_t)(P.num_bounds[t.role] >> 32);
     t.h_first = (uint32_t)X.n_num_blocks;
     t.hc0 = P.num_chunk_first[t.role];
     X.n_num_blocks += P.num_chunk_first[t.role + 1] - P.num_chunk_first[t.role];
@@ -1158,6 +1165,8 @@ void prepare(const hth_kb_s& kb, Plan&& plan, uint32_t n_hyps, Prepared& X) {
   {
     size_t sw = 0;
     for (StrTask& t : str) {
+      t.base_lo = (uint32_t)P.str_bounds[t.role];
+      t.base_hi = (uint32_t)(P.str_bounds[t.role] >> 32);
       t.h_first = (uint32_t)X.n_str_blocks;
       t.hc0 = P.str_chunk_first[t.role];
       X.n_str_blocks += P.str_chunk_first[t.role + 1] - P.str_chunk_first[t.role];
@@ -1229,11 +1238,11 @@ hth_status launch_prepared(hth_kb_s& kb, const Prepared& X, char* ws, uint32_t* 
   DevKB d = dev_view(kb);
   d.sets = P.sets;
   d.n_fixed = kb.d.n_concepts + P.n_sets;
-  d.num_off = P.num_off;
+  d.num_roff = P.num_roff;
   d.num_val = P.num_val;
   d.num_heavy_rows = P.num_heavy_rows;
   d.num_heavy_chunks = P.num_heavy_chunks;
-  d.str_off = P.str_off;
+  d.str_roff = P.str_roff;
   d.str_ids = P.str_ids;
   d.str_heavy_rows = P.str_heavy_rows;
   d.str_heavy_chunks = P.str_heavy_chunks;
@@ -1262,10 +1271,10 @@ hth_status launch_prepared(hth_kb_s& kb, const Prepared& X, char* ws, uint32_t* 
   if (!P.num.empty()) {
     const uint32_t n = (uint32_t)P.num.size();
     const NumTask* nt = reinterpret_cast<const NumTask*>(ws + X.o_num);
-    const uint32_t bpt = std::max<uint32_t>(1, std::min<uint32_t>((kb.W + 7) / 8, (8 * kb.n_cu + n - 1) / n));
+    const uint32_t bpt = std::max<uint32_t>(1, std::min<uint32_t>((kb.W + 7) / 8, (32 * kb.n_cu + n - 1) / n));
     double bytes = 0;   // per task: the role's offsets and values once, its row out
     for (const NumTask& t : P.num)
-      bytes += 8.0 * (kb.N + 1) + 4.0 * (double)(P.num_bounds[t.role + 1] - P.num_bounds[t.role]) + 8.0 * kb.W;
+      bytes += 4.0 * (kb.N + 1) + 4.0 * (double)(P.num_bounds[t.role + 1] - P.num_bounds[t.role]) + 8.0 * kb.W;
     hth_status s = split_launch(Lc, HTH_K_THRESHOLD, bytes, n, bpt, 256, [&](uint32_t i0, uint32_t, uint32_t blocks) {
       hipLaunchKernelGGL(k_numrole, dim3(blocks), dim3(256), 0, st, d, nt + i0, bpt);
     });
@@ -1288,10 +1297,10 @@ hth_status launch_prepared(hth_kb_s& kb, const Prepared& X, char* ws, uint32_t* 
       });
       if (s) return s;
     }
-    const uint32_t bpt = std::max<uint32_t>(1, std::min<uint32_t>((kb.W + 7) / 8, (8 * kb.n_cu + n - 1) / n));
+    const uint32_t bpt = std::max<uint32_t>(1, std::min<uint32_t>((kb.W + 7) / 8, (32 * kb.n_cu + n - 1) / n));
     double bytes = 0;   // per task: the role's offsets and ids once, its row out
     for (const StrTask& t : P.str)
-      bytes += 8.0 * (kb.N + 1) + 4.0 * (double)(P.str_bounds[t.role + 1] - P.str_bounds[t.role]) + 8.0 * kb.W;
+      bytes += 4.0 * (kb.N + 1) + 4.0 * (double)(P.str_bounds[t.role + 1] - P.str_bounds[t.role]) + 8.0 * kb.W;
     s = split_launch(Lc, HTH_K_THRESHOLD, bytes, n, bpt, 256, [&](uint32_t i0, uint32_t, uint32_t blocks) {
       hipLaunchKernelGGL(k_strrole, dim3(blocks), dim3(256), 0, st, d, sk + i0, bpt);
     });

@@ -61,7 +61,7 @@ struct NumTask {
   uint32_t out_row;
   uint32_t h_first;    // first block of this task in its heavy-row launch
   uint32_t hc0;        // first chunk of the role in the numeric chunk table
-  uint32_t pad0, pad1;
+  uint32_t base_lo, base_hi;   // the role's first value (its offsets are relative to it)
 };
 
 // One restriction on a string concrete role: bit x = some value id of x in
@@ -77,6 +77,7 @@ struct StrTask {
   uint32_t hc0;        // first chunk of the role in the string chunk table
   uint32_t set_word;
   uint32_t pad;
+  uint32_t base_lo, base_hi;   // the role's first value (its offsets are relative to it)
 };
 
 // The thresholds on one property, tasks[first .. first + n) (n <= 32).
@@ -170,11 +171,11 @@ struct DevKB {
   const uint32_t* heavy_rows; // subjects of the heavy rows, by direction 2r + dir, increasing
   const HeavyChunk* heavy_chunks;  // by direction, then heavy row, then k
   const uint32_t* heavy_chunk0;    // [heavy rows + 1] first chunk of each heavy row
-  const int64_t* num_off;          // [P][N+1] numeric concrete roles, absolute into num_val
+  const uint32_t* num_roff;        // [P][N+1] numeric concrete roles, relative to each role's first value
   const float* num_val;            // [V]
   const uint32_t* num_heavy_rows;  // subjects of the numeric roles' heavy rows, by role
   const HeavyChunk* num_heavy_chunks;
-  const int64_t* str_off;          // [Q][N+1] string concrete roles, absolute into str_ids
+  const uint32_t* str_roff;        // [Q][N+1] string concrete roles, relative to each role's first id
   const int32_t* str_ids;          // [V'] dictionary ids
   const uint32_t* str_heavy_rows;
   const HeavyChunk* str_heavy_chunks;

@@ -784,10 +784,10 @@ extern "C" hth_status hth_kb_create(const hth_kb_desc* desc, void* derived, size
 namespace hth {
 
 struct NumLayout {
-  size_t heavy, hchunk, hchunk0, meta, total;
+  size_t heavy, hchunk, hchunk0, meta, roff, total;
   size_t heavy_cap, chunk_cap;
 };
-static NumLayout num_layout(uint32_t n_roles, uint64_t n_values) {
+static NumLayout num_layout(uint32_t N, uint32_t n_roles, uint64_t n_values) {
   NumLayout L{};
   L.heavy_cap = n_values / (kHeavyMinFloor + 1) + 2;
   L.chunk_cap = n_values / kHeavyChunk + L.heavy_cap + 2;
@@ -796,6 +796,7 @@ static NumLayout num_layout(uint32_t n_roles, uint64_t n_values) {
   L.hchunk = at; at += align_up(L.chunk_cap * sizeof(HeavyChunk), 256);
   L.hchunk0 = at; at += align_up((L.heavy_cap + 1) * 4, 256);
   L.meta = at; at += align_up((4 + (size_t)n_roles) * 4, 256);
+  L.roff = at; at += align_up((size_t)n_roles * (N + 1) * 4, 256);
   L.total = at;
   return L;
 }
@@ -826,6 +827,14 @@ __global__ void k_check_values(const float* __restrict__ v, uint64_t n, uint32_t
   if (bad) atomicOr(flags, F_TARGET);
 }
 
+// 32-bit offsets relative to each role's first value (one thread per entry).
+__global__ void k_rel_offsets(const int64_t* __restrict__ off, uint32_t N, uint32_t* __restrict__ rel) {
+  const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+  if (x > N) return;
+  const int64_t* o = off + (size_t)r * (N + 1);
+  rel[(size_t)r * (N + 1) + x] = (uint32_t)(o[x] - o[0]);
+}
+
 // Heavy rows of numeric role r (more than hmin values) as (r, subject, degree).
 __global__ void __launch_bounds__(256)
 k_heavy_rows64(const int64_t* __restrict__ o, uint32_t N, uint32_t hmin, uint32_t r, uint32_t cap,
@@ -847,7 +856,7 @@ k_heavy_rows64(const int64_t* __restrict__ o, uint32_t N, uint32_t hmin, uint32_
 extern "C" hth_status hth_numeric_derived_bytes(hth_kb kb, uint32_t n_roles, uint64_t n_values, size_t* bytes) {
   if (!kb || !bytes) return fail(HTH_E_INVALID, "NULL argument");
   if (n_roles >= (1u << 16) || n_values >= (1ull << 40)) return fail(HTH_E_RANGE, "too many numeric roles or values");
-  *bytes = num_layout(n_roles, n_values).total;
+  *bytes = num_layout(kb->N, n_roles, n_values).total;
   return HTH_OK;
 }
 
@@ -872,6 +881,7 @@ __global__ void k_check_monotone64(const int64_t* __restrict__ o, uint64_t n, ui
 // and their chunks in the caller's derived buffer, per-role first chunk and
 // first value on the host.
 struct ValueRoles {
+  uint32_t* roff = nullptr;   // [n_roles][N+1] relative offsets
   uint32_t* rows = nullptr;
   HeavyChunk* chunks = nullptr;
   std::vector<uint32_t> chunk_first;
@@ -956,6 +966,10 @@ static hth_status value_roles(hth_kb_s* kb, uint32_t n_roles, const int64_t* off
   }
   out.bounds.assign(n_roles + 1, 0);
   for (uint32_t r = 0; r < n_roles; ++r) out.bounds[r + 1] = (uint64_t)ends[2 * r + 1];
+  out.roff = reinterpret_cast<uint32_t*>(dv + L.roff);
+  hipLaunchKernelGGL(k_rel_offsets, dim3((N + 256) / 256, n_roles), dim3(256), 0, st, offsets, N, out.roff);
+  HTH_HIP(hipGetLastError());
+  HTH_HIP(hipStreamSynchronize(st));
   return HTH_OK;
 }
 
@@ -977,7 +991,7 @@ extern "C" hth_status hth_kb_set_numeric(hth_kb kb, uint32_t n_roles, const int6
   }
   if (!offsets || (n_values && !values) || !derived) return fail(HTH_E_INVALID, "NULL argument");
   if (n_roles >= (1u << 16) || n_values >= (1ull << 40)) return fail(HTH_E_RANGE, "too many numeric roles or values");
-  const NumLayout L = num_layout(n_roles, n_values);
+  const NumLayout L = num_layout(kb->N, n_roles, n_values);
   if (derived_bytes < L.total) return fail(HTH_E_NOMEM, "numeric derived buffer smaller than hth_numeric_derived_bytes");
   if (reinterpret_cast<uintptr_t>(derived) % 256) return fail(HTH_E_INVALID, "derived buffer must be 256-byte aligned");
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -989,6 +1003,7 @@ extern "C" hth_status hth_kb_set_numeric(hth_kb kb, uint32_t n_roles, const int6
   kb->n_num = n_roles;
   kb->num_off = offsets;
   kb->num_val = values;
+  kb->num_roff = V.roff;
   kb->num_heavy_rows = V.rows;
   kb->num_heavy_chunks = V.chunks;
   kb->num_chunk_first = V.chunk_first;
@@ -1016,7 +1031,7 @@ extern "C" hth_status hth_kb_set_strings(hth_kb kb, uint32_t n_roles, const int6
   if (!offsets || (n_values && !ids) || !derived || !str_offsets) return fail(HTH_E_INVALID, "NULL argument");
   if (n_roles >= (1u << 16) || n_values >= (1ull << 40)) return fail(HTH_E_RANGE, "too many string roles or values");
   if (n_strings >= (1u << 31)) return fail(HTH_E_RANGE, "n_strings >= 2^31");
-  const NumLayout L = num_layout(n_roles, n_values);
+  const NumLayout L = num_layout(kb->N, n_roles, n_values);
   if (derived_bytes < L.total) return fail(HTH_E_NOMEM, "string derived buffer smaller than hth_string_derived_bytes");
   if (reinterpret_cast<uintptr_t>(derived) % 256) return fail(HTH_E_INVALID, "derived buffer must be 256-byte aligned");
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1033,6 +1048,7 @@ extern "C" hth_status hth_kb_set_strings(hth_kb kb, uint32_t n_roles, const int6
   kb->str_ids = ids;
   kb->dict_off = str_offsets;
   kb->dict_chars = chars;
+  kb->str_roff = V.roff;
   kb->str_heavy_rows = V.rows;
   kb->str_heavy_chunks = V.chunks;
   kb->str_chunk_first = V.chunk_first;

@@ -45,6 +45,7 @@ struct hth_kb_s {
   hth::HeavyChunk* num_heavy_chunks = nullptr;
   std::vector<uint32_t> num_chunk_first;   // [n_num+1] first chunk of each role
   std::vector<uint64_t> num_bounds;        // [n_num+1] first value of each role
+  uint32_t* num_roff = nullptr;            // [n_num][N+1] relative offsets (numeric derived buffer)
   // string concrete roles (hth_kb_set_strings) and CONTAIN patterns
   uint32_t n_str = 0, n_strings = 0, n_patterns = 0;
   const int64_t* str_off = nullptr;
@@ -57,6 +58,7 @@ struct hth_kb_s {
   hth::HeavyChunk* str_heavy_chunks = nullptr;
   std::vector<uint32_t> str_chunk_first;   // [n_str+1]
   std::vector<uint64_t> str_bounds;        // [n_str+1]
+  uint32_t* str_roff = nullptr;            // [n_str][N+1] relative offsets (string derived buffer)
   const uint64_t* pos = nullptr;
   const uint64_t* neg = nullptr;
   const uint64_t* sets = nullptr;      // caller's set table (hth_kb_set_sets)

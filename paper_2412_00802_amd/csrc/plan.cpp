@@ -504,7 +504,7 @@ struct Compiler {
     P.sets = kb.sets;
     P.n_sets = kb.n_sets;
     if (!P.num.empty()) {
-      P.num_off = kb.num_off;
+      P.num_roff = kb.num_roff;
       P.num_val = kb.num_val;
       P.num_heavy_rows = kb.num_heavy_rows;
       P.num_heavy_chunks = kb.num_heavy_chunks;
@@ -512,7 +512,7 @@ struct Compiler {
       P.num_bounds = kb.num_bounds;
     }
     if (!P.str.empty()) {
-      P.str_off = kb.str_off;
+      P.str_roff = kb.str_roff;
       P.str_ids = kb.str_ids;
       P.str_heavy_rows = kb.str_heavy_rows;
       P.str_heavy_chunks = kb.str_heavy_chunks;

@@ -30,14 +30,14 @@ struct Plan {
   std::vector<ThrTask> thr;
   std::vector<NumTask> num;         // restrictions on numeric concrete roles
   // the numeric concrete roles the plan was compiled against
-  const int64_t* num_off = nullptr;
+  const uint32_t* num_roff = nullptr;
   const float* num_val = nullptr;
   const uint32_t* num_heavy_rows = nullptr;
   const HeavyChunk* num_heavy_chunks = nullptr;
   std::vector<uint32_t> num_chunk_first;
   std::vector<uint64_t> num_bounds;        // [P+1] first value of each numeric role
   std::vector<StrTask> str;                // restrictions on string concrete roles
-  const int64_t* str_off = nullptr;
+  const uint32_t* str_roff = nullptr;
   const int32_t* str_ids = nullptr;
   const uint32_t* str_heavy_rows = nullptr;
   const HeavyChunk* str_heavy_chunks = nullptr;

@@ -144,7 +144,7 @@ def main():
             for op, h in (("MIN 0.5, decided by the first value", ("nge", 0, 0.5)),
                           ("MIN 2.0, every value read", ("nge", 0, 2.0))):
                 ms = time_op(eng, h, args.reps)
-                byts = 4.0 * e + 8.0 * (n + 1) + 2 * w8
+                byts = 4.0 * e + 4.0 * (n + 1) + 2 * w8
                 emit({"case": f"M3 numeric {shape}, {op}", "assertions": e, "individuals": n,
                       "us_per_op": round(ms * 1e3, 2), "GBps": round(byts / (ms * 1e-3) / 1e9, 1)})
             eng.close()
@@ -169,7 +169,7 @@ def main():
                           ("CONTAIN, matching", ("scontains", 0, b"0007")),
                           ("CONTAIN, no match", ("scontains", 0, b"0008"))):
                 ms = time_op(eng, eng.intern(h), args.reps)
-                byts = 4.0 * e + 8.0 * (n + 1) + 2 * w8
+                byts = 4.0 * e + 4.0 * (n + 1) + 2 * w8
                 emit({"case": f"M4 string {shape}, {op}", "assertions": e, "individuals": n,
                       "us_per_op": round(ms * 1e3, 2), "GBps": round(byts / (ms * 1e-3) / 1e9, 1)})
             eng.close()
@@ -182,7 +182,7 @@ def main():
                  "clearing, the operation, coverage), HIP events around back-to-back launches.  GB/s "
                  "counts algorithmic bytes: M1 the five rows read, the example rows and the output; M2 "
                  "the assertions' targets (4 B each), the row offsets (4 B per individual) and two bit "
-                 "rows; M3 and M4 the values or string ids (4 B each), the int64 offsets (8 B per "
+                 "rows; M3 and M4 the values or string ids (4 B each), the 32-bit row offsets (4 B per "
                  "individual) and two bit rows.", "",
                  "| case | individuals | assertions | us per op | GB/s |", "|---|---|---|---|---|"]
         for r in results:
