@@ -1161,30 +1161,17 @@ void prepare(const hth_kb_s& kb, Plan&& plan, uint32_t n_hyps, Prepared& X) {
     X.n_num_blocks += P.num_chunk_first[t.role + 1] - P.num_chunk_first[t.role];
   }
   X.o_num = X.blob.add(num);
+  // string tasks: CONTAIN first (k_contains takes them as one range), each
+  // with its id set; heavy-row blocks numbered in table order
   std::vector<StrTask> str(P.str);
-  {
-    size_t sw = 0;
-    for (StrTask& t : str) {
-      t.base_lo = (uint32_t)P.str_bounds[t.role];
-      t.base_hi = (uint32_t)(P.str_bounds[t.role] >> 32);
-      t.h_first = (uint32_t)X.n_str_blocks;
-      t.hc0 = P.str_chunk_first[t.role];
-      X.n_str_blocks += P.str_chunk_first[t.role + 1] - P.str_chunk_first[t.role];
-      if (t.kind == 1) {
-        t.set_word = (uint32_t)sw;
-        sw += idset_words(P.n_strings);
-        X.n_contains++;
-      }
-    }
-  }
-  // CONTAIN tasks first in their own table, so that k_contains takes a range
   std::stable_partition(str.begin(), str.end(), [](const StrTask& t) { return t.kind == 1; });
-  {   // the heavy-block numbering must follow the table order
-    size_t hb = 0;
-    for (StrTask& t : str) {
-      t.h_first = (uint32_t)hb;
-      hb += P.str_chunk_first[t.role + 1] - P.str_chunk_first[t.role];
-    }
+  for (StrTask& t : str) {
+    t.base_lo = (uint32_t)P.str_bounds[t.role];
+    t.base_hi = (uint32_t)(P.str_bounds[t.role] >> 32);
+    t.hc0 = P.str_chunk_first[t.role];
+    t.h_first = (uint32_t)X.n_str_blocks;
+    X.n_str_blocks += P.str_chunk_first[t.role + 1] - P.str_chunk_first[t.role];
+    if (t.kind == 1) t.set_word = (uint32_t)(X.n_contains++ * idset_words(P.n_strings));
   }
   X.o_str = X.blob.add(str);
   X.n_thr_groups = thr_groups.size();
@@ -1204,7 +1191,6 @@ void prepare(const hth_kb_s& kb, Plan&& plan, uint32_t n_hyps, Prepared& X) {
   for (const PlanLevel& PL : P.levels) max_groups = std::max(max_groups, PL.groups.size());
   X.o_hcnt = X.tables + (size_t)P.n_slots * kb.S * 8 + (max_groups ? t_area_bytes(kb) : 0);
   X.o_part = X.o_hcnt + heavy_counter_bytes(kb, P);
-  X.o_idset = 0;   // set below, after the partial counts
   size_t part = 0;
   for (size_t L = 0; L < NL; ++L)
     for (const GroupChunk& c : X.lv_chunks[L]) part = std::max(part, chunk_partial_bytes(kb, X.lv_groups[L], c));
