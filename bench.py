@@ -21,7 +21,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "exact hypotheses/sec + achieved HBM GB/s; screened vs plain exhaustive"
 HBM_PEAK_GBS = 8000.0
-KIND_NAMES = {0: "k_threshold", 1: "k_region", 2: "k_role", 3: "k_tbuild", 4: "k_group", 5: "k_fill_rows"}
+KIND_NAMES = {0: "k_threshold", 1: "k_region", 2: "k_role", 3: "k_tbuild", 4: "k_group", 5: "k_fill_rows",
+              6: "k_dp_emit"}
 # the dominant kernel's source: its counters are void once these change
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2412_00802_amd", "csrc", f)
                   for f in ("group_kernels.h", "hth_internal.h")]
@@ -190,6 +191,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--device-plans", type=int, default=0, metavar="STEPS",
+                    help="also time STEPS evaluations of the batch with plans generated on the device")
     ap.add_argument("--autotune", action="store_true", help="pick the schedule with the autotuner first")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of 256 MiB (byte-counter calibration)")
@@ -307,6 +310,38 @@ def main():
                  "equal_to_batched": bool((pgot == got[:P]).all())}
         log(f"[bench] plain: {P / pdt:,.0f} hyp/s")
 
+    dplans = None
+    if args.device_plans:
+        # the batch's node arrays already in device memory; a step generates
+        # the plan there (count pass + summary readback, emit pass) and runs it
+        d_nodes, d_offs, d_ch = eng.upload_batch(encoded=(nodes, offs, ch))
+        n_nodes = int(nodes.shape[0])
+        dc = torch.empty((H, 2), dtype=torch.int32, device="cuda")
+
+        def dstep():
+            plan, nb = hthedl.hth_dplan_create(eng.handle, d_nodes, n_nodes, d_offs, H, d_ch, int(d_ch.shape[0]),
+                                               stream)
+            eng.ensure_workspace(nb)
+            hthedl.hth_dplan_launch(plan, eng.ws, eng.ws_bytes, dc, stream)
+            hthedl.hth_dplan_destroy(plan)
+
+        dstep()
+        torch.cuda.synchronize()
+        hthedl.hth_profile_begin(eng.handle)
+        t0 = time.perf_counter()
+        for _ in range(args.device_plans):
+            dstep()
+        torch.cuda.synchronize()
+        ddt = time.perf_counter() - t0
+        dent = hthedl.hth_profile_end(eng.handle)
+        dgot = dc.cpu().numpy().view(np.uint32)
+        dplans = {"value": round(H * args.device_plans / ddt, 1), "unit": "hypotheses/s",
+                  "ms_per_step": round(ddt / args.device_plans * 1e3, 3),
+                  "equal_to_batched": bool((dgot == got).all()),
+                  "kernels_ms_per_step": {KIND_NAMES.get(k, str(k)): round(e["ms"] / args.device_plans, 3)
+                                          for k, e in enumerate(dent) if e["launches"]}}
+        log(f"[bench] device plans: {dplans}")
+
     cpu = None
     parity = None
     if args.cpu_sample:
@@ -327,7 +362,8 @@ def main():
                    "n_individuals": cfg.n_individuals, "n_assertions": kb.n_edges,
                    "mode": "batched",
                    "schedule": schedule or hthedl.hth_kb_get_tuning(eng.handle)},
-        "roofline": roofline, "cpu_baseline": cpu, "plain": plain, "parity_sample": parity,
+        "roofline": roofline, "cpu_baseline": cpu, "plain": plain, "device_plans": dplans,
+        "parity_sample": parity,
         "kernels": kernels,
     }
     print(json.dumps(out), flush=True)

@@ -301,6 +301,42 @@ hth_status hth_plan_launch(hth_plan plan, void* ws, size_t ws_bytes, uint32_t* d
                            void* stream);
 hth_status hth_plan_destroy(hth_plan plan);
 
+/* Plans generated on the device.  The paper generates each hypothesis's
+ * evaluation plan on CPU threads and leaves generation on the GPU, with little
+ * or no CPU involvement, as future work (Sections 4 and 7).  Here the batch is
+ * already in DEVICE memory, in the layout hth_eval_batch takes on the host:
+ * d_nodes [n_nodes], d_hyp_node_offsets [n_hyps + 1] (hypothesis h is
+ * d_nodes[offsets[h] .. offsets[h+1]), local child indices; offsets need not
+ * start at 0, so a chunk of a larger batch is the same arrays with the offsets
+ * pointer advanced), d_children [n_children].  The plan is the paper's
+ * per-hypothesis plan: every DL operation of every hypothesis is one task, run
+ * level by level on the executor's kernels (no sharing across hypotheses, no
+ * shared CSR passes); every node is evaluated, reachable from its root or not.
+ *
+ * hth_dplan_create runs the count pass on `stream` (validation, role-nesting
+ * levels, region programs' sizes) and waits for its summary (a few hundred
+ * bytes): the only data the host reads.  *ws_bytes receives the workspace that
+ * hth_dplan_launch needs.  The plan owns a device buffer of 12 bytes per node
+ * and keeps the kb's set table as it was at creation.  The device arrays must
+ * stay allocated and unchanged until the plan's last launch.
+ * hth_dplan_launch writes the plan's tables into ws on the device and runs
+ * every kernel of the evaluation on `stream`, without waiting; d_counts
+ * [n_hyps][2] as hth_eval_batch.  Launches of one plan must not overlap;
+ * hth_dplan_destroy waits for the plan's last launch before it frees its buffer.
+ * Errors (create): as hth_eval_batch, with the first failing hypothesis and
+ * node; HTH_E_UNSUPPORTED for HTH_NUM_* / HTH_STR_* nodes, role restrictions
+ * nested more than 16 deep, and regions with more than 32 nested operators;
+ * HTH_E_RANGE for n_hyps = 0 or n_nodes > 2^24.  (launch) HTH_E_NOMEM when
+ * ws_bytes is short, HTH_E_INVALID when ws is not 256-byte aligned.  The plan
+ * must not outlive its kb. */
+typedef struct hth_dplan_s* hth_dplan;
+hth_status hth_dplan_create(hth_kb kb, const hth_node* d_nodes, uint32_t n_nodes,
+                            const uint32_t* d_hyp_node_offsets, uint32_t n_hyps, const uint32_t* d_children,
+                            uint32_t n_children, void* stream, hth_dplan* out, size_t* ws_bytes);
+hth_status hth_dplan_launch(hth_dplan plan, void* ws, size_t ws_bytes, uint32_t* d_counts /* [n_hyps][2] */,
+                            void* stream);
+hth_status hth_dplan_destroy(hth_dplan plan);
+
 /* Measurement.  Between hth_profile_begin and hth_profile_end every kernel the
  * library launches for this kb is bracketed by two HIP events recorded on the
  * launch stream, and the host adds up the algorithmic HBM bytes of the launch
@@ -315,6 +351,7 @@ enum {
   HTH_K_TBUILD = 3,     /* transposed child rows for shared role passes */
   HTH_K_GROUP = 4,      /* shared role passes (up to 64 role nodes per CSR scan) */
   HTH_K_FILL = 5,       /* zero-count results of words without assertions */
+  HTH_K_PLAN = 6,       /* plan generation on the device (hth_dplan_launch) */
   HTH_K_NUM = 8
 };
 typedef struct {

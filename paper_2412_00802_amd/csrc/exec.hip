@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <vector>
 
 #include "kb_handle.h"
@@ -827,24 +828,11 @@ double csr_bytes(const hth_kb_s& kb, uint32_t role, uint32_t inv) {
          4.0 * (double)(kb.role_base[role + 1] - kb.role_base[role]);
 }
 
-hth_status launch_regions(Launcher& L, const DevKB& d, const RegionTask* tasks, const uint32_t* code,
-                          const std::vector<RegionTask>& host, const std::vector<uint32_t>& hcode) {
-  const uint32_t n = (uint32_t)host.size();
+// n region tasks whose programs need at most `depth` stack entries
+hth_status launch_regions_n(Launcher& L, const DevKB& d, const RegionTask* tasks, const uint32_t* code,
+                            uint32_t n, int depth, double bytes) {
   if (!n) return HTH_OK;
-  double bytes = 0;
-  if (L.kb.prof)
-    for (const RegionTask& t : host) bytes += region_bytes(L.kb, t, hcode);
   // the register kernel when every program's stack fits its shift register
-  int depth = 0;
-  for (const RegionTask& t : host) {
-    int sp = 0;
-    for (uint32_t i = 0; i < t.code_len; ++i) {
-      const uint32_t op = hcode[t.code_off + i] & 15u;
-      if (op <= RP_BOT) sp += i ? 1 : 0;
-      else if (op != RP_NOT) --sp;
-      depth = std::max(depth, sp + 1);
-    }
-  }
   if (depth <= kRegDepth && L.kb.tune.region_reg) {
     const uint32_t rw = L.kb.tune.region_reg;     // words per lane: 1, 2 or 4
     const uint32_t tiles = (d.S + 256 * rw - 1) / (256 * rw);
@@ -864,13 +852,27 @@ hth_status launch_regions(Launcher& L, const DevKB& d, const RegionTask* tasks, 
   });
 }
 
-hth_status launch_roles(Launcher& L, const DevKB& d, const RoleTask* tasks,
-                        const std::vector<RoleTask>& host) {
-  const hth_kb_s& kb = L.kb;
-  const uint32_t n = (uint32_t)host.size();
-  if (!n) return HTH_OK;
+hth_status launch_regions(Launcher& L, const DevKB& d, const RegionTask* tasks, const uint32_t* code,
+                          const std::vector<RegionTask>& host, const std::vector<uint32_t>& hcode) {
   double bytes = 0;
-  for (const RoleTask& t : host) bytes += csr_bytes(kb, t.role, t.inv) + 2.0 * kb.W * 8;
+  if (L.kb.prof)
+    for (const RegionTask& t : host) bytes += region_bytes(L.kb, t, hcode);
+  int depth = 0;
+  for (const RegionTask& t : host) {
+    int sp = 0;
+    for (uint32_t i = 0; i < t.code_len; ++i) {
+      const uint32_t op = hcode[t.code_off + i] & 15u;
+      if (op <= RP_BOT) sp += i ? 1 : 0;
+      else if (op != RP_NOT) --sp;
+      depth = std::max(depth, sp + 1);
+    }
+  }
+  return launch_regions_n(L, d, tasks, code, (uint32_t)host.size(), depth, bytes);
+}
+
+hth_status launch_roles_n(Launcher& L, const DevKB& d, const RoleTask* tasks, uint32_t n, double bytes) {
+  const hth_kb_s& kb = L.kb;
+  if (!n) return HTH_OK;
   const size_t lds = (size_t)kb.W * 8;
   if (lds <= kb.lds_per_block) {
     // one 1024-lane block per CU holds the child row in LDS: one round of blocks,
@@ -886,6 +888,13 @@ hth_status launch_roles(Launcher& L, const DevKB& d, const RoleTask* tasks,
   return split_launch(L, HTH_K_ROLE, bytes, n, bpt, 256, [&](uint32_t t0, uint32_t, uint32_t blocks) {
     hipLaunchKernelGGL(k_role<false>, dim3(blocks), dim3(256), 0, L.st, d, tasks + t0, bpt);
   });
+}
+
+hth_status launch_roles(Launcher& L, const DevKB& d, const RoleTask* tasks,
+                        const std::vector<RoleTask>& host) {
+  double bytes = 0;
+  for (const RoleTask& t : host) bytes += csr_bytes(L.kb, t.role, t.inv) + 2.0 * L.kb.W * 8;
+  return launch_roles_n(L, d, tasks, (uint32_t)host.size(), bytes);
 }
 
 template <typename TW>
@@ -1211,14 +1220,19 @@ __global__ void k_zero_u32(uint32_t* __restrict__ p, uint32_t n) {
   if (i < n) p[i] = 0;
 }
 
-// The kernels of a prepared plan whose tables are in ws: no copies, no
-// allocation and no memset (the counts are cleared by a kernel).
-hth_status launch_prepared(hth_kb_s& kb, const Prepared& X, char* ws, uint32_t* counts, uint64_t* instances,
-                           hipStream_t st) {
+// k_role<true> stages the child row in up to lds_per_block bytes of LDS
+void role_attributes(const hth_kb_s& kb) {
   std::call_once(g_attr_once, [&] {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_role<true>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kb.lds_per_block);
   });
+}
+
+// The kernels of a prepared plan whose tables are in ws: no copies, no
+// allocation and no memset (the counts are cleared by a kernel).
+hth_status launch_prepared(hth_kb_s& kb, const Prepared& X, char* ws, uint32_t* counts, uint64_t* instances,
+                           hipStream_t st) {
+  role_attributes(kb);
   const Plan& P = X.P;
   const size_t slot_bytes = (size_t)kb.S * 8;
   DevKB d = dev_view(kb);
@@ -1537,3 +1551,5 @@ extern "C" hth_status hth_profile_end(hth_kb kb, hth_prof_entry* out) {
   kb->prof_recs.clear();
   return st;
 }
+
+#include "devplan.h"

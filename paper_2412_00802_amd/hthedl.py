@@ -38,7 +38,8 @@ EXPORTED = ["hth_kb_derived_bytes", "hth_kb_create", "hth_kb_set_examples", "hth
             "hth_batch_workspace_bytes", "hth_head_score", "hth_kb_get_tuning", "hth_kb_set_tuning",
             "hth_kb_set_sets", "hth_eval_batch_sets", "hth_densify_delta", "hth_plan_create",
             "hth_plan_upload", "hth_plan_launch", "hth_plan_destroy", "hth_numeric_derived_bytes",
-            "hth_kb_set_numeric", "hth_string_derived_bytes", "hth_kb_set_strings", "hth_kb_set_patterns"]
+            "hth_kb_set_numeric", "hth_string_derived_bytes", "hth_kb_set_strings", "hth_kb_set_patterns",
+            "hth_dplan_create", "hth_dplan_launch", "hth_dplan_destroy"]
 
 
 class HthError(RuntimeError):
@@ -107,6 +108,9 @@ def lib() -> ctypes.CDLL:
             "hth_plan_upload": [P, P, S, P],
             "hth_plan_launch": [P, P, S, P, P],
             "hth_plan_destroy": [P],
+            "hth_dplan_create": [P, P, U32, P, U32, P, U32, P, ctypes.POINTER(P), ctypes.POINTER(S)],
+            "hth_dplan_launch": [P, P, S, P, P],
+            "hth_dplan_destroy": [P],
             "hth_batch_workspace_bytes": [P, P, P, U32, P, U32, ctypes.POINTER(S)],
             "hth_sync": [P],
             "hth_profile_begin": [P],
@@ -317,6 +321,26 @@ def hth_plan_launch(plan, ws, ws_bytes: int, d_counts, stream=None) -> None:
 
 def hth_plan_destroy(plan) -> None:
     _check(lib().hth_plan_destroy(plan))
+
+
+def hth_dplan_create(kb, d_nodes, n_nodes: int, d_offsets, n_hyps: int, d_children, n_children: int,
+                     stream=None):
+    """Plan generated on the device from device arrays (d_nodes: the node
+    records as bytes, d_offsets [n_hyps+1] and d_children as 32-bit tensors)
+    -> (plan handle, workspace bytes)."""
+    h, nb = ctypes.c_void_p(), ctypes.c_size_t()
+    _check(lib().hth_dplan_create(kb, _ptr(d_nodes), n_nodes, _ptr(d_offsets), n_hyps,
+                                  _ptr(d_children) if n_children else None, n_children, _stream(stream),
+                                  ctypes.byref(h), ctypes.byref(nb)))
+    return h, nb.value
+
+
+def hth_dplan_launch(plan, ws, ws_bytes: int, d_counts, stream=None) -> None:
+    _check(lib().hth_dplan_launch(plan, _ptr(ws), ws_bytes, _ptr(d_counts), _stream(stream)))
+
+
+def hth_dplan_destroy(plan) -> None:
+    _check(lib().hth_dplan_destroy(plan))
 
 
 def hth_batch_workspace_bytes(kb, nodes: np.ndarray, offsets: np.ndarray, children: np.ndarray) -> int:
@@ -676,6 +700,42 @@ class Engine:
             self.ws = None
             self.ws = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
             self.ws_bytes = nbytes
+
+    def upload_batch(self, hyps: Sequence = None, encoded=None):
+        """The batch's node arrays in device memory: (nodes as bytes,
+        offsets, children) tensors, as hth_dplan_create takes them."""
+        torch = self.torch
+        nodes, offs, ch = encoded if encoded is not None else encode_batch(hyps)
+        d_nodes = torch.from_numpy(np.ascontiguousarray(nodes, dtype=NODE_DTYPE).view(np.uint8)).to(self.device)
+        d_offs = torch.from_numpy(np.ascontiguousarray(offs, dtype=np.uint32).view(np.int32)).to(self.device)
+        d_ch = torch.from_numpy(np.ascontiguousarray(ch, dtype=np.uint32).view(np.int32)).to(self.device)
+        return d_nodes, d_offs, d_ch
+
+    def eval_batch_device(self, hyps: Sequence = None, counts=None, chunk: Optional[int] = None,
+                          encoded=None, device_batch=None, stream=None) -> Optional[np.ndarray]:
+        """Batched evaluation with plans generated on the device (hth_dplan_*):
+        the node arrays go to the device once (or come as device_batch, from
+        upload_batch or a device-side producer), and each chunk of `chunk`
+        hypotheses gets its plan from the library's count and emit kernels.
+        uint32 [H][2]."""
+        torch = self.torch
+        d_nodes, d_offs, d_ch = device_batch if device_batch is not None else self.upload_batch(hyps, encoded)
+        H = int(d_offs.shape[0] - 1)
+        n_nodes = int(d_nodes.shape[0] // NODE_DTYPE.itemsize)
+        out = counts if counts is not None else torch.empty((H, 2), dtype=torch.int32, device=self.device)
+        chunk = H if not chunk else chunk
+        for a in range(0, H, chunk):
+            b = min(H, a + chunk)
+            plan, nb = hth_dplan_create(self.handle, d_nodes, n_nodes, d_offs[a:], b - a, d_ch,
+                                        int(d_ch.shape[0]), stream)
+            try:
+                self.ensure_workspace(max(nb, 256))
+                hth_dplan_launch(plan, self.ws, self.ws_bytes, out[a:b], stream)
+            finally:
+                hth_dplan_destroy(plan)
+        if counts is not None:
+            return None
+        return out.cpu().numpy().view(np.uint32)
 
     def eval_batch(self, hyps: Sequence, stream=None, counts=None, chunk: Optional[int] = None,
                    encoded=None) -> Optional[np.ndarray]:

@@ -1,0 +1,274 @@
+"""GPU parity of plans generated on the device (hth_dplan_*): the node arrays
+sit in device memory, the library's count and emit kernels build the plan,
+and the coverage equals the oracle's (and the host-compiled batch's) bit for
+bit.  Errors are found by the count pass, before any evaluation kernel runs."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_2412_00802_amd import hthedl, synth
+from tests.test_parity_gpu import heavy_kb, heavy_zoo
+
+pytestmark = pytest.mark.gpu
+
+OPS = hthedl.OPS
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "the gpu tests need an MI355X"
+    hthedl.lib()
+    return torch
+
+
+def check_device(kb, hyps, label, chunk=None, eng=None, host=True):
+    say(f"[devplan] {label}: N={kb.n} hyps={len(hyps)}")
+    eng = eng or hthedl.Engine(kb, max_hyps=max(1, len(hyps)))
+    want = Oracle(kb).coverages(hyps)
+    got = eng.eval_batch_device(hyps, chunk=chunk)
+    bad = np.flatnonzero((got != want).any(axis=1))
+    assert bad.size == 0, f"device plan mismatch at {bad[:5]}: {hyps[bad[0]]} got {got[bad[0]]} want {want[bad[0]]}"
+    if host:
+        assert np.array_equal(eng.eval_batch(hyps), want)
+    return eng
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 4097])
+def test_tail_sizes(n):
+    cfg = synth.small_config(n=n, n_concepts=10, n_roles=3, cap=min(16, max(1, n)),
+                             n_pos=max(1, n // 5), n_neg=n // 5, n_hyps=48, seed_index=300 + n % 97)
+    kb = synth.make_kb(cfg)
+    check_device(kb, synth.make_hypotheses(cfg, kb), f"tail n={n}")
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_small_workloads(seed):
+    """Random hypotheses over every construct (thresholds included), 600 per
+    batch: several blocks of the one-thread-per-hypothesis passes."""
+    cfg = synth.small_config(n=3000 + 517 * seed, n_concepts=24, n_roles=4, s=1.2 + 0.3 * seed,
+                             cap=[8, 64, 300, 1000][seed], n_data=3, n_pos=400, n_neg=300, n_hyps=600,
+                             hyp_depth=5, seed_index=400 + seed)
+    kb = synth.make_kb(cfg)
+    check_device(kb, synth.make_hypotheses(cfg, kb), f"small seed={seed}")
+
+
+@pytest.mark.parametrize("heavy_min", [None, 1024])
+def test_heavy_rows(monkeypatch, heavy_min):
+    """Heavy rows at several levels: the per-level heavy-block ranges come
+    from the device scan over the role tasks in task order."""
+    if heavy_min is not None:
+        monkeypatch.setenv("HTHEDL_HEAVY_MIN", str(heavy_min))
+    kb = heavy_kb()
+    hs = heavy_zoo()
+    hs += [("exists", 0, 0, ("atleast", 2049, 0, 0, ("not", ("atom", 2)))),
+           ("atmost", 3000, 1, 1, ("exists", 0, 1, ("and", ("atom", 0), ("atom", 1)))),
+           ("and", ("forall", 1, 1, ("exists", 0, 0, ("top",))), ("atleast", 1025, 0, 0, ("atom", 0)))]
+    check_device(kb, hs, f"heavy rows, threshold {heavy_min}", chunk=150)
+
+
+def test_set_table_leaves():
+    import torch
+    cfg = synth.small_config(n=20000, n_concepts=24, n_roles=4, s=1.5, cap=100, n_data=3,
+                             n_pos=2000, n_neg=2000, seed_index=1600)
+    kb = synth.make_kb(cfg)
+    o = Oracle(kb)
+    subs = synth.make_hypotheses(cfg, kb, count=20, depth=3)
+    eng = hthedl.Engine(kb)
+    table = torch.zeros((len(subs), eng.S), dtype=torch.int64, device="cuda")
+    nodes, offs, ch = hthedl.encode_batch(subs)
+    eng.ensure_workspace(hthedl.hth_batch_workspace_bytes(eng.handle, nodes, offs, ch))
+    cnt = torch.empty((len(subs), 2), dtype=torch.int32, device="cuda")
+    hthedl.hth_eval_batch_sets(eng.handle, nodes, offs, ch, eng.ws, eng.ws_bytes, table, cnt)
+    hthedl.hth_kb_set_sets(eng.handle, table, len(subs))
+    rng = np.random.default_rng(3)
+    hyps, full = [], []
+    for i, s in enumerate(subs):
+        a = ("atom", int(rng.integers(0, 24)))
+        e = ("exists", int(rng.integers(0, 4)), int(rng.integers(0, 2)), ("set", i))
+        hyps += [("and", ("set", i), a), ("or", ("not", ("set", i)), e), e]
+        full += [("and", s, a), ("or", ("not", s), ("exists", e[1], e[2], s)), ("exists", e[1], e[2], s)]
+    got = eng.eval_batch_device(hyps)
+    assert np.array_equal(got, o.coverages(full))
+    hthedl.hth_kb_set_sets(eng.handle, None, 0)
+
+
+def _node(op, inv=0, arity=0, arg=0, child=0, q=0):
+    return (OPS[op], inv, arity, arg, child, q)
+
+
+def _batch(hyp_nodes, hyp_children):
+    """Hand-built hypotheses: lists of node tuples (local child indices; and/or
+    `child` relative to the hypothesis's own children list)."""
+    nodes, children, offs = [], [], [0]
+    for nd, ch in zip(hyp_nodes, hyp_children):
+        base = len(children)
+        for t in nd:
+            t = list(t)
+            if t[0] in (OPS["and"], OPS["or"]):
+                t[4] += base
+            nodes.append(tuple(t))
+        children.extend(ch)
+        offs.append(len(nodes))
+    return (np.array(nodes, dtype=hthedl.NODE_DTYPE), np.array(offs, dtype=np.uint32),
+            np.array(children, dtype=np.uint32))
+
+
+def test_shared_nodes_within_a_hypothesis():
+    """The node format allows a DAG inside a hypothesis: a node referenced
+    twice is evaluated once and read from both places; a shared compound
+    filler is written into each referencing region's program."""
+    cfg = synth.small_config(n=5000, n_concepts=8, n_roles=2, cap=20, n_data=1, n_pos=900, n_neg=900,
+                             seed_index=1900)
+    kb = synth.make_kb(cfg)
+    t = float(kb.deciles[0, 4])
+    tb = int(np.float32(t).view(np.uint32))
+    a0, ex = ("atom", 0), ("exists", 1, 0, ("atom", 0))
+    conj = ("and", ex, ex)
+    hyp_nodes = [
+        # 0 A0, 1 exists r1.A0, 2 and(1, 1), 3 not 1, 4 or(2, 3, 0)
+        [_node("atom", arg=0), _node("exists", arg=1, child=0), _node("and", arity=2, child=0),
+         _node("not", child=1), _node("or", arity=3, child=2)],
+        # 0 A0, 1 exists, 2 and(1,1), 3 atleast 2 r0^- .(2), 4 forall r1.(2), 5 and(3, 4, 2), 6 dge
+        [_node("atom", arg=0), _node("exists", arg=1, child=0), _node("and", arity=2, child=0),
+         _node("atleast", inv=1, arg=0, child=2, q=2), _node("forall", arg=1, child=2),
+         _node("dge", arg=0, q=tb), _node("and", arity=4, child=2)],
+        # unreachable nodes before the root are evaluated too and change nothing
+        [_node("atom", arg=3), _node("atmost", arg=1, child=0, q=1), _node("atom", arg=5)],
+    ]
+    hyp_children = [[1, 1, 2, 3, 0], [1, 1, 3, 4, 2, 5]]
+    hyp_children.append([])
+    trees = [("or", conj, ("not", ex), a0),
+             ("and", ("atleast", 2, 0, 1, conj), ("forall", 1, 0, conj), conj, ("dge", 0, t)),
+             ("atom", 5)]
+    enc = _batch(hyp_nodes, hyp_children)
+    eng = hthedl.Engine(kb)
+    got = eng.eval_batch_device(encoded=enc)
+    assert np.array_equal(got, Oracle(kb).coverages(trees))
+    assert np.array_equal(eng.eval_batch(None, encoded=enc), got)
+
+
+def _balanced(k, rng, op="and"):
+    if k == 0:
+        return ("atom", int(rng.integers(0, 16)))
+    other = "or" if op == "and" else "and"
+    return (op, _balanced(k - 1, rng, other), _balanced(k - 1, rng, other))
+
+
+def test_deep_regions_and_nested_roles():
+    """Region programs that need 2..16 stack entries (the register kernel up to
+    six, the LDS kernel above), role restrictions nested 16 deep, and the
+    limits beyond (17 entries, 17 levels, 33 nested operators) rejected."""
+    cfg = synth.small_config(n=3000, n_concepts=16, n_roles=2, cap=8, n_data=1, n_pos=500, n_neg=500,
+                             seed_index=2000)
+    kb = synth.make_kb(cfg)
+    rng = np.random.default_rng(20)
+    hyps = [_balanced(k, rng, op) for k in (1, 2, 5, 6, 7, 9) for op in ("and", "or")]
+    nest = ("atom", 1)
+    for i in range(16):
+        nest = ("exists", i % 2, (i // 2) % 2, ("or", nest, ("atom", i % 16)) if i % 3 == 0 else nest)
+    hyps.append(nest)
+    hyps.append(("exists", 0, 0, _balanced(8, rng)))      # a deep filler region
+    eng = hthedl.Engine(kb, max_nodes=1 << 17)
+    for reg in (2, 0):
+        hthedl.hth_kb_set_tuning(eng.handle, region_reg=reg)
+        check_device(kb, hyps, f"deep regions, region_reg {reg}", eng=eng, host=False)
+    deep16 = _balanced(15, rng)
+    assert np.array_equal(eng.eval_batch_device([deep16]), Oracle(kb).coverages([deep16]))
+    for bad in (_balanced(16, rng), ("exists", 0, 0, nest)):
+        with pytest.raises(hthedl.HthError) as e:
+            eng.eval_batch_device([("atom", 0), bad])
+        assert e.value.status == -7 and "hypothesis 1" in str(e.value), str(e.value)
+    chain = ("and", ("atom", 0), ("atom", 1))
+    for _ in range(33):
+        chain = ("not", chain)
+    with pytest.raises(hthedl.HthError) as e:
+        eng.eval_batch_device([chain])
+    assert e.value.status == -7
+    chain32 = ("and", ("atom", 0), ("atom", 1))
+    for _ in range(31):
+        chain32 = ("not", chain32)
+    assert np.array_equal(eng.eval_batch_device([chain32]), Oracle(kb).coverages([chain32]))
+
+
+def test_errors(gpu):
+    """Each invalid node is reported with its hypothesis and node by the count
+    pass; nothing is evaluated (the counts keep their sentinel)."""
+    torch = gpu
+    cfg = synth.small_config(n=2000, n_concepts=6, n_roles=2, cap=8, n_data=2, seed_index=2100)
+    kb = synth.make_kb(cfg)
+    eng = hthedl.Engine(kb)
+    good = [_node("atom", arg=1)]
+    nan = int(np.float32(np.nan).view(np.uint32))
+    cases = [
+        ([_node("atom", arg=6)], [], -2, "concept"),
+        ([_node("atom", arg=0), _node("not", child=1)], [], -5, "child"),
+        ([_node("atom", arg=0), _node("exists", arg=2, child=0)], [], -2, "role"),
+        ([_node("atom", arg=0), _node("exists", inv=2, arg=0, child=0)], [], -1, "inv"),
+        ([_node("atom", arg=0), _node("atleast", arg=0, child=0, q=1 << 31)], [], -2, "n >"),
+        ([_node("dge", arg=2, q=0)], [], -2, "property"),
+        ([_node("dle", arg=0, q=nan)], [], -1, "NaN"),
+        ([_node("nge", arg=0, q=0)], [], -7, "concrete"),
+        ([_node("set", arg=0)], [], -2, "set row"),
+        ([(99, 0, 0, 0, 0, 0)], [], -1, "unknown op"),
+        ([_node("atom", arg=0), _node("and", arity=3, child=0)], [0, 0], -2, "children range"),
+        ([_node("atom", arg=0), _node("or", arity=2, child=0)], [0, 1], -5, "child"),
+    ]
+    counts = torch.full((2, 2), -7, dtype=torch.int32, device="cuda")
+    for nodes, ch, status, word in cases:
+        enc = _batch([good, nodes], [[], ch])
+        d = eng.upload_batch(encoded=enc)
+        with pytest.raises(hthedl.HthError) as e:
+            eng.eval_batch_device(device_batch=d, counts=counts)
+        assert e.value.status == status, (nodes, str(e.value))
+        assert "hypothesis 1 node" in str(e.value) and word in str(e.value), str(e.value)
+    assert (counts.cpu().numpy() == -7).all()
+    # offsets: empty hypothesis, decreasing, past the node array
+    d_nodes, _, d_ch = eng.upload_batch(encoded=_batch([good, good], [[], []]))
+    for offs, status in (([0, 1, 1], -5), ([0, 2, 1], -1), ([0, 1, 3], -1)):
+        d_offs = torch.tensor(offs, dtype=torch.int32, device="cuda")
+        with pytest.raises(hthedl.HthError) as e:
+            eng.eval_batch_device(device_batch=(d_nodes, d_offs, d_ch), counts=counts)
+        assert e.value.status == status, (offs, str(e.value))
+    with pytest.raises(hthedl.HthError) as e:
+        hthedl.hth_dplan_create(eng.handle, d_nodes, 2, d_offs, 0, None, 0)
+    assert e.value.status == -2
+
+
+def test_chunks_relaunch_and_workspace(gpu):
+    """Chunks of one uploaded batch (the offsets pointer advanced), a plan
+    launched twice, and the workspace checks."""
+    torch = gpu
+    cfg = synth.small_config(n=8000, n_concepts=16, n_roles=3, cap=64, n_data=2, n_pos=1000, n_neg=1000,
+                             n_hyps=300, hyp_depth=5, seed_index=2200)
+    kb = synth.make_kb(cfg)
+    hyps = synth.make_hypotheses(cfg, kb)
+    want = Oracle(kb).coverages(hyps)
+    eng = hthedl.Engine(kb, max_hyps=len(hyps))
+    d = eng.upload_batch(hyps)
+    for chunk in (1, 37, 300):
+        assert np.array_equal(eng.eval_batch_device(device_batch=d, chunk=chunk), want), chunk
+    d_nodes, d_offs, d_ch = d
+    n_nodes = d_nodes.shape[0] // 16
+    plan, nb = hthedl.hth_dplan_create(eng.handle, d_nodes, n_nodes, d_offs[100:], 50, d_ch, d_ch.shape[0])
+    try:
+        ws = torch.empty(nb + 512, dtype=torch.uint8, device="cuda")
+        out = torch.empty((50, 2), dtype=torch.int32, device="cuda")
+        for _ in range(2):
+            out.fill_(-1)
+            hthedl.hth_dplan_launch(plan, ws, nb, out)
+            assert np.array_equal(out.cpu().numpy().view(np.uint32), want[100:150])
+        with pytest.raises(hthedl.HthError) as e:
+            hthedl.hth_dplan_launch(plan, ws, nb - 1, out)
+        assert e.value.status == -3
+        with pytest.raises(hthedl.HthError) as e:
+            hthedl.hth_dplan_launch(plan, ws[8:], nb, out)
+        assert e.value.status == -1
+    finally:
+        hthedl.hth_dplan_destroy(plan)
