@@ -308,16 +308,20 @@ hth_status hth_plan_destroy(hth_plan plan);
  * d_nodes [n_nodes], d_hyp_node_offsets [n_hyps + 1] (hypothesis h is
  * d_nodes[offsets[h] .. offsets[h+1]), local child indices; offsets need not
  * start at 0, so a chunk of a larger batch is the same arrays with the offsets
- * pointer advanced), d_children [n_children].  The plan is the paper's
- * per-hypothesis plan: every DL operation of every hypothesis is one task, run
- * level by level on the executor's kernels (no sharing across hypotheses, no
- * shared CSR passes); every node is evaluated, reachable from its root or not.
+ * pointer advanced), d_children [n_children].  Every DL operation of every
+ * hypothesis is one task (identical subexpressions of different hypotheses are
+ * each evaluated on their own; every node is evaluated, reachable from its
+ * root or not), run level by level on the executor's kernels with the kb's schedule:
+ * role nodes of one (level, role, direction) share CSR passes, thresholds on
+ * one property a column pass.
  *
  * hth_dplan_create runs the count pass on `stream` (validation, role-nesting
- * levels, region programs' sizes) and waits for its summary (a few hundred
- * bytes): the only data the host reads.  *ws_bytes receives the workspace that
- * hth_dplan_launch needs.  The plan owns a device buffer of 12 bytes per node
- * and keeps the kb's set table as it was at creation.  The device arrays must
+ * levels, region programs' sizes, table sizes) and waits for its counts (a few
+ * bytes per role direction and property): the only data the host reads; the
+ * host builds the shared passes and the table layout from them.  *ws_bytes
+ * receives the workspace that hth_dplan_launch needs.  The plan owns device
+ * buffers (12 bytes per node, and the shared passes' tables) and keeps the
+ * kb's set table and schedule as they were at creation.  The device arrays must
  * stay allocated and unchanged until the plan's last launch.
  * hth_dplan_launch writes the plan's tables into ws on the device and runs
  * every kernel of the evaluation on `stream`, without waiting; d_counts

@@ -6,16 +6,22 @@
 // device memory (hth_node arrays, as hth_eval_batch takes them on the host),
 // and two passes of one thread per hypothesis build the plan there:
 //   k_dp_count  validates every node, computes each node's role-nesting level,
-//               region-program stack depth and program length, and sums the
-//               table sizes per level into a small summary -- the only data the
-//               host reads back (it sizes the workspace and the launches);
+//               region-program stack depth and program length, and counts the
+//               plan's tables: role nodes per (level, role direction) bucket,
+//               thresholds per property, regions, rows, program words.  The
+//               counts are the only data the host reads back;
+//   (host)      from the counts alone: table bases, the shared CSR passes of
+//               each large bucket (ceil(count / group_k) passes), their T rows
+//               and XCD placement, threshold groups, the workspace layout;
 //   k_dp_emit   assigns bit rows, writes the threshold, role, fill and region
-//               tasks at per-level cursors and writes every region program.
-// The plan is the per-hypothesis plan of the paper: each DL operation of each
-// hypothesis is one task (no subexpression sharing across hypotheses, no
-// shared CSR passes, no push), scheduled level by level on the executor's own
-// kernels.  Every node of a hypothesis is evaluated, reachable from its root
-// or not.  Concrete-role constructs (HTH_NUM_*, HTH_STR_*) are not generated.
+//               tasks and the shared passes' members (and acceptance masks) at
+//               per-table cursors, and writes every region program.
+// Each DL operation of each hypothesis is one task: subexpressions are not
+// shared across hypotheses (the host compiler's hash-consing), and single
+// existential restrictions are not pushed; role nodes of one bucket still
+// share CSR passes, and thresholds on one property a column pass.  Every node
+// of a hypothesis is evaluated, reachable from its root or not.
+// Concrete-role constructs (HTH_NUM_*, HTH_STR_*) are not generated.
 // Included by exec.hip only.
 #pragma once
 
@@ -35,12 +41,22 @@ enum : uint32_t {
 struct DpSummary {
   unsigned long long err;       // lowest (hypothesis << 32 | node << 8 | reason); ~0 = none
   unsigned long long code;      // region-program instructions of all regions
-  unsigned long long nhb[kDpLevels], nhc[kDpLevels];   // heavy-row blocks / (task, heavy row) pairs
   uint32_t levels, mat_depth, root_depth, pad;         // maxima
-  uint32_t n_thr, n_slots;      // sums (contiguous with the per-level arrays below)
-  uint32_t mat[kDpLevels], role[kDpLevels], fill[kDpLevels];
+  uint32_t n_thr, n_slots;      // sums (contiguous with the per-level array below)
+  uint32_t mat[kDpLevels];
 };
-constexpr int kDpSums = 2 + 3 * kDpLevels;
+constexpr int kDpSums = 2 + kDpLevels;
+
+// Role nodes are counted per bucket (level, direction 2r + dir): bk[0][L][rd]
+// those a shared pass can decide (see GroupTask), bk[1][L][rd] the others.
+// The host turns the counts into the buckets' shared passes (DpBucket) and the
+// per-level tables of the role nodes that run alone.
+struct DpBucket {
+  uint32_t first_group;          // the bucket's first shared pass; kNone: its nodes run alone
+  uint32_t member_base;          // member table index of that pass's first member
+  uint32_t k;                    // members per pass (the last may hold fewer)
+  uint32_t pad;
+};
 
 struct DpCursor {                // allocation cursors of the emit pass
   unsigned long long code;
@@ -50,6 +66,7 @@ struct DpCursor {                // allocation cursors of the emit pass
 
 struct DpBases {                 // each level's first entry in the task tables
   uint32_t mat[kDpLevels], role[kDpLevels], fill[kDpLevels];
+  uint32_t nrole[kDpLevels];     // role nodes that run alone, per level
 };
 
 struct DpKB {                    // what the passes read of the knowledge base
@@ -57,16 +74,22 @@ struct DpKB {                    // what the passes read of the knowledge base
   uint32_t n_fixed;              // the first slot row: the all-zero row
   uint32_t n_dir;                // 2 R + 1
   const uint32_t* dir;           // [3][2R+1]: non-empty words, first heavy chunk, first heavy row
+  uint32_t* pk;                  // [n_data] thresholds per property (count pass)
 };
 
 struct DpTables {
   ThrTask* thr;
-  ThrGroup* thg;
   RegionTask* mat;
   RegionTask* roots;
   RoleTask* roles;
   FillTask* fills;               // fills[0]: the zero row
   uint32_t* code;
+  GroupTask* groups;             // the shared passes (copied from the plan's shells each launch)
+  GroupMember* members;
+  const DpBucket* buckets;       // [kDpLevels][2R]
+  uint32_t* bcur;                // [kDpLevels][2R] member cursors
+  const uint32_t* pbase;         // [n_data] first threshold task of each property
+  uint32_t* pcur;                // [n_data] threshold cursors
 };
 
 // per-node facts of the count pass: bits 0-7 role-nesting height + 1 (0: no
@@ -88,23 +111,28 @@ __device__ __forceinline__ uint32_t dp_heavy(const DpKB& K, uint32_t rd) {
   return K.dir[2 * K.n_dir + rd + 1] - K.dir[2 * K.n_dir + rd];
 }
 
+// a shared pass decides the node (saturating counts up to kGroupMaxCount)
+__device__ __forceinline__ bool dp_groupable(const hth_node& x) {
+  return x.op == HTH_EXISTS || x.op == HTH_FORALL ||
+         (x.op == HTH_ATLEAST ? x.q.n <= kGroupMaxCount : x.q.n < kGroupMaxCount);
+}
+
 __global__ void __launch_bounds__(256)
 k_dp_count(const hth_node* __restrict__ nodes, const uint32_t* __restrict__ offs,
            const uint32_t* __restrict__ kids, uint32_t n_nodes, uint32_t n_kids, uint32_t n_hyps, DpKB K,
-           uint32_t* __restrict__ info, uint32_t* __restrict__ len, DpSummary* __restrict__ sum) {
+           uint32_t* __restrict__ info, uint32_t* __restrict__ len, DpSummary* __restrict__ sum,
+           uint32_t* __restrict__ bk) {
   __shared__ uint32_t s_sum[kDpSums];
-  __shared__ unsigned long long s_nhb[kDpLevels], s_nhc[kDpLevels], s_code;
+  __shared__ unsigned long long s_code;
   __shared__ uint32_t s_max[3];
   for (uint32_t i = threadIdx.x; i < kDpSums; i += blockDim.x) s_sum[i] = 0;
-  if (threadIdx.x < kDpLevels) s_nhb[threadIdx.x] = s_nhc[threadIdx.x] = 0;
   if (threadIdx.x < 3) s_max[threadIdx.x] = 0;
   if (threadIdx.x == 0) s_code = 0;
   __syncthreads();
   uint32_t* const s_thr = s_sum;
   uint32_t* const s_slots = s_sum + 1;
   uint32_t* const s_mat = s_sum + 2;
-  uint32_t* const s_role = s_mat + kDpLevels;
-  uint32_t* const s_fill = s_role + kDpLevels;
+  const uint32_t nbk = kDpLevels * (K.n_dir - 1);
   const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
   if (h < n_hyps) {
     auto err = [&](uint32_t node, uint32_t why) {
@@ -143,6 +171,7 @@ k_dp_count(const hth_node* __restrict__ nodes, const uint32_t* __restrict__ offs
           if (x.arg >= K.n_data) why = DP_PROP;
           else if (x.q.t != x.q.t) why = DP_NAN;
           flags = kDpRow;
+          if (!why) atomicAdd(K.pk + x.arg, 1u);
           atomicAdd(s_thr, 1u);
           atomicAdd(s_slots, 1u);
           break;
@@ -230,13 +259,8 @@ k_dp_count(const hth_node* __restrict__ nodes, const uint32_t* __restrict__ offs
             atomicMax(s_max + 1, (ci >> 8) & 255u);
           }
           const uint32_t rd = 2 * x.arg + x.inv;
-          atomicAdd(s_role + lvl, 1u);
+          atomicAdd(bk + (dp_groupable(x) ? 0u : nbk) + lvl * (K.n_dir - 1) + rd, 1u);
           atomicAdd(s_slots, 1u);
-          if (dp_nwords(K, rd) < K.W) atomicAdd(s_fill + lvl, 1u);
-          if (const uint32_t nb = dp_chunks(K, rd)) {
-            atomicAdd(s_nhb + lvl, (unsigned long long)nb);
-            atomicAdd(s_nhc + lvl, (unsigned long long)dp_heavy(K, rd));
-          }
           atomicMax(s_max, lvl + 1);
           break;
         }
@@ -272,10 +296,6 @@ k_dp_count(const hth_node* __restrict__ nodes, const uint32_t* __restrict__ offs
   uint32_t* const out = &sum->n_thr;
   for (uint32_t i = threadIdx.x; i < kDpSums; i += blockDim.x)
     if (s_sum[i]) atomicAdd(out + i, s_sum[i]);
-  if (threadIdx.x < kDpLevels) {
-    if (s_nhb[threadIdx.x]) atomicAdd(&sum->nhb[threadIdx.x], s_nhb[threadIdx.x]);
-    if (s_nhc[threadIdx.x]) atomicAdd(&sum->nhc[threadIdx.x], s_nhc[threadIdx.x]);
-  }
   if (threadIdx.x == 0) {
     atomicMax(&sum->levels, s_max[0]);
     atomicMax(&sum->mat_depth, s_max[1]);
@@ -373,14 +393,14 @@ k_dp_emit(const hth_node* __restrict__ nodes, const uint32_t* __restrict__ offs,
     if (dp_column(x.op)) {
       const uint32_t r = K.n_fixed + 1 + atomicAdd(&cur->slots, 1u);
       row[b + i] = r;
-      const uint32_t t = atomicAdd(&cur->thr, 1u);
+      // the property's tasks are contiguous: one column pass serves up to 32
+      const uint32_t t = T.pbase[x.arg] + atomicAdd(T.pcur + x.arg, 1u);
       ThrTask tt;
       tt.prop = x.arg;
       tt.cmp = x.op == HTH_DATA_GE ? 0u : x.op == HTH_DATA_LE ? 1u : 2u;
       tt.t = x.q.t;
       tt.out_row = r;
       T.thr[t] = tt;
-      T.thg[t] = ThrGroup{x.arg, t, 1u, 0u};
     } else if (dp_role(x.op)) {
       const uint32_t r = K.n_fixed + 1 + atomicAdd(&cur->slots, 1u);
       row[b + i] = r;
@@ -413,6 +433,32 @@ k_dp_emit(const hth_node* __restrict__ nodes, const uint32_t* __restrict__ offs,
         default: lo = x.q.n; hi = x.q.n; break;
       }
       const uint32_t rd = 2 * x.arg + x.inv;
+      const uint32_t nw = dp_nwords(K, rd);
+      if (nw < K.W)
+        T.fills[B.fill[lvl] + atomicAdd(&cur->fill[lvl], 1u)] = FillTask{r, lo == 0 ? 1u : 0u};
+      const uint32_t q = lvl * (K.n_dir - 1) + rd;
+      const DpBucket bu = T.buckets[q];
+      if (bu.first_group != kNone && dp_groupable(x)) {
+        // a member of one of its bucket's shared passes
+        const uint32_t j = atomicAdd(T.bcur + q, 1u);
+        GroupMember m;
+        m.child_row = crow;
+        m.neg = neg;
+        m.lo = lo;
+        m.hi = hi;
+        m.sat = hi == kInf ? lo : hi + 1;
+        m.out_row = r;
+        m.pad0 = m.pad1 = 0;
+        T.members[bu.member_base + j] = m;
+        unsigned long long* acc =
+            reinterpret_cast<unsigned long long*>(T.groups[bu.first_group + j / bu.k].acc);
+        const unsigned long long bit = 1ull << (j % bu.k);
+        for (uint32_t v = 0; v <= kGroupMaxCount; ++v) {
+          const bool ok = v < kGroupMaxCount ? (lo <= v && v <= hi) : (hi == kInf && lo <= kGroupMaxCount);
+          if (ok) atomicOr(acc + v, bit);
+        }
+        continue;
+      }
       RoleTask t;
       t.role = x.arg;
       t.inv = x.inv;
@@ -422,14 +468,12 @@ k_dp_emit(const hth_node* __restrict__ nodes, const uint32_t* __restrict__ offs,
       t.hi = hi;
       t.sat = hi == kInf ? lo : hi + 1;
       t.out_row = r;
-      t.n_words = dp_nwords(K, rd);
+      t.n_words = nw;
       t.h_first = 0;                         // set by k_dp_heavy where heavy rows exist
       t.c_first = 0;
       t.hc0 = K.dir[K.n_dir + rd];
       t.hr0 = K.dir[2 * K.n_dir + rd];
       T.roles[B.role[lvl] + atomicAdd(&cur->role[lvl], 1u)] = t;
-      if (t.n_words < K.W)
-        T.fills[B.fill[lvl] + atomicAdd(&cur->fill[lvl], 1u)] = FillTask{r, lo == 0 ? 1u : 0u};
     }
   }
   const unsigned long long off = atomicAdd(&cur->code, (unsigned long long)len[b + n - 1]);
@@ -469,10 +513,10 @@ __device__ __forceinline__ uint32_t dp_block_scan(uint32_t v, uint32_t* s_w, uin
 // order (k_role_heavy finds a block's task by binary search over them).
 // One 1024-lane block per level.
 __global__ void __launch_bounds__(1024)
-k_dp_heavy(RoleTask* __restrict__ roles, DpBases B, const DpSummary* __restrict__ sum, DpKB K) {
+k_dp_heavy(RoleTask* __restrict__ roles, DpBases B, DpKB K) {
   __shared__ uint32_t s_w[17];
   const uint32_t L = blockIdx.x;
-  const uint32_t n = sum->role[L], base = B.role[L];
+  const uint32_t n = B.nrole[L], base = B.role[L];
   uint32_t carry_b = 0, carry_c = 0;
   for (uint32_t i0 = 0; i0 < n; i0 += blockDim.x) {
     const uint32_t i = i0 + threadIdx.x;
@@ -495,6 +539,13 @@ k_dp_heavy(RoleTask* __restrict__ roles, DpBases B, const DpSummary* __restrict_
   }
 }
 
+// dst[i] = src[i] for i < n (the shared passes' shells, fresh for each launch)
+__global__ void __launch_bounds__(256)
+k_dp_copy(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
 }  // namespace
 }  // namespace hth
 
@@ -507,19 +558,35 @@ struct hth_dplan_s {
   uint32_t n_nodes = 0, n_hyps = 0, n_kids = 0;
   const uint64_t* sets = nullptr;
   uint32_t n_sets = 0;
-  char* buf = nullptr;                // per-node facts and rows, summary, cursors, direction table
+  char* buf = nullptr;     // per-node facts and rows, summary, cursors, bucket counts, direction table
+  char* buf2 = nullptr;    // shared-pass shells, bucket table, XCD slot table, bucket cursors
   uint32_t* info = nullptr;
   uint32_t* len = nullptr;
   uint32_t* row = nullptr;
   hth::DpSummary* d_sum = nullptr;
   hth::DpCursor* d_cur = nullptr;
+  uint32_t* d_bk = nullptr;
+  hth::GroupTask* d_shells = nullptr;
+  hth::DpBucket* d_buckets = nullptr;
+  uint32_t* d_xslots = nullptr;
+  uint32_t* d_bcur = nullptr;
+  uint32_t* d_pbase = nullptr;        // first threshold task of each property
+  uint32_t* d_pcur = nullptr;
+  hth::ThrGroup* d_thg = nullptr;     // threshold groups: up to 32 tasks of one property
+  uint32_t n_buckets = 0, n_thg = 0;
   hth::DpKB K{};
   hth::DpSummary sum{};
   hth::DpBases B{};
-  uint32_t n_mat = 0, n_role = 0, n_fill = 0;
+  uint32_t n_mat = 0, n_role = 0, n_fill = 0, n_groups = 0, n_members = 0;
+  uint32_t fills[hth::kDpLevels] = {};
+  uint64_t nhb[hth::kDpLevels] = {}, nhc[hth::kDpLevels] = {};
   uint64_t max_nhb = 0;
-  size_t o_thr = 0, o_thg = 0, o_mat = 0, o_root = 0, o_role = 0, o_fill = 0, o_code = 0, o_part = 0,
-         o_slot = 0, need = 0;
+  std::vector<std::vector<hth::GroupTask>> lv_groups;
+  std::vector<std::vector<hth::GroupChunk>> lv_chunks;
+  std::vector<size_t> lv_gbase;
+  size_t o_thr = 0, o_mat = 0, o_root = 0, o_role = 0, o_fill = 0, o_code = 0, o_part = 0,
+         o_grp = 0, o_mem = 0, o_tarea = 0, o_gpart = 0, o_slot = 0, need = 0;
+  hth_kb_s::Tuning tune;              // the schedule the plan was laid out for
   hipEvent_t done = nullptr;          // recorded after each launch: destroy waits for it
   ~hth_dplan_s() {
     if (done) {
@@ -527,6 +594,7 @@ struct hth_dplan_s {
       (void)hipEventDestroy(done);
     }
     if (buf) (void)hipFree(buf);
+    if (buf2) (void)hipFree(buf2);
   }
 };
 
@@ -555,6 +623,95 @@ const char* dp_reason(uint32_t why, hth_status* code) {
   }
 }
 
+// The host's part of a device plan: from the count pass's summary and bucket
+// counts, the per-level table bases, the shared passes (a bucket with at least
+// group_min decidable nodes gets ceil(count / group_k) passes, its nodes taken
+// in the order the emit pass reaches them), their T rows and XCD placement,
+// and the workspace layout.
+hth_status dp_schedule(hth_dplan_s& p, const std::vector<uint32_t>& bk, std::vector<DpBucket>& buckets,
+                       std::vector<uint32_t>& xslots) {
+  const hth_kb_s& kb = *p.kb;
+  const DpSummary& S = p.sum;
+  const uint32_t R2 = p.K.n_dir - 1, nbk = kDpLevels * R2;
+  const uint32_t group_min = kb.tune.group_min ? kb.tune.group_min : 0xFFFFFFFFu;
+  const uint32_t gk = std::max<uint32_t>(1, std::min<uint32_t>(kb.tune.group_k, kMaxK));
+  buckets.assign(nbk, DpBucket{kNone, 0, 0, 0});
+  p.lv_groups.assign(S.levels, {});
+  p.lv_chunks.assign(S.levels, {});
+  p.lv_gbase.assign(S.levels, 0);
+  uint32_t fill = 1;                        // fills[0]: the zero row
+  for (uint32_t L = 0; L < kDpLevels; ++L) {
+    p.B.mat[L] = p.n_mat;
+    p.B.role[L] = p.n_role;
+    p.B.fill[L] = fill;
+    p.n_mat += S.mat[L];
+    if (L >= S.levels) continue;
+    uint64_t solo = 0, nb = 0, nc = 0, nf = 0;
+    for (uint32_t rd = 0; rd < R2; ++rd) {
+      const uint64_t g = bk[L * R2 + rd], o = bk[nbk + L * R2 + rd];
+      const bool grouped = g && g >= group_min;
+      const uint64_t alone = o + (grouped ? 0 : g);
+      solo += alone;
+      nb += alone * (kb.chunk_first[rd + 1] - kb.chunk_first[rd]);
+      nc += alone * (kb.heavy_first[rd + 1] - kb.heavy_first[rd]);
+      if (kb.n_words[rd] < kb.W) nf += g + o;
+      if (!grouped) continue;
+      DpBucket& bu = buckets[L * R2 + rd];
+      bu.first_group = p.n_groups + (uint32_t)p.lv_groups[L].size();
+      bu.member_base = p.n_members;
+      bu.k = gk;
+      for (uint64_t i0 = 0; i0 < g; i0 += gk) {
+        GroupTask gt{};
+        gt.role = rd / 2;
+        gt.inv = rd & 1;
+        gt.k = (uint32_t)std::min<uint64_t>(gk, g - i0);
+        gt.first = (uint32_t)(p.n_members + i0);
+        gt.n_words = kb.n_words[rd];
+        gt.compact = kb.tune.t_compact && 2ull * kb.n_obj[rd] <= kb.N;
+        p.lv_groups[L].push_back(gt);
+      }
+      p.n_members += (uint32_t)g;
+    }
+    if (nb >= (1ull << 32) || nc >= (1ull << 32)) return fail(HTH_E_RANGE, "heavy-row blocks of one level exceed 2^32");
+    p.B.nrole[L] = (uint32_t)solo;
+    p.n_role += (uint32_t)solo;
+    p.fills[L] = (uint32_t)nf;
+    fill += (uint32_t)nf;
+    p.nhb[L] = nb;
+    p.nhc[L] = nc;
+    p.max_nhb = std::max(p.max_nhb, nb);
+    p.lv_gbase[L] = p.n_groups;
+    p.lv_chunks[L] = chunk_groups(kb, p.lv_groups[L]);
+    for (GroupChunk& c : p.lv_chunks[L])
+      if (kb.tune.xcd_local && c.n >= 8) place_on_xcds(kb, p.lv_groups[L], c, xslots);
+    p.n_groups += (uint32_t)p.lv_groups[L].size();
+  }
+  p.n_fill = fill;
+  size_t gpart = 0;
+  for (uint32_t L = 0; L < S.levels; ++L)
+    for (const GroupChunk& c : p.lv_chunks[L]) gpart = std::max(gpart, chunk_partial_bytes(kb, p.lv_groups[L], c));
+  size_t at = 0;
+  auto area = [&](size_t bytes) {
+    const size_t a = at;
+    at = align_up(at + bytes, 256);
+    return a;
+  };
+  p.o_thr = area((size_t)S.n_thr * sizeof(ThrTask));
+  p.o_mat = area((size_t)p.n_mat * sizeof(RegionTask));
+  p.o_root = area((size_t)p.n_hyps * sizeof(RegionTask));
+  p.o_role = area((size_t)p.n_role * sizeof(RoleTask));
+  p.o_fill = area((size_t)fill * sizeof(FillTask));
+  p.o_code = area((size_t)S.code * 4);
+  p.o_part = area((size_t)p.max_nhb * 4);
+  p.o_grp = area((size_t)p.n_groups * sizeof(GroupTask));
+  p.o_mem = area((size_t)p.n_members * sizeof(GroupMember));
+  p.o_tarea = area(p.n_groups ? t_area_bytes(kb) : 0);
+  p.o_gpart = area(gpart);
+  p.o_slot = area(((size_t)S.n_slots + 1) * kb.S * 8);
+  p.need = at;
+  return HTH_OK;
+}
+
 }  // namespace
 }  // namespace hth
 
@@ -579,28 +736,32 @@ extern "C" hth_status hth_dplan_create(hth_kb kb, const hth_node* d_nodes, uint3
   p->n_hyps = n_hyps;
   p->n_kids = n_children;
   std::vector<uint32_t> dir;
-  {
-    std::lock_guard<std::mutex> g(kb->mu);
-    p->sets = kb->sets;
-    p->n_sets = kb->n_sets;
-    const uint32_t nd = 2 * kb->d.n_roles + 1;
-    dir.assign(3 * (size_t)nd, 0);
-    for (uint32_t rd = 0; rd + 1 < nd; ++rd) dir[rd] = kb->n_words[rd];
-    for (uint32_t rd = 0; rd < nd; ++rd) {
-      dir[nd + rd] = kb->chunk_first[rd];
-      dir[2 * nd + rd] = kb->heavy_first[rd];
-    }
-    p->K.n_concepts = kb->d.n_concepts;
-    p->K.n_sets = kb->n_sets;
-    p->K.n_roles = kb->d.n_roles;
-    p->K.n_data = kb->d.n_data;
-    p->K.W = kb->W;
-    p->K.n_fixed = kb->d.n_concepts + kb->n_sets;
-    p->K.n_dir = nd;
+  std::lock_guard<std::mutex> g(kb->mu);
+  p->sets = kb->sets;
+  p->n_sets = kb->n_sets;
+  p->tune = kb->tune;
+  const uint32_t nd = 2 * kb->d.n_roles + 1;
+  dir.assign(3 * (size_t)nd, 0);
+  for (uint32_t rd = 0; rd + 1 < nd; ++rd) dir[rd] = kb->n_words[rd];
+  for (uint32_t rd = 0; rd < nd; ++rd) {
+    dir[nd + rd] = kb->chunk_first[rd];
+    dir[2 * nd + rd] = kb->heavy_first[rd];
   }
+  p->K.n_concepts = kb->d.n_concepts;
+  p->K.n_sets = kb->n_sets;
+  p->K.n_roles = kb->d.n_roles;
+  p->K.n_data = kb->d.n_data;
+  p->K.W = kb->W;
+  p->K.n_fixed = kb->d.n_concepts + kb->n_sets;
+  p->K.n_dir = nd;
+  p->n_buckets = kDpLevels * (nd - 1);
+  const size_t nbk2 = 2 * (size_t)p->n_buckets;
   const size_t o_info = 0, o_len = align_up((size_t)n_nodes * 4, 256), o_row = o_len + o_len;
   const size_t o_sum = o_row + o_len, o_cur = o_sum + align_up(sizeof(DpSummary), 256);
-  const size_t o_dir = o_cur + align_up(sizeof(DpCursor), 256);
+  const size_t o_bk = o_cur + align_up(sizeof(DpCursor), 256);
+  const size_t o_pk = o_bk + align_up(nbk2 * 4, 256);
+  const size_t nd_data = kb->d.n_data;
+  const size_t o_dir = o_pk + align_up(nd_data * 4, 256);
   const size_t total = o_dir + dir.size() * 4;
   HTH_HIP(hipMalloc(reinterpret_cast<void**>(&p->buf), total));
   HTH_HIP(hipEventCreateWithFlags(&p->done, hipEventDisableTiming));
@@ -609,15 +770,23 @@ extern "C" hth_status hth_dplan_create(hth_kb kb, const hth_node* d_nodes, uint3
   p->row = reinterpret_cast<uint32_t*>(p->buf + o_row);
   p->d_sum = reinterpret_cast<DpSummary*>(p->buf + o_sum);
   p->d_cur = reinterpret_cast<DpCursor*>(p->buf + o_cur);
+  p->d_bk = reinterpret_cast<uint32_t*>(p->buf + o_bk);
   p->K.dir = reinterpret_cast<const uint32_t*>(p->buf + o_dir);
+  p->K.pk = reinterpret_cast<uint32_t*>(p->buf + o_pk);
   HTH_HIP(hipMemcpyAsync(p->buf + o_dir, dir.data(), dir.size() * 4, hipMemcpyHostToDevice, st));
   DpSummary init{};
   init.err = ~0ull;
   HTH_HIP(hipMemcpyAsync(p->d_sum, &init, sizeof(init), hipMemcpyHostToDevice, st));
+  HTH_HIP(hipMemsetAsync(p->d_bk, 0, nbk2 * 4, st));
+  if (nd_data) HTH_HIP(hipMemsetAsync(p->K.pk, 0, nd_data * 4, st));
   hipLaunchKernelGGL(k_dp_count, dim3((n_hyps + 255) / 256), dim3(256), 0, st, d_nodes, d_hyp_node_offsets,
-                     d_children, n_nodes, n_children, n_hyps, p->K, p->info, p->len, p->d_sum);
+                     d_children, n_nodes, n_children, n_hyps, p->K, p->info, p->len, p->d_sum, p->d_bk);
   HTH_HIP(hipGetLastError());
+  std::vector<uint32_t> bk(nbk2);
   HTH_HIP(hipMemcpyAsync(&p->sum, p->d_sum, sizeof(DpSummary), hipMemcpyDeviceToHost, st));
+  HTH_HIP(hipMemcpyAsync(bk.data(), p->d_bk, nbk2 * 4, hipMemcpyDeviceToHost, st));
+  std::vector<uint32_t> pk(nd_data);
+  if (nd_data) HTH_HIP(hipMemcpyAsync(pk.data(), p->K.pk, nd_data * 4, hipMemcpyDeviceToHost, st));
   HTH_HIP(hipStreamSynchronize(st));
   const DpSummary& S = p->sum;
   if (S.err != ~0ull) {
@@ -629,35 +798,46 @@ extern "C" hth_status hth_dplan_create(hth_kb kb, const hth_node* d_nodes, uint3
   if (S.code >= (1ull << 32)) return fail(HTH_E_RANGE, "region programs exceed 2^32 instructions");
   // row ids must fit the 27-bit argument of the region bytecode
   if ((uint64_t)p->K.n_fixed + 1 + S.n_slots >= (1ull << 27)) return fail(HTH_E_RANGE, "too many bit rows");
-  uint32_t fill = 1;                        // fills[0]: the zero row
-  for (uint32_t L = 0; L < kDpLevels; ++L) {
-    if (S.nhb[L] >= (1ull << 32) || S.nhc[L] >= (1ull << 32))
-      return fail(HTH_E_RANGE, "heavy-row blocks of one level exceed 2^32");
-    p->B.mat[L] = p->n_mat;
-    p->B.role[L] = p->n_role;
-    p->B.fill[L] = fill;
-    p->n_mat += S.mat[L];
-    p->n_role += S.role[L];
-    fill += S.fill[L];
-    p->max_nhb = std::max<uint64_t>(p->max_nhb, S.nhb[L]);
+  std::vector<DpBucket> buckets;
+  std::vector<uint32_t> xslots;
+  hth_status s = dp_schedule(*p, bk, buckets, xslots);
+  if (s) return s;
+  std::vector<GroupTask> shells;
+  for (const auto& lg : p->lv_groups) shells.insert(shells.end(), lg.begin(), lg.end());
+  // thresholds: each property's tasks together, in groups of at most 32
+  std::vector<uint32_t> pbase(nd_data);
+  std::vector<ThrGroup> thg;
+  uint32_t tsum = 0;
+  for (uint32_t q = 0; q < nd_data; ++q) {
+    pbase[q] = tsum;
+    for (uint32_t i = 0; i < pk[q]; i += 32) thg.push_back(ThrGroup{q, tsum + i, std::min<uint32_t>(32, pk[q] - i), 0});
+    tsum += pk[q];
   }
-  p->n_fill = fill;
-  size_t at = 0;
-  auto area = [&](size_t bytes) {
-    const size_t a = at;
-    at = align_up(at + bytes, 256);
-    return a;
-  };
-  p->o_thr = area((size_t)S.n_thr * sizeof(ThrTask));
-  p->o_thg = area((size_t)S.n_thr * sizeof(ThrGroup));
-  p->o_mat = area((size_t)p->n_mat * sizeof(RegionTask));
-  p->o_root = area((size_t)n_hyps * sizeof(RegionTask));
-  p->o_role = area((size_t)p->n_role * sizeof(RoleTask));
-  p->o_fill = area((size_t)fill * sizeof(FillTask));
-  p->o_code = area((size_t)S.code * 4);
-  p->o_part = area((size_t)p->max_nhb * 4);
-  p->o_slot = area(((size_t)S.n_slots + 1) * kb->S * 8);
-  p->need = at;
+  if (tsum != S.n_thr) return fail(HTH_E_DEVICE, "threshold counts disagree");
+  p->n_thg = (uint32_t)thg.size();
+  const size_t b_shell = 0, b_bucket = align_up(shells.size() * sizeof(GroupTask), 256);
+  const size_t b_xslot = b_bucket + align_up(buckets.size() * sizeof(DpBucket), 256);
+  const size_t b_bcur = b_xslot + align_up(xslots.size() * 4, 256);
+  const size_t b_thg = b_bcur + align_up((size_t)p->n_buckets * 4, 256);
+  const size_t b_pbase = b_thg + align_up(thg.size() * sizeof(ThrGroup), 256);
+  const size_t b_pcur = b_pbase + align_up(nd_data * 4, 256);
+  HTH_HIP(hipMalloc(reinterpret_cast<void**>(&p->buf2), b_pcur + nd_data * 4 + 4));
+  p->d_shells = reinterpret_cast<GroupTask*>(p->buf2 + b_shell);
+  p->d_buckets = reinterpret_cast<DpBucket*>(p->buf2 + b_bucket);
+  p->d_xslots = reinterpret_cast<uint32_t*>(p->buf2 + b_xslot);
+  p->d_bcur = reinterpret_cast<uint32_t*>(p->buf2 + b_bcur);
+  p->d_thg = reinterpret_cast<ThrGroup*>(p->buf2 + b_thg);
+  p->d_pbase = reinterpret_cast<uint32_t*>(p->buf2 + b_pbase);
+  p->d_pcur = reinterpret_cast<uint32_t*>(p->buf2 + b_pcur);
+  if (!thg.empty())
+    HTH_HIP(hipMemcpyAsync(p->d_thg, thg.data(), thg.size() * sizeof(ThrGroup), hipMemcpyHostToDevice, st));
+  if (nd_data) HTH_HIP(hipMemcpyAsync(p->d_pbase, pbase.data(), nd_data * 4, hipMemcpyHostToDevice, st));
+  if (!shells.empty())
+    HTH_HIP(hipMemcpyAsync(p->d_shells, shells.data(), shells.size() * sizeof(GroupTask), hipMemcpyHostToDevice, st));
+  HTH_HIP(hipMemcpyAsync(p->d_buckets, buckets.data(), buckets.size() * sizeof(DpBucket), hipMemcpyHostToDevice, st));
+  if (!xslots.empty())
+    HTH_HIP(hipMemcpyAsync(p->d_xslots, xslots.data(), xslots.size() * 4, hipMemcpyHostToDevice, st));
+  HTH_HIP(hipStreamSynchronize(st));   // the host vectors above end here
   *ws_bytes = p->need;
   *out = guard.release();
   return HTH_OK;
@@ -675,16 +855,22 @@ extern "C" hth_status hth_dplan_launch(hth_dplan plan, void* ws, size_t ws_bytes
   const hipStream_t st = static_cast<hipStream_t>(stream);
   hth_kb_s& kb = *p.kb;
   std::lock_guard<std::mutex> g(kb.mu);
+  TuneScope ts(kb, p.tune);
   role_attributes(kb);
   char* w = static_cast<char*>(ws);
   DpTables T;
   T.thr = reinterpret_cast<ThrTask*>(w + p.o_thr);
-  T.thg = reinterpret_cast<ThrGroup*>(w + p.o_thg);
   T.mat = reinterpret_cast<RegionTask*>(w + p.o_mat);
   T.roots = reinterpret_cast<RegionTask*>(w + p.o_root);
   T.roles = reinterpret_cast<RoleTask*>(w + p.o_role);
   T.fills = reinterpret_cast<FillTask*>(w + p.o_fill);
   T.code = reinterpret_cast<uint32_t*>(w + p.o_code);
+  T.groups = reinterpret_cast<GroupTask*>(w + p.o_grp);
+  T.members = reinterpret_cast<GroupMember*>(w + p.o_mem);
+  T.buckets = p.d_buckets;
+  T.bcur = p.d_bcur;
+  T.pbase = p.d_pbase;
+  T.pcur = p.d_pcur;
   DevKB d = dev_view(kb);
   d.sets = p.sets;
   d.n_fixed = p.K.n_fixed;
@@ -697,6 +883,18 @@ extern "C" hth_status hth_dplan_launch(hth_dplan plan, void* ws, size_t ws_bytes
   const uint32_t ncur = (uint32_t)(sizeof(DpCursor) / 4);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, st, reinterpret_cast<uint32_t*>(p.d_cur), ncur);
   HTH_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_zero_u32, dim3((p.n_buckets + 255) / 256), dim3(256), 0, st, p.d_bcur, p.n_buckets);
+  HTH_HIP(hipGetLastError());
+  if (p.K.n_data) {
+    hipLaunchKernelGGL(k_zero_u32, dim3((p.K.n_data + 255) / 256), dim3(256), 0, st, p.d_pcur, p.K.n_data);
+    HTH_HIP(hipGetLastError());
+  }
+  if (p.n_groups) {
+    const uint32_t nw = (uint32_t)(p.n_groups * sizeof(GroupTask) / 4);
+    hipLaunchKernelGGL(k_dp_copy, dim3((nw + 255) / 256), dim3(256), 0, st, reinterpret_cast<uint32_t*>(T.groups),
+                       reinterpret_cast<const uint32_t*>(p.d_shells), nw);
+    HTH_HIP(hipGetLastError());
+  }
   const DpSummary& S = p.sum;
   Launcher Lc{kb, st};
   hth_status s = Lc.run(HTH_K_PLAN, 0.0, [&] {
@@ -705,10 +903,10 @@ extern "C" hth_status hth_dplan_launch(hth_dplan plan, void* ws, size_t ws_bytes
   });
   if (s) return s;
   bool heavy = false;
-  for (uint32_t L = 0; L < S.levels; ++L) heavy |= S.nhc[L] > 0;
+  for (uint32_t L = 0; L < S.levels; ++L) heavy |= p.nhc[L] > 0;
   if (heavy) {
     s = Lc.run(HTH_K_PLAN, 0.0, [&] {
-      hipLaunchKernelGGL(k_dp_heavy, dim3(S.levels), dim3(1024), 0, st, T.roles, p.B, p.d_sum, p.K);
+      hipLaunchKernelGGL(k_dp_heavy, dim3(S.levels), dim3(1024), 0, st, T.roles, p.B, p.K);
     });
     if (s) return s;
   }
@@ -717,37 +915,43 @@ extern "C" hth_status hth_dplan_launch(hth_dplan plan, void* ws, size_t ws_bytes
     hipLaunchKernelGGL(k_fill_rows, dim3(ftiles), dim3(256), 0, st, d, T.fills, ftiles);
   });
   if (s) return s;
-  if (S.n_thr) {
-    const uint32_t n = S.n_thr, bpt = std::max<uint32_t>(1, (kb.W + 127) / 128);
-    const double bytes = n * (4.0 * kb.N + 8.0 * kb.W);
+  if (p.n_thg) {
+    const uint32_t n = p.n_thg, bpt = std::max<uint32_t>(1, (kb.W + 127) / 128);
+    const double bytes = n * 4.0 * kb.N + S.n_thr * 8.0 * kb.W;
     s = split_launch(Lc, HTH_K_THRESHOLD, bytes, n, bpt, 256, [&](uint32_t i0, uint32_t, uint32_t blocks) {
-      hipLaunchKernelGGL(k_threshold, dim3(blocks), dim3(256), 0, st, d, T.thg + i0, T.thr, bpt);
+      hipLaunchKernelGGL(k_threshold, dim3(blocks), dim3(256), 0, st, d, p.d_thg + i0, T.thr, bpt);
     });
     if (s) return s;
   }
+  void* tarea = w + p.o_tarea;
   for (uint32_t L = 0; L < S.levels; ++L) {
     s = launch_regions_n(Lc, d, T.mat + p.B.mat[L], T.code, S.mat[L], (int)S.mat_depth, 0.0);
     if (s) return s;
-    if (S.fill[L]) {
-      const uint32_t n = S.fill[L];
+    if (p.fills[L]) {
+      const uint32_t n = p.fills[L];
       s = split_launch(Lc, HTH_K_FILL, (double)n * kb.W * 8, n, ftiles, 256, [&](uint32_t i0, uint32_t, uint32_t blocks) {
         hipLaunchKernelGGL(k_fill_rows, dim3(blocks), dim3(256), 0, st, d, T.fills + p.B.fill[L] + i0, ftiles);
       });
       if (s) return s;
     }
     const RoleTask* rol = T.roles + p.B.role[L];
-    s = launch_roles_n(Lc, d, rol, S.role[L], 0.0);
+    const uint32_t nt = p.B.nrole[L];
+    s = launch_roles_n(Lc, d, rol, nt, 0.0);
     if (s) return s;
-    if (S.nhc[L]) {
+    if (p.nhc[L]) {
       uint32_t* partial = reinterpret_cast<uint32_t*>(w + p.o_part);
-      const uint32_t nt = S.role[L];
-      s = split_launch(Lc, HTH_K_ROLE, 0.0, S.nhb[L], 1, 256, [&](uint32_t b0, uint32_t, uint32_t blocks) {
+      s = split_launch(Lc, HTH_K_ROLE, 0.0, p.nhb[L], 1, 256, [&](uint32_t b0, uint32_t, uint32_t blocks) {
         hipLaunchKernelGGL(k_role_heavy, dim3(blocks), dim3(256), 0, st, d, rol, nt, b0, partial);
       });
       if (s) return s;
-      s = split_launch(Lc, HTH_K_ROLE, 0.0, S.nhc[L], 1, 256, [&](uint32_t i0, uint32_t, uint32_t blocks) {
+      s = split_launch(Lc, HTH_K_ROLE, 0.0, p.nhc[L], 1, 256, [&](uint32_t i0, uint32_t, uint32_t blocks) {
         hipLaunchKernelGGL(k_role_heavy_fix, dim3(blocks), dim3(256), 0, st, d, rol, nt, i0, partial);
       });
+      if (s) return s;
+    }
+    if (!p.lv_groups[L].empty()) {
+      s = launch_groups(Lc, d, T.groups + p.lv_gbase[L], T.members, p.lv_groups[L], p.lv_chunks[L], p.d_xslots,
+                        tarea, w + p.o_gpart);
       if (s) return s;
     }
   }

@@ -1453,7 +1453,20 @@ extern "C" hth_status hth_eval_batch_sets(hth_kb kb, const hth_node* nodes,
 struct hth_plan_s {
   hth_kb kb = nullptr;
   hth::Prepared X;
+  hth_kb_s::Tuning tune;   // the schedule the tables were laid out for
 };
+
+namespace hth {
+// The kb's schedule replaced by a plan's for the duration of its launch (the
+// caller holds kb.mu): the launch sizes and the workspace areas it was laid
+// out with stay consistent whatever hth_kb_set_tuning did since.
+struct TuneScope {
+  hth_kb_s& kb;
+  hth_kb_s::Tuning saved;
+  TuneScope(hth_kb_s& k, const hth_kb_s::Tuning& t) : kb(k), saved(k.tune) { kb.tune = t; }
+  ~TuneScope() { kb.tune = saved; }
+};
+}  // namespace hth
 
 extern "C" hth_status hth_plan_create(hth_kb kb, const hth_node* nodes, const uint32_t* hyp_node_offsets,
                                       uint32_t n_hyps, const uint32_t* children, uint32_t n_children,
@@ -1471,6 +1484,7 @@ extern "C" hth_status hth_plan_create(hth_kb kb, const hth_node* nodes, const ui
   hth_plan_s* pl = new (std::nothrow) hth_plan_s();
   if (!pl) return fail(HTH_E_NOMEM, "host allocation failed");
   pl->kb = kb;
+  pl->tune = kb->tune;
   prepare(*kb, std::move(P), n_hyps, pl->X);
   *out = pl;
   *ws_bytes = pl->X.need;
@@ -1492,6 +1506,7 @@ extern "C" hth_status hth_plan_launch(hth_plan plan, void* ws, size_t ws_bytes, 
   hth_status s = check_ws(plan->X, static_cast<char*>(ws), ws_bytes);
   if (s) return s;
   std::lock_guard<std::mutex> g(plan->kb->mu);
+  TuneScope ts(*plan->kb, plan->tune);
   return launch_prepared(*plan->kb, plan->X, static_cast<char*>(ws), d_counts, nullptr,
                          static_cast<hipStream_t>(stream));
 }

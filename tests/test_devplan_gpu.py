@@ -272,3 +272,55 @@ def test_chunks_relaunch_and_workspace(gpu):
         assert e.value.status == -1
     finally:
         hthedl.hth_dplan_destroy(plan)
+
+
+@pytest.mark.parametrize("tuning", [dict(group_min=0), dict(group_k=8), dict(group_min=1, xcd_local=0),
+                                    dict(t_segment_kb=16), dict(t_compact=0, unroll=8)])
+def test_schedules(tuning):
+    """Device plans under other schedules: every role node alone, narrow
+    shared passes, single-node passes, chip-wide passes, passes cut by T row,
+    full-width T rows.  The count pass's bucket counts decide the shared
+    passes; the emit pass fills their members in any order."""
+    cfg = synth.small_config(n=30000, n_concepts=32, n_roles=3, s=1.4, cap=400, n_data=2, n_pos=3000,
+                             n_neg=3000, n_hyps=700, hyp_depth=5, seed_index=2300)
+    kb = synth.make_kb(cfg)
+    hyps = synth.make_hypotheses(cfg, kb)
+    eng = hthedl.Engine(kb, max_hyps=len(hyps))
+    hthedl.hth_kb_set_tuning(eng.handle, **tuning)
+    check_device(kb, hyps, f"schedule {tuning}", eng=eng)
+
+
+def test_plans_keep_their_schedule(gpu):
+    """A compiled plan (hth_plan_*) and a device plan (hth_dplan_*) run with
+    the schedule they were laid out for, whatever hth_kb_set_tuning did since:
+    passes cut by T row need a partial-count area that only a plan created
+    with the cut has."""
+    torch = gpu
+    cfg = synth.small_config(n=30000, n_concepts=32, n_roles=3, s=1.4, cap=400, n_data=2, n_pos=3000,
+                             n_neg=3000, n_hyps=300, hyp_depth=4, seed_index=2400)
+    kb = synth.make_kb(cfg)
+    hyps = synth.make_hypotheses(cfg, kb)
+    want = Oracle(kb).coverages(hyps)
+    eng = hthedl.Engine(kb, max_hyps=len(hyps))
+    nodes, offs, ch = hthedl.encode_batch(hyps)
+    d_nodes, d_offs, d_ch = eng.upload_batch(encoded=(nodes, offs, ch))
+    out = torch.empty((len(hyps), 2), dtype=torch.int32, device="cuda")
+    for at_create, at_launch in ((dict(t_segment_kb=0, region_reg=2), dict(t_segment_kb=64, region_reg=0)),
+                                 (dict(t_segment_kb=64, region_reg=0), dict(t_segment_kb=0, region_reg=4))):
+        hthedl.hth_kb_set_tuning(eng.handle, **at_create)
+        plan, nb = hthedl.hth_plan_create(eng.handle, nodes, offs, ch)
+        dplan, dnb = hthedl.hth_dplan_create(eng.handle, d_nodes, nodes.shape[0], d_offs, len(hyps), d_ch,
+                                             d_ch.shape[0])
+        hthedl.hth_kb_set_tuning(eng.handle, **at_launch)
+        try:
+            ws = torch.empty(max(nb, dnb), dtype=torch.uint8, device="cuda")
+            hthedl.hth_plan_upload(plan, ws, nb)
+            out.fill_(-1)
+            hthedl.hth_plan_launch(plan, ws, nb, out)
+            assert np.array_equal(out.cpu().numpy().view(np.uint32), want), at_create
+            out.fill_(-1)
+            hthedl.hth_dplan_launch(dplan, ws, dnb, out)
+            assert np.array_equal(out.cpu().numpy().view(np.uint32), want), at_create
+        finally:
+            hthedl.hth_plan_destroy(plan)
+            hthedl.hth_dplan_destroy(dplan)
