@@ -308,10 +308,11 @@ hth_status hth_plan_destroy(hth_plan plan);
  * d_nodes [n_nodes], d_hyp_node_offsets [n_hyps + 1] (hypothesis h is
  * d_nodes[offsets[h] .. offsets[h+1]), local child indices; offsets need not
  * start at 0, so a chunk of a larger batch is the same arrays with the offsets
- * pointer advanced), d_children [n_children].  Every DL operation of every
- * hypothesis is one task (identical subexpressions of different hypotheses are
- * each evaluated on their own; every node is evaluated, reachable from its
- * root or not), run level by level on the executor's kernels with the kb's schedule:
+ * pointer advanced), d_children [n_children].  Identical threshold leaves of
+ * the batch share one task; every other DL operation of every hypothesis is one
+ * task (identical compound subexpressions of different hypotheses are each
+ * evaluated on their own; every node is evaluated, reachable from its root or
+ * not), run level by level on the executor's kernels with the kb's schedule:
  * role nodes of one (level, role, direction) share CSR passes, thresholds on
  * one property a column pass.
  *

@@ -8,18 +8,21 @@
 //   k_dp_count  validates every node, computes each node's role-nesting level,
 //               region-program stack depth and program length, and counts the
 //               plan's tables: role nodes per (level, role direction) bucket,
-//               thresholds per property, regions, rows, program words.  The
-//               counts are the only data the host reads back;
+//               distinct thresholds per property (identical threshold leaves of
+//               the batch are hash-consed into one task and row), regions,
+//               rows, program words.  The counts are the only data the host
+//               reads back;
 //   (host)      from the counts alone: table bases, the shared CSR passes of
 //               each large bucket (ceil(count / group_k) passes), their T rows
 //               and XCD placement, threshold groups, the workspace layout;
 //   k_dp_emit   assigns bit rows, writes the threshold, role, fill and region
 //               tasks and the shared passes' members (and acceptance masks) at
 //               per-table cursors, and writes every region program.
-// Each DL operation of each hypothesis is one task: subexpressions are not
-// shared across hypotheses (the host compiler's hash-consing), and single
-// existential restrictions are not pushed; role nodes of one bucket still
-// share CSR passes, and thresholds on one property a column pass.  Every node
+// Every other DL operation of each hypothesis is one task: compound
+// subexpressions are not shared across hypotheses (the host compiler
+// hash-conses the whole DAG), and single existential restrictions are not
+// pushed; role nodes of one bucket still share CSR passes, and thresholds on
+// one property a column pass.  Every node
 // of a hypothesis is evaluated, reachable from its root or not.
 // Concrete-role constructs (HTH_NUM_*, HTH_STR_*) are not generated.
 // Included by exec.hip only.
@@ -74,8 +77,28 @@ struct DpKB {                    // what the passes read of the knowledge base
   uint32_t n_fixed;              // the first slot row: the all-zero row
   uint32_t n_dir;                // 2 R + 1
   const uint32_t* dir;           // [3][2R+1]: non-empty words, first heavy chunk, first heavy row
-  uint32_t* pk;                  // [n_data] thresholds per property (count pass)
+  uint32_t* pk;                  // [n_data] distinct thresholds per property (count pass)
+  unsigned long long* tkey;      // threshold table: keys (kDpEmpty = free) ...
+  uint32_t* tval;                // ... and per entry: index within its property, owning node
+  uint32_t tmask;                // entries - 1 (a power of two above twice the nodes)
+  uint32_t n_thr;                // distinct thresholds (emit pass): their rows come first
 };
+
+constexpr unsigned long long kDpEmpty = ~0ull;
+
+// A threshold leaf's key: property, comparison and the threshold's bits.
+__device__ __forceinline__ unsigned long long dp_thr_key(const hth_node& x) {
+  const uint32_t cmp = x.op == HTH_DATA_GE ? 0u : x.op == HTH_DATA_LE ? 1u : 2u;
+  return ((unsigned long long)(x.arg * 4u + cmp) << 32) | x.q.n;
+}
+__device__ __forceinline__ uint32_t dp_hash(unsigned long long k, uint32_t mask) {
+  k ^= k >> 33;
+  k *= 0xFF51AFD7ED558CCDull;
+  k ^= k >> 33;
+  k *= 0xC4CEB9FE1A85EC53ull;
+  k ^= k >> 33;
+  return (uint32_t)k & mask;
+}
 
 struct DpTables {
   ThrTask* thr;
@@ -89,7 +112,6 @@ struct DpTables {
   const DpBucket* buckets;       // [kDpLevels][2R]
   uint32_t* bcur;                // [kDpLevels][2R] member cursors
   const uint32_t* pbase;         // [n_data] first threshold task of each property
-  uint32_t* pcur;                // [n_data] threshold cursors
 };
 
 // per-node facts of the count pass: bits 0-7 role-nesting height + 1 (0: no
@@ -171,9 +193,21 @@ k_dp_count(const hth_node* __restrict__ nodes, const uint32_t* __restrict__ offs
           if (x.arg >= K.n_data) why = DP_PROP;
           else if (x.q.t != x.q.t) why = DP_NAN;
           flags = kDpRow;
-          if (!why) atomicAdd(K.pk + x.arg, 1u);
-          atomicAdd(s_thr, 1u);
-          atomicAdd(s_slots, 1u);
+          if (!why) {
+            // one task and row per distinct threshold of the batch: the first
+            // node to claim a key owns it
+            const unsigned long long key = dp_thr_key(x);
+            for (uint32_t hs = dp_hash(key, K.tmask);; hs = (hs + 1) & K.tmask) {
+              const unsigned long long prev = atomicCAS(K.tkey + hs, kDpEmpty, key);
+              if (prev == kDpEmpty) {
+                K.tval[2 * hs] = atomicAdd(K.pk + x.arg, 1u);
+                K.tval[2 * hs + 1] = b + i;
+                atomicAdd(s_thr, 1u);
+                break;
+              }
+              if (prev == key) break;
+            }
+          }
           break;
         case HTH_NOT: {
           if (x.child >= i) {
@@ -391,18 +425,24 @@ k_dp_emit(const hth_node* __restrict__ nodes, const uint32_t* __restrict__ offs,
   for (uint32_t i = 0; i < n; ++i) {
     const hth_node x = nodes[b + i];
     if (dp_column(x.op)) {
-      const uint32_t r = K.n_fixed + 1 + atomicAdd(&cur->slots, 1u);
+      // the distinct threshold's task (the property's tasks are contiguous:
+      // one column pass serves up to 32) and row
+      const unsigned long long key = dp_thr_key(x);
+      uint32_t hs = dp_hash(key, K.tmask);
+      while (K.tkey[hs] != key) hs = (hs + 1) & K.tmask;
+      const uint32_t t = T.pbase[x.arg] + K.tval[2 * hs];
+      const uint32_t r = K.n_fixed + 1 + t;
       row[b + i] = r;
-      // the property's tasks are contiguous: one column pass serves up to 32
-      const uint32_t t = T.pbase[x.arg] + atomicAdd(T.pcur + x.arg, 1u);
-      ThrTask tt;
-      tt.prop = x.arg;
-      tt.cmp = x.op == HTH_DATA_GE ? 0u : x.op == HTH_DATA_LE ? 1u : 2u;
-      tt.t = x.q.t;
-      tt.out_row = r;
-      T.thr[t] = tt;
+      if (K.tval[2 * hs + 1] == b + i) {
+        ThrTask tt;
+        tt.prop = x.arg;
+        tt.cmp = x.op == HTH_DATA_GE ? 0u : x.op == HTH_DATA_LE ? 1u : 2u;
+        tt.t = x.q.t;
+        tt.out_row = r;
+        T.thr[t] = tt;
+      }
     } else if (dp_role(x.op)) {
-      const uint32_t r = K.n_fixed + 1 + atomicAdd(&cur->slots, 1u);
+      const uint32_t r = K.n_fixed + 1 + K.n_thr + atomicAdd(&cur->slots, 1u);
       row[b + i] = r;
       const uint32_t c = b + x.child, ci = info[c], lvl = ci & 255u;
       const uint8_t cop = nodes[c].op;
@@ -416,7 +456,7 @@ k_dp_emit(const hth_node* __restrict__ nodes, const uint32_t* __restrict__ offs,
         crow = dp_leaf_row(K, nodes, row, b + nodes[c].child);
         neg = 1;
       } else {
-        crow = K.n_fixed + 1 + atomicAdd(&cur->slots, 1u);
+        crow = K.n_fixed + 1 + K.n_thr + atomicAdd(&cur->slots, 1u);
         const unsigned long long off = atomicAdd(&cur->code, (unsigned long long)len[c]);
         dp_program(K, nodes, kids, info, row, b, x.child, T.code + off);
         T.mat[B.mat[lvl] + atomicAdd(&cur->mat[lvl], 1u)] = RegionTask{(uint32_t)off, len[c], crow, kNone};
@@ -571,7 +611,6 @@ struct hth_dplan_s {
   uint32_t* d_xslots = nullptr;
   uint32_t* d_bcur = nullptr;
   uint32_t* d_pbase = nullptr;        // first threshold task of each property
-  uint32_t* d_pcur = nullptr;
   hth::ThrGroup* d_thg = nullptr;     // threshold groups: up to 32 tasks of one property
   uint32_t n_buckets = 0, n_thg = 0;
   hth::DpKB K{};
@@ -707,7 +746,7 @@ hth_status dp_schedule(hth_dplan_s& p, const std::vector<uint32_t>& bk, std::vec
   p.o_mem = area((size_t)p.n_members * sizeof(GroupMember));
   p.o_tarea = area(p.n_groups ? t_area_bytes(kb) : 0);
   p.o_gpart = area(gpart);
-  p.o_slot = area(((size_t)S.n_slots + 1) * kb.S * 8);
+  p.o_slot = area(((size_t)S.n_slots + S.n_thr + 1) * kb.S * 8);
   p.need = at;
   return HTH_OK;
 }
@@ -724,6 +763,7 @@ extern "C" hth_status hth_dplan_create(hth_kb kb, const hth_node* d_nodes, uint3
   if (n_children && !d_children) return fail(HTH_E_INVALID, "children is NULL");
   if (n_hyps == 0) return fail(HTH_E_RANGE, "a plan needs at least one hypothesis");
   if (n_nodes > (1u << 24)) return fail(HTH_E_RANGE, "more than 2^24 nodes in one call");
+  if (kb->d.n_data >= (1u << 29)) return fail(HTH_E_RANGE, "more than 2^29 properties");
   const hipStream_t st = static_cast<hipStream_t>(stream);
   hth_dplan_s* p = new (std::nothrow) hth_dplan_s();
   if (!p) return fail(HTH_E_NOMEM, "host allocation failed");
@@ -762,7 +802,11 @@ extern "C" hth_status hth_dplan_create(hth_kb kb, const hth_node* d_nodes, uint3
   const size_t o_pk = o_bk + align_up(nbk2 * 4, 256);
   const size_t nd_data = kb->d.n_data;
   const size_t o_dir = o_pk + align_up(nd_data * 4, 256);
-  const size_t total = o_dir + dir.size() * 4;
+  uint32_t tcap = 1024;
+  while (tcap < 2ull * n_nodes) tcap <<= 1;
+  const size_t o_tkey = o_dir + align_up(dir.size() * 4, 256);
+  const size_t o_tval = o_tkey + (size_t)tcap * 8;
+  const size_t total = o_tval + (size_t)tcap * 8;
   HTH_HIP(hipMalloc(reinterpret_cast<void**>(&p->buf), total));
   HTH_HIP(hipEventCreateWithFlags(&p->done, hipEventDisableTiming));
   p->info = reinterpret_cast<uint32_t*>(p->buf + o_info);
@@ -773,12 +817,16 @@ extern "C" hth_status hth_dplan_create(hth_kb kb, const hth_node* d_nodes, uint3
   p->d_bk = reinterpret_cast<uint32_t*>(p->buf + o_bk);
   p->K.dir = reinterpret_cast<const uint32_t*>(p->buf + o_dir);
   p->K.pk = reinterpret_cast<uint32_t*>(p->buf + o_pk);
+  p->K.tkey = reinterpret_cast<unsigned long long*>(p->buf + o_tkey);
+  p->K.tval = reinterpret_cast<uint32_t*>(p->buf + o_tval);
+  p->K.tmask = tcap - 1;
   HTH_HIP(hipMemcpyAsync(p->buf + o_dir, dir.data(), dir.size() * 4, hipMemcpyHostToDevice, st));
   DpSummary init{};
   init.err = ~0ull;
   HTH_HIP(hipMemcpyAsync(p->d_sum, &init, sizeof(init), hipMemcpyHostToDevice, st));
   HTH_HIP(hipMemsetAsync(p->d_bk, 0, nbk2 * 4, st));
   if (nd_data) HTH_HIP(hipMemsetAsync(p->K.pk, 0, nd_data * 4, st));
+  HTH_HIP(hipMemsetAsync(p->K.tkey, 0xFF, (size_t)tcap * 8, st));
   hipLaunchKernelGGL(k_dp_count, dim3((n_hyps + 255) / 256), dim3(256), 0, st, d_nodes, d_hyp_node_offsets,
                      d_children, n_nodes, n_children, n_hyps, p->K, p->info, p->len, p->d_sum, p->d_bk);
   HTH_HIP(hipGetLastError());
@@ -797,7 +845,7 @@ extern "C" hth_status hth_dplan_create(hth_kb kb, const hth_node* d_nodes, uint3
   }
   if (S.code >= (1ull << 32)) return fail(HTH_E_RANGE, "region programs exceed 2^32 instructions");
   // row ids must fit the 27-bit argument of the region bytecode
-  if ((uint64_t)p->K.n_fixed + 1 + S.n_slots >= (1ull << 27)) return fail(HTH_E_RANGE, "too many bit rows");
+  if ((uint64_t)p->K.n_fixed + 1 + S.n_thr + S.n_slots >= (1ull << 27)) return fail(HTH_E_RANGE, "too many bit rows");
   std::vector<DpBucket> buckets;
   std::vector<uint32_t> xslots;
   hth_status s = dp_schedule(*p, bk, buckets, xslots);
@@ -814,21 +862,20 @@ extern "C" hth_status hth_dplan_create(hth_kb kb, const hth_node* d_nodes, uint3
     tsum += pk[q];
   }
   if (tsum != S.n_thr) return fail(HTH_E_DEVICE, "threshold counts disagree");
+  p->K.n_thr = S.n_thr;
   p->n_thg = (uint32_t)thg.size();
   const size_t b_shell = 0, b_bucket = align_up(shells.size() * sizeof(GroupTask), 256);
   const size_t b_xslot = b_bucket + align_up(buckets.size() * sizeof(DpBucket), 256);
   const size_t b_bcur = b_xslot + align_up(xslots.size() * 4, 256);
   const size_t b_thg = b_bcur + align_up((size_t)p->n_buckets * 4, 256);
   const size_t b_pbase = b_thg + align_up(thg.size() * sizeof(ThrGroup), 256);
-  const size_t b_pcur = b_pbase + align_up(nd_data * 4, 256);
-  HTH_HIP(hipMalloc(reinterpret_cast<void**>(&p->buf2), b_pcur + nd_data * 4 + 4));
+  HTH_HIP(hipMalloc(reinterpret_cast<void**>(&p->buf2), b_pbase + nd_data * 4 + 4));
   p->d_shells = reinterpret_cast<GroupTask*>(p->buf2 + b_shell);
   p->d_buckets = reinterpret_cast<DpBucket*>(p->buf2 + b_bucket);
   p->d_xslots = reinterpret_cast<uint32_t*>(p->buf2 + b_xslot);
   p->d_bcur = reinterpret_cast<uint32_t*>(p->buf2 + b_bcur);
   p->d_thg = reinterpret_cast<ThrGroup*>(p->buf2 + b_thg);
   p->d_pbase = reinterpret_cast<uint32_t*>(p->buf2 + b_pbase);
-  p->d_pcur = reinterpret_cast<uint32_t*>(p->buf2 + b_pcur);
   if (!thg.empty())
     HTH_HIP(hipMemcpyAsync(p->d_thg, thg.data(), thg.size() * sizeof(ThrGroup), hipMemcpyHostToDevice, st));
   if (nd_data) HTH_HIP(hipMemcpyAsync(p->d_pbase, pbase.data(), nd_data * 4, hipMemcpyHostToDevice, st));
@@ -870,7 +917,6 @@ extern "C" hth_status hth_dplan_launch(hth_dplan plan, void* ws, size_t ws_bytes
   T.buckets = p.d_buckets;
   T.bcur = p.d_bcur;
   T.pbase = p.d_pbase;
-  T.pcur = p.d_pcur;
   DevKB d = dev_view(kb);
   d.sets = p.sets;
   d.n_fixed = p.K.n_fixed;
@@ -885,10 +931,6 @@ extern "C" hth_status hth_dplan_launch(hth_dplan plan, void* ws, size_t ws_bytes
   HTH_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_zero_u32, dim3((p.n_buckets + 255) / 256), dim3(256), 0, st, p.d_bcur, p.n_buckets);
   HTH_HIP(hipGetLastError());
-  if (p.K.n_data) {
-    hipLaunchKernelGGL(k_zero_u32, dim3((p.K.n_data + 255) / 256), dim3(256), 0, st, p.d_pcur, p.K.n_data);
-    HTH_HIP(hipGetLastError());
-  }
   if (p.n_groups) {
     const uint32_t nw = (uint32_t)(p.n_groups * sizeof(GroupTask) / 4);
     hipLaunchKernelGGL(k_dp_copy, dim3((nw + 255) / 256), dim3(256), 0, st, reinterpret_cast<uint32_t*>(T.groups),

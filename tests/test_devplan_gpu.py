@@ -324,3 +324,23 @@ def test_plans_keep_their_schedule(gpu):
         finally:
             hthedl.hth_plan_destroy(plan)
             hthedl.hth_dplan_destroy(dplan)
+
+
+def test_shared_thresholds():
+    """Identical threshold leaves across the batch share one task and row
+    (hash-consed by the count pass); the same value under another comparison,
+    -0.0 against +0.0, infinities and 40 thresholds on one property (two
+    column passes) stay distinct where they must."""
+    cfg = synth.small_config(n=9000, n_concepts=8, n_roles=2, cap=20, n_data=3, n_pos=1500, n_neg=1500,
+                             seed_index=2500)
+    kb = synth.make_kb(cfg)
+    rng = np.random.default_rng(25)
+    vals = [float(v) for v in kb.deciles[1]] + [0.0, -0.0, float("inf"), float("-inf")]
+    vals += [float(v) for v in np.float32(rng.normal(size=30))]
+    leaves = [(op, p, t) for p in (0, 1) for t in vals for op in ("dge", "dle", "deq")]
+    hyps = []
+    for _ in range(900):
+        a, b = leaves[int(rng.integers(len(leaves)))], leaves[int(rng.integers(len(leaves)))]
+        k = int(rng.integers(3))
+        hyps.append(a if k == 0 else ("and", a, b) if k == 1 else ("exists", 0, 1, ("or", a, ("not", b))))
+    check_device(kb, hyps, "shared thresholds", chunk=400)
