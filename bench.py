@@ -318,9 +318,11 @@ def main():
         n_nodes = int(nodes.shape[0])
         dc = torch.empty((H, 2), dtype=torch.int32, device="cuda")
 
+        eng.ensure_plan_scratch(n_nodes)
+
         def dstep():
             plan, nb = hthedl.hth_dplan_create(eng.handle, d_nodes, n_nodes, d_offs, H, d_ch, int(d_ch.shape[0]),
-                                               stream)
+                                               eng.dp_scratch, eng.dp_scratch_bytes, stream)
             eng.ensure_workspace(nb)
             hthedl.hth_dplan_launch(plan, eng.ws, eng.ws_bytes, dc, stream)
             hthedl.hth_dplan_destroy(plan)

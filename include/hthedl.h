@@ -320,24 +320,31 @@ hth_status hth_plan_destroy(hth_plan plan);
  * levels, region programs' sizes, table sizes) and waits for its counts (a few
  * bytes per role direction and property): the only data the host reads; the
  * host builds the shared passes and the table layout from them.  *ws_bytes
- * receives the workspace that hth_dplan_launch needs.  The plan owns device
- * buffers (12 bytes per node, and the shared passes' tables) and keeps the
- * kb's set table and schedule as they were at creation.  The device arrays must
- * stay allocated and unchanged until the plan's last launch.
+ * receives the workspace that hth_dplan_launch needs.  `scratch` is device
+ * memory of at least hth_dplan_scratch_bytes(kb, n_nodes) (about 230 bytes per
+ * node: per-node facts, the threshold hash table, the plan's own tables),
+ * 256-byte aligned, owned by the caller and held by the plan until it is
+ * destroyed.  The plan keeps the kb's set table and schedule as they were at
+ * creation.  The node arrays must stay allocated and unchanged until the
+ * plan's last launch.
  * hth_dplan_launch writes the plan's tables into ws on the device and runs
  * every kernel of the evaluation on `stream`, without waiting; d_counts
  * [n_hyps][2] as hth_eval_batch.  Launches of one plan must not overlap;
- * hth_dplan_destroy waits for the plan's last launch before it frees its buffer.
+ * hth_dplan_destroy waits for the plan's last launch (the caller may then
+ * free or reuse the scratch).
  * Errors (create): as hth_eval_batch, with the first failing hypothesis and
  * node; HTH_E_UNSUPPORTED for HTH_NUM_* / HTH_STR_* nodes, role restrictions
  * nested more than 16 deep, and regions with more than 32 nested operators;
- * HTH_E_RANGE for n_hyps = 0 or n_nodes > 2^24.  (launch) HTH_E_NOMEM when
+ * HTH_E_RANGE for n_hyps = 0 or n_nodes > 2^24; HTH_E_NOMEM / HTH_E_INVALID
+ * for a short or misaligned scratch.  (launch) HTH_E_NOMEM when
  * ws_bytes is short, HTH_E_INVALID when ws is not 256-byte aligned.  The plan
  * must not outlive its kb. */
 typedef struct hth_dplan_s* hth_dplan;
+hth_status hth_dplan_scratch_bytes(hth_kb kb, uint32_t n_nodes, size_t* bytes);
 hth_status hth_dplan_create(hth_kb kb, const hth_node* d_nodes, uint32_t n_nodes,
                             const uint32_t* d_hyp_node_offsets, uint32_t n_hyps, const uint32_t* d_children,
-                            uint32_t n_children, void* stream, hth_dplan* out, size_t* ws_bytes);
+                            uint32_t n_children, void* scratch, size_t scratch_bytes, void* stream,
+                            hth_dplan* out, size_t* ws_bytes);
 hth_status hth_dplan_launch(hth_dplan plan, void* ws, size_t ws_bytes, uint32_t* d_counts /* [n_hyps][2] */,
                             void* stream);
 hth_status hth_dplan_destroy(hth_dplan plan);

@@ -598,8 +598,7 @@ struct hth_dplan_s {
   uint32_t n_nodes = 0, n_hyps = 0, n_kids = 0;
   const uint64_t* sets = nullptr;
   uint32_t n_sets = 0;
-  char* buf = nullptr;     // per-node facts and rows, summary, cursors, bucket counts, direction table
-  char* buf2 = nullptr;    // shared-pass shells, bucket table, XCD slot table, bucket cursors
+  char* buf = nullptr;     // the caller's scratch (see DpScratch)
   uint32_t* info = nullptr;
   uint32_t* len = nullptr;
   uint32_t* row = nullptr;
@@ -632,13 +631,51 @@ struct hth_dplan_s {
       (void)hipEventSynchronize(done);
       (void)hipEventDestroy(done);
     }
-    if (buf) (void)hipFree(buf);
-    if (buf2) (void)hipFree(buf2);
   }
 };
 
 namespace hth {
 namespace {
+
+// The plan's scratch (caller memory, hth_dplan_scratch_bytes): per-node facts
+// and rows, the count pass's summary and counts, cursors, the direction table,
+// the threshold hash table, and the host-built tables with bounds from the node
+// count (a shared pass holds at least one node, an XCD slot round at most
+// eight passes, a threshold group at least one threshold).
+struct DpScratch {
+  size_t info, len, row, sum, cur, bk, pk, dir, tkey, tval, shell, bucket, xslot, bcur, thg, pbase, total;
+  uint32_t tcap;
+};
+DpScratch dp_scratch(const hth_kb_s& kb, uint32_t n_nodes) {
+  DpScratch L{};
+  const size_t n = n_nodes, nd = 2 * (size_t)kb.d.n_roles + 1, nb = kDpLevels * (nd - 1);
+  L.tcap = 1024;
+  while (L.tcap < 2ull * n) L.tcap <<= 1;
+  size_t at = 0;
+  auto area = [&](size_t bytes) {
+    const size_t a = at;
+    at = align_up(at + bytes, 256);
+    return a;
+  };
+  L.info = area(n * 4);
+  L.len = area(n * 4);
+  L.row = area(n * 4);
+  L.sum = area(sizeof(DpSummary));
+  L.cur = area(sizeof(DpCursor));
+  L.bk = area(2 * nb * 4);
+  L.pk = area((size_t)kb.d.n_data * 4);
+  L.dir = area(3 * nd * 4);
+  L.tkey = area((size_t)L.tcap * 8);
+  L.tval = area((size_t)L.tcap * 8);
+  L.shell = area(n * sizeof(GroupTask));
+  L.bucket = area(nb * sizeof(DpBucket));
+  L.xslot = area(8 * n * 4);
+  L.bcur = area(nb * 4);
+  L.thg = area(n * sizeof(ThrGroup));
+  L.pbase = area((size_t)kb.d.n_data * 4);
+  L.total = at;
+  return L;
+}
 
 const char* dp_reason(uint32_t why, hth_status* code) {
   switch (why) {
@@ -754,12 +791,21 @@ hth_status dp_schedule(hth_dplan_s& p, const std::vector<uint32_t>& bk, std::vec
 }  // namespace
 }  // namespace hth
 
+extern "C" hth_status hth_dplan_scratch_bytes(hth_kb kb, uint32_t n_nodes, size_t* bytes) {
+  using namespace hth;
+  if (!kb || !bytes) return fail(HTH_E_INVALID, "NULL argument");
+  *bytes = dp_scratch(*kb, n_nodes).total;
+  return HTH_OK;
+}
+
 extern "C" hth_status hth_dplan_create(hth_kb kb, const hth_node* d_nodes, uint32_t n_nodes,
                                        const uint32_t* d_hyp_node_offsets, uint32_t n_hyps,
-                                       const uint32_t* d_children, uint32_t n_children, void* stream,
-                                       hth_dplan* out, size_t* ws_bytes) {
+                                       const uint32_t* d_children, uint32_t n_children, void* scratch,
+                                       size_t scratch_bytes, void* stream, hth_dplan* out, size_t* ws_bytes) {
   using namespace hth;
-  if (!kb || !d_nodes || !d_hyp_node_offsets || !out || !ws_bytes) return fail(HTH_E_INVALID, "NULL argument");
+  if (!kb || !d_nodes || !d_hyp_node_offsets || !scratch || !out || !ws_bytes)
+    return fail(HTH_E_INVALID, "NULL argument");
+  if (reinterpret_cast<uintptr_t>(scratch) % 256) return fail(HTH_E_INVALID, "scratch must be 256-byte aligned");
   if (n_children && !d_children) return fail(HTH_E_INVALID, "children is NULL");
   if (n_hyps == 0) return fail(HTH_E_RANGE, "a plan needs at least one hypothesis");
   if (n_nodes > (1u << 24)) return fail(HTH_E_RANGE, "more than 2^24 nodes in one call");
@@ -796,31 +842,26 @@ extern "C" hth_status hth_dplan_create(hth_kb kb, const hth_node* d_nodes, uint3
   p->K.n_dir = nd;
   p->n_buckets = kDpLevels * (nd - 1);
   const size_t nbk2 = 2 * (size_t)p->n_buckets;
-  const size_t o_info = 0, o_len = align_up((size_t)n_nodes * 4, 256), o_row = o_len + o_len;
-  const size_t o_sum = o_row + o_len, o_cur = o_sum + align_up(sizeof(DpSummary), 256);
-  const size_t o_bk = o_cur + align_up(sizeof(DpCursor), 256);
-  const size_t o_pk = o_bk + align_up(nbk2 * 4, 256);
   const size_t nd_data = kb->d.n_data;
-  const size_t o_dir = o_pk + align_up(nd_data * 4, 256);
-  uint32_t tcap = 1024;
-  while (tcap < 2ull * n_nodes) tcap <<= 1;
-  const size_t o_tkey = o_dir + align_up(dir.size() * 4, 256);
-  const size_t o_tval = o_tkey + (size_t)tcap * 8;
-  const size_t total = o_tval + (size_t)tcap * 8;
-  HTH_HIP(hipMalloc(reinterpret_cast<void**>(&p->buf), total));
+  const DpScratch L = dp_scratch(*kb, n_nodes);
+  if (scratch_bytes < L.total)
+    return fail(HTH_E_NOMEM, "scratch too small: need " + std::to_string(L.total) + " bytes, have " +
+                                 std::to_string(scratch_bytes));
+  const uint32_t tcap = L.tcap;
   HTH_HIP(hipEventCreateWithFlags(&p->done, hipEventDisableTiming));
-  p->info = reinterpret_cast<uint32_t*>(p->buf + o_info);
-  p->len = reinterpret_cast<uint32_t*>(p->buf + o_len);
-  p->row = reinterpret_cast<uint32_t*>(p->buf + o_row);
-  p->d_sum = reinterpret_cast<DpSummary*>(p->buf + o_sum);
-  p->d_cur = reinterpret_cast<DpCursor*>(p->buf + o_cur);
-  p->d_bk = reinterpret_cast<uint32_t*>(p->buf + o_bk);
-  p->K.dir = reinterpret_cast<const uint32_t*>(p->buf + o_dir);
-  p->K.pk = reinterpret_cast<uint32_t*>(p->buf + o_pk);
-  p->K.tkey = reinterpret_cast<unsigned long long*>(p->buf + o_tkey);
-  p->K.tval = reinterpret_cast<uint32_t*>(p->buf + o_tval);
+  p->buf = static_cast<char*>(scratch);
+  p->info = reinterpret_cast<uint32_t*>(p->buf + L.info);
+  p->len = reinterpret_cast<uint32_t*>(p->buf + L.len);
+  p->row = reinterpret_cast<uint32_t*>(p->buf + L.row);
+  p->d_sum = reinterpret_cast<DpSummary*>(p->buf + L.sum);
+  p->d_cur = reinterpret_cast<DpCursor*>(p->buf + L.cur);
+  p->d_bk = reinterpret_cast<uint32_t*>(p->buf + L.bk);
+  p->K.dir = reinterpret_cast<const uint32_t*>(p->buf + L.dir);
+  p->K.pk = reinterpret_cast<uint32_t*>(p->buf + L.pk);
+  p->K.tkey = reinterpret_cast<unsigned long long*>(p->buf + L.tkey);
+  p->K.tval = reinterpret_cast<uint32_t*>(p->buf + L.tval);
   p->K.tmask = tcap - 1;
-  HTH_HIP(hipMemcpyAsync(p->buf + o_dir, dir.data(), dir.size() * 4, hipMemcpyHostToDevice, st));
+  HTH_HIP(hipMemcpyAsync(p->buf + L.dir, dir.data(), dir.size() * 4, hipMemcpyHostToDevice, st));
   DpSummary init{};
   init.err = ~0ull;
   HTH_HIP(hipMemcpyAsync(p->d_sum, &init, sizeof(init), hipMemcpyHostToDevice, st));
@@ -864,18 +905,14 @@ extern "C" hth_status hth_dplan_create(hth_kb kb, const hth_node* d_nodes, uint3
   if (tsum != S.n_thr) return fail(HTH_E_DEVICE, "threshold counts disagree");
   p->K.n_thr = S.n_thr;
   p->n_thg = (uint32_t)thg.size();
-  const size_t b_shell = 0, b_bucket = align_up(shells.size() * sizeof(GroupTask), 256);
-  const size_t b_xslot = b_bucket + align_up(buckets.size() * sizeof(DpBucket), 256);
-  const size_t b_bcur = b_xslot + align_up(xslots.size() * 4, 256);
-  const size_t b_thg = b_bcur + align_up((size_t)p->n_buckets * 4, 256);
-  const size_t b_pbase = b_thg + align_up(thg.size() * sizeof(ThrGroup), 256);
-  HTH_HIP(hipMalloc(reinterpret_cast<void**>(&p->buf2), b_pbase + nd_data * 4 + 4));
-  p->d_shells = reinterpret_cast<GroupTask*>(p->buf2 + b_shell);
-  p->d_buckets = reinterpret_cast<DpBucket*>(p->buf2 + b_bucket);
-  p->d_xslots = reinterpret_cast<uint32_t*>(p->buf2 + b_xslot);
-  p->d_bcur = reinterpret_cast<uint32_t*>(p->buf2 + b_bcur);
-  p->d_thg = reinterpret_cast<ThrGroup*>(p->buf2 + b_thg);
-  p->d_pbase = reinterpret_cast<uint32_t*>(p->buf2 + b_pbase);
+  if (shells.size() > n_nodes || xslots.size() > 8ull * n_nodes || thg.size() > n_nodes)
+    return fail(HTH_E_DEVICE, "plan tables beyond their bounds");
+  p->d_shells = reinterpret_cast<GroupTask*>(p->buf + L.shell);
+  p->d_buckets = reinterpret_cast<DpBucket*>(p->buf + L.bucket);
+  p->d_xslots = reinterpret_cast<uint32_t*>(p->buf + L.xslot);
+  p->d_bcur = reinterpret_cast<uint32_t*>(p->buf + L.bcur);
+  p->d_thg = reinterpret_cast<ThrGroup*>(p->buf + L.thg);
+  p->d_pbase = reinterpret_cast<uint32_t*>(p->buf + L.pbase);
   if (!thg.empty())
     HTH_HIP(hipMemcpyAsync(p->d_thg, thg.data(), thg.size() * sizeof(ThrGroup), hipMemcpyHostToDevice, st));
   if (nd_data) HTH_HIP(hipMemcpyAsync(p->d_pbase, pbase.data(), nd_data * 4, hipMemcpyHostToDevice, st));

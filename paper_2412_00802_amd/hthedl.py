@@ -39,7 +39,7 @@ EXPORTED = ["hth_kb_derived_bytes", "hth_kb_create", "hth_kb_set_examples", "hth
             "hth_kb_set_sets", "hth_eval_batch_sets", "hth_densify_delta", "hth_plan_create",
             "hth_plan_upload", "hth_plan_launch", "hth_plan_destroy", "hth_numeric_derived_bytes",
             "hth_kb_set_numeric", "hth_string_derived_bytes", "hth_kb_set_strings", "hth_kb_set_patterns",
-            "hth_dplan_create", "hth_dplan_launch", "hth_dplan_destroy"]
+            "hth_dplan_scratch_bytes", "hth_dplan_create", "hth_dplan_launch", "hth_dplan_destroy"]
 
 
 class HthError(RuntimeError):
@@ -108,7 +108,8 @@ def lib() -> ctypes.CDLL:
             "hth_plan_upload": [P, P, S, P],
             "hth_plan_launch": [P, P, S, P, P],
             "hth_plan_destroy": [P],
-            "hth_dplan_create": [P, P, U32, P, U32, P, U32, P, ctypes.POINTER(P), ctypes.POINTER(S)],
+            "hth_dplan_scratch_bytes": [P, U32, ctypes.POINTER(S)],
+            "hth_dplan_create": [P, P, U32, P, U32, P, U32, P, S, P, ctypes.POINTER(P), ctypes.POINTER(S)],
             "hth_dplan_launch": [P, P, S, P, P],
             "hth_dplan_destroy": [P],
             "hth_batch_workspace_bytes": [P, P, P, U32, P, U32, ctypes.POINTER(S)],
@@ -323,15 +324,21 @@ def hth_plan_destroy(plan) -> None:
     _check(lib().hth_plan_destroy(plan))
 
 
+def hth_dplan_scratch_bytes(kb, n_nodes: int) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().hth_dplan_scratch_bytes(kb, n_nodes, ctypes.byref(out)))
+    return out.value
+
+
 def hth_dplan_create(kb, d_nodes, n_nodes: int, d_offsets, n_hyps: int, d_children, n_children: int,
-                     stream=None):
+                     scratch, scratch_bytes: int, stream=None):
     """Plan generated on the device from device arrays (d_nodes: the node
-    records as bytes, d_offsets [n_hyps+1] and d_children as 32-bit tensors)
-    -> (plan handle, workspace bytes)."""
+    records as bytes, d_offsets [n_hyps+1] and d_children as 32-bit tensors;
+    scratch: hth_dplan_scratch_bytes bytes) -> (plan handle, workspace bytes)."""
     h, nb = ctypes.c_void_p(), ctypes.c_size_t()
     _check(lib().hth_dplan_create(kb, _ptr(d_nodes), n_nodes, _ptr(d_offsets), n_hyps,
-                                  _ptr(d_children) if n_children else None, n_children, _stream(stream),
-                                  ctypes.byref(h), ctypes.byref(nb)))
+                                  _ptr(d_children) if n_children else None, n_children, _ptr(scratch),
+                                  scratch_bytes, _stream(stream), ctypes.byref(h), ctypes.byref(nb)))
     return h, nb.value
 
 
@@ -701,6 +708,14 @@ class Engine:
             self.ws = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
             self.ws_bytes = nbytes
 
+    def ensure_plan_scratch(self, n_nodes: int) -> None:
+        """Scratch for device plans over batches of up to n_nodes nodes."""
+        nbytes = hth_dplan_scratch_bytes(self.handle, n_nodes)
+        if nbytes > getattr(self, "dp_scratch_bytes", 0):
+            self.dp_scratch = None
+            self.dp_scratch = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
+            self.dp_scratch_bytes = nbytes
+
     def upload_batch(self, hyps: Sequence = None, encoded=None):
         """The batch's node arrays in device memory: (nodes as bytes,
         offsets, children) tensors, as hth_dplan_create takes them."""
@@ -724,10 +739,11 @@ class Engine:
         n_nodes = int(d_nodes.shape[0] // NODE_DTYPE.itemsize)
         out = counts if counts is not None else torch.empty((H, 2), dtype=torch.int32, device=self.device)
         chunk = H if not chunk else chunk
+        self.ensure_plan_scratch(n_nodes)
         for a in range(0, H, chunk):
             b = min(H, a + chunk)
             plan, nb = hth_dplan_create(self.handle, d_nodes, n_nodes, d_offs[a:], b - a, d_ch,
-                                        int(d_ch.shape[0]), stream)
+                                        int(d_ch.shape[0]), self.dp_scratch, self.dp_scratch_bytes, stream)
             try:
                 self.ensure_workspace(max(nb, 256))
                 hth_dplan_launch(plan, self.ws, self.ws_bytes, out[a:b], stream)

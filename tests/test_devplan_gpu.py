@@ -236,9 +236,16 @@ def test_errors(gpu):
         with pytest.raises(hthedl.HthError) as e:
             eng.eval_batch_device(device_batch=(d_nodes, d_offs, d_ch), counts=counts)
         assert e.value.status == status, (offs, str(e.value))
+    eng.ensure_plan_scratch(2)
     with pytest.raises(hthedl.HthError) as e:
-        hthedl.hth_dplan_create(eng.handle, d_nodes, 2, d_offs, 0, None, 0)
+        hthedl.hth_dplan_create(eng.handle, d_nodes, 2, d_offs, 0, None, 0, eng.dp_scratch, eng.dp_scratch_bytes)
     assert e.value.status == -2
+    need = hthedl.hth_dplan_scratch_bytes(eng.handle, 2)
+    assert need <= eng.dp_scratch_bytes
+    for scratch, nbytes, status in ((eng.dp_scratch, need - 1, -3), (eng.dp_scratch[8:], need, -1)):
+        with pytest.raises(hthedl.HthError) as e:
+            hthedl.hth_dplan_create(eng.handle, d_nodes, 2, d_offs, 1, None, 0, scratch, nbytes)
+        assert e.value.status == status
 
 
 def test_chunks_relaunch_and_workspace(gpu):
@@ -256,7 +263,9 @@ def test_chunks_relaunch_and_workspace(gpu):
         assert np.array_equal(eng.eval_batch_device(device_batch=d, chunk=chunk), want), chunk
     d_nodes, d_offs, d_ch = d
     n_nodes = d_nodes.shape[0] // 16
-    plan, nb = hthedl.hth_dplan_create(eng.handle, d_nodes, n_nodes, d_offs[100:], 50, d_ch, d_ch.shape[0])
+    eng.ensure_plan_scratch(n_nodes)
+    plan, nb = hthedl.hth_dplan_create(eng.handle, d_nodes, n_nodes, d_offs[100:], 50, d_ch, d_ch.shape[0],
+                                       eng.dp_scratch, eng.dp_scratch_bytes)
     try:
         ws = torch.empty(nb + 512, dtype=torch.uint8, device="cuda")
         out = torch.empty((50, 2), dtype=torch.int32, device="cuda")
@@ -309,8 +318,9 @@ def test_plans_keep_their_schedule(gpu):
                                  (dict(t_segment_kb=64, region_reg=0), dict(t_segment_kb=0, region_reg=4))):
         hthedl.hth_kb_set_tuning(eng.handle, **at_create)
         plan, nb = hthedl.hth_plan_create(eng.handle, nodes, offs, ch)
+        eng.ensure_plan_scratch(nodes.shape[0])
         dplan, dnb = hthedl.hth_dplan_create(eng.handle, d_nodes, nodes.shape[0], d_offs, len(hyps), d_ch,
-                                             d_ch.shape[0])
+                                             d_ch.shape[0], eng.dp_scratch, eng.dp_scratch_bytes)
         hthedl.hth_kb_set_tuning(eng.handle, **at_launch)
         try:
             ws = torch.empty(max(nb, dnb), dtype=torch.uint8, device="cuda")
