@@ -51,6 +51,11 @@ def recorded_traffic(kernel: str, traffic_file: str = TRAFFIC_FILE):
     return None if k is None else k["hbm_bytes_per_launch"]
 
 
+def kernel_name(name: str) -> str:
+    """A rocprofv3 kernel name without its arguments (anonymous namespaces dropped)."""
+    return name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")[:60]
+
+
 def summarize(kt_dir: str, fetch_dir: str, write_dir: str, command: str, out_md: str,
               sha: str = None, title: str = "c2 workload (1M individuals, 4096 hypotheses, batched)",
               traffic_file: str = TRAFFIC_FILE, tcc_dir: str = None) -> None:
@@ -91,7 +96,7 @@ def summarize(kt_dir: str, fetch_dir: str, write_dir: str, command: str, out_md:
              "## Kernel time (kernel trace)", "",
              "| kernel | calls | avg us | total % |", "|---|---|---|---|"]
     for r in sorted(stats, key=lambda r: -float(r["Percentage"]))[:12]:
-        lines.append(f"| {r['Name'].split('(')[0].replace('void ', '')[:60]} | {r['Calls']} | "
+        lines.append(f"| {kernel_name(r['Name'])} | {r['Calls']} | "
                      f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
     lines += ["", "## Bytes (FETCH_SIZE / WRITE_SIZE, KiB per dispatch)", "",
               f"Calibration: `{ck[:50]}` (one elementwise pass over {COPY_BYTES >> 20} MiB of untouched memory) reads "
@@ -139,7 +144,7 @@ def summarize_trace(kt_dir: str, command: str, out_md: str, title: str) -> None:
              "    " + command.format(opts="--kernel-trace --stats --output-format csv"), "",
              "| kernel | calls | avg us | total ms | total % |", "|---|---|---|---|---|"]
     for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:16]:
-        lines.append(f"| {r['Name'].split('(')[0].replace('void ', '')[:60]} | {r['Calls']} | "
+        lines.append(f"| {kernel_name(r['Name'])} | {r['Calls']} | "
                      f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['TotalDurationNs']) / 1e6:.1f} | "
                      f"{float(r['Percentage']):.1f} |")
     open(out_md, "w").write("\n".join(lines) + "\n")
