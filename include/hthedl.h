@@ -349,6 +349,53 @@ hth_status hth_dplan_launch(hth_dplan plan, void* ws, size_t ws_bytes, uint32_t*
                             void* stream);
 hth_status hth_dplan_destroy(hth_dplan plan);
 
+/* Refinement candidates written on the device: the one-step specialisation
+ * that adds a conjunct, candidate = P and X, for parents P whose instance sets
+ * are rows of the registered set table (hth_kb_set_sets).  With
+ * hth_dplan_create this keeps a refinement round's candidates and plans on the
+ * device (the paper's Section 7 future work; the paper defines no refinement
+ * operator, the conjunct family is this library's).  16 bytes per spec. */
+enum {
+  HTH_CJ_ATOM = 0,     /* X = atomic concept a */
+  HTH_CJ_EXISTS = 1,   /* X = exists role b (inv: inverse) . atomic concept a */
+  HTH_CJ_GE = 2,       /* X = property a >= threshold (b: float bits) */
+  HTH_CJ_LE = 3,       /* X = property a <= threshold */
+  HTH_CJ_EQ = 4        /* X = property a == threshold */
+};
+typedef struct {
+  uint32_t parent;     /* set-table row of P */
+  uint8_t kind;        /* HTH_CJ_* */
+  uint8_t inv;
+  uint16_t pad;
+  uint32_t a, b;
+} hth_conjunct;
+
+/* n = n_parents * per_parent specs into d_specs (device [n]): spec i refines
+ * the parent in set-table row d_parent_rows[i / per_parent] (device [n_parents]).
+ * Draw i reads values 4i .. 4i+3 of the SplitMix64 sequence (Steele, Lea and
+ * Flood, OOPSLA 2014) started at `seed`, so it depends on (seed, i) only:
+ *   u0 mod 10: 0-4 an atom, 5-7 an existential, 8-9 a threshold (u3 bit 0:
+ *   1 = LE, 0 = GE); an existential without roles or a threshold without
+ *   properties becomes an atom;
+ *   atom: a = u1 mod n_concepts;  existential: b = u1 mod n_roles, inv = bit
+ *   32 of u1, a = u2 mod n_concepts;  threshold: a = u1 mod n_data, the
+ *   threshold d_deciles[a][u2 mod 9] (device float [n_data][9]).
+ * Duplicate draws are possible.  Asynchronous on `stream`.  Errors:
+ * HTH_E_INVALID (NULL arguments; deciles NULL with n_data > 0), HTH_E_RANGE
+ * (n >= 2^31, no concepts). */
+hth_status hth_draw_conjuncts(hth_kb kb, uint64_t seed, const uint32_t* d_parent_rows, uint32_t n_parents,
+                              uint32_t per_parent, const float* d_deciles, hth_conjunct* d_specs, void* stream);
+
+/* Candidate i of d_specs (device [n]) as a hypothesis batch in the layout
+ * hth_eval_batch and hth_dplan_create take: d_nodes [4n], d_hyp_node_offsets
+ * [n+1] (= 4i), d_children [2n].  Hypothesis i is SET(parent), X's leaf,
+ * X's existential (or an unreferenced TOP), AND(SET, X).  Nothing is validated
+ * here: hth_dplan_create validates the nodes (a kind outside HTH_CJ_* becomes
+ * an op it rejects).  Asynchronous on `stream`.  Errors: HTH_E_INVALID (NULL),
+ * HTH_E_RANGE (n >= 2^22). */
+hth_status hth_conjoin(const hth_conjunct* d_specs, uint32_t n, hth_node* d_nodes, uint32_t* d_hyp_node_offsets,
+                       uint32_t* d_children, void* stream);
+
 /* Measurement.  Between hth_profile_begin and hth_profile_end every kernel the
  * library launches for this kb is bracketed by two HIP events recorded on the
  * launch stream, and the host adds up the algorithmic HBM bytes of the launch

@@ -17,7 +17,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libhthedl.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["kb.hip", "plan.cpp", "exec.hip", "mlp.hip"]
+SOURCES = ["kb.hip", "plan.cpp", "exec.hip", "mlp.hip", "refine.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -30,6 +30,12 @@ NODE_DTYPE = np.dtype([("op", np.uint8), ("inv", np.uint8), ("arity", np.uint16)
                        ("arg", np.uint32), ("child", np.uint32), ("q", np.uint32)])
 assert NODE_DTYPE.itemsize == 16
 
+# hth_conjunct: an added conjunct (kind HTH_CJ_*) of a set-table parent
+CONJ_DTYPE = np.dtype([("parent", np.uint32), ("kind", np.uint8), ("inv", np.uint8), ("pad", np.uint16),
+                       ("a", np.uint32), ("b", np.uint32)])
+assert CONJ_DTYPE.itemsize == 16
+CJ_ATOM, CJ_EXISTS, CJ_GE, CJ_LE, CJ_EQ = range(5)
+
 EXPORTED = ["hth_kb_derived_bytes", "hth_kb_create", "hth_kb_set_examples", "hth_kb_max_degree",
             "hth_kb_destroy", "hth_workspace_bytes", "hth_eval_one", "hth_eval_batch",
             "hth_sync", "hth_status_str", "hth_last_error", "hth_profile_begin",
@@ -39,7 +45,8 @@ EXPORTED = ["hth_kb_derived_bytes", "hth_kb_create", "hth_kb_set_examples", "hth
             "hth_kb_set_sets", "hth_eval_batch_sets", "hth_densify_delta", "hth_plan_create",
             "hth_plan_upload", "hth_plan_launch", "hth_plan_destroy", "hth_numeric_derived_bytes",
             "hth_kb_set_numeric", "hth_string_derived_bytes", "hth_kb_set_strings", "hth_kb_set_patterns",
-            "hth_dplan_scratch_bytes", "hth_dplan_create", "hth_dplan_launch", "hth_dplan_destroy"]
+            "hth_dplan_scratch_bytes", "hth_dplan_create", "hth_dplan_launch", "hth_dplan_destroy",
+            "hth_draw_conjuncts", "hth_conjoin"]
 
 
 class HthError(RuntimeError):
@@ -111,6 +118,8 @@ def lib() -> ctypes.CDLL:
             "hth_dplan_scratch_bytes": [P, U32, ctypes.POINTER(S)],
             "hth_dplan_create": [P, P, U32, P, U32, P, U32, P, S, P, ctypes.POINTER(P), ctypes.POINTER(S)],
             "hth_dplan_launch": [P, P, S, P, P],
+            "hth_draw_conjuncts": [P, U64, P, U32, U32, P, P, P],
+            "hth_conjoin": [P, U32, P, P, P, P],
             "hth_dplan_destroy": [P],
             "hth_batch_workspace_bytes": [P, P, P, U32, P, U32, ctypes.POINTER(S)],
             "hth_sync": [P],
@@ -340,6 +349,39 @@ def hth_dplan_create(kb, d_nodes, n_nodes: int, d_offsets, n_hyps: int, d_childr
                                   _ptr(d_children) if n_children else None, n_children, _ptr(scratch),
                                   scratch_bytes, _stream(stream), ctypes.byref(h), ctypes.byref(nb)))
     return h, nb.value
+
+
+def _need_bytes(t, nbytes: int, what: str) -> None:
+    """A device tensor argument must hold what the library writes or reads."""
+    if t is not None and not isinstance(t, int) and t.numel() * t.element_size() < nbytes:
+        raise ValueError(f"{what}: {t.numel() * t.element_size()} bytes, the call needs {nbytes}")
+
+
+def hth_draw_conjuncts(kb, seed: int, d_parent_rows, n_parents: int, per_parent: int, d_deciles, d_specs,
+                       stream=None) -> None:
+    _need_bytes(d_parent_rows, 4 * n_parents, "parent rows")
+    _need_bytes(d_specs, CONJ_DTYPE.itemsize * n_parents * per_parent, "specs")
+    _check(lib().hth_draw_conjuncts(kb, seed, _ptr(d_parent_rows), n_parents, per_parent, _ptr(d_deciles),
+                                    _ptr(d_specs), _stream(stream)))
+
+
+def hth_conjoin(d_specs, n: int, d_nodes, d_offsets, d_children, stream=None) -> None:
+    _need_bytes(d_specs, CONJ_DTYPE.itemsize * n, "specs")
+    _need_bytes(d_nodes, 4 * NODE_DTYPE.itemsize * n, "nodes")
+    _need_bytes(d_offsets, 4 * (n + 1), "offsets")
+    _need_bytes(d_children, 8 * n, "children")
+    _check(lib().hth_conjoin(_ptr(d_specs), n, _ptr(d_nodes), _ptr(d_offsets), _ptr(d_children), _stream(stream)))
+
+
+def conjunct_tuple(spec) -> tuple:
+    """The conjunct of one hth_conjunct record, in the tuple form."""
+    k, a, b = int(spec["kind"]), int(spec["a"]), int(spec["b"])
+    if k == CJ_ATOM:
+        return ("atom", a)
+    if k == CJ_EXISTS:
+        return ("exists", b, int(spec["inv"]), ("atom", a))
+    t = float(np.uint32(b).view(np.float32))
+    return ({CJ_GE: "dge", CJ_LE: "dle", CJ_EQ: "deq"}[k], a, t)
 
 
 def hth_dplan_launch(plan, ws, ws_bytes: int, d_counts, stream=None) -> None:
@@ -715,6 +757,25 @@ class Engine:
             self.dp_scratch = None
             self.dp_scratch = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
             self.dp_scratch_bytes = nbytes
+
+    def conjunct_candidates(self, parent_rows, per_parent: int, seed: int, deciles=None):
+        """Refinement candidates drawn and written on the device
+        (hth_draw_conjuncts, hth_conjoin): parent_rows (set-table rows) x
+        per_parent added conjuncts.  -> (specs, (nodes, offsets, children)),
+        all device tensors; the batch goes to eval_batch_device."""
+        torch = self.torch
+        rows = torch.as_tensor(np.asarray(parent_rows, dtype=np.uint32).view(np.int32), device=self.device)
+        n = int(rows.shape[0]) * per_parent
+        dec = None
+        if self.desc.n_data:
+            dec = torch.as_tensor(np.ascontiguousarray(deciles, dtype=np.float32), device=self.device)
+        specs = torch.empty(n * CONJ_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
+        nodes = torch.empty(4 * n * NODE_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
+        offs = torch.empty(n + 1, dtype=torch.int32, device=self.device)
+        ch = torch.empty(max(1, 2 * n), dtype=torch.int32, device=self.device)
+        hth_draw_conjuncts(self.handle, seed, rows, int(rows.shape[0]), per_parent, dec, specs)
+        hth_conjoin(specs, n, nodes, offs, ch)
+        return specs, (nodes, offs, ch[:2 * n])
 
     def upload_batch(self, hyps: Sequence = None, encoded=None):
         """The batch's node arrays in device memory: (nodes as bytes,

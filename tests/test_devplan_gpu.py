@@ -354,3 +354,62 @@ def test_shared_thresholds():
         k = int(rng.integers(3))
         hyps.append(a if k == 0 else ("and", a, b) if k == 1 else ("exists", 0, 1, ("or", a, ("not", b))))
     check_device(kb, hyps, "shared thresholds", chunk=400)
+
+
+def test_device_candidates(gpu):
+    """Added-conjunct candidates drawn and written on the device equal the CPU
+    reference's specs and node arrays bit for bit, and their device plans
+    cover what the oracle gives for parent and conjunct."""
+    import torch
+    from tests import conjunct_ref
+    cfg = synth.small_config(n=20000, n_concepts=24, n_roles=4, s=1.5, cap=100, n_data=3,
+                             n_pos=2000, n_neg=2000, seed_index=2600)
+    kb = synth.make_kb(cfg)
+    o = Oracle(kb)
+    parents = synth.make_hypotheses(cfg, kb, count=7, depth=3)
+    eng = hthedl.Engine(kb)
+    table = torch.zeros((len(parents), eng.S), dtype=torch.int64, device="cuda")
+    nodes, offs, ch = hthedl.encode_batch(parents)
+    eng.ensure_workspace(hthedl.hth_batch_workspace_bytes(eng.handle, nodes, offs, ch))
+    cnt = torch.empty((len(parents), 2), dtype=torch.int32, device="cuda")
+    hthedl.hth_eval_batch_sets(eng.handle, nodes, offs, ch, eng.ws, eng.ws_bytes, table, cnt)
+    hthedl.hth_kb_set_sets(eng.handle, table, len(parents))
+    rows = np.array([3, 0, 5, 1, 2, 6, 4], dtype=np.uint32)
+    for seed, per in ((2412, 41), (7, 1), (1 << 63, 300)):
+        d_specs, batch = eng.conjunct_candidates(rows, per, seed, kb.deciles)
+        specs = d_specs.cpu().numpy().view(hthedl.CONJ_DTYPE)
+        want = conjunct_ref.draw(seed, rows, per, kb.n_concepts, kb.n_roles, kb.n_data, kb.deciles)
+        assert np.array_equal(specs, want), seed
+        wn, wo, wc = conjunct_ref.conjoin(want)
+        got_nodes = batch[0].cpu().numpy().view(hthedl.NODE_DTYPE)
+        assert np.array_equal(got_nodes, wn) and np.array_equal(batch[1].cpu().numpy().view(np.uint32), wo)
+        assert np.array_equal(batch[2].cpu().numpy().view(np.uint32), wc)
+        full = [("and", parents[int(c["parent"])], hthedl.conjunct_tuple(c)) for c in specs]
+        got = eng.eval_batch_device(device_batch=batch)
+        assert np.array_equal(got, o.coverages(full)), seed
+        assert np.array_equal(eng.eval_batch(None, encoded=(wn, wo, wc)), got)
+    # a kind outside the family is rejected by the plan's count pass
+    bad = want.copy()
+    bad["kind"][5] = 9
+    d_bad = torch.from_numpy(bad.view(np.uint8)).cuda()
+    n = bad.shape[0]
+    bn = torch.empty(16 * 4 * n, dtype=torch.uint8, device="cuda")
+    bo = torch.empty(n + 1, dtype=torch.int32, device="cuda")
+    bc = torch.empty(2 * n, dtype=torch.int32, device="cuda")
+    hthedl.hth_conjoin(d_bad, n, bn, bo, bc)
+    with pytest.raises(hthedl.HthError) as e:
+        eng.eval_batch_device(device_batch=(bn, bo, bc))
+    assert e.value.status == -1 and "hypothesis 5 node 1" in str(e.value)
+    hthedl.hth_kb_set_sets(eng.handle, None, 0)
+    # a KB without properties draws no thresholds
+    cfg0 = synth.small_config(n=3000, n_concepts=9, n_roles=2, n_data=0, n_pos=300, n_neg=300, seed_index=2601)
+    kb0 = synth.make_kb(cfg0)
+    eng0 = hthedl.Engine(kb0)
+    t0 = torch.full((2, eng0.S), -1, dtype=torch.int64, device="cuda")   # both parents: every individual
+    hthedl.hth_kb_set_sets(eng0.handle, t0, 2)
+    d0, b0 = eng0.conjunct_candidates(np.array([1, 0], np.uint32), 60, 31, None)
+    s0 = d0.cpu().numpy().view(hthedl.CONJ_DTYPE)
+    assert np.array_equal(s0, conjunct_ref.draw(31, [1, 0], 60, kb0.n_concepts, kb0.n_roles, 0, kb0.deciles))
+    full0 = [("and", ("top",), hthedl.conjunct_tuple(c)) for c in s0]
+    assert np.array_equal(eng0.eval_batch_device(device_batch=b0), Oracle(kb0).coverages(full0))
+    hthedl.hth_kb_set_sets(eng0.handle, None, 0)
