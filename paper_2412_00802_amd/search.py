@@ -164,8 +164,10 @@ class Refiner:
                     out.append((op, node[1], float(self.dec[node[1], tighter])))
         return out
 
-    def refine(self, h, count: int) -> List[tuple]:
-        """Up to `count` distinct one-step specialisations of h."""
+    def refine(self, h, count: int, conjuncts: bool = True) -> List[tuple]:
+        """Up to `count` distinct one-step specialisations of h: up to half of
+        them local (a position of h specialised), the rest added conjuncts
+        (none with conjuncts=False)."""
         seen, out = {h}, []
         locs = []
         for path, node, pol in self.positions(h):
@@ -177,7 +179,7 @@ class Refiner:
                 seen.add(c)
                 out.append(c)
         tries = 0
-        while len(out) < count and tries < 8 * count:
+        while conjuncts and len(out) < count and tries < 8 * count:
             tries += 1
             base = h[1:] if h[0] == "and" else (h,)
             c = ("and",) + tuple(base) + (self.conjunct(),)

@@ -104,14 +104,14 @@ class SetCache:
             return h[:-1] + (self._sub(h[-1]),)
         return h
 
-    def refill(self, parents: Sequence[tuple], chunk: int) -> float:
+    def refill(self, parents: Sequence[tuple], chunk: int, every_parent: bool = False) -> float:
         """Write the sets of the parents' subtrees (parents first, up to cap)
         into the other half, each computed from the current half; returns the
-        device time in ms."""
+        device time in ms.  every_parent: atomic parents get rows too."""
         torch = self.eng.torch
         want: Dict[tuple, None] = {}
         for p in parents:
-            if p[0] not in ("atom", "top", "bot"):
+            if every_parent or p[0] not in ("atom", "top", "bot"):
                 want.setdefault(p, None)
         for p in parents:
             subtrees(p, want)
@@ -195,6 +195,82 @@ def run_trace(cfg, kb, eng, rounds: int, per_round: int, beam: int, chunk: int, 
         refine_s = time.perf_counter() - t_ref
 
 
+def run_trace_device(cfg, kb, eng, rounds: int, per_round: int, beam: int, chunk: int, cache: SetCache, rng,
+                     seed: int, decode: bool = False):
+    """The trace with each round's added conjuncts made on the device: the
+    host writes only the local specialisations of the parents (tree positions
+    changed); hth_draw_conjuncts and hth_conjoin fill the rest of the round
+    from the parents' set-table rows, and device plans evaluate them.  Only the
+    selected candidates' specs come back to the host (to name the next
+    parents).  Yields one record per round, as run_trace does (the round's
+    candidates in full form only with decode, which reads every spec back)."""
+    torch = eng.torch
+    ref = search.Refiner(kb, rng)
+    t_ref = time.perf_counter()
+    host = round0(cfg, kb, per_round)
+    host_parent = [None] * len(host)
+    parents: List[tuple] = []
+    refine_s = time.perf_counter() - t_ref
+    for r in range(rounds):
+        t0 = time.perf_counter()
+        exprs = [cache.substitute(c, p) for c, p in zip(host, host_parent)]
+        n_dev = per_round - len(host) if parents else 0
+        out = torch.empty((len(host) + n_dev, 2), dtype=torch.int32, device=eng.device)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        if host:
+            eng.eval_batch(None, counts=out[:len(host)], chunk=chunk, encoded=hthedl.encode_batch(exprs))
+        if n_dev:
+            per = -(-n_dev // len(parents))
+            rows = np.array([cache.slot[p] for p in parents], dtype=np.uint32)
+            d_specs, (dn, do, dc) = eng.conjunct_candidates(rows, per, seed + r, kb.deciles)
+            eng.eval_batch_device(device_batch=(dn, do[:n_dev + 1], dc[:2 * n_dev]), counts=out[len(host):])
+        e1.record()
+        counts = out.cpu().numpy().view(np.uint32).copy()
+        dev_ms = e0.elapsed_time(e1)
+        top = search.top_indices(counts, eng.n_pos, beam)
+        specs = d_specs.cpu().numpy().view(hthedl.CONJ_DTYPE) if n_dev else None
+        by_row = {cache.slot[p]: p for p in parents}
+
+        def full(i):
+            if i < len(host):
+                return host[i]
+            sp = specs[i - len(host)]
+            p = by_row[int(sp["parent"])]
+            return ("and",) + (p[1:] if p[0] == "and" else (p,)) + (hthedl.conjunct_tuple(sp),)
+
+        cands = [full(i) for i in range(len(host) + n_dev)] if decode else None
+        nxt, seen = [], set()
+        for i in top:
+            c = full(i)
+            if c not in seen:                   # device draws may repeat
+                seen.add(c)
+                nxt.append(c)
+        parents = nxt
+        fill_ms = cache.refill(parents, chunk, every_parent=True)
+        t_eval = time.perf_counter() - t0
+        best = counts[top[0]]
+        rec = {"round": r, "candidates": len(host) + n_dev, "on_device": n_dev, "device_ms": round(dev_ms, 3),
+               "set_fill_ms": round(fill_ms, 3), "refine_s": round(refine_s, 3),
+               "end_to_end_s": round(refine_s + t_eval, 3),
+               "best_f1": round(float(search.f1_float(best[None], eng.n_pos)[0]), 5),
+               "best": [int(best[0]), int(best[1])]}
+        yield rec, cands, counts
+        # the host's share of the next round: local specialisations only
+        t_ref = time.perf_counter()
+        per_parent = max(1, per_round // max(1, len(parents)))
+        host, host_parent, seen = [], [], set()
+        for p in parents:
+            for c in ref.refine(p, per_parent, conjuncts=False):
+                if c not in seen:
+                    seen.add(c)
+                    host.append(c)
+                    host_parent.append(p)
+        host, host_parent = host[:per_round], host_parent[:per_round]
+        refine_s = time.perf_counter() - t_ref
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--small", action="store_true", help="a reduced KB with the same pipeline")
@@ -206,6 +282,8 @@ def main():
     ap.add_argument("--no-cache", action="store_true")
     ap.add_argument("--compare", action="store_true", help="also run the trace without the set table and "
                     "check that every round's counts are identical")
+    ap.add_argument("--device-candidates", action="store_true",
+                    help="make each round's added conjuncts on the device (hth_draw_conjuncts, device plans)")
     args = ap.parse_args()
     import torch
 
@@ -221,6 +299,8 @@ def main():
     eng = hthedl.Engine(kb, max_nodes=64, max_hyps=1)
     log(f"[trace] uploaded + kb_create in {time.perf_counter() - t:.1f}s")
     runs = [("cached", not args.no_cache)] + ([("plain", False)] if args.compare else [])
+    if args.device_candidates:
+        runs = [("device candidates", True)]
     result = {"workload": f"{cfg.name}: {kb.n:,} individuals, {kb.n_concepts} concepts, {kb.n_roles} roles / "
                           f"{kb.n_edges:,} assertions (Zipf s={cfg.zipf_s}, cap {cfg.degree_cap}), {kb.n_data} "
                           f"float32 properties; {args.rounds} rounds x {args.per_round} candidates, beam "
@@ -230,16 +310,18 @@ def main():
         cache = SetCache(eng, args.cache_rows) if use_cache else None
         rng = np.random.default_rng(synth.BASE_SEED + 40)
         recs = []
-        for i, (rec, cands, counts) in enumerate(run_trace(cfg, kb, eng, args.rounds, args.per_round, args.beam,
-                                                           args.chunk, cache, rng)):
+        gen = (run_trace_device(cfg, kb, eng, args.rounds, args.per_round, args.beam, args.chunk, cache, rng,
+                                synth.BASE_SEED + 41) if args.device_candidates else
+               run_trace(cfg, kb, eng, args.rounds, args.per_round, args.beam, args.chunk, cache, rng))
+        for i, (rec, cands, counts) in enumerate(gen):
             log(f"[trace] {name} round {rec['round']}: {rec['candidates']} candidates, device "
                 f"{rec['device_ms']:.1f} ms (+{rec['set_fill_ms']:.1f} ms set fill), end-to-end "
-                f"{rec['end_to_end_s']:.2f}s, nodes {rec['nodes']} -> {rec['nodes_after_sets']}, best F1 "
-                f"{rec['best_f1']}")
+                f"{rec['end_to_end_s']:.2f}s, nodes {rec.get('nodes')} -> {rec.get('nodes_after_sets')}, "
+                f"on the device {rec.get('on_device', 0)}, best F1 {rec['best_f1']}")
             recs.append(rec)
             if name == "cached":
                 ref_counts.append(counts)
-            else:
+            elif name == "plain":
                 assert np.array_equal(ref_counts[i], counts), f"round {i}: set-table counts differ"
         if cache is not None:
             cache.close()
