@@ -196,8 +196,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--device-plans", type=int, default=0, metavar="STEPS",
-                    help="also time STEPS evaluations of the batch with plans generated on the device")
+    ap.add_argument("--device-plans", type=int, default=5, metavar="STEPS",
+                    help="also time STEPS evaluations of the batch with plans generated on the device (0: skip)")
     ap.add_argument("--autotune", action="store_true", help="pick the schedule with the autotuner first")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of 256 MiB (byte-counter calibration)")

@@ -386,15 +386,20 @@ typedef struct {
 hth_status hth_draw_conjuncts(hth_kb kb, uint64_t seed, const uint32_t* d_parent_rows, uint32_t n_parents,
                               uint32_t per_parent, const float* d_deciles, hth_conjunct* d_specs, void* stream);
 
-/* Candidate i of d_specs (device [n]) as a hypothesis batch in the layout
+/* Candidate i of d_specs (device [n]) as hypotheses in the layout
  * hth_eval_batch and hth_dplan_create take: d_nodes [4n], d_hyp_node_offsets
- * [n+1] (= 4i), d_children [2n].  Hypothesis i is SET(parent), X's leaf,
- * X's existential (or an unreferenced TOP), AND(SET, X).  Nothing is validated
- * here: hth_dplan_create validates the nodes (a kind outside HTH_CJ_* becomes
- * an op it rejects).  Asynchronous on `stream`.  Errors: HTH_E_INVALID (NULL),
- * HTH_E_RANGE (n >= 2^22). */
+ * [n+1] (= node_base + 4i), d_children [2n], the AND of candidate i starting
+ * at children entry child_base + 2i.  With both bases 0 the arrays are a batch
+ * of their own; otherwise the three pointers point into a larger batch at
+ * node node_base and children entry child_base (its first hypotheses written
+ * by someone else), so that one plan covers the whole batch.  Hypothesis i is
+ * SET(parent), X's leaf, X's existential (or an unreferenced TOP), AND(SET, X).
+ * Nothing is validated here: hth_dplan_create validates the nodes (a kind
+ * outside HTH_CJ_* becomes an op it rejects).  Asynchronous on `stream`.
+ * Errors: HTH_E_INVALID (NULL), HTH_E_RANGE (n >= 2^22, or an index beyond
+ * 2^32). */
 hth_status hth_conjoin(const hth_conjunct* d_specs, uint32_t n, hth_node* d_nodes, uint32_t* d_hyp_node_offsets,
-                       uint32_t* d_children, void* stream);
+                       uint32_t* d_children, uint32_t node_base, uint32_t child_base, void* stream);
 
 /* Measurement.  Between hth_profile_begin and hth_profile_end every kernel the
  * library launches for this kb is bracketed by two HIP events recorded on the

@@ -78,14 +78,15 @@ __device__ __forceinline__ hth_node mk_node(uint8_t op, uint8_t inv, uint16_t ar
 
 // Candidate i: nodes 4i .. 4i+3 = SET(parent), the conjunct's leaf, the
 // existential over it (or an unreferenced ⊤), AND(set, conjunct); children
-// 2i, 2i+1; offsets[i] = 4i.  A kind outside HTH_CJ_* writes an op that
-// hth_dplan_create rejects.
+// 2i, 2i+1; offsets[i] = node_base + 4i, and the AND's children start at
+// child_base + 2i (the candidates may follow other hypotheses in one batch).
+// A kind outside HTH_CJ_* writes an op that hth_dplan_create rejects.
 __global__ void __launch_bounds__(256)
 k_conjoin(const hth_conjunct* __restrict__ specs, uint32_t n, hth_node* __restrict__ nodes,
-          uint32_t* __restrict__ offs, uint32_t* __restrict__ kids) {
+          uint32_t* __restrict__ offs, uint32_t* __restrict__ kids, uint32_t node_base, uint32_t child_base) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i > n) return;
-  offs[i] = 4 * i;
+  offs[i] = node_base + 4 * i;
   if (i == n) return;
   const hth_conjunct c = specs[i];
   hth_node* o = nodes + 4 * (size_t)i;
@@ -113,7 +114,7 @@ k_conjoin(const hth_conjunct* __restrict__ specs, uint32_t n, hth_node* __restri
       o[2] = mk_node(HTH_TOP, 0, 0, 0, 0, 0);
       break;
   }
-  o[3] = mk_node(HTH_AND, 0, 2, 0, 2 * i, 0);
+  o[3] = mk_node(HTH_AND, 0, 2, 0, child_base + 2 * i, 0);
   kids[2 * (size_t)i] = 0;
   kids[2 * (size_t)i + 1] = x;
 }
@@ -140,11 +141,14 @@ extern "C" hth_status hth_draw_conjuncts(hth_kb kb, uint64_t seed, const uint32_
 }
 
 extern "C" hth_status hth_conjoin(const hth_conjunct* d_specs, uint32_t n, hth_node* d_nodes,
-                                  uint32_t* d_hyp_node_offsets, uint32_t* d_children, void* stream) {
+                                  uint32_t* d_hyp_node_offsets, uint32_t* d_children, uint32_t node_base,
+                                  uint32_t child_base, void* stream) {
   if (!d_specs || !d_nodes || !d_hyp_node_offsets || !d_children) return fail(HTH_E_INVALID, "NULL argument");
   if (n >= (1u << 22)) return fail(HTH_E_RANGE, "more than 2^22 - 1 candidates (2^24 nodes)");
+  if ((uint64_t)node_base + 4ull * n >= (1ull << 32) || (uint64_t)child_base + 2ull * n >= (1ull << 32))
+    return fail(HTH_E_RANGE, "node or children index beyond 2^32");
   hipLaunchKernelGGL(k_conjoin, dim3((n + 1 + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream), d_specs,
-                     n, d_nodes, d_hyp_node_offsets, d_children);
+                     n, d_nodes, d_hyp_node_offsets, d_children, node_base, child_base);
   HTH_HIP(hipGetLastError());
   return HTH_OK;
 }

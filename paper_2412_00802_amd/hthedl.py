@@ -119,7 +119,7 @@ def lib() -> ctypes.CDLL:
             "hth_dplan_create": [P, P, U32, P, U32, P, U32, P, S, P, ctypes.POINTER(P), ctypes.POINTER(S)],
             "hth_dplan_launch": [P, P, S, P, P],
             "hth_draw_conjuncts": [P, U64, P, U32, U32, P, P, P],
-            "hth_conjoin": [P, U32, P, P, P, P],
+            "hth_conjoin": [P, U32, P, P, P, U32, U32, P],
             "hth_dplan_destroy": [P],
             "hth_batch_workspace_bytes": [P, P, P, U32, P, U32, ctypes.POINTER(S)],
             "hth_sync": [P],
@@ -365,12 +365,16 @@ def hth_draw_conjuncts(kb, seed: int, d_parent_rows, n_parents: int, per_parent:
                                     _ptr(d_specs), _stream(stream)))
 
 
-def hth_conjoin(d_specs, n: int, d_nodes, d_offsets, d_children, stream=None) -> None:
+def hth_conjoin(d_specs, n: int, d_nodes, d_offsets, d_children, node_base: int = 0, child_base: int = 0,
+                stream=None) -> None:
+    """d_nodes, d_offsets and d_children point where the candidates go (views
+    into a larger batch when the bases are not 0)."""
     _need_bytes(d_specs, CONJ_DTYPE.itemsize * n, "specs")
     _need_bytes(d_nodes, 4 * NODE_DTYPE.itemsize * n, "nodes")
     _need_bytes(d_offsets, 4 * (n + 1), "offsets")
     _need_bytes(d_children, 8 * n, "children")
-    _check(lib().hth_conjoin(_ptr(d_specs), n, _ptr(d_nodes), _ptr(d_offsets), _ptr(d_children), _stream(stream)))
+    _check(lib().hth_conjoin(_ptr(d_specs), n, _ptr(d_nodes), _ptr(d_offsets), _ptr(d_children), node_base,
+                             child_base, _stream(stream)))
 
 
 def conjunct_tuple(spec) -> tuple:
@@ -758,24 +762,39 @@ class Engine:
             self.dp_scratch = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
             self.dp_scratch_bytes = nbytes
 
-    def conjunct_candidates(self, parent_rows, per_parent: int, seed: int, deciles=None):
+    def conjunct_candidates(self, parent_rows, per_parent: int, seed: int, deciles=None, before=None,
+                            count: Optional[int] = None):
         """Refinement candidates drawn and written on the device
         (hth_draw_conjuncts, hth_conjoin): parent_rows (set-table rows) x
-        per_parent added conjuncts.  -> (specs, (nodes, offsets, children)),
-        all device tensors; the batch goes to eval_batch_device."""
+        per_parent added conjuncts, of which the first `count` (all by
+        default) go into the batch.  before: an encoded batch (nodes, offsets,
+        children) uploaded in front of the candidates, so that one plan covers
+        both.  -> (specs, (nodes, offsets, children)), all device tensors; the
+        batch goes to eval_batch_device."""
         torch = self.torch
         rows = torch.as_tensor(np.asarray(parent_rows, dtype=np.uint32).view(np.int32), device=self.device)
-        n = int(rows.shape[0]) * per_parent
+        n_draw = int(rows.shape[0]) * per_parent
+        n = n_draw if count is None else min(count, n_draw)
         dec = None
         if self.desc.n_data:
             dec = torch.as_tensor(np.ascontiguousarray(deciles, dtype=np.float32), device=self.device)
-        specs = torch.empty(n * CONJ_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
-        nodes = torch.empty(4 * n * NODE_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
-        offs = torch.empty(n + 1, dtype=torch.int32, device=self.device)
-        ch = torch.empty(max(1, 2 * n), dtype=torch.int32, device=self.device)
+        specs = torch.empty(n_draw * CONJ_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
+        hn = hc = hh = 0
+        if before is not None:
+            bn, bo, bc = before
+            hh, hn, hc = int(bo.shape[0]) - 1, int(bn.shape[0]), int(bc.shape[0])
+        nodes = torch.empty((hn + 4 * n) * NODE_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
+        offs = torch.empty(hh + n + 1, dtype=torch.int32, device=self.device)
+        ch = torch.empty(max(1, hc + 2 * n), dtype=torch.int32, device=self.device)
+        if before is not None:
+            nodes[:hn * NODE_DTYPE.itemsize].copy_(torch.from_numpy(
+                np.ascontiguousarray(bn, dtype=NODE_DTYPE).view(np.uint8)))
+            offs[:hh].copy_(torch.from_numpy(np.ascontiguousarray(bo[:hh], dtype=np.uint32).view(np.int32)))
+            if hc:
+                ch[:hc].copy_(torch.from_numpy(np.ascontiguousarray(bc, dtype=np.uint32).view(np.int32)))
         hth_draw_conjuncts(self.handle, seed, rows, int(rows.shape[0]), per_parent, dec, specs)
-        hth_conjoin(specs, n, nodes, offs, ch)
-        return specs, (nodes, offs, ch[:2 * n])
+        hth_conjoin(specs, n, nodes[hn * NODE_DTYPE.itemsize:], offs[hh:], ch[hc:], hn, hc)
+        return specs, (nodes, offs, ch[:hc + 2 * n])
 
     def upload_batch(self, hyps: Sequence = None, encoded=None):
         """The batch's node arrays in device memory: (nodes as bytes,

@@ -219,13 +219,16 @@ def run_trace_device(cfg, kb, eng, rounds: int, per_round: int, beam: int, chunk
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
+        # two plans: the host's candidates compiled on the host, where identical
+        # subtrees of different candidates are evaluated once (they share many),
+        # and the device's candidates planned on the device
         if host:
             eng.eval_batch(None, counts=out[:len(host)], chunk=chunk, encoded=hthedl.encode_batch(exprs))
         if n_dev:
             per = -(-n_dev // len(parents))
             rows = np.array([cache.slot[p] for p in parents], dtype=np.uint32)
-            d_specs, (dn, do, dc) = eng.conjunct_candidates(rows, per, seed + r, kb.deciles)
-            eng.eval_batch_device(device_batch=(dn, do[:n_dev + 1], dc[:2 * n_dev]), counts=out[len(host):])
+            d_specs, batch = eng.conjunct_candidates(rows, per, seed + r, kb.deciles, count=n_dev)
+            eng.eval_batch_device(device_batch=batch, counts=out[len(host):])
         e1.record()
         counts = out.cpu().numpy().view(np.uint32).copy()
         dev_ms = e0.elapsed_time(e1)

@@ -43,8 +43,9 @@ def draw(seed, parent_rows, per_parent, n_concepts, n_roles, n_data, deciles) ->
     return out
 
 
-def conjoin(specs: np.ndarray):
-    """-> (nodes [4n], offsets [n+1], children [2n]) as hth_conjoin writes them."""
+def conjoin(specs: np.ndarray, node_base: int = 0, child_base: int = 0):
+    """-> (nodes [4n], offsets [n+1], children [2n]) as hth_conjoin writes them
+    at the given bases."""
     n = specs.shape[0]
     nodes = np.zeros(4 * n, dtype=NODE_DTYPE)
     kids = np.zeros(2 * n, dtype=np.uint32)
@@ -64,6 +65,6 @@ def conjoin(specs: np.ndarray):
             nodes[4 * i + 1] = (0xFF, 0, 0, 0, 0, 0)
         if x == 1:
             nodes[4 * i + 2] = (OPS["top"], 0, 0, 0, 0, 0)
-        nodes[4 * i + 3] = (OPS["and"], 0, 2, 0, 2 * i, 0)
+        nodes[4 * i + 3] = (OPS["and"], 0, 2, 0, child_base + 2 * i, 0)
         kids[2 * i + 1] = x
-    return nodes, (4 * np.arange(n + 1)).astype(np.uint32), kids
+    return nodes, (node_base + 4 * np.arange(n + 1)).astype(np.uint32), kids

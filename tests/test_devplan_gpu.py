@@ -388,6 +388,19 @@ def test_device_candidates(gpu):
         got = eng.eval_batch_device(device_batch=batch)
         assert np.array_equal(got, o.coverages(full)), seed
         assert np.array_equal(eng.eval_batch(None, encoded=(wn, wo, wc)), got)
+    # host hypotheses in front of the candidates, one plan for both
+    front = synth.make_hypotheses(cfg, kb, count=50, depth=3)
+    enc = hthedl.encode_batch(front)
+    d_specs, batch = eng.conjunct_candidates(rows, 9, 5, kb.deciles, before=enc, count=60)
+    specs = d_specs.cpu().numpy().view(hthedl.CONJ_DTYPE)
+    assert specs.shape[0] == 63 and np.array_equal(specs, conjunct_ref.draw(5, rows, 9, kb.n_concepts, kb.n_roles,
+                                                                             kb.n_data, kb.deciles))
+    wn, wo, wc = conjunct_ref.conjoin(specs[:60], enc[0].shape[0], enc[2].shape[0])
+    assert np.array_equal(batch[0].cpu().numpy().view(hthedl.NODE_DTYPE), np.concatenate([enc[0], wn]))
+    assert np.array_equal(batch[1].cpu().numpy().view(np.uint32), np.concatenate([enc[1][:-1], wo]))
+    assert np.array_equal(batch[2].cpu().numpy().view(np.uint32), np.concatenate([enc[2], wc]))
+    both = front + [("and", parents[int(c["parent"])], hthedl.conjunct_tuple(c)) for c in specs[:60]]
+    assert np.array_equal(eng.eval_batch_device(device_batch=batch), o.coverages(both))
     # a kind outside the family is rejected by the plan's count pass
     bad = want.copy()
     bad["kind"][5] = 9
