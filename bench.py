@@ -198,6 +198,8 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--device-plans", type=int, default=5, metavar="STEPS",
                     help="also time STEPS evaluations of the batch with plans generated on the device (0: skip)")
+    ap.add_argument("--device-chunk", type=int, default=0,
+                    help="hypotheses per device plan (0: the whole batch in one plan)")
     ap.add_argument("--autotune", action="store_true", help="pick the schedule with the autotuner first")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of 256 MiB (byte-counter calibration)")
@@ -324,13 +326,16 @@ def main():
         dc = torch.empty((H, 2), dtype=torch.int32, device="cuda")
 
         eng.ensure_plan_scratch(n_nodes)
+        dchunk = args.device_chunk or H
 
         def dstep():
-            plan, nb = hthedl.hth_dplan_create(eng.handle, d_nodes, n_nodes, d_offs, H, d_ch, int(d_ch.shape[0]),
-                                               eng.dp_scratch, eng.dp_scratch_bytes, stream)
-            eng.ensure_workspace(nb)
-            hthedl.hth_dplan_launch(plan, eng.ws, eng.ws_bytes, dc, stream)
-            hthedl.hth_dplan_destroy(plan)
+            for a in range(0, H, dchunk):
+                b = min(H, a + dchunk)
+                plan, nb = hthedl.hth_dplan_create(eng.handle, d_nodes, n_nodes, d_offs[a:], b - a, d_ch,
+                                                   int(d_ch.shape[0]), eng.dp_scratch, eng.dp_scratch_bytes, stream)
+                eng.ensure_workspace(nb)
+                hthedl.hth_dplan_launch(plan, eng.ws, eng.ws_bytes, dc[a:b], stream)
+                hthedl.hth_dplan_destroy(plan)
 
         dstep()
         torch.cuda.synchronize()
@@ -342,7 +347,7 @@ def main():
         ddt = time.perf_counter() - t0
         dent = hthedl.hth_profile_end(eng.handle)
         dgot = dc.cpu().numpy().view(np.uint32)
-        dplans = {"value": round(H * args.device_plans / ddt, 1), "unit": "hypotheses/s",
+        dplans = {"value": round(H * args.device_plans / ddt, 1), "unit": "hypotheses/s", "hyps_per_plan": dchunk,
                   "ms_per_step": round(ddt / args.device_plans * 1e3, 3),
                   "equal_to_batched": bool((dgot == got).all()),
                   "kernels_ms_per_step": {KIND_NAMES.get(k, str(k)): round(e["ms"] / args.device_plans, 3)

@@ -334,7 +334,7 @@ hth_status hth_plan_destroy(hth_plan plan);
  * free or reuse the scratch).
  * Errors (create): as hth_eval_batch, with the first failing hypothesis and
  * node; HTH_E_UNSUPPORTED for HTH_NUM_* / HTH_STR_* nodes, role restrictions
- * nested more than 16 deep, and regions with more than 32 nested operators;
+ * nested more than 64 deep, and regions with more than 32 nested operators;
  * HTH_E_RANGE for n_hyps = 0 or n_nodes > 2^24; HTH_E_NOMEM / HTH_E_INVALID
  * for a short or misaligned scratch.  (launch) HTH_E_NOMEM when
  * ws_bytes is short, HTH_E_INVALID when ws is not 256-byte aligned.  The plan

@@ -31,7 +31,7 @@
 namespace hth {
 namespace {
 
-constexpr uint32_t kDpLevels = 16;          // most role-nesting levels
+constexpr uint32_t kDpLevels = 64;          // most role-nesting levels
 constexpr uint32_t kDpNest = 32;            // most operators nested inside one region
 constexpr uint32_t kDpMaxLen = 1u << 30;    // longest region program (instructions)
 
@@ -692,7 +692,7 @@ const char* dp_reason(uint32_t why, hth_status* code) {
     case DP_PROP: *code = HTH_E_RANGE; return "property id out of range";
     case DP_NAN: *code = HTH_E_INVALID; return "threshold is NaN";
     case DP_CONCRETE: *code = HTH_E_UNSUPPORTED; return "concrete-role constructs are not generated on the device";
-    case DP_LEVELS: *code = HTH_E_UNSUPPORTED; return "role restrictions nested more than 16 deep";
+    case DP_LEVELS: *code = HTH_E_UNSUPPORTED; return "role restrictions nested more than 64 deep";
     case DP_DEPTH: *code = HTH_E_UNSUPPORTED; return "boolean region nested deeper than 16 operand levels";
     case DP_NEST: *code = HTH_E_UNSUPPORTED; return "boolean region with more than 32 nested operators";
     default: *code = HTH_E_RANGE; return "region program longer than 2^30 instructions";

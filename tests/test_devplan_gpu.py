@@ -163,15 +163,15 @@ def _balanced(k, rng, op="and"):
 
 def test_deep_regions_and_nested_roles():
     """Region programs that need 2..16 stack entries (the register kernel up to
-    six, the LDS kernel above), role restrictions nested 16 deep, and the
-    limits beyond (17 entries, 17 levels, 33 nested operators) rejected."""
+    six, the LDS kernel above), role restrictions nested 64 deep, and the
+    limits beyond (17 entries, 65 levels, 33 nested operators) rejected."""
     cfg = synth.small_config(n=3000, n_concepts=16, n_roles=2, cap=8, n_data=1, n_pos=500, n_neg=500,
                              seed_index=2000)
     kb = synth.make_kb(cfg)
     rng = np.random.default_rng(20)
     hyps = [_balanced(k, rng, op) for k in (1, 2, 5, 6, 7, 9) for op in ("and", "or")]
     nest = ("atom", 1)
-    for i in range(16):
+    for i in range(64):
         nest = ("exists", i % 2, (i // 2) % 2, ("or", nest, ("atom", i % 16)) if i % 3 == 0 else nest)
     hyps.append(nest)
     hyps.append(("exists", 0, 0, _balanced(8, rng)))      # a deep filler region
