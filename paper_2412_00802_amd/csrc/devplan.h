@@ -82,6 +82,17 @@ struct DpKB {                    // what the passes read of the knowledge base
   uint32_t* tval;                // ... and per entry: index within its property, owning node
   uint32_t tmask;                // entries - 1 (a power of two above twice the nodes)
   uint32_t n_thr;                // distinct thresholds (emit pass): their rows come first
+  // hash-consing of the batch (count pass): canon[g] = the representative of
+  // node g (the first equal node to claim the key), crep the table of
+  // representatives (same size as the threshold table), nbase[g] = the first
+  // node of g's hypothesis; per representative: rowidx (role nodes) and, for
+  // a compound filler, matclaim (the role node that materialises it) and matrow
+  uint32_t* canon;
+  uint32_t* nbase;
+  uint32_t* crep;
+  uint32_t* rowidx;
+  uint32_t* matclaim;
+  uint32_t* matrow;
 };
 
 constexpr unsigned long long kDpEmpty = ~0ull;
@@ -133,6 +144,68 @@ __device__ __forceinline__ uint32_t dp_heavy(const DpKB& K, uint32_t rd) {
   return K.dir[2 * K.n_dir + rd + 1] - K.dir[2 * K.n_dir + rd];
 }
 
+// The fields that decide a node's meaning (others are ignored: q of ∃/∀, inv
+// outside role constructs, the child field of leaves), packed for hashing and
+// comparison; the children's representatives complete the key.
+struct DpKey {
+  uint32_t head, arg, q;
+};
+__device__ __forceinline__ DpKey dp_key(const hth_node& x) {
+  const bool role = dp_role(x.op), card = x.op >= HTH_ATLEAST && x.op <= HTH_EXACTLY;
+  const bool nary = x.op == HTH_AND || x.op == HTH_OR;
+  const bool has_arg = role || x.op == HTH_ATOM || x.op == HTH_SET || dp_column(x.op);
+  DpKey k;
+  k.head = (uint32_t)x.op | ((role ? (uint32_t)x.inv : 0u) << 8) | ((nary ? (uint32_t)x.arity : 0u) << 16);
+  k.arg = has_arg ? x.arg : 0u;
+  k.q = (card || dp_column(x.op)) ? x.q.n : 0u;
+  return k;
+}
+__device__ __forceinline__ uint64_t dp_mix(uint64_t h, uint64_t v) {
+  h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+  return h * 0xFF51AFD7ED558CCDull;
+}
+// child j of node x (hypothesis at b): its representative
+__device__ __forceinline__ uint32_t dp_child_rep(const DpKB& K, const hth_node& x, const uint32_t* kids, uint32_t b,
+                                                 uint32_t j) {
+  const uint32_t c = (x.op == HTH_AND || x.op == HTH_OR) ? kids[x.child + j] : x.child;
+  return K.canon[b + c];
+}
+__device__ __forceinline__ uint32_t dp_n_children(const hth_node& x) {
+  if (x.op == HTH_AND || x.op == HTH_OR) return x.arity;
+  return (x.op == HTH_NOT || dp_role(x.op)) ? 1u : 0u;
+}
+
+// The representative of node g (local index i of the hypothesis at b), whose
+// children already have theirs.  Open addressing over crep: a free slot is
+// claimed with atomicCAS; an occupied one holds a representative whose key is
+// compared exactly (its fields, and its children's representatives, written
+// by its own thread before the claim and published by the fence before it).
+// No thread ever waits for another.
+__device__ uint32_t dp_canon(const DpKB& K, const hth_node* __restrict__ nodes, const uint32_t* __restrict__ kids,
+                             uint32_t b, uint32_t g, const hth_node& x) {
+  const DpKey k = dp_key(x);
+  const uint32_t nc = dp_n_children(x);
+  uint64_t h = dp_mix(dp_mix(dp_mix(0, k.head), k.arg), k.q);
+  for (uint32_t j = 0; j < nc; ++j) h = dp_mix(h, dp_child_rep(K, x, kids, b, j));
+  K.nbase[g] = b;
+  __threadfence();                      // this node's base and its children's representatives first
+  for (uint32_t hs = (uint32_t)(h ^ (h >> 32)) & K.tmask;; hs = (hs + 1) & K.tmask) {
+    uint32_t r = K.crep[hs];
+    if (r == kNone) {
+      r = atomicCAS(K.crep + hs, kNone, g);
+      if (r == kNone) return g;
+    }
+    __threadfence();                    // the representative's base and children are visible
+    const hth_node y = nodes[r];
+    const DpKey ky = dp_key(y);
+    if (ky.head != k.head || ky.arg != k.arg || ky.q != k.q) continue;
+    const uint32_t by = K.nbase[r];
+    bool same = true;
+    for (uint32_t j = 0; j < nc && same; ++j) same = dp_child_rep(K, y, kids, by, j) == dp_child_rep(K, x, kids, b, j);
+    if (same) return r;
+  }
+}
+
 // a shared pass decides the node (saturating counts up to kGroupMaxCount)
 __device__ __forceinline__ bool dp_groupable(const hth_node& x) {
   return x.op == HTH_EXISTS || x.op == HTH_FORALL ||
@@ -152,7 +225,6 @@ k_dp_count(const hth_node* __restrict__ nodes, const uint32_t* __restrict__ offs
   if (threadIdx.x == 0) s_code = 0;
   __syncthreads();
   uint32_t* const s_thr = s_sum;
-  uint32_t* const s_slots = s_sum + 1;
   uint32_t* const s_mat = s_sum + 2;
   const uint32_t nbk = kDpLevels * (K.n_dir - 1);
   const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
@@ -173,6 +245,7 @@ k_dp_count(const hth_node* __restrict__ nodes, const uint32_t* __restrict__ offs
     for (uint32_t i = 0; i < n && ok; ++i) {
       const hth_node x = nodes[b + i];
       uint32_t hgt = 0, dep = 1, nest = 0, flags = 0;
+      uint32_t role_lvl = kNone, mat_c = kNone;   // a role node's level and compound filler
       uint64_t L = 1;
       uint32_t why = 0;
       switch (x.op) {
@@ -287,15 +360,9 @@ k_dp_count(const hth_node* __restrict__ nodes, const uint32_t* __restrict__ offs
               why = DP_NEST;
               break;
             }
-            atomicAdd(s_mat + lvl, 1u);
-            atomicAdd(s_slots, 1u);
-            atomicAdd(&s_code, (unsigned long long)len[c]);
-            atomicMax(s_max + 1, (ci >> 8) & 255u);
+            mat_c = c;
           }
-          const uint32_t rd = 2 * x.arg + x.inv;
-          atomicAdd(bk + (dp_groupable(x) ? 0u : nbk) + lvl * (K.n_dir - 1) + rd, 1u);
-          atomicAdd(s_slots, 1u);
-          atomicMax(s_max, lvl + 1);
+          role_lvl = lvl;
           break;
         }
         case HTH_NUM_GE:
@@ -317,6 +384,25 @@ k_dp_count(const hth_node* __restrict__ nodes, const uint32_t* __restrict__ offs
       }
       info[b + i] = hgt | (min(dep, 255u) << 8) | (min(nest, 255u) << 16) | flags;
       len[b + i] = (uint32_t)L;
+      const uint32_t g = b + i, rep = dp_canon(K, nodes, kids, b, g, x);
+      K.canon[g] = rep;
+      if (role_lvl != kNone && rep == g) {
+        // a representative role node: its row, its task in its bucket, and the
+        // materialisation of its compound filler unless an equal one is claimed
+        const uint32_t lvl = role_lvl, rd = 2 * x.arg + x.inv;
+        K.rowidx[g] = atomicAdd(&sum->n_slots, 1u);
+        atomicAdd(bk + (dp_groupable(x) ? 0u : nbk) + lvl * (K.n_dir - 1) + rd, 1u);
+        atomicMax(s_max, lvl + 1);
+        if (mat_c != kNone) {
+          const uint32_t cc = K.canon[mat_c];
+          if (atomicCAS(K.matclaim + cc, kNone, g) == kNone) {
+            K.matrow[cc] = atomicAdd(&sum->n_slots, 1u);
+            atomicAdd(s_mat + lvl, 1u);
+            atomicAdd(&s_code, (unsigned long long)len[mat_c]);
+            atomicMax(s_max + 1, (info[mat_c] >> 8) & 255u);
+          }
+        }
+      }
     }
     if (ok) {   // the root's region, with coverage
       const uint32_t r = b + n - 1, ri = info[r];
@@ -442,8 +528,12 @@ k_dp_emit(const hth_node* __restrict__ nodes, const uint32_t* __restrict__ offs,
         T.thr[t] = tt;
       }
     } else if (dp_role(x.op)) {
-      const uint32_t r = K.n_fixed + 1 + K.n_thr + atomicAdd(&cur->slots, 1u);
+      // rows of role nodes and materialised fillers were numbered by the count
+      // pass, per representative; a node equal to an earlier one has no task
+      const uint32_t rep = K.canon[b + i];
+      const uint32_t r = K.n_fixed + 1 + K.n_thr + K.rowidx[rep];
       row[b + i] = r;
+      if (rep != b + i) continue;
       const uint32_t c = b + x.child, ci = info[c], lvl = ci & 255u;
       const uint8_t cop = nodes[c].op;
       uint32_t crow, neg = 0;
@@ -456,10 +546,13 @@ k_dp_emit(const hth_node* __restrict__ nodes, const uint32_t* __restrict__ offs,
         crow = dp_leaf_row(K, nodes, row, b + nodes[c].child);
         neg = 1;
       } else {
-        crow = K.n_fixed + 1 + K.n_thr + atomicAdd(&cur->slots, 1u);
-        const unsigned long long off = atomicAdd(&cur->code, (unsigned long long)len[c]);
-        dp_program(K, nodes, kids, info, row, b, x.child, T.code + off);
-        T.mat[B.mat[lvl] + atomicAdd(&cur->mat[lvl], 1u)] = RegionTask{(uint32_t)off, len[c], crow, kNone};
+        const uint32_t cc = K.canon[c];
+        crow = K.n_fixed + 1 + K.n_thr + K.matrow[cc];
+        if (K.matclaim[cc] == b + i) {
+          const unsigned long long off = atomicAdd(&cur->code, (unsigned long long)len[c]);
+          dp_program(K, nodes, kids, info, row, b, x.child, T.code + off);
+          T.mat[B.mat[lvl] + atomicAdd(&cur->mat[lvl], 1u)] = RegionTask{(uint32_t)off, len[c], crow, kNone};
+        }
       }
       // count predicate (lo <= cnt <= hi over the successors in the child, or
       // outside it for the universal restriction)
@@ -643,7 +736,8 @@ namespace {
 // count (a shared pass holds at least one node, an XCD slot round at most
 // eight passes, a threshold group at least one threshold).
 struct DpScratch {
-  size_t info, len, row, sum, cur, bk, pk, dir, tkey, tval, shell, bucket, xslot, bcur, thg, pbase, total;
+  size_t info, len, row, canon, nbase, rowidx, matclaim, matrow, sum, cur, bk, pk, dir, tkey, tval, crep, shell,
+      bucket, xslot, bcur, thg, pbase, total;
   uint32_t tcap;
 };
 DpScratch dp_scratch(const hth_kb_s& kb, uint32_t n_nodes) {
@@ -660,6 +754,11 @@ DpScratch dp_scratch(const hth_kb_s& kb, uint32_t n_nodes) {
   L.info = area(n * 4);
   L.len = area(n * 4);
   L.row = area(n * 4);
+  L.canon = area(n * 4);
+  L.nbase = area(n * 4);
+  L.rowidx = area(n * 4);
+  L.matclaim = area(n * 4);
+  L.matrow = area(n * 4);
   L.sum = area(sizeof(DpSummary));
   L.cur = area(sizeof(DpCursor));
   L.bk = area(2 * nb * 4);
@@ -667,6 +766,7 @@ DpScratch dp_scratch(const hth_kb_s& kb, uint32_t n_nodes) {
   L.dir = area(3 * nd * 4);
   L.tkey = area((size_t)L.tcap * 8);
   L.tval = area((size_t)L.tcap * 8);
+  L.crep = area((size_t)L.tcap * 4);
   L.shell = area(n * sizeof(GroupTask));
   L.bucket = area(nb * sizeof(DpBucket));
   L.xslot = area(8 * n * 4);
@@ -861,6 +961,12 @@ extern "C" hth_status hth_dplan_create(hth_kb kb, const hth_node* d_nodes, uint3
   p->K.tkey = reinterpret_cast<unsigned long long*>(p->buf + L.tkey);
   p->K.tval = reinterpret_cast<uint32_t*>(p->buf + L.tval);
   p->K.tmask = tcap - 1;
+  p->K.canon = reinterpret_cast<uint32_t*>(p->buf + L.canon);
+  p->K.nbase = reinterpret_cast<uint32_t*>(p->buf + L.nbase);
+  p->K.crep = reinterpret_cast<uint32_t*>(p->buf + L.crep);
+  p->K.rowidx = reinterpret_cast<uint32_t*>(p->buf + L.rowidx);
+  p->K.matclaim = reinterpret_cast<uint32_t*>(p->buf + L.matclaim);
+  p->K.matrow = reinterpret_cast<uint32_t*>(p->buf + L.matrow);
   HTH_HIP(hipMemcpyAsync(p->buf + L.dir, dir.data(), dir.size() * 4, hipMemcpyHostToDevice, st));
   DpSummary init{};
   init.err = ~0ull;
@@ -868,6 +974,8 @@ extern "C" hth_status hth_dplan_create(hth_kb kb, const hth_node* d_nodes, uint3
   HTH_HIP(hipMemsetAsync(p->d_bk, 0, nbk2 * 4, st));
   if (nd_data) HTH_HIP(hipMemsetAsync(p->K.pk, 0, nd_data * 4, st));
   HTH_HIP(hipMemsetAsync(p->K.tkey, 0xFF, (size_t)tcap * 8, st));
+  HTH_HIP(hipMemsetAsync(p->K.crep, 0xFF, (size_t)tcap * 4, st));
+  if (n_nodes) HTH_HIP(hipMemsetAsync(p->K.matclaim, 0xFF, (size_t)n_nodes * 4, st));
   hipLaunchKernelGGL(k_dp_count, dim3((n_hyps + 255) / 256), dim3(256), 0, st, d_nodes, d_hyp_node_offsets,
                      d_children, n_nodes, n_children, n_hyps, p->K, p->info, p->len, p->d_sum, p->d_bk);
   HTH_HIP(hipGetLastError());
