@@ -308,11 +308,11 @@ hth_status hth_plan_destroy(hth_plan plan);
  * d_nodes [n_nodes], d_hyp_node_offsets [n_hyps + 1] (hypothesis h is
  * d_nodes[offsets[h] .. offsets[h+1]), local child indices; offsets need not
  * start at 0, so a chunk of a larger batch is the same arrays with the offsets
- * pointer advanced), d_children [n_children].  Identical threshold leaves of
- * the batch share one task; every other DL operation of every hypothesis is one
- * task (identical compound subexpressions of different hypotheses are each
- * evaluated on their own; every node is evaluated, reachable from its root or
- * not), run level by level on the executor's kernels with the kb's schedule:
+ * pointer advanced), d_children [n_children].  Equal subexpressions of the
+ * batch (same construct, arguments and equal children, children in the given
+ * order) are evaluated once; every distinct DL operation is one task (every
+ * node is evaluated, reachable from its root or not), run level by level on
+ * the executor's kernels with the kb's schedule:
  * role nodes of one (level, role, direction) share CSR passes, thresholds on
  * one property a column pass.
  *
@@ -321,8 +321,8 @@ hth_status hth_plan_destroy(hth_plan plan);
  * bytes per role direction and property): the only data the host reads; the
  * host builds the shared passes and the table layout from them.  *ws_bytes
  * receives the workspace that hth_dplan_launch needs.  `scratch` is device
- * memory of at least hth_dplan_scratch_bytes(kb, n_nodes) (about 230 bytes per
- * node: per-node facts, the threshold hash table, the plan's own tables),
+ * memory of at least hth_dplan_scratch_bytes(kb, n_nodes) (about 270 bytes per
+ * node: per-node facts, the hash-consing tables, the plan's own tables),
  * 256-byte aligned, owned by the caller and held by the plan until it is
  * destroyed.  The plan keeps the kb's set table and schedule as they were at
  * creation.  The node arrays must stay allocated and unchanged until the

@@ -6,25 +6,25 @@
 // device memory (hth_node arrays, as hth_eval_batch takes them on the host),
 // and two passes of one thread per hypothesis build the plan there:
 //   k_dp_count  validates every node, computes each node's role-nesting level,
-//               region-program stack depth and program length, and counts the
-//               plan's tables: role nodes per (level, role direction) bucket,
-//               distinct thresholds per property (identical threshold leaves of
-//               the batch are hash-consed into one task and row), regions,
-//               rows, program words.  The counts are the only data the host
-//               reads back;
+//               region-program stack depth and program length, hash-conses
+//               the batch (each node gets a representative: the first equal
+//               node, by construct, arguments and children's representatives)
+//               and threshold leaves, numbers the rows of representative role
+//               nodes and of the compound fillers they materialise, and counts
+//               the plan's tables: role nodes per (level, role direction)
+//               bucket, distinct thresholds per property, regions, program
+//               words.  The counts are the only data the host reads back;
 //   (host)      from the counts alone: table bases, the shared CSR passes of
 //               each large bucket (ceil(count / group_k) passes), their T rows
 //               and XCD placement, threshold groups, the workspace layout;
-//   k_dp_emit   assigns bit rows, writes the threshold, role, fill and region
-//               tasks and the shared passes' members (and acceptance masks) at
-//               per-table cursors, and writes every region program.
-// Every other DL operation of each hypothesis is one task: compound
-// subexpressions are not shared across hypotheses (the host compiler
-// hash-conses the whole DAG), and single existential restrictions are not
-// pushed; role nodes of one bucket still share CSR passes, and thresholds on
-// one property a column pass.  Every node
-// of a hypothesis is evaluated, reachable from its root or not.
-// Concrete-role constructs (HTH_NUM_*, HTH_STR_*) are not generated.
+//   k_dp_emit   writes the threshold, role, fill and region tasks and the
+//               shared passes' members (and acceptance masks) of the
+//               representatives at per-table cursors, and every region program.
+// Unlike the host compiler, children of and / or are not sorted or flattened
+// (and(a, b) and and(b, a) are two subexpressions), and single existential
+// restrictions are not pushed.  Every node of a hypothesis is evaluated,
+// reachable from its root or not.  Concrete-role constructs (HTH_NUM_*,
+// HTH_STR_*) are not generated.
 // Included by exec.hip only.
 #pragma once
 
