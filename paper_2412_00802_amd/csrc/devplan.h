@@ -87,13 +87,28 @@ struct DpKB {                    // what the passes read of the knowledge base
   // representatives (same size as the threshold table), nbase[g] = the first
   // node of g's hypothesis; per representative: rowidx (role nodes) and, for
   // a compound filler, matclaim (the role node that materialises it) and matrow
-  uint32_t* canon;
+  uint32_t* canon;                // leaves: synthetic ids from n_nodes up (see dp_leaf_id)
   uint32_t* nbase;
   uint32_t* crep;
   uint32_t* rowidx;
   uint32_t* matclaim;
   uint32_t* matrow;
+  uint32_t n_nodes;
 };
+
+// The representative of a leaf is an id of its own, never a node index:
+// n_nodes + 0 (top), + 1 (bottom), + 2 + a (atom a), + 2 + C + s (set row s),
+// + 2 + C + n_sets + slot (threshold in the threshold table's slot).  Leaf ids
+// are only compared, never used to index per-node arrays.
+__device__ __forceinline__ uint32_t dp_leaf_id(const DpKB& K, const hth_node& x, uint32_t thr_slot) {
+  switch (x.op) {
+    case HTH_TOP: return K.n_nodes;
+    case HTH_BOT: return K.n_nodes + 1;
+    case HTH_ATOM: return K.n_nodes + 2 + x.arg;
+    case HTH_SET: return K.n_nodes + 2 + K.n_concepts + x.arg;
+    default: return K.n_nodes + 2 + K.n_concepts + K.n_sets + thr_slot;
+  }
+}
 
 constexpr unsigned long long kDpEmpty = ~0ull;
 
@@ -164,11 +179,20 @@ __device__ __forceinline__ uint64_t dp_mix(uint64_t h, uint64_t v) {
   h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
   return h * 0xFF51AFD7ED558CCDull;
 }
+// Representatives and bases are read and written by threads on every XCD
+// while the count pass runs: device-scope atomic accesses, which bypass the
+// caches that are not coherent between XCDs.
+__device__ __forceinline__ uint32_t dp_load(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void dp_store(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 // child j of node x (hypothesis at b): its representative
 __device__ __forceinline__ uint32_t dp_child_rep(const DpKB& K, const hth_node& x, const uint32_t* kids, uint32_t b,
                                                  uint32_t j) {
   const uint32_t c = (x.op == HTH_AND || x.op == HTH_OR) ? kids[x.child + j] : x.child;
-  return K.canon[b + c];
+  return dp_load(K.canon + b + c);
 }
 __device__ __forceinline__ uint32_t dp_n_children(const hth_node& x) {
   if (x.op == HTH_AND || x.op == HTH_OR) return x.arity;
@@ -177,29 +201,30 @@ __device__ __forceinline__ uint32_t dp_n_children(const hth_node& x) {
 
 // The representative of node g (local index i of the hypothesis at b), whose
 // children already have theirs.  Open addressing over crep: a free slot is
-// claimed with atomicCAS; an occupied one holds a representative whose key is
-// compared exactly (its fields, and its children's representatives, written
-// by its own thread before the claim and published by the fence before it).
-// No thread ever waits for another.
+// claimed with a release compare-and-swap; an occupied one (read with
+// acquire) holds a representative whose key is compared exactly: its fields,
+// and its children's representatives, which its own thread stored before the
+// claim.  No thread ever waits for another.
 __device__ uint32_t dp_canon(const DpKB& K, const hth_node* __restrict__ nodes, const uint32_t* __restrict__ kids,
                              uint32_t b, uint32_t g, const hth_node& x) {
   const DpKey k = dp_key(x);
   const uint32_t nc = dp_n_children(x);
   uint64_t h = dp_mix(dp_mix(dp_mix(0, k.head), k.arg), k.q);
   for (uint32_t j = 0; j < nc; ++j) h = dp_mix(h, dp_child_rep(K, x, kids, b, j));
-  K.nbase[g] = b;
-  __threadfence();                      // this node's base and its children's representatives first
+  dp_store(K.nbase + g, b);
   for (uint32_t hs = (uint32_t)(h ^ (h >> 32)) & K.tmask;; hs = (hs + 1) & K.tmask) {
-    uint32_t r = K.crep[hs];
+    uint32_t r = __hip_atomic_load(K.crep + hs, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
     if (r == kNone) {
-      r = atomicCAS(K.crep + hs, kNone, g);
-      if (r == kNone) return g;
+      uint32_t expected = kNone;
+      if (__hip_atomic_compare_exchange_strong(K.crep + hs, &expected, g, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+                                               __HIP_MEMORY_SCOPE_AGENT))
+        return g;
+      r = expected;                     // the representative that claimed the slot first
     }
-    __threadfence();                    // the representative's base and children are visible
     const hth_node y = nodes[r];
     const DpKey ky = dp_key(y);
     if (ky.head != k.head || ky.arg != k.arg || ky.q != k.q) continue;
-    const uint32_t by = K.nbase[r];
+    const uint32_t by = dp_load(K.nbase + r);
     bool same = true;
     for (uint32_t j = 0; j < nc && same; ++j) same = dp_child_rep(K, y, kids, by, j) == dp_child_rep(K, x, kids, b, j);
     if (same) return r;
@@ -246,6 +271,7 @@ k_dp_count(const hth_node* __restrict__ nodes, const uint32_t* __restrict__ offs
       const hth_node x = nodes[b + i];
       uint32_t hgt = 0, dep = 1, nest = 0, flags = 0;
       uint32_t role_lvl = kNone, mat_c = kNone;   // a role node's level and compound filler
+      uint32_t thr_slot = 0;                       // a threshold's slot in the threshold table
       uint64_t L = 1;
       uint32_t why = 0;
       switch (x.op) {
@@ -276,9 +302,13 @@ k_dp_count(const hth_node* __restrict__ nodes, const uint32_t* __restrict__ offs
                 K.tval[2 * hs] = atomicAdd(K.pk + x.arg, 1u);
                 K.tval[2 * hs + 1] = b + i;
                 atomicAdd(s_thr, 1u);
+                thr_slot = hs;
                 break;
               }
-              if (prev == key) break;
+              if (prev == key) {
+                thr_slot = hs;
+                break;
+              }
             }
           }
           break;
@@ -384,8 +414,10 @@ k_dp_count(const hth_node* __restrict__ nodes, const uint32_t* __restrict__ offs
       }
       info[b + i] = hgt | (min(dep, 255u) << 8) | (min(nest, 255u) << 16) | flags;
       len[b + i] = (uint32_t)L;
-      const uint32_t g = b + i, rep = dp_canon(K, nodes, kids, b, g, x);
-      K.canon[g] = rep;
+      const uint32_t g = b + i;
+      const bool leaf = x.op == HTH_TOP || x.op == HTH_BOT || x.op == HTH_ATOM || x.op == HTH_SET || dp_column(x.op);
+      const uint32_t rep = leaf ? dp_leaf_id(K, x, thr_slot) : dp_canon(K, nodes, kids, b, g, x);
+      dp_store(K.canon + g, rep);
       if (role_lvl != kNone && rep == g) {
         // a representative role node: its row, its task in its bucket, and the
         // materialisation of its compound filler unless an equal one is claimed
@@ -394,7 +426,7 @@ k_dp_count(const hth_node* __restrict__ nodes, const uint32_t* __restrict__ offs
         atomicAdd(bk + (dp_groupable(x) ? 0u : nbk) + lvl * (K.n_dir - 1) + rd, 1u);
         atomicMax(s_max, lvl + 1);
         if (mat_c != kNone) {
-          const uint32_t cc = K.canon[mat_c];
+          const uint32_t cc = dp_load(K.canon + mat_c);
           if (atomicCAS(K.matclaim + cc, kNone, g) == kNone) {
             K.matrow[cc] = atomicAdd(&sum->n_slots, 1u);
             atomicAdd(s_mat + lvl, 1u);
@@ -967,6 +999,7 @@ extern "C" hth_status hth_dplan_create(hth_kb kb, const hth_node* d_nodes, uint3
   p->K.rowidx = reinterpret_cast<uint32_t*>(p->buf + L.rowidx);
   p->K.matclaim = reinterpret_cast<uint32_t*>(p->buf + L.matclaim);
   p->K.matrow = reinterpret_cast<uint32_t*>(p->buf + L.matrow);
+  p->K.n_nodes = n_nodes;
   HTH_HIP(hipMemcpyAsync(p->buf + L.dir, dir.data(), dir.size() * 4, hipMemcpyHostToDevice, st));
   DpSummary init{};
   init.err = ~0ull;

@@ -426,3 +426,24 @@ def test_device_candidates(gpu):
     full0 = [("and", ("top",), hthedl.conjunct_tuple(c)) for c in s0]
     assert np.array_equal(eng0.eval_batch_device(device_batch=b0), Oracle(kb0).coverages(full0))
     hthedl.hth_kb_set_sets(eng0.handle, None, 0)
+
+
+def test_hash_consing_shares_equal_subexpressions():
+    """A batch repeated twenty times plans exactly the passes of the batch
+    alone: every copy of a subexpression finds the first one's representative."""
+    cfg = synth.small_config(n=30000, n_concepts=32, n_roles=3, s=1.4, cap=400, n_data=2, n_pos=3000,
+                             n_neg=3000, n_hyps=60, hyp_depth=5, seed_index=2700)
+    kb = synth.make_kb(cfg)
+    hyps = synth.make_hypotheses(cfg, kb)
+    eng = hthedl.Engine(kb, max_hyps=20 * len(hyps))
+    launches = {}
+    for reps in (1, 20):
+        batch = hyps * reps
+        eng.eval_batch_device(batch)
+        hthedl.hth_profile_begin(eng.handle)
+        got = eng.eval_batch_device(batch)
+        prof = hthedl.hth_profile_end(eng.handle)
+        launches[reps] = [prof[k]["launches"] for k in (0, 2, 3, 4)]   # thresholds, roles, T builds, passes
+        assert np.array_equal(got, np.tile(Oracle(kb).coverages(hyps), (reps, 1)))
+    say(f"[devplan] launches alone / repeated: {launches}")
+    assert launches[1] == launches[20]
