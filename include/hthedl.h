@@ -348,6 +348,15 @@ hth_status hth_dplan_create(hth_kb kb, const hth_node* d_nodes, uint32_t n_nodes
 hth_status hth_dplan_launch(hth_dplan plan, void* ws, size_t ws_bytes, uint32_t* d_counts /* [n_hyps][2] */,
                             void* stream);
 hth_status hth_dplan_destroy(hth_dplan plan);
+/* The structure of a device plan, as its count pass and the host's schedule
+ * left it: role-nesting levels; distinct role nodes (one per class of equal
+ * role subexpressions), of which shared_passes groups hold the members of
+ * shared CSR passes; distinct thresholds; materialised compound fillers; bit
+ * rows of the workspace.  Errors: HTH_E_INVALID (NULL). */
+typedef struct {
+  uint32_t levels, role_nodes, shared_passes, thresholds, materialised, rows;
+} hth_dplan_info;
+hth_status hth_dplan_stats(hth_dplan plan, hth_dplan_info* out);
 
 /* Refinement candidates written on the device: the one-step specialisation
  * that adds a conjunct, candidate = P and X, for parents P whose instance sets

@@ -1181,6 +1181,21 @@ extern "C" hth_status hth_dplan_launch(hth_dplan plan, void* ws, size_t ws_bytes
   return HTH_OK;
 }
 
+extern "C" hth_status hth_dplan_stats(hth_dplan plan, hth_dplan_info* out) {
+  using namespace hth;
+  if (!plan || !out) return hth::fail(HTH_E_INVALID, "NULL argument");
+  const hth_dplan_s& p = *plan;
+  out->levels = p.sum.levels;
+  out->role_nodes = p.n_role + p.n_members;
+  out->shared_passes = p.n_groups;
+  out->thresholds = p.sum.n_thr;
+  uint32_t mats = 0;
+  for (uint32_t L = 0; L < kDpLevels; ++L) mats += p.sum.mat[L];
+  out->materialised = mats;
+  out->rows = p.sum.n_slots + p.sum.n_thr + 1;
+  return HTH_OK;
+}
+
 extern "C" hth_status hth_dplan_destroy(hth_dplan plan) {
   delete plan;
   return HTH_OK;

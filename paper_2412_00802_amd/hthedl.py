@@ -46,7 +46,7 @@ EXPORTED = ["hth_kb_derived_bytes", "hth_kb_create", "hth_kb_set_examples", "hth
             "hth_plan_upload", "hth_plan_launch", "hth_plan_destroy", "hth_numeric_derived_bytes",
             "hth_kb_set_numeric", "hth_string_derived_bytes", "hth_kb_set_strings", "hth_kb_set_patterns",
             "hth_dplan_scratch_bytes", "hth_dplan_create", "hth_dplan_launch", "hth_dplan_destroy",
-            "hth_draw_conjuncts", "hth_conjoin"]
+            "hth_draw_conjuncts", "hth_conjoin", "hth_dplan_stats"]
 
 
 class HthError(RuntimeError):
@@ -73,6 +73,11 @@ class Tuning(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class DplanInfo(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint32) for f in ("levels", "role_nodes", "shared_passes", "thresholds",
+                                                 "materialised", "rows")]
 
 
 class ProfEntry(ctypes.Structure):
@@ -121,6 +126,7 @@ def lib() -> ctypes.CDLL:
             "hth_draw_conjuncts": [P, U64, P, U32, U32, P, P, P],
             "hth_conjoin": [P, U32, P, P, P, U32, U32, P],
             "hth_dplan_destroy": [P],
+            "hth_dplan_stats": [P, ctypes.POINTER(DplanInfo)],
             "hth_batch_workspace_bytes": [P, P, P, U32, P, U32, ctypes.POINTER(S)],
             "hth_sync": [P],
             "hth_profile_begin": [P],
@@ -390,6 +396,12 @@ def conjunct_tuple(spec) -> tuple:
 
 def hth_dplan_launch(plan, ws, ws_bytes: int, d_counts, stream=None) -> None:
     _check(lib().hth_dplan_launch(plan, _ptr(ws), ws_bytes, _ptr(d_counts), _stream(stream)))
+
+
+def hth_dplan_stats(plan) -> dict:
+    info = DplanInfo()
+    _check(lib().hth_dplan_stats(plan, ctypes.byref(info)))
+    return {f: int(getattr(info, f)) for f, _ in DplanInfo._fields_}
 
 
 def hth_dplan_destroy(plan) -> None:

@@ -447,3 +447,53 @@ def test_hash_consing_shares_equal_subexpressions():
         assert np.array_equal(got, np.tile(Oracle(kb).coverages(hyps), (reps, 1)))
     say(f"[devplan] launches alone / repeated: {launches}")
     assert launches[1] == launches[20]
+
+
+ROLE_OPS = ("exists", "forall", "atleast", "atmost", "exactly")
+
+
+def _distinct(hyps):
+    """Distinct role subexpressions and thresholds of a batch, with the deepest
+    role nesting (equality of the tuple forms: what hash-consing must find)."""
+    roles, thr = set(), set()
+
+    def walk(h):
+        if h[0] in ROLE_OPS:
+            roles.add(h)
+            return walk(h[-1]) + 1
+        if h[0] in ("dge", "dle", "deq"):
+            thr.add((h[0], h[1], np.float32(h[2]).view(np.uint32).item()))
+        if h[0] == "not":
+            return walk(h[1])
+        if h[0] in ("and", "or"):
+            return max([walk(c) for c in h[1:]] + [0])
+        return 0
+
+    depth = max(walk(h) for h in hyps)
+    return len(roles), len(thr), depth
+
+
+def test_hash_consing_finds_every_shared_subtree(gpu):
+    """Sized hypotheses whose subtrees come from a shared pool (the uneven
+    batch's generator): the device plan holds exactly one role node per
+    distinct role subexpression and one task per distinct threshold, and its
+    levels are the deepest role nesting."""
+    cfg = synth.small_config(n=20000, n_concepts=48, n_roles=4, s=1.5, cap=200, n_data=4, n_pos=2000,
+                             n_neg=2000, seed_index=2800)
+    kb = synth.make_kb(cfg)
+    hyps = synth.make_sized_hypotheses(cfg, kb, count=3000)
+    n_roles, n_thr, depth = _distinct(hyps)
+    eng = hthedl.Engine(kb, max_hyps=len(hyps))
+    nodes, offs, ch = hthedl.encode_batch(hyps)
+    d_nodes, d_offs, d_ch = eng.upload_batch(encoded=(nodes, offs, ch))
+    eng.ensure_plan_scratch(nodes.shape[0])
+    plan, nb = hthedl.hth_dplan_create(eng.handle, d_nodes, nodes.shape[0], d_offs, len(hyps), d_ch, d_ch.shape[0],
+                                       eng.dp_scratch, eng.dp_scratch_bytes)
+    try:
+        info = hthedl.hth_dplan_stats(plan)
+    finally:
+        hthedl.hth_dplan_destroy(plan)
+    say(f"[devplan] pool batch: {info}; distinct role subexpressions {n_roles}, thresholds {n_thr}, depth {depth}")
+    assert info["role_nodes"] == n_roles and info["thresholds"] == n_thr and info["levels"] == depth
+    got = eng.eval_batch_device(encoded=(nodes, offs, ch))
+    assert np.array_equal(got, Oracle(kb).coverages(hyps))
