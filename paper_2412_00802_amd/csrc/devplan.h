@@ -45,7 +45,8 @@ struct DpSummary {
   unsigned long long err;       // lowest (hypothesis << 32 | node << 8 | reason); ~0 = none
   unsigned long long code;      // region-program instructions of all regions
   uint32_t levels, mat_depth, root_depth, pad;         // maxima
-  uint32_t n_thr, n_slots;      // sums (contiguous with the per-level array below)
+  uint32_t n_thr;               // summed per block (contiguous with the per-level array below)
+  uint32_t n_slots;             // row counter: role and filler rows are numbered from it
   uint32_t mat[kDpLevels];
 };
 constexpr int kDpSums = 2 + kDpLevels;
@@ -63,7 +64,6 @@ struct DpBucket {
 
 struct DpCursor {                // allocation cursors of the emit pass
   unsigned long long code;
-  uint32_t thr, slots;
   uint32_t mat[kDpLevels], role[kDpLevels], fill[kDpLevels];
 };
 
@@ -740,7 +740,7 @@ struct hth_dplan_s {
   hth::DpKB K{};
   hth::DpSummary sum{};
   hth::DpBases B{};
-  uint32_t n_mat = 0, n_role = 0, n_fill = 0, n_groups = 0, n_members = 0;
+  uint32_t n_mat = 0, n_role = 0, n_groups = 0, n_members = 0;
   uint32_t fills[hth::kDpLevels] = {};
   uint64_t nhb[hth::kDpLevels] = {}, nhc[hth::kDpLevels] = {};
   uint64_t max_nhb = 0;
@@ -894,7 +894,6 @@ hth_status dp_schedule(hth_dplan_s& p, const std::vector<uint32_t>& bk, std::vec
       if (kb.tune.xcd_local && c.n >= 8) place_on_xcds(kb, p.lv_groups[L], c, xslots);
     p.n_groups += (uint32_t)p.lv_groups[L].size();
   }
-  p.n_fill = fill;
   size_t gpart = 0;
   for (uint32_t L = 0; L < S.levels; ++L)
     for (const GroupChunk& c : p.lv_chunks[L]) gpart = std::max(gpart, chunk_partial_bytes(kb, p.lv_groups[L], c));
