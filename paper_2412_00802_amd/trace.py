@@ -200,9 +200,9 @@ def run_trace_device(cfg, kb, eng, rounds: int, per_round: int, beam: int, chunk
     """The trace with each round's added conjuncts made on the device: the
     host writes only the local specialisations of the parents (tree positions
     changed); hth_draw_conjuncts and hth_conjoin fill the rest of the round
-    from the parents' set-table rows, and device plans evaluate them.  Only the
-    selected candidates' specs come back to the host (to name the next
-    parents).  Yields one record per round, as run_trace does (the round's
+    from the parents' set-table rows.  Both halves are planned on the device
+    (hth_dplan_*).  Only the selected candidates' specs come back to the host
+    (to name the next parents).  Yields one record per round, as run_trace does (the round's
     candidates in full form only with decode, which reads every spec back)."""
     torch = eng.torch
     ref = search.Refiner(kb, rng)
@@ -219,11 +219,10 @@ def run_trace_device(cfg, kb, eng, rounds: int, per_round: int, beam: int, chunk
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        # two plans: the host's candidates compiled on the host, where identical
-        # subtrees of different candidates are evaluated once (they share many),
-        # and the device's candidates planned on the device
+        # two plans, both generated on the device: the host's candidates
+        # (uploaded) and the device's (written there)
         if host:
-            eng.eval_batch(None, counts=out[:len(host)], chunk=chunk, encoded=hthedl.encode_batch(exprs))
+            eng.eval_batch_device(encoded=hthedl.encode_batch(exprs), counts=out[:len(host)])
         if n_dev:
             per = -(-n_dev // len(parents))
             rows = np.array([cache.slot[p] for p in parents], dtype=np.uint32)
