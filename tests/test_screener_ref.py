@@ -114,3 +114,30 @@ def test_predicted_f1_from_log_removed_counts():
     f = S.predicted_f1(z, n_pos, n_neg, base, kind="log_removed")
     np.testing.assert_allclose(f, [2 * 40 / (40 + 10 + 100), 2 * 35 / (35 + 6 + 100), 0.0], rtol=1e-12)
     assert S.predicted_f1(np.array([[-3.0, -1.0]]), n_pos, n_neg, base[:1], kind="log_removed")[0] == f[0]
+
+
+def test_fnv1a64_published_vectors():
+    """The subtree hash's byte hash is FNV-1a 64 (xor, then multiply), pinned to
+    the published test vectors of Fowler, Noll and Vo; FNV-1 (multiply, then
+    xor) gives other values and would fail."""
+    assert S._fnv(S.FNV_OFFSET, b"") == 0xCBF29CE484222325
+    assert S._fnv(S.FNV_OFFSET, b"a") == 0xAF63DC4C8601EC8C
+    assert S._fnv(S.FNV_OFFSET, b"foobar") == 0x85944171F73967E8
+    # the FNV-1 vectors of the same inputs differ from what _fnv returns
+    assert S._fnv(S.FNV_OFFSET, b"a") != 0xAF63BD4C8601B7BE
+    assert S._fnv(S.FNV_OFFSET, b"foobar") != 0x340D8765A4DDA9C2
+    # byte order: a header is hashed as its little-endian bytes
+    h = S._header("atom", arg=0x01020304)
+    assert h[4:8] == b"\x04\x03\x02\x01"
+
+
+def test_splitmix64_published_outputs():
+    """_splitmix(x) is the output of a SplitMix64 generator whose state was x
+    (Steele, Lea and Flood): state + golden gamma, then the two multiply-xorshift
+    rounds.  Outputs k = 0, 1, 2, ... of seed s are _splitmix(s + k * gamma);
+    seed 1234567 gives the published reference sequence, seed 0 its first value."""
+    gamma = 0x9E3779B97F4A7C15
+    seq = [S._splitmix((1234567 + k * gamma) & S.MASK64) for k in range(5)]
+    assert seq == [6457827717110365317, 3203168211198807973, 9817491932198370423,
+                   4593380528125082431, 16408922859458223821]
+    assert S._splitmix(0) == 0xE220A8397B1DCDAF

@@ -120,3 +120,46 @@ def test_refinement_rounds_end_on_a_small_candidate_space():
         assert len(cands) == len(set(cands)) and counts.shape == (len(cands), 2)
         n += 1
     assert n == 2
+
+
+def test_oracle_f1_hand_values():
+    """F1 = 2TP / (2TP + FP + FN) with TP = pos, FP = neg, FN = |P| - pos."""
+    from fractions import Fraction
+
+    from oracle.dl import f1_score
+
+    def f(p, n, P):
+        a, b = f1_score(p, n, P)
+        return Fraction(a, b)
+
+    assert f(20, 10, 40) == Fraction(40, 70)          # 2*20 / (40 + 10 + 20)
+    assert f(40, 0, 40) == 1                          # every positive, no negative
+    assert f(0, 7, 40) == 0
+    assert f(10, 5, 40) == Fraction(20, 55)           # 20 / (20 + 5 + 30)
+    assert f1_score(0, 0, 0) == (0, 1)                # empty denominator
+    assert f(3, 1, 4) == Fraction(6, 8)               # TP 3, FP 1, FN 1
+
+
+def test_rank_agrees_with_the_oracle_f1():
+    """search.rank's order, checked against the oracle's exact F1: F1 never
+    rises along the order, and equal F1 breaks by pos descending, neg ascending,
+    size ascending, then index."""
+    from fractions import Fraction
+
+    from oracle.dl import f1_score
+    rng = np.random.default_rng(7)
+    n_pos = 50
+    counts = np.stack([rng.integers(0, n_pos + 1, 400), rng.integers(0, 60, 400)], axis=1)
+    counts[::7] = counts[3]                           # plenty of exact ties
+    sizes = rng.integers(1, 6, 400)
+    order = search.rank(counts, n_pos, sizes)
+    assert sorted(order.tolist()) == list(range(400))
+
+    def key(i):
+        a, b = f1_score(int(counts[i, 0]), int(counts[i, 1]), n_pos)
+        return (-Fraction(a, b), -int(counts[i, 0]), int(counts[i, 1]), int(sizes[i]), i)
+
+    assert order.tolist() == sorted(range(400), key=key)
+    # the vectorised pre-filter keeps the exact order (no size tie-break there)
+    top = search.top_indices(counts, n_pos, 25)
+    assert top.tolist() == sorted(range(400), key=lambda i: key(i)[:3] + (i,))[:25]
