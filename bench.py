@@ -26,7 +26,7 @@ KIND_NAMES = {0: "k_threshold", 1: "k_region", 2: "k_role", 3: "k_tbuild", 4: "k
 # the dominant kernel's source: its counters are void once these change
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2412_00802_amd", "csrc", f)
                   for f in ("group_kernels.h", "hth_internal.h")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2.json")   # counters of the c2 workload
+TRAFFIC_DIR = os.path.join(ROOT, "profiles")          # traffic_<workload>.json: the counters of a workload
 COPY_BYTES = 256 << 20      # elementwise pass used to calibrate the byte counters
 
 
@@ -38,11 +38,16 @@ def source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(kernel: str, traffic_file: str = TRAFFIC_FILE):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or
-    None when the kernel source changed since the counters were taken."""
+def traffic_file(workload: str) -> str:
+    return os.path.join(TRAFFIC_DIR, f"traffic_{workload}.json")
+
+
+def recorded_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary of
+    `workload`, or None when the kernel source changed since the counters
+    were taken."""
     try:
-        rec = json.load(open(traffic_file))
+        rec = json.load(open(traffic_file(workload)))
     except (OSError, ValueError):
         return None
     if rec.get("source_sha") != source_sha():
@@ -57,8 +62,8 @@ def kernel_name(name: str) -> str:
 
 
 def summarize(kt_dir: str, fetch_dir: str, write_dir: str, command: str, out_md: str,
-              sha: str = None, title: str = "c2 workload (1M individuals, 4096 hypotheses, batched)",
-              traffic_file: str = TRAFFIC_FILE, tcc_dir: str = None) -> None:
+              sha: str = None, title: str = "c3 workload (4M individuals, 65,536 hypotheses, batched)",
+              workload: str = "c3", tcc_dir: str = None) -> None:
     """Turn rocprofv3 outputs (kernel trace stats, FETCH_SIZE, WRITE_SIZE passes,
     each run with --calibrate-copy) into the committed summary and traffic file.
     sha: the kernel source hash of the profiled build (default: the current one)."""
@@ -99,7 +104,7 @@ def summarize(kt_dir: str, fetch_dir: str, write_dir: str, command: str, out_md:
         lines.append(f"| {kernel_name(r['Name'])} | {r['Calls']} | "
                      f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
     lines += ["", "## Bytes (FETCH_SIZE / WRITE_SIZE, KiB per dispatch)", "",
-              f"Calibration: `{ck[:50]}` (one elementwise pass over {COPY_BYTES >> 20} MiB of untouched memory) reads "
+              f"Calibration: `{ck[:50]}` (one elementwise pass over {COPY_BYTES >> 20} MiB written just before, into another buffer) reads "
               f"{fetch[ck][1]:.0f} KiB and writes {write[ck][1]:.0f} KiB per dispatch: "
               f"{f_fac:.3f} fetched bytes and {w_fac:.3f} written bytes per counted KiB-byte.", "",
               "| kernel | fetch KiB | write KiB | HBM bytes per launch (scaled) |", "|---|---|---|---|"]
@@ -130,7 +135,7 @@ def summarize(kt_dir: str, fetch_dir: str, write_dir: str, command: str, out_md:
             h, m = hit.get(k, (0, 0.0))[1], miss[k][1]
             lines.append(f"| {k[:60]} | {h:.3g} | {m:.3g} | {m / max(h + m, 1e-9):.2f} |")
     open(out_md, "w").write("\n".join(lines) + "\n")
-    json.dump(out, open(traffic_file, "w"), indent=1)
+    json.dump(out, open(traffic_file(workload), "w"), indent=1)
 
 
 def summarize_trace(kt_dir: str, command: str, out_md: str, title: str) -> None:
@@ -171,19 +176,72 @@ def make_workload_hypotheses(name, cfg, kb):
     return synth.make_hypotheses(cfg, kb)
 
 
-def cpu_baseline(kb, hyps, sample: int, budget_s: float):
-    from oracle import Oracle
-    o = Oracle(kb)
-    for r in range(kb.n_roles):          # the KB resident in RAM before timing
-        o.assertions(r)
-    t0 = time.perf_counter()
-    out = []
-    for h in hyps[:sample]:
-        out.append(o.coverage(h))
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return np.asarray(out, dtype=np.uint32).reshape(-1, 2), dt
+def cpu_info() -> dict:
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model}
+
+
+def cpu_baseline(kb, hyps, got, budget_s: float, runs: int):
+    """The C++ oracle (one byte per membership, recursive, OpenMP over
+    hypotheses) on a bounded sample: `runs` timed runs on all the cores this
+    process may use and `runs` on one thread.  The sample is sized from a
+    first probe so that all runs together take about budget_s seconds."""
+    from oracle.cpp_oracle import CppOracle, batch_tokens
+    info = cpu_info()
+    threads = info["affinity"]
+    t = time.perf_counter()
+    o = CppOracle(kb)
+    load_s = time.perf_counter() - t
+    # probe: a few hypotheses on all threads
+    probe = min(len(hyps), max(8, threads))
+    toks, offs = batch_tokens(hyps[:probe])
+    t = time.perf_counter()
+    o.coverages_tokens(toks, offs, threads)
+    per_hyp_1t = (time.perf_counter() - t) * threads / probe       # thread-seconds per hypothesis
+    # all-core runs get ~2/3 of the budget, one-thread runs ~1/3
+    n_all = int(min(len(hyps), max(threads, budget_s * 2 / 3 / runs / per_hyp_1t * threads)))
+    n_one = int(min(n_all, max(2, budget_s / 3 / runs / per_hyp_1t)))
+    toks, offs = batch_tokens(hyps[:n_all])
+    rates_all, rates_one, want = [], [], None
+    for _ in range(runs):
+        t = time.perf_counter()
+        want = o.coverages_tokens(toks, offs, threads)
+        rates_all.append(n_all / (time.perf_counter() - t))
+    t1, o1 = batch_tokens(hyps[:n_one])
+    for _ in range(runs):
+        t = time.perf_counter()
+        o.coverages_tokens(t1, o1, 1)
+        rates_one.append(n_one / (time.perf_counter() - t))
+    o.close()
+    parity = {"checked": n_all, "equal": int((got[:n_all] == want).all(axis=1).sum()), "against": "oracle/cpp"}
+    rec = {"value": round(float(np.median(rates_all)), 2), "unit": "hypotheses/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"first {n_all} hypotheses of the batch (one thread: first {n_one}); oracle/cpp, one byte "
+                     f"per membership, OpenMP over hypotheses; KB in RAM (conversion {load_s:.1f}s excluded); "
+                     f"{runs} runs each, median",
+           "all_cores": {"threads": threads, "runs": [round(r, 2) for r in rates_all],
+                         "mean": round(float(np.mean(rates_all)), 2), "median": round(float(np.median(rates_all)), 2)},
+           "one_thread": {"runs": [round(r, 3) for r in rates_one], "mean": round(float(np.mean(rates_one)), 3),
+                          "median": round(float(np.median(rates_one)), 3)},
+           "cpu": info}
+    return rec, parity
+
+
+def kernel_table(entries, steps):
+    out = {}
+    for k, e in enumerate(entries):
+        if e["launches"]:
+            out[KIND_NAMES.get(k, str(k))] = {
+                "launches_per_step": e["launches"] / steps, "ms_per_step": round(e["ms"] / steps, 4),
+                "model_GBps": round(e["bytes"] / (e["ms"] * 1e-3) / 1e9, 1) if e["ms"] else None}
+    return out
 
 
 def main():
@@ -191,33 +249,41 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c2")
-    ap.add_argument("--plain", type=int, default=512, help="hypotheses timed one at a time (0 = skip)")
-    ap.add_argument("--cpu-sample", type=int, default=512)
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--config", default="c3")
+    ap.add_argument("--host-plans", action="store_true",
+                    help="time the host-compiled batch (hth_eval_batch) as the step instead of device plans")
+    ap.add_argument("--other-steps", type=int, default=3, help="steps of the other plan path (0: skip)")
+    ap.add_argument("--graph", type=int, default=10, metavar="REPLAYS",
+                    help="replays of the step's plan launch captured in a HIP graph (0: skip)")
+    ap.add_argument("--plain", type=int, default=256, help="hypotheses timed one at a time (0 = skip)")
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of the CPU-baseline runs (0: skip)")
+    ap.add_argument("--cpu-runs", type=int, default=5)
+    ap.add_argument("--c5", type=int, default=1, help="screened-search leg on the c3 KB (c3 only)")
+    ap.add_argument("--c5-pairs", type=int, default=200_000)
+    ap.add_argument("--c4-rounds", type=int, default=3, help="refinement-trace rounds at c4 (0: skip)")
+    ap.add_argument("--time-budget", type=float, default=420.0,
+                    help="seconds after which the optional legs are skipped")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--device-plans", type=int, default=5, metavar="STEPS",
-                    help="also time STEPS evaluations of the batch with plans generated on the device (0: skip)")
-    ap.add_argument("--device-chunk", type=int, default=0,
-                    help="hypotheses per device plan (0: the whole batch in one plan)")
     ap.add_argument("--autotune", action="store_true", help="pick the schedule with the autotuner first")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of 256 MiB (byte-counter calibration)")
     ap.add_argument("--summarize", nargs=3, metavar=("KT_DIR", "FETCH_DIR", "WRITE_DIR"))
-    ap.add_argument("--summary-out", default=os.path.join(ROOT, "profiles", "k_group_c2.md"))
+    ap.add_argument("--summary-out", default=os.path.join(ROOT, "profiles", "k_group_c3.md"))
     ap.add_argument("--summary-sha", default=None, help="kernel source hash of the profiled build")
     ap.add_argument("--summary-tcc", default=None, help="rocprofv3 output of the L2 hit/miss pass")
     ap.add_argument("--summarize-trace", default=None, metavar="KT_DIR",
                     help="write only the kernel-time table of a kernel-trace run")
     ap.add_argument("--summary-title", default="")
     ap.add_argument("--summary-command", default="rocprofv3 {opts} -d OUT -o run -- python3 bench.py "
-                    "--steps 2 --warmup 1 --plain 0 --cpu-sample 0 --no-profile --calibrate-copy")
+                    "--steps 2 --warmup 1 --plain 0 --cpu-budget 0 --c5 0 --c4-rounds 0 --graph 0 "
+                    "--other-steps 0 --no-profile --calibrate-copy")
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, args.summary_command, args.summary_out, args.summary_title)
         return
     if args.summarize:
         summarize(*args.summarize, args.summary_command, args.summary_out, args.summary_sha,
+                  title=args.summary_title or f"{args.config} workload, batched", workload=args.config,
                   tcc_dir=args.summary_tcc)
         return
     if args.gpus != 1:
@@ -225,8 +291,9 @@ def main():
               "design note, not part of this build", file=sys.stderr)
         sys.exit(2)
 
+    t_start = time.perf_counter()
     import torch
-    from paper_2412_00802_amd import hthedl, synth
+    from paper_2412_00802_amd import bytes_model, hthedl, synth
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     cfg = synth.CONFIGS[args.config]
@@ -238,15 +305,35 @@ def main():
     t = time.perf_counter()
     eng = hthedl.Engine(kb, max_nodes=64, max_hyps=1)
     eng.ensure_workspace(hthedl.hth_batch_workspace_bytes(eng.handle, nodes, offs, ch))
+    d_nodes, d_offs, d_ch = eng.upload_batch(encoded=(nodes, offs, ch))
+    n_nodes = int(nodes.shape[0])
+    eng.ensure_plan_scratch(n_nodes)
     torch.cuda.synchronize()
-    log(f"[bench] uploaded + kb_create in {time.perf_counter() - t:.1f}s; workspace {eng.ws_bytes / 2**30:.2f} GiB")
+    log(f"[bench] uploaded + kb_create in {time.perf_counter() - t:.1f}s")
     H = len(hyps)
-    counts = torch.empty((H, 2), dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
+    counts = torch.empty((H, 2), dtype=torch.int32, device="cuda")
+    other = torch.empty((H, 2), dtype=torch.int32, device="cuda")
 
-    def step():
-        hthedl.hth_eval_batch(eng.handle, nodes, offs, ch, eng.ws, eng.ws_bytes, counts, stream)
+    def host_step(out):
+        hthedl.hth_eval_batch(eng.handle, nodes, offs, ch, eng.ws, eng.ws_bytes, out, stream)
 
+    def device_plan():
+        plan, nb = hthedl.hth_dplan_create(eng.handle, d_nodes, n_nodes, d_offs, H, d_ch, int(d_ch.shape[0]),
+                                           eng.dp_scratch, eng.dp_scratch_bytes, stream)
+        eng.ensure_workspace(nb)
+        return plan
+
+    def device_step(out):
+        # the node arrays are in HBM: the plan is generated there (count pass,
+        # the summary read back, the emit pass) and run
+        plan = device_plan()
+        try:
+            hthedl.hth_dplan_launch(plan, eng.ws, eng.ws_bytes, out, stream)
+        finally:
+            hthedl.hth_dplan_destroy(plan)
+
+    step, other_step = (host_step, device_step) if args.host_plans else (device_step, host_step)
     schedule = None
     if args.autotune:
         from paper_2412_00802_amd import autotune
@@ -254,56 +341,122 @@ def main():
         eng.ensure_workspace(hthedl.hth_batch_workspace_bytes(eng.handle, nodes, offs, ch))
         log(f"[bench] schedule {schedule}")
     if args.calibrate_copy:
-        # one elementwise kernel over memory nothing has touched: reads and
-        # writes COPY_BYTES each (the byte-counter calibration)
-        src = torch.empty(COPY_BYTES // 4, dtype=torch.int32, device="cuda")
+        # the byte-counter calibration: one elementwise kernel reading a buffer
+        # that was written first (so its pages are resident) and writing another
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
         dst = torch.add(src, 1)
         torch.cuda.synchronize()
         del src, dst
     for _ in range(args.warmup):
-        step()
+        step(counts)
     torch.cuda.synchronize()
     if not args.no_profile:
         hthedl.hth_profile_begin(eng.handle)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        step(counts)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    entries = None
-    if not args.no_profile:
-        entries = hthedl.hth_profile_end(eng.handle)
+    entries = hthedl.hth_profile_end(eng.handle) if not args.no_profile else None
     got = counts.cpu().numpy().view(np.uint32).copy()
     value = H * args.steps / dt
-    log(f"[bench] batched: {value:,.0f} hyp/s ({dt / args.steps * 1e3:.3f} ms/step)")
+    ms_step = dt / args.steps * 1e3
+    log(f"[bench] batched ({'host' if args.host_plans else 'device'} plans): {value:,.0f} hyp/s "
+        f"({ms_step:.3f} ms/step)")
 
-    roofline = None
-    kernels = {}
+    # the byte model of this batch: the roofline of the whole step
+    t = time.perf_counter()
+    shape = bytes_model.KBShape(kb)
+    model = bytes_model.batch_model(hyps, shape)
+    log(f"[bench] byte model in {time.perf_counter() - t:.1f}s: {bytes_model.summary(model)}")
+    step_roofline = {"bound": "hbm", "model_bytes": model["total"], "achieved": round(model["total"] / dt * args.steps / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(model["total"] / (dt / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
+                     "model_GB": bytes_model.summary(model)}
+
+    roofline, kernels = None, {}
     if entries is not None:
-        for k, e in enumerate(entries):
-            if e["launches"]:
-                kernels[KIND_NAMES.get(k, str(k))] = {
-                    "launches_per_step": e["launches"] / args.steps,
-                    "ms_per_step": e["ms"] / args.steps,
-                    "GBps": e["bytes"] / (e["ms"] * 1e-3) / 1e9 if e["ms"] else None}
+        kernels = kernel_table(entries, args.steps)
         dom = max(range(len(entries)), key=lambda k: entries[k]["ms"])
         e = entries[dom]
         ach = e["bytes"] / (e["ms"] * 1e-3) / 1e9
-        roofline = {"kernel": KIND_NAMES.get(dom), "bound": "hbm", "achieved": round(ach, 1),
+        name = KIND_NAMES.get(dom)
+        roofline = {"kernel": name, "bound": "hbm", "achieved": round(ach, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                    "traffic": recorded_traffic(KIND_NAMES.get(dom)) if args.config == "c2" and not args.autotune
-                    else None,
+                    "traffic": recorded_traffic(name, args.config) if not args.autotune else None,
                     "algorithmic_bytes_per_launch": e["bytes"] / e["launches"],
-                    "avg_launch_ms": e["ms"] / e["launches"]}
+                    "avg_launch_ms": e["ms"] / e["launches"],
+                    "launches_per_step": e["launches"] / args.steps,
+                    "bytes_note": "byte model: each (role, direction) CSR once per sweep, the members' "
+                                  "listed output words; T rows are not counted"}
         log(f"[bench] kernels: {json.dumps(kernels)}")
 
-    plain = None
+    elapsed = lambda: time.perf_counter() - t_start  # noqa: E731
+    extra = {}
+    # the other plan path, same batch: counts must agree
+    if args.other_steps:
+        other_step(other)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.other_steps):
+            other_step(other)
+        torch.cuda.synchronize()
+        odt = time.perf_counter() - t0
+        ogot = other.cpu().numpy().view(np.uint32)
+        extra["host_plans" if not args.host_plans else "device_plans"] = {
+            "value": round(H * args.other_steps / odt, 1), "unit": "hypotheses/s",
+            "ms_per_step": round(odt / args.other_steps * 1e3, 3), "equal": bool((ogot == got).all())}
+        log(f"[bench] other path: {extra}")
+
+    # one device plan launched eagerly, then captured in a HIP graph and replayed
+    if args.graph:
+        plan = device_plan()
+        try:
+            gc = torch.empty((H, 2), dtype=torch.int32, device="cuda")
+            hthedl.hth_dplan_launch(plan, eng.ws, eng.ws_bytes, gc, stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.graph):
+                hthedl.hth_dplan_launch(plan, eng.ws, eng.ws_bytes, gc, stream)
+            torch.cuda.synchronize()
+            eager = (time.perf_counter() - t0) / args.graph
+            g = torch.cuda.CUDAGraph()
+            side = torch.cuda.Stream()
+            side.wait_stream(stream)
+            with torch.cuda.stream(side):
+                g.capture_begin()
+                hthedl.hth_dplan_launch(plan, eng.ws, eng.ws_bytes, gc, side)
+                g.capture_end()
+            stream.wait_stream(side)
+            torch.cuda.synchronize()
+            ok = True
+            t_rep = 0.0
+            for _ in range(args.graph):
+                gc.fill_(-1)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                g.replay()
+                torch.cuda.synchronize()
+                t_rep += time.perf_counter() - t0
+                ok &= bool((gc.cpu().numpy().view(np.uint32) == got).all())
+            extra["graph"] = {"replays": args.graph, "replay_ms": round(t_rep / args.graph * 1e3, 3),
+                              "eager_launch_ms": round(eager * 1e3, 3),
+                              "replay_hyp_per_s": round(H / (t_rep / args.graph), 1),
+                              "every_replay_equal": ok,
+                              "note": "the same device plan launched eagerly and replayed from one capture; "
+                                      "plan generation (count pass, readback) is outside both"}
+            del g
+        finally:
+            hthedl.hth_dplan_destroy(plan)
+        log(f"[bench] graph: {extra['graph']}")
+
     if args.plain:
         P = min(args.plain, H)
         pc = torch.empty((P, 2), dtype=torch.int32, device="cuda")
-        sub = hyps[:P]
-        enc = [hthedl.encode_one(h) for h in sub]
+        enc = [hthedl.encode_one(h) for h in hyps[:P]]
+        eng.reserve(max(e[0].shape[0] for e in enc), 1)
         for i in range(min(8, P)):
             hthedl.hth_eval_one(eng.handle, enc[i][0], enc[i][1], eng.ws, eng.ws_bytes, None, pc[i], stream)
         torch.cuda.synchronize()
@@ -313,72 +466,84 @@ def main():
         torch.cuda.synchronize()
         pdt = time.perf_counter() - t0
         pgot = pc.cpu().numpy().view(np.uint32)
-        plain = {"value": round(P / pdt, 1), "unit": "hypotheses/s", "hyps": P,
-                 "equal_to_batched": bool((pgot == got[:P]).all())}
-        log(f"[bench] plain: {P / pdt:,.0f} hyp/s")
+        pm = sum(bytes_model.plain_model(h, shape) for h in hyps[:P])
+        extra["plain"] = {"value": round(P / pdt, 1), "unit": "hypotheses/s", "hyps": P,
+                          "equal_to_batched": bool((pgot == got[:P]).all()),
+                          "model_frac": round(pm / pdt / 1e9 / HBM_PEAK_GBS, 4)}
+        log(f"[bench] plain: {extra['plain']}")
 
-    dplans = None
-    if args.device_plans:
-        # the batch's node arrays already in device memory; a step generates
-        # the plan there (count pass + summary readback, emit pass) and runs it
-        d_nodes, d_offs, d_ch = eng.upload_batch(encoded=(nodes, offs, ch))
-        n_nodes = int(nodes.shape[0])
-        dc = torch.empty((H, 2), dtype=torch.int32, device="cuda")
+    cpu, parity = None, None
+    if args.cpu_budget > 0:
+        cpu, parity = cpu_baseline(kb, hyps, got, args.cpu_budget, args.cpu_runs)
+        log(f"[bench] oracle/cpp: {cpu}; parity {parity}")
 
-        eng.ensure_plan_scratch(n_nodes)
-        dchunk = args.device_chunk or H
-
-        def dstep():
-            for a in range(0, H, dchunk):
-                b = min(H, a + dchunk)
-                plan, nb = hthedl.hth_dplan_create(eng.handle, d_nodes, n_nodes, d_offs[a:], b - a, d_ch,
-                                                   int(d_ch.shape[0]), eng.dp_scratch, eng.dp_scratch_bytes, stream)
-                eng.ensure_workspace(nb)
-                hthedl.hth_dplan_launch(plan, eng.ws, eng.ws_bytes, dc[a:b], stream)
-                hthedl.hth_dplan_destroy(plan)
-
-        dstep()
-        torch.cuda.synchronize()
-        hthedl.hth_profile_begin(eng.handle)
-        t0 = time.perf_counter()
-        for _ in range(args.device_plans):
-            dstep()
-        torch.cuda.synchronize()
-        ddt = time.perf_counter() - t0
-        dent = hthedl.hth_profile_end(eng.handle)
-        dgot = dc.cpu().numpy().view(np.uint32)
-        dplans = {"value": round(H * args.device_plans / ddt, 1), "unit": "hypotheses/s", "hyps_per_plan": dchunk,
-                  "ms_per_step": round(ddt / args.device_plans * 1e3, 3),
-                  "equal_to_batched": bool((dgot == got).all()),
-                  "kernels_ms_per_step": {KIND_NAMES.get(k, str(k)): round(e["ms"] / args.device_plans, 3)
-                                          for k, e in enumerate(dent) if e["launches"]}}
-        log(f"[bench] device plans: {dplans}")
-
-    cpu = None
-    parity = None
-    if args.cpu_sample:
-        want, cdt = cpu_baseline(kb, hyps, args.cpu_sample, args.cpu_budget)
-        n = want.shape[0]
-        parity = {"checked": n, "equal": int((got[:n] == want).all(axis=1).sum())}
-        cpu = {"value": round(n / cdt, 3), "unit": "hypotheses/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {n} of the {H} {args.config} hypotheses, numpy set-based oracle, "
-                         f"one thread, KB in RAM, {cdt:.1f}s"}
-        log(f"[bench] oracle: {n / cdt:.2f} hyp/s; parity {parity}")
+    if args.c5 and args.config == "c3" and elapsed() < args.time_budget:
+        from paper_2412_00802_amd import screened
+        t = time.perf_counter()
+        c5 = screened.run(kb, eng, pairs=args.c5_pairs, modes=("logdelta",), sweep=(), name="c3")
+        scr = c5["screener"]["logdelta"]
+        extra["c5"] = {"screened_hyp_per_s": scr["screened_hyp_per_s"],
+                       "exhaustive_hyp_per_s": c5["exhaustive_hyp_per_s"], "speedup": scr["speedup"],
+                       "recall_at_100": scr["recall_at_100"], "exact_budget": scr["exact_budget"],
+                       "candidates": c5["candidates"], "stages_s": scr["stages_synchronised"],
+                       "screened_seconds": scr["screened_seconds"], "exhaustive_seconds": c5["exhaustive_seconds"],
+                       "train_seconds": scr["train_seconds"], "training_pairs": c5["training_pairs"],
+                       "random_recall_at_100": c5["random_recall_at_100"],
+                       "leg_seconds": round(time.perf_counter() - t, 1)}
+        log(f"[bench] c5: {extra['c5']}")
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "hypotheses/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": describe(args.config, cfg, kb), "n_hyps": H,
                    "n_individuals": cfg.n_individuals, "n_assertions": kb.n_edges,
-                   "mode": "batched",
+                   "mode": "batched, plans generated on the device" if not args.host_plans else
+                           "batched, plans compiled on the host",
                    "schedule": schedule or hthedl.hth_kb_get_tuning(eng.handle)},
-        "roofline": roofline, "cpu_baseline": cpu, "plain": plain, "device_plans": dplans,
-        "parity_sample": parity,
-        "kernels": kernels,
+        "roofline": roofline, "step_roofline": step_roofline, "cpu_baseline": cpu,
+        "parity_sample": parity, "kernels": kernels,
     }
+    out.update(extra)
+
+    if args.c4_rounds and elapsed() < args.time_budget:
+        del eng, d_nodes, d_offs, d_ch, counts, other
+        kb = None
+        torch.cuda.empty_cache()
+        out["c4"] = c4_leg(args.c4_rounds, log)
     print(json.dumps(out), flush=True)
+
+
+def c4_leg(rounds: int, log) -> dict:
+    """A few rounds of the c4 refinement trace (32M individuals, 16,384
+    candidates per round, added conjuncts drawn on the device): device and
+    end-to-end hypotheses/s per round."""
+    from paper_2412_00802_amd import hthedl, synth, trace
+    t = time.perf_counter()
+    cfg = synth.CONFIGS["c4"]
+    kb = synth.make_kb(cfg)
+    gen_s = time.perf_counter() - t
+    t = time.perf_counter()
+    eng = hthedl.Engine(kb, max_nodes=64, max_hyps=1)
+    up_s = time.perf_counter() - t
+    cache = trace.SetCache(eng, 4096)
+    rng = np.random.default_rng(synth.BASE_SEED + 40)
+    recs = []
+    for rec, _, _ in trace.run_trace_device(cfg, kb, eng, rounds, 16384, 256, 16384, cache, rng,
+                                            synth.BASE_SEED + 41):
+        log(f"[bench] c4 round {rec['round']}: {rec}")
+        recs.append(rec)
+    cache.close()
+    later = recs[1:] or recs
+    dev = sum(r["device_ms"] + r["set_fill_ms"] for r in later) / 1e3
+    e2e = sum(r["end_to_end_s"] for r in later)
+    n = sum(r["candidates"] for r in later)
+    return {"workload": f"c4: {kb.n:,} individuals, {kb.n_edges:,} assertions, {kb.n_data} properties; "
+                        f"{rounds} trace rounds x 16,384 candidates, beam 256, added conjuncts drawn on the device",
+            "device_hyp_per_s": round(n / dev, 1), "end_to_end_hyp_per_s": round(n / e2e, 1),
+            "rounds_counted": len(later), "kb_generate_s": round(gen_s, 1), "kb_upload_s": round(up_s, 1),
+            "rounds": recs}
 
 
 if __name__ == "__main__":

@@ -51,8 +51,11 @@ enum {
   HTH_E_UNSUPPORTED = -7  /* valid request outside this build's limits */
 };
 
-/* DL constructs (Section 3.2).  The paper's string restrictions (EQUAL,
- * CONTAIN) and multi-valued numeric roles are not part of this library. */
+/* DL constructs (Section 3.2): the boolean constructs, the object-role
+ * restrictions, single-valued data thresholds, and the concrete-role
+ * restrictions over multi-valued numeric roles (MIN, MAX, EXACT) and string
+ * roles (EQUAL, CONTAIN) of Section 3.2.3.  The inverse-role CSR is always
+ * derived by the library (hth_kb_create); a caller cannot hand one in. */
 enum {
   HTH_TOP = 0,      /* every individual */
   HTH_BOT = 1,      /* no individual */
@@ -303,7 +306,7 @@ hth_status hth_plan_destroy(hth_plan plan);
 
 /* Plans generated on the device.  The paper generates each hypothesis's
  * evaluation plan on CPU threads and leaves generation on the GPU, with little
- * or no CPU involvement, as future work (Sections 4 and 7).  Here the batch is
+ * or no CPU involvement, as future work (Sections 4 and 8).  Here the batch is
  * already in DEVICE memory, in the layout hth_eval_batch takes on the host:
  * d_nodes [n_nodes], d_hyp_node_offsets [n_hyps + 1] (hypothesis h is
  * d_nodes[offsets[h] .. offsets[h+1]), local child indices; offsets need not
@@ -362,7 +365,7 @@ hth_status hth_dplan_stats(hth_dplan plan, hth_dplan_info* out);
  * that adds a conjunct, candidate = P and X, for parents P whose instance sets
  * are rows of the registered set table (hth_kb_set_sets).  With
  * hth_dplan_create this keeps a refinement round's candidates and plans on the
- * device (the paper's Section 7 future work; the paper defines no refinement
+ * device (the paper's Section 8 future work; the paper defines no refinement
  * operator, the conjunct family is this library's).  16 bytes per spec. */
 enum {
   HTH_CJ_ATOM = 0,     /* X = atomic concept a */

@@ -2,7 +2,7 @@
 //
 // The paper builds an evaluation plan per hypothesis on CPU threads and names
 // plan generation on the GPU, with little or no CPU involvement, as future
-// work (Sections 4 and 7).  Here the hypotheses of a batch are already in
+// work (Sections 4 and 8).  Here the hypotheses of a batch are already in
 // device memory (hth_node arrays, as hth_eval_batch takes them on the host),
 // and two passes of one thread per hypothesis build the plan there:
 //   k_dp_count  validates every node, computes each node's role-nesting level,
@@ -1136,7 +1136,7 @@ extern "C" hth_status hth_dplan_launch(hth_dplan plan, void* ws, size_t ws_bytes
   if (s) return s;
   if (p.n_thg) {
     const uint32_t n = p.n_thg, bpt = std::max<uint32_t>(1, (kb.W + 127) / 128);
-    const double bytes = n * 4.0 * kb.N + S.n_thr * 8.0 * kb.W;
+    const double bytes = n * 4.0 * kb.N;   // the columns (model bytes; rows are an intermediate)
     s = split_launch(Lc, HTH_K_THRESHOLD, bytes, n, bpt, 256, [&](uint32_t i0, uint32_t, uint32_t blocks) {
       hipLaunchKernelGGL(k_threshold, dim3(blocks), dim3(256), 0, st, d, p.d_thg + i0, T.thr, bpt);
     });
@@ -1144,6 +1144,7 @@ extern "C" hth_status hth_dplan_launch(hth_dplan plan, void* ws, size_t ws_bytes
   }
   void* tarea = w + p.o_tarea;
   for (uint32_t L = 0; L < S.levels; ++L) {
+    Lc.csr_seen.clear();
     s = launch_regions_n(Lc, d, T.mat + p.B.mat[L], T.code, S.mat[L], (int)S.mat_depth, 0.0);
     if (s) return s;
     if (p.fills[L]) {

@@ -758,6 +758,11 @@ DevKB dev_view(const hth_kb_s& kb) {
 struct Launcher {
   hth_kb_s& kb;
   hipStream_t st;
+  // the (role, direction) CSRs already counted in this sweep (one role-nesting
+  // level): the byte model reads each once per sweep however many passes use it
+  std::vector<uint32_t> csr_seen;
+
+  double csr_once(uint32_t role, uint32_t inv);
 
   hth_status event(hipEvent_t* e) {
     if (!kb.event_pool.empty()) {
@@ -804,21 +809,28 @@ hth_status split_launch(Launcher& L, int kind, double bytes, uint64_t items, uin
   return HTH_OK;
 }
 
-// algorithmic bytes of a region task: every distinct row it reads once, its
-// output row once, the two example rows when it counts coverage
-double region_bytes(const hth_kb_s& kb, const RegionTask& t, const std::vector<uint32_t>& code) {
+// algorithmic bytes of the region tasks of one sweep (byte model): every
+// distinct row they read once, each output row once, the two example rows
+// once and 8 bytes of counts per hypothesis whose coverage they take
+double region_bytes(const hth_kb_s& kb, const std::vector<RegionTask>& tasks, const std::vector<uint32_t>& code) {
   const double w8 = (double)kb.W * 8;
   std::vector<uint32_t> leaves;
-  for (uint32_t i = 0; i < t.code_len; ++i) {
-    const uint32_t ins = code[t.code_off + i];
-    if ((ins & 15u) == RP_LEAF) leaves.push_back(ins >> 5);
+  double b = 0;
+  bool cover = false;
+  for (const RegionTask& t : tasks) {
+    for (uint32_t i = 0; i < t.code_len; ++i) {
+      const uint32_t ins = code[t.code_off + i];
+      if ((ins & 15u) == RP_LEAF) leaves.push_back(ins >> 5);
+    }
+    if (t.out_row != kNone) b += w8;
+    if (t.cover != kNone) {
+      b += 8;
+      cover = true;
+    }
   }
   std::sort(leaves.begin(), leaves.end());
   leaves.erase(std::unique(leaves.begin(), leaves.end()), leaves.end());
-  double b = leaves.size() * w8;
-  if (t.out_row != kNone) b += w8;
-  if (t.cover != kNone) b += 2 * w8 + 8;
-  return b;
+  return b + leaves.size() * w8 + (cover ? 2 * w8 : 0.0);
 }
 
 // a CSR direction scanned once: 32-bit row offsets and the role's targets
@@ -826,6 +838,13 @@ double csr_bytes(const hth_kb_s& kb, uint32_t role, uint32_t inv) {
   const double words = kb.n_words.empty() ? kb.W : kb.n_words[2 * role + inv];
   return 4.0 * std::min<double>((double)kb.N + 1, 65.0 * words) +
          4.0 * (double)(kb.role_base[role + 1] - kb.role_base[role]);
+}
+
+double Launcher::csr_once(uint32_t role, uint32_t inv) {
+  const uint32_t key = 2 * role + inv;
+  if (std::find(csr_seen.begin(), csr_seen.end(), key) != csr_seen.end()) return 0.0;
+  csr_seen.push_back(key);
+  return csr_bytes(kb, role, inv);
 }
 
 // n region tasks whose programs need at most `depth` stack entries
@@ -854,9 +873,7 @@ hth_status launch_regions_n(Launcher& L, const DevKB& d, const RegionTask* tasks
 
 hth_status launch_regions(Launcher& L, const DevKB& d, const RegionTask* tasks, const uint32_t* code,
                           const std::vector<RegionTask>& host, const std::vector<uint32_t>& hcode) {
-  double bytes = 0;
-  if (L.kb.prof)
-    for (const RegionTask& t : host) bytes += region_bytes(L.kb, t, hcode);
+  const double bytes = L.kb.prof ? region_bytes(L.kb, host, hcode) : 0.0;
   int depth = 0;
   for (const RegionTask& t : host) {
     int sp = 0;
@@ -892,8 +909,10 @@ hth_status launch_roles_n(Launcher& L, const DevKB& d, const RoleTask* tasks, ui
 
 hth_status launch_roles(Launcher& L, const DevKB& d, const RoleTask* tasks,
                         const std::vector<RoleTask>& host) {
+  // per node: its CSR once per sweep, its child row in, its listed words out
   double bytes = 0;
-  for (const RoleTask& t : host) bytes += csr_bytes(L.kb, t.role, t.inv) + 2.0 * L.kb.W * 8;
+  for (const RoleTask& t : host)
+    bytes += L.csr_once(t.role, t.inv) + 8.0 * L.kb.W + 8.0 * L.kb.n_words[2 * t.role + t.inv];
   return launch_roles_n(L, d, tasks, (uint32_t)host.size(), bytes);
 }
 
@@ -904,12 +923,14 @@ hth_status launch_group_chunk(Launcher& L, const DevKB& d, const GroupTask* grou
   const hth_kb_s& kb = L.kb;
   const size_t g0 = c.first;
   const uint32_t n = c.n;
+  // byte model: the transpose reads the members' child rows (T is an
+  // intermediate of this design, not counted); the pass reads its CSR once per
+  // sweep and writes the members' listed words (the other words are filled)
   double tb = 0, gb = 0;
   for (uint32_t i = 0; i < n; ++i) {
     const GroupTask& G = host[g0 + i];
-    const double tbytes = (double)t_rows(kb, G) * sizeof(TW);
-    tb += (double)G.k * kb.W * 8 + tbytes;     // child rows in, T out
-    gb += csr_bytes(kb, G.role, G.inv) + tbytes + (double)G.k * kb.W * 8;
+    tb += (double)G.k * kb.W * 8;
+    gb += L.csr_once(G.role, G.inv) + (double)G.k * G.n_words * 8;
   }
   TW* T = static_cast<TW*>(tarea);
   const uint32_t tiles = (kb.W + 255) / 256;
@@ -1072,7 +1093,7 @@ std::once_flag g_attr_once;
 struct Prepared {
   Plan P;
   Blob blob;
-  struct LevelAt { size_t mat, role, group, fill, nrole, ngroup, nfill, nhb, nhc, push, npush; };
+  struct LevelAt { size_t mat, role, group, fill, nrole, ngroup, nfill, nhb, nhc, push, npush; double fill_bytes; };
   std::vector<LevelAt> at;
   size_t root_at = 0;
   std::vector<std::vector<RoleTask>> lv_roles;
@@ -1110,13 +1131,14 @@ void prepare(const hth_kb_s& kb, Plan&& plan, uint32_t n_hyps, Prepared& X) {
   X.lv_chunks.assign(NL, {});
   for (size_t L = 0; L < NL; ++L) {
     const PlanLevel& PL = P.levels[L];
-    X.at[L] = {regions.size(), roles.size(), groups.size(), fills.size(), 0, 0, 0, 0, 0, pushes.size(), 0};
+    X.at[L] = {regions.size(), roles.size(), groups.size(), fills.size(), 0, 0, 0, 0, 0, pushes.size(), 0, 0.0};
     regions.insert(regions.end(), PL.mat.begin(), PL.mat.end());
     for (RoleTask t : PL.roles) {
       const uint32_t rd = 2 * t.role + t.inv;
       t.n_words = kb.n_words[rd];
       if (pushed(kb, t)) {
         fills.push_back(FillTask{t.out_row, t.lo == 0 ? 1u : 0u});
+        X.at[L].fill_bytes += 8.0 * kb.W;
         pushes.push_back(t);
         X.lv_push[L].push_back(t);
         continue;
@@ -1127,15 +1149,20 @@ void prepare(const hth_kb_s& kb, Plan&& plan, uint32_t n_hyps, Prepared& X) {
       t.c_first = (uint32_t)X.at[L].nhc;
       X.at[L].nhb += kb.chunk_first[rd + 1] - kb.chunk_first[rd];
       X.at[L].nhc += kb.heavy_first[rd + 1] - kb.heavy_first[rd];
-      if (t.n_words < kb.W) fills.push_back(FillTask{t.out_row, t.lo == 0 ? 1u : 0u});
+      if (t.n_words < kb.W) {
+        fills.push_back(FillTask{t.out_row, t.lo == 0 ? 1u : 0u});
+        X.at[L].fill_bytes += 8.0 * (kb.W - t.n_words);
+      }
       roles.push_back(t);
       X.lv_roles[L].push_back(t);
     }
     const uint32_t mbase = (uint32_t)members.size();
     for (GroupTask g : level_groups(kb, PL)) {
-      if (g.n_words < kb.W)
+      if (g.n_words < kb.W) {
         for (uint32_t j = 0; j < g.k; ++j)
           fills.push_back(FillTask{PL.members[g.first + j].out_row, (uint32_t)((g.acc[0] >> j) & 1)});
+        X.at[L].fill_bytes += 8.0 * g.k * (kb.W - g.n_words);
+      }
       g.first += mbase;
       X.lv_groups[L].push_back(g);
     }
@@ -1316,7 +1343,10 @@ hth_status launch_prepared(hth_kb_s& kb, const Prepared& X, char* ws, uint32_t* 
     // about 32 words per wave: enough independent column loads in flight
     const uint32_t n = (uint32_t)X.n_thr_groups;
     const uint32_t bpt = std::max<uint32_t>(1, (kb.W + 127) / 128);
-    const double bytes = n * 4.0 * kb.N + X.n_thr_tasks * 8.0 * kb.W;
+    std::vector<uint32_t> props;
+    for (const ThrTask& t : P.thr) props.push_back(t.prop);
+    std::sort(props.begin(), props.end());
+    const double bytes = 4.0 * kb.N * (double)(std::unique(props.begin(), props.end()) - props.begin());
     hth_status s = split_launch(Lc, HTH_K_THRESHOLD, bytes, n, bpt, 256, [&](uint32_t i0, uint32_t, uint32_t blocks) {
       hipLaunchKernelGGL(k_threshold, dim3(blocks), dim3(256), 0, st, d, thg + i0, thr, bpt);
     });
@@ -1325,11 +1355,12 @@ hth_status launch_prepared(hth_kb_s& kb, const Prepared& X, char* ws, uint32_t* 
   for (size_t L = 0; L < P.levels.size(); ++L) {
     const PlanLevel& PL = P.levels[L];
     const Prepared::LevelAt& at = X.at[L];
+    Lc.csr_seen.clear();
     hth_status s = launch_regions(Lc, d, reg + at.mat, code, PL.mat, P.code);
     if (s) return s;
     if (at.nfill) {
       const uint32_t n = (uint32_t)at.nfill, tiles = (kb.S + 255) / 256;
-      s = split_launch(Lc, HTH_K_FILL, (double)n * kb.W * 8, n, tiles, 256, [&](uint32_t i0, uint32_t, uint32_t blocks) {
+      s = split_launch(Lc, HTH_K_FILL, at.fill_bytes, n, tiles, 256, [&](uint32_t i0, uint32_t, uint32_t blocks) {
         hipLaunchKernelGGL(k_fill_rows, dim3(blocks), dim3(256), 0, st, d, fil + at.fill + i0, tiles);
       });
       if (s) return s;

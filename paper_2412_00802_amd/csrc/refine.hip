@@ -1,7 +1,7 @@
 // Refinement candidates written on the device (hth_draw_conjuncts, hth_conjoin).
 //
 // The paper leaves generating evaluation plans on the GPU as future work
-// (Section 7); this file covers the step before the plan, for the one-step
+// (Section 8, Conclusion and future work); this file covers the step before the plan, for the one-step
 // specialisation that adds a conjunct: candidate = P ⊓ X, where P is a parent
 // whose instance set is a row of the caller's set table and X is an atomic
 // concept, an existential ∃r.A / ∃r⁻.A over an atomic concept, or a threshold

@@ -100,6 +100,179 @@ def score(scr: Screener, fb: FeatureBatch, n: int, n_pos: int, n_neg: int, out, 
                               base=None if base is None else base[r0:r0 + m], kind=kind)
 
 
+def run(kb, eng, pairs: int = 200_000, candidates_beam: int = 4096, refinements: int = 256, epochs: int = 20,
+        top: float = 0.02, audit: float = 0.005, k: int = 100, lr: float = 5e-4, per_round: int = 16384,
+        chunk: int = 65536, modes=("logdelta", "delta", "relative", "absolute"), sweep=(0.02, 0.05, 0.1),
+        name: str = "c3") -> dict:
+    """The screened search on one resident KB: training pairs from the exact
+    engine, screeners trained on the GPU, candidates, the exhaustive exact
+    evaluation (the judge) and each screener's pipeline.  Returns the record."""
+    import torch
+    rng = np.random.default_rng(synth.BASE_SEED + 50)
+
+    # 1. training pairs from the engine
+    t = time.perf_counter()
+    hyps, counts, pcounts, tparents, tpidx = gather_training_pairs(eng, kb, pairs, per_round, 256, rng, chunk)
+    t_pairs = time.perf_counter() - t
+    order = rng.permutation(len(hyps))
+    hyps = [hyps[i] for i in order]
+    counts, pcounts, tpidx = counts[order], pcounts[order], tpidx[order]
+    n_val = len(hyps) // 10
+    n_tr = len(hyps) - n_val
+    fb = FeatureBatch(*hthedl.encode_batch(hyps))
+    tpfb = FeatureBatch(*hthedl.encode_batch(tparents))
+    tpi = torch.from_numpy(tpidx.astype(np.int32)).cuda()
+
+    # 2. training: "logdelta" predicts log(1 + removed positives / negatives)
+    # from features relative to the parent, with the squared error; "delta"
+    # the shares of the parent's coverage a refinement keeps, from the same
+    # features; "relative" those shares from the candidate's own features;
+    # "absolute" the covered fractions of the examples
+    models = {}
+    for mode in modes:
+        if mode == "logdelta":
+            y = torch.from_numpy(removal_targets(counts, pcounts)).cuda()
+        else:
+            y = torch.from_numpy(coverage_targets(counts, eng.n_pos, eng.n_neg,
+                                                  None if mode == "absolute" else pcounts)).cuda()
+        scr = Screener(init_params(seed=11), batch=8192, lr=lr, loss="mse" if mode == "logdelta" else "bce")
+        t = time.perf_counter()
+        losses = train(scr, fb, y, n_tr, epochs, 1024, rng,
+                       *((tpfb, tpi) if mode in ("delta", "logdelta") else (None, None)))
+        models[mode] = (scr, losses, time.perf_counter() - t)
+
+    # 3. candidates: the best `candidates_beam` evaluated so far, each refined
+    best = search.top_indices(counts, eng.n_pos, candidates_beam)
+    parents = [hyps[i] for i in best]
+    ref = search.Refiner(kb, rng)
+    cands, parent_of = [], []
+    seen = set()
+    t = time.perf_counter()
+    for pi, p in enumerate(parents):
+        for c in ref.refine(p, refinements):
+            if c not in seen:
+                seen.add(c)
+                cands.append(c)
+                parent_of.append(pi)
+    t_cands = time.perf_counter() - t
+    parent_of = np.asarray(parent_of)
+    n = len(cands)
+    log(f"[screen] {n:,} candidates from {len(parents)} parents ({t_cands:.1f}s)")
+    cenc = hthedl.encode_batch(cands, child_offsets=True)
+    cfb = FeatureBatch(*cenc[:3])
+    cbase = torch.from_numpy(counts[best][parent_of].astype(np.uint32).view(np.int32)).cuda()
+    cpfb = FeatureBatch(*hthedl.encode_batch(parents))
+    cpi = torch.from_numpy(parent_of.astype(np.int32)).cuda()
+    n_sel = int(round(top * n))
+    n_aud = int(round(audit * n))
+    aud = rng.choice(n, size=n_aud, replace=False)           # drawn on the host: an input
+    scores = torch.empty(n, dtype=torch.float32, device="cuda")
+    sel = torch.empty(n_sel, dtype=torch.int32, device="cuda")
+    work = torch.empty(65538, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+
+    # 4. exhaustive exact evaluation of every candidate (the judge)
+    t0 = time.perf_counter()
+    allc = torch.empty((n, 2), dtype=torch.int32, device="cuda")
+    eng.eval_batch(None, counts=allc, chunk=chunk, encoded=cenc[:3])
+    all_np = allc.cpu().numpy().view(np.uint32)
+    exact_top = search.top_indices(all_np, eng.n_pos, k)
+    torch.cuda.synchronize()
+    t_exh = time.perf_counter() - t0
+    f_np = search.f1_float(all_np, eng.n_pos)
+
+    def screened(scr, mode, m_sel, sel_t, stages=None):
+        """features + scores + top-k + exact evaluation of the selection; with
+        `stages` (a dict) each stage is synchronised and timed on its own."""
+        mark = time.perf_counter()
+
+        def stage(key):
+            nonlocal mark
+            if stages is not None:
+                torch.cuda.synchronize()
+                now = time.perf_counter()
+                stages[key] = round(now - mark, 5)
+                mark = now
+
+        rel = mode in ("delta", "logdelta")
+        cfb.recompute()
+        if rel:
+            cpfb.recompute()
+        stage("features_s")
+        score(scr, cfb, n, eng.n_pos, eng.n_neg, scores, base=None if mode == "absolute" else cbase,
+              parents=cpfb if rel else None, parent_index=cpi if rel else None,
+              kind=1 if mode == "logdelta" else 0)
+        stage("mlp_s")
+        hthedl.hth_topk(scores, n, m_sel, sel_t, work)
+        chosen = np.union1d(sel_t.cpu().numpy().astype(np.int64), aud)
+        stage("topk_s")
+        sub = hthedl.gather_encoded(cenc, chosen)
+        sc = torch.empty((chosen.size, 2), dtype=torch.int32, device="cuda")
+        eng.eval_batch(None, counts=sc, chunk=chunk, encoded=sub)
+        sc_np = sc.cpu().numpy().view(np.uint32)
+        got = chosen[search.top_indices(sc_np, eng.n_pos, k)]
+        stage("exact_s")
+        return chosen, sc_np, got
+
+    # 5. screened: features + scores + top-k + exact evaluation of the selection
+    res = {}
+    for mode, (scr, losses, t_train) in models.items():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        chosen, sc_np, screened_top = screened(scr, mode, n_sel, sel)
+        torch.cuda.synchronize()
+        t_screen = time.perf_counter() - t0
+        assert np.array_equal(all_np[chosen], sc_np), "screened and exhaustive exact counts differ"
+        stages = {}
+        screened(scr, mode, n_sel, sel, stages)          # the same pipeline again, stage by stage
+        s_np = scores.cpu().numpy()
+        rank_corr = float(np.corrcoef(np.argsort(np.argsort(s_np)), np.argsort(np.argsort(f_np)))[0, 1])
+        res[mode] = {"screened_hyp_per_s": round(n / t_screen, 1), "speedup": round(t_exh / t_screen, 3),
+                     f"recall_at_{k}": search.recall_at(screened_top, exact_top),
+                     "score_rank_correlation": round(rank_corr, 4), "exact_budget": int(chosen.size),
+                     "screened_seconds": round(t_screen, 4), "stages_synchronised": stages,
+                     "train_seconds": round(t_train, 2),
+                     "train_loss_first_last": [round(losses[0], 5), round(losses[-1], 5)]}
+        log(f"[screen] {mode}: recall@{k} {res[mode][f'recall_at_{k}']:.2f}, "
+            f"{res[mode]['speedup']}x the exhaustive rate; stages {stages}")
+    # recall and speed of the logdelta screener at other exact budgets
+    budget_sweep = []
+    if "logdelta" in models:
+        scr_d = models["logdelta"][0]
+        for frac in sweep:
+            m_sel = int(round(frac * n))
+            sel_m = torch.empty(m_sel, dtype=torch.int32, device="cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            chosen, _, got = screened(scr_d, "logdelta", m_sel, sel_m)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            budget_sweep.append({"top_fraction": frac, "exact_budget": int(chosen.size),
+                                 f"recall_at_{k}": search.recall_at(got, exact_top),
+                                 "speedup": round(t_exh / dt, 3)})
+            log(f"[screen] logdelta at top {frac}: recall {budget_sweep[-1][f'recall_at_{k}']:.2f}, "
+                f"{budget_sweep[-1]['speedup']}x")
+    # ties at the k-th exact F1 make part of the exact top-k a matter of the index tie-break
+    kth = np.sort(f_np)[::-1][k - 1] if n >= k else 0.0
+    ties = int(np.sum(np.isclose(f_np, kth, rtol=0, atol=1e-12)))
+    first = next(iter(res.values()))
+    budget = first["exact_budget"]
+    rand = rng.choice(n, size=budget, replace=False)
+    rand_top = rand[search.top_indices(all_np[rand], eng.n_pos, k)]
+    pf1 = search.f1_float(counts[best], eng.n_pos)[parent_of]
+    heur = np.argsort(-pf1, kind="stable")[:budget]
+    heur_top = heur[search.top_indices(all_np[heur], eng.n_pos, k)]
+    return {
+        "workload": f"screened search on the {name} KB ({kb.n:,} individuals)",
+        "candidates": n, "top_fraction": top, "audit_fraction": audit,
+        "exhaustive_hyp_per_s": round(n / t_exh, 1), "exhaustive_seconds": round(t_exh, 4),
+        "screener": res, "logdelta_budget_sweep": budget_sweep, "candidates_tied_at_kth_f1": ties,
+        f"random_recall_at_{k}": search.recall_at(rand_top, exact_top),
+        f"parent_f1_recall_at_{k}": search.recall_at(heur_top, exact_top),
+        "training_pairs": len(hyps), "pairs_seconds": round(t_pairs, 2), "candidates_seconds": round(t_cands, 2),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--small", action="store_true", help="a reduced run of the same pipeline")
@@ -111,13 +284,13 @@ def main():
     ap.add_argument("--audit", type=float, default=0.005)
     ap.add_argument("--k", type=int, default=100)
     ap.add_argument("--lr", type=float, default=5e-4)
+    ap.add_argument("--modes", default="logdelta,delta,relative,absolute")
     ap.add_argument("--sweep", default="0.02,0.05,0.1",
                     help="top fractions at which the delta screener's recall and speed are also reported")
     args = ap.parse_args()
-    import torch
 
     cfg = synth.CONFIGS["c3"]
-    per_round, chunk = 16384, 65536
+    per_round = 16384
     if args.small:
         cfg = synth.small_config(n=200_000, n_concepts=256, depth=5, n_roles=12, s=1.6, cap=1024,
                                  n_data=8, missing=0.1, n_pos=10_000, n_neg=10_000, seed_index=3,
@@ -129,158 +302,9 @@ def main():
     kb = synth.make_kb(cfg)
     log(f"[screen] KB {cfg.name}: N={kb.n:,}, {kb.n_edges:,} assertions ({time.perf_counter() - t:.1f}s)")
     eng = hthedl.Engine(kb, max_nodes=64, max_hyps=1)
-    rng = np.random.default_rng(synth.BASE_SEED + 50)
-
-    # 1. training pairs from the engine
-    t = time.perf_counter()
-    hyps, counts, pcounts, tparents, tpidx = gather_training_pairs(eng, kb, args.pairs, per_round, 256, rng, chunk)
-    t_pairs = time.perf_counter() - t
-    order = rng.permutation(len(hyps))
-    hyps = [hyps[i] for i in order]
-    counts, pcounts, tpidx = counts[order], pcounts[order], tpidx[order]
-    n_val = len(hyps) // 10
-    n_tr = len(hyps) - n_val
-    fb = FeatureBatch(*hthedl.encode_batch(hyps))
-    tpfb = FeatureBatch(*hthedl.encode_batch(tparents))
-    tpi = torch.from_numpy(tpidx.astype(np.int32)).cuda()
-
-    # 2. training: "relative" predicts the shares of the parent's coverage a
-    # refinement keeps (the parent was evaluated exactly); "absolute" the
-    # covered fractions of the examples
-    # "delta": shares of the parent's coverage from features relative to the
-    # parent; "logdelta": log(1 + removed positives / negatives) from the same
-    # features, with the squared error
-    models = {}
-    for mode in ("logdelta", "delta", "relative", "absolute"):
-        if mode == "logdelta":
-            y = torch.from_numpy(removal_targets(counts, pcounts)).cuda()
-        else:
-            y = torch.from_numpy(coverage_targets(counts, eng.n_pos, eng.n_neg,
-                                                  None if mode == "absolute" else pcounts)).cuda()
-        scr = Screener(init_params(seed=11), batch=8192, lr=args.lr, loss="mse" if mode == "logdelta" else "bce")
-        t = time.perf_counter()
-        losses = train(scr, fb, y, n_tr, args.epochs, 1024, rng,
-                       *((tpfb, tpi) if mode in ("delta", "logdelta") else (None, None)))
-        models[mode] = (scr, losses, time.perf_counter() - t)
-
-    # 3. candidates: the best `beam` evaluated so far, each refined
-    top = search.top_indices(counts, eng.n_pos, args.candidates_beam)
-    parents = [hyps[i] for i in top]
-    ref = search.Refiner(kb, rng)
-    cands, parent_of = [], []
-    seen = set()
-    for pi, p in enumerate(parents):
-        for c in ref.refine(p, args.refinements):
-            if c not in seen:
-                seen.add(c)
-                cands.append(c)
-                parent_of.append(pi)
-    parent_of = np.asarray(parent_of)
-    n = len(cands)
-    log(f"[screen] {n:,} candidates from {len(parents)} parents")
-    cenc = hthedl.encode_batch(cands, child_offsets=True)
-    cfb = FeatureBatch(*cenc[:3])
-    cbase = torch.from_numpy(counts[top][parent_of].astype(np.uint32).view(np.int32)).cuda()
-    cpfb = FeatureBatch(*hthedl.encode_batch(parents))
-    cpi = torch.from_numpy(parent_of.astype(np.int32)).cuda()
-    n_sel = int(round(args.top * n))
-    n_aud = int(round(args.audit * n))
-    audit = rng.choice(n, size=n_aud, replace=False)           # drawn on the host: an input
-    scores = torch.empty(n, dtype=torch.float32, device="cuda")
-    sel = torch.empty(n_sel, dtype=torch.int32, device="cuda")
-    work = torch.empty(65538, dtype=torch.int32, device="cuda")
-    torch.cuda.synchronize()
-
-    # 4. exhaustive exact evaluation of every candidate (the judge)
-    t0 = time.perf_counter()
-    allc = torch.empty((n, 2), dtype=torch.int32, device="cuda")
-    eng.eval_batch(None, counts=allc, chunk=chunk, encoded=cenc[:3])
-    all_np = allc.cpu().numpy().view(np.uint32)
-    exact_top = search.top_indices(all_np, eng.n_pos, args.k)
-    torch.cuda.synchronize()
-    t_exh = time.perf_counter() - t0
-    f_np = search.f1_float(all_np, eng.n_pos)
-
-    # 5. screened: features + scores + top-k + exact evaluation of the selection
-    res = {}
-    for mode, (scr, losses, t_train) in models.items():
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        cfb.recompute()
-        rel = mode in ("delta", "logdelta")
-        if rel:
-            cpfb.recompute()
-        score(scr, cfb, n, eng.n_pos, eng.n_neg, scores, base=None if mode == "absolute" else cbase,
-              parents=cpfb if rel else None, parent_index=cpi if rel else None,
-              kind=1 if mode == "logdelta" else 0)
-        hthedl.hth_topk(scores, n, n_sel, sel, work)
-        chosen = np.union1d(sel.cpu().numpy().astype(np.int64), audit)
-        sub = hthedl.gather_encoded(cenc, chosen)
-        sc = torch.empty((chosen.size, 2), dtype=torch.int32, device="cuda")
-        eng.eval_batch(None, counts=sc, chunk=chunk, encoded=sub)
-        sc_np = sc.cpu().numpy().view(np.uint32)
-        screened_top = chosen[search.top_indices(sc_np, eng.n_pos, args.k)]
-        torch.cuda.synchronize()
-        t_screen = time.perf_counter() - t0
-        assert np.array_equal(all_np[chosen], sc_np), "screened and exhaustive exact counts differ"
-        s_np = scores.cpu().numpy()
-        rank_corr = float(np.corrcoef(np.argsort(np.argsort(s_np)), np.argsort(np.argsort(f_np)))[0, 1])
-        res[mode] = {"screened_hyp_per_s": round(n / t_screen, 1), "speedup": round(t_exh / t_screen, 3),
-                     f"recall_at_{args.k}": search.recall_at(screened_top, exact_top),
-                     "score_rank_correlation": round(rank_corr, 4), "exact_budget": int(chosen.size),
-                     "screened_seconds": round(t_screen, 4), "train_seconds": round(t_train, 2),
-                     "train_loss_first_last": [round(losses[0], 5), round(losses[-1], 5)]}
-        log(f"[screen] {mode}: recall@{args.k} {res[mode][f'recall_at_{args.k}']:.2f}, "
-            f"{res[mode]['speedup']}x the exhaustive rate")
-    # recall and speed of the logdelta screener at other exact budgets (its scores
-    # are computed again: the timing covers the whole screened pipeline)
-    sweep = []
-    scr_d = models["logdelta"][0]
-    for frac in [float(v) for v in args.sweep.split(",") if v]:
-        m_sel = int(round(frac * n))
-        sel_m = torch.empty(m_sel, dtype=torch.int32, device="cuda")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        cfb.recompute()
-        cpfb.recompute()
-        score(scr_d, cfb, n, eng.n_pos, eng.n_neg, scores, base=cbase, parents=cpfb, parent_index=cpi, kind=1)
-        hthedl.hth_topk(scores, n, m_sel, sel_m, work)
-        chosen = np.union1d(sel_m.cpu().numpy().astype(np.int64), audit)
-        sc = torch.empty((chosen.size, 2), dtype=torch.int32, device="cuda")
-        eng.eval_batch(None, counts=sc, chunk=chunk, encoded=hthedl.gather_encoded(cenc, chosen))
-        sc_np = sc.cpu().numpy().view(np.uint32)
-        got = chosen[search.top_indices(sc_np, eng.n_pos, args.k)]
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        sweep.append({"top_fraction": frac, "exact_budget": int(chosen.size),
-                      f"recall_at_{args.k}": search.recall_at(got, exact_top), "speedup": round(t_exh / dt, 3)})
-        log(f"[screen] logdelta at top {frac}: recall {sweep[-1][f'recall_at_{args.k}']:.2f}, "
-            f"{sweep[-1]['speedup']}x")
-    # where the exact top-k sit in the logdelta screener's order (percentiles)
-    order = np.argsort(-scores.cpu().numpy(), kind="stable")
-    pos_in = np.empty(n, dtype=np.int64)
-    pos_in[order] = np.arange(n)
-    pct = np.sort(pos_in[exact_top] / n * 100.0)
-    log(f"[screen] exact top-{args.k} at screener percentiles: median {np.median(pct):.3f}, "
-        f"worst {', '.join(f'{v:.2f}' for v in pct[-8:])}")
-    # ties at the k-th exact F1 make part of the exact top-k a matter of the index tie-break
-    kth = np.sort(f_np)[::-1][args.k - 1] if n >= args.k else 0.0
-    ties = int(np.sum(np.isclose(f_np, kth, rtol=0, atol=1e-12)))
-    budget = res["logdelta"]["exact_budget"]
-    rand = rng.choice(n, size=budget, replace=False)
-    rand_top = rand[search.top_indices(all_np[rand], eng.n_pos, args.k)]
-    pf1 = search.f1_float(counts[top], eng.n_pos)[parent_of]
-    heur = np.argsort(-pf1, kind="stable")[:budget]
-    heur_top = heur[search.top_indices(all_np[heur], eng.n_pos, args.k)]
-    out = {
-        "workload": f"screened search on the {cfg.name} KB ({kb.n:,} individuals)",
-        "candidates": n, "top_fraction": args.top, "audit_fraction": args.audit,
-        "exhaustive_hyp_per_s": round(n / t_exh, 1), "exhaustive_seconds": round(t_exh, 4),
-        "screener": res, "logdelta_budget_sweep": sweep, f"candidates_tied_at_kth_f1": ties,
-        f"random_recall_at_{args.k}": search.recall_at(rand_top, exact_top),
-        f"parent_f1_recall_at_{args.k}": search.recall_at(heur_top, exact_top),
-        "training_pairs": len(hyps), "pairs_seconds": round(t_pairs, 2),
-    }
+    out = run(kb, eng, args.pairs, args.candidates_beam, args.refinements, args.epochs, args.top, args.audit,
+              args.k, args.lr, per_round, modes=[m for m in args.modes.split(",") if m],
+              sweep=[float(v) for v in args.sweep.split(",") if v], name=cfg.name)
     print(json.dumps(out), flush=True)
 
 

@@ -16,13 +16,14 @@ def test_more_than_one_gpu_is_refused():
     assert r.stdout.strip() == ""
 
 
-def test_recorded_traffic_is_void_when_the_kernel_changed(tmp_path):
+def test_recorded_traffic_is_void_when_the_kernel_changed(tmp_path, monkeypatch):
     sys.path.insert(0, ROOT)
     import bench
-    f = tmp_path / "traffic.json"
+    monkeypatch.setattr(bench, "TRAFFIC_DIR", str(tmp_path))
+    f = tmp_path / "traffic_cX.json"
     f.write_text(json.dumps({"source_sha": bench.source_sha(),
                              "kernels": {"k_group": {"hbm_bytes_per_launch": 123.0}}}))
-    assert bench.recorded_traffic("k_group", str(f)) == 123.0
+    assert bench.recorded_traffic("k_group", "cX") == 123.0
     f.write_text(json.dumps({"source_sha": "0" * 16, "kernels": {"k_group": {"hbm_bytes_per_launch": 123.0}}}))
-    assert bench.recorded_traffic("k_group", str(f)) is None
-    assert bench.recorded_traffic("k_group", str(tmp_path / "missing.json")) is None
+    assert bench.recorded_traffic("k_group", "cX") is None
+    assert bench.recorded_traffic("k_group", "missing") is None

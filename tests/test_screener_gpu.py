@@ -192,7 +192,38 @@ def test_topk(torch, n, k):
     np.testing.assert_array_equal(np.sort(key[got]), np.sort(key)[n - k:])
 
 
+def _gemm_bound(a, b, k):
+    """Element-wise bound of an fp32-accumulated product a @ b against its exact
+    value: 8 * 2^-24 * sqrt(K) * (|a| @ |b|) (rounding of each partial sum,
+    random-walk growth over the reduction length K)."""
+    return 8 * 2.0 ** -24 * np.sqrt(k) * (np.abs(a) @ np.abs(b))
+
+
+def _close(name, got, want, bound, rtol=1e-3):
+    """|got - want| <= rtol |want| + bound, element by element."""
+    err = np.abs(got - want)
+    lim = rtol * np.abs(want) + bound
+    bad = np.argwhere(err > lim)
+    say(f"[train] {name}: max |err| {err.max():.3e}, worst err/limit {np.max(err / np.maximum(lim, 1e-300)):.3f}")
+    assert bad.size == 0, (name, bad[:4].tolist(), got[tuple(bad[0])], want[tuple(bad[0])])
+
+
+def _half_ulp(name, got_bf16, pre):
+    """A stored bf16 value is the exact value rounded to nearest: within half a
+    bf16 unit in the last place (2^-8 relative) of the exact fp64 value, plus
+    the fp32 accumulation bound carried in `pre[1]`."""
+    exact, bound = pre
+    _close(name, got_bf16, exact, bound + 1e-30, rtol=2.0 ** -8)
+
+
 def test_training_step_matches_reference(torch):
+    """One training step, element by element.  Each stored tensor of the step
+    (h1, h2, z, dz, dh2, dh1) and each gradient is compared with the float64
+    product of the operands the GPU itself stored for that step, so both sides
+    see identical bf16 roundings: gradients within rel 1e-3 plus the fp32
+    accumulation bound of their reduction length, bf16 activations within half
+    a bf16 ulp of the exact value.  The whole step is then also compared with
+    the independent float64 reference (relative norm, a summary)."""
     from paper_2412_00802_amd.screener import Screener, init_params
     rng = np.random.default_rng(11)
     B = 256
@@ -206,14 +237,35 @@ def test_training_step_matches_reference(torch):
     Y = torch.from_numpy(y).cuda()
     scr.train_step(B, Y)
     torch.cuda.synchronize()
+    scale = 1.0 / (2 * B)
+    d = lambda t: t.detach().float().cpu().numpy().astype(np.float64)   # noqa: E731
+    xg, h1, h2, z, dz, dh2, dh1 = (d(t) for t in (scr.x, scr.h1, scr.h2, scr.z, scr.dz, scr.dh2, scr.dh1))
+    g = {k: d(v) for k, v in scr.g.items()}
+    w1b, w2b = S.bf16(params["w1"]), S.bf16(params["w2"])
+    w3, b1, b2, b3 = (params[k].astype(np.float64) for k in ("w3", "b1", "b2", "b3"))
+    np.testing.assert_array_equal(xg, x)                       # small integers: exact in bf16
+    # forward, each layer from the GPU's own stored input
+    _half_ulp("h1", h1, (np.maximum(xg @ w1b + b1, 0.0), _gemm_bound(xg, w1b, 4096)))
+    _half_ulp("h2", h2, (np.maximum(h1 @ w2b + b2, 0.0), _gemm_bound(h1, w2b, 1024)))
+    _close("z", z, h2 @ w3 + b3, _gemm_bound(h2, w3, 256), rtol=1e-5)
+    _close("dz", dz, (1.0 / (1.0 + np.exp(-z)) - y) * scale, 1e-9, rtol=1e-5)
+    # backward
+    _close("g.w3", g["w3"], h2.T @ dz, _gemm_bound(h2.T, dz, B))
+    _close("g.b3", g["b3"], dz.sum(0), _gemm_bound(np.ones((1, B)), dz, B)[0])
+    _half_ulp("dh2", dh2, ((dz @ w3.T) * (h2 > 0), _gemm_bound(dz, w3.T, 2)))
+    _close("g.w2", g["w2"], h1.T @ dh2, _gemm_bound(h1.T, dh2, B))
+    _close("g.b2", g["b2"], dh2.sum(0), _gemm_bound(np.ones((1, B)), dh2, B)[0])
+    _half_ulp("dh1", dh1, ((dh2 @ w2b.T) * (h1 > 0), _gemm_bound(dh2, w2b.T, 256)))
+    _close("g.w1", g["w1"], xg.T @ dh1, _gemm_bound(xg.T, dh1, B))
+    _close("g.b1", g["b1"], dh1.sum(0), _gemm_bound(np.ones((1, B)), dh1, B)[0])
+    # summary against the independent float64 reference of the whole step
     p64 = {k: v.astype(np.float64) for k, v in params.items()}
     acts, loss = S.forward(p64, x.astype(np.float64), y.astype(np.float64), rounding=True)
-    g = S.backward(p64, acts, y.astype(np.float64), 1.0 / (2 * B), rounding=True)
+    gr = S.backward(p64, acts, y.astype(np.float64), scale, rounding=True)
     assert abs(scr.loss.item() - loss) <= 2e-3 * abs(loss)
     for k in ("w3", "b3", "w2", "b2", "w1", "b1"):
-        got, want = scr.g[k].cpu().numpy().astype(np.float64), g[k]
-        rel = np.linalg.norm(got - want) / max(np.linalg.norm(want), 1e-30)
-        say(f"[train] grad {k}: relative error {rel:.2e}")
+        rel = np.linalg.norm(g[k] - gr[k]) / max(np.linalg.norm(gr[k]), 1e-30)
+        say(f"[train] grad {k}: relative error against the whole-step reference {rel:.2e}")
         assert rel < 2e-2, (k, rel)
 
 
