@@ -262,6 +262,27 @@ hth_status hth_eval_one(hth_kb kb, const hth_node* nodes, uint32_t n_nodes,
                         void* ws, size_t ws_bytes, uint64_t* d_instances, uint32_t* d_counts,
                         void* stream);
 
+/* hth_eval_one for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * workspace is a fixed array of HTH_NOALLOC_SCRATCH_BYTES in the library's
+ * device data, one per GPU, held until the process ends; its address is looked
+ * up once per device on the first call there.  The call allocates nothing:
+ * the caller passes only the inputs and outputs, as for hth_eval_one.
+ * Results are those of hth_eval_one (the same plan and kernels).
+ * - HTH_E_NOMEM, before any launch, when the hypothesis's plan needs more than
+ *   HTH_NOALLOC_SCRATCH_BYTES (about (role nodes + materialised fillers + 2)
+ *   bit rows of 8 * stride_words bytes, plus a few KB of tables); use
+ *   hth_eval_one with a workspace then.
+ * - Every call on one GPU shares that GPU's array: calls that overlap on the
+ *   device (several streams, or several host threads) race and are not
+ *   supported.  Calls in order on one stream are fine.  No scratch content
+ *   needs to start at zero; each call writes what it reads.
+ * - The node arrays are copied from the host on `stream` during the call. */
+#define HTH_NOALLOC_SCRATCH_BYTES (64u << 20)
+hth_status hth_eval_one_noalloc(hth_kb kb, const hth_node* nodes, uint32_t n_nodes,
+                                const uint32_t* children, uint32_t n_children,
+                                uint64_t* d_instances, uint32_t* d_counts, void* stream);
+
 /* Exact workspace hth_eval_batch needs for this batch (the batch is compiled on
  * the host; nothing is launched).  Same arguments as hth_eval_batch. */
 hth_status hth_batch_workspace_bytes(hth_kb kb, const hth_node* nodes, const uint32_t* hyp_node_offsets,

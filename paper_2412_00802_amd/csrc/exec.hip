@@ -1441,6 +1441,68 @@ extern "C" hth_status hth_eval_one(hth_kb kb, const hth_node* nodes, uint32_t n_
                   static_cast<hipStream_t>(stream));
 }
 
+// The workspace of hth_eval_one_noalloc: a fixed array in the code object's
+// device data, one copy per GPU, held until the process ends.  Host code
+// never passes the array's name to a kernel or a copy (on the host it is only
+// a stand-in); it uses the device address hipGetSymbolAddress gives for the
+// GPU the call runs on.
+namespace hth {
+namespace {
+__device__ __align__(256) uint64_t scratch[HTH_NOALLOC_SCRATCH_BYTES / 8];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};
+
+// The scratch array's address on `device`, looked up once per device with
+// that device current (the caller's current device is restored).
+hth_status scratch_on(int device, char** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(HTH_E_UNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch[device]) {
+    int cur = 0;
+    HTH_HIP(hipGetDevice(&cur));
+    if (cur != device) HTH_HIP(hipSetDevice(device));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) HTH_HIP(hipSetDevice(cur));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p || reinterpret_cast<uintptr_t>(p) % 256) return fail(HTH_E_DEVICE, "scratch address not 256-byte aligned");
+    g_scratch[device] = static_cast<char*>(p);
+  }
+  *out = g_scratch[device];
+  return HTH_OK;
+}
+}  // namespace
+}  // namespace hth
+
+extern "C" hth_status hth_eval_one_noalloc(hth_kb kb, const hth_node* nodes, uint32_t n_nodes,
+                                           const uint32_t* children, uint32_t n_children,
+                                           uint64_t* d_instances, uint32_t* d_counts, void* stream) {
+  if (!kb || !nodes || !d_counts) return fail(HTH_E_INVALID, "NULL argument");
+  if (n_children && !children) return fail(HTH_E_INVALID, "children is NULL");
+  uint32_t offs[2] = {0, n_nodes};
+  PlanOptions opt;
+  opt.instances = d_instances != nullptr;
+  Plan P;
+  hth_status s = compile_plan(*kb, nodes, offs, 1, children, n_children, opt, P);
+  if (s) return s;
+  char* ws = nullptr;
+  s = scratch_on(kb->device, &ws);
+  if (s) return s;
+  std::lock_guard<std::mutex> g(kb->mu);
+  Prepared X;
+  prepare(*kb, std::move(P), 1, X);
+  if (X.need > (size_t)HTH_NOALLOC_SCRATCH_BYTES)
+    return fail(HTH_E_NOMEM, "hth_eval_one_noalloc: this hypothesis needs " + std::to_string(X.need) +
+                                 " bytes of workspace; the fixed scratch holds " +
+                                 std::to_string((size_t)HTH_NOALLOC_SCRATCH_BYTES) +
+                                 " (use hth_eval_one with a caller workspace)");
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  HTH_HIP(hipMemcpyAsync(ws, X.blob.bytes.data(), X.blob.bytes.size(), hipMemcpyHostToDevice, st));
+  return launch_prepared(*kb, X, ws, d_counts, d_instances, st);
+}
+
 namespace {
 hth_status eval_batch_impl(hth_kb kb, const hth_node* nodes, const uint32_t* hyp_node_offsets,
                            uint32_t n_hyps, const uint32_t* children, uint32_t n_children, void* ws,

@@ -46,7 +46,7 @@ EXPORTED = ["hth_kb_derived_bytes", "hth_kb_create", "hth_kb_set_examples", "hth
             "hth_plan_upload", "hth_plan_launch", "hth_plan_destroy", "hth_numeric_derived_bytes",
             "hth_kb_set_numeric", "hth_string_derived_bytes", "hth_kb_set_strings", "hth_kb_set_patterns",
             "hth_dplan_scratch_bytes", "hth_dplan_create", "hth_dplan_launch", "hth_dplan_destroy",
-            "hth_draw_conjuncts", "hth_conjoin", "hth_dplan_stats"]
+            "hth_draw_conjuncts", "hth_conjoin", "hth_dplan_stats", "hth_eval_one_noalloc"]
 
 
 class HthError(RuntimeError):
@@ -108,6 +108,7 @@ def lib() -> ctypes.CDLL:
             "hth_kb_set_tuning": [P, ctypes.POINTER(Tuning)],
             "hth_workspace_bytes": [P, U32, U32, ctypes.POINTER(S)],
             "hth_eval_one": [P, P, U32, P, U32, P, S, P, P, P],
+            "hth_eval_one_noalloc": [P, P, U32, P, U32, P, P, P],
             "hth_eval_batch": [P, P, P, U32, P, U32, P, S, P, P],
             "hth_eval_batch_sets": [P, P, P, U32, P, U32, P, S, P, P, P],
             "hth_kb_set_sets": [P, P, U32],
@@ -294,6 +295,19 @@ def hth_eval_one(kb, nodes: np.ndarray, children: np.ndarray, ws, ws_bytes: int,
     _check(lib().hth_eval_one(kb, _np_ptr(nodes), nodes.shape[0], _np_ptr(children),
                               children.shape[0], _ptr(ws), ws_bytes, _ptr(d_instances),
                               _ptr(d_counts), _stream(stream)))
+
+
+# bytes of the fixed device scratch behind hth_eval_one_noalloc (HTH_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def hth_eval_one_noalloc(kb, nodes: np.ndarray, children: np.ndarray, d_instances, d_counts,
+                         stream=None) -> None:
+    nodes = np.ascontiguousarray(nodes, dtype=NODE_DTYPE)
+    children = np.ascontiguousarray(children, dtype=np.uint32)
+    _check(lib().hth_eval_one_noalloc(kb, _np_ptr(nodes), nodes.shape[0], _np_ptr(children),
+                                      children.shape[0], _ptr(d_instances), _ptr(d_counts),
+                                      _stream(stream)))
 
 
 def hth_eval_batch(kb, nodes: np.ndarray, offsets: np.ndarray, children: np.ndarray, ws,

@@ -100,3 +100,11 @@ def test_batch_encoding_offsets():
     nodes, offs, ch = hthedl.encode_batch(hs)
     assert offs[0] == 0 and offs[-1] == len(nodes) and len(offs) == 21
     assert [offs[i + 1] - offs[i] for i in range(20)] == [synth.hyp_size(h) for h in hs]
+
+
+def test_noalloc_scratch_size_matches_header():
+    """The binding's scratch size is the header's HTH_NOALLOC_SCRATCH_BYTES."""
+    text = open(os.path.join(ROOT, "include", "hthedl.h")).read()
+    m = re.search(r"#define\s+HTH_NOALLOC_SCRATCH_BYTES\s+\((\d+)u\s*<<\s*(\d+)\)", text)
+    assert m, "HTH_NOALLOC_SCRATCH_BYTES not found"
+    assert int(m.group(1)) << int(m.group(2)) == hthedl.NOALLOC_SCRATCH_BYTES
