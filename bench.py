@@ -22,10 +22,15 @@ sys.path.insert(0, ROOT)
 METRIC = "exact hypotheses/sec + achieved HBM GB/s; screened vs plain exhaustive"
 HBM_PEAK_GBS = 8000.0
 KIND_NAMES = {0: "k_threshold", 1: "k_region", 2: "k_role", 3: "k_tbuild", 4: "k_group", 5: "k_fill_rows",
-              6: "k_dp_emit"}
+              6: "k_dp_emit", 7: "k_group_short"}
 # the dominant kernel's source: its counters are void once these change
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2412_00802_amd", "csrc", f)
-                  for f in ("group_kernels.h", "hth_internal.h")]
+                  for f in ("group_kernels.h", "hth_internal.h", "exec.hip")]
+# the kernels that write every role node's row (or add a root's coverage) and
+# read each (role, direction) CSR: the roofline's kernel family, against the
+# byte model's role-pass bytes
+ROLE_PASS_KINDS = (2, 4, 5, 7)          # k_role (+ heavy rows), k_group, k_fill_rows, k_group_short
+ROLE_PASS_KERNELS = ("k_role", "k_role_heavy", "k_role_heavy_fix", "k_group", "k_group_short", "k_fill_rows")
 TRAFFIC_DIR = os.path.join(ROOT, "profiles")          # traffic_<workload>.json: the counters of a workload
 COPY_BYTES = 256 << 20      # elementwise pass used to calibrate the byte counters
 
@@ -42,18 +47,23 @@ def traffic_file(workload: str) -> str:
     return os.path.join(TRAFFIC_DIR, f"traffic_{workload}.json")
 
 
-def recorded_traffic(kernel: str, workload: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary of
-    `workload`, or None when the kernel source changed since the counters
-    were taken."""
+def recorded_traffic(kernels, workload: str):
+    """HBM bytes per step of the kernels named in `kernels` (summed over their
+    launches) from the committed counter summary of `workload`, or None when
+    the kernel sources changed since the counters were taken."""
     try:
         rec = json.load(open(traffic_file(workload)))
     except (OSError, ValueError):
         return None
     if rec.get("source_sha") != source_sha():
         return None
-    k = rec.get("kernels", {}).get(kernel)
-    return None if k is None else k["hbm_bytes_per_launch"]
+    steps = rec.get("steps", 3)
+    tot = 0.0
+    for k in kernels:
+        e = rec.get("kernels", {}).get(k)
+        if e is not None:
+            tot += e["hbm_bytes_per_launch"] * e["launches"] / steps
+    return tot
 
 
 def kernel_name(name: str) -> str:
@@ -97,7 +107,7 @@ def summarize(kt_dir: str, fetch_dir: str, write_dir: str, command: str, out_md:
              "Counter passes (one counter per run):", "",
              "    " + command.format(opts="--pmc FETCH_SIZE --output-format csv"),
              "    " + command.format(opts="--pmc WRITE_SIZE --output-format csv"), "",
-             f"Kernel source sha256[:16] of csrc/group_kernels.h + csrc/hth_internal.h: {sha}", "",
+             f"Kernel source sha256[:16] of csrc/group_kernels.h + csrc/hth_internal.h + csrc/exec.hip: {sha}", "",
              "## Kernel time (kernel trace)", "",
              "| kernel | calls | avg us | total % |", "|---|---|---|---|"]
     for r in sorted(stats, key=lambda r: -float(r["Percentage"]))[:12]:
@@ -108,7 +118,7 @@ def summarize(kt_dir: str, fetch_dir: str, write_dir: str, command: str, out_md:
               f"{fetch[ck][1]:.0f} KiB and writes {write[ck][1]:.0f} KiB per dispatch: "
               f"{f_fac:.3f} fetched bytes and {w_fac:.3f} written bytes per counted KiB-byte.", "",
               "| kernel | fetch KiB | write KiB | HBM bytes per launch (scaled) |", "|---|---|---|---|"]
-    out = {"source_sha": sha, "fetch_factor": f_fac, "write_factor": w_fac, "kernels": {}}
+    out = {"source_sha": sha, "fetch_factor": f_fac, "write_factor": w_fac, "steps": 3, "kernels": {}}
     agg = {}
     for k in sorted(fetch, key=lambda k: -fetch[k][1]):
         if k not in write:
@@ -138,8 +148,10 @@ def summarize(kt_dir: str, fetch_dir: str, write_dir: str, command: str, out_md:
     json.dump(out, open(traffic_file(workload), "w"), indent=1)
 
 
-def summarize_trace(kt_dir: str, command: str, out_md: str, title: str) -> None:
-    """Kernel-time table of one rocprofv3 --kernel-trace --stats run."""
+def summarize_trace(kt_dir: str, command: str, out_md: str, title: str, by_grid: str = None) -> None:
+    """Kernel-time table of one rocprofv3 --kernel-trace --stats run; with
+    by_grid, also the dispatches of the kernels whose names hold that text,
+    grouped by grid (workgroups in x and y)."""
     import csv
     import glob
     stats = []
@@ -152,6 +164,19 @@ def summarize_trace(kt_dir: str, command: str, out_md: str, title: str) -> None:
         lines.append(f"| {kernel_name(r['Name'])} | {r['Calls']} | "
                      f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['TotalDurationNs']) / 1e6:.1f} | "
                      f"{float(r['Percentage']):.1f} |")
+    if by_grid:
+        groups = {}
+        for f in glob.glob(os.path.join(kt_dir, "*kernel_trace.csv")):
+            for r in csv.DictReader(open(f)):
+                if by_grid not in r["Kernel_Name"]:
+                    continue
+                key = (kernel_name(r["Kernel_Name"]), int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"]),
+                       int(r["Grid_Size_Y"]))
+                groups.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        lines += ["", f"Dispatches of `{by_grid}` by grid (workgroups in x, y; one 128 x 128 output tile each):", "",
+                  "| kernel | grid x, y | calls | avg us | total ms |", "|---|---|---|---|---|"]
+        for (name, gx, gy), v in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
+            lines.append(f"| {name} | {gx}, {gy} | {len(v)} | {sum(v) / len(v):.1f} | {sum(v) / 1e3:.2f} |")
     open(out_md, "w").write("\n".join(lines) + "\n")
 
 
@@ -256,10 +281,15 @@ def main():
     ap.add_argument("--graph", type=int, default=10, metavar="REPLAYS",
                     help="replays of the step's plan launch captured in a HIP graph (0: skip)")
     ap.add_argument("--plain", type=int, default=256, help="hypotheses timed one at a time (0 = skip)")
+    ap.add_argument("--cache-rows", type=int, default=32768,
+                    help="rows of the cross-batch subexpression cache leg: the batch in four chunks, "
+                         "with and without the cache (0: skip)")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of the CPU-baseline runs (0: skip)")
     ap.add_argument("--cpu-runs", type=int, default=5)
     ap.add_argument("--c5", type=int, default=1, help="screened-search leg on the c3 KB (c3 only)")
     ap.add_argument("--c5-pairs", type=int, default=200_000)
+    ap.add_argument("--c5-mode", default="logdelta", help="the screener of the c5 leg (see screened.py)")
+    ap.add_argument("--c5-draws", type=int, default=3, help="candidate sets of the c5 leg")
     ap.add_argument("--c4-rounds", type=int, default=3, help="refinement-trace rounds at c4 (0: skip)")
     ap.add_argument("--time-budget", type=float, default=420.0,
                     help="seconds after which the optional legs are skipped")
@@ -274,12 +304,14 @@ def main():
     ap.add_argument("--summarize-trace", default=None, metavar="KT_DIR",
                     help="write only the kernel-time table of a kernel-trace run")
     ap.add_argument("--summary-title", default="")
+    ap.add_argument("--summary-by-grid", default=None, help="group these kernels' dispatches by grid")
     ap.add_argument("--summary-command", default="rocprofv3 {opts} -d OUT -o run -- python3 bench.py "
                     "--steps 2 --warmup 1 --plain 0 --cpu-budget 0 --c5 0 --c4-rounds 0 --graph 0 "
                     "--other-steps 0 --no-profile --calibrate-copy")
     args = ap.parse_args()
     if args.summarize_trace:
-        summarize_trace(args.summarize_trace, args.summary_command, args.summary_out, args.summary_title)
+        summarize_trace(args.summarize_trace, args.summary_command, args.summary_out, args.summary_title,
+                        args.summary_by_grid)
         return
     if args.summarize:
         summarize(*args.summarize, args.summary_command, args.summary_out, args.summary_sha,
@@ -379,18 +411,23 @@ def main():
     roofline, kernels = None, {}
     if entries is not None:
         kernels = kernel_table(entries, args.steps)
-        dom = max(range(len(entries)), key=lambda k: entries[k]["ms"])
-        e = entries[dom]
-        ach = e["bytes"] / (e["ms"] * 1e-3) / 1e9
-        name = KIND_NAMES.get(dom)
-        roofline = {"kernel": name, "bound": "hbm", "achieved": round(ach, 1),
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                    "traffic": recorded_traffic(name, args.config) if not args.autotune else None,
-                    "algorithmic_bytes_per_launch": e["bytes"] / e["launches"],
-                    "avg_launch_ms": e["ms"] / e["launches"],
-                    "launches_per_step": e["launches"] / args.steps,
-                    "bytes_note": "byte model: each (role, direction) CSR once per sweep, the members' "
-                                  "listed output words; T rows are not counted"}
+        # the role passes: every role node's row written once (or a root's
+        # coverage added without one) and each (role, direction) CSR read once
+        # per level sweep -- the byte model's role-pass bytes -- over the
+        # summed event time of the kernels that do it
+        ms = sum(entries[k]["ms"] for k in ROLE_PASS_KINDS) / args.steps
+        launches = sum(entries[k]["launches"] for k in ROLE_PASS_KINDS) / args.steps
+        ach = model["role_pass"] / (ms * 1e-3) / 1e9
+        traffic = recorded_traffic(ROLE_PASS_KERNELS, args.config) if not args.autotune else None
+        roofline = {"kernel": "role passes (" + " + ".join(KIND_NAMES[k] for k in ROLE_PASS_KINDS) + ")",
+                    "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(ach / HBM_PEAK_GBS, 4),
+                    "traffic": traffic, "traffic_unit": "HBM bytes per step (counters, all launches of the family)",
+                    "model_bytes_per_step": model["role_pass"], "ms_per_step": round(ms, 4),
+                    "launches_per_step": launches, "avg_launch_ms": round(ms / max(launches, 1), 4),
+                    "bytes_note": "byte model role-pass bytes: each (role, direction) CSR once per level sweep "
+                                  "+ one row write per role node with a row (a node that is only a hypothesis's "
+                                  "root gets its coverage fused, no row); reads of children are in step_roofline"}
         log(f"[bench] kernels: {json.dumps(kernels)}")
 
     elapsed = lambda: time.perf_counter() - t_start  # noqa: E731
@@ -452,6 +489,9 @@ def main():
             hthedl.hth_dplan_destroy(plan)
         log(f"[bench] graph: {extra['graph']}")
 
+    if args.cache_rows:
+        extra["cache"] = cache_leg(eng, nodes, offs, ch, H, got, args.cache_rows, stream, log)
+
     if args.plain:
         P = min(args.plain, H)
         pc = torch.empty((P, 2), dtype=torch.int32, device="cuda")
@@ -480,15 +520,19 @@ def main():
     if args.c5 and args.config == "c3" and elapsed() < args.time_budget:
         from paper_2412_00802_amd import screened
         t = time.perf_counter()
-        c5 = screened.run(kb, eng, pairs=args.c5_pairs, modes=("logdelta",), sweep=(), name="c3")
-        scr = c5["screener"]["logdelta"]
+        c5 = screened.run(kb, eng, pairs=args.c5_pairs, modes=(args.c5_mode,), sweep=(), name="c3",
+                          draws=args.c5_draws)
+        scr = c5["screener"][args.c5_mode]
         extra["c5"] = {"screened_hyp_per_s": scr["screened_hyp_per_s"],
                        "exhaustive_hyp_per_s": c5["exhaustive_hyp_per_s"], "speedup": scr["speedup"],
                        "recall_at_100": scr["recall_at_100"], "exact_budget": scr["exact_budget"],
                        "candidates": c5["candidates"], "stages_s": scr["stages_synchronised"],
                        "screened_seconds": scr["screened_seconds"], "exhaustive_seconds": c5["exhaustive_seconds"],
                        "train_seconds": scr["train_seconds"], "training_pairs": c5["training_pairs"],
-                       "random_recall_at_100": c5["random_recall_at_100"],
+                       "random_recall_at_100": c5["random_recall_at_100"], "screener": args.c5_mode,
+                       "draws": c5["draws"], "recall_at_100_per_draw": c5["recall_at_100_per_draw"][args.c5_mode],
+                       "recall_at_100_mean": c5["recall_at_100_mean"][args.c5_mode],
+                       "recall_at_100_min": c5["recall_at_100_min"][args.c5_mode],
                        "leg_seconds": round(time.perf_counter() - t, 1)}
         log(f"[bench] c5: {extra['c5']}")
 
@@ -513,6 +557,51 @@ def main():
         torch.cuda.empty_cache()
         out["c4"] = c4_leg(args.c4_rounds, log)
     print(json.dumps(out), flush=True)
+
+
+def cache_leg(eng, nodes, offs, ch, H, got, n_rows, stream, log) -> dict:
+    """The batch in four consecutive chunks (host-compiled plans), first without
+    and then with the cross-batch subexpression cache: later chunks read the
+    role restrictions they share with earlier ones from the cache's rows."""
+    import torch
+    from paper_2412_00802_amd import hthedl
+    q = (H + 3) // 4
+    chunks = [hthedl.slice_encoded((nodes, offs, ch), a, min(H, a + q)) for a in range(0, H, q)]
+    for c in chunks:
+        eng.ensure_workspace(hthedl.hth_batch_workspace_bytes(eng.handle, *c))
+    out = torch.empty((H, 2), dtype=torch.int32, device="cuda")
+
+    def run(cache):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i, c in enumerate(chunks):
+            o = out[i * q:i * q + int(c[1].shape[0]) - 1]
+            if cache is None:
+                hthedl.hth_eval_batch(eng.handle, *c, eng.ws, eng.ws_bytes, o, stream)
+            else:
+                hthedl.hth_eval_batch_cached(eng.handle, cache, *c, eng.ws, eng.ws_bytes, o, stream)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    run(None)
+    t_plain = run(None)
+    rows = torch.empty((n_rows, eng.S), dtype=torch.int64, device="cuda")
+    cache = hthedl.hth_cache_create(eng.handle, rows, n_rows)
+    try:
+        t_cached = run(cache)
+        equal = bool((out.cpu().numpy().view(np.uint32) == got).all())
+        st = hthedl.hth_cache_stats(cache)
+    finally:
+        hthedl.hth_cache_destroy(cache)
+    del rows
+    rec = {"chunks": len(chunks), "rows": n_rows, "row_bytes": eng.S * 8,
+           "ms_without": round(t_plain * 1e3, 3), "ms_with": round(t_cached * 1e3, 3),
+           "hyp_per_s_with": round(H / t_cached, 1), "equal": equal,
+           "hits": st["hits"], "misses": st["misses"], "evictions": st["evictions"],
+           "note": "four chunks of the batch in order, host-compiled plans, each chunk reading the role "
+                   "restrictions earlier chunks left in the cache"}
+    log(f"[bench] cache: {rec}")
+    return rec
 
 
 def c4_leg(rounds: int, log) -> dict:

@@ -230,7 +230,11 @@ hth_status hth_kb_max_degree(hth_kb kb, uint32_t role, uint32_t inv, uint32_t* o
  *   of the individuals is evaluated from the concept's members: each marks
  *   the subjects that reach it, where no row of the other direction holds
  *   more than 64 assertions (0 = always count per subject; at most 100;
- *   default 2). */
+ *   default 2);
+ * short_rows: a shared pass over a role direction whose rows all hold at most
+ *   this many assertions walks each subject's row on one lane (no slicing of
+ *   the words' assertion ranges, no scan across lanes) and stores eight words
+ *   of each member's output at once (0 = never; at most 64; default 12). */
 typedef struct {
   uint32_t group_min;
   uint32_t group_k;
@@ -241,6 +245,7 @@ typedef struct {
   uint32_t t_compact;
   uint32_t t_segment_kb;
   uint32_t push_pct;
+  uint32_t short_rows;
 } hth_tuning;
 hth_status hth_kb_get_tuning(hth_kb kb, hth_tuning* out);
 hth_status hth_kb_set_tuning(hth_kb kb, const hth_tuning* t);   /* HTH_E_RANGE if out of range */
@@ -306,6 +311,43 @@ hth_status hth_eval_batch_sets(hth_kb kb, const hth_node* nodes, const uint32_t*
                                uint32_t n_hyps, const uint32_t* children, uint32_t n_children,
                                void* ws, size_t ws_bytes, uint64_t* d_sets, uint32_t* d_counts,
                                void* stream);
+
+/* A cross-batch cache of role-restriction results (this library's extension of
+ * the per-batch shared subexpressions of Section 4's evaluation plans):
+ * d_rows is caller device memory [n_rows][stride_words] (64-byte aligned),
+ * registered as the kb's set table for as long as the cache lives.  Every
+ * subexpression of a batch evaluated with hth_eval_batch_cached is interned by
+ * its canonical form in one persistent table, so equal subexpressions of
+ * different batches are recognised exactly (no hash is trusted alone).  A
+ * role restriction whose subexpression holds a row is read from that row and
+ * its subtree is not evaluated; one without a row is given the least recently
+ * used row that no subexpression of the current batch reads, and its result is
+ * written there for later batches (when every row is in use by the batch, it
+ * runs in the workspace as in hth_eval_batch).  The table of interned forms is
+ * cleared, with every row, when it passes 2^24 entries.
+ * - hth_cache_create: n_rows 1 .. 2^24 - 1; replaces any registered set table.
+ *   The rows' contents need no initialisation.
+ * - hth_eval_batch_cached: as hth_eval_batch (same workspace bound from
+ *   hth_batch_workspace_bytes); HTH_SET leaves are rejected (HTH_E_UNSUPPORTED),
+ *   and HTH_E_STATE when another set table replaced the cache's.  Batches must
+ *   run in order on one stream (a batch reads rows earlier batches wrote).  On
+ *   an error the batch's admissions are undone.  Calls on one cache are
+ *   serialised.
+ * - hth_cache_stats: counters since creation (hits and misses count the
+ *   batches' distinct live role restrictions).
+ * - hth_cache_destroy: unregisters the rows (the caller then frees them). */
+typedef struct hth_cache_s* hth_cache;
+typedef struct {
+  uint64_t hits, misses, admitted, evictions, batches;
+  uint32_t entries, rows;
+} hth_cache_info;
+hth_status hth_cache_create(hth_kb kb, uint64_t* d_rows, uint32_t n_rows, hth_cache* out);
+hth_status hth_eval_batch_cached(hth_kb kb, hth_cache cache, const hth_node* nodes,
+                                 const uint32_t* hyp_node_offsets, uint32_t n_hyps, const uint32_t* children,
+                                 uint32_t n_children, void* ws, size_t ws_bytes, uint32_t* d_counts,
+                                 void* stream);
+hth_status hth_cache_stats(hth_cache cache, hth_cache_info* out);
+hth_status hth_cache_destroy(hth_cache cache);
 
 /* Compiled batches for repeated evaluation.  hth_plan_create compiles a batch
  * as hth_eval_batch does (same arguments, host arrays) and reports the
@@ -449,6 +491,7 @@ enum {
   HTH_K_GROUP = 4,      /* shared role passes (up to 64 role nodes per CSR scan) */
   HTH_K_FILL = 5,       /* zero-count results of words without assertions */
   HTH_K_PLAN = 6,       /* plan generation on the device (hth_dplan_launch) */
+  HTH_K_GROUP_SHORT = 7, /* shared role passes over directions of short rows (a lane per subject) */
   HTH_K_NUM = 8
 };
 typedef struct {
@@ -489,10 +532,15 @@ hth_status hth_densify(const uint16_t* d_feat, const uint32_t* d_hyp_node_offset
  * of hypothesis row0 + r with feature f) - (subtrees of parent p with feature
  * f), p = d_parent_index[row0 + r] indexing a second feature set
  * (d_parent_feat, d_parent_offsets) of the parents.  What the refinement
- * added is positive, what it replaced negative; unchanged subtrees cancel. */
+ * added is positive, what it replaced negative; unchanged subtrees cancel.
+ * parent_context = 1 also adds the parent's own subtree counts at feature
+ * f XOR 2048 (the other half of the index space), so that the screener sees
+ * what the refinement changed and what it was applied to; 0 leaves them out.
+ * Errors: HTH_E_INVALID (NULL), HTH_E_RANGE (parent_context > 1). */
 hth_status hth_densify_delta(const uint16_t* d_feat, const uint32_t* d_hyp_node_offsets, uint32_t row0,
                              uint32_t n_rows, const uint16_t* d_parent_feat, const uint32_t* d_parent_offsets,
-                             const uint32_t* d_parent_index, uint16_t* d_x, void* stream);
+                             const uint32_t* d_parent_index, uint32_t parent_context, uint16_t* d_x,
+                             void* stream);
 
 /* C[M][N] = op(A) op(B) on the MFMA units (bf16 operands, fp32 accumulation).
  * trans_a = 0: A is [M][lda]; 1: A is given transposed as [K][lda].
@@ -538,6 +586,12 @@ hth_status hth_adamw(float* p, const float* g, float* m, float* v, uint16_t* pbf
 
 /* d[i] = bf16(s[i]) (round to nearest even). */
 hth_status hth_to_bf16(const float* s, uint16_t* d, size_t n, void* stream);
+
+/* dst [cols][rows] = the transpose of the bf16 matrix src [rows][cols] (not in
+ * place): the weights in the [N][K] layout that the forward layers' products
+ * (trans_b = 1) read.  Errors: HTH_E_INVALID (NULL or src == dst),
+ * HTH_E_RANGE (rows or cols not positive). */
+hth_status hth_transpose_bf16(const uint16_t* src, int rows, int cols, uint16_t* dst, void* stream);
 
 /* Indices of the k largest scores (d_idx [k], in no particular order; among
  * equal scores at the threshold, which ones are taken is unspecified; NaN

@@ -102,9 +102,14 @@ def dense_features(hyps) -> np.ndarray:
     return x
 
 
-def delta_features(children, parents, parent_index) -> np.ndarray:
-    """[H][4096] subtree counts of each child minus those of its parent."""
-    return dense_features(children) - dense_features(parents)[np.asarray(parent_index)]
+def delta_features(children, parents, parent_index, context: bool = False) -> np.ndarray:
+    """[H][4096] subtree counts of each child minus those of its parent; with
+    context, plus the parent's own counts at index f XOR 2048."""
+    par = dense_features(parents)[np.asarray(parent_index)]
+    x = dense_features(children) - par
+    if context:
+        x += par[:, np.arange(FEATURE_DIM) ^ (FEATURE_DIM // 2)]
+    return x
 
 
 def bf16(x) -> np.ndarray:

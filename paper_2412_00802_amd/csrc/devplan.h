@@ -93,8 +93,13 @@ struct DpKB {                    // what the passes read of the knowledge base
   uint32_t* rowidx;
   uint32_t* matclaim;
   uint32_t* matrow;
+  // per representative: kDpRead when some node reads it, plus the number of
+  // hypotheses it is the root of (a role node read by nothing else and the
+  // root of one hypothesis adds its coverage in its shared pass, without a row)
+  uint32_t* ruse;
   uint32_t n_nodes;
 };
+constexpr uint32_t kDpRead = 1u << 31;
 
 // The representative of a leaf is an id of its own, never a node index:
 // n_nodes + 0 (top), + 1 (bottom), + 2 + a (atom a), + 2 + C + s (set row s),
@@ -418,6 +423,13 @@ k_dp_count(const hth_node* __restrict__ nodes, const uint32_t* __restrict__ offs
       const bool leaf = x.op == HTH_TOP || x.op == HTH_BOT || x.op == HTH_ATOM || x.op == HTH_SET || dp_column(x.op);
       const uint32_t rep = leaf ? dp_leaf_id(K, x, thr_slot) : dp_canon(K, nodes, kids, b, g, x);
       dp_store(K.canon + g, rep);
+      if (rep == g) {   // its children are read (an equal node's are the same representatives)
+        const uint32_t nc = dp_n_children(x);
+        for (uint32_t j = 0; j < nc; ++j) {
+          const uint32_t cr = dp_child_rep(K, x, kids, b, j);
+          if (cr < K.n_nodes) atomicOr(K.ruse + cr, kDpRead);
+        }
+      }
       if (role_lvl != kNone && rep == g) {
         // a representative role node: its row, its task in its bucket, and the
         // materialisation of its compound filler unless an equal one is claimed
@@ -438,6 +450,8 @@ k_dp_count(const hth_node* __restrict__ nodes, const uint32_t* __restrict__ offs
     }
     if (ok) {   // the root's region, with coverage
       const uint32_t r = b + n - 1, ri = info[r];
+      const uint32_t rr = dp_load(K.canon + r);
+      if (rr < K.n_nodes) atomicAdd(K.ruse + rr, 1u);
       if (((ri >> 8) & 255u) > (uint32_t)kStackDepth) err(n - 1, DP_DEPTH);
       else if (((ri >> 16) & 255u) > kDpNest) err(n - 1, DP_NEST);
       atomicAdd(&s_code, (unsigned long long)len[r]);
@@ -540,6 +554,7 @@ k_dp_emit(const hth_node* __restrict__ nodes, const uint32_t* __restrict__ offs,
   if (h == 0) T.fills[0] = FillTask{K.n_fixed, 0u};
   if (h >= n_hyps) return;
   const uint32_t b = offs[h], n = offs[h + 1] - b;
+  bool root_fused = false;
   for (uint32_t i = 0; i < n; ++i) {
     const hth_node x = nodes[b + i];
     if (dp_column(x.op)) {
@@ -599,11 +614,18 @@ k_dp_emit(const hth_node* __restrict__ nodes, const uint32_t* __restrict__ offs,
       }
       const uint32_t rd = 2 * x.arg + x.inv;
       const uint32_t nw = dp_nwords(K, rd);
-      if (nw < K.W)
-        T.fills[B.fill[lvl] + atomicAdd(&cur->fill[lvl], 1u)] = FillTask{r, lo == 0 ? 1u : 0u};
       const uint32_t q = lvl * (K.n_dir - 1) + rd;
       const DpBucket bu = T.buckets[q];
-      if (bu.first_group != kNone && dp_groupable(x)) {
+      const bool member = bu.first_group != kNone && dp_groupable(x);
+      // the root of this hypothesis only, read by no node: its shared pass adds
+      // its coverage, it gets no row (its fill task writes the zero row, which
+      // holds zeros already) and the hypothesis no root region
+      const bool fused = member && i + 1 == n && K.ruse[b + i] == 1u;
+      root_fused |= fused;
+      if (nw < K.W)
+        T.fills[B.fill[lvl] + atomicAdd(&cur->fill[lvl], 1u)] =
+            fused ? FillTask{K.n_fixed, 0u} : FillTask{r, lo == 0 ? 1u : 0u};
+      if (member) {
         // a member of one of its bucket's shared passes
         const uint32_t j = atomicAdd(T.bcur + q, 1u);
         GroupMember m;
@@ -612,8 +634,9 @@ k_dp_emit(const hth_node* __restrict__ nodes, const uint32_t* __restrict__ offs,
         m.lo = lo;
         m.hi = hi;
         m.sat = hi == kInf ? lo : hi + 1;
-        m.out_row = r;
-        m.pad0 = m.pad1 = 0;
+        m.out_row = fused ? kNone : r;
+        m.cover = fused ? h : kNone;
+        m.pad = 0;
         T.members[bu.member_base + j] = m;
         unsigned long long* acc =
             reinterpret_cast<unsigned long long*>(T.groups[bu.first_group + j / bu.k].acc);
@@ -640,6 +663,10 @@ k_dp_emit(const hth_node* __restrict__ nodes, const uint32_t* __restrict__ offs,
       t.hr0 = K.dir[2 * K.n_dir + rd];
       T.roles[B.role[lvl] + atomicAdd(&cur->role[lvl], 1u)] = t;
     }
+  }
+  if (root_fused) {
+    T.roots[h] = RegionTask{0u, 0u, kNone, kNone};
+    return;
   }
   const unsigned long long off = atomicAdd(&cur->code, (unsigned long long)len[b + n - 1]);
   dp_program(K, nodes, kids, info, row, b, n - 1, T.code + off);
@@ -768,7 +795,7 @@ namespace {
 // count (a shared pass holds at least one node, an XCD slot round at most
 // eight passes, a threshold group at least one threshold).
 struct DpScratch {
-  size_t info, len, row, canon, nbase, rowidx, matclaim, matrow, sum, cur, bk, pk, dir, tkey, tval, crep, shell,
+  size_t info, len, row, canon, nbase, rowidx, matclaim, matrow, ruse, sum, cur, bk, pk, dir, tkey, tval, crep, shell,
       bucket, xslot, bcur, thg, pbase, total;
   uint32_t tcap;
 };
@@ -791,6 +818,7 @@ DpScratch dp_scratch(const hth_kb_s& kb, uint32_t n_nodes) {
   L.rowidx = area(n * 4);
   L.matclaim = area(n * 4);
   L.matrow = area(n * 4);
+  L.ruse = area(n * 4);
   L.sum = area(sizeof(DpSummary));
   L.cur = area(sizeof(DpCursor));
   L.bk = area(2 * nb * 4);
@@ -863,23 +891,31 @@ hth_status dp_schedule(hth_dplan_s& p, const std::vector<uint32_t>& bk, std::vec
       nb += alone * (kb.chunk_first[rd + 1] - kb.chunk_first[rd]);
       nc += alone * (kb.heavy_first[rd + 1] - kb.heavy_first[rd]);
       if (kb.n_words[rd] < kb.W) nf += g + o;
-      if (!grouped) continue;
-      DpBucket& bu = buckets[L * R2 + rd];
-      bu.first_group = p.n_groups + (uint32_t)p.lv_groups[L].size();
-      bu.member_base = p.n_members;
-      bu.k = gk;
-      for (uint64_t i0 = 0; i0 < g; i0 += gk) {
-        GroupTask gt{};
-        gt.role = rd / 2;
-        gt.inv = rd & 1;
-        gt.k = (uint32_t)std::min<uint64_t>(gk, g - i0);
-        gt.first = (uint32_t)(p.n_members + i0);
-        gt.n_words = kb.n_words[rd];
-        gt.compact = kb.tune.t_compact && 2ull * kb.n_obj[rd] <= kb.N;
-        p.lv_groups[L].push_back(gt);
-      }
-      p.n_members += (uint32_t)g;
     }
+    // the shared passes, those over short-row directions first (a launch
+    // holds passes of one kind); a bucket's passes stay consecutive
+    for (int want_short = 1; want_short >= 0; --want_short)
+      for (uint32_t rd = 0; rd < R2; ++rd) {
+        const uint64_t g = bk[L * R2 + rd];
+        const bool sr = short_rows(kb, rd);
+        if (!(g && g >= group_min) || (int)sr != want_short) continue;
+        DpBucket& bu = buckets[L * R2 + rd];
+        bu.first_group = p.n_groups + (uint32_t)p.lv_groups[L].size();
+        bu.member_base = p.n_members;
+        bu.k = gk;
+        for (uint64_t i0 = 0; i0 < g; i0 += gk) {
+          GroupTask gt{};
+          gt.role = rd / 2;
+          gt.inv = rd & 1;
+          gt.k = (uint32_t)std::min<uint64_t>(gk, g - i0);
+          gt.first = (uint32_t)(p.n_members + i0);
+          gt.n_words = kb.n_words[rd];
+          gt.compact = kb.tune.t_compact && 2ull * kb.n_obj[rd] <= kb.N;
+          gt.short_rows = sr;
+          p.lv_groups[L].push_back(gt);
+        }
+        p.n_members += (uint32_t)g;
+      }
     if (nb >= (1ull << 32) || nc >= (1ull << 32)) return fail(HTH_E_RANGE, "heavy-row blocks of one level exceed 2^32");
     p.B.nrole[L] = (uint32_t)solo;
     p.n_role += (uint32_t)solo;
@@ -998,6 +1034,7 @@ extern "C" hth_status hth_dplan_create(hth_kb kb, const hth_node* d_nodes, uint3
   p->K.rowidx = reinterpret_cast<uint32_t*>(p->buf + L.rowidx);
   p->K.matclaim = reinterpret_cast<uint32_t*>(p->buf + L.matclaim);
   p->K.matrow = reinterpret_cast<uint32_t*>(p->buf + L.matrow);
+  p->K.ruse = reinterpret_cast<uint32_t*>(p->buf + L.ruse);
   p->K.n_nodes = n_nodes;
   HTH_HIP(hipMemcpyAsync(p->buf + L.dir, dir.data(), dir.size() * 4, hipMemcpyHostToDevice, st));
   DpSummary init{};
@@ -1008,6 +1045,7 @@ extern "C" hth_status hth_dplan_create(hth_kb kb, const hth_node* d_nodes, uint3
   HTH_HIP(hipMemsetAsync(p->K.tkey, 0xFF, (size_t)tcap * 8, st));
   HTH_HIP(hipMemsetAsync(p->K.crep, 0xFF, (size_t)tcap * 4, st));
   if (n_nodes) HTH_HIP(hipMemsetAsync(p->K.matclaim, 0xFF, (size_t)n_nodes * 4, st));
+  if (n_nodes) HTH_HIP(hipMemsetAsync(p->K.ruse, 0, (size_t)n_nodes * 4, st));
   hipLaunchKernelGGL(k_dp_count, dim3((n_hyps + 255) / 256), dim3(256), 0, st, d_nodes, d_hyp_node_offsets,
                      d_children, n_nodes, n_children, n_hyps, p->K, p->info, p->len, p->d_sum, p->d_bk);
   HTH_HIP(hipGetLastError());

@@ -262,6 +262,7 @@ k_region(DevKB kb, const RegionTask* __restrict__ tasks, const uint32_t* __restr
   __shared__ uint64_t stk[kStackDepth][kRegionThreads];
   const uint32_t tile = blockIdx.x / n_tasks, task = blockIdx.x % n_tasks;
   const RegionTask T = tasks[task];
+  if (T.out_row == kNone && T.cover == kNone) return;   // a root whose coverage a shared pass adds
   const uint32_t tid = threadIdx.x;
   const uint32_t w = tile * kRegionThreads + tid;
   const bool live = w < kb.W;
@@ -319,6 +320,7 @@ k_region_reg(DevKB kb, const RegionTask* __restrict__ tasks, const uint32_t* __r
   __shared__ uint32_t s_pq[2][4];
   const uint32_t tile = blockIdx.x / n_tasks, task = blockIdx.x % n_tasks;
   const RegionTask T = tasks[task];
+  if (T.out_row == kNone && T.cover == kNone) return;   // a root whose coverage a shared pass adds
   const uint32_t tid = threadIdx.x;
   const uint32_t w0 = tile * (256 * R) + tid;
   uint64_t top[R], st[D > 1 ? D - 1 : 1][R];
@@ -647,6 +649,12 @@ void place_on_xcds(const hth_kb_s& kb, const std::vector<GroupTask>& gs, GroupCh
 // blocks per XCD round) to stay far below 2^31 work-items
 constexpr size_t kMaxGroupsPerLaunch = 2048;
 
+// Role direction rd = 2 role + inv holds only short rows: its shared passes
+// walk one subject per lane (k_group_short)
+inline bool short_rows(const hth_kb_s& kb, uint32_t rd) {
+  return kb.tune.short_rows && kb.max_deg[rd & 1][rd >> 1] <= kb.tune.short_rows;
+}
+
 std::vector<GroupChunk> chunk_groups(const hth_kb_s& kb, std::vector<GroupTask>& gs) {
   std::vector<GroupChunk> out;
   size_t i = 0;
@@ -654,7 +662,7 @@ std::vector<GroupChunk> chunk_groups(const hth_kb_s& kb, std::vector<GroupTask>&
     uint32_t wb = t_width_bytes(gs[i].k);
     uint64_t rows = t_rows(kb, gs[i]);
     size_t j = i + 1;
-    while (j < gs.size() && j - i < kMaxGroupsPerLaunch) {
+    while (j < gs.size() && j - i < kMaxGroupsPerLaunch && gs[j].short_rows == gs[i].short_rows) {
       const uint32_t nwb = std::max(wb, t_width_bytes(gs[j].k));
       if ((rows + t_rows(kb, gs[j])) * nwb > kb.tune.t_budget) break;
       rows += t_rows(kb, gs[j]);
@@ -956,6 +964,12 @@ hth_status launch_group_chunk(Launcher& L, const DevKB& d, const GroupTask* grou
     nwd += G.n_words;
   }
   const bool multi = nwd > 0 && ew < 96.0 * nwd;
+  if (host[g0].short_rows) {   // every row short: a lane per subject, one pass
+    return L.run(HTH_K_GROUP_SHORT, gb, [&] {
+      hipLaunchKernelGGL((k_group_short<TW, kShortWords>), dim3(nblocks), dim3(256), 0, L.st, d, groups + g0,
+                         members, T, bpg, xslots);
+    });
+  }
   uint64_t seg_rows;
   const uint32_t P = chunk_segments(kb, host, c, &seg_rows);
   for (uint32_t sg = 0; sg < P; ++sg) {
@@ -1028,13 +1042,16 @@ inline bool pushed(const hth_kb_s& kb, const RoleTask& t) {
 }
 
 // The shared passes of a level as launched: word counts and T layout set.
+// Short-row groups first, so that a launch holds groups of one kind.
 std::vector<GroupTask> level_groups(const hth_kb_s& kb, const PlanLevel& PL) {
   std::vector<GroupTask> out;
   for (GroupTask g : PL.groups) {
     g.n_words = kb.n_words[2 * g.role + g.inv];
     g.compact = kb.tune.t_compact && 2ull * kb.n_obj[2 * g.role + g.inv] <= kb.N;
+    g.short_rows = short_rows(kb, 2 * g.role + g.inv);
     out.push_back(g);
   }
+  std::stable_partition(out.begin(), out.end(), [](const GroupTask& g) { return g.short_rows != 0; });
   return out;
 }
 
@@ -1159,9 +1176,12 @@ void prepare(const hth_kb_s& kb, Plan&& plan, uint32_t n_hyps, Prepared& X) {
     const uint32_t mbase = (uint32_t)members.size();
     for (GroupTask g : level_groups(kb, PL)) {
       if (g.n_words < kb.W) {
-        for (uint32_t j = 0; j < g.k; ++j)
-          fills.push_back(FillTask{PL.members[g.first + j].out_row, (uint32_t)((g.acc[0] >> j) & 1)});
-        X.at[L].fill_bytes += 8.0 * g.k * (kb.W - g.n_words);
+        for (uint32_t j = 0; j < g.k; ++j) {
+          const uint32_t r = PL.members[g.first + j].out_row;
+          if (r == kNone) continue;              // coverage added by the pass, no row
+          fills.push_back(FillTask{r, (uint32_t)((g.acc[0] >> j) & 1)});
+          X.at[L].fill_bytes += 8.0 * (kb.W - g.n_words);
+        }
       }
       g.first += mbase;
       X.lv_groups[L].push_back(g);
@@ -1540,6 +1560,94 @@ extern "C" hth_status hth_eval_batch_sets(hth_kb kb, const hth_node* nodes,
   if (!d_sets) return fail(HTH_E_INVALID, "d_sets is NULL");
   return eval_batch_impl(kb, nodes, hyp_node_offsets, n_hyps, children, n_children, ws, ws_bytes,
                          d_sets, d_counts, stream);
+}
+
+// The cross-batch subexpression cache (hth_cache_*): the library's LRU over
+// the caller's rows, registered as the kb's set table.
+struct hth_cache_s {
+  hth_kb kb = nullptr;
+  hth::SubexprCache* c = nullptr;
+  uint64_t* rows = nullptr;
+  uint32_t n_rows = 0;
+  std::mutex mu;   // one cached evaluation at a time: compile, admit, launch
+  ~hth_cache_s() { hth::cache_delete(c); }
+};
+
+extern "C" hth_status hth_cache_create(hth_kb kb, uint64_t* d_rows, uint32_t n_rows, hth_cache* out) {
+  if (!kb || !d_rows || !out) return fail(HTH_E_INVALID, "NULL argument");
+  if (n_rows == 0 || n_rows >= (1u << 24)) return fail(HTH_E_RANGE, "a cache holds 1 .. 2^24 - 1 rows");
+  if (reinterpret_cast<uintptr_t>(d_rows) % 64) return fail(HTH_E_INVALID, "cache rows must be 64-byte aligned");
+  hth_cache_s* c = new (std::nothrow) hth_cache_s();
+  if (!c) return fail(HTH_E_NOMEM, "host allocation failed");
+  c->c = cache_new(n_rows);
+  if (!c->c) {
+    delete c;
+    return fail(HTH_E_NOMEM, "host allocation failed");
+  }
+  c->kb = kb;
+  c->rows = d_rows;
+  c->n_rows = n_rows;
+  std::lock_guard<std::mutex> g(kb->mu);
+  kb->sets = d_rows;
+  kb->n_sets = n_rows;
+  *out = c;
+  return HTH_OK;
+}
+
+extern "C" hth_status hth_cache_destroy(hth_cache cache) {
+  if (!cache) return HTH_OK;
+  {
+    std::lock_guard<std::mutex> g(cache->kb->mu);
+    if (cache->kb->sets == cache->rows) {
+      cache->kb->sets = nullptr;
+      cache->kb->n_sets = 0;
+    }
+  }
+  delete cache;
+  return HTH_OK;
+}
+
+extern "C" hth_status hth_cache_stats(hth_cache cache, hth_cache_info* out) {
+  if (!cache || !out) return fail(HTH_E_INVALID, "NULL argument");
+  std::lock_guard<std::mutex> g(cache->mu);
+  const CacheCounters k = cache_counters(cache->c);
+  *out = hth_cache_info{k.hits, k.misses, k.admitted, k.evictions, k.batches, k.entries, k.rows};
+  return HTH_OK;
+}
+
+extern "C" hth_status hth_eval_batch_cached(hth_kb kb, hth_cache cache, const hth_node* nodes,
+                                            const uint32_t* hyp_node_offsets, uint32_t n_hyps,
+                                            const uint32_t* children, uint32_t n_children, void* ws,
+                                            size_t ws_bytes, uint32_t* d_counts, void* stream) {
+  if (!kb || !cache || !nodes || !hyp_node_offsets || !ws || !d_counts) return fail(HTH_E_INVALID, "NULL argument");
+  if (cache->kb != kb) return fail(HTH_E_INVALID, "the cache belongs to another kb");
+  if (n_children && !children) return fail(HTH_E_INVALID, "children is NULL");
+  if (n_hyps == 0) return HTH_OK;
+  if (hyp_node_offsets[0] != 0) return fail(HTH_E_INVALID, "hyp_node_offsets[0] must be 0");
+  std::lock_guard<std::mutex> gc(cache->mu);
+  {
+    std::lock_guard<std::mutex> g(kb->mu);
+    if (kb->sets != cache->rows) return fail(HTH_E_STATE, "another set table replaced the cache's rows");
+  }
+  for (uint32_t h = 0; h < n_hyps; ++h)
+    for (uint32_t i = hyp_node_offsets[h]; i < hyp_node_offsets[h + 1]; ++i)
+      if (nodes[i].op == HTH_SET)
+        return fail(HTH_E_UNSUPPORTED, "set-table leaves are the cache's own rows in a cached evaluation");
+  PlanOptions opt;
+  opt.group_min = kb->tune.group_min ? kb->tune.group_min : 0xFFFFFFFFu;
+  opt.group_k = kb->tune.group_k;
+  opt.cache = cache->c;
+  Plan P;
+  hth_status s = compile_plan(*kb, nodes, hyp_node_offsets, n_hyps, children, n_children, opt, P);
+  if (s) {
+    cache_rollback(cache->c);
+    return s;
+  }
+  std::lock_guard<std::mutex> g(kb->mu);
+  s = run_plan(*kb, std::move(P), static_cast<char*>(ws), ws_bytes, d_counts, n_hyps, nullptr,
+               static_cast<hipStream_t>(stream));
+  if (s) cache_rollback(cache->c);
+  return s;
 }
 
 // A compiled batch kept for repeated launches (hth_plan_*).

@@ -130,6 +130,56 @@ __device__ __forceinline__ TW accept(const Planes<TW>& p, const TW (&acc)[kGroup
   return (res & ~p.ov) | (p.ov & acc[8]);
 }
 
+// Coverage of a member without an output row (GroupMember::cover): lane j
+// keeps member j's counts of covered positives and negatives.  A member that
+// accepts the zero count (z) also holds every individual of the words its
+// direction lists no assertion for, and those words are never visited: each
+// wave therefore adds z * popcount(P) over its share of all words and takes
+// z * popcount(P) off again for every word it visits (counts wrap modulo 2^32
+// in between; the total is exact).
+struct Cover {
+  uint32_t h;          // hypothesis, or kNone
+  bool z;              // the member accepts the zero count
+  uint32_t p, q;
+};
+__device__ __forceinline__ Cover cover_of(const GroupTask* G, const GroupMember* members, uint32_t k, int lane) {
+  Cover c{kNone, false, 0u, 0u};
+  if ((uint32_t)lane < k) {
+    c.h = members[G->first + lane].cover;
+    c.z = (G->acc[0] >> lane) & 1ull;
+  }
+  return c;
+}
+__device__ __forceinline__ void cover_word(Cover& c, const DevKB& kb, uint32_t w, uint64_t v) {
+  w = __builtin_amdgcn_readfirstlane(w);   // the same word on every lane: scalar loads
+  const uint64_t P = kb.pos[w], N = kb.neg[w];
+  c.p += (uint32_t)__popcll(v & P) - (c.z ? (uint32_t)__popcll(P) : 0u);
+  c.q += (uint32_t)__popcll(v & N) - (c.z ? (uint32_t)__popcll(N) : 0u);
+}
+// wave `wave` of `waves`: its share of all words, then the member's atomics
+__device__ __forceinline__ void cover_finish(Cover& c, const DevKB& kb, uint32_t wave, uint32_t waves, int lane) {
+  if (__ballot(c.h != kNone && c.z)) {
+    for (uint32_t w0 = wave * 64; w0 < kb.W; w0 += waves * 64) {
+      const uint32_t w = w0 + lane;
+      uint32_t pp = w < kb.W ? (uint32_t)__popcll(kb.pos[w]) : 0u;
+      uint32_t qq = w < kb.W ? (uint32_t)__popcll(kb.neg[w]) : 0u;
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) {
+        pp += __shfl_xor(pp, d, 64);
+        qq += __shfl_xor(qq, d, 64);
+      }
+      if (c.h != kNone && c.z) {
+        c.p += pp;
+        c.q += qq;
+      }
+    }
+  }
+  if (c.h != kNone) {
+    if (c.p) atomicAdd(kb.counts + 2 * c.h, c.p);
+    if (c.q) atomicAdd(kb.counts + 2 * c.h + 1, c.q);
+  }
+}
+
 // A shared pass cut by T row ("target segments"), so that the T rows one pass
 // fetches fit an XCD's L2: pass s counts only the assertions whose T row is in
 // [lo, hi).  Every pass walks the same rows; the counts of a row finished in
@@ -196,7 +246,9 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
 #pragma unroll
   for (int v = 0; v <= (int)kGroupMaxCount; ++v) acc[v] = (TW)G->acc[v];
   const uint32_t seg_n = sp.hi - sp.lo;
-  uint64_t* const my_out = (uint32_t)lane < k ? out_ptr(kb, members[G->first + lane].out_row) : nullptr;
+  const uint32_t my_row = (uint32_t)lane < k ? members[G->first + lane].out_row : kNone;
+  uint64_t* const my_out = my_row != kNone ? out_ptr(kb, my_row) : nullptr;
+  Cover cv = cover_of(G, members, k, lane);
   const uint32_t nw = blockDim.x >> 6;
   const uint32_t istep = bpg * nw;
   const uint32_t* words = kb.words + (size_t)(2 * G->role + G->inv) * kb.W;
@@ -382,6 +434,7 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
           if (rw.wd[m] * 64 + lane >= kb.N) rv = 0;
           const uint64_t mine = wave_transpose64((uint64_t)rv, lane);
           if (my_out) my_out[rw.wd[m]] = mine;
+          if (cv.h != kNone) cover_word(cv, kb, rw.wd[m], mine);
         }
       }
     }
@@ -391,6 +444,106 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
     s = ns;
     se = nse;
   }
+  if (sp.last) cover_finish(cv, kb, b * nw + wv, bpg * nw, lane);
+}
+
+// A shared pass over a role direction whose rows are all short (at most the
+// schedule's short_rows assertions): lane l of a wave owns subject 64 w + l of
+// each of MW consecutive entries of the direction's word list and walks that
+// subject's row alone, all MW rows in step.  A lane's counters are its own
+// subject's, so the words' assertion ranges are not sliced and nothing is
+// scanned across lanes.  The members' predicates are transposed into one word
+// per member; MW consecutive, aligned words go out as one run per member.
+constexpr int kShortWords = 4;
+template <typename TW, int MW>
+__global__ void __launch_bounds__(256)
+k_group_short(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __restrict__ members,
+              const TW* __restrict__ tarea, uint32_t bpg, const uint32_t* __restrict__ xslots) {
+  static_assert(MW % 2 == 0, "runs are stored two words at a time");
+  uint32_t g, b;
+  if (xslots) {   // one XCD per group, as in k_group
+    const uint32_t x = blockIdx.x & 7, j = blockIdx.x >> 3;
+    g = xslots[(j / bpg) * 8 + x];
+    b = j % bpg;
+    if (g == kNone) return;
+  } else {
+    g = blockIdx.x / bpg;
+    b = blockIdx.x % bpg;
+  }
+  const GroupTask* G = groups + g;
+  const uint32_t k = G->k;
+  const TW* T = tarea + G->t_off;
+  const uint32_t* off = (G->inv ? kb.inv_off : kb.fwd_off) + (size_t)G->role * (kb.N + 1);
+  const int32_t* tg = (G->compact ? (G->inv ? kb.ctg_inv : kb.ctg_fwd) : (G->inv ? kb.inv_tg : kb.fwd_tg)) +
+                      kb.role_base[G->role];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  TW acc[kGroupMaxCount + 1];
+#pragma unroll
+  for (int v = 0; v <= (int)kGroupMaxCount; ++v) acc[v] = (TW)G->acc[v];
+  const uint32_t my_row = (uint32_t)lane < k ? members[G->first + lane].out_row : kNone;
+  uint64_t* const my_out = my_row != kNone ? out_ptr(kb, my_row) : nullptr;
+  Cover cv = cover_of(G, members, k, lane);
+  const uint32_t nw = blockDim.x >> 6;
+  const uint32_t* words = kb.words + (size_t)(2 * G->role + G->inv) * kb.W;
+  const uint32_t n_words = G->n_words;
+  const uint32_t n_iter = (n_words + MW - 1) / MW;
+  for (uint32_t it = b * nw + wv; it < n_iter; it += bpg * nw) {
+    uint32_t wd[MW], e[MW], ee[MW];
+#pragma unroll
+    for (int m = 0; m < MW; ++m) {
+      const uint32_t idx = it * MW + m;
+      wd[m] = kNone;
+      e[m] = ee[m] = 0;
+      if (idx < n_words) {
+        const uint32_t w = words[idx], x = w * 64 + lane;
+        wd[m] = w;
+        if (x < kb.N) {
+          e[m] = off[x];
+          ee[m] = off[x + 1];
+        }
+      }
+    }
+    Planes<TW> p[MW];
+#pragma unroll
+    for (int m = 0; m < MW; ++m) p[m] = Planes<TW>{0, 0, 0, 0};
+    // step d reads assertion d of every row still open (rows hold at most
+    // short_rows assertions, so the wave leaves after that many steps)
+    for (;;) {
+      bool open = false;
+#pragma unroll
+      for (int m = 0; m < MW; ++m) open |= e[m] < ee[m];
+      if (!__ballot(open)) break;
+      int32_t t[MW];
+#pragma unroll
+      for (int m = 0; m < MW; ++m) t[m] = e[m] < ee[m] ? tg[e[m]] : -1;
+#pragma unroll
+      for (int m = 0; m < MW; ++m)
+        if (t[m] >= 0) {
+          planes_inc(p[m], T[(uint32_t)t[m]]);
+          ++e[m];
+        }
+    }
+    uint64_t o[MW];
+#pragma unroll
+    for (int m = 0; m < MW; ++m) {
+      TW rv = accept(p[m], acc);
+      if (wd[m] == kNone || wd[m] * 64 + lane >= kb.N) rv = 0;
+      o[m] = wave_transpose64((uint64_t)rv, lane);
+      if (cv.h != kNone && wd[m] != kNone) cover_word(cv, kb, wd[m], o[m]);
+    }
+    if (my_out) {
+      if (wd[MW - 1] != kNone && wd[MW - 1] - wd[0] == MW - 1 && wd[0] % MW == 0) {
+        ulonglong2* q = reinterpret_cast<ulonglong2*>(my_out + wd[0]);
+#pragma unroll
+        for (int i = 0; i < MW / 2; ++i) q[i] = make_ulonglong2(o[2 * i], o[2 * i + 1]);
+      } else {
+#pragma unroll
+        for (int m = 0; m < MW; ++m)
+          if (wd[m] != kNone) my_out[wd[m]] = o[m];
+      }
+    }
+  }
+  cover_finish(cv, kb, b * nw + wv, bpg * nw, lane);
 }
 
 }  // namespace hth

@@ -142,14 +142,20 @@ struct GroupTask {
   uint32_t n_words;    // non-empty words of (role, inv), set at launch
   uint32_t compact;    // 1: T holds the direction's objects only, indexed by object rank
   uint64_t t_off;      // first T row of the group in the T area (in T rows)
+  uint32_t short_rows; // 1: every row of (role, inv) is short: one lane walks each subject
+  uint32_t pad;
 };
 constexpr uint32_t kGroupMaxCount = 8;
+// A member whose node is the root of exactly one hypothesis and read by no
+// other node has no output row (out_row = kNone): the pass adds its words'
+// coverage of the examples into that hypothesis's counts (cover) instead.
 struct GroupMember {
   uint32_t child_row;
   uint32_t neg;
   uint32_t lo, hi, sat;
-  uint32_t out_row;
-  uint32_t pad0, pad1;
+  uint32_t out_row;    // n_fixed + slot, or kNone with cover set
+  uint32_t cover;      // hypothesis index, or kNone
+  uint32_t pad;
 };
 
 // Device view of the knowledge base and of one call's buffers (by value).
@@ -204,6 +210,8 @@ __device__ __forceinline__ const uint64_t* row_ptr(const DevKB& kb, uint32_t id)
 }
 __device__ __forceinline__ uint64_t* out_ptr(const DevKB& kb, uint32_t id) {
   if (id == kInstances) return kb.instances;
+  // a row of the set table: written when the table is a subexpression cache
+  if (id < kb.n_fixed) return const_cast<uint64_t*>(kb.sets) + (size_t)(id - kb.n_concepts) * kb.S;
   return kb.slots + (size_t)(id - kb.n_fixed) * kb.S;
 }
 

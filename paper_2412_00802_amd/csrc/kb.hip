@@ -766,6 +766,7 @@ extern "C" hth_status hth_kb_create(const hth_kb_desc* desc, void* derived, size
   kb->tune.t_compact = (uint32_t)env_u("HTHEDL_T_COMPACT", kb->tune.t_compact);
   kb->tune.t_segment_kb = (uint32_t)std::min<uint64_t>(1u << 22, env_u("HTHEDL_TSEG_KB", kb->tune.t_segment_kb));
   kb->tune.push_pct = (uint32_t)std::min<uint64_t>(100, env_u("HTHEDL_PUSH_PCT", kb->tune.push_pct));
+  kb->tune.short_rows = (uint32_t)std::min<uint64_t>(64, env_u("HTHEDL_SHORT_ROWS", kb->tune.short_rows));
   kb->heavy_min = (uint32_t)std::min<uint64_t>(
       1u << 30, std::max<uint64_t>(kHeavyMinFloor, env_u("HTHEDL_HEAVY_MIN", kb->heavy_min)));
   kb->lds_per_block = prop.sharedMemPerBlock;
@@ -1115,6 +1116,7 @@ extern "C" hth_status hth_kb_get_tuning(hth_kb kb, hth_tuning* out) {
   out->t_compact = kb->tune.t_compact;
   out->t_segment_kb = kb->tune.t_segment_kb;
   out->push_pct = kb->tune.push_pct;
+  out->short_rows = kb->tune.short_rows;
   return HTH_OK;
 }
 
@@ -1123,7 +1125,7 @@ extern "C" hth_status hth_kb_set_tuning(hth_kb kb, const hth_tuning* t) {
   if (t->group_k < 1 || t->group_k > 64 || t->xcd_local > 1 || t->t_budget_mb < 1 ||
       t->t_budget_mb > (1u << 20) || (t->unroll != 8 && t->unroll != 16) ||
       (t->region_reg != 0 && t->region_reg != 1 && t->region_reg != 2 && t->region_reg != 4) ||
-      t->t_compact > 1 || t->t_segment_kb > (1u << 22) || t->push_pct > 100)
+      t->t_compact > 1 || t->t_segment_kb > (1u << 22) || t->push_pct > 100 || t->short_rows > 64)
     return fail(HTH_E_RANGE, "tuning value out of range");
   std::lock_guard<std::mutex> g(kb->mu);
   kb->tune.group_min = t->group_min;
@@ -1135,6 +1137,7 @@ extern "C" hth_status hth_kb_set_tuning(hth_kb kb, const hth_tuning* t) {
   kb->tune.t_compact = t->t_compact;
   kb->tune.t_segment_kb = t->t_segment_kb;
   kb->tune.push_pct = t->push_pct;
+  kb->tune.short_rows = t->short_rows;
   return HTH_OK;
 }
 

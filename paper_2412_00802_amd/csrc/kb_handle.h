@@ -91,6 +91,8 @@ struct hth_kb_s {
     uint32_t t_compact = 1;      // 1: T rows of objects only where they are <= N/2
     uint32_t t_segment_kb = 0;   // T bytes per pass of a shared pass (0: one pass over all rows)
     uint32_t push_pct = 2;       // single ∃ρ.A with A under this % of N: pushed from A's members (0: never)
+    uint32_t short_rows = 12;    // shared passes over directions whose rows are all at most this long walk
+                                 // one subject per lane (0: never)
   } tune;
 };
 

@@ -100,7 +100,7 @@ __global__ void k_features(const hth_node* __restrict__ nodes, const uint32_t* _
 __global__ void __launch_bounds__(256)
 k_densify(const uint16_t* __restrict__ feat, const uint32_t* __restrict__ offs, uint32_t row0,
           uint32_t n_rows, const uint16_t* __restrict__ pfeat, const uint32_t* __restrict__ poffs,
-          const uint32_t* __restrict__ pidx, __bf16* __restrict__ x) {
+          const uint32_t* __restrict__ pidx, uint32_t context, __bf16* __restrict__ x) {
   __shared__ int32_t cnt[kFeatDim];
   const uint32_t r = blockIdx.x;
   if (r >= n_rows) return;
@@ -112,6 +112,10 @@ k_densify(const uint16_t* __restrict__ feat, const uint32_t* __restrict__ offs, 
     const uint32_t p = pidx[row0 + r];
     const uint32_t pb = poffs[p], pe = poffs[p + 1];
     for (uint32_t i = pb + threadIdx.x; i < pe; i += 256) atomicSub(&cnt[pfeat[i] & (kFeatDim - 1)], 1);
+    // the parent itself, in the other half of the index space (top bit flipped)
+    if (context)
+      for (uint32_t i = pb + threadIdx.x; i < pe; i += 256)
+        atomicAdd(&cnt[(pfeat[i] & (kFeatDim - 1)) ^ (kFeatDim / 2)], 1);
   }
   __syncthreads();
   __bf16* row = x + (size_t)r * kFeatDim;
@@ -244,6 +248,115 @@ k_gemm_bf16(int M, int N, int K, const __bf16* __restrict__ A, int lda, const __
         if (ep.c32) ep.c32[(size_t)gm * ep.ldc + gn] = v;
         if (ep.cbf) ep.cbf[(size_t)gm * ep.ldcb + gn] = (__bf16)v;
       }
+}
+
+// ---------------------------------------------------------------------------
+// The same product for A [M][K] and B given as [N][K] (both operands
+// contiguous along K), the forward layers' layout: every tile is staged with
+// 16-byte loads and stores.  Tiles of 128 x 128 x 64; while the MFMAs work
+// on the k-tile in LDS, the next k-tile's global loads are already in flight
+// into registers.  4 waves, each a 64 x 64 quarter of the tile as 2 x 2
+// products of 32 x 32 on v_mfma_f32_32x32x16_bf16.
+// ---------------------------------------------------------------------------
+constexpr int NBK = 64, NLDK = NBK + 8;   // LDS rows padded by 16 bytes
+__global__ void __launch_bounds__(256)
+k_gemm_nt(int M, int N, int K, const __bf16* __restrict__ A, int lda, const __bf16* __restrict__ B, int ldb,
+          GemmEpi ep) {
+  __shared__ __bf16 As[BM][NLDK];
+  __shared__ __bf16 Bs[BN][NLDK];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+  // a tile row holds 64 k = 8 chunks of 8; thread t stages chunks t + 256 c
+  bf16x8 ra[4], rb[4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int chunk = tid + 256 * c, row = chunk >> 3, kk = (chunk & 7) * 8;
+      const int gk = k0 + kk;
+      const int gm = m0 + row, gn = n0 + row;
+      if (gm < M && gk < K) ra[c] = *reinterpret_cast<const bf16x8*>(A + (size_t)gm * lda + gk);
+      else
+#pragma unroll
+        for (int i = 0; i < 8; ++i) ra[c][i] = (__bf16)0.f;
+      if (gn < N && gk < K) rb[c] = *reinterpret_cast<const bf16x8*>(B + (size_t)gn * ldb + gk);
+      else
+#pragma unroll
+        for (int i = 0; i < 8; ++i) rb[c][i] = (__bf16)0.f;
+    }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int chunk = tid + 256 * c, row = chunk >> 3, kk = (chunk & 7) * 8;
+      *reinterpret_cast<bf16x8*>(&As[row][kk]) = ra[c];
+      *reinterpret_cast<bf16x8*>(&Bs[row][kk]) = rb[c];
+    }
+  };
+  load(0);
+  stage();
+  __syncthreads();
+  for (int k0 = 0; k0 < K; k0 += NBK) {
+    const bool more = k0 + NBK < K;
+    if (more) load(k0 + NBK);                     // in flight during the MFMAs below
+#pragma unroll
+    for (int ks = 0; ks < NBK; ks += 16) {
+      bf16x8 a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        a[i] = *reinterpret_cast<const bf16x8*>(&As[wm * 64 + i * 32 + (lane & 31)][ks + 8 * (lane >> 5)]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        b[j] = *reinterpret_cast<const bf16x8*>(&Bs[wn * 64 + j * 32 + (lane & 31)][ks + 8 * (lane >> 5)]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+    if (more) {
+      stage();
+      __syncthreads();
+    }
+  }
+  // epilogue: register r of lane l holds row 8(r/4) + 4(l/32) + r%4, column l%32
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int gm = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int gn = n0 + wn * 64 + j * 32 + (lane & 31);
+        if (gm >= M || gn >= N) continue;
+        float v = acc[i][j][r];
+        if (ep.bias) v += ep.bias[gn];
+        if (ep.relu) v = fmaxf(v, 0.f);
+        if (ep.mask && !((float)ep.mask[(size_t)gm * ep.ldm + gn] > 0.f)) v = 0.f;
+        if (ep.c32) ep.c32[(size_t)gm * ep.ldc + gn] = v;
+        if (ep.cbf) ep.cbf[(size_t)gm * ep.ldcb + gn] = (__bf16)v;
+      }
+}
+
+// dst[c][r] = src[r][c] for a rows x cols bf16 matrix (32 x 32 tiles through LDS)
+__global__ void __launch_bounds__(256)
+k_transpose_bf16(const __bf16* __restrict__ src, int rows, int cols, __bf16* __restrict__ dst) {
+  __shared__ __bf16 t[32][33];
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8 threads
+  for (int i = ty; i < 32; i += 8)
+    if (r0 + i < rows && c0 + tx < cols) t[i][tx] = src[(size_t)(r0 + i) * cols + c0 + tx];
+  __syncthreads();
+  for (int i = ty; i < 32; i += 8)
+    if (c0 + i < cols && r0 + tx < rows) dst[(size_t)(c0 + i) * rows + r0 + tx] = t[tx][i];
 }
 
 // ---------------------------------------------------------------------------
@@ -453,7 +566,7 @@ extern "C" hth_status hth_densify(const uint16_t* d_feat, const uint32_t* d_hyp_
   if (!d_feat || !d_hyp_node_offsets || !d_x) return fail(HTH_E_INVALID, "NULL argument");
   if (!n_rows) return HTH_OK;
   hipLaunchKernelGGL(k_densify, dim3(n_rows), dim3(256), 0, static_cast<hipStream_t>(stream), d_feat,
-                     d_hyp_node_offsets, row0, n_rows, nullptr, nullptr, nullptr,
+                     d_hyp_node_offsets, row0, n_rows, nullptr, nullptr, nullptr, 0u,
                      reinterpret_cast<__bf16*>(d_x));
   HTH_HIP(hipGetLastError());
   return HTH_OK;
@@ -462,13 +575,14 @@ extern "C" hth_status hth_densify(const uint16_t* d_feat, const uint32_t* d_hyp_
 extern "C" hth_status hth_densify_delta(const uint16_t* d_feat, const uint32_t* d_hyp_node_offsets,
                                         uint32_t row0, uint32_t n_rows, const uint16_t* d_parent_feat,
                                         const uint32_t* d_parent_offsets, const uint32_t* d_parent_index,
-                                        uint16_t* d_x, void* stream) {
+                                        uint32_t parent_context, uint16_t* d_x, void* stream) {
   if (!d_feat || !d_hyp_node_offsets || !d_parent_feat || !d_parent_offsets || !d_parent_index || !d_x)
     return fail(HTH_E_INVALID, "NULL argument");
+  if (parent_context > 1) return fail(HTH_E_RANGE, "parent_context must be 0 or 1");
   if (!n_rows) return HTH_OK;
   hipLaunchKernelGGL(k_densify, dim3(n_rows), dim3(256), 0, static_cast<hipStream_t>(stream), d_feat,
                      d_hyp_node_offsets, row0, n_rows, d_parent_feat, d_parent_offsets, d_parent_index,
-                     reinterpret_cast<__bf16*>(d_x));
+                     parent_context, reinterpret_cast<__bf16*>(d_x));
   HTH_HIP(hipGetLastError());
   return HTH_OK;
 }
@@ -494,7 +608,7 @@ extern "C" hth_status hth_gemm_bf16(int trans_a, int trans_b, int M, int N, int 
   if (trans_a == 0 && trans_b == 0)
     hipLaunchKernelGGL((k_gemm_bf16<0, 0>), grid, block, 0, st, M, N, K, a, lda, b, ldb, ep);
   else if (trans_a == 0)
-    hipLaunchKernelGGL((k_gemm_bf16<0, 1>), grid, block, 0, st, M, N, K, a, lda, b, ldb, ep);
+    hipLaunchKernelGGL(k_gemm_nt, grid, block, 0, st, M, N, K, a, lda, b, ldb, ep);
   else
     hipLaunchKernelGGL((k_gemm_bf16<1, 0>), grid, block, 0, st, M, N, K, a, lda, b, ldb, ep);
   HTH_HIP(hipGetLastError());
@@ -556,6 +670,17 @@ extern "C" hth_status hth_adamw(float* p, const float* g, float* m, float* v, ui
   const unsigned g_ = (unsigned)std::min<size_t>((n + 255) / 256, 8192);
   hipLaunchKernelGGL(k_adamw, dim3(std::max(1u, g_)), dim3(256), 0, static_cast<hipStream_t>(stream), p, g,
                      m, v, reinterpret_cast<__bf16*>(pbf), n, lr, beta1, beta2, eps, wd, c1, c2);
+  HTH_HIP(hipGetLastError());
+  return HTH_OK;
+}
+
+extern "C" hth_status hth_transpose_bf16(const uint16_t* src, int rows, int cols, uint16_t* dst, void* stream) {
+  if (!src || !dst) return fail(HTH_E_INVALID, "NULL argument");
+  if (rows <= 0 || cols <= 0) return fail(HTH_E_RANGE, "rows and cols must be positive");
+  if (src == dst) return fail(HTH_E_INVALID, "the transpose is not in place");
+  const dim3 grid((cols + 31) / 32, (rows + 31) / 32), block(256);
+  hipLaunchKernelGGL(k_transpose_bf16, grid, block, 0, static_cast<hipStream_t>(stream),
+                     reinterpret_cast<const __bf16*>(src), rows, cols, reinterpret_cast<__bf16*>(dst));
   HTH_HIP(hipGetLastError());
   return HTH_OK;
 }

@@ -5,7 +5,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <new>
 #include <string>
+#include <unordered_map>
 
 namespace hth {
 namespace {
@@ -137,6 +139,110 @@ class Dag {
     table_.swap(t);
   }
 };
+
+}  // namespace
+
+// The cache: a persistent DAG of every subexpression seen, and rows kept in
+// least-recently-used order (rows[] is a doubly linked list through prev/next,
+// most recent at head).  A batch stamps every row it reads or writes, and
+// only rows stamped by earlier batches are evicted.
+struct SubexprCache {
+  static constexpr uint32_t kMaxNodes = 1u << 24;   // the DAG is flushed beyond this
+  Dag g;
+  struct Row {
+    uint32_t gid = kNone;
+    uint64_t stamp = 0;
+    uint32_t prev = kNone, next = kNone;
+  };
+  std::vector<Row> rows;
+  std::unordered_map<uint32_t, uint32_t> row_of;   // DAG id -> row
+  uint32_t head = kNone, tail = kNone;
+  uint64_t batch = 0;
+  std::vector<uint32_t> admitted_now;   // rows given out by the batch being compiled
+  CacheCounters cnt;
+
+  explicit SubexprCache(uint32_t n) : rows(n) {
+    for (uint32_t i = 0; i < n; ++i) push_front(i);
+    cnt.rows = n;
+  }
+  void unlink(uint32_t i) {
+    Row& r = rows[i];
+    if (r.prev != kNone) rows[r.prev].next = r.next; else head = r.next;
+    if (r.next != kNone) rows[r.next].prev = r.prev; else tail = r.prev;
+    r.prev = r.next = kNone;
+  }
+  void push_front(uint32_t i) {
+    rows[i].prev = kNone;
+    rows[i].next = head;
+    if (head != kNone) rows[head].prev = i;
+    head = i;
+    if (tail == kNone) tail = i;
+  }
+  void touch(uint32_t i) {
+    rows[i].stamp = batch;
+    unlink(i);
+    push_front(i);
+  }
+  void flush() {
+    g = Dag();
+    row_of.clear();
+    for (Row& r : rows) r.gid = kNone;
+    cnt.entries = 0;
+  }
+  // a new batch: the DAG is flushed when it has grown past its bound
+  void begin() {
+    ++batch;
+    ++cnt.batches;
+    admitted_now.clear();
+    if (g.nodes.size() > kMaxNodes) flush();
+  }
+  uint32_t lookup(uint32_t gid) const {
+    auto it = row_of.find(gid);
+    return it == row_of.end() ? kNone : it->second;
+  }
+  // the least recently used row not stamped by this batch, for `gid`
+  uint32_t admit(uint32_t gid) {
+    if (tail == kNone || rows[tail].stamp == batch) return kNone;
+    const uint32_t i = tail;
+    if (rows[i].gid != kNone) {
+      row_of.erase(rows[i].gid);
+      ++cnt.evictions;
+      --cnt.entries;
+    }
+    rows[i].gid = gid;
+    row_of[gid] = i;
+    ++cnt.entries;
+    ++cnt.admitted;
+    touch(i);
+    admitted_now.push_back(i);
+    return i;
+  }
+  void rollback() {
+    for (uint32_t i : admitted_now) {
+      if (rows[i].gid != kNone) {
+        row_of.erase(rows[i].gid);
+        --cnt.entries;
+      }
+      rows[i].gid = kNone;
+      rows[i].stamp = 0;
+      unlink(i);
+      // a freed row goes to the tail: the next one to be given out
+      rows[i].prev = tail;
+      rows[i].next = kNone;
+      if (tail != kNone) rows[tail].next = i; else head = i;
+      tail = i;
+    }
+    cnt.admitted -= admitted_now.size();
+    admitted_now.clear();
+  }
+};
+
+SubexprCache* cache_new(uint32_t n_rows) { return new (std::nothrow) SubexprCache(n_rows); }
+void cache_delete(SubexprCache* c) { delete c; }
+CacheCounters cache_counters(const SubexprCache* c) { return c->cnt; }
+void cache_rollback(SubexprCache* c) { c->rollback(); }
+
+namespace {
 
 inline bool is_role(uint8_t op) { return op >= HTH_EXISTS && op <= HTH_EXACTLY; }
 inline bool is_column(uint8_t op) { return op == HTH_DATA_GE || op == HTH_DATA_LE || op == HTH_DATA_EQ; }
@@ -312,14 +418,44 @@ struct Compiler {
     return HTH_OK;
   }
 
+  // The batch's canonical nodes in the cache's persistent DAG (children first,
+  // so each node's children already have their ids there).
+  void cache_ids(SubexprCache& C, std::vector<uint32_t>& gid) {
+    gid.assign(dag.nodes.size(), kNone);
+    std::vector<uint32_t> ks;
+    for (uint32_t v = 0; v < dag.nodes.size(); ++v) {
+      const CNode& n = dag.nodes[v];
+      if (n.op == HTH_NOT) gid[v] = C.g.mk_not(gid[n.a]);
+      else if (is_role(n.op)) gid[v] = C.g.mk_role(n.op, n.inv, n.arg, n.q, gid[n.a]);
+      else if (n.op == HTH_AND || n.op == HTH_OR) {
+        ks.clear();
+        for (uint32_t j = 0; j < n.kid_n; ++j) ks.push_back(gid[dag.kids[n.kid_off + j]]);
+        gid[v] = C.g.mk_nary(n.op, ks);
+      } else {
+        gid[v] = C.g.leaf(n.op, n.inv, n.arg, n.q);
+      }
+    }
+  }
+
   hth_status build(const PlanOptions& opt, Plan& P) {
     const size_t nv = dag.nodes.size();
     height.assign(nv, -1);
     live.assign(nv, 0);
     row.assign(nv, kNone);
     depth.assign(nv, -1);
+    // cross-batch cache: a role node whose subexpression holds a row is a
+    // leaf of this plan (read from that row); its subtree is not evaluated
+    SubexprCache* C = opt.cache;
+    std::vector<uint32_t> gid, hit_row(nv, kNone);
+    if (C) {
+      C->begin();
+      cache_ids(*C, gid);
+      for (uint32_t v = 0; v < nv; ++v)
+        if (is_role(dag.nodes[v].op)) hit_row[v] = C->lookup(gid[v]);
+    }
     for (uint32_t v = 0; v < nv; ++v) {
       const CNode& n = dag.nodes[v];
+      if (hit_row[v] != kNone) continue;           // a cached row: no role below it to run
       if (n.op == HTH_NOT) height[v] = height[n.a];
       else if (n.op == HTH_AND || n.op == HTH_OR) {
         int32_t h = -1;
@@ -331,11 +467,49 @@ struct Compiler {
     }
     for (uint32_t r : roots) live[r] = 1;
     for (size_t i = nv; i-- > 0;) {
-      if (!live[i]) continue;
+      if (!live[i] || hit_row[i] != kNone) continue;
       const CNode& n = dag.nodes[i];
       if (n.a != kNone) live[n.a] = 1;
       for (uint32_t j = 0; j < n.kid_n; ++j) live[dag.kids[n.kid_off + j]] = 1;
     }
+    // the rows this batch reads stay until it has run; live role nodes without
+    // one are given rows of their own while the cache has rows older than this
+    // batch (their results then stay for later batches)
+    std::vector<uint8_t> in_cache(nv, 0);
+    if (C) {
+      // every row read is stamped first, so that no admission below evicts it
+      for (uint32_t v = 0; v < nv; ++v) {
+        if (!live[v] || hit_row[v] == kNone) continue;
+        C->touch(hit_row[v]);
+        C->cnt.hits++;
+        row[v] = kb.d.n_concepts + hit_row[v];
+      }
+      for (uint32_t v = 0; v < nv; ++v) {
+        if (!live[v] || !is_role(dag.nodes[v].op) || hit_row[v] != kNone) continue;
+        C->cnt.misses++;
+        const uint32_t r = C->admit(gid[v]);
+        if (r != kNone) {
+          row[v] = kb.d.n_concepts + r;
+          in_cache[v] = 1;
+        }
+      }
+    }
+    // a role node that is the root of one hypothesis and read by no other node
+    // needs no row when it runs in a shared pass: the pass adds its coverage
+    // into that hypothesis's counts, and the hypothesis has no root region
+    std::vector<uint8_t> used(nv, 0);
+    std::vector<uint32_t> root_uses(nv, 0), root_hyp(nv, kNone);
+    for (size_t i = 0; i < nv; ++i) {
+      if (!live[i]) continue;
+      const CNode& n = dag.nodes[i];
+      if (n.a != kNone) used[n.a] = 1;
+      for (uint32_t j = 0; j < n.kid_n; ++j) used[dag.kids[n.kid_off + j]] = 1;
+    }
+    for (uint32_t h = 0; h < roots.size(); ++h) {
+      root_uses[roots[h]]++;
+      root_hyp[roots[h]] = h;
+    }
+    std::vector<uint8_t> covered_by_pass(roots.size(), 0);
     int32_t max_level = -1;
     for (uint32_t v = 0; v < nv; ++v) {
       if (!live[v]) continue;
@@ -364,8 +538,8 @@ struct Compiler {
         std::memcpy(&t.q, &n.q, 4);
         t.out_row = row[v];
         P.str.push_back(t);
-      } else if (is_role(n.op)) {
-        row[v] = new_row();
+      } else if (is_role(n.op) && hit_row[v] == kNone) {
+        if (!in_cache[v]) row[v] = new_row();
         max_level = std::max(max_level, height[v]);
         P.n_role_nodes++;
       }
@@ -376,7 +550,7 @@ struct Compiler {
     struct Pending { uint32_t v, child_row, neg; };
     std::vector<std::vector<Pending>> per_level(max_level + 1);
     for (uint32_t v = 0; v < nv; ++v) {
-      if (!live[v] || !is_role(dag.nodes[v].op)) continue;
+      if (!live[v] || !is_role(dag.nodes[v].op) || hit_row[v] != kNone) continue;
       const CNode& n = dag.nodes[v];
       const uint32_t c = n.a;
       const CNode& cn = dag.nodes[c];
@@ -477,7 +651,14 @@ struct Compiler {
             predicate(grp[q], m.lo, m.hi, m.neg);
             m.sat = m.hi == kInf ? m.lo : m.hi + 1;
             m.child_row = grp[q].child_row;
-            m.out_row = row[grp[q].v];
+            const uint32_t v = grp[q].v;
+            m.out_row = row[v];
+            m.cover = kNone;
+            if (!opt.instances && !used[v] && root_uses[v] == 1 && !in_cache[v]) {
+              m.out_row = kNone;
+              m.cover = root_hyp[v];
+              covered_by_pass[root_hyp[v]] = 1;
+            }
             const uint32_t jbit = (uint32_t)(q - g0);
             for (uint32_t v = 0; v <= kGroupMaxCount; ++v) {
               const bool ok = v < kGroupMaxCount ? (m.lo <= v && v <= m.hi)
@@ -493,6 +674,7 @@ struct Compiler {
     }
     // roots with coverage
     for (uint32_t h = 0; h < roots.size(); ++h) {
+      if (covered_by_pass[h]) continue;
       RegionTask t;
       hth_status s = program(roots[h], P.code, t.code_off, t.code_len);
       if (s) return s;

@@ -12,7 +12,24 @@
 
 namespace hth {
 
+// A cross-batch cache of role-node rows (plan.cpp): canonical subexpressions
+// of every batch compiled with it are interned in one persistent DAG, so that
+// equal subexpressions of different batches get the same id; a role node whose
+// id holds a row is read from that row, and a role node without one may be
+// given the least recently used row to write its result into.
+struct SubexprCache;
+SubexprCache* cache_new(uint32_t n_rows);
+void cache_delete(SubexprCache* c);
+struct CacheCounters {
+  uint64_t hits = 0, misses = 0, admitted = 0, evictions = 0, batches = 0;
+  uint32_t entries = 0, rows = 0;
+};
+CacheCounters cache_counters(const SubexprCache* c);
+// Undo the admissions of the last compiled batch (its launch did not happen).
+void cache_rollback(SubexprCache* c);
+
 struct PlanOptions {
+  SubexprCache* cache = nullptr; // cross-batch cache of role-node rows (the set table)
   bool instances = false;        // write the (single) root's instance set
   uint32_t group_min = 0xFFFFFFFFu;  // (role, dir, level) buckets with at least this many
                                      // role nodes use a shared CSR pass; others run alone

@@ -40,13 +40,14 @@ EXPORTED = ["hth_kb_derived_bytes", "hth_kb_create", "hth_kb_set_examples", "hth
             "hth_kb_destroy", "hth_workspace_bytes", "hth_eval_one", "hth_eval_batch",
             "hth_sync", "hth_status_str", "hth_last_error", "hth_profile_begin",
             "hth_profile_end", "hth_features", "hth_densify", "hth_gemm_bf16", "hth_head_forward",
-            "hth_head_backward", "hth_colsum", "hth_adamw", "hth_to_bf16", "hth_topk",
+            "hth_head_backward", "hth_colsum", "hth_adamw", "hth_to_bf16", "hth_topk", "hth_transpose_bf16",
             "hth_batch_workspace_bytes", "hth_head_score", "hth_kb_get_tuning", "hth_kb_set_tuning",
             "hth_kb_set_sets", "hth_eval_batch_sets", "hth_densify_delta", "hth_plan_create",
             "hth_plan_upload", "hth_plan_launch", "hth_plan_destroy", "hth_numeric_derived_bytes",
             "hth_kb_set_numeric", "hth_string_derived_bytes", "hth_kb_set_strings", "hth_kb_set_patterns",
             "hth_dplan_scratch_bytes", "hth_dplan_create", "hth_dplan_launch", "hth_dplan_destroy",
-            "hth_draw_conjuncts", "hth_conjoin", "hth_dplan_stats", "hth_eval_one_noalloc"]
+            "hth_draw_conjuncts", "hth_conjoin", "hth_dplan_stats", "hth_eval_one_noalloc",
+            "hth_cache_create", "hth_eval_batch_cached", "hth_cache_stats", "hth_cache_destroy"]
 
 
 class HthError(RuntimeError):
@@ -69,10 +70,16 @@ class Tuning(ctypes.Structure):
                 ("xcd_local", ctypes.c_uint32), ("t_budget_mb", ctypes.c_uint32),
                 ("unroll", ctypes.c_uint32), ("region_reg", ctypes.c_uint32),
                 ("t_compact", ctypes.c_uint32), ("t_segment_kb", ctypes.c_uint32),
-                ("push_pct", ctypes.c_uint32)]
+                ("push_pct", ctypes.c_uint32), ("short_rows", ctypes.c_uint32)]
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class CacheInfo(ctypes.Structure):
+    _fields_ = [("hits", ctypes.c_uint64), ("misses", ctypes.c_uint64), ("admitted", ctypes.c_uint64),
+                ("evictions", ctypes.c_uint64), ("batches", ctypes.c_uint64), ("entries", ctypes.c_uint32),
+                ("rows", ctypes.c_uint32)]
 
 
 class DplanInfo(ctypes.Structure):
@@ -109,6 +116,10 @@ def lib() -> ctypes.CDLL:
             "hth_workspace_bytes": [P, U32, U32, ctypes.POINTER(S)],
             "hth_eval_one": [P, P, U32, P, U32, P, S, P, P, P],
             "hth_eval_one_noalloc": [P, P, U32, P, U32, P, P, P],
+            "hth_cache_create": [P, P, U32, ctypes.POINTER(P)],
+            "hth_eval_batch_cached": [P, P, P, P, U32, P, U32, P, S, P, P],
+            "hth_cache_stats": [P, ctypes.POINTER(CacheInfo)],
+            "hth_cache_destroy": [P],
             "hth_eval_batch": [P, P, P, U32, P, U32, P, S, P, P],
             "hth_eval_batch_sets": [P, P, P, U32, P, U32, P, S, P, P, P],
             "hth_kb_set_sets": [P, P, U32],
@@ -134,7 +145,7 @@ def lib() -> ctypes.CDLL:
             "hth_profile_end": [P, ctypes.POINTER(ProfEntry)],
             "hth_features": [P, P, U32, P, U32, P, P, P, P],
             "hth_densify": [P, P, U32, U32, P, P],
-            "hth_densify_delta": [P, P, U32, U32, P, P, P, P, P],
+            "hth_densify_delta": [P, P, U32, U32, P, P, P, U32, P, P],
             "hth_gemm_bf16": [I, I, I, I, I, P, I, P, I, P, I, P, I, P, I, P, I, P],
             "hth_head_forward": [P, I, I, P, P, P, P, P, F, P, I, P],
             "hth_head_backward": [P, I, I, P, P, P, P, P],
@@ -142,6 +153,7 @@ def lib() -> ctypes.CDLL:
             "hth_colsum": [P, I, I, I, P, P],
             "hth_adamw": [P, P, P, P, P, S, F, F, F, F, F, I, P],
             "hth_to_bf16": [P, P, S, P],
+            "hth_transpose_bf16": [P, ctypes.c_int, ctypes.c_int, P, P],
             "hth_topk": [P, U32, U32, P, P, P],
         }
         for name, args in sig.items():
@@ -320,6 +332,32 @@ def hth_eval_batch(kb, nodes: np.ndarray, offsets: np.ndarray, children: np.ndar
                                 _ptr(d_counts), _stream(stream)))
 
 
+def hth_cache_create(kb, d_rows, n_rows: int):
+    out = ctypes.c_void_p()
+    _check(lib().hth_cache_create(kb, _ptr(d_rows), n_rows, ctypes.byref(out)))
+    return out.value
+
+
+def hth_eval_batch_cached(kb, cache, nodes: np.ndarray, offsets: np.ndarray, children: np.ndarray, ws,
+                          ws_bytes: int, d_counts, stream=None) -> None:
+    nodes = np.ascontiguousarray(nodes, dtype=NODE_DTYPE)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint32)
+    children = np.ascontiguousarray(children, dtype=np.uint32)
+    _check(lib().hth_eval_batch_cached(kb, cache, _np_ptr(nodes), _np_ptr(offsets), offsets.shape[0] - 1,
+                                       _np_ptr(children), children.shape[0], _ptr(ws), ws_bytes,
+                                       _ptr(d_counts), _stream(stream)))
+
+
+def hth_cache_stats(cache) -> dict:
+    info = CacheInfo()
+    _check(lib().hth_cache_stats(cache, ctypes.byref(info)))
+    return {f: int(getattr(info, f)) for f, _ in info._fields_}
+
+
+def hth_cache_destroy(cache) -> None:
+    _check(lib().hth_cache_destroy(cache))
+
+
 def hth_eval_batch_sets(kb, nodes: np.ndarray, offsets: np.ndarray, children: np.ndarray, ws,
                         ws_bytes: int, d_sets, d_counts, stream=None) -> None:
     nodes = np.ascontiguousarray(nodes, dtype=NODE_DTYPE)
@@ -464,9 +502,10 @@ def hth_densify(d_feat, d_offsets, row0: int, n_rows: int, d_x, stream=None) -> 
 
 
 def hth_densify_delta(d_feat, d_offsets, row0: int, n_rows: int, d_parent_feat, d_parent_offsets,
-                      d_parent_index, d_x, stream=None) -> None:
+                      d_parent_index, d_x, stream=None, parent_context: int = 0) -> None:
     _check(lib().hth_densify_delta(_ptr(d_feat), _ptr(d_offsets), row0, n_rows, _ptr(d_parent_feat),
-                                   _ptr(d_parent_offsets), _ptr(d_parent_index), _ptr(d_x), _stream(stream)))
+                                   _ptr(d_parent_offsets), _ptr(d_parent_index), parent_context, _ptr(d_x),
+                                   _stream(stream)))
 
 
 def hth_gemm_bf16(trans_a: int, trans_b: int, M: int, N: int, K: int, A, lda: int, B, ldb: int,
@@ -504,6 +543,10 @@ def hth_adamw(p, g, m, v, pbf, n: int, lr: float, beta1: float, beta2: float, ep
 
 def hth_to_bf16(s, d, n: int, stream=None) -> None:
     _check(lib().hth_to_bf16(_ptr(s), _ptr(d), n, _stream(stream)))
+
+
+def hth_transpose_bf16(src, rows: int, cols: int, dst, stream=None) -> None:
+    _check(lib().hth_transpose_bf16(_ptr(src), rows, cols, _ptr(dst), _stream(stream)))
 
 
 def hth_topk(d_scores, n: int, k: int, d_idx, d_work, stream=None) -> None:

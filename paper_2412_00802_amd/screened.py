@@ -44,7 +44,7 @@ def removal_targets(counts: np.ndarray, base: np.ndarray) -> np.ndarray:
     return np.log1p(d).astype(np.float32)
 
 
-def gather_training_pairs(eng, kb, n_pairs, per_round, beam, rng, chunk):
+def gather_training_pairs(eng, kb, n_pairs, per_round, beam, rng, chunk, late_beam: int = 0):
     """Refinement rounds from top; every candidate is evaluated exactly.
     Returns the candidates, their counts, their parents' counts, the parents
     (distinct, in round order) and each candidate's parent index."""
@@ -55,7 +55,7 @@ def gather_training_pairs(eng, kb, n_pairs, per_round, beam, rng, chunk):
     rounds = (n_pairs + per_round - 1) // per_round
     for r, cands, cnt, plist, pi, pc in search.refinement_rounds(
             kb, ev, eng.n_pos, rounds, per_round, beam, rng, start_counts=[eng.n_pos, eng.n_neg],
-            with_parents=True):
+            with_parents=True, late_beam=late_beam):
         hyps.extend(cands)
         counts.append(cnt)
         pcounts.append(pc)
@@ -68,9 +68,10 @@ def gather_training_pairs(eng, kb, n_pairs, per_round, beam, rng, chunk):
 
 
 def train(scr: Screener, fb: FeatureBatch, y_dev, n: int, epochs: int, batch: int, rng,
-          parents: FeatureBatch = None, parent_index=None) -> List[float]:
+          parents: FeatureBatch = None, parent_index=None, context: int = 0) -> List[float]:
     """Epochs of minibatch AdamW over rows [0, n); with parents, the features
-    are relative to each row's parent (hth_densify_delta)."""
+    are relative to each row's parent (hth_densify_delta; with context, the
+    parent's own features too)."""
     torch = scr.t
     losses = []
     nb = n // batch
@@ -78,7 +79,7 @@ def train(scr: Screener, fb: FeatureBatch, y_dev, n: int, epochs: int, batch: in
         scr.loss.zero_()
         for bi in rng.permutation(nb):
             r0 = int(bi) * batch
-            fb.densify(r0, batch, scr.x, parents, parent_index)
+            fb.densify(r0, batch, scr.x, parents, parent_index, context)
             scr.train_step(batch, y_dev[r0:r0 + batch])
         losses.append(scr.loss.item() / (2 * nb * batch))
         log(f"[screen] epoch {ep}: loss {losses[-1]:.5f}")
@@ -87,32 +88,36 @@ def train(scr: Screener, fb: FeatureBatch, y_dev, n: int, epochs: int, batch: in
 
 
 def score(scr: Screener, fb: FeatureBatch, n: int, n_pos: int, n_neg: int, out, base=None,
-          parents: FeatureBatch = None, parent_index=None, kind: int = 0) -> None:
+          parents: FeatureBatch = None, parent_index=None, kind: int = 0, context: int = 0) -> None:
     """Predicted F1 of candidates [0, n); base (device uint32 [n][2]): the
     parents' coverage (kept shares, kind 0, or removed counts, kind 1);
     parents: features relative to the parents."""
     B = scr.batch
     for r0 in range(0, n, B):
         m = min(B, n - r0)
-        fb.densify(r0, m, scr.x, parents, parent_index)
+        fb.densify(r0, m, scr.x, parents, parent_index, context)
         z = scr.logits(m)
         hthedl.hth_head_score(z, m, float(n_pos), float(n_neg), out[r0:r0 + m],
                               base=None if base is None else base[r0:r0 + m], kind=kind)
 
 
-def run(kb, eng, pairs: int = 200_000, candidates_beam: int = 4096, refinements: int = 256, epochs: int = 20,
+def run(kb, eng, pairs: int = 200_000, candidates_beam: int = 4096, refinements: int = 256, epochs: int = 10,
         top: float = 0.02, audit: float = 0.005, k: int = 100, lr: float = 5e-4, per_round: int = 16384,
         chunk: int = 65536, modes=("logdelta", "delta", "relative", "absolute"), sweep=(0.02, 0.05, 0.1),
-        name: str = "c3") -> dict:
+        name: str = "c3", draws: int = 1, late_beam: int = 0, weight_decay: float = 1e-4) -> dict:
     """The screened search on one resident KB: training pairs from the exact
     engine, screeners trained on the GPU, candidates, the exhaustive exact
-    evaluation (the judge) and each screener's pipeline.  Returns the record."""
+    evaluation (the judge) and each screener's pipeline.  With draws > 1 the
+    candidates are drawn again from the same parents that many times (the
+    screeners are not retrained) and each draw's recall is reported.  Returns
+    the record."""
     import torch
     rng = np.random.default_rng(synth.BASE_SEED + 50)
 
     # 1. training pairs from the engine
     t = time.perf_counter()
-    hyps, counts, pcounts, tparents, tpidx = gather_training_pairs(eng, kb, pairs, per_round, 256, rng, chunk)
+    hyps, counts, pcounts, tparents, tpidx = gather_training_pairs(eng, kb, pairs, per_round, 256, rng, chunk,
+                                                                   late_beam)
     t_pairs = time.perf_counter() - t
     order = rng.permutation(len(hyps))
     hyps = [hyps[i] for i in order]
@@ -124,26 +129,53 @@ def run(kb, eng, pairs: int = 200_000, candidates_beam: int = 4096, refinements:
     tpi = torch.from_numpy(tpidx.astype(np.int32)).cuda()
 
     # 2. training: "logdelta" predicts log(1 + removed positives / negatives)
-    # from features relative to the parent, with the squared error; "delta"
+    # from features relative to the parent, with the squared error ("logctx":
+    # the same with the parent's own features beside them); "delta"
     # the shares of the parent's coverage a refinement keeps, from the same
     # features; "relative" those shares from the candidate's own features;
     # "absolute" the covered fractions of the examples
     models = {}
     for mode in modes:
-        if mode == "logdelta":
+        if mode in LOG_MODES:
             y = torch.from_numpy(removal_targets(counts, pcounts)).cuda()
         else:
             y = torch.from_numpy(coverage_targets(counts, eng.n_pos, eng.n_neg,
                                                   None if mode == "absolute" else pcounts)).cuda()
-        scr = Screener(init_params(seed=11), batch=8192, lr=lr, loss="mse" if mode == "logdelta" else "bce")
+        scr = Screener(init_params(seed=11), batch=8192, lr=lr, weight_decay=weight_decay,
+                       loss="mse" if mode in LOG_MODES else "bce")
         t = time.perf_counter()
         losses = train(scr, fb, y, n_tr, epochs, 1024, rng,
-                       *((tpfb, tpi) if mode in ("delta", "logdelta") else (None, None)))
+                       *((tpfb, tpi) if mode in REL_MODES else (None, None)), context=int(mode == "logctx"))
         models[mode] = (scr, losses, time.perf_counter() - t)
-
-    # 3. candidates: the best `candidates_beam` evaluated so far, each refined
     best = search.top_indices(counts, eng.n_pos, candidates_beam)
     parents = [hyps[i] for i in best]
+    out = None
+    recalls = {m: [] for m in models}
+    for d in range(draws):
+        rec = _draw(kb, eng, models, parents, counts[best], rng, refinements, top, audit, k, chunk,
+                    sweep if d == 0 else (), log_tag=f"draw {d}")
+        for m in models:
+            recalls[m].append(rec["screener"][m][f"recall_at_{k}"])
+        if out is None:
+            out = rec
+    out.update({"workload": f"screened search on the {name} KB ({kb.n:,} individuals)",
+                "training_pairs": len(hyps), "pairs_seconds": round(t_pairs, 2), "draws": draws,
+                f"recall_at_{k}_per_draw": recalls,
+                f"recall_at_{k}_mean": {m: round(float(np.mean(v)), 4) for m, v in recalls.items()},
+                f"recall_at_{k}_min": {m: round(float(np.min(v)), 4) for m, v in recalls.items()}})
+    return out
+
+
+LOG_MODES = ("logdelta", "logctx")            # targets: log(1 + removed counts)
+REL_MODES = ("delta", "logdelta", "logctx")   # features relative to the parent
+
+
+def _draw(kb, eng, models, parents, pcounts, rng, refinements, top, audit, k, chunk, sweep, log_tag=""):
+    """One set of candidates (every parent refined), the exhaustive exact
+    evaluation of all of them, and each screener's pipeline on them."""
+    import torch
+
+    # 3. candidates: the best `candidates_beam` evaluated so far, each refined
     ref = search.Refiner(kb, rng)
     cands, parent_of = [], []
     seen = set()
@@ -160,7 +192,7 @@ def run(kb, eng, pairs: int = 200_000, candidates_beam: int = 4096, refinements:
     log(f"[screen] {n:,} candidates from {len(parents)} parents ({t_cands:.1f}s)")
     cenc = hthedl.encode_batch(cands, child_offsets=True)
     cfb = FeatureBatch(*cenc[:3])
-    cbase = torch.from_numpy(counts[best][parent_of].astype(np.uint32).view(np.int32)).cuda()
+    cbase = torch.from_numpy(pcounts[parent_of].astype(np.uint32).view(np.int32)).cuda()
     cpfb = FeatureBatch(*hthedl.encode_batch(parents))
     cpi = torch.from_numpy(parent_of.astype(np.int32)).cuda()
     n_sel = int(round(top * n))
@@ -194,14 +226,14 @@ def run(kb, eng, pairs: int = 200_000, candidates_beam: int = 4096, refinements:
                 stages[key] = round(now - mark, 5)
                 mark = now
 
-        rel = mode in ("delta", "logdelta")
+        rel = mode in REL_MODES
         cfb.recompute()
         if rel:
             cpfb.recompute()
         stage("features_s")
         score(scr, cfb, n, eng.n_pos, eng.n_neg, scores, base=None if mode == "absolute" else cbase,
               parents=cpfb if rel else None, parent_index=cpi if rel else None,
-              kind=1 if mode == "logdelta" else 0)
+              kind=1 if mode in LOG_MODES else 0, context=int(mode == "logctx"))
         stage("mlp_s")
         hthedl.hth_topk(scores, n, m_sel, sel_t, work)
         chosen = np.union1d(sel_t.cpu().numpy().astype(np.int64), aud)
@@ -233,24 +265,25 @@ def run(kb, eng, pairs: int = 200_000, candidates_beam: int = 4096, refinements:
                      "screened_seconds": round(t_screen, 4), "stages_synchronised": stages,
                      "train_seconds": round(t_train, 2),
                      "train_loss_first_last": [round(losses[0], 5), round(losses[-1], 5)]}
-        log(f"[screen] {mode}: recall@{k} {res[mode][f'recall_at_{k}']:.2f}, "
+        log(f"[screen] {log_tag} {mode}: recall@{k} {res[mode][f'recall_at_{k}']:.2f}, "
             f"{res[mode]['speedup']}x the exhaustive rate; stages {stages}")
-    # recall and speed of the logdelta screener at other exact budgets
+    # recall and speed of the first log-removal screener at other exact budgets
     budget_sweep = []
-    if "logdelta" in models:
-        scr_d = models["logdelta"][0]
+    swept = next((m for m in models if m in LOG_MODES), None)
+    if swept:
+        scr_d = models[swept][0]
         for frac in sweep:
             m_sel = int(round(frac * n))
             sel_m = torch.empty(m_sel, dtype=torch.int32, device="cuda")
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            chosen, _, got = screened(scr_d, "logdelta", m_sel, sel_m)
+            chosen, _, got = screened(scr_d, swept, m_sel, sel_m)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             budget_sweep.append({"top_fraction": frac, "exact_budget": int(chosen.size),
                                  f"recall_at_{k}": search.recall_at(got, exact_top),
                                  "speedup": round(t_exh / dt, 3)})
-            log(f"[screen] logdelta at top {frac}: recall {budget_sweep[-1][f'recall_at_{k}']:.2f}, "
+            log(f"[screen] {swept} at top {frac}: recall {budget_sweep[-1][f'recall_at_{k}']:.2f}, "
                 f"{budget_sweep[-1]['speedup']}x")
     # ties at the k-th exact F1 make part of the exact top-k a matter of the index tie-break
     kth = np.sort(f_np)[::-1][k - 1] if n >= k else 0.0
@@ -259,17 +292,17 @@ def run(kb, eng, pairs: int = 200_000, candidates_beam: int = 4096, refinements:
     budget = first["exact_budget"]
     rand = rng.choice(n, size=budget, replace=False)
     rand_top = rand[search.top_indices(all_np[rand], eng.n_pos, k)]
-    pf1 = search.f1_float(counts[best], eng.n_pos)[parent_of]
+    pf1 = search.f1_float(pcounts, eng.n_pos)[parent_of]
     heur = np.argsort(-pf1, kind="stable")[:budget]
     heur_top = heur[search.top_indices(all_np[heur], eng.n_pos, k)]
     return {
-        "workload": f"screened search on the {name} KB ({kb.n:,} individuals)",
         "candidates": n, "top_fraction": top, "audit_fraction": audit,
         "exhaustive_hyp_per_s": round(n / t_exh, 1), "exhaustive_seconds": round(t_exh, 4),
-        "screener": res, "logdelta_budget_sweep": budget_sweep, "candidates_tied_at_kth_f1": ties,
+        "screener": res, "budget_sweep": budget_sweep, "budget_sweep_screener": swept,
+        "candidates_tied_at_kth_f1": ties,
         f"random_recall_at_{k}": search.recall_at(rand_top, exact_top),
         f"parent_f1_recall_at_{k}": search.recall_at(heur_top, exact_top),
-        "training_pairs": len(hyps), "pairs_seconds": round(t_pairs, 2), "candidates_seconds": round(t_cands, 2),
+        "candidates_seconds": round(t_cands, 2),
     }
 
 
@@ -279,14 +312,19 @@ def main():
     ap.add_argument("--pairs", type=int, default=200_000)
     ap.add_argument("--candidates-beam", type=int, default=4096)
     ap.add_argument("--refinements", type=int, default=256)
-    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--epochs", type=int, default=10)
     ap.add_argument("--top", type=float, default=0.02)
     ap.add_argument("--audit", type=float, default=0.005)
     ap.add_argument("--k", type=int, default=100)
     ap.add_argument("--lr", type=float, default=5e-4)
     ap.add_argument("--modes", default="logdelta,delta,relative,absolute")
     ap.add_argument("--sweep", default="0.02,0.05,0.1",
-                    help="top fractions at which the delta screener's recall and speed are also reported")
+                    help="top fractions at which the first log-removal screener's recall and speed are also "
+                         "reported")
+    ap.add_argument("--draws", type=int, default=1, help="candidate sets drawn from the same parents")
+    ap.add_argument("--weight-decay", type=float, default=1e-4)
+    ap.add_argument("--late-beam", type=int, default=0,
+                    help="beam of the training rounds' second half (0: the same 256 throughout)")
     args = ap.parse_args()
 
     cfg = synth.CONFIGS["c3"]
@@ -304,7 +342,8 @@ def main():
     eng = hthedl.Engine(kb, max_nodes=64, max_hyps=1)
     out = run(kb, eng, args.pairs, args.candidates_beam, args.refinements, args.epochs, args.top, args.audit,
               args.k, args.lr, per_round, modes=[m for m in args.modes.split(",") if m],
-              sweep=[float(v) for v in args.sweep.split(",") if v], name=cfg.name)
+              sweep=[float(v) for v in args.sweep.split(",") if v], name=cfg.name, draws=args.draws,
+              late_beam=args.late_beam, weight_decay=args.weight_decay)
     print(json.dumps(out), flush=True)
 
 

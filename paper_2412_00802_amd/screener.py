@@ -57,8 +57,13 @@ class Screener:
         bf = torch.bfloat16
         self.w1b = torch.empty((D_IN, D_H1), dtype=bf, device=self.dev)
         self.w2b = torch.empty((D_H1, D_H2), dtype=bf, device=self.dev)
+        # the forward products read the weights as [N][K] (both operands
+        # contiguous along K); kept in step with w1b / w2b
+        self.w1t = torch.empty((D_H1, D_IN), dtype=bf, device=self.dev)
+        self.w2t = torch.empty((D_H2, D_H1), dtype=bf, device=self.dev)
         hthedl.hth_to_bf16(self.p["w1"], self.w1b, D_IN * D_H1)
         hthedl.hth_to_bf16(self.p["w2"], self.w2b, D_H1 * D_H2)
+        self._transpose()
         B = batch
         self.x = torch.empty((B, D_IN), dtype=bf, device=self.dev)
         self.h1 = torch.empty((B, D_H1), dtype=bf, device=self.dev)
@@ -69,14 +74,18 @@ class Screener:
         self.dh1 = torch.empty((B, D_H1), dtype=bf, device=self.dev)
         self.loss = torch.zeros(1, dtype=torch.float32, device=self.dev)
 
+    def _transpose(self) -> None:
+        hthedl.hth_transpose_bf16(self.w1b, D_IN, D_H1, self.w1t)
+        hthedl.hth_transpose_bf16(self.w2b, D_H1, D_H2, self.w2t)
+
     # -- layers -------------------------------------------------------------
 
     def forward(self, n: int, x=None):
         """h1, h2, z for the first n rows of self.x (or of x)."""
         x = self.x if x is None else x
         G = hthedl.hth_gemm_bf16
-        G(0, 0, n, D_H1, D_IN, x, D_IN, self.w1b, D_H1, bias=self.p["b1"], relu=1, cbf=self.h1, ldcb=D_H1)
-        G(0, 0, n, D_H2, D_H1, self.h1, D_H1, self.w2b, D_H2, bias=self.p["b2"], relu=1, cbf=self.h2,
+        G(0, 1, n, D_H1, D_IN, x, D_IN, self.w1t, D_IN, bias=self.p["b1"], relu=1, cbf=self.h1, ldcb=D_H1)
+        G(0, 1, n, D_H2, D_H1, self.h1, D_H1, self.w2t, D_H1, bias=self.p["b2"], relu=1, cbf=self.h2,
           ldcb=D_H2)
 
     def train_step(self, n: int, y, x=None) -> None:
@@ -101,6 +110,7 @@ class Screener:
             hthedl.hth_adamw(self.p[k], self.g[k], self.m[k], self.v[k], pbf, self.p[k].numel(),
                              self.lr, self.b1, self.b2, self.eps, self.wd if k[0] == "w" else 0.0,
                              self.step_no)
+        self._transpose()
 
     def logits(self, n: int, x=None):
         self.forward(n, x)
@@ -133,11 +143,13 @@ class FeatureBatch:
         hthedl.hth_features(self.nodes, self.offsets, self.n_hyps, self.children, self.n_children,
                             self.hash, self.feat, self.bad)
 
-    def densify(self, row0: int, n: int, x, parents: "FeatureBatch" = None, parent_index=None) -> None:
+    def densify(self, row0: int, n: int, x, parents: "FeatureBatch" = None, parent_index=None,
+                context: int = 0) -> None:
         """Rows [row0, row0 + n) into x; with parents (and a device uint32
-        parent_index per hypothesis), minus each parent's features."""
+        parent_index per hypothesis), minus each parent's features, and with
+        context the parent's own features in the other half of the index."""
         if parents is None:
             hthedl.hth_densify(self.feat, self.offsets, row0, n, x)
         else:
             hthedl.hth_densify_delta(self.feat, self.offsets, row0, n, parents.feat, parents.offsets,
-                                     parent_index, x)
+                                     parent_index, x, parent_context=context)

@@ -191,9 +191,11 @@ class Refiner:
 
 def refinement_rounds(kb, evaluate: Callable[[Sequence[tuple]], np.ndarray], n_pos: int,
                       rounds: int, per_round: int, beam: int, rng: np.random.Generator,
-                      start: Sequence[tuple] = (("top",),), start_counts=None, with_parents: bool = False):
+                      start: Sequence[tuple] = (("top",),), start_counts=None, with_parents: bool = False,
+                      late_beam: int = 0):
     """A refinement trace: each round refines the previous round's top `beam`
-    hypotheses into `per_round` candidates and evaluates them exactly.
+    hypotheses into `per_round` candidates and evaluates them exactly (from
+    round rounds // 2 on, the top `late_beam` when it is set).
     Yields (round, candidates, counts), and with with_parents also the round's
     parents, each candidate's parent index among them and its parent's
     coverage (start_counts for the first round's parents)."""
@@ -231,7 +233,7 @@ def refinement_rounds(kb, evaluate: Callable[[Sequence[tuple]], np.ndarray], n_p
             yield r, cands, counts, list(parents), pidx, pcounts[pidx]
         else:
             yield r, cands, counts
-        top = top_indices(counts, n_pos, beam)
+        top = top_indices(counts, n_pos, late_beam if late_beam and r + 1 >= rounds // 2 else beam)
         parents = [cands[i] for i in top]
         pcounts = np.asarray(counts, dtype=np.int64)[top]
 

@@ -21,9 +21,11 @@ def test_recorded_traffic_is_void_when_the_kernel_changed(tmp_path, monkeypatch)
     import bench
     monkeypatch.setattr(bench, "TRAFFIC_DIR", str(tmp_path))
     f = tmp_path / "traffic_cX.json"
-    f.write_text(json.dumps({"source_sha": bench.source_sha(),
-                             "kernels": {"k_group": {"hbm_bytes_per_launch": 123.0}}}))
-    assert bench.recorded_traffic("k_group", "cX") == 123.0
-    f.write_text(json.dumps({"source_sha": "0" * 16, "kernels": {"k_group": {"hbm_bytes_per_launch": 123.0}}}))
-    assert bench.recorded_traffic("k_group", "cX") is None
-    assert bench.recorded_traffic("k_group", "missing") is None
+    kernels = {"k_group": {"hbm_bytes_per_launch": 123.0, "launches": 6},
+               "k_fill_rows": {"hbm_bytes_per_launch": 10.0, "launches": 3}}
+    f.write_text(json.dumps({"source_sha": bench.source_sha(), "steps": 3, "kernels": kernels}))
+    # per step: 123 x 6 / 3 + 10 x 3 / 3
+    assert bench.recorded_traffic(("k_group", "k_fill_rows", "k_absent"), "cX") == 256.0
+    f.write_text(json.dumps({"source_sha": "0" * 16, "steps": 3, "kernels": kernels}))
+    assert bench.recorded_traffic(("k_group",), "cX") is None
+    assert bench.recorded_traffic(("k_group",), "missing") is None

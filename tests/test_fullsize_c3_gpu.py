@@ -32,8 +32,23 @@ def test_c3_full_batch_against_oracle():
     say(f"[c3] {kb.n_edges:,} assertions, {H} hypotheses")
     enc = hthedl.encode_batch(hyps)
     eng = hthedl.Engine(kb, max_nodes=64, max_hyps=1)
+    # hash-consing on the device, with the batch's 256 blocks of hypotheses
+    # spread over every XCD: one role node per distinct role subexpression and
+    # one row per distinct threshold, exactly
+    from tests.test_devplan_gpu import _distinct
+    n_roles, n_thr, depth = _distinct(hyps)
+    d_nodes, d_offs, d_ch = eng.upload_batch(encoded=enc)
+    eng.ensure_plan_scratch(int(enc[0].shape[0]))
+    plan, _ = hthedl.hth_dplan_create(eng.handle, d_nodes, int(enc[0].shape[0]), d_offs, H, d_ch,
+                                      int(d_ch.shape[0]), eng.dp_scratch, eng.dp_scratch_bytes)
+    try:
+        info = hthedl.hth_dplan_stats(plan)
+    finally:
+        hthedl.hth_dplan_destroy(plan)
+    say(f"[c3] device plan {info}; distinct role subexpressions {n_roles}, thresholds {n_thr}, depth {depth}")
+    assert info["role_nodes"] == n_roles and info["thresholds"] == n_thr and info["levels"] == depth
     # the benchmark's step: one device-generated plan for the whole batch
-    dev = eng.eval_batch_device(encoded=enc)
+    dev = eng.eval_batch_device(device_batch=(d_nodes, d_offs, d_ch))
     # host-compiled plan, instance rows written for every hypothesis
     nodes, offs, ch = enc
     eng.ensure_workspace(hthedl.hth_batch_workspace_bytes(eng.handle, nodes, offs, ch))

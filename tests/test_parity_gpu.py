@@ -825,3 +825,77 @@ def test_value_roles_in_compiled_plans():
             assert np.array_equal(counts.cpu().numpy().view(np.uint32), want)
     finally:
         hthedl.hth_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("n", [200_003, 65_536])
+def test_short_row_passes(n):
+    """Shared passes that walk one subject per lane (directions whose rows are
+    all short, like the inverse of a role with sparse subjects and uniform
+    objects): equal to the oracle and to the sliced passes, at every T width,
+    compact or full T rows, with the short-row limit below, at and above the
+    longest row, through host-compiled and device-generated plans."""
+    cfg = synth.small_config(n=n, n_concepts=40, n_roles=3, s=1.6, cap=300, n_data=2, n_pos=n // 10,
+                             n_neg=n // 12, seed_index=2600 + n % 7, total_edges=n // 2)
+    kb = synth.make_kb(cfg)
+    rng = np.random.default_rng(26)
+    hyps = []
+    for _ in range(900):
+        r, inv = int(rng.integers(0, 3)), int(rng.integers(0, 2))
+        c = ("atom", int(rng.integers(0, 40)))
+        if rng.random() < 0.4:
+            r2 = int(rng.integers(0, 3))
+            c = ("exists", r2, 1 - inv, c) if rng.random() < 0.5 else ("or", c, ("atleast", 2, r2, inv, c))
+        op = rng.choice(["exists", "forall", "atleast", "atmost", "exactly"])
+        hyps.append((op, r, inv, c) if op in ("exists", "forall") else (op, int(rng.integers(0, 5)), r, inv, c))
+    want = Oracle(kb).coverages(hyps)
+    eng = hthedl.Engine(kb, max_hyps=len(hyps))
+    longest = [hthedl.hth_kb_max_degree(eng.handle, r, 1) for r in range(3)]
+    say(f"[parity] short rows n={n}: longest inverse rows {longest}, forward "
+        f"{[hthedl.hth_kb_max_degree(eng.handle, r, 0) for r in range(3)]}")
+    assert max(longest) <= 12
+    for limit in (0, min(longest) - 1, 12, 64):
+        for k, compact in ((8, 1), (64, 1), (32, 0)):
+            hthedl.hth_kb_set_tuning(eng.handle, group_min=1, group_k=k, t_compact=compact, short_rows=max(0, limit))
+            got = eng.eval_batch(hyps)
+            bad = np.flatnonzero((got != want).any(axis=1))
+            assert bad.size == 0, (limit, k, compact, hyps[bad[0]], got[bad[0]], want[bad[0]])
+            got = eng.eval_batch_device(hyps)
+            bad = np.flatnonzero((got != want).any(axis=1))
+            assert bad.size == 0, ("device", limit, k, compact, hyps[bad[0]], got[bad[0]], want[bad[0]])
+
+
+@pytest.mark.parametrize("short_rows", [0, 12])
+def test_role_roots_with_fused_coverage(short_rows):
+    """Hypotheses that are a single role restriction: where such a node is the
+    root of one hypothesis and read by no other node, its shared pass adds its
+    coverage directly (no row, no root region).  Covered: universal and
+    at-most roots (they hold every individual of the words without
+    assertions), roots repeated in the batch, roots that other hypotheses also
+    read, both directions of roles with sparse subjects, host-compiled and
+    device-generated plans; all against the oracle."""
+    n = 150_011
+    cfg = synth.small_config(n=n, n_concepts=32, n_roles=3, s=1.6, cap=500, n_data=2, n_pos=n // 9,
+                             n_neg=n // 11, seed_index=2700, total_edges=n // 3)
+    kb = synth.make_kb(cfg)
+    rng = np.random.default_rng(27)
+    hyps = []
+    for _ in range(1200):
+        r, inv = int(rng.integers(0, 3)), int(rng.integers(0, 2))
+        c = ("atom", int(rng.integers(0, 32)))
+        if rng.random() < 0.3:
+            c = ("and", c, ("exists", int(rng.integers(0, 3)), 1 - inv, ("atom", int(rng.integers(0, 32)))))
+        op = rng.choice(["exists", "forall", "atleast", "atmost"])
+        hyps.append((op, r, inv, c) if op in ("exists", "forall") else (op, int(rng.integers(0, 4)), r, inv, c))
+    hyps += hyps[:40]                                             # roots repeated
+    hyps += [("and", h, ("atom", 1)) for h in hyps[40:80]]        # roots read by other hypotheses
+    hyps += [("not", h) for h in hyps[80:100]]
+    want = Oracle(kb).coverages(hyps)
+    eng = hthedl.Engine(kb, max_hyps=len(hyps))
+    for k in (64, 16):
+        hthedl.hth_kb_set_tuning(eng.handle, group_min=2, group_k=k, short_rows=short_rows)
+        got = eng.eval_batch(hyps)
+        bad = np.flatnonzero((got != want).any(axis=1))
+        assert bad.size == 0, ("host", k, hyps[bad[0]], got[bad[0]], want[bad[0]])
+        got = eng.eval_batch_device(hyps)
+        bad = np.flatnonzero((got != want).any(axis=1))
+        assert bad.size == 0, ("device", k, hyps[bad[0]], got[bad[0]], want[bad[0]])

@@ -70,6 +70,27 @@ def test_gemm_epilogues(torch):
     np.testing.assert_allclose(c32.cpu().numpy(), want, rtol=1e-4, atol=1e-3)
 
 
+def test_gemm_nt_epilogue_and_transpose(torch):
+    """The forward layers' layout (B as [N][K] from hth_transpose_bf16): bias,
+    ReLU and the bf16 output, on ragged sizes with K not a multiple of the
+    64-wide k-tile; the transpose is exact."""
+    rng = np.random.default_rng(6)
+    M, N, K = 333, 200, 1000
+    a, b = rng.standard_normal((M, K)).astype(np.float32), rng.standard_normal((K, N)).astype(np.float32)
+    bias = rng.standard_normal(N).astype(np.float32)
+    A, B = bf16_dev(torch, a), bf16_dev(torch, b)
+    Bt = torch.empty((N, K), dtype=torch.bfloat16, device="cuda")
+    hthedl.hth_transpose_bf16(B, K, N, Bt)
+    np.testing.assert_array_equal(f64(torch, Bt), S.bf16(b).T)
+    c32 = torch.empty((M, N), dtype=torch.float32, device="cuda")
+    cbf = torch.empty((M, N), dtype=torch.bfloat16, device="cuda")
+    hthedl.hth_gemm_bf16(0, 1, M, N, K, A, K, Bt, K, bias=torch.from_numpy(bias).cuda(), relu=1,
+                         c32=c32, ldc=N, cbf=cbf, ldcb=N)
+    want = np.maximum(S.bf16(a) @ S.bf16(b) + bias, 0)
+    np.testing.assert_allclose(c32.cpu().numpy(), want, rtol=1e-4, atol=1e-4 * np.sqrt(K))
+    np.testing.assert_array_equal(f64(torch, cbf), S.bf16(c32.cpu().numpy()))
+
+
 def _feature_batch(torch, hyps):
     from paper_2412_00802_amd.screener import FeatureBatch
     nodes, offs, ch = hthedl.encode_batch(hyps)
@@ -112,6 +133,9 @@ def test_features_and_densify(torch):
     xd = torch.empty((len(kids), S.FEATURE_DIM), dtype=torch.bfloat16, device="cuda")
     kfb.densify(3, len(kids) - 3, xd, parents=pfb, parent_index=P)
     np.testing.assert_array_equal(f64(torch, xd)[:len(kids) - 3], S.delta_features(kids, parents, pidx)[3:])
+    kfb.densify(3, len(kids) - 3, xd, parents=pfb, parent_index=P, context=1)
+    np.testing.assert_array_equal(f64(torch, xd)[:len(kids) - 3],
+                                  S.delta_features(kids, parents, pidx, context=True)[3:])
 
 
 def test_features_flag_malformed_children(torch):

@@ -105,6 +105,20 @@ def test_delta_features_cancel_unchanged_subtrees():
     assert not S.delta_features([parent], [parent], [0]).any()
 
 
+def test_delta_features_with_parent_context():
+    """The context variant adds the parent's own subtree counts once, each at
+    its feature index with the top bit (2048) flipped, and nothing else."""
+    parent = ("and", ("atom", 1), ("exists", 0, 1, ("atom", 2)))
+    child = ("and", ("atom", 1), ("exists", 0, 1, ("atom", 2)), ("atom", 7))
+    d0 = S.delta_features([child], [parent], [0])[0]
+    d1 = S.delta_features([child], [parent], [0], context=True)[0]
+    want = np.zeros(S.FEATURE_DIM)
+    for _, f in S.subtree_features(parent):
+        want[f ^ 2048] += 1
+    np.testing.assert_array_equal(d1 - d0, want)
+    assert (d1 - d0).sum() == len(S.subtree_features(parent)) == 4
+
+
 def test_predicted_f1_from_log_removed_counts():
     """z = log(1 + removed): z = 0 keeps the base; z = log(1 + r) removes r
     (exactly, up to rounding); removals beyond the base clamp to 0."""
