@@ -25,17 +25,40 @@ __device__ __forceinline__ void transpose64(uint64_t (&a)[64]) {
   }
 }
 
+// Word `byte_off / 8` of a row whose address every lane holds: the address
+// goes to scalar registers and the load takes the lane's 32-bit byte offset.
+__device__ __forceinline__ uint64_t uniform_row_word(const uint64_t* row, uint32_t byte_off) {
+  typedef const char __attribute__((address_space(1)))* GlobalBytes;
+  const uint64_t v = reinterpret_cast<uint64_t>(row);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  const GlobalBytes base = (GlobalBytes)(((uint64_t)hi << 32) | lo);
+  return *(const uint64_t __attribute__((address_space(1)))*)(base + byte_off);
+}
+
 // T_g[y] bit j = bit(child_j, y) ^ neg_j for the groups of one launch; one lane
 // per 64-individual word, transposed in registers.  T rows are TW wide
 // (8 * sizeof(TW) >= every group's k).  A compact group keeps the rows of its
 // direction's objects only, at their ranks; words without objects are skipped.
+// The members' row addresses are resolved once per block into LDS, so that a
+// lane issues all of its member loads before it waits for any of them; slots
+// beyond k read member 0's row again and drop it.
 template <typename TW>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 k_tbuild(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __restrict__ members,
          TW* __restrict__ tarea, uint32_t tiles) {
   constexpr int KB = 8 * sizeof(TW);
+  __shared__ const uint64_t* s_row[KB];
+  __shared__ uint64_t s_flip[KB];
   const uint32_t g = blockIdx.x / tiles, tile = blockIdx.x % tiles;
   const GroupTask G = groups[g];
+  if (threadIdx.x < (uint32_t)KB) {
+    const uint32_t j = threadIdx.x, m = j < G.k ? j : 0u;   // every group has a member 0
+    const GroupMember M = members[G.first + m];
+    s_row[j] = row_ptr(kb, M.child_row);
+    s_flip[j] = M.neg ? ~0ull : 0ull;
+  }
+  __syncthreads();
   const uint32_t w = tile * 256 + threadIdx.x;
   if (w >= kb.W) return;
   const uint32_t rd = 2 * G.role + G.inv;
@@ -43,14 +66,9 @@ k_tbuild(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __re
   if (!omask) return;
   uint64_t a[64];
 #pragma unroll
-  for (int j = 0; j < 64; ++j) {
-    uint64_t v = 0;
-    if (j < KB && (uint32_t)j < G.k) {
-      const GroupMember M = members[G.first + j];
-      v = row_ptr(kb, M.child_row)[w] ^ (M.neg ? ~0ull : 0ull);
-    }
-    a[j] = v;
-  }
+  for (int j = 0; j < KB; ++j) a[j] = uniform_row_word(s_row[j], w * 8u);
+#pragma unroll
+  for (int j = 0; j < 64; ++j) a[j] = j < KB && (j == 0 || (uint32_t)j < G.k) ? a[j] ^ s_flip[j] : 0ull;
   transpose64(a);
   TW* T = tarea + G.t_off;
   if (!G.compact) {
