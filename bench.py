@@ -307,7 +307,7 @@ def main():
     ap.add_argument("--summary-by-grid", default=None, help="group these kernels' dispatches by grid")
     ap.add_argument("--summary-command", default="rocprofv3 {opts} -d OUT -o run -- python3 bench.py "
                     "--steps 2 --warmup 1 --plain 0 --cpu-budget 0 --c5 0 --c4-rounds 0 --graph 0 "
-                    "--other-steps 0 --no-profile --calibrate-copy")
+                    "--other-steps 0 --cache-rows 0 --no-profile --calibrate-copy")
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, args.summary_command, args.summary_out, args.summary_title,

@@ -308,11 +308,16 @@ k_region(DevKB kb, const RegionTask* __restrict__ tasks, const uint32_t* __restr
 }
 
 // The same regions with the value stack in registers (a shift register of
-// depth D, enough for most programs) and R words per lane, so that each leaf
-// puts R independent loads in flight per lane and no LDS limits occupancy.
-// Lane t handles words tile*256R + r*256 + t (coalesced per r).  Coverage is
-// reduced over the block and added with one atomic pair per block.
+// depth D, enough for most programs) and R words per lane, so that no LDS
+// limits occupancy.  The words of the program's first kRegLeaves leaves (and
+// the example words a covered root needs) are loaded before anything is
+// evaluated, so that a lane has all of them in flight at once; the program
+// then runs leaf by leaf from registers, and leaves beyond the first
+// kRegLeaves are loaded where they occur.  Lane t handles words
+// tile*256R + r*256 + t (coalesced per r).  Coverage is reduced over the block
+// and added with one atomic pair per block.
 constexpr int kRegDepth = 6;     // D: most stack entries a program may need
+constexpr int kRegLeaves = 3;    // leaves whose words are loaded up front
 template <int D, int R>
 __global__ void __launch_bounds__(256)
 k_region_reg(DevKB kb, const RegionTask* __restrict__ tasks, const uint32_t* __restrict__ code,
@@ -323,44 +328,84 @@ k_region_reg(DevKB kb, const RegionTask* __restrict__ tasks, const uint32_t* __r
   if (T.out_row == kNone && T.cover == kNone) return;   // a root whose coverage a shared pass adds
   const uint32_t tid = threadIdx.x;
   const uint32_t w0 = tile * (256 * R) + tid;
-  uint64_t top[R], st[D > 1 ? D - 1 : 1][R];
+  const uint32_t* prog = code + T.code_off;
+  const uint32_t len = T.code_len;
+  uint64_t lv[kRegLeaves][R], ex_p[R], ex_n[R];
+  {
+    uint32_t pc = 0;
 #pragma unroll
-  for (int r = 0; r < R; ++r) top[r] = 0;
-  for (uint32_t pc = 0; pc < T.code_len; ++pc) {
-    const uint32_t ins = code[T.code_off + pc];
-    const uint32_t op = ins & 15u, arg = ins >> 5;
-    if (op <= RP_BOT) {
-      if (pc) {                                   // push: shift the stack down
-#pragma unroll
-        for (int i = D - 2; i > 0; --i)
-#pragma unroll
-          for (int r = 0; r < R; ++r) st[i][r] = st[i - 1][r];
-#pragma unroll
-        for (int r = 0; r < R; ++r) st[0][r] = top[r];
-      }
-      if (op == RP_LEAF) {
-        const uint64_t* row = row_ptr(kb, arg);
-        const uint64_t negm = (ins & 16u) ? ~0ull : 0ull;
+    for (int j = 0; j < kRegLeaves; ++j) {
+      while (pc < len && (prog[pc] & 15u) != RP_LEAF) ++pc;
+      if (pc < len) {
+        const uint64_t* row = row_ptr(kb, prog[pc] >> 5);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const uint32_t w = w0 + r * 256;
-          top[r] = w < kb.W ? (row[w] ^ negm) : 0ull;
+          lv[j][r] = w < kb.W ? row[w] : 0ull;
         }
+        ++pc;
       } else {
 #pragma unroll
-        for (int r = 0; r < R; ++r) top[r] = op == RP_TOP ? ~0ull : 0ull;
+        for (int r = 0; r < R; ++r) lv[j][r] = 0;
       }
-    } else if (op == RP_NOT) {
+    }
+  }
 #pragma unroll
-      for (int r = 0; r < R; ++r) top[r] = ~top[r];
-    } else {                                      // pop b, top = top op b
-      const bool conj = op == RP_AND;
+  for (int r = 0; r < R; ++r) {
+    const uint32_t w = w0 + r * 256;
+    const bool c = T.cover != kNone && w < kb.W;
+    ex_p[r] = c ? kb.pos[w] : 0ull;
+    ex_n[r] = c ? kb.neg[w] : 0ull;
+  }
+  uint64_t top[R], st[D > 1 ? D - 1 : 1][R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) top[r] = conj ? (top[r] & st[0][r]) : (top[r] | st[0][r]);
+  for (int r = 0; r < R; ++r) top[r] = 0;
+  uint32_t pc = 0;
+  // segment j runs the program up to and including its j-th leaf; the last
+  // segment runs the rest, loading its leaves itself
 #pragma unroll
-      for (int i = 0; i + 1 < D - 1; ++i)
+  for (int j = 0; j <= kRegLeaves; ++j) {
+    while (pc < len) {
+      const uint32_t ins = prog[pc++];
+      const uint32_t op = ins & 15u, arg = ins >> 5;
+      if (op <= RP_BOT) {
+        if (pc > 1) {                             // push: shift the stack down
 #pragma unroll
-        for (int r = 0; r < R; ++r) st[i][r] = st[i + 1][r];
+          for (int i = D - 2; i > 0; --i)
+#pragma unroll
+            for (int r = 0; r < R; ++r) st[i][r] = st[i - 1][r];
+#pragma unroll
+          for (int r = 0; r < R; ++r) st[0][r] = top[r];
+        }
+        if (op == RP_LEAF) {
+          const uint64_t negm = (ins & 16u) ? ~0ull : 0ull;
+          if (j < kRegLeaves) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) top[r] = lv[j < kRegLeaves ? j : 0][r] ^ negm;
+            break;
+          }
+          const uint64_t* row = row_ptr(kb, arg);
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const uint32_t w = w0 + r * 256;
+            top[r] = w < kb.W ? (row[w] ^ negm) : 0ull;
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r) top[r] = op == RP_TOP ? ~0ull : 0ull;
+        }
+      } else if (op == RP_NOT) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) top[r] = ~top[r];
+      } else {                                    // pop b, top = top op b
+        const bool conj = op == RP_AND;
+#pragma unroll
+        for (int r = 0; r < R; ++r) top[r] = conj ? (top[r] & st[0][r]) : (top[r] | st[0][r]);
+#pragma unroll
+        for (int i = 0; i + 1 < D - 1; ++i)
+#pragma unroll
+          for (int r = 0; r < R; ++r) st[i][r] = st[i + 1][r];
+      }
     }
   }
   uint32_t p = 0, q = 0;
@@ -374,10 +419,8 @@ k_region_reg(DevKB kb, const RegionTask* __restrict__ tasks, const uint32_t* __r
     if (w >= kb.W) v = 0;
     else if (w == kb.W - 1) v &= kb.tail;
     if (out && w < kb.S) out[w] = v;
-    if (T.cover != kNone && w < kb.W) {
-      p += (uint32_t)__popcll(v & kb.pos[w]);
-      q += (uint32_t)__popcll(v & kb.neg[w]);
-    }
+    p += (uint32_t)__popcll(v & ex_p[r]);
+    q += (uint32_t)__popcll(v & ex_n[r]);
   }
   if (T.cover != kNone) {
     p = wave_sum(p);

@@ -36,6 +36,12 @@ __device__ __forceinline__ uint64_t uniform_row_word(const uint64_t* row, uint32
   return *(const uint64_t __attribute__((address_space(1)))*)(base + byte_off);
 }
 
+// A 32-bit word that every lane reads at the same address, through the
+// scalar cache: its wait does not also wait for the wave's vector stores.
+__device__ __forceinline__ uint32_t scalar_u32(const uint32_t* p) {
+  return *(const __attribute__((address_space(4))) uint32_t*)p;
+}
+
 // T_g[y] bit j = bit(child_j, y) ^ neg_j for the groups of one launch; one lane
 // per 64-individual word, transposed in registers.  T rows are TW wide
 // (8 * sizeof(TW) >= every group's k).  A compact group keeps the rows of its
@@ -254,10 +260,11 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
   const TW* T = tarea + G->t_off;
   const size_t roff = (size_t)G->role * (kb.N + 1);
   const uint32_t* off = (G->inv ? kb.inv_off : kb.fwd_off) + roff;
+  const uint32_t off_end = off[kb.N];
   // a compact group reads each assertion's object rank instead of its object
   const int32_t* tg = (G->compact ? (G->inv ? kb.ctg_inv : kb.ctg_fwd) : (G->inv ? kb.inv_tg : kb.fwd_tg)) +
                       kb.role_base[G->role];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   uint32_t* ro = s_ro[wv];
   TW (*pl)[R] = s_pl[wv];
   TW acc[kGroupMaxCount + 1];
@@ -280,18 +287,20 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
   struct Rows {
     uint32_t lo[MW], hi[MW], wd[MW];
   };
+  // loads without branches around them (clamped indices, results masked
+  // after), so that a wave has all of an iteration's loads in flight at once
   auto fetch = [&](uint32_t it, Rows& q) {
+    uint32_t w[MW];
+#pragma unroll
+    for (int m = 0; m < MW; ++m) w[m] = scalar_u32(words + min(it * MW + m, n_words - 1));
 #pragma unroll
     for (int m = 0; m < MW; ++m) {
-      const uint32_t idx = it * MW + m;
-      q.wd[m] = kNone;
-      q.lo[m] = q.hi[m] = 0;
-      if (it < n_iter && idx < n_words) {
-        const uint32_t w = words[idx], x = w * 64 + lane;
-        q.wd[m] = w;
-        q.lo[m] = off[x < kb.N ? x : kb.N];
-        q.hi[m] = x < kb.N ? off[x + 1] : q.lo[m];
-      }
+      const bool in = it < n_iter && it * MW + m < n_words;
+      const uint32_t x = w[m] * 64 + lane, xc = min(x, kb.N - 1);
+      const uint32_t lo = off[xc], hi = off[xc + 1];
+      q.wd[m] = in ? w[m] : kNone;   // lo and hi of an entry past the list are never read
+      q.lo[m] = x < kb.N ? lo : off_end;
+      q.hi[m] = x < kb.N ? hi : off_end;
     }
   };
   auto words_in = [&](uint32_t it) { return it < n_iter ? min((uint32_t)MW, n_words - it * MW) : 0u; };
@@ -494,7 +503,7 @@ k_group_short(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember*
   const uint32_t* off = (G->inv ? kb.inv_off : kb.fwd_off) + (size_t)G->role * (kb.N + 1);
   const int32_t* tg = (G->compact ? (G->inv ? kb.ctg_inv : kb.ctg_fwd) : (G->inv ? kb.inv_tg : kb.fwd_tg)) +
                       kb.role_base[G->role];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   TW acc[kGroupMaxCount + 1];
 #pragma unroll
   for (int v = 0; v <= (int)kGroupMaxCount; ++v) acc[v] = (TW)G->acc[v];
@@ -505,21 +514,39 @@ k_group_short(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember*
   const uint32_t* words = kb.words + (size_t)(2 * G->role + G->inv) * kb.W;
   const uint32_t n_words = G->n_words;
   const uint32_t n_iter = (n_words + MW - 1) / MW;
+  // the words of an iteration are stored once the next iteration's loads have
+  // been consumed: a wait on a load also waits for every store issued before
+  // it, so stores issued an iteration earlier have had time to complete
+  uint64_t po[MW];
+  uint32_t pwd[MW];
+#pragma unroll
+  for (int m = 0; m < MW; ++m) pwd[m] = kNone;
+  auto store = [&](const uint64_t (&o)[MW], const uint32_t (&wd)[MW]) {
+    if (!my_out || wd[0] == kNone) return;
+    if (wd[MW - 1] != kNone && wd[MW - 1] - wd[0] == MW - 1 && wd[0] % MW == 0) {
+      ulonglong2* q = reinterpret_cast<ulonglong2*>(my_out + wd[0]);
+#pragma unroll
+      for (int i = 0; i < MW / 2; ++i) q[i] = make_ulonglong2(o[2 * i], o[2 * i + 1]);
+    } else {
+#pragma unroll
+      for (int m = 0; m < MW; ++m)
+        if (wd[m] != kNone) my_out[wd[m]] = o[m];
+    }
+  };
   for (uint32_t it = b * nw + wv; it < n_iter; it += bpg * nw) {
+    // loads without branches around them (clamped indices, results masked
+    // after), so that all of them are in flight at once
     uint32_t wd[MW], e[MW], ee[MW];
 #pragma unroll
+    for (int m = 0; m < MW; ++m) wd[m] = scalar_u32(words + min(it * MW + m, n_words - 1));
+#pragma unroll
     for (int m = 0; m < MW; ++m) {
-      const uint32_t idx = it * MW + m;
-      wd[m] = kNone;
-      e[m] = ee[m] = 0;
-      if (idx < n_words) {
-        const uint32_t w = words[idx], x = w * 64 + lane;
-        wd[m] = w;
-        if (x < kb.N) {
-          e[m] = off[x];
-          ee[m] = off[x + 1];
-        }
-      }
+      const uint32_t x = wd[m] * 64 + lane, xc = min(x, kb.N - 1);
+      e[m] = off[xc];
+      ee[m] = off[xc + 1];
+      const bool in = it * MW + m < n_words && x < kb.N;
+      if (!in) ee[m] = e[m];
+      if (it * MW + m >= n_words) wd[m] = kNone;
     }
     Planes<TW> p[MW];
 #pragma unroll
@@ -531,36 +558,32 @@ k_group_short(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember*
 #pragma unroll
       for (int m = 0; m < MW; ++m) open |= e[m] < ee[m];
       if (!__ballot(open)) break;
+      // the loads of a step go out together (a closed row reads entry 0 of
+      // the role and T row 0, and drops them)
       int32_t t[MW];
 #pragma unroll
-      for (int m = 0; m < MW; ++m) t[m] = e[m] < ee[m] ? tg[e[m]] : -1;
+      for (int m = 0; m < MW; ++m) t[m] = tg[e[m] < ee[m] ? e[m] : 0u];
+      TW v[MW];
 #pragma unroll
-      for (int m = 0; m < MW; ++m)
-        if (t[m] >= 0) {
-          planes_inc(p[m], T[(uint32_t)t[m]]);
-          ++e[m];
-        }
+      for (int m = 0; m < MW; ++m) v[m] = T[e[m] < ee[m] ? (uint32_t)t[m] : 0u];
+#pragma unroll
+      for (int m = 0; m < MW; ++m) {
+        const bool o = e[m] < ee[m];
+        planes_inc(p[m], o ? v[m] : (TW)0);
+        e[m] += o;
+      }
     }
-    uint64_t o[MW];
+    store(po, pwd);
 #pragma unroll
     for (int m = 0; m < MW; ++m) {
       TW rv = accept(p[m], acc);
       if (wd[m] == kNone || wd[m] * 64 + lane >= kb.N) rv = 0;
-      o[m] = wave_transpose64((uint64_t)rv, lane);
-      if (cv.h != kNone && wd[m] != kNone) cover_word(cv, kb, wd[m], o[m]);
-    }
-    if (my_out) {
-      if (wd[MW - 1] != kNone && wd[MW - 1] - wd[0] == MW - 1 && wd[0] % MW == 0) {
-        ulonglong2* q = reinterpret_cast<ulonglong2*>(my_out + wd[0]);
-#pragma unroll
-        for (int i = 0; i < MW / 2; ++i) q[i] = make_ulonglong2(o[2 * i], o[2 * i + 1]);
-      } else {
-#pragma unroll
-        for (int m = 0; m < MW; ++m)
-          if (wd[m] != kNone) my_out[wd[m]] = o[m];
-      }
+      po[m] = wave_transpose64((uint64_t)rv, lane);
+      pwd[m] = wd[m];
+      if (cv.h != kNone && wd[m] != kNone) cover_word(cv, kb, wd[m], po[m]);
     }
   }
+  store(po, pwd);
   cover_finish(cv, kb, b * nw + wv, bpg * nw, lane);
 }
 
