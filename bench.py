@@ -173,7 +173,8 @@ def summarize_trace(kt_dir: str, command: str, out_md: str, title: str, by_grid:
                 key = (kernel_name(r["Kernel_Name"]), int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"]),
                        int(r["Grid_Size_Y"]))
                 groups.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
-        lines += ["", f"Dispatches of `{by_grid}` by grid (workgroups in x, y; one 128 x 128 output tile each):", "",
+        tile = "; one 128 x 128 output tile each" if "gemm" in by_grid else ""
+        lines += ["", f"Dispatches of `{by_grid}` by grid (workgroups in x, y{tile}):", "",
                   "| kernel | grid x, y | calls | avg us | total ms |", "|---|---|---|---|---|"]
         for (name, gx, gy), v in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
             lines.append(f"| {name} | {gx}, {gy} | {len(v)} | {sum(v) / len(v):.1f} | {sum(v) / 1e3:.2f} |")
