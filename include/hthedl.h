@@ -576,7 +576,9 @@ hth_status hth_head_score(const float* z, int Bn, float n_pos, float n_neg, cons
 hth_status hth_head_backward(const uint16_t* h, int Bn, int Kd, const float* w, const float* dz,
                              float* dw, uint16_t* dh, void* stream);
 
-/* out[n] = sum over m of d[m][n] (d bf16 if is_bf16, else fp32; [M][N]). */
+/* out[n] = sum over m of d[m][n] (d bf16 if is_bf16, else fp32; [M][N]),
+ * accumulated in fp32 in an order fixed by (M, N) alone, so repeated calls give
+ * identical bits.  HTH_E_RANGE for negative sizes. */
 hth_status hth_colsum(const void* d, int is_bf16, int M, int N, float* out, void* stream);
 
 /* AdamW (decoupled weight decay) on fp32 parameters p with gradient g and

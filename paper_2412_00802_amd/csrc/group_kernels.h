@@ -41,6 +41,9 @@ __device__ __forceinline__ uint64_t uniform_row_word(const uint64_t* row, uint32
 __device__ __forceinline__ uint32_t scalar_u32(const uint32_t* p) {
   return *(const __attribute__((address_space(4))) uint32_t*)p;
 }
+__device__ __forceinline__ uint64_t scalar_u64(const uint64_t* p) {
+  return *(const __attribute__((address_space(4))) uint64_t*)p;
+}
 
 // T_g[y] bit j = bit(child_j, y) ^ neg_j for the groups of one launch; one lane
 // per 64-individual word, transposed in registers.  T rows are TW wide
@@ -176,7 +179,7 @@ __device__ __forceinline__ Cover cover_of(const GroupTask* G, const GroupMember*
 }
 __device__ __forceinline__ void cover_word(Cover& c, const DevKB& kb, uint32_t w, uint64_t v) {
   w = __builtin_amdgcn_readfirstlane(w);   // the same word on every lane: scalar loads
-  const uint64_t P = kb.pos[w], N = kb.neg[w];
+  const uint64_t P = scalar_u64(kb.pos + w), N = scalar_u64(kb.neg + w);
   c.p += (uint32_t)__popcll(v & P) - (c.z ? (uint32_t)__popcll(P) : 0u);
   c.q += (uint32_t)__popcll(v & N) - (c.z ? (uint32_t)__popcll(N) : 0u);
 }

@@ -457,20 +457,23 @@ k_head_backward(const __bf16* __restrict__ h, int Bn, int Kd, const float* __res
 }
 
 // out[n] = sum_m d[m][n] (bias gradients), one thread per column
-__global__ void k_colsum_bf16(const __bf16* __restrict__ d, int M, int N, float* __restrict__ out) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
+// Column sums of a row-major M x N matrix: a block per 64 columns, lane c of
+// each of its waves on column c (one coalesced row segment per wave and
+// step), wave w on rows w, w + 4, ...; the four waves' sums are added in a
+// fixed order, so the result does not depend on scheduling.
+template <typename T>
+__global__ void __launch_bounds__(256) k_colsum(const T* __restrict__ d, int M, int N, float* __restrict__ out) {
+  __shared__ float part[4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + lane;
   float s = 0.f;
-  for (int m = 0; m < M; ++m) s += (float)d[(size_t)m * N + n];
-  out[n] = s;
-}
-
-__global__ void k_colsum_f32(const float* __restrict__ d, int M, int N, float* __restrict__ out) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
-  float s = 0.f;
-  for (int m = 0; m < M; ++m) s += d[(size_t)m * N + n];
-  out[n] = s;
+  if (n < N) {
+#pragma unroll 8
+    for (int m = wv; m < M; m += 4) s += (float)d[(size_t)m * N + n];
+  }
+  part[wv][lane] = s;
+  __syncthreads();
+  if (wv == 0 && n < N) out[n] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
 }
 
 // AdamW on fp32 master weights (decoupled weight decay), with a bf16 copy
@@ -649,13 +652,15 @@ extern "C" hth_status hth_head_backward(const uint16_t* h, int Bn, int Kd, const
 }
 
 extern "C" hth_status hth_colsum(const void* d, int is_bf16, int M, int N, float* out, void* stream) {
-  if (!d || !out) return fail(HTH_E_INVALID, "NULL argument");
+  if (M < 0 || N < 0) return fail(HTH_E_RANGE, "negative matrix size");
+  if (!N) return HTH_OK;
+  if (!out || (M && !d)) return fail(HTH_E_INVALID, "NULL argument");
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (is_bf16)
-    hipLaunchKernelGGL(k_colsum_bf16, dim3((N + 255) / 256), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_colsum<__bf16>, dim3((N + 63) / 64), dim3(256), 0, st,
                        static_cast<const __bf16*>(d), M, N, out);
   else
-    hipLaunchKernelGGL(k_colsum_f32, dim3((N + 255) / 256), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_colsum<float>, dim3((N + 63) / 64), dim3(256), 0, st,
                        static_cast<const float*>(d), M, N, out);
   HTH_HIP(hipGetLastError());
   return HTH_OK;

@@ -200,6 +200,27 @@ def test_adamw_matches_reference(torch):
     np.testing.assert_array_equal(f64(torch, pb), S.bf16(P.cpu().numpy()))
 
 
+@pytest.mark.parametrize("M,N", [(1024, 1024), (1000, 130), (7, 2), (1, 65), (0, 3)])
+def test_colsum_matches_reference(torch, M, N):
+    """Column sums (bias gradients) of bf16 and fp32 matrices, against fp64
+    sums of the same values, with ragged column tiles and row counts that
+    are not a multiple of the four waves; two calls give identical bits."""
+    rng = np.random.default_rng(M * 31 + N)
+    a = rng.standard_normal((M, N)).astype(np.float32)
+    for is_bf16 in (1, 0):
+        d = torch.from_numpy(a).cuda()
+        if is_bf16:
+            d = d.to(torch.bfloat16)
+        ref = d.float().cpu().numpy().astype(np.float64).sum(axis=0)
+        out = torch.full((N,), 7.0, dtype=torch.float32, device="cuda")
+        hthedl.hth_colsum(d, is_bf16, M, N, out)
+        got = out.cpu().numpy()
+        np.testing.assert_allclose(got, ref, rtol=1e-5, atol=1e-4 * max(1.0, np.sqrt(M)))
+        again = torch.empty_like(out)
+        hthedl.hth_colsum(d, is_bf16, M, N, again)
+        np.testing.assert_array_equal(again.cpu().numpy(), got)
+
+
 @pytest.mark.parametrize("n,k", [(1, 1), (1000, 10), (100003, 2000), (50000, 50000)])
 def test_topk(torch, n, k):
     rng = np.random.default_rng(n + k)
