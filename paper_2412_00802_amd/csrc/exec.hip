@@ -1009,8 +1009,8 @@ hth_status launch_group_chunk(Launcher& L, const DevKB& d, const GroupTask* grou
   const bool multi = nwd > 0 && ew < 96.0 * nwd;
   if (host[g0].short_rows) {   // every row short: a lane per subject, one pass
     return L.run(HTH_K_GROUP_SHORT, gb, [&] {
-      hipLaunchKernelGGL((k_group_short<TW, kShortWords>), dim3(nblocks), dim3(256), 0, L.st, d, groups + g0,
-                         members, T, bpg, xslots);
+      hipLaunchKernelGGL((k_group_short<TW, kShortWords, kShortSub>), dim3(nblocks), dim3(256), 0, L.st, d,
+                         groups + g0, members, T, bpg, xslots);
     });
   }
   uint64_t seg_rows;

@@ -483,15 +483,26 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
 // subject's row alone, all MW rows in step.  A lane's counters are its own
 // subject's, so the words' assertion ranges are not sliced and nothing is
 // scanned across lanes.  The members' predicates are transposed into one word
-// per member; MW consecutive, aligned words go out as one run per member.
-constexpr int kShortWords = 4;
-template <typename TW, int MW>
+// per member.  A wave takes SUB * MW consecutive entries as SUB such
+// iterations and keeps the members' words in LDS; a member's SUB * MW
+// consecutive, aligned words then go out as one segment of a 128-byte line,
+// written by SUB * MW / 2 lanes with 16-byte stores (so that a store
+// instruction touches 64 / (SUB * MW / 2) lines, not 64).  The staged words of
+// a wave's previous entries go out after its next loads: a wait on a load also
+// waits for every store issued before it.
+constexpr int kShortWords = 4;   // MW
+constexpr int kShortSub = 2;     // SUB
+template <typename TW, int MW, int SUB>
 __global__ void __launch_bounds__(256)
 k_group_short(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __restrict__ members,
               const TW* __restrict__ tarea, uint32_t bpg, const uint32_t* __restrict__ xslots) {
-  static_assert(MW % 2 == 0, "runs are stored two words at a time");
+  constexpr int SW = SUB * MW;            // words per wave iteration
+  constexpr int LPM = SW / 2;             // lanes per member line (16 bytes each)
+  static_assert(SW * 8 <= 128 && 64 % LPM == 0, "a member's words of one iteration lie in one 128-byte line");
+  __shared__ uint64_t s_out[4][64][SW + 1];   // + 1 word: rows fall on different banks
+  __shared__ uint64_t* s_dst[64];
   uint32_t g, b;
-  if (xslots) {   // one XCD per group, as in k_group
+  if (xslots) {
     const uint32_t x = blockIdx.x & 7, j = blockIdx.x >> 3;
     g = xslots[(j / bpg) * 8 + x];
     b = j % bpg;
@@ -512,81 +523,94 @@ k_group_short(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember*
   for (int v = 0; v <= (int)kGroupMaxCount; ++v) acc[v] = (TW)G->acc[v];
   const uint32_t my_row = (uint32_t)lane < k ? members[G->first + lane].out_row : kNone;
   uint64_t* const my_out = my_row != kNone ? out_ptr(kb, my_row) : nullptr;
+  if (threadIdx.x < 64) s_dst[threadIdx.x] = my_out;
+  __syncthreads();
   Cover cv = cover_of(G, members, k, lane);
   const uint32_t nw = blockDim.x >> 6;
   const uint32_t* words = kb.words + (size_t)(2 * G->role + G->inv) * kb.W;
   const uint32_t n_words = G->n_words;
-  const uint32_t n_iter = (n_words + MW - 1) / MW;
-  // the words of an iteration are stored once the next iteration's loads have
-  // been consumed: a wait on a load also waits for every store issued before
-  // it, so stores issued an iteration earlier have had time to complete
-  uint64_t po[MW];
-  uint32_t pwd[MW];
+  const uint32_t n_super = (n_words + SW - 1) / SW;
+  uint64_t (*so)[SW + 1] = s_out[wv];
+  uint32_t pw[SW];   // words staged in LDS, not yet written
 #pragma unroll
-  for (int m = 0; m < MW; ++m) pwd[m] = kNone;
-  auto store = [&](const uint64_t (&o)[MW], const uint32_t (&wd)[MW]) {
-    if (!my_out || wd[0] == kNone) return;
-    if (wd[MW - 1] != kNone && wd[MW - 1] - wd[0] == MW - 1 && wd[0] % MW == 0) {
-      ulonglong2* q = reinterpret_cast<ulonglong2*>(my_out + wd[0]);
+  for (int i = 0; i < SW; ++i) pw[i] = kNone;
+  auto flush = [&]() {
+    if (pw[0] == kNone) return;
+    if (pw[SW - 1] != kNone && pw[SW - 1] - pw[0] == SW - 1 && pw[0] % SW == 0) {
+      const int part = lane % LPM;
 #pragma unroll
-      for (int i = 0; i < MW / 2; ++i) q[i] = make_ulonglong2(o[2 * i], o[2 * i + 1]);
-    } else {
+      for (int r = 0; r < LPM; ++r) {
+        const int j = r * (64 / LPM) + lane / LPM;
+        uint64_t* dst = s_dst[j];
+        if (dst) {
+          ulonglong2* q = reinterpret_cast<ulonglong2*>(dst + pw[0]) + part;
+          *q = make_ulonglong2(so[j][2 * part], so[j][2 * part + 1]);
+        }
+      }
+    } else if (my_out) {
 #pragma unroll
-      for (int m = 0; m < MW; ++m)
-        if (wd[m] != kNone) my_out[wd[m]] = o[m];
+      for (int i = 0; i < SW; ++i)
+        if (pw[i] != kNone) my_out[pw[i]] = so[lane][i];
     }
   };
-  for (uint32_t it = b * nw + wv; it < n_iter; it += bpg * nw) {
-    // loads without branches around them (clamped indices, results masked
-    // after), so that all of them are in flight at once
-    uint32_t wd[MW], e[MW], ee[MW];
+  for (uint32_t si = b * nw + wv; si < n_super; si += bpg * nw) {
 #pragma unroll
-    for (int m = 0; m < MW; ++m) wd[m] = scalar_u32(words + min(it * MW + m, n_words - 1));
+    for (int sub = 0; sub < SUB; ++sub) {
+      const uint32_t it = si * SUB + sub;
+      uint32_t wd[MW], e[MW], ee[MW];
 #pragma unroll
-    for (int m = 0; m < MW; ++m) {
-      const uint32_t x = wd[m] * 64 + lane, xc = min(x, kb.N - 1);
-      e[m] = off[xc];
-      ee[m] = off[xc + 1];
-      const bool in = it * MW + m < n_words && x < kb.N;
-      if (!in) ee[m] = e[m];
-      if (it * MW + m >= n_words) wd[m] = kNone;
-    }
-    Planes<TW> p[MW];
-#pragma unroll
-    for (int m = 0; m < MW; ++m) p[m] = Planes<TW>{0, 0, 0, 0};
-    // step d reads assertion d of every row still open (rows hold at most
-    // short_rows assertions, so the wave leaves after that many steps)
-    for (;;) {
-      bool open = false;
-#pragma unroll
-      for (int m = 0; m < MW; ++m) open |= e[m] < ee[m];
-      if (!__ballot(open)) break;
-      // the loads of a step go out together (a closed row reads entry 0 of
-      // the role and T row 0, and drops them)
-      int32_t t[MW];
-#pragma unroll
-      for (int m = 0; m < MW; ++m) t[m] = tg[e[m] < ee[m] ? e[m] : 0u];
-      TW v[MW];
-#pragma unroll
-      for (int m = 0; m < MW; ++m) v[m] = T[e[m] < ee[m] ? (uint32_t)t[m] : 0u];
+      for (int m = 0; m < MW; ++m) wd[m] = scalar_u32(words + min(it * MW + m, n_words - 1));
 #pragma unroll
       for (int m = 0; m < MW; ++m) {
-        const bool o = e[m] < ee[m];
-        planes_inc(p[m], o ? v[m] : (TW)0);
-        e[m] += o;
+        const uint32_t x = wd[m] * 64 + lane, xc = min(x, kb.N - 1);
+        e[m] = off[xc];
+        ee[m] = off[xc + 1];
+        const bool in = it * MW + m < n_words && x < kb.N;
+        if (!in) ee[m] = e[m];
+        if (it * MW + m >= n_words) wd[m] = kNone;
+      }
+      Planes<TW> p[MW];
+#pragma unroll
+      for (int m = 0; m < MW; ++m) p[m] = Planes<TW>{0, 0, 0, 0};
+      for (;;) {
+        bool open = false;
+#pragma unroll
+        for (int m = 0; m < MW; ++m) open |= e[m] < ee[m];
+        if (!__ballot(open)) break;
+        int32_t t[MW];
+#pragma unroll
+        for (int m = 0; m < MW; ++m) t[m] = tg[e[m] < ee[m] ? e[m] : 0u];
+        TW v[MW];
+#pragma unroll
+        for (int m = 0; m < MW; ++m) v[m] = T[e[m] < ee[m] ? (uint32_t)t[m] : 0u];
+#pragma unroll
+        for (int m = 0; m < MW; ++m) {
+          const bool o = e[m] < ee[m];
+          planes_inc(p[m], o ? v[m] : (TW)0);
+          e[m] += o;
+        }
+      }
+      if (sub == 0) {   // the previous entries' words, after this iteration's loads
+        flush();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+#pragma unroll
+      for (int m = 0; m < MW; ++m) {
+        TW rv = accept(p[m], acc);
+        if (wd[m] == kNone || wd[m] * 64 + lane >= kb.N) rv = 0;
+        const uint64_t o = wave_transpose64((uint64_t)rv, lane);
+        so[lane][sub * MW + m] = o;
+        pw[sub * MW + m] = wd[m];
+        if (cv.h != kNone && wd[m] != kNone) cover_word(cv, kb, wd[m], o);
       }
     }
-    store(po, pwd);
-#pragma unroll
-    for (int m = 0; m < MW; ++m) {
-      TW rv = accept(p[m], acc);
-      if (wd[m] == kNone || wd[m] * 64 + lane >= kb.N) rv = 0;
-      po[m] = wave_transpose64((uint64_t)rv, lane);
-      pwd[m] = wd[m];
-      if (cv.h != kNone && wd[m] != kNone) cover_word(cv, kb, wd[m], po[m]);
-    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  store(po, pwd);
+  flush();
   cover_finish(cv, kb, b * nw + wv, bpg * nw, lane);
 }
 
