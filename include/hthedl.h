@@ -212,7 +212,9 @@ hth_status hth_kb_max_degree(hth_kb kb, uint32_t role, uint32_t inv, uint32_t* o
  *   row width 8/16/32/64 bits);
  * xcd_local: 1 = keep each shared pass on one XCD (its L2 holds the pass's
  *   transposed child rows);
- * t_budget_mb: transposed child rows resident per launch (MiB);
+ * t_budget_mb: most transposed child rows one launch of shared passes builds
+ *   and reads (MiB; default 1024).  A plan's workspace holds the most any of
+ *   its launches uses, not the budget;
  * unroll: assertions in flight per lane in passes over directions with many
  *   assertions per word (8 or 16; sparse directions always use 8);
  * region_reg: 1, 2 or 4 = boolean regions whose value stack fits six entries

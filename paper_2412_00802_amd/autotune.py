@@ -32,7 +32,7 @@ def signature(eng) -> str:
 
 def candidates(n_individuals: int) -> List[Dict[str, int]]:
     """Each T width (8..64 bits) with: XCD-local passes and a budget of one
-    group per XCD (and the 64 MiB default), both unrolls; chip-wide passes
+    group per XCD, 64 MiB and the 1 GiB default, both unrolls; chip-wide passes
     with one and four groups per launch; one run sharing passes from a single
     node up; the region kernel at one and four words per lane; and the push
     threshold of single existential restrictions at 0 (never) and 8%.  Widths
@@ -42,18 +42,18 @@ def candidates(n_individuals: int) -> List[Dict[str, int]]:
         t_mb = max(1, -(-(n_individuals * w) // (1 << 20)))
         if t_mb > 1024:
             continue
-        for budget in sorted({max(64, 8 * t_mb), 64}):
+        for budget in sorted({max(64, 8 * t_mb), 64, 1024}):
             for unroll in (8, 16):
                 out.append(dict(group_min=2, group_k=k, xcd_local=1, t_budget_mb=max(budget, t_mb),
                                 unroll=unroll))
         for budget in sorted({t_mb, 4 * t_mb}):
             out.append(dict(group_min=2, group_k=k, xcd_local=0, t_budget_mb=budget, unroll=16))
     widest = max((c["group_k"] for c in out), default=8)
-    out.append(dict(group_min=1, group_k=widest, xcd_local=1, t_budget_mb=64, unroll=16))
+    out.append(dict(group_min=1, group_k=widest, xcd_local=1, t_budget_mb=1024, unroll=16))
     # words per lane of the region kernel (the others keep the default, 2)
-    out += [dict(group_min=2, group_k=widest, xcd_local=1, t_budget_mb=64, unroll=16, region_reg=r) for r in (1, 4)]
+    out += [dict(group_min=2, group_k=widest, xcd_local=1, t_budget_mb=1024, unroll=16, region_reg=r) for r in (1, 4)]
     # the push/pull density switch of single existential restrictions (default 2%)
-    out += [dict(group_min=2, group_k=widest, xcd_local=1, t_budget_mb=64, unroll=16, push_pct=p) for p in (0, 8)]
+    out += [dict(group_min=2, group_k=widest, xcd_local=1, t_budget_mb=1024, unroll=16, push_pct=p) for p in (0, 8)]
     for c in out:
         c.setdefault("region_reg", 2)
         c.setdefault("push_pct", 2)

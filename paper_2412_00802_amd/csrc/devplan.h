@@ -948,7 +948,9 @@ hth_status dp_schedule(hth_dplan_s& p, const std::vector<uint32_t>& bk, std::vec
   p.o_part = area((size_t)p.max_nhb * 4);
   p.o_grp = area((size_t)p.n_groups * sizeof(GroupTask));
   p.o_mem = area((size_t)p.n_members * sizeof(GroupMember));
-  p.o_tarea = area(p.n_groups ? t_area_bytes(kb) : 0);
+  size_t t_bytes = 0;   // the T area: the most one chunk of the plan uses
+  for (uint32_t L = 0; L < S.levels; ++L) t_bytes = std::max(t_bytes, chunks_t_bytes(kb, p.lv_groups[L], p.lv_chunks[L]));
+  p.o_tarea = area(t_bytes);
   p.o_gpart = area(gpart);
   p.o_slot = area(((size_t)S.n_slots + S.n_thr + 1) * kb.S * 8);
   p.need = at;

@@ -723,6 +723,18 @@ std::vector<GroupChunk> chunk_groups(const hth_kb_s& kb, std::vector<GroupTask>&
   return out;
 }
 
+// T bytes the chunks of one level use at most: a chunk's rows run from its
+// first group's t_off (0) to the end of its last group's, at the chunk's width.
+inline size_t chunks_t_bytes(const hth_kb_s& kb, const std::vector<GroupTask>& gs,
+                             const std::vector<GroupChunk>& cs) {
+  size_t most = 0;
+  for (const GroupChunk& c : cs) {
+    const GroupTask& last = gs[c.first + c.n - 1];
+    most = std::max<size_t>(most, (size_t)(last.t_off + t_rows(kb, last)) * c.wb);
+  }
+  return align_up(most, 256);
+}
+
 // Target segments of a chunk: its passes cover T rows in ranges of at most
 // t_segment bytes (at the chunk's T width), when that takes 2..kMaxSegments
 // passes; otherwise one pass over all rows.  seg_rows: T rows per pass.
@@ -1117,6 +1129,19 @@ size_t idset_bytes(const Plan& P) {
 }
 
 // bytes of the packed tables plus slots plus T area for a plan
+// The T area a plan needs: the most any launch's chunk uses, over its levels
+// (the shared passes as launched; never more than t_area_bytes)
+size_t plan_t_bytes(const hth_kb_s& kb, const Plan& P) {
+  size_t most = 0;
+  for (const PlanLevel& PL : P.levels) {
+    if (PL.groups.empty()) continue;
+    std::vector<GroupTask> gs = level_groups(kb, PL);
+    const std::vector<GroupChunk> cs = chunk_groups(kb, gs);
+    most = std::max(most, chunks_t_bytes(kb, gs, cs));
+  }
+  return most;
+}
+
 size_t plan_workspace_bytes(const hth_kb_s& kb, const Plan& P) {
   size_t tables = 0;
   auto add = [&](size_t n, size_t each) { tables = align_up(tables, 256) + n * each; };
@@ -1141,7 +1166,7 @@ size_t plan_workspace_bytes(const hth_kb_s& kb, const Plan& P) {
   add(n_fill, sizeof(FillTask));
   add(P.code.size(), sizeof(uint32_t));
   add(9 * n_grp + 8, sizeof(uint32_t));     // XCD slot tables: at most 8 more than groups per chunk
-  return align_up(tables, 256) + (size_t)P.n_slots * kb.S * 8 + (max_groups ? t_area_bytes(kb) : 0) +
+  return align_up(tables, 256) + (size_t)P.n_slots * kb.S * 8 + (max_groups ? plan_t_bytes(kb, P) : 0) +
          heavy_counter_bytes(kb, P) + partial_bytes(kb, P) + idset_bytes(P);
 }
 
@@ -1286,9 +1311,9 @@ void prepare(const hth_kb_s& kb, Plan&& plan, uint32_t n_hyps, Prepared& X) {
   X.o_xslot = X.blob.add(xslots);
   X.o_push = X.blob.add(pushes);
   X.tables = align_up(X.blob.bytes.size(), 256);
-  size_t max_groups = 0;
-  for (const PlanLevel& PL : P.levels) max_groups = std::max(max_groups, PL.groups.size());
-  X.o_hcnt = X.tables + (size_t)P.n_slots * kb.S * 8 + (max_groups ? t_area_bytes(kb) : 0);
+  size_t t_bytes = 0;   // the T area: the most one chunk of the plan uses
+  for (size_t L = 0; L < NL; ++L) t_bytes = std::max(t_bytes, chunks_t_bytes(kb, X.lv_groups[L], X.lv_chunks[L]));
+  X.o_hcnt = X.tables + (size_t)P.n_slots * kb.S * 8 + t_bytes;
   X.o_part = X.o_hcnt + heavy_counter_bytes(kb, P);
   size_t part = 0;
   for (size_t L = 0; L < NL; ++L)
@@ -1481,8 +1506,11 @@ extern "C" hth_status hth_workspace_bytes(hth_kb kb, uint32_t max_nodes, uint32_
                                           size_t* bytes) {
   if (!kb || !bytes) return fail(HTH_E_INVALID, "NULL argument");
   if (max_hyps == 0 || max_nodes < max_hyps) return fail(HTH_E_RANGE, "need max_nodes >= max_hyps >= 1");
+  // a chunk's T rows: at most t_area_bytes, and at most one row of the widest
+  // T word per individual for each of the plan's nodes
+  const size_t t_bound = std::min(t_area_bytes(*kb), (size_t)max_nodes * align_up(kb->N, 64) * 8);
   *bytes = align_up(table_bound(max_nodes, max_hyps), 256) + (size_t)(max_nodes + 2) * kb->S * 8 +
-           t_area_bytes(*kb) + align_up((size_t)(max_nodes + 2) * kb->chunk_most * 4, 256) +
+           t_bound + align_up((size_t)(max_nodes + 2) * kb->chunk_most * 4, 256) +
            align_up((size_t)(max_nodes + 2) * idset_words(kb->n_strings) * 8, 256);
   return HTH_OK;
 }

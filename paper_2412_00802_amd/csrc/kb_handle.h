@@ -85,7 +85,7 @@ struct hth_kb_s {
     uint32_t group_min = 2;      // smallest (role, dir, level) bucket run as shared passes
     uint32_t group_k = 64;       // most role nodes per shared pass (T row width)
     uint32_t xcd_local = 1;      // 1: all blocks of a shared pass on one XCD
-    size_t t_budget = 64ull << 20;   // bytes of T rows resident per launch
+    size_t t_budget = 1024ull << 20; // bytes of T rows one launch of shared passes may use
     uint32_t group_unroll = 16;  // assertions in flight per lane in a dense shared pass
     uint32_t region_reg = 2;     // words per lane of the register-stack region kernel (0: LDS kernel)
     uint32_t t_compact = 1;      // 1: T rows of objects only where they are <= N/2
