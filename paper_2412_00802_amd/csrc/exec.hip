@@ -309,120 +309,135 @@ k_region(DevKB kb, const RegionTask* __restrict__ tasks, const uint32_t* __restr
 
 // The same regions with the value stack in registers (a shift register of
 // depth D, enough for most programs) and R words per lane, so that no LDS
-// limits occupancy.  The words of the program's first kRegLeaves leaves (and
-// the example words a covered root needs) are loaded before anything is
-// evaluated, so that a lane has all of them in flight at once; the program
-// then runs leaf by leaf from registers, and leaves beyond the first
-// kRegLeaves are loaded where they occur.  Lane t handles words
-// tile*256R + r*256 + t (coalesced per r).  Coverage is reduced over the block
-// and added with one atomic pair per block.
+// limits occupancy.  A block takes one task and a run of `tpb` consecutive
+// tiles (256 R words each) and walks them in order: while it evaluates one
+// tile, the words of the program's first kRegLeaves leaves and the example
+// words of the next tile are already in flight.  The program runs leaf by
+// leaf from registers; leaves beyond the first kRegLeaves are loaded where
+// they occur.  Lane t handles words tile*256R + r*256 + t (coalesced per r).
+// Coverage is summed over the block's tiles and added with one atomic pair.
+// A root whose coverage a shared pass adds has an empty task: its blocks
+// leave at once.
 constexpr int kRegDepth = 6;     // D: most stack entries a program may need
-constexpr int kRegLeaves = 3;    // leaves whose words are loaded up front
+constexpr int kRegLeaves = 2;    // leaves whose words are loaded ahead
 template <int D, int R>
 __global__ void __launch_bounds__(256)
 k_region_reg(DevKB kb, const RegionTask* __restrict__ tasks, const uint32_t* __restrict__ code,
-             uint32_t n_tasks) {
+             uint32_t n_tasks, uint32_t tiles, uint32_t tpb) {
   __shared__ uint32_t s_pq[2][4];
-  const uint32_t tile = blockIdx.x / n_tasks, task = blockIdx.x % n_tasks;
+  const uint32_t run = blockIdx.x / n_tasks, task = blockIdx.x % n_tasks;
   const RegionTask T = tasks[task];
-  if (T.out_row == kNone && T.cover == kNone) return;   // a root whose coverage a shared pass adds
+  if (T.out_row == kNone && T.cover == kNone) return;
   const uint32_t tid = threadIdx.x;
-  const uint32_t w0 = tile * (256 * R) + tid;
   const uint32_t* prog = code + T.code_off;
   const uint32_t len = T.code_len;
-  uint64_t lv[kRegLeaves][R], ex_p[R], ex_n[R];
+  // the first kRegLeaves leaves' rows (a program with fewer reads the example
+  // row in their place and never uses it)
+  const uint64_t* lrow[kRegLeaves];
   {
     uint32_t pc = 0;
 #pragma unroll
     for (int j = 0; j < kRegLeaves; ++j) {
       while (pc < len && (prog[pc] & 15u) != RP_LEAF) ++pc;
-      if (pc < len) {
-        const uint64_t* row = row_ptr(kb, prog[pc] >> 5);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const uint32_t w = w0 + r * 256;
-          lv[j][r] = w < kb.W ? row[w] : 0ull;
-        }
-        ++pc;
-      } else {
-#pragma unroll
-        for (int r = 0; r < R; ++r) lv[j][r] = 0;
-      }
+      lrow[j] = pc < len ? row_ptr(kb, prog[pc] >> 5) : kb.pos;
+      if (pc < len) ++pc;
     }
   }
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint32_t w = w0 + r * 256;
-    const bool c = T.cover != kNone && w < kb.W;
-    ex_p[r] = c ? kb.pos[w] : 0ull;
-    ex_n[r] = c ? kb.neg[w] : 0ull;
-  }
-  uint64_t top[R], st[D > 1 ? D - 1 : 1][R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) top[r] = 0;
-  uint32_t pc = 0;
-  // segment j runs the program up to and including its j-th leaf; the last
-  // segment runs the rest, loading its leaves itself
-#pragma unroll
-  for (int j = 0; j <= kRegLeaves; ++j) {
-    while (pc < len) {
-      const uint32_t ins = prog[pc++];
-      const uint32_t op = ins & 15u, arg = ins >> 5;
-      if (op <= RP_BOT) {
-        if (pc > 1) {                             // push: shift the stack down
-#pragma unroll
-          for (int i = D - 2; i > 0; --i)
-#pragma unroll
-            for (int r = 0; r < R; ++r) st[i][r] = st[i - 1][r];
-#pragma unroll
-          for (int r = 0; r < R; ++r) st[0][r] = top[r];
-        }
-        if (op == RP_LEAF) {
-          const uint64_t negm = (ins & 16u) ? ~0ull : 0ull;
-          if (j < kRegLeaves) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) top[r] = lv[j < kRegLeaves ? j : 0][r] ^ negm;
-            break;
-          }
-          const uint64_t* row = row_ptr(kb, arg);
-#pragma unroll
-          for (int r = 0; r < R; ++r) {
-            const uint32_t w = w0 + r * 256;
-            top[r] = w < kb.W ? (row[w] ^ negm) : 0ull;
-          }
-        } else {
-#pragma unroll
-          for (int r = 0; r < R; ++r) top[r] = op == RP_TOP ? ~0ull : 0ull;
-        }
-      } else if (op == RP_NOT) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) top[r] = ~top[r];
-      } else {                                    // pop b, top = top op b
-        const bool conj = op == RP_AND;
-#pragma unroll
-        for (int r = 0; r < R; ++r) top[r] = conj ? (top[r] & st[0][r]) : (top[r] | st[0][r]);
-#pragma unroll
-        for (int i = 0; i + 1 < D - 1; ++i)
-#pragma unroll
-          for (int r = 0; r < R; ++r) st[i][r] = st[i + 1][r];
-      }
-    }
-  }
-  uint32_t p = 0, q = 0;
+  const bool cover = T.cover != kNone;
   uint64_t* out = T.out_row == kNone ? nullptr
                   : T.out_row == kInstances ? kb.instances + (size_t)T.cover * kb.S
                                             : out_ptr(kb, T.out_row);
+  // loads of one tile, at clamped word indices (no branch around them)
+  auto fetch = [&](uint32_t tile, uint64_t (&lv)[kRegLeaves][R], uint64_t (&ep)[R], uint64_t (&en)[R]) {
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint32_t w = w0 + r * 256;
-    uint64_t v = top[r];
-    if (w >= kb.W) v = 0;
-    else if (w == kb.W - 1) v &= kb.tail;
-    if (out && w < kb.S) out[w] = v;
-    p += (uint32_t)__popcll(v & ex_p[r]);
-    q += (uint32_t)__popcll(v & ex_n[r]);
+    for (int r = 0; r < R; ++r) {
+      const uint32_t wc = min(tile * (256 * R) + r * 256 + tid, kb.W - 1);
+#pragma unroll
+      for (int j = 0; j < kRegLeaves; ++j) lv[j][r] = lrow[j][wc];
+      ep[r] = kb.pos[wc];
+      en[r] = kb.neg[wc];
+    }
+  };
+  const uint32_t t_end = min((run + 1) * tpb, tiles);
+  uint64_t lv[kRegLeaves][R], ep[R], en[R];
+  fetch(run * tpb, lv, ep, en);
+  uint32_t p = 0, q = 0;
+  for (uint32_t tile = run * tpb; tile < t_end; ++tile) {
+    uint64_t nlv[kRegLeaves][R], nep[R], nen[R];
+    if (tile + 1 < t_end) fetch(tile + 1, nlv, nep, nen);
+    const uint32_t w0 = tile * (256 * R) + tid;
+    uint64_t top[R], st[D > 1 ? D - 1 : 1][R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) top[r] = 0;
+    uint32_t pc = 0;
+    // segment j runs the program up to and including its j-th leaf; the last
+    // segment runs the rest, loading its leaves itself
+#pragma unroll
+    for (int j = 0; j <= kRegLeaves; ++j) {
+      while (pc < len) {
+        const uint32_t ins = prog[pc++];
+        const uint32_t op = ins & 15u, arg = ins >> 5;
+        if (op <= RP_BOT) {
+          if (pc > 1) {                           // push: shift the stack down
+#pragma unroll
+            for (int i = D - 2; i > 0; --i)
+#pragma unroll
+              for (int r = 0; r < R; ++r) st[i][r] = st[i - 1][r];
+#pragma unroll
+            for (int r = 0; r < R; ++r) st[0][r] = top[r];
+          }
+          if (op == RP_LEAF) {
+            const uint64_t negm = (ins & 16u) ? ~0ull : 0ull;
+            if (j < kRegLeaves) {
+#pragma unroll
+              for (int r = 0; r < R; ++r) top[r] = lv[j < kRegLeaves ? j : 0][r] ^ negm;
+              break;
+            }
+            const uint64_t* row = row_ptr(kb, arg);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              const uint32_t w = w0 + r * 256;
+              top[r] = w < kb.W ? (row[w] ^ negm) : 0ull;
+            }
+          } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) top[r] = op == RP_TOP ? ~0ull : 0ull;
+          }
+        } else if (op == RP_NOT) {
+#pragma unroll
+          for (int r = 0; r < R; ++r) top[r] = ~top[r];
+        } else {                                  // pop b, top = top op b
+          const bool conj = op == RP_AND;
+#pragma unroll
+          for (int r = 0; r < R; ++r) top[r] = conj ? (top[r] & st[0][r]) : (top[r] | st[0][r]);
+#pragma unroll
+          for (int i = 0; i + 1 < D - 1; ++i)
+#pragma unroll
+            for (int r = 0; r < R; ++r) st[i][r] = st[i + 1][r];
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t w = w0 + r * 256;
+      uint64_t v = top[r];
+      if (w >= kb.W) v = 0;
+      else if (w == kb.W - 1) v &= kb.tail;
+      if (out && w < kb.S) out[w] = v;
+      if (cover) {
+        p += (uint32_t)__popcll(v & ep[r]);
+        q += (uint32_t)__popcll(v & en[r]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      ep[r] = nep[r];
+      en[r] = nen[r];
+#pragma unroll
+      for (int j = 0; j < kRegLeaves; ++j) lv[j][r] = nlv[j][r];
+    }
   }
-  if (T.cover != kNone) {
+  if (cover) {
     p = wave_sum(p);
     q = wave_sum(q);
     if ((tid & 63) == 0) {
@@ -910,6 +925,11 @@ double Launcher::csr_once(uint32_t role, uint32_t inv) {
   return csr_bytes(kb, role, inv);
 }
 
+// tiles one block of the register region kernel walks (with the next tile's
+// loads in flight while it evaluates one)
+constexpr uint32_t kRegionTilesPerBlock = 16;
+constexpr uint64_t kRegionMinBlocks = 16384;
+
 // n region tasks whose programs need at most `depth` stack entries
 hth_status launch_regions_n(Launcher& L, const DevKB& d, const RegionTask* tasks, const uint32_t* code,
                             uint32_t n, int depth, double bytes) {
@@ -918,14 +938,19 @@ hth_status launch_regions_n(Launcher& L, const DevKB& d, const RegionTask* tasks
   if (depth <= kRegDepth && L.kb.tune.region_reg) {
     const uint32_t rw = L.kb.tune.region_reg;     // words per lane: 1, 2 or 4
     const uint32_t tiles = (d.S + 256 * rw - 1) / (256 * rw);
-    return split_launch(L, HTH_K_REGION, bytes, n, tiles, 256, [&](uint32_t t0, uint32_t m, uint32_t blocks) {
+    // a block walks up to kRegionTilesPerBlock tiles of its task, fewer when
+    // the launch would otherwise have under kRegionMinBlocks blocks
+    const uint64_t per = std::max<uint64_t>(1, (uint64_t)n * tiles / kRegionMinBlocks);
+    const uint32_t tpb = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(tiles, kRegionTilesPerBlock), per);
+    const uint32_t runs = (tiles + tpb - 1) / tpb;
+    return split_launch(L, HTH_K_REGION, bytes, n, runs, 256, [&](uint32_t t0, uint32_t m, uint32_t blocks) {
       const dim3 grid(blocks), block(256);
       if (rw == 1)
-        hipLaunchKernelGGL((k_region_reg<kRegDepth, 1>), grid, block, 0, L.st, d, tasks + t0, code, m);
+        hipLaunchKernelGGL((k_region_reg<kRegDepth, 1>), grid, block, 0, L.st, d, tasks + t0, code, m, tiles, tpb);
       else if (rw == 2)
-        hipLaunchKernelGGL((k_region_reg<kRegDepth, 2>), grid, block, 0, L.st, d, tasks + t0, code, m);
+        hipLaunchKernelGGL((k_region_reg<kRegDepth, 2>), grid, block, 0, L.st, d, tasks + t0, code, m, tiles, tpb);
       else
-        hipLaunchKernelGGL((k_region_reg<kRegDepth, 4>), grid, block, 0, L.st, d, tasks + t0, code, m);
+        hipLaunchKernelGGL((k_region_reg<kRegDepth, 4>), grid, block, 0, L.st, d, tasks + t0, code, m, tiles, tpb);
     });
   }
   const uint32_t tiles = (d.S + kRegionThreads - 1) / kRegionThreads;
