@@ -1073,13 +1073,14 @@ extern "C" hth_status hth_dplan_create(hth_kb kb, const hth_node* d_nodes, uint3
   if (s) return s;
   std::vector<GroupTask> shells;
   for (const auto& lg : p->lv_groups) shells.insert(shells.end(), lg.begin(), lg.end());
-  // thresholds: each property's tasks together, in groups of at most 32
+  // thresholds: each property's tasks together, in groups of at most kThrPerPass
   std::vector<uint32_t> pbase(nd_data);
   std::vector<ThrGroup> thg;
   uint32_t tsum = 0;
   for (uint32_t q = 0; q < nd_data; ++q) {
     pbase[q] = tsum;
-    for (uint32_t i = 0; i < pk[q]; i += 32) thg.push_back(ThrGroup{q, tsum + i, std::min<uint32_t>(32, pk[q] - i), 0});
+    for (uint32_t i = 0; i < pk[q]; i += kThrPerPass)
+      thg.push_back(ThrGroup{q, tsum + i, std::min<uint32_t>(kThrPerPass, pk[q] - i), 0});
     tsum += pk[q];
   }
   if (tsum != S.n_thr) return fail(HTH_E_DEVICE, "threshold counts disagree");

@@ -1291,13 +1291,13 @@ void prepare(const hth_kb_s& kb, Plan&& plan, uint32_t n_hyps, Prepared& X) {
   }
   X.root_at = regions.size();
   regions.insert(regions.end(), P.roots.begin(), P.roots.end());
-  // thresholds grouped by property (at most 32 per group): one column pass each
+  // thresholds grouped by property (at most kThrPerPass per group): one column pass each
   std::vector<ThrTask> thr_tasks(P.thr);
   std::stable_sort(thr_tasks.begin(), thr_tasks.end(),
                    [](const ThrTask& a, const ThrTask& b) { return a.prop < b.prop; });
   std::vector<ThrGroup> thr_groups;
   for (uint32_t i = 0; i < thr_tasks.size(); ++i) {
-    if (thr_groups.empty() || thr_groups.back().prop != thr_tasks[i].prop || thr_groups.back().n == 32)
+    if (thr_groups.empty() || thr_groups.back().prop != thr_tasks[i].prop || thr_groups.back().n == kThrPerPass)
       thr_groups.push_back(ThrGroup{thr_tasks[i].prop, i, 0, 0});
     thr_groups.back().n++;
   }

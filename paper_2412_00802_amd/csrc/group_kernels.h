@@ -132,17 +132,56 @@ __device__ __forceinline__ Planes<TW> planes_shfl_up(const Planes<TW>& p, int d)
   return Planes<TW>{shfl_up_w(p.c0, d), shfl_up_w(p.c1, d), shfl_up_w(p.c2, d), shfl_up_w(p.ov, d)};
 }
 
+// Lane exchange with the partner lane ^ D, for a compile-time D: quad
+// permutations through DPP for 1 and 2, swizzles within 32 lanes for 4 to 16,
+// a permute across the halves for 32.  Every lane of the wave takes part.
+template <int D>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v) {
+  if constexpr (D == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);
+  else if constexpr (D == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true);
+  else if constexpr (D < 32) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (D << 10));
+  else return (uint32_t)__shfl_xor((int)v, D, 64);
+}
+
+// One butterfly stage of the lane transpose below, on both 32-bit halves: the
+// lane whose bit D is clear keeps the bits of the D-blocks selected by M and
+// takes the partner's such blocks into the other blocks; its partner keeps the
+// other blocks and takes this lane's remaining blocks.  Each lane rotates what
+// it gives away into the position where the partner needs it (right by D, or
+// left by D), so one rotate, one exchange and one bit insert per half suffice.
+template <int D, uint32_t M>
+__device__ __forceinline__ void transpose_stage(uint32_t& lo, uint32_t& hi, int lane) {
+  const bool up = lane & D;
+  const uint32_t sh = up ? 32u - D : (uint32_t)D, keep = up ? ~M : M;
+  const uint32_t rl = lane_xor<D>(__builtin_amdgcn_alignbit(lo, lo, sh));
+  const uint32_t rh = lane_xor<D>(__builtin_amdgcn_alignbit(hi, hi, sh));
+  lo = (keep & lo) | (~keep & rl);
+  hi = (keep & hi) | (~keep & rh);
+}
+
 // 64 x 64 bit transpose across the lanes of a wave: on entry lane l holds row
 // l (bit j = M[l][j]); on exit lane l holds column l (bit j = M[j][l]).  Six
-// butterfly stages, each swapping the off-diagonal blocks with the partner lane.
+// butterfly stages (block sizes 32, 16, ..., 1), each exchanging off-diagonal
+// blocks with the partner lane.  Called with every lane of the wave active.
 __device__ __forceinline__ uint64_t wave_transpose64(uint64_t x, int lane) {
-  uint64_t m = 0x00000000FFFFFFFFull;
-#pragma unroll
-  for (int d = 32; d != 0; d >>= 1, m ^= (m << d)) {
-    const uint64_t y = __shfl_xor((unsigned long long)x, d, 64);
-    x = (lane & d) ? (((y >> d) & m) | (x & ~m)) : ((x & m) | ((y << d) & ~m));
+  uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+  // the stages' per-lane shift counts and masks are derived from the lane here
+  // rather than kept live across the caller's loop (they would cost registers
+  // the caller needs for occupancy)
+  asm volatile("" : "+v"(lane));
+  {   // 32-bit blocks: the lower half of the wave trades its high words for
+      // the upper half's low words
+    const bool up = lane & 32;
+    const uint32_t r = lane_xor<32>(up ? lo : hi);
+    lo = up ? r : lo;
+    hi = up ? hi : r;
   }
-  return x;
+  transpose_stage<16, 0x0000FFFFu>(lo, hi, lane);
+  transpose_stage<8, 0x00FF00FFu>(lo, hi, lane);
+  transpose_stage<4, 0x0F0F0F0Fu>(lo, hi, lane);
+  transpose_stage<2, 0x33333333u>(lo, hi, lane);
+  transpose_stage<1, 0x55555555u>(lo, hi, lane);
+  return ((uint64_t)hi << 32) | lo;
 }
 
 // The members' acceptance of a count held in bit-sliced planes: bit j of the

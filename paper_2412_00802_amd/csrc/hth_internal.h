@@ -81,6 +81,9 @@ struct StrTask {
 };
 
 // The thresholds on one property, tasks[first .. first + n) (n <= 32).
+// Thresholds on one property served by one pass over its column (the values
+// stay in registers while each threshold's words are written).
+constexpr uint32_t kThrPerPass = 32;
 struct ThrGroup {
   uint32_t prop;
   uint32_t first;
