@@ -1170,7 +1170,7 @@ extern "C" hth_status hth_dplan_launch(hth_dplan plan, void* ws, size_t ws_bytes
     });
     if (s) return s;
   }
-  const uint32_t ftiles = (kb.S + 255) / 256;
+  const uint32_t ftiles = fill_tiles(kb.S);
   s = Lc.run(HTH_K_FILL, (double)kb.W * 8, [&] {   // the zero row
     hipLaunchKernelGGL(k_fill_rows, dim3(ftiles), dim3(256), 0, st, d, T.fills, ftiles);
   });

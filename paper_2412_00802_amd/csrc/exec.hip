@@ -636,16 +636,26 @@ k_push(DevKB kb, const RoleTask* __restrict__ tasks, uint32_t tiles) {
   }
 }
 
-// Zero-count results for the words of a role direction without assertions.
+// Zero-count results for the words of a role direction without assertions:
+// the whole row, four words (two 16-byte stores) per thread.  Rows are
+// stride_words apart, a multiple of 8, so a thread's words never cross a row.
+constexpr uint32_t kFillWords = 4;
+inline uint32_t fill_tiles(uint32_t S) { return (S + 256 * kFillWords - 1) / (256 * kFillWords); }
 __global__ void __launch_bounds__(256)
 k_fill_rows(DevKB kb, const FillTask* __restrict__ tasks, uint32_t tiles) {
   const uint32_t t = blockIdx.x / tiles, tile = blockIdx.x % tiles;
   const FillTask F = tasks[t];
-  const uint32_t w = tile * 256 + threadIdx.x;
-  if (w >= kb.S) return;
-  uint64_t v = 0;
-  if (F.ones && w < kb.W) v = w == kb.W - 1 ? kb.tail : ~0ull;
-  out_ptr(kb, F.out_row)[w] = v;
+  const uint32_t w0 = (tile * 256 + threadIdx.x) * kFillWords;
+  if (w0 >= kb.S) return;
+  uint64_t v[kFillWords];
+#pragma unroll
+  for (uint32_t i = 0; i < kFillWords; ++i) {
+    const uint32_t w = w0 + i;
+    v[i] = F.ones && w < kb.W ? (w == kb.W - 1 ? kb.tail : ~0ull) : 0ull;
+  }
+  ulonglong2* q = reinterpret_cast<ulonglong2*>(out_ptr(kb, F.out_row) + w0);
+  q[0] = make_ulonglong2(v[0], v[1]);
+  q[1] = make_ulonglong2(v[2], v[3]);
 }
 
 }  // namespace hth
@@ -1472,7 +1482,7 @@ hth_status launch_prepared(hth_kb_s& kb, const Prepared& X, char* ws, uint32_t* 
     hth_status s = launch_regions(Lc, d, reg + at.mat, code, PL.mat, P.code);
     if (s) return s;
     if (at.nfill) {
-      const uint32_t n = (uint32_t)at.nfill, tiles = (kb.S + 255) / 256;
+      const uint32_t n = (uint32_t)at.nfill, tiles = fill_tiles(kb.S);
       s = split_launch(Lc, HTH_K_FILL, at.fill_bytes, n, tiles, 256, [&](uint32_t i0, uint32_t, uint32_t blocks) {
         hipLaunchKernelGGL(k_fill_rows, dim3(blocks), dim3(256), 0, st, d, fil + at.fill + i0, tiles);
       });
