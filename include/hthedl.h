@@ -106,7 +106,8 @@ typedef struct {
 
 typedef struct hth_kb_s* hth_kb;   /* opaque host handle */
 
-/* The knowledge base (Section 3.1).  Every pointer is device memory. */
+/* The knowledge base (Section 3.1).  Every pointer is device memory; the bit
+ * rows (concept_bits, pos_bits, neg_bits) are 16-byte aligned. */
 typedef struct {
   uint32_t n_individuals;        /* N, 1 <= N < 2^31 */
   uint32_t stride_words;         /* words per bit row: >= ceil(N/64), a multiple of 8 */
@@ -137,12 +138,14 @@ hth_status hth_kb_derived_bytes(const hth_kb_desc* desc, size_t* bytes);
  * `derived` (device memory of at least hth_kb_derived_bytes).  Synchronous:
  * returns after validation and the build have finished on `stream`.  Errors:
  * HTH_E_INVALID (non-monotone offsets, target out of range, duplicate or
- * unsorted targets, set padding bits), HTH_E_NOMEM (derived too small),
+ * unsorted targets, set padding bits, bit rows not 16-byte aligned),
+ * HTH_E_NOMEM (derived too small),
  * HTH_E_RANGE (sizes beyond the limits above). */
 hth_status hth_kb_create(const hth_kb_desc* desc, void* derived, size_t derived_bytes,
                          void* stream, hth_kb* out);
 
-/* Replace the example rows (device [stride_words] each, zero padding). */
+/* Replace the example rows (device [stride_words] each, zero padding, 16-byte
+ * aligned; HTH_E_INVALID otherwise). */
 hth_status hth_kb_set_examples(hth_kb kb, const uint64_t* pos_bits, const uint64_t* neg_bits);
 
 /* Register the set table that HTH_SET leaves read: device uint64
@@ -150,7 +153,8 @@ hth_status hth_kb_set_examples(hth_kb kb, const uint64_t* pos_bits, const uint64
  * later evaluations in stream order (rows may be rewritten between calls, for
  * instance by hth_eval_batch_sets).  rows = NULL with n_rows = 0 removes it.
  * Must not run concurrently with an evaluation on the same kb.  Errors:
- * HTH_E_INVALID (NULL rows with n_rows > 0), HTH_E_RANGE (n_rows >= 2^24). */
+ * HTH_E_INVALID (NULL rows with n_rows > 0, rows not 16-byte aligned),
+ * HTH_E_RANGE (n_rows >= 2^24). */
 hth_status hth_kb_set_sets(hth_kb kb, const uint64_t* rows, uint32_t n_rows);
 
 /* Multi-valued numeric concrete roles (Section 3.1: a concrete role is a list

@@ -314,7 +314,7 @@ k_region(DevKB kb, const RegionTask* __restrict__ tasks, const uint32_t* __restr
 // tile, the words of the program's first kRegLeaves leaves and the example
 // words of the next tile are already in flight.  The program runs leaf by
 // leaf from registers; leaves beyond the first kRegLeaves are loaded where
-// they occur.  Lane t handles words tile*256R + r*256 + t (coalesced per r).
+// they occur.  Lane t handles words tile*256R + R*t + r (consecutive: 16-byte loads).
 // Coverage is summed over the block's tiles and added with one atomic pair.
 // A root whose coverage a shared pass adds has an empty task: its blocks
 // leave at once.
@@ -347,16 +347,27 @@ k_region_reg(DevKB kb, const RegionTask* __restrict__ tasks, const uint32_t* __r
   uint64_t* out = T.out_row == kNone ? nullptr
                   : T.out_row == kInstances ? kb.instances + (size_t)T.cover * kb.S
                                             : out_ptr(kb, T.out_row);
-  // loads of one tile, at clamped word indices (no branch around them)
-  auto fetch = [&](uint32_t tile, uint64_t (&lv)[kRegLeaves][R], uint64_t (&ep)[R], uint64_t (&en)[R]) {
+  // loads of one tile: a lane's R consecutive words, at an index clamped into
+  // the row (rows hold S words, S a multiple of 8; words past W are masked
+  // later), R-word vector loads with no branch around them
+  auto load_words = [&](const uint64_t* row, uint32_t wc, uint64_t (&v)[R]) {
+    if constexpr (R == 1) {
+      v[0] = row[wc];
+    } else {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const uint32_t wc = min(tile * (256 * R) + r * 256 + tid, kb.W - 1);
-#pragma unroll
-      for (int j = 0; j < kRegLeaves; ++j) lv[j][r] = lrow[j][wc];
-      ep[r] = kb.pos[wc];
-      en[r] = kb.neg[wc];
+      for (int r = 0; r < R; r += 2) {
+        const ulonglong2 q = *reinterpret_cast<const ulonglong2*>(row + wc + r);
+        v[r] = q.x;
+        v[r + 1] = q.y;
+      }
     }
+  };
+  auto fetch = [&](uint32_t tile, uint64_t (&lv)[kRegLeaves][R], uint64_t (&ep)[R], uint64_t (&en)[R]) {
+    const uint32_t wc = min(tile * (256 * R) + tid * R, kb.S - R);
+#pragma unroll
+    for (int j = 0; j < kRegLeaves; ++j) load_words(lrow[j], wc, lv[j]);
+    load_words(kb.pos, wc, ep);
+    load_words(kb.neg, wc, en);
   };
   const uint32_t t_end = min((run + 1) * tpb, tiles);
   uint64_t lv[kRegLeaves][R], ep[R], en[R];
@@ -365,7 +376,7 @@ k_region_reg(DevKB kb, const RegionTask* __restrict__ tasks, const uint32_t* __r
   for (uint32_t tile = run * tpb; tile < t_end; ++tile) {
     uint64_t nlv[kRegLeaves][R], nep[R], nen[R];
     if (tile + 1 < t_end) fetch(tile + 1, nlv, nep, nen);
-    const uint32_t w0 = tile * (256 * R) + tid;
+    const uint32_t w0 = tile * (256 * R) + tid * R;
     uint64_t top[R], st[D > 1 ? D - 1 : 1][R];
 #pragma unroll
     for (int r = 0; r < R; ++r) top[r] = 0;
@@ -396,7 +407,7 @@ k_region_reg(DevKB kb, const RegionTask* __restrict__ tasks, const uint32_t* __r
             const uint64_t* row = row_ptr(kb, arg);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-              const uint32_t w = w0 + r * 256;
+              const uint32_t w = w0 + r;
               top[r] = w < kb.W ? (row[w] ^ negm) : 0ull;
             }
           } else {
@@ -419,7 +430,7 @@ k_region_reg(DevKB kb, const RegionTask* __restrict__ tasks, const uint32_t* __r
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const uint32_t w = w0 + r * 256;
+      const uint32_t w = w0 + r;
       uint64_t v = top[r];
       if (w >= kb.W) v = 0;
       else if (w == kb.W - 1) v &= kb.tail;

@@ -446,6 +446,9 @@ static hth_status check_desc(const hth_kb_desc* d) {
   if (d->stride_words < W || d->stride_words % 8)
     return fail(HTH_E_INVALID, "stride_words must be >= ceil(N/64) and a multiple of 8");
   if (d->n_concepts && !d->concept_bits) return fail(HTH_E_INVALID, "concept_bits is NULL");
+  if ((reinterpret_cast<uintptr_t>(d->concept_bits) | reinterpret_cast<uintptr_t>(d->pos_bits) |
+       reinterpret_cast<uintptr_t>(d->neg_bits)) % 16)
+    return fail(HTH_E_INVALID, "bit rows must be 16-byte aligned");
   if (d->n_roles && (!d->role_offsets || (d->n_edges && !d->role_targets)))
     return fail(HTH_E_INVALID, "role arrays are NULL");
   if (d->n_roles > 65535) return fail(HTH_E_RANGE, "at most 65535 roles");
@@ -1081,6 +1084,8 @@ extern "C" hth_status hth_kb_set_patterns(hth_kb kb, uint32_t n_patterns, const 
 extern "C" hth_status hth_kb_set_examples(hth_kb kb, const uint64_t* pos, const uint64_t* neg) {
   if (!kb) return fail(HTH_E_INVALID, "kb is NULL");
   if (!pos || !neg) return fail(HTH_E_INVALID, "example rows are NULL");
+  if ((reinterpret_cast<uintptr_t>(pos) | reinterpret_cast<uintptr_t>(neg)) % 16)
+    return fail(HTH_E_INVALID, "example rows must be 16-byte aligned");
   std::lock_guard<std::mutex> g(kb->mu);
   kb->pos = pos;
   kb->neg = neg;
@@ -1091,6 +1096,7 @@ extern "C" hth_status hth_kb_set_sets(hth_kb kb, const uint64_t* rows, uint32_t 
   if (!kb) return fail(HTH_E_INVALID, "kb is NULL");
   if (n_rows && !rows) return fail(HTH_E_INVALID, "set rows are NULL");
   if (n_rows >= (1u << 24)) return fail(HTH_E_RANGE, "set table holds at most 2^24 - 1 rows");
+  if (reinterpret_cast<uintptr_t>(rows) % 16) return fail(HTH_E_INVALID, "set rows must be 16-byte aligned");
   std::lock_guard<std::mutex> g(kb->mu);
   kb->sets = n_rows ? rows : nullptr;
   kb->n_sets = n_rows;

@@ -196,6 +196,24 @@ def test_kb_validation(gpu):
     assert "padding" in str(e.value)
 
 
+def test_bit_rows_must_be_16_byte_aligned(gpu):
+    """Example rows and the set table are read with 16-byte loads: a buffer
+    8 bytes off is refused (HTH_E_INVALID) and the previous rows stay."""
+    torch = gpu
+    kb = synth.kb_from_edges(100, [[1, 2, 3]], [[(0, 5), (0, 9), (4, 2)]])
+    eng = hthedl.Engine(kb)
+    want = eng.eval_batch([("atom", 0), ("exists", 0, 0, ("atom", 0))])
+    buf = torch.zeros(eng.S + 2, dtype=torch.int64, device="cuda")
+    off = buf[1:1 + eng.S]
+    with pytest.raises(hthedl.HthError) as e:
+        hthedl.hth_kb_set_examples(eng.handle, off, off)
+    assert "16-byte" in str(e.value)
+    with pytest.raises(hthedl.HthError) as e:
+        hthedl.hth_kb_set_sets(eng.handle, off, 1)
+    assert "16-byte" in str(e.value)
+    assert np.array_equal(eng.eval_batch([("atom", 0), ("exists", 0, 0, ("atom", 0))]), want)
+
+
 def test_kb_validation_heavy_rows(gpu):
     """Rows above the heavy-row threshold are checked chunk by chunk at load:
     an unsorted pair, a duplicate across a chunk boundary and a target out of
