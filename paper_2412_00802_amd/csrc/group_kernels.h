@@ -270,9 +270,11 @@ struct SegPass {
 // serves every member) and adds it into bit-sliced counters; a row complete in
 // the slice has its acceptance written to LDS at once.  Rows that straddle
 // slices leave a tail partial in each lane they cross; one segmented scan over
-// the lanes adds them up for the lane holding the row's last assertion.  A
-// finished row's counters go to LDS (a few stores, so that lanes crossing a
-// row boundary at different steps stay cheap); afterwards every lane turns
+// the lanes adds them up for the lane holding the row's last assertion.  Only
+// non-empty rows are walked: they are packed by a ballot, so that a lane steps
+// from one row to the next in one LDS read however many empty subjects lie
+// between.  A finished row's counters go to LDS (a few stores, so that lanes
+// crossing a row boundary at different steps stay cheap); afterwards every lane turns
 // its own subject's counters into the members' predicates at once, and each
 // word's predicates are transposed by a wave butterfly into one word per
 // member.  MW > 1 serves directions with few assertions per word.
@@ -381,19 +383,30 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
   gather(s, se, t, v);
   for (; it < n_iter; it += istep) {
     const uint32_t mc = words_in(it);
-    const uint32_t nr = 64 * mc;
+    // the iteration's non-empty rows in subject order, by compact index: row i
+    // holds assertions [ro[i], ro[i + 1]).  Empty rows are never walked; their
+    // subjects take the zero count.
+    uint64_t nzm[MW];
+    uint32_t nzb[MW], nnz = 0;
+#pragma unroll
+    for (int m = 0; m < MW; ++m) {
+      nzm[m] = (uint32_t)m < mc ? __ballot(rw.lo[m] < rw.hi[m]) : 0ull;
+      nzb[m] = nnz;
+      nnz += __popcll(nzm[m]);
+    }
+    auto compact = [&](int m) {   // the compact index of this lane's subject of word m
+      return nzb[m] + __builtin_amdgcn_mbcnt_hi((uint32_t)(nzm[m] >> 32),
+                                                __builtin_amdgcn_mbcnt_lo((uint32_t)nzm[m], 0u));
+    };
 #pragma unroll
     for (int m = 0; m < MW; ++m)
-      if ((uint32_t)m < mc) {
-        ro[64 * m + lane] = rw.lo[m];
-        pl[0][64 * m + lane] = pl[1][64 * m + lane] = pl[2][64 * m + lane] = pl[3][64 * m + lane] = (TW)0;
-      }
+      if ((nzm[m] >> lane) & 1ull) ro[compact(m)] = rw.lo[m];
     {
       uint32_t hl = rw.hi[0];
 #pragma unroll
       for (int m = 1; m < MW; ++m)
         if ((uint32_t)m < mc) hl = rw.hi[m];
-      if (lane == 63) ro[nr] = hl;
+      if (lane == 63) ro[nnz] = hl;
     }
     // the pipeline's next stages: offsets of it + 2 istep, targets of it + istep
     Rows rnn;
@@ -419,7 +432,7 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
       int r = 0;
 #pragma unroll
       for (int step = R / 2; step; step >>= 1)
-        if (r + step < (int)nr && ro[r + step] <= s) r += step;
+        if (r + step < (int)nnz && ro[r + step] <= s) r += step;
       bool head = ro[r] < s;
       uint32_t rend = ro[r + 1];
       for (uint32_t e0 = s; e0 < se; e0 += U) {
@@ -486,8 +499,11 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
 #pragma unroll
     for (int m = 0; m < MW; ++m) {
       if ((uint32_t)m < mc) {
-        const int r = 64 * m + lane;
-        Planes<TW> p{pl[0][r], pl[1][r], pl[2][r], pl[3][r]};
+        Planes<TW> p{0, 0, 0, 0};
+        if ((nzm[m] >> lane) & 1ull) {
+          const int r = compact(m);
+          p = Planes<TW>{pl[0][r], pl[1][r], pl[2][r], pl[3][r]};
+        }
         if (part) {
           TW* q = part + (size_t)rw.wd[m] * 256 + lane;
           if (!sp.first) planes_add(p, Planes<TW>{q[0], q[64], q[128], q[192]});
