@@ -910,6 +910,7 @@ hth_status dp_schedule(hth_dplan_s& p, const std::vector<uint32_t>& bk, std::vec
           gt.k = (uint32_t)std::min<uint64_t>(gk, g - i0);
           gt.first = (uint32_t)(p.n_members + i0);
           gt.n_words = kb.n_words[rd];
+          gt.n_obj_words = kb.n_words[rd ^ 1u];
           gt.compact = kb.tune.t_compact && 2ull * kb.n_obj[rd] <= kb.N;
           gt.short_rows = sr;
           p.lv_groups[L].push_back(gt);

@@ -1042,7 +1042,13 @@ hth_status launch_group_chunk(Launcher& L, const DevKB& d, const GroupTask* grou
     gb += L.csr_once(G.role, G.inv) + (double)G.k * G.n_words * 8;
   }
   TW* T = static_cast<TW*>(tarea);
-  const uint32_t tiles = (kb.W + 255) / 256;
+  // 256 words per block: every word, or the object words of a compact group
+  uint32_t span = 1;
+  for (uint32_t i = 0; i < n; ++i) {
+    const GroupTask& G = host[g0 + i];
+    span = std::max(span, G.compact ? G.n_obj_words : kb.W);
+  }
+  const uint32_t tiles = (span + 255) / 256;
   hth_status s = split_launch(L, HTH_K_TBUILD, tb, n, tiles, 256, [&](uint32_t i0, uint32_t, uint32_t blocks) {
     hipLaunchKernelGGL(k_tbuild<TW>, dim3(blocks), dim3(256), 0, L.st, d, groups + g0 + i0, members, T, tiles);
   });
@@ -1148,6 +1154,7 @@ std::vector<GroupTask> level_groups(const hth_kb_s& kb, const PlanLevel& PL) {
   std::vector<GroupTask> out;
   for (GroupTask g : PL.groups) {
     g.n_words = kb.n_words[2 * g.role + g.inv];
+    g.n_obj_words = kb.n_words[(2 * g.role + g.inv) ^ 1u];
     g.compact = kb.tune.t_compact && 2ull * kb.n_obj[2 * g.role + g.inv] <= kb.N;
     g.short_rows = short_rows(kb, 2 * g.role + g.inv);
     out.push_back(g);

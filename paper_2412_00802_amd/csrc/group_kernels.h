@@ -48,7 +48,8 @@ __device__ __forceinline__ uint64_t scalar_u64(const uint64_t* p) {
 // T_g[y] bit j = bit(child_j, y) ^ neg_j for the groups of one launch; one lane
 // per 64-individual word, transposed in registers.  T rows are TW wide
 // (8 * sizeof(TW) >= every group's k).  A compact group keeps the rows of its
-// direction's objects only, at their ranks; words without objects are skipped.
+// direction's objects only, at their ranks, and its lanes take the words that
+// hold objects (a list), not every word.
 // The members' row addresses are resolved once per block into LDS, so that a
 // lane issues all of its member loads before it waits for any of them; slots
 // beyond k read member 0's row again and drop it.
@@ -68,9 +69,18 @@ k_tbuild(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __re
     s_flip[j] = M.neg ? ~0ull : 0ull;
   }
   __syncthreads();
-  const uint32_t w = tile * 256 + threadIdx.x;
-  if (w >= kb.W) return;
   const uint32_t rd = 2 * G.role + G.inv;
+  // a compact group visits only the words that hold objects of its direction
+  // (the other direction's non-empty words, in its word list)
+  uint32_t w;
+  if (G.compact) {
+    const uint32_t i = tile * 256 + threadIdx.x;
+    if (i >= G.n_obj_words) return;
+    w = kb.words[(size_t)(rd ^ 1u) * kb.W + i];
+  } else {
+    w = tile * 256 + threadIdx.x;
+    if (w >= kb.W) return;
+  }
   const uint64_t omask = G.compact ? kb.objmask[(size_t)rd * kb.W + w] : ~0ull;
   if (!omask) return;
   uint64_t a[64];

@@ -146,7 +146,8 @@ struct GroupTask {
   uint32_t compact;    // 1: T holds the direction's objects only, indexed by object rank
   uint64_t t_off;      // first T row of the group in the T area (in T rows)
   uint32_t short_rows; // 1: every row of (role, inv) is short: one lane walks each subject
-  uint32_t pad;
+  uint32_t n_obj_words;  // words holding objects of (role, inv): the non-empty words of
+                         // the other direction (its word list), set with n_words
 };
 constexpr uint32_t kGroupMaxCount = 8;
 // A member whose node is the root of exactly one hypothesis and read by no
