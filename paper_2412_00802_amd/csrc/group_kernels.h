@@ -196,14 +196,17 @@ __device__ __forceinline__ uint64_t wave_transpose64(uint64_t x, int lane) {
 
 // The members' acceptance of a count held in bit-sliced planes: bit j of the
 // result = member j accepts the count of its bit j.
+// A select tree over the planes: c0 picks within each pair of counts, c1
+// between pairs, c2 between halves, ov the count >= 8.  The first level
+// takes acc[2i] ^ (c0 & (acc[2i] ^ acc[2i + 1])), so that no instruction
+// needs two of the (uniform) acceptance words at once.
 template <typename TW>
 __device__ __forceinline__ TW accept(const Planes<TW>& p, const TW (&acc)[kGroupMaxCount + 1]) {
-  const TW c0 = p.c0, c1 = p.c1, c2 = p.c2;
-  const TW n0 = ~c0, n1 = ~c1, n2 = ~c2;
-  const TW res = (n2 & n1 & n0 & acc[0]) | (n2 & n1 & c0 & acc[1]) | (n2 & c1 & n0 & acc[2]) |
-                 (n2 & c1 & c0 & acc[3]) | (c2 & n1 & n0 & acc[4]) | (c2 & n1 & c0 & acc[5]) |
-                 (c2 & c1 & n0 & acc[6]) | (c2 & c1 & c0 & acc[7]);
-  return (res & ~p.ov) | (p.ov & acc[8]);
+  auto pick = [](TW m, TW a, TW b) { return (m & a) | (~m & b); };   // a where m, else b
+  const TW p0 = acc[0] ^ (p.c0 & (acc[0] ^ acc[1])), p1 = acc[2] ^ (p.c0 & (acc[2] ^ acc[3]));
+  const TW p2 = acc[4] ^ (p.c0 & (acc[4] ^ acc[5])), p3 = acc[6] ^ (p.c0 & (acc[6] ^ acc[7]));
+  const TW q = pick(p.c2, pick(p.c1, p3, p2), pick(p.c1, p1, p0));
+  return pick(p.ov, acc[8], q);
 }
 
 // Coverage of a member without an output row (GroupMember::cover): lane j
