@@ -314,7 +314,8 @@ k_region(DevKB kb, const RegionTask* __restrict__ tasks, const uint32_t* __restr
 // tile, the words of the program's first kRegLeaves leaves and the example
 // words of the next tile are already in flight.  The program runs leaf by
 // leaf from registers; leaves beyond the first kRegLeaves are loaded where
-// they occur.  Lane t handles words tile*256R + R*t + r (consecutive: 16-byte loads).
+// they occur.  An operand directly followed by AND or OR is combined with
+// the top at once, so flat conjunctions and disjunctions never move the stack.  Lane t handles words tile*256R + R*t + r (consecutive: 16-byte loads).
 // Coverage is summed over the block's tiles and added with one atomic pair.
 // A root whose coverage a shared pass adds has an empty task: its blocks
 // leave at once.
@@ -389,31 +390,45 @@ k_region_reg(DevKB kb, const RegionTask* __restrict__ tasks, const uint32_t* __r
         const uint32_t ins = prog[pc++];
         const uint32_t op = ins & 15u, arg = ins >> 5;
         if (op <= RP_BOT) {
-          if (pc > 1) {                           // push: shift the stack down
-#pragma unroll
-            for (int i = D - 2; i > 0; --i)
-#pragma unroll
-              for (int r = 0; r < R; ++r) st[i][r] = st[i - 1][r];
-#pragma unroll
-            for (int r = 0; r < R; ++r) st[0][r] = top[r];
-          }
+          uint64_t val[R];                        // the operand's words
+          const bool ahead = op == RP_LEAF && j < kRegLeaves;
           if (op == RP_LEAF) {
             const uint64_t negm = (ins & 16u) ? ~0ull : 0ull;
-            if (j < kRegLeaves) {
+            if (ahead) {
 #pragma unroll
-              for (int r = 0; r < R; ++r) top[r] = lv[j < kRegLeaves ? j : 0][r] ^ negm;
-              break;
-            }
-            const uint64_t* row = row_ptr(kb, arg);
+              for (int r = 0; r < R; ++r) val[r] = lv[j < kRegLeaves ? j : 0][r] ^ negm;
+            } else {
+              const uint64_t* row = row_ptr(kb, arg);
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-              const uint32_t w = w0 + r;
-              top[r] = w < kb.W ? (row[w] ^ negm) : 0ull;
+              for (int r = 0; r < R; ++r) {
+                const uint32_t w = w0 + r;
+                val[r] = w < kb.W ? (row[w] ^ negm) : 0ull;
+              }
             }
           } else {
 #pragma unroll
-            for (int r = 0; r < R; ++r) top[r] = op == RP_TOP ? ~0ull : 0ull;
+            for (int r = 0; r < R; ++r) val[r] = op == RP_TOP ? ~0ull : 0ull;
           }
+          // an operand followed by AND / OR folds into the top: no push, no pop
+          // (every operand of a flattened conjunction or disjunction but the first)
+          const uint32_t nop = pc < len ? (prog[pc] & 15u) : (uint32_t)RP_LEAF;
+          if (pc > 1 && (nop == RP_AND || nop == RP_OR)) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) top[r] = nop == RP_AND ? (top[r] & val[r]) : (top[r] | val[r]);
+            ++pc;
+          } else {
+            if (pc > 1) {                         // push: shift the stack down
+#pragma unroll
+              for (int i = D - 2; i > 0; --i)
+#pragma unroll
+                for (int r = 0; r < R; ++r) st[i][r] = st[i - 1][r];
+#pragma unroll
+              for (int r = 0; r < R; ++r) st[0][r] = top[r];
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) top[r] = val[r];
+          }
+          if (ahead) break;
         } else if (op == RP_NOT) {
 #pragma unroll
           for (int r = 0; r < R; ++r) top[r] = ~top[r];
