@@ -194,6 +194,18 @@ __device__ __forceinline__ uint64_t wave_transpose64(uint64_t x, int lane) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// Lane l's value, in every lane (l the same in all of them).
+template <typename TW>
+__device__ __forceinline__ uint64_t read_lane(TW v, int l) {
+  if constexpr (sizeof(TW) == 8) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+  } else {
+    return (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  }
+}
+
 // The members' acceptance of a count held in bit-sliced planes: bit j of the
 // result = member j accepts the count of its bit j.
 // A select tree over the planes: c0 picks within each pair of counts, c1
@@ -290,7 +302,9 @@ struct SegPass {
 // crossing a row boundary at different steps stay cheap); afterwards every lane turns
 // its own subject's counters into the members' predicates at once, and each
 // word's predicates are transposed by a wave butterfly into one word per
-// member.  MW > 1 serves directions with few assertions per word.
+// member (a word with at most kSparseWord non-empty rows instead starts from
+// the zero count's predicates and takes the others' bits lane by lane).  MW > 1 serves directions with few assertions per word.
+constexpr int kSparseWord = 4;   // words with at most this many non-empty rows skip the transpose
 template <typename TW, int U, int MW>   // U: assertions in flight per lane
 __global__ void __launch_bounds__(256)
 k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __restrict__ members,
@@ -530,7 +544,22 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
         if (sp.last) {
           TW rv = accept(p, acc);
           if (rw.wd[m] * 64 + lane >= kb.N) rv = 0;
-          const uint64_t mine = wave_transpose64((uint64_t)rv, lane);
+          uint64_t mine;
+          if (__popcll(nzm[m]) <= kSparseWord) {
+            // the subjects without assertions take the zero count, so member
+            // j's word is acc[0]'s bit j at each of them; the bits of the few
+            // others are read from their lanes
+            const uint32_t x0 = rw.wd[m] * 64;
+            const uint64_t live = x0 + 64 <= kb.N ? ~0ull : ((1ull << (kb.N - x0)) - 1ull);
+            mine = (((uint64_t)acc[0] >> lane) & 1ull) ? live : 0ull;
+            for (uint64_t z = nzm[m]; z; z &= z - 1) {
+              const int l = __builtin_ctzll(z);
+              const uint64_t bit = (read_lane(rv, l) >> lane) & 1ull;
+              mine = (mine & ~(1ull << l)) | (bit << l);
+            }
+          } else {
+            mine = wave_transpose64((uint64_t)rv, lane);
+          }
           if (my_out) my_out[rw.wd[m]] = mine;
           if (cv.h != kNone) cover_word(cv, kb, rw.wd[m], mine);
         }
