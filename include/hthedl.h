@@ -211,7 +211,9 @@ hth_status hth_kb_max_degree(hth_kb kb, uint32_t role, uint32_t inv, uint32_t* o
 
 /* Schedule of the batched executor (no effect on results, only on speed).
  * group_min: smallest (role, direction, level) bucket of role nodes evaluated
- *   by shared CSR passes (0 = never share);
+ *   by shared CSR passes (0 = never share); on a direction whose rows are all
+ *   within short_rows, or whose non-empty words are at most half of all words,
+ *   a bucket of one node is shared as well;
  * group_k: most role nodes per shared pass (1..64; sets the transposed child
  *   row width 8/16/32/64 bits);
  * xcd_local: 1 = keep each shared pass on one XCD (its L2 holds the pass's

@@ -863,7 +863,7 @@ const char* dp_reason(uint32_t why, hth_status* code) {
 // counts, the per-level table bases, the shared passes (a bucket with at least
 // group_min decidable nodes gets ceil(count / group_k) passes, its nodes taken
 // in the order the emit pass reaches them), their T rows and XCD placement,
-// and the workspace layout.
+// and the workspace layout.  A bucket is large enough from bucket_min nodes.
 hth_status dp_schedule(hth_dplan_s& p, const std::vector<uint32_t>& bk, std::vector<DpBucket>& buckets,
                        std::vector<uint32_t>& xslots) {
   const hth_kb_s& kb = *p.kb;
@@ -885,7 +885,7 @@ hth_status dp_schedule(hth_dplan_s& p, const std::vector<uint32_t>& bk, std::vec
     uint64_t solo = 0, nb = 0, nc = 0, nf = 0;
     for (uint32_t rd = 0; rd < R2; ++rd) {
       const uint64_t g = bk[L * R2 + rd], o = bk[nbk + L * R2 + rd];
-      const bool grouped = g && g >= group_min;
+      const bool grouped = g && g >= bucket_min(kb, rd, group_min);
       const uint64_t alone = o + (grouped ? 0 : g);
       solo += alone;
       nb += alone * (kb.chunk_first[rd + 1] - kb.chunk_first[rd]);
@@ -898,7 +898,7 @@ hth_status dp_schedule(hth_dplan_s& p, const std::vector<uint32_t>& bk, std::vec
       for (uint32_t rd = 0; rd < R2; ++rd) {
         const uint64_t g = bk[L * R2 + rd];
         const bool sr = short_rows(kb, rd);
-        if (!(g && g >= group_min) || (int)sr != want_short) continue;
+        if (!(g && g >= bucket_min(kb, rd, group_min)) || (int)sr != want_short) continue;
         DpBucket& bu = buckets[L * R2 + rd];
         bu.first_group = p.n_groups + (uint32_t)p.lv_groups[L].size();
         bu.member_base = p.n_members;

@@ -2,6 +2,7 @@
 // helpers (host code only; the device-side structures are in hth_internal.h).
 #pragma once
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -110,5 +111,17 @@ hth_status hip_fail(hipError_t e, const char* what);
   } while (0)
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// The smallest bucket of role nodes over direction rd (2 role + dir) that runs
+// as shared passes, given the schedule's group_min (0xFFFFFFFF: never): one
+// node where the direction's rows are all short or at most half of its words
+// hold assertions (a one-node shared pass is faster there than the single-node
+// kernel, which walks every listed word for one node), else group_min.
+inline uint32_t bucket_min(const hth_kb_s& kb, uint32_t rd, uint32_t group_min) {
+  if (group_min == 0xFFFFFFFFu) return group_min;
+  const bool short_dir = kb.tune.short_rows && kb.max_deg[rd & 1][rd >> 1] <= kb.tune.short_rows;
+  const bool sparse = rd < kb.n_words.size() && 2ull * kb.n_words[rd] <= kb.W;
+  return short_dir || sparse ? std::min<uint32_t>(group_min, 1u) : group_min;
+}
 
 }  // namespace hth

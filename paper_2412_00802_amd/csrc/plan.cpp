@@ -612,7 +612,7 @@ struct Compiler {
                                  (n.op == HTH_ATLEAST ? n.q <= kGroupMaxCount : n.q < kGroupMaxCount);
           (groupable ? grp : solo).push_back(items[q]);
         }
-        if (grp.size() < opt.group_min) {
+        if (grp.size() < bucket_min(kb, 2 * first.arg + first.inv, opt.group_min)) {
           solo.insert(solo.end(), grp.begin(), grp.end());
           grp.clear();
         }
