@@ -1087,9 +1087,19 @@ hth_status launch_group_chunk(Launcher& L, const DevKB& d, const GroupTask* grou
   }
   const bool multi = nwd > 0 && ew < 96.0 * nwd;
   if (host[g0].short_rows) {   // every row short: a lane per subject, one pass
+    // exact 3-bit counts when no row of the launch's directions holds 8 assertions
+    uint32_t most = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+      const GroupTask& G = host[g0 + i];
+      most = std::max(most, kb.max_deg[G.inv][G.role]);
+    }
     return L.run(HTH_K_GROUP_SHORT, gb, [&] {
-      hipLaunchKernelGGL((k_group_short<TW, kShortWords, kShortSub>), dim3(nblocks), dim3(256), 0, L.st, d,
-                         groups + g0, members, T, bpg, xslots);
+      if (most < kGroupMaxCount)
+        hipLaunchKernelGGL((k_group_short<TW, kShortWords, kShortSub, true>), dim3(nblocks), dim3(256), 0, L.st,
+                           d, groups + g0, members, T, bpg, xslots);
+      else
+        hipLaunchKernelGGL((k_group_short<TW, kShortWords, kShortSub, false>), dim3(nblocks), dim3(256), 0, L.st,
+                           d, groups + g0, members, T, bpg, xslots);
     });
   }
   uint64_t seg_rows;

@@ -212,13 +212,15 @@ __device__ __forceinline__ uint64_t read_lane(TW v, int l) {
 // between pairs, c2 between halves, ov the count >= 8.  The first level
 // takes acc[2i] ^ (c0 & (acc[2i] ^ acc[2i + 1])), so that no instruction
 // needs two of the (uniform) acceptance words at once.
-template <typename TW>
+// SAT = false: the count is below 8 (ov is not read).
+template <typename TW, bool SAT = true>
 __device__ __forceinline__ TW accept(const Planes<TW>& p, const TW (&acc)[kGroupMaxCount + 1]) {
   auto pick = [](TW m, TW a, TW b) { return (m & a) | (~m & b); };   // a where m, else b
   const TW p0 = acc[0] ^ (p.c0 & (acc[0] ^ acc[1])), p1 = acc[2] ^ (p.c0 & (acc[2] ^ acc[3]));
   const TW p2 = acc[4] ^ (p.c0 & (acc[4] ^ acc[5])), p3 = acc[6] ^ (p.c0 & (acc[6] ^ acc[7]));
   const TW q = pick(p.c2, pick(p.c1, p3, p2), pick(p.c1, p1, p0));
-  return pick(p.ov, acc[8], q);
+  if constexpr (SAT) return pick(p.ov, acc[8], q);
+  else return q;
 }
 
 // Coverage of a member without an output row (GroupMember::cover): lane j
@@ -589,7 +591,9 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
 // waits for every store issued before it.
 constexpr int kShortWords = 4;   // MW
 constexpr int kShortSub = 2;     // SUB
-template <typename TW, int MW, int SUB>
+// EXACT: every row of the launch's directions holds at most 7 assertions, so
+// c2 c1 c0 count exactly and the saturation plane stays empty (not kept).
+template <typename TW, int MW, int SUB, bool EXACT>
 __global__ void __launch_bounds__(256)
 k_group_short(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __restrict__ members,
               const TW* __restrict__ tarea, uint32_t bpg, const uint32_t* __restrict__ xslots) {
@@ -683,7 +687,16 @@ k_group_short(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember*
 #pragma unroll
         for (int m = 0; m < MW; ++m) {
           const bool o = e[m] < ee[m];
-          planes_inc(p[m], o ? v[m] : (TW)0);
+          if constexpr (EXACT) {
+            const TW w = o ? v[m] : (TW)0;
+            const TW k0 = p[m].c0 & w;
+            p[m].c0 ^= w;
+            const TW k1 = p[m].c1 & k0;
+            p[m].c1 ^= k0;
+            p[m].c2 ^= k1;
+          } else {
+            planes_inc(p[m], o ? v[m] : (TW)0);
+          }
           e[m] += o;
         }
       }
@@ -695,7 +708,7 @@ k_group_short(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember*
       }
 #pragma unroll
       for (int m = 0; m < MW; ++m) {
-        TW rv = accept(p[m], acc);
+        TW rv = accept<TW, !EXACT>(p[m], acc);
         if (wd[m] == kNone || wd[m] * 64 + lane >= kb.N) rv = 0;
         const uint64_t o = wave_transpose64((uint64_t)rv, lane);
         so[lane][sub * MW + m] = o;
