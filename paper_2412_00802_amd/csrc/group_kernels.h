@@ -53,6 +53,7 @@ __device__ __forceinline__ uint64_t scalar_u64(const uint64_t* p) {
 // The members' row addresses are resolved once per block into LDS, so that a
 // lane issues all of its member loads before it waits for any of them; slots
 // beyond k read member 0's row again and drop it.
+constexpr int kTStage = 1024;   // T rows a wave stages in LDS
 template <typename TW>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 k_tbuild(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __restrict__ members,
@@ -60,6 +61,7 @@ k_tbuild(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __re
   constexpr int KB = 8 * sizeof(TW);
   __shared__ const uint64_t* s_row[KB];
   __shared__ uint64_t s_flip[KB];
+  __shared__ TW s_t[4][kTStage];   // each wave's compact T rows before they go out as one run
   const uint32_t g = blockIdx.x / tiles, tile = blockIdx.x % tiles;
   const GroupTask G = groups[g];
   if (threadIdx.x < (uint32_t)KB) {
@@ -70,32 +72,56 @@ k_tbuild(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __re
   }
   __syncthreads();
   const uint32_t rd = 2 * G.role + G.inv;
-  // a compact group visits only the words that hold objects of its direction
-  // (the other direction's non-empty words, in its word list)
-  uint32_t w;
-  if (G.compact) {
-    const uint32_t i = tile * 256 + threadIdx.x;
-    if (i >= G.n_obj_words) return;
-    w = kb.words[(size_t)(rd ^ 1u) * kb.W + i];
-  } else {
-    w = tile * 256 + threadIdx.x;
-    if (w >= kb.W) return;
-  }
-  const uint64_t omask = G.compact ? kb.objmask[(size_t)rd * kb.W + w] : ~0ull;
-  if (!omask) return;
-  uint64_t a[64];
-#pragma unroll
-  for (int j = 0; j < KB; ++j) a[j] = uniform_row_word(s_row[j], w * 8u);
-#pragma unroll
-  for (int j = 0; j < 64; ++j) a[j] = j < KB && (j == 0 || (uint32_t)j < G.k) ? a[j] ^ s_flip[j] : 0ull;
-  transpose64(a);
   TW* T = tarea + G.t_off;
+  // the words of lane's 64 individuals from every member's child row, flipped
+  // where the member counts the complement, transposed into T rows
+  auto build = [&](uint32_t w, uint64_t (&a)[64]) {
+#pragma unroll
+    for (int j = 0; j < KB; ++j) a[j] = uniform_row_word(s_row[j], w * 8u);
+#pragma unroll
+    for (int j = 0; j < 64; ++j) a[j] = j < KB && (j == 0 || (uint32_t)j < G.k) ? a[j] ^ s_flip[j] : 0ull;
+    transpose64(a);
+  };
   if (!G.compact) {
+    const uint32_t w = tile * 256 + threadIdx.x;
+    if (w >= kb.W) return;
+    uint64_t a[64];
+    build(w, a);
     T += (size_t)w * 64;
 #pragma unroll
     for (int b = 0; b < 64; ++b) T[b] = (TW)a[b];
-  } else {
-    T += kb.objbase[(size_t)rd * (kb.W + 1) + w];
+    return;
+  }
+  // a compact group visits only the words that hold objects of its direction
+  // (the other direction's non-empty words, in its word list).  A wave's
+  // objects have consecutive ranks, so their rows are gathered in LDS and
+  // written as one run (a wave with more rows than the stage stores directly).
+  const uint32_t i = tile * 256 + threadIdx.x;
+  const bool valid = i < G.n_obj_words;
+  const uint32_t w = valid ? kb.words[(size_t)(rd ^ 1u) * kb.W + i] : 0u;
+  const uint64_t omask = valid ? kb.objmask[(size_t)rd * kb.W + w] : 0ull;
+  const uint64_t act = __ballot(omask != 0ull);
+  if (!act) return;
+  const uint32_t r0 = omask ? kb.objbase[(size_t)rd * (kb.W + 1) + w] : 0u;
+  uint64_t a[64];
+  if (omask) build(w, a);
+  const int first = __ffsll((unsigned long long)act) - 1, last = 63 - __clzll(act);
+  const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)r0, first);
+  const uint32_t end = (uint32_t)__builtin_amdgcn_readlane((int)(r0 + (uint32_t)__popcll(omask)), last);
+  const uint32_t cnt = end - base;
+  if (cnt <= (uint32_t)kTStage) {
+    TW* st = s_t[threadIdx.x >> 6];
+    if (omask) {
+#pragma unroll
+      for (int b = 0; b < 64; ++b)
+        if ((omask >> b) & 1ull) st[r0 - base + __popcll(omask & ((1ull << b) - 1ull))] = (TW)a[b];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (uint32_t j = threadIdx.x & 63; j < cnt; j += 64) T[base + j] = st[j];
+  } else if (omask) {
+    T += r0;
 #pragma unroll
     for (int b = 0; b < 64; ++b)
       if ((omask >> b) & 1ull) T[__popcll(omask & ((1ull << b) - 1ull))] = (TW)a[b];
