@@ -372,6 +372,9 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
   const uint32_t seg_n = sp.hi - sp.lo;
   const uint32_t my_row = (uint32_t)lane < k ? members[G->first + lane].out_row : kNone;
   uint64_t* const my_out = my_row != kNone ? out_ptr(kb, my_row) : nullptr;
+  __shared__ uint64_t* s_dst[64];     // every member's output row
+  if (threadIdx.x < 64) s_dst[threadIdx.x] = my_out;
+  __syncthreads();
   Cover cv = cover_of(G, members, k, lane);
   const uint32_t nw = blockDim.x >> 6;
   const uint32_t istep = bpg * nw;
@@ -551,8 +554,10 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
     // each word: lane l's subject 64 w + l.  Its counts go on to the next
     // pass of a cut shared pass, or become every member's predicate,
     // transposed into one output word per member.
+    uint64_t mine_m[MW];
 #pragma unroll
     for (int m = 0; m < MW; ++m) {
+      mine_m[m] = 0;
       if ((uint32_t)m < mc) {
         Planes<TW> p{0, 0, 0, 0};
         if ((nzm[m] >> lane) & 1ull) {
@@ -588,9 +593,40 @@ k_group(DevKB kb, const GroupTask* __restrict__ groups, const GroupMember* __res
           } else {
             mine = wave_transpose64((uint64_t)rv, lane);
           }
-          if (my_out) my_out[rw.wd[m]] = mine;
+          mine_m[m] = mine;
           if (cv.h != kNone) cover_word(cv, kb, rw.wd[m], mine);
         }
+      }
+    }
+    if (sp.last) {
+      if constexpr (sizeof(TW) == 8 && MW > 1 && 64 % MW == 0) {
+        // the members' words go out with MW consecutive lanes on one member's
+        // row (64 / MW rows per store, not 64), through the counter planes'
+        // LDS (read above, not needed again before the next walk)
+        uint64_t* sw = reinterpret_cast<uint64_t*>(&pl[0][0]);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int m = 0; m < MW; ++m) sw[lane * MW + m] = mine_m[m];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int m = lane % MW;
+        uint32_t wm = rw.wd[0];
+#pragma unroll
+        for (int k = 1; k < MW; ++k)
+          if (m == k) wm = rw.wd[k];
+#pragma unroll
+        for (int r = 0; r < MW; ++r) {
+          const int j = r * (64 / MW) + lane / MW;   // member
+          uint64_t* dst = s_dst[j];
+          if (dst && (uint32_t)m < mc) dst[wm] = sw[j * MW + m];
+        }
+      } else if (my_out) {
+#pragma unroll
+        for (int m = 0; m < MW; ++m)
+          if ((uint32_t)m < mc) my_out[rw.wd[m]] = mine_m[m];
       }
     }
     __builtin_amdgcn_wave_barrier();
