@@ -882,6 +882,43 @@ def test_short_row_passes(n):
             assert bad.size == 0, ("device", limit, k, compact, hyps[bad[0]], got[bad[0]], want[bad[0]])
 
 
+def test_tbuild_dense_and_sparse_compact_objects():
+    """Compact T rows where a 64-word wave of the T build holds more object
+    rows than it stages in LDS (forward directions whose objects are about 40%
+    of the individuals: the wave stores its rows directly) and fewer (inverse
+    directions, 10%: the rows go out as one run from LDS), at every T width,
+    through host-compiled and device-generated plans, against the oracle."""
+    n = 131_101
+    cfg = synth.small_config(n=n, n_concepts=24, n_roles=3, s=1.5, cap=40, n_data=1, n_pos=n // 10,
+                             n_neg=n // 12, seed_index=2800, total_edges=3 * n // 2)
+    kb = synth.make_kb(cfg)
+    off, tg = np.asarray(kb.role_offsets), np.asarray(kb.role_targets)
+    for r in range(3):
+        obj = np.zeros(n, bool)
+        obj[tg[int(off[r, 0]):int(off[r, -1])]] = True
+        per_wave = np.add.reduceat(obj.astype(np.int64), np.arange(0, n, 4096))
+        assert 2 * int(obj.sum()) <= n and per_wave.max() > 1024   # compact, some waves beyond the stage
+    rng = np.random.default_rng(28)
+    hyps = []
+    for _ in range(700):
+        r, inv = int(rng.integers(0, 3)), int(rng.integers(0, 2))
+        c = ("atom", int(rng.integers(0, 24)))
+        if rng.random() < 0.3:
+            c = ("or", c, ("exists", int(rng.integers(0, 3)), 1 - inv, ("atom", int(rng.integers(0, 24)))))
+        op = rng.choice(["exists", "forall", "atleast", "atmost", "exactly"])
+        hyps.append((op, r, inv, c) if op in ("exists", "forall") else (op, int(rng.integers(0, 6)), r, inv, c))
+    want = Oracle(kb).coverages(hyps)
+    eng = hthedl.Engine(kb, max_hyps=len(hyps))
+    for k in (64, 32, 16, 8):
+        hthedl.hth_kb_set_tuning(eng.handle, group_min=1, group_k=k, t_compact=1)
+        got = eng.eval_batch(hyps)
+        bad = np.flatnonzero((got != want).any(axis=1))
+        assert bad.size == 0, ("host", k, hyps[bad[0]], got[bad[0]], want[bad[0]])
+        got = eng.eval_batch_device(hyps)
+        bad = np.flatnonzero((got != want).any(axis=1))
+        assert bad.size == 0, ("device", k, hyps[bad[0]], got[bad[0]], want[bad[0]])
+
+
 @pytest.mark.parametrize("short_rows", [0, 12])
 def test_role_roots_with_fused_coverage(short_rows):
     """Hypotheses that are a single role restriction: where such a node is the
