@@ -919,6 +919,40 @@ def test_tbuild_dense_and_sparse_compact_objects():
         assert bad.size == 0, ("device", k, hyps[bad[0]], got[bad[0]], want[bad[0]])
 
 
+def test_short_row_passes_with_saturating_counts():
+    """Short-row passes over directions whose longest rows hold 8 to 12
+    assertions (every direction of this KB is within the short-row limit):
+    the counters keep their saturation plane, and counts from 6 to beyond 8
+    decide the members.  Host-compiled and device-generated plans, every T
+    width, against the oracle."""
+    n = 90_001
+    cfg = synth.small_config(n=n, n_concepts=20, n_roles=2, s=1.2, cap=12, n_data=1, n_pos=n // 10,
+                             n_neg=n // 12, seed_index=2901, total_edges=5 * n)
+    kb = synth.make_kb(cfg)
+    rng = np.random.default_rng(29)
+    hyps = []
+    for _ in range(600):
+        r, inv = int(rng.integers(0, 2)), int(rng.integers(0, 2))
+        c = ("atom", int(rng.integers(0, 20)))
+        if rng.random() < 0.3:
+            c = ("not", c)
+        op = rng.choice(["exists", "forall", "atleast", "atmost", "exactly"])
+        hyps.append((op, r, inv, c) if op in ("exists", "forall") else (op, int(rng.integers(1, 9)), r, inv, c))
+    want = Oracle(kb).coverages(hyps)
+    eng = hthedl.Engine(kb, max_hyps=len(hyps))
+    longest = [hthedl.hth_kb_max_degree(eng.handle, r, d) for r in range(2) for d in range(2)]
+    say(f"[parity] saturating short rows: longest rows {longest}")
+    assert max(longest) >= 8 and max(longest) <= 12
+    for k in (64, 8):
+        hthedl.hth_kb_set_tuning(eng.handle, group_min=1, group_k=k, short_rows=12)
+        got = eng.eval_batch(hyps)
+        bad = np.flatnonzero((got != want).any(axis=1))
+        assert bad.size == 0, ("host", k, hyps[bad[0]], got[bad[0]], want[bad[0]])
+        got = eng.eval_batch_device(hyps)
+        bad = np.flatnonzero((got != want).any(axis=1))
+        assert bad.size == 0, ("device", k, hyps[bad[0]], got[bad[0]], want[bad[0]])
+
+
 @pytest.mark.parametrize("short_rows", [0, 12])
 def test_role_roots_with_fused_coverage(short_rows):
     """Hypotheses that are a single role restriction: where such a node is the
