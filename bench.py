@@ -321,7 +321,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is a "
-              "design note, not part of this build", file=sys.stderr)
+              "design note, not implemented", file=sys.stderr)
         sys.exit(2)
 
     t_start = time.perf_counter()

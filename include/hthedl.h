@@ -48,7 +48,7 @@ enum {
   HTH_E_DEVICE = -4,      /* a HIP call failed (text in hth_last_error) */
   HTH_E_PLAN = -5,        /* hypothesis not in postfix form */
   HTH_E_STATE = -6,       /* handle used in the wrong state */
-  HTH_E_UNSUPPORTED = -7  /* valid request outside this build's limits */
+  HTH_E_UNSUPPORTED = -7  /* valid request outside the library's limits */
 };
 
 /* DL constructs (Section 3.2): the boolean constructs, the object-role
